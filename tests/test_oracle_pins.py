@@ -1,0 +1,438 @@
+"""Pins of the CPU FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: a library
+routine (SciPy/NumPy), a closed form, an invariant, or brute force on tiny
+inputs.  None of these tests touches the GPU library.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.sparse.csgraph import connected_components, laplacian as csgraph_laplacian
+from scipy.sparse.csgraph import minimum_spanning_tree
+
+import workloads as W
+
+
+def dense_from_csr(csr):
+    n = csr.n
+    A = np.zeros((n, n))
+    for p in range(n):
+        for j in range(csr.rowptr[p], csr.rowptr[p + 1]):
+            A[p, csr.col[j]] += csr.val[j]
+    return np.diag(csr.deg) - A
+
+
+def adjacency(n, u, v, w):
+    return sp.coo_matrix((np.concatenate([w, w]), (np.concatenate([u, v]), np.concatenate([v, u]))),
+                         shape=(n, n)).toarray()
+
+
+TINY = [
+    W.grid2d(4, 4, seed=11),
+    W.grid2d(5, 7, seed=12, wdist=("lognormal", 0.0, 1.0)),
+    W.random_connected(30, 40, seed=13),
+    W.random_connected(64, 150, seed=14, wdist=("lognormal", 0.0, 1.5)),
+]
+
+
+# --------------------------------------------------------------------------- Laplacian (Sec. 2.1)
+
+@pytest.mark.parametrize("g", TINY, ids=lambda g: g.name)
+def test_laplacian_matches_scipy(orc, g):
+    csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    L = dense_from_csr(csr)
+    Lref = csgraph_laplacian(adjacency(g.n, g.u, g.v, g.w))
+    assert np.allclose(L, Lref, rtol=0, atol=1e-14)
+    # ascending columns, entry -> edge id consistent with the edge list
+    for p in range(g.n):
+        cols = csr.col[csr.rowptr[p]:csr.rowptr[p + 1]]
+        assert np.all(np.diff(cols) > 0)
+    e = csr.eid
+    rows = np.repeat(np.arange(g.n), np.diff(csr.rowptr))
+    assert np.all(csr.val == g.w[e])
+    assert np.all(np.minimum(rows, csr.col) == g.u[e])
+    assert np.all(np.maximum(rows, csr.col) == g.v[e])
+
+
+def test_laplacian_integer_row_sums_exact(orc):
+    g = W.random_connected(200, 500, seed=3)
+    w = np.floor(g.w * 8.0) + 1.0             # small integers: sums are exact
+    csr = orc.laplacian_csr(g.n, g.u, g.v, w)
+    rowsum = np.zeros(g.n)
+    for p in range(g.n):
+        rowsum[p] = csr.deg[p] - sum(csr.val[csr.rowptr[p]:csr.rowptr[p + 1]])
+    assert np.all(rowsum == 0.0)
+
+
+def test_quadratic_form_identity(orc):
+    # x^T L x = sum_E w (x_p - x_q)^2 (Sec. 2.1)
+    g = TINY[3]
+    csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    L = dense_from_csr(csr)
+    x = np.random.default_rng(0).standard_normal(g.n)
+    lhs = x @ L @ x
+    rhs = math.fsum(g.w * (x[g.u] - x[g.v]) ** 2)
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+
+
+# --------------------------------------------------------------------------- exact sum / centring
+
+def test_exact_sum_matches_fsum(orc):
+    rng = np.random.default_rng(1)
+    cases = [rng.standard_normal(10000),
+             np.array([1e16, 1.0, -1e16, 1e-16, 3.0]),
+             np.array([1e-16, 1.0, 1e16]),
+             rng.standard_normal(1000) * 10.0 ** rng.integers(-20, 20, 1000)]
+    for x in cases:
+        assert orc.exact_sum(x) == math.fsum(x)
+
+
+def test_center_orthogonal_to_ones(orc):
+    X0 = W.random_block(1000, 8, 5)
+    X, mean = orc.center(X0)
+    for c in range(8):
+        assert mean[c] == math.fsum(X0[:, c]) / 1000.0
+        assert abs(math.fsum(X[:, c])) < 1e-12
+
+
+# --------------------------------------------------------------------------- smoothing (Sec. 3.2)
+
+def _closed_form_smooth(L, deg, X0, T, omega):
+    """X_T = D^-1/2 V (I - omega Lambda)^T V^T D^1/2 X0 with V Lambda V^T = D^-1/2 L D^-1/2."""
+    dh = np.sqrt(deg)
+    Nrm = L / dh[:, None] / dh[None, :]
+    lam, V = np.linalg.eigh(Nrm)
+    f = (1.0 - omega * lam) ** T
+    return (V * f) @ (V.T @ (dh[:, None] * X0)) / dh[:, None]
+
+
+@pytest.mark.parametrize("g", TINY, ids=lambda g: g.name)
+@pytest.mark.parametrize("omega", [0.5, 0.3])
+def test_smoothing_closed_form(orc, g, omega):
+    csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    L = dense_from_csr(csr)
+    X0, _ = orc.center(W.random_block(g.n, 4, 7))
+    T = 12
+    X = orc.smooth(csr, X0, T, omega)
+    Xref = _closed_form_smooth(L, csr.deg, X0, T, omega)
+    assert np.max(np.abs(X - Xref)) <= 1e-12 * np.max(np.abs(X0))
+
+
+def test_smoothing_invariants(orc):
+    g = W.grid2d(12, 9, seed=4, wdist=("lognormal", 0.0, 1.0))
+    csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    L = dense_from_csr(csr)
+    X, _ = orc.center(W.random_block(g.n, 3, 8))
+    m0 = csr.deg @ X
+    energy = np.trace(X.T @ L @ X)
+    for _ in range(15):
+        X = orc.smooth(csr, X, 1, 0.5)
+        # 1^T D X is conserved by I - omega D^-1 L
+        assert np.allclose(csr.deg @ X, m0, rtol=0, atol=1e-12)
+        e2 = np.trace(X.T @ L @ X)
+        assert e2 <= energy * (1 + 1e-13)        # Dirichlet energy never increases for omega <= 1
+        energy = e2
+
+
+def test_smoothing_complete_graph(orc):
+    # unit-weight K_n: a centred x maps to x * (1 - omega n / (n - 1))
+    n = 9
+    a, b = np.triu_indices(n, 1)
+    csr = orc.laplacian_csr(n, a, b, np.ones(a.shape[0]))
+    X, _ = orc.center(W.random_block(n, 2, 9))
+    for omega in (0.5, 0.25):
+        Y = orc.smooth(csr, X, 1, omega)
+        assert np.allclose(Y, X * (1 - omega * n / (n - 1)), rtol=0, atol=1e-14)
+
+
+def test_smoothing_masked_cone(orc):
+    from scipy.sparse.csgraph import shortest_path
+
+    g = W.grid2d(15, 15, seed=6)
+    csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    X0, _ = orc.center(W.random_block(g.n, 4, 10))
+    T = 6
+    full = orc.smooth(csr, X0, T, 0.5)
+    seeds = [0, 37, 112]
+    D = shortest_path(sp.csr_matrix(adjacency(g.n, g.u, g.v, np.ones(g.m))), unweighted=True,
+                      indices=seeds)
+    dist = np.minimum(D.min(axis=0), 1 << 20).astype(np.int32)
+    part = orc.smooth_masked(csr, X0, T, 0.5, dist)
+    assert np.array_equal(part[seeds], full[seeds])
+
+
+# --------------------------------------------------------------------------- scores (Eq. 16-19)
+
+@pytest.mark.parametrize("g", TINY[1:], ids=lambda g: g.name)
+def test_scores_full_embedding_equal_leverage(orc, g):
+    # with U_eff = [u_i / sqrt(lambda_i)] over all nontrivial pairs the score is w * R_eff (Eq. 19)
+    csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    L = dense_from_csr(csr)
+    lam, V = np.linalg.eigh(L)
+    U = V[:, 1:] / np.sqrt(lam[1:])
+    s = orc.edge_scores(U, g.u, g.v, g.w)
+    Lp = np.linalg.pinv(L)
+    reff = Lp[g.u, g.u] + Lp[g.v, g.v] - 2 * Lp[g.u, g.v]
+    assert np.allclose(s, g.w * reff, rtol=1e-10, atol=0)
+    # leverage scores of a connected graph sum to n - 1
+    assert abs(s.sum() - (g.n - 1)) < 1e-9 * g.n
+
+
+def test_scores_on_tree_are_path_stretch(orc):
+    g = W.random_connected(40, 60, seed=21)
+    intree, comps = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    assert comps == 1
+    t = intree.astype(bool)
+    L = dense_from_csr(orc.laplacian_csr(g.n, g.u[t], g.v[t], g.w[t]))
+    lam, V = np.linalg.eigh(L)
+    U = V[:, 1:] / np.sqrt(lam[1:])
+    s = orc.edge_scores(U, g.u, g.v, g.w)
+    # brute force: walk the unique tree path and add 1/w of its edges
+    adj = {p: [] for p in range(g.n)}
+    for e in np.nonzero(t)[0]:
+        adj[int(g.u[e])].append((int(g.v[e]), g.w[e]))
+        adj[int(g.v[e])].append((int(g.u[e]), g.w[e]))
+
+    def path_resistance(a, b):
+        stack = [(a, -1, 0.0)]
+        while stack:
+            x, par, r = stack.pop()
+            if x == b:
+                return r
+            for y, wy in adj[x]:
+                if y != par:
+                    stack.append((y, x, r + 1.0 / wy))
+        raise AssertionError
+
+    stretch = np.array([g.w[e] * path_resistance(int(g.u[e]), int(g.v[e])) for e in range(g.m)])
+    assert np.allclose(s, stretch, rtol=1e-9, atol=0)
+
+
+def test_first_order_perturbation(orc):
+    # Eq. 16: adding an edge of tiny weight eps moves lambda_i by eps (u_i^T e_pq)^2 + O(eps^2)
+    g = W.random_connected(12, 8, seed=2)
+    L = dense_from_csr(orc.laplacian_csr(g.n, g.u, g.v, g.w))
+    lam, V = np.linalg.eigh(L)
+    p, q = 0, 7
+    e = np.zeros(g.n); e[p], e[q] = 1, -1
+    for eps in (1e-3, 1e-4):
+        lam2 = np.linalg.eigvalsh(L + eps * np.outer(e, e))
+        pred = eps * (V.T @ e) ** 2
+        err = np.max(np.abs((lam2 - lam) - pred)[1:])
+        assert err < 50 * eps * eps
+
+
+# --------------------------------------------------------------------------- selection (Alg. 1)
+
+def test_select_matches_sort(orc):
+    rng = np.random.default_rng(3)
+    s = np.round(rng.random(5000) * 50) / 7.0    # many ties
+    eid = np.sort(rng.choice(100000, 5000, replace=False)).astype(np.int32)
+    for k in (0, 1, 17, 999, 5000):
+        pos, tau = orc.select_topk(s, eid, k)
+        order = np.lexsort((eid, -s))
+        assert np.array_equal(pos, order[:k])
+        if k:
+            assert tau == s[order[k - 1]]
+
+
+def test_ksel_examples(orc):
+    assert orc.ksel(0.05, 3969) == 199
+    assert orc.ksel(0.10, 1037961) == 103797
+
+
+# --------------------------------------------------------------------------- spanning tree (Sec. 3.4)
+
+@pytest.mark.parametrize("g", TINY + [W.grid2d(30, 30, seed=5)], ids=lambda g: g.name)
+def test_max_spanning_tree_matches_scipy(orc, g):
+    intree, comps = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    assert comps == 1 and intree.sum() == g.n - 1
+    ref = minimum_spanning_tree(sp.csr_matrix((-g.w, (g.u, g.v)), shape=(g.n, g.n))).tocoo()
+    ref_set = set(zip(np.minimum(ref.row, ref.col), np.maximum(ref.row, ref.col)))
+    got = set(zip(g.u[intree == 1], g.v[intree == 1]))
+    assert got == ref_set
+
+
+def test_max_spanning_tree_ties_take_smaller_id(orc):
+    # unit-weight 4-cycle: Kruskal over ascending id keeps edges 0, 1, 2
+    u = np.array([0, 0, 1, 2]); v = np.array([1, 3, 2, 3])
+    intree, _ = orc.max_spanning_forest(4, u, v, np.ones(4))
+    assert list(intree) == [1, 1, 1, 0]
+
+
+def test_components_match_scipy(orc):
+    g = W.random_connected(300, 100, seed=8)
+    mask = (np.arange(g.m) % 3) != 0
+    c, lab = orc.components(g.n, g.u, g.v, mask)
+    A = sp.coo_matrix((np.ones(int(mask.sum())), (g.u[mask], g.v[mask])), shape=(g.n, g.n))
+    c2, lab2 = connected_components(A, directed=False)
+    assert c == c2
+    # same partition
+    assert len(set(zip(lab, lab2))) == c
+
+
+# --------------------------------------------------------------------------- affinity (Sec. 3.2)
+
+def test_affinity_is_squared_cosine(orc):
+    from scipy.spatial.distance import cosine
+
+    g = TINY[2]
+    Xb = W.random_block(g.n, 6, 12)
+    a = orc.affinity(Xb, g.u, g.v)
+    ref = np.array([(1.0 - cosine(Xb[p], Xb[q])) ** 2 for p, q in zip(g.u, g.v)])
+    assert np.allclose(a, ref, rtol=1e-12, atol=1e-15)
+    # special values: parallel rows -> 1, orthogonal rows -> 0, a zero row -> 0
+    Y = np.array([[1.0, 2.0], [-2.0, -4.0], [2.0, -1.0], [0.0, 0.0]])
+    a2 = orc.affinity(Y, [0, 0, 0], [1, 2, 3])
+    assert a2[0] == 1.0 and a2[1] == 0.0 and a2[2] == 0.0
+
+
+# --------------------------------------------------------------------------- coarsening (Eq. 3-7)
+
+def _coarsen_dense(orc, g, seed=3, T=8):
+    agg, nc, cu, cv, cw, rep, a_edge = orc.coarsen_level(g.n, g.u, g.v, g.w,
+                                                         W.random_block(g.n, 4, seed), T)
+    Hp = np.zeros((g.n, nc))
+    Hp[np.arange(g.n), agg] = 1.0                      # H+ of Eq. 5
+    H = (Hp / Hp.sum(axis=0)).T                        # H of Eq. 4
+    return agg, nc, cu, cv, cw, rep, Hp, H
+
+
+@pytest.mark.parametrize("g", [W.grid2d(8, 8, seed=31), W.random_connected(60, 120, seed=32)],
+                         ids=lambda g: g.name)
+def test_galerkin_is_eq3(orc, g):
+    agg, nc, cu, cv, cw, rep, Hp, H = _coarsen_dense(orc, g)
+    assert 1 < nc <= g.n // 2                          # every aggregate has >= 2 nodes
+    assert np.allclose(H @ Hp, np.eye(nc))             # H H+ = I
+    L = dense_from_csr(orc.laplacian_csr(g.n, g.u, g.v, g.w))
+    Lc_ref = Hp.T @ L @ Hp                             # Eq. 3 with H^{-T} = H+^T
+    Lc = dense_from_csr(orc.laplacian_csr(nc, cu, cv, cw))
+    assert np.allclose(Lc, Lc_ref, rtol=0, atol=1e-12)
+    # every aggregate is connected inside G
+    for I in range(nc):
+        S = np.nonzero(agg == I)[0]
+        inside = np.isin(g.u, S) & np.isin(g.v, S)
+        c, _ = connected_components(sp.coo_matrix((np.ones(int(inside.sum())), (g.u[inside], g.v[inside])),
+                                                  shape=(g.n, g.n)).tocsr()[S][:, S], directed=False)
+        assert c == 1
+    # representative fine edge: heaviest between the two aggregates, ties smallest id
+    for e_c in range(cu.shape[0]):
+        between = ((agg[g.u] == cu[e_c]) & (agg[g.v] == cv[e_c])) | ((agg[g.u] == cv[e_c]) & (agg[g.v] == cu[e_c]))
+        ids = np.nonzero(between)[0]
+        best = ids[np.lexsort((ids, -g.w[ids]))[0]]
+        assert rep[e_c] == best
+    # aggregates numbered by ascending smallest member
+    firsts = [np.min(np.nonzero(agg == I)[0]) for I in range(nc)]
+    assert firsts == sorted(firsts)
+
+
+def test_coarse_eigenvalue_bounds(orc):
+    # min|S| lambda_i(L) <= lambda_i(L_c) <= max|S| lambda_{i+N-Nc}(L)  (Eq. 7 lower bound, interlacing)
+    g = W.grid2d(9, 8, seed=33, wdist=("lognormal", 0.0, 1.0))
+    agg, nc, cu, cv, cw, rep, Hp, H = _coarsen_dense(orc, g)
+    L = dense_from_csr(orc.laplacian_csr(g.n, g.u, g.v, g.w))
+    Lc = dense_from_csr(orc.laplacian_csr(nc, cu, cv, cw))
+    lam = np.linalg.eigvalsh(L)
+    lamc = np.linalg.eigvalsh(Lc)
+    sizes = np.bincount(agg)
+    for i in range(nc):
+        assert sizes.min() * lam[i] <= lamc[i] + 1e-10
+        assert lamc[i] <= sizes.max() * lam[i + g.n - nc] + 1e-10
+
+
+def test_aggregate_pointer_rule_brute_force(orc):
+    g = W.random_connected(40, 50, seed=34)
+    csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    a = np.round(np.random.default_rng(1).random(g.m) * 4) / 4     # ties in affinity
+    agg, ptr, nc = orc.aggregate(csr, a[csr.eid])
+    for p in range(g.n):
+        best = None
+        for e in range(g.m):
+            if p not in (g.u[e], g.v[e]):
+                continue
+            q = int(g.v[e] if g.u[e] == p else g.u[e])
+            key = (a[e], g.w[e], -q)
+            if best is None or key > best[0]:
+                best = (key, q)
+        assert ptr[p] == best[1]
+    c, lab = connected_components(sp.coo_matrix((np.ones(g.n), (np.arange(g.n), ptr)), shape=(g.n, g.n)),
+                                  directed=False)
+    assert c == nc and len(set(zip(lab, agg))) == nc
+
+
+def test_backward_mapping_of_a_tree_is_a_tree(orc):
+    g = W.grid2d(20, 20, seed=35)
+    agg, nc, cu, cv, cw, rep, _ = orc.coarsen_level(g.n, g.u, g.v, g.w, W.random_block(g.n, 4, 2), 8)
+    ctree, comps = orc.max_spanning_forest(nc, cu, cv, cw)
+    assert comps == 1
+    intra = agg[g.u] == agg[g.v]
+    inner, _ = orc.max_spanning_forest(g.n, g.u, g.v, g.w, allowed=intra)
+    base = inner.astype(bool)
+    base[rep[ctree == 1]] = True
+    assert base.sum() == g.n - 1
+    c, _ = orc.components(g.n, g.u, g.v, base)
+    assert c == 1
+
+
+# --------------------------------------------------------------------------- sparsifier and kappa (Eq. 2)
+
+def test_kappa_dense_and_sparse_agree(orc):
+    g = W.grid2d(12, 12, seed=40)
+    r = orc.sparsify_single(g.n, g.u, g.v, g.w, W.random_block(g.n, 8, 41), 10, 0.1)
+    mask = r.keep > 0
+    kd, lmax, lmin = orc.kappa_dense(g.n, g.u, g.v, g.w, mask)
+    ks, _, _ = orc.kappa_sparse(g.n, g.u, g.v, g.w, mask)
+    assert abs(kd - ks) <= 1e-6 * kd
+    assert lmin >= 1 - 1e-9                    # P is a subgraph of G, so L_G >= L_P
+
+
+def test_kappa_monotone_and_tree_bounds(orc):
+    g = W.grid2d(10, 10, seed=42, wdist=("lognormal", 0.0, 1.0))
+    intree, _ = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    t = intree.astype(bool)
+    k_tree, lmax, _ = orc.kappa_dense(g.n, g.u, g.v, g.w, t)
+    # exact stretch bounds: max_e w_e R_T(e) <= lambda_max(L_T^+ L_G) <= sum_e w_e R_T(e)
+    LT = dense_from_csr(orc.laplacian_csr(g.n, g.u[t], g.v[t], g.w[t]))
+    Lp = np.linalg.pinv(LT)
+    st = g.w * (Lp[g.u, g.u] + Lp[g.v, g.v] - 2 * Lp[g.u, g.v])
+    assert st.max() <= lmax * (1 + 1e-9) and lmax <= st.sum() * (1 + 1e-9)
+    # adding edges never increases kappa
+    order = np.argsort(-st)
+    mask = t.copy()
+    prev = k_tree
+    for e in order[:10]:
+        if mask[e]:
+            continue
+        mask[e] = True
+        k2, _, _ = orc.kappa_dense(g.n, g.u, g.v, g.w, mask)
+        assert k2 <= prev * (1 + 1e-9)
+        prev = k2
+
+
+def test_sparsifier_structure(orc):
+    g = W.config_graph(1)
+    r = orc.sparsify_single(g.n, g.u, g.v, g.w, W.config_block(1, g.n), 10, 0.05)
+    lr = r.levels[0]
+    assert lr.n_cand == 3969 and lr.k_sel == 199
+    assert (r.keep == 1).sum() == g.n - 1 and (r.keep == 2).sum() == 199
+    c, _ = orc.components(g.n, g.u, g.v, r.keep > 0)
+    assert c == 1
+    # the recovered edges are exactly the top 199 scores among off-tree edges
+    s = lr.score
+    thr = np.sort(s)[::-1][198]
+    assert np.all(s[np.isin(lr.cand, lr.chosen)] >= thr)
+
+
+def test_multilevel_structure(orc):
+    g = W.grid2d(40, 40, seed=43, wdist=("lognormal", 0.0, 1.0))
+    X0s = [W.random_block(g.n, 8, 50 + l) for l in range(3)]
+    r, lv = orc.sparsify_multilevel(g.n, g.u, g.v, g.w, X0s, 3, 10, 0.1)
+    assert lv[0].n > lv[1].n > lv[2].n
+    keep = r.keep
+    c, _ = orc.components(g.n, g.u, g.v, keep > 0)
+    assert c == 1
+    lr = r.levels[-1]
+    assert (keep == 2).sum() == lr.k_sel
+    assert (keep > 0).sum() < g.m
