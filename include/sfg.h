@@ -1,0 +1,264 @@
+/*
+ * sfg.h -- C ABI of libsfg, the MI355X (gfx950) implementation of the
+ * data-parallel hot path of SF-GRASS (Zhang, Zhao, Feng, "SF-GRASS:
+ * Solver-Free Graph Spectral Sparsification", ICCAD 2020).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers are DEVICE pointers unless the comment says (host).  The caller
+ *   owns all memory; no entry point keeps a pointer after it returns.
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   Work is enqueued on it in order.  Entry points that return host scalars
+ *   (marked "synchronises") wait for the stream before returning.
+ * - Graphs are canonical undirected edge lists: u[e] < v[e], sorted by
+ *   (u, v), no duplicates, node ids in [0, n), weights finite and > 0.  The
+ *   edge id is the list index; every tie-break uses it.
+ * - Blocks of vectors are n-by-k, row-major (node-major): element (p, c)
+ *   at p*k + c.
+ * - Status codes are returned; sfg_last_error() gives a message for the
+ *   last non-OK status on the calling thread.  Asynchronous device faults
+ *   surface as SFG_EHIP at the next call that checks the stream.  No C++
+ *   exception crosses the ABI.
+ * - The four primitives (sfg_laplacian_csr, sfg_smooth, sfg_edge_scores,
+ *   sfg_select_topk and the affinity / coarsening calls) allocate nothing:
+ *   the caller passes a workspace of at least sfg_workspace_bytes() bytes.
+ *   sfg_sparsify allocates its intermediate buffers itself (stream-ordered)
+ *   and frees them before it returns.
+ * - Sizes: nnz = 2*(number of edges in the graph) must be < 2^31.
+ */
+#ifndef SFG_H_
+#define SFG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SFG_OK = 0,
+    SFG_EINVAL = 1,        /* bad argument or malformed edge list */
+    SFG_ENOTCONN = 2,      /* graph (or candidate sparsifier) is not connected */
+    SFG_ENOMEM = 3,        /* device allocation failed (sfg_sparsify only) */
+    SFG_EHIP = 4,          /* HIP runtime error; message has the HIP error string */
+    SFG_EWORKSPACE = 5,    /* workspace smaller than sfg_workspace_bytes() */
+    SFG_EUNSUPPORTED = 6,  /* valid request this build does not support (e.g. k > 64) */
+    SFG_ENUMERIC = 7       /* NaN/Inf met in scores */
+} sfg_status;
+
+typedef enum { SFG_F64 = 0, SFG_F32 = 1, SFG_F16 = 2, SFG_BF16 = 3 } sfg_dtype;
+
+/* Compressed sparse rows of the adjacency A of a weighted graph.  The
+ * Laplacian L = D - A (Sec. 2.1) is implicit: deg holds D.  Columns are
+ * ascending in every row.  A view: owns nothing. */
+typedef struct {
+    int64_t n;             /* rows (nodes) */
+    int64_t nnz;           /* stored entries = 2 * edges */
+    const int32_t *rowptr; /* [n+1] */
+    const int32_t *col;    /* [nnz] */
+    const void *val;       /* [nnz] of vt: edge weight */
+    const int32_t *eid;    /* [nnz] edge id of each entry (may be NULL if unused) */
+    const void *deg;       /* [n] of vt: weighted degree */
+    sfg_dtype vt;          /* SFG_F64 or SFG_F32 */
+} sfg_csr;
+
+/* Operation codes for sfg_workspace_bytes. */
+typedef enum {
+    SFG_OP_LAPLACIAN_CSR = 0,
+    SFG_OP_SMOOTH = 1,
+    SFG_OP_SELECT_TOPK = 2,
+    SFG_OP_AFFINITY = 3,
+    SFG_OP_COARSEN = 4
+} sfg_op;
+
+/* Which graph's embedding scores the candidates (Sec. 3.5 derives the score
+ * from eigenvectors of the current sparsifier; Alg. 1 embeds the graph). */
+typedef enum { SFG_EMBED_SPARSIFIER = 0, SFG_EMBED_GRAPH = 1 } sfg_embed;
+
+/* Workspace (bytes) needed by an operation.  For SFG_OP_LAPLACIAN_CSR, m is
+ * the edge count; for SFG_OP_SMOOTH, n, k and t (the storage dtype); for
+ * SFG_OP_SELECT_TOPK, m is the candidate count; for SFG_OP_AFFINITY, n, k;
+ * for SFG_OP_COARSEN, n, m, k. */
+size_t sfg_workspace_bytes(int op, int64_t n, int64_t m, int32_t k, sfg_dtype t);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *sfg_last_error(void);
+
+/*
+ * Build the CSR of the adjacency and the degree vector of the graph
+ * (Sec. 2.1: A(p,q) = w(p,q); D(p,p) = sum of the weights at p).
+ *   n, m        nodes, edges of the canonical edge list u, v, w (wt = F64|F32)
+ *   mask        optional [m] uint8: only edges with mask[e] != 0 are included
+ *               (NULL = all), e.g. the spanning tree or current sparsifier
+ *   rowptr      out [n+1] int32
+ *   col, eid    out [nnz] int32, nnz = 2 * included edges; columns ascend in a
+ *               row, so entries of a row are in ascending edge id
+ *   val         out [nnz] of wt (the edge weight)
+ *   deg         out [n] of wt; summed in FP64 in ascending edge id, then
+ *               stored in wt
+ *   nnz_out     (host, may be NULL) receives nnz; synchronises when non-NULL
+ * Errors: SFG_EINVAL on bad sizes/dtypes, SFG_EWORKSPACE.
+ */
+sfg_status sfg_laplacian_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v,
+                             const void *w, sfg_dtype wt, const uint8_t *mask,
+                             int32_t *rowptr, int32_t *col, void *val, int32_t *eid, void *deg,
+                             int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Local spectral embedding (Sec. 3.2): make the k random vectors x0
+ * orthogonal to the all-one vector (subtract each column's mean; the mean is
+ * the column sum rounded once, divided by n), then apply `sweeps` damped
+ * Jacobi relaxations of L x = 0:
+ *     x_p <- (1 - omega) x_p + omega * (sum_q A_pq x_q) / D_pp
+ * with the row sum taken in ascending column order.
+ *   H          graph to smooth (vt F64 when storage is F64, else F32)
+ *   k          1..64 vectors; sweeps >= 0; 0 < omega <= 1 (0.5 damps the
+ *              top of the spectrum of bipartite graphs)
+ *   x0         [n*k] FP64, not modified
+ *   storage    element type of the iterates: F64 (FP64 arithmetic) or
+ *              F32/F16/BF16 (FP32 arithmetic, rounding to nearest even on
+ *              every store)
+ *   final_f32  when storage is F16/BF16: store the last iterate in FP32
+ *   x          out [n*k] of storage (of F32 when final_f32)
+ * Errors: SFG_EINVAL, SFG_EUNSUPPORTED (k > 64 or an unsupported
+ * combination), SFG_EWORKSPACE.
+ */
+sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega,
+                      const double *x0, sfg_dtype storage, int32_t final_f32, void *x,
+                      void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Edge scores (Eq. 18 with the smoothed block in place of eigenvectors;
+ * Alg. 1's edge distortion): s_e = w_e * sum_c (x_pc - x_qc)^2 over the k
+ * columns, c ascending.
+ *   x, xt      smoothed block [n*k] (F64, F32, F16 or BF16)
+ *   ne         number of scored edges
+ *   cand       optional [ne] edge ids into u, v, w (NULL: edge i is scored)
+ *   u, v, w    edge list (wt = F64 or F32)
+ *   score, st  out [ne]: F64 (requires xt = F64 and wt = F64, FP64
+ *              arithmetic) or F32 (FP32 arithmetic)
+ */
+sfg_status sfg_edge_scores(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t ne,
+                           const int32_t *cand, const int32_t *u, const int32_t *v,
+                           const void *w, sfg_dtype wt, void *score, sfg_dtype st, void *stream);
+
+/*
+ * Top-k selection (Alg. 1, "include top few edges with large distortion"):
+ * order the ne scores by value descending, then position ascending (callers
+ * keep candidates in ascending edge id, so this is edge id ascending), and
+ * mark the first k.
+ *   score, st  [ne] non-negative F64 or F32 scores
+ *   sel        out [ne] uint8: 1 if chosen else 0
+ *   tau        out (device, 1 double): the k-th largest score (+inf if k = 0)
+ *   tau_host   (host, may be NULL) receives tau; synchronises when non-NULL
+ * Errors: SFG_EINVAL when k > ne; SFG_ENUMERIC on a NaN or negative score.
+ */
+sfg_status sfg_select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel,
+                           double *tau, double *tau_host, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Maximum-weight spanning tree (the MST the paper uses in place of a
+ * low-stretch tree, Sec. 3.4): the unique tree that Kruskal's rule picks
+ * under the order (weight descending, edge id ascending).
+ *   allowed    optional [m] uint8 restricting the usable edges (NULL = all);
+ *              with a restriction the result is a spanning forest
+ *   in_tree    out [m] uint8: 1 for tree edges
+ *   n_comp     (host) receives the number of components of the forest;
+ *              synchronises
+ * Errors: SFG_ENOMEM, SFG_EHIP.  (Allocates internally.)
+ */
+sfg_status sfg_spanning_tree(int64_t n, int64_t m, const int32_t *u, const int32_t *v,
+                             const void *w, sfg_dtype wt, const uint8_t *allowed,
+                             uint8_t *in_tree, int64_t *n_comp, void *stream);
+
+/*
+ * Node affinity of the algebraic-distance type used to form aggregation
+ * sets (Sec. 3.2): with xb = x minus its column means,
+ *     a_pq = (xb_p . xb_q)^2 / (|xb_p|^2 |xb_q|^2),   0 if a norm is 0.
+ *   x, xt      smoothed block [n*k] (F64 or F32)
+ *   aff        out [m] of at (F64 requires xt F64; else F32)
+ */
+sfg_status sfg_affinity(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t m,
+                        const int32_t *u, const int32_t *v, void *aff, sfg_dtype at,
+                        void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * One spectral-coarsening step (Sec. 3.2-3.3, Eqs. 3-5): aggregation sets
+ * from the affinities, then the Galerkin coarse graph L_c = H+^T L H+.
+ * Aggregation rule (the paper leaves it open): every node points to the
+ * neighbour with the largest (affinity, weight, -id); aggregates are the
+ * connected components of these pointers, numbered by smallest member.
+ *   G          CSR of the graph (with eid); vt F64 or F32
+ *   m,u,v,w,wt its canonical edge list
+ *   aff, at    [m] edge affinities (F64 or F32)
+ *   agg        out [n] aggregate id of each node
+ *   n_coarse   (host) out: number of aggregates; synchronises
+ *   m_coarse   (host) out: number of coarse edges
+ *   cu,cv,cw   out [<= m] canonical coarse edge list (cw of wt: sums of
+ *              fine weights, added in ascending fine edge id, in FP64)
+ *   crep       out [<= m] per coarse edge, the heaviest fine edge between
+ *              the two aggregates (ties: smallest id), kept by the
+ *              backward mapping of Sec. 3.4
+ */
+sfg_status sfg_coarsen(const sfg_csr *G, int64_t m, const int32_t *u, const int32_t *v,
+                       const void *w, sfg_dtype wt, const void *aff, sfg_dtype at,
+                       int32_t *agg, int64_t *n_coarse, int64_t *m_coarse, int32_t *cu,
+                       int32_t *cv, void *cw, int32_t *crep, void *ws, size_t ws_bytes,
+                       void *stream);
+
+/* Parameters of sfg_sparsify (host struct). */
+typedef struct {
+    int32_t levels;        /* 1 = spanning tree + one scoring pass; >1 = Alg. 1 hierarchy */
+    int32_t k;             /* vectors per embedding, 1..64 */
+    int32_t sweeps;        /* smoothing sweeps per embedding */
+    double omega;          /* damping, 0 < omega <= 1 */
+    double frac;           /* recovered fraction f of each level's candidates: k_sel = ceil(f * n_cand) */
+    int32_t embed;         /* sfg_embed */
+    sfg_dtype storage;     /* iterate storage: F64, F32, F16, BF16 */
+    int32_t final_f32;     /* F16/BF16: last iterate in FP32 */
+    double band;           /* F16/BF16/F32: relative margin m of FP64 re-scoring around the threshold (0 = none) */
+} sfg_params;
+
+/* Per-level report (host). */
+typedef struct {
+    int64_t n, m;          /* level graph size */
+    int64_t n_cand;        /* off-subgraph candidates */
+    int64_t k_sel;         /* edges recovered */
+    double tau;            /* k_sel-th largest score */
+    int64_t band;          /* edges re-scored in FP64 (precision form) */
+    int64_t band_above;    /* edges accepted above the band */
+    int32_t band_rounds;   /* margin doublings needed */
+    float ms_smooth, ms_score, ms_select, ms_other;
+} sfg_level_report;
+
+typedef struct {
+    int32_t levels;
+    sfg_level_report level[16];   /* index 0 = finest */
+} sfg_report;
+
+/*
+ * Spectral sparsifier P of G (the problem of Sec. 2.2 and Alg. 1):
+ * levels = 1: maximum-weight spanning tree, embed (sparsifier = the tree, or
+ *   the graph), score the off-tree edges, add the top ceil(f * n_cand).
+ * levels > 1: Alg. 1 -- coarsen G_0..G_{levels-1}, P_last = G_last, then for
+ *   each finer level map the sparsifier back (per-aggregate spanning trees and
+ *   the heaviest fine edge of each coarse sparsifier edge) and add the top
+ *   f of that level's off-subgraph edges.
+ *   x0         random blocks, FP64: level l uses rows [0, N_l) of the n-by-k
+ *              block at x0 + l*n*k  (caller draws levels*n*k values)
+ *   keep       out [m] uint8: 0 not in P, 1 in P before the final additions
+ *              (the tree, or the mapped sparsifier), 2 recovered at level 0
+ *   rep        (host, may be NULL) per-level report
+ * Synchronises.  Errors: SFG_EINVAL, SFG_ENOTCONN, SFG_ENOMEM, SFG_EHIP,
+ * SFG_EUNSUPPORTED.
+ */
+sfg_status sfg_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w,
+                        sfg_dtype wt, const sfg_params *p, const double *x0, uint8_t *keep,
+                        sfg_report *rep, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFG_H_ */

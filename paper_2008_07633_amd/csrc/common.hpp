@@ -1,0 +1,173 @@
+// Internal helpers of libsfg (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sfg.h"
+
+namespace sfg {
+
+// ---------------------------------------------------------------- errors
+
+struct Error {
+    sfg_status st;
+    std::string msg;
+};
+
+void set_last_error(const std::string &msg);
+void clear_last_error();
+
+[[noreturn]] inline void fail(sfg_status st, const std::string &msg) { throw Error{st, msg}; }
+
+#define SFG_HIP(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            ::sfg::fail(SFG_EHIP, std::string(#call) + ": " + hipGetErrorString(e_) + " at " + \
+                                      __FILE__ + ":" + std::to_string(__LINE__));            \
+    } while (0)
+
+#define SFG_LAUNCH_CHECK() SFG_HIP(hipGetLastError())
+
+#define SFG_REQUIRE(cond, st, msg)               \
+    do {                                         \
+        if (!(cond)) ::sfg::fail((st), (msg));   \
+    } while (0)
+
+// Wrap an entry point body: maps internal errors to status codes.
+template <typename F>
+inline sfg_status guard(F &&f) {
+    try {
+        f();
+        clear_last_error();
+        return SFG_OK;
+    } catch (const Error &e) {
+        set_last_error(e.msg);
+        return e.st;
+    } catch (const std::exception &e) {
+        set_last_error(std::string("internal error: ") + e.what());
+        return SFG_EHIP;
+    } catch (...) {
+        set_last_error("internal error");
+        return SFG_EHIP;
+    }
+}
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---------------------------------------------------------------- workspace carving
+
+// Bump allocator over a caller workspace.  With base == nullptr it only
+// measures, so the same plan function gives sfg_workspace_bytes().
+struct Carver {
+    char *base;
+    size_t used = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <typename T>
+    T *take(size_t count) {
+        used = (used + 255) & ~size_t(255);
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+inline size_t dtype_size(sfg_dtype t) {
+    switch (t) {
+        case SFG_F64: return 8;
+        case SFG_F32: return 4;
+        case SFG_F16: return 2;
+        case SFG_BF16: return 2;
+    }
+    return 0;
+}
+
+inline bool valid_dtype(int t) { return t >= SFG_F64 && t <= SFG_BF16; }
+
+// ---------------------------------------------------------------- device helpers
+
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;
+
+// Workgroups are dealt round-robin to the 8 XCDs; remap so that each XCD
+// walks one contiguous range of logical blocks (neighbouring rows share that
+// XCD's L2).  Bijective for any grid size.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+    uint32_t q = nb / kNumXcd, r = nb % kNumXcd;
+    uint32_t x = b % kNumXcd, i = b / kNumXcd;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+template <typename T> struct DT;
+template <> struct DT<double> { static constexpr sfg_dtype id = SFG_F64; };
+template <> struct DT<float> { static constexpr sfg_dtype id = SFG_F32; };
+template <> struct DT<__half> { static constexpr sfg_dtype id = SFG_F16; };
+template <> struct DT<__hip_bfloat16> { static constexpr sfg_dtype id = SFG_BF16; };
+
+// value conversions (round to nearest even on narrowing)
+template <typename TO, typename FROM> __device__ __forceinline__ TO cvt(FROM x);
+template <> __device__ __forceinline__ double cvt<double, double>(double x) { return x; }
+template <> __device__ __forceinline__ double cvt<double, float>(float x) { return (double)x; }
+template <> __device__ __forceinline__ float cvt<float, float>(float x) { return x; }
+template <> __device__ __forceinline__ float cvt<float, double>(double x) { return (float)x; }
+template <> __device__ __forceinline__ float cvt<float, __half>(__half x) { return __half2float(x); }
+template <> __device__ __forceinline__ float cvt<float, __hip_bfloat16>(__hip_bfloat16 x) {
+    return __bfloat162float(x);
+}
+template <> __device__ __forceinline__ __half cvt<__half, float>(float x) { return __float2half(x); }
+template <> __device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16, float>(float x) {
+    return __float2bfloat16(x);
+}
+template <> __device__ __forceinline__ __half cvt<__half, double>(double x) { return __float2half((float)x); }
+template <> __device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16, double>(double x) {
+    return __float2bfloat16((float)x);
+}
+template <> __device__ __forceinline__ double cvt<double, __half>(__half x) { return (double)__half2float(x); }
+template <> __device__ __forceinline__ double cvt<double, __hip_bfloat16>(__hip_bfloat16 x) {
+    return (double)__bfloat162float(x);
+}
+
+// ---------------------------------------------------------------- shared device routines
+
+// Exclusive prefix sum of int32 counts; out may alias nothing.  n elements in,
+// n+1 written (out[n] = total).  Scratch: scan_scratch_ints(n) ints.
+size_t scan_scratch_ints(int64_t n);
+void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *scratch, hipStream_t s);
+
+// Fill with a value (kernel, not a memset node, so it is safe under capture).
+void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
+
+// Stream-ordered device allocations owned by one sfg_sparsify call, freed
+// (stream-ordered) when it returns.  SFG_FAIL_ALLOC_AFTER=n makes the
+// (n+1)-th allocation fail, to test the error path.
+struct DevArena {
+    hipStream_t s;
+    std::vector<void *> ptrs;
+    long fail_after = -1;
+    long count = 0;
+    explicit DevArena(hipStream_t st);
+    ~DevArena();
+    DevArena(const DevArena &) = delete;
+    DevArena &operator=(const DevArena &) = delete;
+    void *raw(size_t bytes);
+    template <typename T>
+    T *alloc(size_t n) {
+        return static_cast<T *>(raw(n * sizeof(T)));
+    }
+};
+
+inline uint32_t grid_for(int64_t items, int block) {
+    int64_t g = (items + block - 1) / block;
+    return (uint32_t)(g < 1 ? 1 : g);
+}
+
+}  // namespace sfg

@@ -1,0 +1,256 @@
+// Top-k selection of edge scores (Alg. 1: "include top few edges with large
+// distortion"): order by score descending, then position ascending, keep the
+// first k.
+//
+// Scores are non-negative IEEE numbers, whose bit patterns order like the
+// values, so the k-th largest key is found by most-significant-digit radix
+// select: per pass, a histogram (LDS, integer atomics) of the keys that
+// still match the digits fixed so far, then one workgroup picks the digit
+// that contains rank k.  Passes stay on the device (no host round trips).
+// Ties at the threshold take the lowest positions: a scan over the tie flags
+// gives each tied key its rank.
+#include "common.hpp"
+
+namespace sfg {
+
+namespace {
+
+constexpr int kBins = 2048;
+constexpr int kHistThreads = 256;
+
+struct SelState {
+    uint64_t prefix;
+    uint64_t fixed;
+    int64_t krem;      // rank (1-based) still sought inside the current bucket
+    int64_t count_gt;  // keys known to be larger than the bucket
+    uint32_t err;
+    uint32_t pad;
+};
+
+template <typename TS> struct KeyOf;
+template <> struct KeyOf<double> {
+    using K = uint64_t;
+    static constexpr int bits = 64;
+};
+template <> struct KeyOf<float> {
+    using K = uint32_t;
+    static constexpr int bits = 32;
+};
+
+template <typename TS>
+__device__ __forceinline__ typename KeyOf<TS>::K key_of(TS x) {
+    typename KeyOf<TS>::K k;
+    __builtin_memcpy(&k, &x, sizeof(k));
+    return k;
+}
+
+template <typename TS>
+__device__ __forceinline__ bool bad_key(typename KeyOf<TS>::K k) {
+    using K = typename KeyOf<TS>::K;
+    constexpr int B = KeyOf<TS>::bits;
+    constexpr int mant = (B == 64) ? 52 : 23;
+    const K sign = K(1) << (B - 1);
+    const K expmask = ((K(1) << (B - 1 - mant)) - 1) << mant;
+    // negative (including -0) or NaN
+    return (k & sign) || (((k & expmask) == expmask) && (k & ((K(1) << mant) - 1)));
+}
+
+__global__ void k_sel_init(SelState *st, int64_t k, uint32_t *hist) {
+    if (threadIdx.x == 0) {
+        st->prefix = 0;
+        st->fixed = 0;
+        st->krem = k;
+        st->count_gt = 0;
+        st->err = 0;
+    }
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
+}
+
+template <typename TS>
+__global__ __launch_bounds__(kHistThreads) void k_sel_hist(int64_t ne, const TS *__restrict__ score,
+                                                           const SelState *__restrict__ st, int shift, int width,
+                                                           int check, uint32_t *hist, SelState *stw) {
+    using K = typename KeyOf<TS>::K;
+    __shared__ uint32_t h[kBins];
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    const K prefix = (K)st->prefix, fixed = (K)st->fixed;
+    const K dmask = (K(1) << width) - 1;
+    uint32_t bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += (int64_t)gridDim.x * blockDim.x) {
+        const K key = key_of(score[i]);
+        if (check) bad |= bad_key<TS>(key) ? 1u : 0u;
+        if ((key & fixed) == prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
+    }
+    if (bad) atomicOr(&stw->err, 1u);
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBins; b += blockDim.x)
+        if (h[b]) atomicAdd(&hist[b], h[b]);
+}
+
+// One workgroup of 256 threads, 8 bins each; finds the digit holding rank
+// krem counted from the top, updates the state and clears the histogram.
+__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, int shift, int width) {
+    __shared__ int64_t suffix[257];
+    const int t = threadIdx.x;
+    const int nb = 1 << width;
+    const int per = (nb + 255) / 256;
+    int64_t mine = 0;
+    for (int i = 0; i < per; ++i) {
+        const int b = t * per + i;
+        if (b < nb) mine += hist[b];
+    }
+    suffix[t] = mine;
+    if (t == 0) suffix[256] = 0;
+    __syncthreads();
+    // inclusive suffix sums: suffix[t] = sum of threads >= t
+    for (int d = 1; d < 256; d <<= 1) {
+        int64_t add = (t + d < 256) ? suffix[t + d] : 0;
+        __syncthreads();
+        suffix[t] += add;
+        __syncthreads();
+    }
+    const int64_t krem = st->krem;
+    const int64_t above = suffix[t + 1];   // suffix[256] stays 0
+    if (above < krem && krem <= above + mine) {
+        int64_t acc = above;
+        for (int i = per - 1; i >= 0; --i) {
+            const int b = t * per + i;
+            if (b >= nb) continue;
+            const int64_t c = hist[b];
+            if (krem <= acc + c) {
+                st->count_gt += acc;
+                st->krem = krem - acc;
+                st->prefix |= (uint64_t)b << shift;
+                st->fixed |= (uint64_t)(nb - 1) << shift;
+                break;
+            }
+            acc += c;
+        }
+    }
+    __syncthreads();
+    if (t == 0 && suffix[0] < krem) st->err |= 2u;
+    for (int i = 0; i < per; ++i) {
+        const int b = t * per + i;
+        if (b < nb) hist[b] = 0;
+    }
+}
+
+template <typename TS>
+__global__ void k_sel_flags(int64_t ne, const TS *__restrict__ score, const SelState *__restrict__ st,
+                            int32_t *flags) {
+    using K = typename KeyOf<TS>::K;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    flags[i] = key_of(score[i]) == (K)st->prefix ? 1 : 0;
+}
+
+template <typename TS>
+__global__ void k_sel_mark(int64_t ne, const TS *__restrict__ score, const SelState *__restrict__ st,
+                           const int32_t *__restrict__ tie_rank, uint8_t *sel, double *tau) {
+    using K = typename KeyOf<TS>::K;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const K thr = (K)st->prefix;
+    if (i == 0) {
+        TS tv;
+        __builtin_memcpy(&tv, &thr, sizeof(tv));
+        *tau = st->err ? __builtin_nan("") : (double)tv;
+    }
+    if (i >= ne) return;
+    const K key = key_of(score[i]);
+    uint8_t s = 0;
+    if (key > thr) s = 1;
+    else if (key == thr && tie_rank[i] < st->krem) s = 1;
+    sel[i] = s;
+}
+
+__global__ void k_sel_empty(double *tau) { *tau = __builtin_inf(); }
+
+struct SelPlan {
+    SelState *st;
+    uint32_t *hist;
+    int32_t *flags, *rank, *scan;
+};
+
+SelPlan plan_select(Carver &c, int64_t ne) {
+    SelPlan p;
+    p.st = c.take<SelState>(1);
+    p.hist = c.take<uint32_t>(kBins);
+    p.flags = c.take<int32_t>(ne + 1);
+    p.rank = c.take<int32_t>(ne + 1);
+    p.scan = c.take<int32_t>(scan_scratch_ints(ne + 1));
+    return p;
+}
+
+template <typename TS>
+void run_select(const TS *score, int64_t ne, int64_t k, uint8_t *sel, double *tau, const SelPlan &p,
+                hipStream_t s) {
+    constexpr int B = KeyOf<TS>::bits;
+    hipLaunchKernelGGL(k_sel_init, dim3(1), dim3(256), 0, s, p.st, k, p.hist);
+    SFG_LAUNCH_CHECK();
+    int64_t hb = (ne + kHistThreads * 16 - 1) / (kHistThreads * 16);
+    if (hb > 2048) hb = 2048;
+    if (hb < 1) hb = 1;
+    int hi = B;
+    bool first = true;
+    while (hi > 0) {
+        const int width = hi >= 11 ? 11 : hi;
+        const int shift = hi - width;
+        hipLaunchKernelGGL(k_sel_hist<TS>, dim3((uint32_t)hb), dim3(kHistThreads), 0, s, ne, score, p.st, shift,
+                           width, first ? 1 : 0, p.hist, p.st);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, p.st, p.hist, shift, width);
+        SFG_LAUNCH_CHECK();
+        hi = shift;
+        first = false;
+    }
+    hipLaunchKernelGGL(k_sel_flags<TS>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, score, p.st, p.flags);
+    SFG_LAUNCH_CHECK();
+    exclusive_scan_i32(p.flags, p.rank, ne, p.scan, s);
+    hipLaunchKernelGGL(k_sel_mark<TS>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, score, p.st, p.rank, sel, tau);
+    SFG_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+size_t select_workspace_bytes(int64_t ne) {
+    Carver c(nullptr);
+    plan_select(c, ne);
+    return c.used + 256;
+}
+
+void select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel, double *tau, void *ws,
+                 size_t ws_bytes, hipStream_t s) {
+    SFG_REQUIRE(ne >= 0 && k >= 0 && k <= ne, SFG_EINVAL, "select_topk: need 0 <= k <= ne");
+    SFG_REQUIRE(ne < (int64_t(1) << 31) - 1, SFG_EUNSUPPORTED, "select_topk: ne must be < 2^31-1");
+    SFG_REQUIRE(st == SFG_F64 || st == SFG_F32, SFG_EINVAL, "select_topk: scores must be F64 or F32");
+    SFG_REQUIRE(tau && (ne == 0 || (score && sel)), SFG_EINVAL, "select_topk: null pointer");
+    SFG_REQUIRE(ws_bytes >= select_workspace_bytes(ne), SFG_EWORKSPACE, "select_topk: workspace too small");
+    if (k == 0) {
+        fill_u8(sel, ne, 0, s);
+        hipLaunchKernelGGL(k_sel_empty, dim3(1), dim3(1), 0, s, tau);
+        SFG_LAUNCH_CHECK();
+        return;
+    }
+    Carver c(ws);
+    SelPlan p = plan_select(c, ne);
+    if (st == SFG_F64)
+        run_select<double>((const double *)score, ne, k, sel, tau, p, s);
+    else
+        run_select<float>((const float *)score, ne, k, sel, tau, p, s);
+}
+
+}  // namespace sfg
+
+extern "C" sfg_status sfg_select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel,
+                                      double *tau, double *tau_host, void *ws, size_t ws_bytes, void *stream) {
+    return sfg::guard([&] {
+        hipStream_t s = sfg::as_stream(stream);
+        sfg::select_topk(score, st, ne, k, sel, tau, ws, ws_bytes, s);
+        if (tau_host) {
+            SFG_HIP(hipMemcpyAsync(tau_host, tau, sizeof(double), hipMemcpyDeviceToHost, s));
+            SFG_HIP(hipStreamSynchronize(s));
+            if (*tau_host != *tau_host) sfg::fail(SFG_ENUMERIC, "select_topk: NaN or negative score");
+        }
+    });
+}

@@ -1,0 +1,419 @@
+// Sparsifier driver (the problem of Sec. 2.2, Alg. 1) and its host-side
+// helpers: input validation, candidate compaction, the maximum-weight
+// spanning tree, and workspace sizing.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <numeric>
+#include <vector>
+
+#include "common.hpp"
+
+namespace sfg {
+
+// from the other translation units
+size_t csr_workspace_bytes(int64_t n, int64_t m);
+void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+               const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val, int32_t *eid, void *deg, void *ws,
+               size_t ws_bytes, hipStream_t s);
+size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
+void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
+            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s);
+void edge_scores(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t ne, const int32_t *cand,
+                 const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt, void *score, sfg_dtype st,
+                 hipStream_t s);
+size_t select_workspace_bytes(int64_t ne);
+void select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel, double *tau, void *ws,
+                 size_t ws_bytes, hipStream_t s);
+size_t affinity_workspace_bytes(int64_t n, int32_t k);
+size_t coarsen_workspace_bytes(int64_t n, int64_t m);
+void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, const double *x0, int64_t n_cand,
+                  const int32_t *cand, const int32_t *u, const int32_t *v, const double *w64, const float *score_lo,
+                  int64_t k_sel, double tau_lo, double band, uint8_t *sel, sfg_level_report *rep, hipStream_t s);
+void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                         const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep, hipStream_t s);
+
+// ------------------------------------------------------------------ device arena (sfg_sparsify only)
+
+DevArena::DevArena(hipStream_t st) : s(st) {
+    const char *e = getenv("SFG_FAIL_ALLOC_AFTER");
+    fail_after = e ? atol(e) : -1;
+}
+
+DevArena::~DevArena() {
+    for (void *p : ptrs) (void)hipFreeAsync(p, s);
+}
+
+void *DevArena::raw(size_t bytes) {
+    if (fail_after >= 0 && count >= fail_after) fail(SFG_ENOMEM, "device allocation failed (SFG_FAIL_ALLOC_AFTER)");
+    void *p = nullptr;
+    hipError_t e = hipMallocAsync(&p, bytes < 256 ? 256 : bytes, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(SFG_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) + " bytes failed: " +
+                             hipGetErrorString(e));
+    }
+    ptrs.push_back(p);
+    ++count;
+    return p;
+}
+
+// ------------------------------------------------------------------ validation
+
+namespace {
+
+template <typename TW>
+__global__ void k_validate(int64_t n, int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                           const TW *__restrict__ w, uint32_t *flag) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const int32_t a = u[e], b = v[e];
+    uint32_t bad = 0;
+    if (a < 0 || b >= n || a >= b) bad |= 1u;
+    if (e > 0) {
+        const int32_t pa = u[e - 1], pb = v[e - 1];
+        if (!(pa < a || (pa == a && pb < b))) bad |= 2u;
+    }
+    const double we = (double)w[e];
+    if (!(we > 0.0) || !(we < __builtin_inf())) bad |= 4u;
+    if (bad) atomicOr(flag, bad);
+}
+
+__global__ void k_flags_eq(int64_t m, const uint8_t *__restrict__ mask, uint8_t want, int32_t *flags) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) flags[e] = (mask[e] == want) ? 1 : 0;
+}
+
+__global__ void k_scatter_ids(int64_t m, const int32_t *__restrict__ flags, const int32_t *__restrict__ pos,
+                              int32_t *out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m && flags[e]) out[pos[e]] = (int32_t)e;
+}
+
+__global__ void k_f64_to_f32(int64_t m, const double *__restrict__ a, float *__restrict__ b) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) b[e] = (float)a[e];
+}
+
+__global__ void k_f32_to_f64(int64_t m, const float *__restrict__ a, double *__restrict__ b) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) b[e] = (double)a[e];
+}
+
+__global__ void k_keep_init(int64_t m, const uint8_t *__restrict__ base, uint8_t *keep) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) keep[e] = base[e] ? 1 : 0;
+}
+
+__global__ void k_keep_add(int64_t nc, const int32_t *__restrict__ cand, const uint8_t *__restrict__ sel,
+                           uint8_t *keep) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc && sel[i]) keep[cand[i]] = 2;
+}
+
+}  // namespace
+
+void validate_edges(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                    DevArena &A, hipStream_t s) {
+    SFG_REQUIRE(n >= 1 && m >= 0, SFG_EINVAL, "edge list: need n >= 1, m >= 0");
+    SFG_REQUIRE(wt == SFG_F64 || wt == SFG_F32, SFG_EINVAL, "edge list: weights must be F64 or F32");
+    if (m == 0) return;
+    uint32_t *flag = A.alloc<uint32_t>(1);
+    fill_i32(reinterpret_cast<int32_t *>(flag), 1, 0, s);
+    if (wt == SFG_F64)
+        hipLaunchKernelGGL(k_validate<double>, dim3(grid_for(m, 256)), dim3(256), 0, s, n, m, u, v,
+                           (const double *)w, flag);
+    else
+        hipLaunchKernelGGL(k_validate<float>, dim3(grid_for(m, 256)), dim3(256), 0, s, n, m, u, v, (const float *)w,
+                           flag);
+    SFG_LAUNCH_CHECK();
+    uint32_t h = 0;
+    SFG_HIP(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    if (h & 1u) fail(SFG_EINVAL, "edge list: an edge has u >= v or an id out of range");
+    if (h & 2u) fail(SFG_EINVAL, "edge list: not sorted by (u, v) or has duplicates");
+    if (h & 4u) fail(SFG_EINVAL, "edge list: a weight is not finite and positive");
+}
+
+// Edge ids e with mask[e] == want, ascending; returns their count (synchronises).
+int64_t compact_ids(const uint8_t *mask, uint8_t want, int64_t m, int32_t *out, DevArena &A, hipStream_t s) {
+    if (m == 0) return 0;
+    int32_t *flags = A.alloc<int32_t>(m + 1);
+    int32_t *pos = A.alloc<int32_t>(m + 1);
+    int32_t *scr = A.alloc<int32_t>(scan_scratch_ints(m + 1));
+    hipLaunchKernelGGL(k_flags_eq, dim3(grid_for(m, 256)), dim3(256), 0, s, m, mask, want, flags);
+    SFG_LAUNCH_CHECK();
+    exclusive_scan_i32(flags, pos, m, scr, s);
+    hipLaunchKernelGGL(k_scatter_ids, dim3(grid_for(m, 256)), dim3(256), 0, s, m, flags, pos, out);
+    SFG_LAUNCH_CHECK();
+    int32_t cnt = 0;
+    SFG_HIP(hipMemcpyAsync(&cnt, pos + m, sizeof(cnt), hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    return cnt;
+}
+
+void convert_weights(const void *w, sfg_dtype wt, sfg_dtype want, int64_t m, void *out, hipStream_t s) {
+    if (m == 0) return;
+    if (wt == want) {
+        SFG_HIP(hipMemcpyAsync(out, w, (size_t)m * dtype_size(wt), hipMemcpyDeviceToDevice, s));
+    } else if (wt == SFG_F64 && want == SFG_F32) {
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(m, 256)), dim3(256), 0, s, m, (const double *)w, (float *)out);
+    } else if (wt == SFG_F32 && want == SFG_F64) {
+        hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(m, 256)), dim3(256), 0, s, m, (const float *)w, (double *)out);
+    } else {
+        fail(SFG_EINVAL, "weights: unsupported conversion");
+    }
+    SFG_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ maximum-weight spanning tree
+// Kruskal on the host over (weight desc, edge id asc).  The tree is input
+// preparation for the scoring passes, computed once per graph.
+
+int64_t spanning_tree_host(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                           const uint8_t *allowed, uint8_t *in_tree, hipStream_t s) {
+    std::vector<int32_t> hu(m), hv(m);
+    std::vector<double> hw(m);
+    std::vector<uint8_t> hal;
+    if (m > 0) {
+        SFG_HIP(hipMemcpyAsync(hu.data(), u, m * 4, hipMemcpyDeviceToHost, s));
+        SFG_HIP(hipMemcpyAsync(hv.data(), v, m * 4, hipMemcpyDeviceToHost, s));
+        if (wt == SFG_F64) {
+            SFG_HIP(hipMemcpyAsync(hw.data(), w, m * 8, hipMemcpyDeviceToHost, s));
+        } else {
+            std::vector<float> f(m);
+            SFG_HIP(hipMemcpyAsync(f.data(), w, m * 4, hipMemcpyDeviceToHost, s));
+            SFG_HIP(hipStreamSynchronize(s));
+            for (int64_t e = 0; e < m; ++e) hw[e] = f[e];
+        }
+        if (allowed) {
+            hal.resize(m);
+            SFG_HIP(hipMemcpyAsync(hal.data(), allowed, m, hipMemcpyDeviceToHost, s));
+        }
+        SFG_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int32_t> ord;
+    ord.reserve(m);
+    for (int64_t e = 0; e < m; ++e)
+        if (!allowed || hal[e]) ord.push_back((int32_t)e);
+    std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
+        if (hw[a] != hw[b]) return hw[a] > hw[b];
+        return a < b;
+    });
+    std::vector<int32_t> par(n);
+    std::iota(par.begin(), par.end(), 0);
+    auto find = [&](int32_t x) {
+        while (par[x] != x) {
+            par[x] = par[par[x]];
+            x = par[x];
+        }
+        return x;
+    };
+    std::vector<uint8_t> t(m, 0);
+    int64_t comps = n;
+    for (int32_t e : ord) {
+        int32_t a = find(hu[e]), b = find(hv[e]);
+        if (a == b) continue;
+        if (a < b) par[b] = a; else par[a] = b;
+        t[e] = 1;
+        --comps;
+    }
+    if (m > 0) {
+        SFG_HIP(hipMemcpyAsync(in_tree, t.data(), m, hipMemcpyHostToDevice, s));
+        SFG_HIP(hipStreamSynchronize(s));
+    }
+    return comps;
+}
+
+// ------------------------------------------------------------------ one scoring pass
+
+namespace {
+
+struct Timer {
+    hipEvent_t a, b;
+    hipStream_t s;
+    explicit Timer(hipStream_t st) : s(st) {
+        SFG_HIP(hipEventCreate(&a));
+        SFG_HIP(hipEventCreate(&b));
+    }
+    ~Timer() {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    void start() { SFG_HIP(hipEventRecord(a, s)); }
+    float stop() {
+        SFG_HIP(hipEventRecord(b, s));
+        SFG_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        SFG_HIP(hipEventElapsedTime(&ms, a, b));
+        return ms;
+    }
+};
+
+}  // namespace
+
+// Embed (smooth on the scoring graph), score the edges outside `base`, add
+// the top ceil(frac * n_cand) of them.  Writes keep (1 = base, 2 = added).
+void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
+                 const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
+                 DevArena &A, hipStream_t s) {
+    const bool f64 = p->storage == SFG_F64;
+    const sfg_dtype vt = f64 ? SFG_F64 : SFG_F32;
+    const void *wv = f64 ? (const void *)w64 : (const void *)w32;
+    const uint8_t *hmask = (p->embed == SFG_EMBED_GRAPH) ? nullptr : base;
+    Timer tm(s);
+    tm.start();
+    // scoring graph H
+    int32_t *rowptr = A.alloc<int32_t>(n + 1);
+    int32_t *col = A.alloc<int32_t>(2 * m + 1);
+    int32_t *eid = A.alloc<int32_t>(2 * m + 1);
+    void *val = A.raw((2 * m + 1) * dtype_size(vt));
+    void *deg = A.raw(n * dtype_size(vt));
+    size_t wsb = csr_workspace_bytes(n, m);
+    void *ws = A.raw(wsb);
+    build_csr(n, m, u, v, wv, vt, hmask, rowptr, col, val, eid, deg, ws, wsb, s);
+    int32_t nnz = 0;
+    SFG_HIP(hipMemcpyAsync(&nnz, rowptr + n, 4, hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    sfg_csr H{n, nnz, rowptr, col, val, eid, deg, vt};
+    // embedding
+    const bool f32last = p->final_f32 && (p->storage == SFG_F16 || p->storage == SFG_BF16);
+    const sfg_dtype xt = f32last ? SFG_F32 : p->storage;
+    void *x = A.raw((size_t)n * p->k * dtype_size(xt));
+    size_t wss = smooth_workspace_bytes(n, p->k, p->storage);
+    void *wsm = A.raw(wss);
+    float ms_other = tm.stop();
+    tm.start();
+    smooth(&H, p->k, p->sweeps, p->omega, x0, p->storage, p->final_f32, x, wsm, wss, s);
+    float ms_smooth = tm.stop();
+    // candidates: edges outside the current sparsifier, ascending id
+    tm.start();
+    int32_t *cand = A.alloc<int32_t>(m + 1);
+    const int64_t nc = compact_ids(base, 0, m, cand, A, s);
+    const sfg_dtype st = f64 ? SFG_F64 : SFG_F32;
+    void *score = A.raw((nc + 1) * dtype_size(st));
+    edge_scores(x, xt, n, p->k, nc, cand, u, v, wv, vt, score, st, s);
+    float ms_score = tm.stop();
+    tm.start();
+    const int64_t ksel = (int64_t)std::ceil(p->frac * (double)nc);
+    uint8_t *sel = A.alloc<uint8_t>(nc + 1);
+    double *tau = A.alloc<double>(1);
+    size_t wsel = select_workspace_bytes(nc);
+    void *wse = A.raw(wsel);
+    select_topk(score, st, nc, ksel, sel, tau, wse, wsel, s);
+    double tau_h = 0;
+    SFG_HIP(hipMemcpyAsync(&tau_h, tau, 8, hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    if (tau_h != tau_h) fail(SFG_ENUMERIC, "sparsify: NaN or negative edge score");
+    if (rep) {
+        rep->n = n;
+        rep->m = m;
+        rep->n_cand = nc;
+        rep->k_sel = ksel;
+        rep->tau = tau_h;
+        rep->band = 0;
+        rep->band_above = 0;
+        rep->band_rounds = 0;
+    }
+    if (!f64 && p->band > 0.0 && ksel > 0 && ksel < nc) {
+        // precision form: FP64 re-scoring of the edges near the threshold
+        int32_t *rowptr64 = rowptr;
+        void *val64 = val, *deg64 = deg;
+        int32_t *col64 = col, *eid64 = eid;
+        val64 = A.raw((2 * m + 1) * 8);
+        deg64 = A.raw(n * 8);
+        rowptr64 = A.alloc<int32_t>(n + 1);
+        col64 = A.alloc<int32_t>(2 * m + 1);
+        eid64 = A.alloc<int32_t>(2 * m + 1);
+        build_csr(n, m, u, v, w64, SFG_F64, hmask, rowptr64, col64, val64, eid64, deg64, ws, wsb, s);
+        sfg_csr H64{n, nnz, rowptr64, col64, val64, eid64, deg64, SFG_F64};
+        band_rescore(&H64, p->k, p->sweeps, p->omega, x0, nc, cand, u, v, w64, (const float *)score, ksel, tau_h,
+                     p->band, sel, rep, s);
+    }
+    hipLaunchKernelGGL(k_keep_init, dim3(grid_for(m, 256)), dim3(256), 0, s, m, base, keep);
+    SFG_LAUNCH_CHECK();
+    if (nc > 0) {
+        hipLaunchKernelGGL(k_keep_add, dim3(grid_for(nc, 256)), dim3(256), 0, s, nc, cand, sel, keep);
+        SFG_LAUNCH_CHECK();
+    }
+    float ms_select = tm.stop();
+    if (rep) {
+        rep->ms_smooth = ms_smooth;
+        rep->ms_score = ms_score;
+        rep->ms_select = ms_select;
+        rep->ms_other = ms_other;
+    }
+}
+
+void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                           const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep, DevArena &A,
+                           hipStream_t s) {
+    double *w64 = A.alloc<double>(m + 1);
+    convert_weights(w, wt, SFG_F64, m, w64, s);
+    float *w32 = nullptr;
+    if (p->storage != SFG_F64) {
+        w32 = A.alloc<float>(m + 1);
+        convert_weights(w, wt, SFG_F32, m, w32, s);
+    }
+    uint8_t *tree = A.alloc<uint8_t>(m + 1);
+    const int64_t comps = spanning_tree_host(n, m, u, v, w64, SFG_F64, nullptr, tree, s);
+    if (comps != 1) fail(SFG_ENOTCONN, "sparsify: graph has " + std::to_string(comps) + " components");
+    sfg_level_report *lr = rep ? &rep->level[0] : nullptr;
+    if (rep) rep->levels = 1;
+    score_level(n, m, u, v, w64, w32, tree, p, x0, keep, lr, A, s);
+}
+
+void check_params(const sfg_params *p) {
+    SFG_REQUIRE(p, SFG_EINVAL, "sparsify: null params");
+    SFG_REQUIRE(p->levels >= 1 && p->levels <= 16, SFG_EINVAL, "sparsify: levels must be in [1, 16]");
+    SFG_REQUIRE(p->k >= 1, SFG_EINVAL, "sparsify: k must be >= 1");
+    SFG_REQUIRE(p->k <= 64, SFG_EUNSUPPORTED, "sparsify: k > 64 is not supported");
+    SFG_REQUIRE(p->sweeps >= 0, SFG_EINVAL, "sparsify: sweeps must be >= 0");
+    SFG_REQUIRE(p->omega > 0.0 && p->omega <= 1.0, SFG_EINVAL, "sparsify: omega must be in (0, 1]");
+    SFG_REQUIRE(p->frac >= 0.0 && p->frac <= 1.0, SFG_EINVAL, "sparsify: frac must be in [0, 1]");
+    SFG_REQUIRE(p->embed == SFG_EMBED_SPARSIFIER || p->embed == SFG_EMBED_GRAPH, SFG_EINVAL, "sparsify: bad embed");
+    SFG_REQUIRE(valid_dtype(p->storage), SFG_EINVAL, "sparsify: bad storage dtype");
+    SFG_REQUIRE(p->band >= 0.0 && p->band < 1.0, SFG_EINVAL, "sparsify: band must be in [0, 1)");
+}
+
+}  // namespace sfg
+
+extern "C" size_t sfg_workspace_bytes(int op, int64_t n, int64_t m, int32_t k, sfg_dtype t) {
+    switch (op) {
+        case SFG_OP_LAPLACIAN_CSR: return sfg::csr_workspace_bytes(n < 1 ? 1 : n, m);
+        case SFG_OP_SMOOTH: return sfg::smooth_workspace_bytes(n < 1 ? 1 : n, k < 1 ? 1 : k, t);
+        case SFG_OP_SELECT_TOPK: return sfg::select_workspace_bytes(m < 0 ? 0 : m);
+        case SFG_OP_AFFINITY: return sfg::affinity_workspace_bytes(n < 1 ? 1 : n, k < 1 ? 1 : k);
+        case SFG_OP_COARSEN: return sfg::coarsen_workspace_bytes(n < 1 ? 1 : n, m < 0 ? 0 : m);
+        default: return 0;
+    }
+}
+
+extern "C" sfg_status sfg_spanning_tree(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w,
+                                        sfg_dtype wt, const uint8_t *allowed, uint8_t *in_tree, int64_t *n_comp,
+                                        void *stream) {
+    return sfg::guard([&] {
+        SFG_REQUIRE(n >= 1 && m >= 0, SFG_EINVAL, "spanning_tree: bad sizes");
+        SFG_REQUIRE(wt == SFG_F64 || wt == SFG_F32, SFG_EINVAL, "spanning_tree: weights must be F64 or F32");
+        SFG_REQUIRE(n_comp, SFG_EINVAL, "spanning_tree: n_comp is required");
+        *n_comp = sfg::spanning_tree_host(n, m, u, v, w, wt, allowed, in_tree, sfg::as_stream(stream));
+    });
+}
+
+extern "C" sfg_status sfg_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w,
+                                   sfg_dtype wt, const sfg_params *p, const double *x0, uint8_t *keep,
+                                   sfg_report *rep, void *stream) {
+    return sfg::guard([&] {
+        hipStream_t s = sfg::as_stream(stream);
+        sfg::check_params(p);
+        SFG_REQUIRE(x0 && keep, SFG_EINVAL, "sparsify: null pointer");
+        sfg::DevArena A(s);
+        sfg::validate_edges(n, m, u, v, w, wt, A, s);
+        if (rep) std::memset(rep, 0, sizeof(*rep));
+        if (p->levels == 1)
+            sfg::single_level_sparsify(n, m, u, v, w, wt, p, x0, keep, rep, A, s);
+        else
+            sfg::multilevel_sparsify(n, m, u, v, w, wt, p, x0, keep, rep, s);
+        SFG_HIP(hipStreamSynchronize(s));
+    });
+}

@@ -1,0 +1,284 @@
+"""Python binding of libsfg (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own: it allocates outputs and workspaces as torch device
+tensors, passes their pointers and torch's current stream, and turns a
+non-OK status into :class:`SfgError`.  If ``libsfg.so`` has not been built
+the binding raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfg.so")
+
+# sfg_dtype
+F64, F32, F16, BF16 = 0, 1, 2, 3
+_TORCH_TO_SFG = {torch.float64: F64, torch.float32: F32, torch.float16: F16, torch.bfloat16: BF16}
+_SFG_TO_TORCH = {v: k for k, v in _TORCH_TO_SFG.items()}
+
+# sfg_op
+OP_LAPLACIAN_CSR, OP_SMOOTH, OP_SELECT_TOPK, OP_AFFINITY, OP_COARSEN = 0, 1, 2, 3, 4
+EMBED_SPARSIFIER, EMBED_GRAPH = 0, 1
+
+STATUS = {0: "SFG_OK", 1: "SFG_EINVAL", 2: "SFG_ENOTCONN", 3: "SFG_ENOMEM", 4: "SFG_EHIP",
+          5: "SFG_EWORKSPACE", 6: "SFG_EUNSUPPORTED", 7: "SFG_ENUMERIC"}
+
+EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores",
+            "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify"]
+
+
+class SfgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class CsrStruct(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("rowptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("val", ctypes.c_void_p), ("eid", ctypes.c_void_p),
+                ("deg", ctypes.c_void_p), ("vt", ctypes.c_int)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("k", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("omega", ctypes.c_double), ("frac", ctypes.c_double), ("embed", ctypes.c_int32),
+                ("storage", ctypes.c_int), ("final_f32", ctypes.c_int32), ("band", ctypes.c_double)]
+
+
+class LevelReport(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("n_cand", ctypes.c_int64),
+                ("k_sel", ctypes.c_int64), ("tau", ctypes.c_double), ("band", ctypes.c_int64),
+                ("band_above", ctypes.c_int64), ("band_rounds", ctypes.c_int32),
+                ("ms_smooth", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_select", ctypes.c_float),
+                ("ms_other", ctypes.c_float)]
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("level", LevelReport * 16)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsfg.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_2008_07633_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, I32, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int
+        S, D = ctypes.c_size_t, ctypes.c_double
+        L.sfg_workspace_bytes.argtypes = [I, I64, I64, I32, I]
+        L.sfg_workspace_bytes.restype = S
+        L.sfg_last_error.argtypes = []
+        L.sfg_last_error.restype = ctypes.c_char_p
+        L.sfg_laplacian_csr.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P, P, P, P, S, P]
+        L.sfg_smooth.argtypes = [P, I32, I32, D, P, I, I32, P, P, S, P]
+        L.sfg_edge_scores.argtypes = [P, I, I64, I32, I64, P, P, P, P, I, P, I, P]
+        L.sfg_select_topk.argtypes = [P, I, I64, I64, P, P, P, P, S, P]
+        L.sfg_spanning_tree.argtypes = [I64, I64, P, P, P, I, P, P, P, P]
+        L.sfg_affinity.argtypes = [P, I, I64, I32, I64, P, P, P, I, P, S, P]
+        L.sfg_coarsen.argtypes = [P, I64, P, P, P, I, P, I, P, P, P, P, P, P, P, P, S, P]
+        L.sfg_sparsify.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P]
+        for name in EXPORTED:
+            if name not in ("sfg_workspace_bytes", "sfg_last_error"):
+                getattr(L, name).restype = I
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = lib().sfg_last_error()
+        raise SfgError(status, msg.decode() if msg else "")
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libsfg takes device tensors")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dt(t: torch.Tensor) -> int:
+    return _TORCH_TO_SFG[t.dtype]
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def sfg_workspace_bytes(op: int, n: int, m: int, k: int, dtype) -> int:
+    t = dtype if isinstance(dtype, int) else _TORCH_TO_SFG[dtype]
+    return int(lib().sfg_workspace_bytes(op, n, m, k, t))
+
+
+@dataclass
+class Csr:
+    """Device CSR of the adjacency plus the degree vector (views of torch tensors)."""
+    n: int
+    nnz: int
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+    eid: torch.Tensor
+    deg: torch.Tensor
+
+    def struct(self) -> CsrStruct:
+        return CsrStruct(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(),
+                         self.eid.data_ptr(), self.deg.data_ptr(), _TORCH_TO_SFG[self.val.dtype])
+
+
+def sfg_laplacian_csr(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
+                      mask: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None,
+                      out: Optional[Csr] = None, nnz: Optional[int] = None) -> Csr:
+    """CSR of A and the degrees D of the graph (L = D - A).  With ``out`` and
+    ``nnz`` given nothing is allocated and the call does not synchronise."""
+    m = int(u.shape[0])
+    dev = u.device
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_LAPLACIAN_CSR, n, m, 0, w.dtype), dev)
+    if out is None:
+        cap = 2 * m if mask is None else 2 * int(mask.sum().item())
+        out = Csr(n, cap, torch.empty(n + 1, dtype=torch.int32, device=dev),
+                  torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                  torch.empty(max(cap, 1), dtype=w.dtype, device=dev),
+                  torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                  torch.empty(n, dtype=w.dtype, device=dev))
+    got = ctypes.c_int64(0)
+    _check(lib().sfg_laplacian_csr(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(mask), _ptr(out.rowptr),
+                                   _ptr(out.col), _ptr(out.val), _ptr(out.eid), _ptr(out.deg),
+                                   None if nnz is not None else ctypes.byref(got), _ptr(ws), ws.numel(),
+                                   _stream()))
+    out.nnz = int(nnz) if nnz is not None else int(got.value)
+    return out
+
+
+def sfg_smooth(H: Csr, x0: torch.Tensor, sweeps: int, omega: float = 0.5, storage=torch.float64,
+               final_f32: bool = False, out: Optional[torch.Tensor] = None,
+               ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Centre the n-by-k FP64 block x0 and smooth it with damped-Jacobi sweeps on H."""
+    n, k = int(x0.shape[0]), int(x0.shape[1])
+    st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
+    odt = torch.float32 if (final_f32 and st in (F16, BF16)) else _SFG_TO_TORCH[st]
+    if out is None:
+        out = torch.empty((n, k), dtype=odt, device=x0.device)
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_SMOOTH, n, 0, k, st), x0.device)
+    hs = H.struct()
+    _check(lib().sfg_smooth(ctypes.byref(hs), k, sweeps, float(omega), _ptr(x0), st, int(bool(final_f32)),
+                            _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def sfg_edge_scores(x: torch.Tensor, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
+                    cand: Optional[torch.Tensor] = None, score_dtype=None,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """w_e * |x_u - x_v|^2 for every candidate edge (all edges if cand is None)."""
+    n, k = int(x.shape[0]), int(x.shape[1])
+    ne = int(cand.shape[0]) if cand is not None else int(u.shape[0])
+    sdt = score_dtype or (torch.float64 if x.dtype == torch.float64 else torch.float32)
+    if out is None:
+        out = torch.empty(max(ne, 1), dtype=sdt, device=x.device)[:ne]
+    _check(lib().sfg_edge_scores(_ptr(x), _dt(x), n, k, ne, _ptr(cand), _ptr(u), _ptr(v), _ptr(w), _dt(w),
+                                 _ptr(out), _TORCH_TO_SFG[out.dtype], _stream()))
+    return out
+
+
+def sfg_select_topk(score: torch.Tensor, k: int, sel: Optional[torch.Tensor] = None,
+                    tau: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, sync: bool = True):
+    """Mark the top k scores (ties: lower position first).  Returns (sel, tau)."""
+    ne = int(score.shape[0])
+    dev = score.device
+    if sel is None:
+        sel = torch.empty(max(ne, 1), dtype=torch.uint8, device=dev)[:ne]
+    if tau is None:
+        tau = torch.empty(1, dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_SELECT_TOPK, 0, ne, 0, score.dtype), dev)
+    th = ctypes.c_double(0.0)
+    _check(lib().sfg_select_topk(_ptr(score), _dt(score), ne, int(k), _ptr(sel), _ptr(tau),
+                                 ctypes.byref(th) if sync else None, _ptr(ws), ws.numel(), _stream()))
+    return sel, (th.value if sync else tau)
+
+
+def sfg_spanning_tree(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
+                      allowed: Optional[torch.Tensor] = None):
+    """Maximum-weight spanning forest (weight desc, edge id asc).  Returns (in_tree, n_components)."""
+    m = int(u.shape[0])
+    out = torch.empty(max(m, 1), dtype=torch.uint8, device=u.device)[:m]
+    nc = ctypes.c_int64(0)
+    _check(lib().sfg_spanning_tree(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(allowed), _ptr(out),
+                                   ctypes.byref(nc), _stream()))
+    return out, int(nc.value)
+
+
+def sfg_affinity(x: torch.Tensor, u: torch.Tensor, v: torch.Tensor, aff_dtype=None,
+                 out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    n, k = int(x.shape[0]), int(x.shape[1])
+    m = int(u.shape[0])
+    adt = aff_dtype or x.dtype
+    if out is None:
+        out = torch.empty(max(m, 1), dtype=adt, device=x.device)[:m]
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_AFFINITY, n, m, k, x.dtype), x.device)
+    _check(lib().sfg_affinity(_ptr(x), _dt(x), n, k, m, _ptr(u), _ptr(v), _ptr(out), _dt(out), _ptr(ws),
+                              ws.numel(), _stream()))
+    return out
+
+
+def sfg_coarsen(G: Csr, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, aff: torch.Tensor,
+                ws: Optional[torch.Tensor] = None):
+    """One coarsening step.  Returns (agg, cu, cv, cw, crep) trimmed to the coarse sizes."""
+    m = int(u.shape[0])
+    dev = u.device
+    agg = torch.empty(G.n, dtype=torch.int32, device=dev)
+    cu = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    cv = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    cw = torch.empty(max(m, 1), dtype=w.dtype, device=dev)
+    crep = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_COARSEN, G.n, m, 0, w.dtype), dev)
+    nc, mc = ctypes.c_int64(0), ctypes.c_int64(0)
+    gs = G.struct()
+    _check(lib().sfg_coarsen(ctypes.byref(gs), m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(aff), _dt(aff),
+                             _ptr(agg), ctypes.byref(nc), ctypes.byref(mc), _ptr(cu), _ptr(cv), _ptr(cw),
+                             _ptr(crep), _ptr(ws), ws.numel(), _stream()))
+    mc = int(mc.value)
+    return agg, int(nc.value), cu[:mc], cv[:mc], cw[:mc], crep[:mc]
+
+
+def make_params(levels=1, k=8, sweeps=10, omega=0.5, frac=0.05, embed=EMBED_SPARSIFIER, storage=F64,
+                final_f32=False, band=0.0) -> Params:
+    st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
+    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band)
+
+
+def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: torch.Tensor,
+                 params: Params, keep: Optional[torch.Tensor] = None):
+    """Sparsifier keep mask (0 off, 1 base sparsifier, 2 recovered) and the per-level report."""
+    m = int(u.shape[0])
+    if keep is None:
+        keep = torch.empty(max(m, 1), dtype=torch.uint8, device=u.device)[:m]
+    rep = Report()
+    _check(lib().sfg_sparsify(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), ctypes.byref(params), _ptr(x0),
+                              _ptr(keep), ctypes.byref(rep), _stream()))
+    levels = []
+    for i in range(rep.levels):
+        L = rep.level[i]
+        levels.append({f: getattr(L, f) for f, _ in LevelReport._fields_})
+    return keep, levels

@@ -1,0 +1,80 @@
+"""The C-ABI library loads and exports every entry point the header declares.
+
+Runs without a GPU: only host-side calls (workspace sizing, argument checks
+that fail before any device work) are made.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sfg.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(sfg_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2008_07633_amd import sfg
+
+    return sfg.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_symbols()
+    for required in ["sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores", "sfg_coarsen", "sfg_sparsify"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    from paper_2008_07633_amd import sfg
+
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+    assert sorted(sfg.EXPORTED) == declared_symbols()
+
+
+def test_workspace_sizes_are_host_only(L):
+    from paper_2008_07633_amd import sfg
+
+    a = sfg.sfg_workspace_bytes(sfg.OP_SMOOTH, 1000, 0, 16, sfg.F64)
+    b = sfg.sfg_workspace_bytes(sfg.OP_SMOOTH, 1000, 0, 16, sfg.F32)
+    assert a >= 2 * 1000 * 16 * 8 and b >= 2 * 1000 * 16 * 4 and a > b
+    assert sfg.sfg_workspace_bytes(sfg.OP_LAPLACIAN_CSR, 100, 300, 0, sfg.F64) > 5 * 101 * 4
+    assert sfg.sfg_workspace_bytes(sfg.OP_SELECT_TOPK, 0, 10000, 0, sfg.F64) > 2 * 10000 * 4
+    assert sfg.sfg_workspace_bytes(99, 1, 1, 1, sfg.F64) == 0
+
+
+def test_argument_errors_before_device_work(L):
+    from paper_2008_07633_amd import sfg
+
+    H = sfg.CsrStruct(0, 0, None, None, None, None, None, sfg.F64)
+    st = L.sfg_smooth(ctypes.byref(H), 4, 1, 0.5, None, sfg.F64, 0, None, None, 0, None)
+    assert sfg.STATUS[st] == "SFG_EINVAL"
+    assert b"null pointer" in L.sfg_last_error()
+    p = sfg.make_params(k=100)
+    st = L.sfg_sparsify(10, 0, None, None, None, sfg.F64, ctypes.byref(p), None, None, None, None)
+    assert sfg.STATUS[st] == "SFG_EUNSUPPORTED"
+    p = sfg.make_params(omega=1.5)
+    st = L.sfg_sparsify(10, 0, None, None, None, sfg.F64, ctypes.byref(p), None, None, None, None)
+    assert sfg.STATUS[st] == "SFG_EINVAL"
+    st = L.sfg_select_topk(None, sfg.F64, 10, 11, None, None, None, None, 0, None)
+    assert sfg.STATUS[st] == "SFG_EINVAL"
+    st = L.sfg_edge_scores(None, sfg.F64, 10, 65, 1, None, None, None, None, sfg.F64, None, sfg.F64, None)
+    assert sfg.STATUS[st] == "SFG_EUNSUPPORTED"
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2008_07633_amd import sfg
+
+    monkeypatch.setattr(sfg, "_lib", None)
+    monkeypatch.setattr(sfg, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        sfg.lib()

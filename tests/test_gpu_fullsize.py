@@ -1,0 +1,65 @@
+"""Parity at the full power-grid size (1000 x 1000 mesh plus 2% diagonal
+shortcuts, 16 vectors, 20 sweeps, 10% recovery) in the launch configuration
+the benchmark times.  The oracle runs the whole pass on the CPU (seconds)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_powergrid_full_size_f64_identical(orc):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_07633_amd import sfg as S
+
+    g = W.config_graph(2)
+    prm = W.config_params(2)
+    X0 = W.config_block(2, g.n)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, prm["sweeps"], prm["frac"])
+    u, v, w = (torch.from_numpy(a).cuda() for a in (g.u, g.v, g.w))
+    x0 = torch.from_numpy(X0).cuda()
+    # the benchmark's pass: tree CSR, smoothing, candidate scores, selection
+    tree, comps = S.sfg_spanning_tree(g.n, u, v, w)
+    assert comps == 1
+    cand = torch.nonzero(tree == 0).reshape(-1).to(torch.int32)
+    H = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
+    X = S.sfg_smooth(H, x0, prm["sweeps"], 0.5, storage=torch.float64)
+    s = S.sfg_edge_scores(X, u, v, w, cand=cand)
+    k = orc.ksel(prm["frac"], int(cand.numel()))
+    sel, tau = S.sfg_select_topk(s, k)
+    lr = ref.levels[0]
+    assert np.array_equal(cand.cpu().numpy(), lr.cand)
+    assert np.array_equal(s.cpu().numpy(), lr.score)          # bitwise
+    got = cand[sel.bool()].cpu().numpy()
+    assert np.array_equal(np.sort(got), np.sort(lr.chosen))
+    assert tau == lr.tau
+    # the library driver gives the same sparsifier
+    keep, rep = S.sfg_sparsify(g.n, u, v, w, x0, S.make_params(k=prm["k"], sweeps=prm["sweeps"], frac=prm["frac"]))
+    assert np.array_equal(keep.cpu().numpy(), ref.keep)
+
+
+def test_powergrid_full_size_f32_close(orc):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_07633_amd import sfg as S
+
+    g = W.config_graph(2)
+    prm = W.config_params(2)
+    X0 = W.config_block(2, g.n)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, prm["sweeps"], prm["frac"])
+    lr = ref.levels[0]
+    u, v = torch.from_numpy(g.u).cuda(), torch.from_numpy(g.v).cuda()
+    w64 = torch.from_numpy(g.w).cuda()
+    w32 = w64.float()
+    tree, _ = S.sfg_spanning_tree(g.n, u, v, w64)
+    cand = torch.nonzero(tree == 0).reshape(-1).to(torch.int32)
+    H = S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree)
+    X = S.sfg_smooth(H, torch.from_numpy(X0).cuda(), prm["sweeps"], 0.5, storage=torch.float32)
+    s = S.sfg_edge_scores(X, u, v, w32, cand=cand).cpu().numpy().astype(np.float64)
+    err = orc.score_errors(s, lr.score, lr.tau)
+    # FP32 storage and arithmetic: ~20 sweeps x a few roundings of 6e-8
+    assert err["max_abs_over_tau"] < 1e-4, err
+    assert err["max_rel_selected_region"] < 1e-4, err

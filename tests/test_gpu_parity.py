@@ -1,0 +1,269 @@
+"""GPU parity: libsfg (through its C ABI) against the CPU FP64 oracle.
+
+FP64 paths are compared bit for bit: the GPU kernels add every row and every
+score in the oracle's order with one rounding per operation.  Reduced
+precision paths are compared with tolerances derived from their unit
+roundoff.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_07633_amd import sfg
+
+    sfg.lib()
+    return sfg
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+GRAPHS = {
+    "grid64": lambda: W.config_graph(1),
+    "rand1500": lambda: W.random_connected(1500, 4000, seed=71, wdist=("lognormal", 0.0, 1.0)),
+    "pgrid_97": lambda: W.powergrid(97, 103, 0.02, seed=72),
+    "mesh_13": lambda: W.mesh3d(13, 11, 9, seed=73),
+    "path2": lambda: W.grid2d(1, 2, seed=74),
+    "star": lambda: W.Graph(300, np.zeros(299, np.int32), np.arange(1, 300, dtype=np.int32),
+                            np.linspace(0.5, 2.0, 299), name="star"),
+}
+
+
+@pytest.fixture(scope="module", params=list(GRAPHS))
+def graph(request):
+    return GRAPHS[request.param]()
+
+
+# --------------------------------------------------------------------------- a1: Laplacian CSR
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_laplacian_csr_bitwise(S, orc, graph, masked):
+    g = graph
+    mask = None
+    if masked:
+        mask, _ = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    for wdt in (np.float64, np.float32):
+        w = g.w.astype(wdt)
+        sel = np.ones(g.m, bool) if mask is None else mask.astype(bool)
+        ref = orc.laplacian_csr(g.n, g.u[sel], g.v[sel], w[sel].astype(np.float64))
+        H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(w), mask=None if mask is None else dev(mask))
+        assert H.nnz == ref.col.shape[0]
+        assert np.array_equal(host(H.rowptr), ref.rowptr.astype(np.int32))
+        assert np.array_equal(host(H.col)[:H.nnz], ref.col)
+        ids = np.nonzero(sel)[0]
+        assert np.array_equal(host(H.eid)[:H.nnz], ids[ref.eid])
+        assert np.array_equal(host(H.val)[:H.nnz], ref.val.astype(wdt))
+        assert np.array_equal(host(H.deg), ref.deg.astype(wdt))
+
+
+# --------------------------------------------------------------------------- a2+a3: smoothing
+
+@pytest.mark.parametrize("k,sweeps", [(1, 3), (3, 5), (8, 10), (16, 20), (32, 4), (64, 2), (16, 0)])
+def test_smooth_f64_bitwise(S, orc, graph, k, sweeps):
+    g = graph
+    X0 = W.random_block(g.n, k, 100 + k)
+    ref_csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    Xc, _ = orc.center(X0)
+    ref = orc.smooth(ref_csr, Xc, sweeps, 0.5)
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w))
+    X = S.sfg_smooth(H, dev(X0), sweeps, 0.5, storage=torch.float64)
+    np.testing.assert_array_equal(host(X), ref)
+
+
+def test_smooth_omega_and_tree(S, orc):
+    g = W.powergrid(60, 70, 0.02, seed=75)
+    tree, _ = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    t = tree.astype(bool)
+    X0 = W.random_block(g.n, 16, 9)
+    ref_csr = orc.laplacian_csr(g.n, g.u[t], g.v[t], g.w[t])
+    for omega in (0.5, 0.3, 1.0):
+        ref = orc.smooth(ref_csr, orc.center(X0)[0], 7, omega)
+        H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w), mask=dev(tree))
+        X = S.sfg_smooth(H, dev(X0), 7, omega)
+        np.testing.assert_array_equal(host(X), ref)
+
+
+@pytest.mark.parametrize("storage,final_f32,tol", [
+    (torch.float32, False, 2e-5),
+    (torch.float16, True, 6e-3),
+    (torch.float16, False, 2e-2),
+    (torch.bfloat16, True, 5e-2),
+])
+def test_smooth_reduced_precision(S, orc, storage, final_f32, tol):
+    # Bound: every sweep is a convex combination, so the stored iterate carries
+    # at most ~(sweeps + 1) storage roundings of |X| scale; tol is that bound
+    # (u = 6e-8, 4.9e-4, 3.9e-3 for FP32, FP16, BF16) relative to max |X0|.
+    g = W.powergrid(80, 80, 0.02, seed=76)
+    k, T = 16, 20
+    X0 = W.random_block(g.n, k, 11)
+    ref = orc.smooth(orc.laplacian_csr(g.n, g.u, g.v, g.w), orc.center(X0)[0], T, 0.5)
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w.astype(np.float32)))
+    X = S.sfg_smooth(H, dev(X0), T, 0.5, storage=storage, final_f32=final_f32)
+    err = np.max(np.abs(host(X.float()).astype(np.float64) - ref)) / np.max(np.abs(X0))
+    assert err < tol, err
+
+
+# --------------------------------------------------------------------------- a4: scores and affinities
+
+def test_scores_f64_bitwise(S, orc, graph):
+    g = graph
+    k = 16
+    X = W.random_block(g.n, k, 5)
+    ref = orc.edge_scores(X, g.u, g.v, g.w)
+    s = S.sfg_edge_scores(dev(X), dev(g.u), dev(g.v), dev(g.w))
+    np.testing.assert_array_equal(host(s), ref)
+    # candidate subset (every third edge)
+    cand = np.arange(0, g.m, 3, dtype=np.int32)
+    s2 = S.sfg_edge_scores(dev(X), dev(g.u), dev(g.v), dev(g.w), cand=dev(cand))
+    np.testing.assert_array_equal(host(s2), ref[cand])
+
+
+@pytest.mark.parametrize("k", [1, 5, 8, 32, 64])
+def test_scores_and_affinity_shapes(S, orc, k):
+    g = W.random_connected(700, 1500, seed=77)
+    X = W.random_block(g.n, k, 6)
+    np.testing.assert_array_equal(host(S.sfg_edge_scores(dev(X), dev(g.u), dev(g.v), dev(g.w))),
+                                  orc.edge_scores(X, g.u, g.v, g.w))
+    a = S.sfg_affinity(dev(X), dev(g.u), dev(g.v))
+    np.testing.assert_array_equal(host(a), orc.affinity(orc.center(X)[0], g.u, g.v))
+
+
+def test_scores_reduced_precision(S, orc):
+    g = W.random_connected(2000, 6000, seed=78)
+    X = W.random_block(g.n, 32, 7)
+    ref = orc.edge_scores(X, g.u, g.v, g.w)
+    w32 = dev(g.w.astype(np.float32))
+    for xdt, tol in ((torch.float32, 1e-5), (torch.float16, 3e-2), (torch.bfloat16, 2e-1)):
+        s = S.sfg_edge_scores(dev(X).to(xdt), dev(g.u), dev(g.v), w32)
+        rel = np.abs(host(s).astype(np.float64) - ref) / np.max(ref)
+        assert rel.max() < tol, (xdt, rel.max())
+
+
+# --------------------------------------------------------------------------- a5: selection
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_select_topk_matches_sort(S, orc, dt):
+    rng = np.random.default_rng(8)
+    for ne, ties in ((1, False), (5000, True), (123457, False), (300000, True)):
+        s = rng.random(ne) * 10
+        if ties:
+            s = np.round(s * 16) / 16
+        s = s.astype(dt == torch.float64 and np.float64 or np.float32).astype(np.float64)
+        eid = np.arange(ne, dtype=np.int32)
+        for k in sorted({0, 1, ne // 7, ne // 2, ne}):
+            sel, tau = S.sfg_select_topk(dev(s, dt), k)
+            pos, tau_ref = orc.select_topk(s, eid, k)
+            want = np.zeros(ne, np.uint8)
+            want[pos] = 1
+            assert np.array_equal(host(sel), want), (ne, k)
+            if k:
+                assert tau == tau_ref
+            else:
+                assert tau == float("inf")
+
+
+def test_select_rejects_bad_scores(S):
+    s = torch.tensor([1.0, float("nan"), 3.0], dtype=torch.float64, device="cuda")
+    with pytest.raises(S.SfgError, match="SFG_ENUMERIC"):
+        S.sfg_select_topk(s, 1)
+    s = torch.tensor([1.0, -2.0, 3.0], dtype=torch.float64, device="cuda")
+    with pytest.raises(S.SfgError, match="SFG_ENUMERIC"):
+        S.sfg_select_topk(s, 2)
+    with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+        S.sfg_select_topk(s, 4)
+
+
+# --------------------------------------------------------------------------- spanning tree
+
+def test_spanning_tree(S, orc, graph):
+    g = graph
+    ref, comps = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    t, c = S.sfg_spanning_tree(g.n, dev(g.u), dev(g.v), dev(g.w))
+    assert c == comps == 1
+    assert np.array_equal(host(t), ref)
+
+
+# --------------------------------------------------------------------------- whole single-level pass
+
+@pytest.mark.parametrize("embed", ["sparsifier", "graph"])
+def test_sparsify_single_level_matches_oracle(S, orc, graph, embed):
+    g = graph
+    k, T, f = 8, 10, 0.05
+    X0 = W.random_block(g.n, k, 31)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, T, f, embed=embed)
+    p = S.make_params(k=k, sweeps=T, frac=f, embed=S.EMBED_GRAPH if embed == "graph" else S.EMBED_SPARSIFIER)
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), p)
+    assert np.array_equal(host(keep), ref.keep)
+    lr = ref.levels[0]
+    assert rep[0]["n_cand"] == lr.n_cand and rep[0]["k_sel"] == lr.k_sel
+    if lr.k_sel:
+        assert rep[0]["tau"] == lr.tau
+
+
+def test_sparsify_deterministic(S):
+    g = W.powergrid(120, 110, 0.02, seed=79)
+    X0 = dev(W.random_block(g.n, 16, 3))
+    p = S.make_params(k=16, sweeps=20, frac=0.1)
+    a, _ = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), X0, p)
+    b, _ = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), X0, p)
+    assert torch.equal(a, b)
+
+
+# --------------------------------------------------------------------------- error paths
+
+def test_sparsify_errors(S):
+    g = W.grid2d(10, 10, seed=80)
+    X0 = dev(W.random_block(g.n, 8, 1))
+    p = S.make_params()
+    # disconnected: drop every edge at node 0
+    keepe = (g.u != 0)
+    with pytest.raises(S.SfgError, match="SFG_ENOTCONN"):
+        S.sfg_sparsify(g.n, dev(g.u[keepe]), dev(g.v[keepe]), dev(g.w[keepe]), X0, p)
+    # malformed: swapped endpoints, unsorted, bad weight
+    u2, v2 = g.u.copy(), g.v.copy()
+    u2[3], v2[3] = v2[3], u2[3]
+    with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+        S.sfg_sparsify(g.n, dev(u2), dev(v2), dev(g.w), X0, p)
+    w2 = g.w.copy()
+    w2[5] = 0.0
+    with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+        S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(w2), X0, p)
+    with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+        S.sfg_sparsify(g.n, dev(g.u[::-1].copy()), dev(g.v[::-1].copy()), dev(g.w), X0, p)
+    # injected allocation failure
+    os.environ["SFG_FAIL_ALLOC_AFTER"] = "3"
+    try:
+        with pytest.raises(S.SfgError, match="SFG_ENOMEM"):
+            S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), X0, p)
+    finally:
+        del os.environ["SFG_FAIL_ALLOC_AFTER"]
+    keep, _ = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), X0, p)   # still works afterwards
+    assert int((keep == 1).sum()) == g.n - 1
+
+
+def test_workspace_too_small(S):
+    g = W.grid2d(8, 8, seed=81)
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w))
+    ws = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.SfgError, match="SFG_EWORKSPACE"):
+        S.sfg_smooth(H, dev(W.random_block(g.n, 4, 2)), 3, ws=ws)
