@@ -230,6 +230,7 @@ typedef struct {
     int64_t band_above;    /* edges accepted above the band */
     int32_t band_rounds;   /* margin doublings needed */
     float ms_smooth, ms_score, ms_select, ms_other;
+    int64_t cone_rows;     /* row updates spent on FP64 re-scoring (sum over sweeps) */
 } sfg_level_report;
 
 typedef struct {

@@ -1,13 +1,221 @@
-// Precision form: FP64 re-scoring of the candidates near the selection
-// threshold.
+// Precision form: candidates scored from a reduced-precision embedding are
+// split around the reduced-precision threshold tau~ (the k_sel-th largest):
+//   A = { s~ > (1+m) tau~ }   accepted outright,
+//   B = { |s~ - tau~| <= m tau~ }   re-scored exactly in FP64,
+// and the final set is A plus the best k_sel - |A| of B by FP64 score (ties:
+// lower edge id).  If k_sel - |A| falls outside [0, |B|] the margin m doubles.
+//
+// The FP64 scores of B are recomputed only where they depend: a score after
+// T sweeps depends on the T-hop neighbourhood of its endpoints, so a
+// multi-source BFS (capped at T hops) orders the rows by distance and sweep
+// t recomputes the rows within T - t hops, with the same per-row arithmetic
+// as the full FP64 pass.
+#include <vector>
+
 #include "common.hpp"
 
 namespace sfg {
 
-void band_rescore(const sfg_csr *, int32_t, int32_t, double, const double *, int64_t, const int32_t *,
-                  const int32_t *, const int32_t *, const double *, const float *, int64_t, double, double,
-                  uint8_t *, sfg_level_report *, hipStream_t) {
-    fail(SFG_EUNSUPPORTED, "band re-scoring not built yet");
+int64_t compact_ids(const uint8_t *mask, uint8_t want, int64_t m, int32_t *out, DevArena &A, hipStream_t s);
+void edge_scores(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t ne, const int32_t *cand,
+                 const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt, void *score, sfg_dtype st,
+                 hipStream_t s);
+size_t select_workspace_bytes(int64_t ne);
+void select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel, double *tau, void *ws,
+                 size_t ws_bytes, hipStream_t s);
+size_t cone_partial_bytes(int64_t n, int32_t k);
+double *smooth_cone_f64(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0,
+                        const int32_t *rows_by_dist, const int64_t *active, double *buf0, double *buf1,
+                        void *partial_ws, double *mean, hipStream_t s);
+
+namespace {
+
+// 0 = below the band, 1 = in the band, 2 = above it
+__global__ void k_band_class(int64_t nc, const float *__restrict__ s, double lo, double hi, uint8_t *cls) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    const double x = (double)s[i];
+    cls[i] = x > hi ? 2 : (x >= lo ? 1 : 0);
+}
+
+__global__ void k_count_cls(int64_t nc, const uint8_t *__restrict__ cls, unsigned long long *cnt) {
+    __shared__ unsigned int c1, c2;
+    if (threadIdx.x == 0) c1 = c2 = 0;
+    __syncthreads();
+    unsigned int a = 0, b = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nc; i += (int64_t)gridDim.x * blockDim.x) {
+        a += cls[i] == 1;
+        b += cls[i] == 2;
+    }
+    atomicAdd(&c1, a);
+    atomicAdd(&c2, b);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicAdd(&cnt[0], (unsigned long long)c1);
+        atomicAdd(&cnt[1], (unsigned long long)c2);
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+__global__ void k_gather_ids(int64_t nb, const int32_t *__restrict__ pos, const int32_t *__restrict__ cand,
+                             int32_t *eids) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) eids[i] = cand[pos[i]];
+}
+
+__global__ void k_seed_dist(int64_t nb, const int32_t *__restrict__ eids, const int32_t *__restrict__ u,
+                            const int32_t *__restrict__ v, int32_t *dist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int32_t e = eids[i];
+    dist[u[e]] = 0;
+    dist[v[e]] = 0;
+}
+
+// One BFS level: rows at distance `level` lower their neighbours to level+1.
+__global__ void k_bfs_level(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                            int32_t level, int32_t *dist) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n || dist[p] != level) return;
+    for (int32_t j = rowptr[p]; j < rowptr[p + 1]; ++j) {
+        const int32_t q = col[j];
+        if (dist[q] > level + 1) atomicMin(&dist[q], level + 1);
+    }
+}
+
+__global__ void k_dist_hist(int64_t n, const int32_t *__restrict__ dist, int32_t cap, int32_t *hist) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n && dist[p] <= cap) atomicAdd(&hist[dist[p]], 1);
+}
+
+__global__ void k_dist_scatter(int64_t n, const int32_t *__restrict__ dist, int32_t cap,
+                               const int32_t *__restrict__ start, int32_t *fill, int32_t *rows) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t d = dist[p];
+    if (d > cap) return;
+    rows[start[d] + atomicAdd(&fill[d], 1)] = (int32_t)p;
+}
+
+__global__ void k_band_final(int64_t nc, const uint8_t *__restrict__ cls, uint8_t *sel) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) sel[i] = cls[i] == 2 ? 1 : 0;
+}
+
+__global__ void k_band_apply(int64_t nb, const int32_t *__restrict__ pos, const uint8_t *__restrict__ selb,
+                             uint8_t *sel) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) sel[pos[i]] = selb[i];
+}
+
+}  // namespace
+
+void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, const double *x0, int64_t n_cand,
+                  const int32_t *cand, const int32_t *u, const int32_t *v, const double *w64, const float *score_lo,
+                  int64_t k_sel, double tau_lo, double band, uint8_t *sel, sfg_level_report *rep, DevArena &A,
+                  hipStream_t s) {
+    const int64_t n = H64->n;
+    uint8_t *cls = A.alloc<uint8_t>(n_cand + 1);
+    unsigned long long *cnt = A.alloc<unsigned long long>(2);
+    double m = band;
+    int32_t rounds = 0;
+    int64_t nB = 0, nA = 0;
+    for (;;) {
+        const double lo = (1.0 - m) * tau_lo, hi = (1.0 + m) * tau_lo;
+        hipLaunchKernelGGL(k_band_class, dim3(grid_for(n_cand, 256)), dim3(256), 0, s, n_cand, score_lo, lo, hi, cls);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, cnt, 2);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_count_cls, dim3(256), dim3(256), 0, s, n_cand, cls, cnt);
+        SFG_LAUNCH_CHECK();
+        unsigned long long h[2];
+        SFG_HIP(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+        SFG_HIP(hipStreamSynchronize(s));
+        nB = (int64_t)h[0];
+        nA = (int64_t)h[1];
+        const int64_t need = k_sel - nA;
+        if (need >= 0 && need <= nB) break;
+        m *= 2.0;
+        ++rounds;
+        SFG_REQUIRE(rounds <= 40, SFG_ENUMERIC, "band: margin doubling did not converge");
+    }
+    const int64_t need = k_sel - nA;
+    // B as candidate positions (ascending, so ascending edge id) and edge ids
+    int32_t *posB = A.alloc<int32_t>(nB + 1);
+    const int64_t nB2 = compact_ids(cls, 1, n_cand, posB, A, s);
+    SFG_REQUIRE(nB2 == nB, SFG_EHIP, "band: inconsistent band size");
+    int32_t *eB = A.alloc<int32_t>(nB + 1);
+    if (nB > 0) {
+        hipLaunchKernelGGL(k_gather_ids, dim3(grid_for(nB, 256)), dim3(256), 0, s, nB, posB, cand, eB);
+        SFG_LAUNCH_CHECK();
+    }
+    int64_t cone_rows = 0;
+    double *sB = A.alloc<double>(nB + 1);
+    if (nB > 0) {
+        // dependency cone: hop distance (capped at sweeps+1) from the band's endpoints
+        int32_t *dist = A.alloc<int32_t>(n + 1);
+        fill_i32(dist, n, sweeps + 1, s);
+        hipLaunchKernelGGL(k_seed_dist, dim3(grid_for(nB, 256)), dim3(256), 0, s, nB, eB, u, v, dist);
+        SFG_LAUNCH_CHECK();
+        for (int32_t lvl = 0; lvl < sweeps; ++lvl) {
+            hipLaunchKernelGGL(k_bfs_level, dim3(grid_for(n, 256)), dim3(256), 0, s, n, H64->rowptr, H64->col, lvl,
+                               dist);
+            SFG_LAUNCH_CHECK();
+        }
+        int32_t *hist = A.alloc<int32_t>(sweeps + 2);
+        int32_t *fill = A.alloc<int32_t>(sweeps + 2);
+        int32_t *start = A.alloc<int32_t>(sweeps + 2);
+        fill_i32(hist, sweeps + 2, 0, s);
+        fill_i32(fill, sweeps + 2, 0, s);
+        hipLaunchKernelGGL(k_dist_hist, dim3(grid_for(n, 256)), dim3(256), 0, s, n, dist, sweeps, hist);
+        SFG_LAUNCH_CHECK();
+        std::vector<int32_t> hh(sweeps + 1);
+        SFG_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * (sweeps + 1), hipMemcpyDeviceToHost, s));
+        SFG_HIP(hipStreamSynchronize(s));
+        std::vector<int32_t> st(sweeps + 2, 0);
+        for (int32_t d = 0; d <= sweeps; ++d) st[d + 1] = st[d] + hh[d];
+        SFG_HIP(hipMemcpyAsync(start, st.data(), sizeof(int32_t) * (sweeps + 2), hipMemcpyHostToDevice, s));
+        const int64_t in_cone = st[sweeps + 1];
+        int32_t *rows = A.alloc<int32_t>(in_cone + 1);
+        hipLaunchKernelGGL(k_dist_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, n, dist, sweeps, start, fill,
+                           rows);
+        SFG_LAUNCH_CHECK();
+        // sweep t (0-based) recomputes the rows within sweeps-1-t hops
+        std::vector<int64_t> active(sweeps > 0 ? sweeps : 1);
+        for (int32_t t = 0; t < sweeps; ++t) {
+            active[t] = st[sweeps - t];   // rows with dist <= sweeps-1-t
+            cone_rows += active[t];
+        }
+        double *b0 = A.alloc<double>((size_t)n * k);
+        double *b1 = A.alloc<double>((size_t)n * k);
+        double *mean = A.alloc<double>(k);
+        void *partial = A.raw(cone_partial_bytes(n, k));
+        double *X = smooth_cone_f64(H64, k, sweeps, omega, x0, rows, active.data(), b0, b1, partial, mean, s);
+        edge_scores(X, SFG_F64, n, k, nB, eB, u, v, w64, SFG_F64, sB, SFG_F64, s);
+    }
+    // final: A, plus the best `need` of B by FP64 score
+    hipLaunchKernelGGL(k_band_final, dim3(grid_for(n_cand, 256)), dim3(256), 0, s, n_cand, cls, sel);
+    SFG_LAUNCH_CHECK();
+    if (nB > 0) {
+        uint8_t *selB = A.alloc<uint8_t>(nB + 1);
+        double *tauB = A.alloc<double>(1);
+        const size_t wsb = select_workspace_bytes(nB);
+        void *ws = A.raw(wsb);
+        select_topk(sB, SFG_F64, nB, need, selB, tauB, ws, wsb, s);
+        hipLaunchKernelGGL(k_band_apply, dim3(grid_for(nB, 256)), dim3(256), 0, s, nB, posB, selB, sel);
+        SFG_LAUNCH_CHECK();
+        if (rep && need > 0) SFG_HIP(hipMemcpyAsync(&rep->tau, tauB, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (rep) {
+        rep->band = nB;
+        rep->band_above = nA;
+        rep->band_rounds = rounds;
+        rep->cone_rows = cone_rows;
+    }
+    SFG_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace sfg

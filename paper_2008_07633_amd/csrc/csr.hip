@@ -12,7 +12,7 @@
 //  2. two exclusive scans: rowptr and the edge-list start of each row
 //  3. drop each lower entry's edge id into its row (unordered, atomic slot)
 //  4. order each row's lower part by edge id: rank = number of smaller ids
-//     in the segment, one wavefront per row
+//     in the segment (a thread per short row, a wavefront per long one)
 //  5. one thread per row writes col/val/eid and the degree, in column order
 #include "common.hpp"
 
@@ -21,7 +21,7 @@ namespace sfg {
 namespace {
 
 struct CsrPlan {
-    int32_t *cnt_lo, *cnt_hi, *cnt_all, *tmp, *estart, *fill, *scan;
+    int32_t *cnt_lo, *cnt_hi, *cnt_all, *tmp, *estart, *fill, *scan, *long_cnt;
 };
 
 CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
@@ -34,6 +34,7 @@ CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
     p.estart = c.take<int32_t>(n + 1);
     p.fill = c.take<int32_t>(n + 1);
     p.scan = c.take<int32_t>(scan_scratch_ints(n + 1));
+    p.long_cnt = c.take<int32_t>(1);
     return p;
 }
 
@@ -66,20 +67,48 @@ __global__ void k_place_lower(int64_t m, const int32_t *__restrict__ v, const ui
 
 // Order the lower part of each row by edge id.  Reads the unordered ids from
 // `eid`, writes them ordered into `col` (used as scratch here).  Ids in a
-// segment are distinct, so rank = count of smaller ids.
-__global__ __launch_bounds__(256) void k_rank_lower(int64_t n, const int32_t *__restrict__ rowptr,
+// segment are distinct, so rank = count of smaller ids.  Short segments (the
+// common case) take one thread each; longer ones are queued for a wavefront.
+constexpr int kShortSeg = 32;
+
+__global__ __launch_bounds__(256) void k_rank_short(int64_t n, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ cnt_lo,
-                                                    const int32_t *__restrict__ eid, int32_t *col) {
-    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int lane = threadIdx.x & (kWave - 1);
+                                                    const int32_t *__restrict__ eid, int32_t *col,
+                                                    int32_t *long_rows, int32_t *long_cnt) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= n) return;
     const int32_t len = cnt_lo[row];
+    if (len > kShortSeg) {
+        long_rows[atomicAdd(long_cnt, 1)] = (int32_t)row;
+        return;
+    }
     const int32_t base = rowptr[row];
-    for (int32_t i = lane; i < len; i += kWave) {
+    for (int32_t i = 0; i < len; ++i) {
         const int32_t mine = eid[base + i];
         int32_t rank = 0;
         for (int32_t j = 0; j < len; ++j) rank += (eid[base + j] < mine) ? 1 : 0;
         col[base + rank] = mine;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ cnt_lo,
+                                                   const int32_t *__restrict__ eid, int32_t *col,
+                                                   const int32_t *__restrict__ long_rows,
+                                                   const int32_t *__restrict__ long_cnt) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const int32_t cnt = *long_cnt;
+    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; r < cnt; r += nwaves) {
+        const int32_t row = long_rows[r];
+        const int32_t len = cnt_lo[row];
+        const int32_t base = rowptr[row];
+        for (int32_t i = lane; i < len; i += kWave) {
+            const int32_t mine = eid[base + i];
+            int32_t rank = 0;
+            for (int32_t j = 0; j < len; ++j) rank += (eid[base + j] < mine) ? 1 : 0;
+            col[base + rank] = mine;
+        }
     }
 }
 
@@ -95,7 +124,7 @@ __global__ void k_fill_rows(int64_t n, const int32_t *__restrict__ u, const int3
     double d = 0.0;
     const int32_t nlo = cnt_lo[p];
     for (int32_t t = 0; t < nlo; ++t, ++j) {
-        const int32_t e = col[j];          // ordered lower ids left by k_rank_lower
+        const int32_t e = col[j];          // ordered lower ids left by the rank kernels
         eid[j] = e;
         col[j] = u[e];
         const TW we = w[e];
@@ -152,8 +181,12 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
         hipLaunchKernelGGL(k_place_lower, dim3(grid_for(m, 256)), dim3(256), 0, s, m, v, mask, rowptr, p.fill,
                            eid);
         SFG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_rank_lower, dim3(grid_for(n * kWave, 256)), dim3(256), 0, s, n, rowptr, p.cnt_lo,
-                           eid, col);
+        fill_i32(p.long_cnt, 1, 0, s);
+        // p.tmp (the row totals) is free once rowptr is scanned: it holds the long-row queue
+        hipLaunchKernelGGL(k_rank_short, dim3(grid_for(n, 256)), dim3(256), 0, s, n, rowptr, p.cnt_lo, eid, col,
+                           p.tmp, p.long_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_rank_long, dim3(256), dim3(256), 0, s, rowptr, p.cnt_lo, eid, col, p.tmp, p.long_cnt);
         SFG_LAUNCH_CHECK();
     }
     if (wt == SFG_F64)

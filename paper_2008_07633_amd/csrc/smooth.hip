@@ -7,14 +7,20 @@
 //   - the block X is node-major, so the k values of one neighbour are one
 //     contiguous k*elt-byte run;
 //   - a row is served by k/VPL lanes, each owning VPL consecutive columns
-//     (one 8- or 16-byte load per neighbour), so one pass over the row's
-//     col/val entries feeds all k vectors and a wavefront covers
-//     64*VPL/k rows;
-//   - each lane sums its row in ascending column order (no cross-lane
-//     reduction, no atomics), which makes the FP64 result identical to the
-//     plain sequential definition;
+//     (one wide load per neighbour), so one pass over the row's col/val
+//     entries feeds all k vectors;
+//   - the neighbour loop is unrolled by U with clamped indices: U col/val
+//     loads, then U block-row gathers are in flight before any add, which
+//     hides the dependent-load latency of short rows;
+//   - each lane still adds its row in ascending column order (no cross-lane
+//     reduction, no atomics), so the FP64 result equals the plain
+//     sequential definition bit for bit;
+//   - the first sweep reads the raw FP64 block and subtracts the column
+//     means on the fly (centring costs no extra pass);
 //   - workgroups are remapped so every XCD sweeps one contiguous row range
 //     and neighbour rows tend to hit its own L2.
+#include <cstdlib>
+
 #include "common.hpp"
 
 namespace sfg {
@@ -52,7 +58,7 @@ __device__ __forceinline__ DD dd_add1(DD a, double b) {
 }
 
 constexpr int kSumThreads = 256;
-constexpr int kSumMaxBlocks = 1024;
+constexpr int kSumMaxBlocks = 2048;
 
 template <typename TIN>
 __global__ __launch_bounds__(kSumThreads) void k_colsum_partial(int64_t n, int32_t k, const TIN *__restrict__ x,
@@ -63,8 +69,20 @@ __global__ __launch_bounds__(kSumThreads) void k_colsum_partial(int64_t n, int32
     DD acc{0.0, 0.0};
     const int64_t start = (int64_t)blockIdx.x * rows_per_block;
     const int64_t end = start + rows_per_block < n ? start + rows_per_block : n;
-    if (r0 < rpi)
-        for (int64_t row = start + r0; row < end; row += rpi) acc = dd_add1(acc, cvt<double>(x[row * k + c]));
+    if (r0 < rpi) {
+        int64_t row = start + r0;
+        for (; row + 3 * rpi < end; row += 4 * rpi) {
+            const double a0 = cvt<double>(x[row * k + c]);
+            const double a1 = cvt<double>(x[(row + rpi) * k + c]);
+            const double a2 = cvt<double>(x[(row + 2 * rpi) * k + c]);
+            const double a3 = cvt<double>(x[(row + 3 * rpi) * k + c]);
+            acc = dd_add1(acc, a0);
+            acc = dd_add1(acc, a1);
+            acc = dd_add1(acc, a2);
+            acc = dd_add1(acc, a3);
+        }
+        for (; row < end; row += rpi) acc = dd_add1(acc, cvt<double>(x[row * k + c]));
+    }
     shi[threadIdx.x] = acc.hi;
     slo[threadIdx.x] = acc.lo;
     __syncthreads();
@@ -75,13 +93,26 @@ __global__ __launch_bounds__(kSumThreads) void k_colsum_partial(int64_t n, int32
     }
 }
 
-__global__ void k_colsum_final(int32_t nb, int32_t k, const DD *partial, int64_t n, double *mean) {
-    const int c = threadIdx.x;
-    if (c >= k) return;
+// One workgroup per column: strided partial sums, then a fixed-shape tree.
+__global__ __launch_bounds__(256) void k_colsum_final(int32_t nb, int32_t k, const DD *__restrict__ partial,
+                                                      int64_t n, double *mean) {
+    __shared__ double shi[256], slo[256];
+    const int c = blockIdx.x, t = threadIdx.x;
     DD s{0.0, 0.0};
-    for (int b = 0; b < nb; ++b) s = dd_add(s, partial[(int64_t)b * k + c]);
-    // s.hi is s.hi + s.lo rounded to nearest (quick_two_sum leaves it normalised)
-    mean[c] = s.hi / (double)n;
+    for (int b = t; b < nb; b += 256) s = dd_add(s, partial[(int64_t)b * k + c]);
+    shi[t] = s.hi;
+    slo[t] = s.lo;
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if (t < stride) {
+            DD r = dd_add(DD{shi[t], slo[t]}, DD{shi[t + stride], slo[t + stride]});
+            shi[t] = r.hi;
+            slo[t] = r.lo;
+        }
+        __syncthreads();
+    }
+    // shi[0] is shi[0] + slo[0] rounded to nearest (quick_two_sum normalises)
+    if (t == 0) mean[c] = shi[0] / (double)n;
 }
 
 template <typename TO>
@@ -103,34 +134,79 @@ struct alignas(sizeof(T) * N) Vec {
 __device__ __forceinline__ double madd(double acc, double w, double x) { return acc + w * x; }
 __device__ __forceinline__ float madd(float acc, float w, float x) { return __builtin_fmaf(w, x, acc); }
 
-template <typename TX, typename TO, typename TW, typename TA, int VPL>
-__global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr_log2, int32_t k,
+// Load VPL consecutive block values as the accumulation type.  With CENTER
+// the source is the raw FP64 block: subtract the column mean, round to the
+// storage type, then widen -- the same values a separate centring pass
+// would have stored.
+template <typename TIN, typename TX, typename TA, int VPL, bool CENTER>
+__device__ __forceinline__ void load_row(const TIN *p, const double *mo, TA (&out)[VPL]) {
+    const Vec<TIN, VPL> v = *reinterpret_cast<const Vec<TIN, VPL> *>(p);
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+        if constexpr (CENTER)
+            out[i] = cvt<TA>(cvt<TX>(cvt<double>(v.v[i]) - mo[i]));
+        else
+            out[i] = cvt<TA>(v.v[i]);
+    }
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ T stream_load(const T *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, int U, bool CENTER, bool NT>
+__global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, int32_t lpr_log2, int32_t k,
+                                               const int32_t *__restrict__ rows,
                                                const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col, const TW *__restrict__ val,
-                                               const TW *__restrict__ deg, const TX *__restrict__ x,
-                                               TO *__restrict__ y, TA keep, TA omega) {
+                                               const TW *__restrict__ deg, const TIN *__restrict__ x,
+                                               const double *__restrict__ mean, TO *__restrict__ y, TA keep,
+                                               TA omega) {
     const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t t = (int64_t)b * 256 + threadIdx.x;
     if (t >= nthreads) return;
-    const int64_t row = t >> lpr_log2;
-    const int32_t off = (int32_t)(t & ((1 << lpr_log2) - 1)) * VPL;
-    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    const int64_t ri = lpr_log2 >= 0 ? (t >> lpr_log2) : t / lpr;
+    const int32_t off = (int32_t)(t - ri * lpr) * VPL;
+    // rows == nullptr: every row in order; else only the listed rows
+    const int64_t row = rows ? (int64_t)rows[ri] : ri;
+    double mo[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) mo[i] = CENTER ? mean[off + i] : 0.0;
+    const int32_t j0 = stream_load<NT>(rowptr + row), j1 = stream_load<NT>(rowptr + row + 1);
+    TA self[VPL];
+    load_row<TIN, TX, TA, VPL, CENTER>(x + row * k + off, mo, self);
+    const TA d = cvt<TA>(stream_load<NT>(deg + row));
     TA acc[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
-    for (int32_t j = j0; j < j1; ++j) {
-        const int64_t c = col[j];
-        const TA wv = cvt<TA>(val[j]);
-        const Vec<TX, VPL> xv = *reinterpret_cast<const Vec<TX, VPL> *>(x + c * k + off);
+    for (int32_t j = j0; j < j1; j += U) {
+        int32_t cj[U];
+        TA wj[U];
 #pragma unroll
-        for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], wv, cvt<TA>(xv.v[i]));
+        for (int i = 0; i < U; ++i) {
+            const int32_t jj = (j + i < j1) ? j + i : j1 - 1;
+            cj[i] = stream_load<NT>(col + jj);
+            wj[i] = cvt<TA>(stream_load<NT>(val + jj));
+        }
+        TA xv[U][VPL];
+#pragma unroll
+        for (int i = 0; i < U; ++i) load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)cj[i] * k + off, mo, xv[i]);
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            if (j + i < j1) {
+#pragma unroll
+                for (int q = 0; q < VPL; ++q) acc[q] = madd(acc[q], wj[i], xv[i][q]);
+            }
+        }
     }
-    const TA d = cvt<TA>(deg[row]);
-    const Vec<TX, VPL> self = *reinterpret_cast<const Vec<TX, VPL> *>(x + row * k + off);
     Vec<TO, VPL> out;
 #pragma unroll
     for (int i = 0; i < VPL; ++i) {
-        const TA a = keep * cvt<TA>(self.v[i]);
+        const TA a = keep * self[i];
         const TA q = acc[i] / d;
         const TA bo = omega * q;
         out.v[i] = cvt<TO>(a + bo);
@@ -138,53 +214,90 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr_log
     *reinterpret_cast<Vec<TO, VPL> *>(y + row * k + off) = out;
 }
 
-int ilog2(int x) {
-    int r = 0;
-    while ((1 << r) < x) ++r;
-    return r;
+int ilog2_exact(int x) {
+    for (int r = 0; r < 31; ++r)
+        if ((1 << r) == x) return r;
+    return -1;
 }
 
-template <typename TX, typename TO, typename TW, typename TA, int VPL>
-void launch_sweep_v(const sfg_csr *H, int32_t k, const TX *x, TO *y, double omega, hipStream_t s) {
+// Tuning knobs (environment, read once): SFG_SWEEP_U = neighbour unroll
+// (2, 4 or 8; default 2 for FP64 rows averaging <= 3 entries, else 4) and
+// SFG_SWEEP_NT = 1 to stream the CSR arrays with nontemporal loads.
+int env_int(const char *name, int dflt) {
+    const char *e = getenv(name);
+    return e ? atoi(e) : dflt;
+}
+
+template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, int U, bool CENTER>
+void launch_sweep_u(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
+                    const int32_t *rows, int64_t nrows, hipStream_t s) {
+    static const bool nt = env_int("SFG_SWEEP_NT", 0) != 0;
     const int lpr = k / VPL;
-    const int64_t nthreads = H->n * (int64_t)lpr;
-    hipLaunchKernelGGL((k_sweep<TX, TO, TW, TA, VPL>), dim3(grid_for(nthreads, 256)), dim3(256), 0, s, nthreads,
-                       ilog2(lpr), k, H->rowptr, H->col, (const TW *)H->val, (const TW *)H->deg, x, y,
-                       (TA)(1.0 - omega), (TA)omega);
+    const int64_t nthreads = nrows * (int64_t)lpr;
+    if (nthreads == 0) return;
+    const dim3 g(grid_for(nthreads, 256)), b(256);
+    if (nt)
+        hipLaunchKernelGGL((k_sweep<TIN, TX, TO, TW, TA, VPL, U, CENTER, true>), g, b, 0, s, nthreads, lpr,
+                           ilog2_exact(lpr), k, rows, H->rowptr, H->col, (const TW *)H->val, (const TW *)H->deg, x, mean,
+                           y, (TA)(1.0 - omega), (TA)omega);
+    else
+        hipLaunchKernelGGL((k_sweep<TIN, TX, TO, TW, TA, VPL, U, CENTER, false>), g, b, 0, s, nthreads, lpr,
+                           ilog2_exact(lpr), k, rows, H->rowptr, H->col, (const TW *)H->val, (const TW *)H->deg, x, mean,
+                           y, (TA)(1.0 - omega), (TA)omega);
     SFG_LAUNCH_CHECK();
 }
 
-// Columns per lane: the widest of 16 bytes that divides k into a power-of-two
-// lane count (overridable with SFG_VPL for tuning).
+template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, bool CENTER>
+void launch_sweep_v(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
+                    const int32_t *rows, int64_t nrows, hipStream_t s) {
+    static const int forced = env_int("SFG_SWEEP_U", 0);
+    const int u = forced ? forced : ((sizeof(TX) == 8 && H->nnz <= 3 * H->n) ? 2 : 4);
+    if (u <= 2)
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 2, CENTER>(H, k, x, mean, y, omega, rows, nrows, s);
+    else if (u <= 4)
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 4, CENTER>(H, k, x, mean, y, omega, rows, nrows, s);
+    else
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 8, CENTER>(H, k, x, mean, y, omega, rows, nrows, s);
+}
+
+// Columns per lane: the widest run that divides k, of at most 32 bytes for
+// FP64 and 16 bytes otherwise (measured best on the 1M-node power grid:
+// 4 lanes per 16-vector row in both cases).  SFG_VPL overrides it, up to
+// 64 bytes, for tuning.
 template <typename TX>
 int pick_vpl(int32_t k) {
-    int best = 1;
-    const int maxv = 16 / (int)sizeof(TX);
-    static int forced = [] {
+    static const int forced = [] {
         const char *e = getenv("SFG_VPL");
         return e ? atoi(e) : 0;
     }();
-    for (int v = 1; v <= maxv; v <<= 1) {
-        if (k % v) continue;
-        int lpr = k / v;
-        if ((lpr & (lpr - 1)) != 0) continue;
-        if (forced && v == forced) return v;
-        best = v;
-    }
+    if (forced > 0 && k % forced == 0 && forced * (int)sizeof(TX) <= 64) return forced;
+    const int maxb = sizeof(TX) == 8 ? 32 : 16;
+    int best = 1;
+    for (int v = 1; v * (int)sizeof(TX) <= maxb; v <<= 1)
+        if (k % v == 0) best = v;
     return best;
 }
 
-template <typename TX, typename TO, typename TW, typename TA>
-void launch_sweep(const sfg_csr *H, int32_t k, const TX *x, TO *y, double omega, hipStream_t s) {
+template <typename TIN, typename TX, typename TO, typename TW, typename TA, bool CENTER>
+void launch_sweep(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
+                  hipStream_t s, const int32_t *rows = nullptr, int64_t nrows = -1) {
+    if (nrows < 0) nrows = H->n;
     const int vpl = pick_vpl<TX>(k);
-    constexpr int maxv = 16 / (int)sizeof(TX);
+    constexpr int maxv = 64 / (int)sizeof(TX);
     switch (vpl) {
-        case 1: launch_sweep_v<TX, TO, TW, TA, 1>(H, k, x, y, omega, s); break;
-        case 2: if constexpr (maxv >= 2) { launch_sweep_v<TX, TO, TW, TA, 2>(H, k, x, y, omega, s); break; } [[fallthrough]];
-        case 4: if constexpr (maxv >= 4) { launch_sweep_v<TX, TO, TW, TA, 4>(H, k, x, y, omega, s); break; } [[fallthrough]];
-        case 8: if constexpr (maxv >= 8) { launch_sweep_v<TX, TO, TW, TA, 8>(H, k, x, y, omega, s); break; } [[fallthrough]];
-        default: fail(SFG_EUNSUPPORTED, "smooth: no kernel for this lane split");
+        case 1: launch_sweep_v<TIN, TX, TO, TW, TA, 1, CENTER>(H, k, x, mean, y, omega, rows, nrows, s); return;
+        case 2: launch_sweep_v<TIN, TX, TO, TW, TA, 2, CENTER>(H, k, x, mean, y, omega, rows, nrows, s); return;
+        case 4: launch_sweep_v<TIN, TX, TO, TW, TA, 4, CENTER>(H, k, x, mean, y, omega, rows, nrows, s); return;
+        case 8: launch_sweep_v<TIN, TX, TO, TW, TA, 8, CENTER>(H, k, x, mean, y, omega, rows, nrows, s); return;
+        case 16:
+            if constexpr (maxv >= 16) {
+                launch_sweep_v<TIN, TX, TO, TW, TA, 16, CENTER>(H, k, x, mean, y, omega, rows, nrows, s);
+                return;
+            }
+            break;
+        default: break;
     }
+    fail(SFG_EUNSUPPORTED, "smooth: no kernel for this lane split");
 }
 
 struct SmoothPlan {
@@ -208,18 +321,23 @@ SmoothPlan plan_smooth(Carver &c, int64_t n, int32_t k, sfg_dtype storage) {
     return p;
 }
 
+template <typename TIN>
+void launch_column_means(const TIN *x, int64_t n, int32_t k, DD *partial, double *mean, hipStream_t s) {
+    const int nb = colsum_blocks(n);
+    const int64_t rpb = (n + nb - 1) / nb;
+    hipLaunchKernelGGL(k_colsum_partial<TIN>, dim3(nb), dim3(kSumThreads), 0, s, n, k, x, rpb, partial);
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_colsum_final, dim3(k), dim3(256), 0, s, nb, k, partial, n, mean);
+    SFG_LAUNCH_CHECK();
+}
+
 template <typename TX, typename TW, typename TA>
 void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, bool final_f32,
                 void *xout, const SmoothPlan &p, hipStream_t s) {
     const int64_t n = H->n;
     const int64_t total = n * (int64_t)k;
-    // a2: column means and centring (the block becomes orthogonal to 1)
-    const int nb = colsum_blocks(n);
-    const int64_t rpb = (n + nb - 1) / nb;
-    hipLaunchKernelGGL(k_colsum_partial<double>, dim3(nb), dim3(kSumThreads), 0, s, n, k, x0, rpb, p.partial);
-    SFG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, nb, k, p.partial, n, p.mean);
-    SFG_LAUNCH_CHECK();
+    // a2: column means (the block becomes orthogonal to the all-one vector)
+    launch_column_means<double>(x0, n, k, p.partial, p.mean, s);
     if (sweeps == 0) {
         if (final_f32)
             hipLaunchKernelGGL(k_center_convert<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, total, k, x0,
@@ -231,24 +349,59 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
         return;
     }
     TX *b0 = (TX *)p.buf0, *b1 = (TX *)p.buf1;
-    hipLaunchKernelGGL(k_center_convert<TX>, dim3(grid_for(total, 256)), dim3(256), 0, s, total, k, x0, p.mean, b0);
-    SFG_LAUNCH_CHECK();
-    // a3: sweeps, ping-pong through the workspace, the last one into xout
+    // a3: sweeps; the first centres on the fly, the last writes xout
     for (int32_t t = 0; t < sweeps; ++t) {
-        const TX *src = (t % 2 == 0) ? b0 : b1;
-        if (t == sweeps - 1) {
-            if (final_f32)
-                launch_sweep<TX, float, TW, TA>(H, k, src, (float *)xout, omega, s);
+        const bool last = (t == sweeps - 1);
+        TX *dst = (t % 2 == 0) ? b0 : b1;
+        if (t == 0) {
+            if (last && final_f32)
+                launch_sweep<double, TX, float, TW, TA, true>(H, k, x0, p.mean, (float *)xout, omega, s);
             else
-                launch_sweep<TX, TX, TW, TA>(H, k, src, (TX *)xout, omega, s);
-        } else {
-            TX *dst = (t % 2 == 0) ? b1 : b0;
-            launch_sweep<TX, TX, TW, TA>(H, k, src, dst, omega, s);
+                launch_sweep<double, TX, TX, TW, TA, true>(H, k, x0, p.mean, last ? (TX *)xout : dst, omega, s);
+            continue;
         }
+        const TX *src = (t % 2 == 0) ? b1 : b0;
+        if (last && final_f32)
+            launch_sweep<TX, TX, float, TW, TA, false>(H, k, src, nullptr, (float *)xout, omega, s);
+        else
+            launch_sweep<TX, TX, TX, TW, TA, false>(H, k, src, nullptr, last ? (TX *)xout : dst, omega, s);
     }
 }
 
 }  // namespace
+
+// FP64 smoothing restricted to a dependency cone (precision form).  rows_by_dist
+// lists rows in ascending hop distance from the rows whose final values are
+// wanted; active[t] (host) is how many of them sweep t+1 recomputes, i.e. the
+// rows within sweeps-(t+1) hops.  Every recomputed row is added exactly as in
+// the full FP64 pass, so rows at distance 0 end bit-identical to it.
+// Returns the buffer that holds the final iterate.
+size_t cone_partial_bytes(int64_t n, int32_t k) { return (size_t)colsum_blocks(n) * k * sizeof(DD); }
+
+double *smooth_cone_f64(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0,
+                        const int32_t *rows_by_dist, const int64_t *active, double *buf0, double *buf1,
+                        void *partial_ws, double *mean, hipStream_t s) {
+    SFG_REQUIRE(H->vt == SFG_F64, SFG_EUNSUPPORTED, "cone smoothing needs an F64 graph");
+    launch_column_means<double>(x0, H->n, k, (DD *)partial_ws, mean, s);
+    if (sweeps == 0) {
+        const int64_t total = H->n * (int64_t)k;
+        hipLaunchKernelGGL(k_center_convert<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, total, k, x0,
+                           mean, buf0);
+        SFG_LAUNCH_CHECK();
+        return buf0;
+    }
+    double *dst = buf0;
+    for (int32_t t = 0; t < sweeps; ++t) {
+        dst = (t % 2 == 0) ? buf0 : buf1;
+        if (t == 0)
+            launch_sweep<double, double, double, double, double, true>(H, k, x0, mean, dst, omega, s, rows_by_dist,
+                                                                       active[t]);
+        else
+            launch_sweep<double, double, double, double, double, false>(H, k, (t % 2 == 0) ? buf1 : buf0, nullptr,
+                                                                        dst, omega, s, rows_by_dist, active[t]);
+    }
+    return dst;
+}
 
 size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage) {
     Carver c(nullptr);
@@ -266,6 +419,7 @@ void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const dou
     SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth: omega must be in (0, 1]");
     SFG_REQUIRE(valid_dtype(storage), SFG_EINVAL, "smooth: bad storage dtype");
     SFG_REQUIRE(H->n * (int64_t)k < (int64_t(1) << 40), SFG_EUNSUPPORTED, "smooth: block too large");
+    SFG_REQUIRE(H->nnz == 0 || (H->col && H->val), SFG_EINVAL, "smooth: null pointer");
     SFG_REQUIRE(ws_bytes >= smooth_workspace_bytes(H->n, k, storage), SFG_EWORKSPACE, "smooth: workspace too small");
     const bool f32last = final_f32 && (storage == SFG_F16 || storage == SFG_BF16);
     Carver c(ws);
@@ -294,20 +448,13 @@ void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const dou
 // used for the affinity's centring.
 void column_means(const void *x, sfg_dtype xt, int64_t n, int32_t k, double *mean, void *partial_ws,
                   hipStream_t s) {
-    const int nb = colsum_blocks(n);
-    const int64_t rpb = (n + nb - 1) / nb;
     DD *partial = (DD *)partial_ws;
     if (xt == SFG_F64)
-        hipLaunchKernelGGL(k_colsum_partial<double>, dim3(nb), dim3(kSumThreads), 0, s, n, k, (const double *)x, rpb,
-                           partial);
+        launch_column_means<double>((const double *)x, n, k, partial, mean, s);
     else if (xt == SFG_F32)
-        hipLaunchKernelGGL(k_colsum_partial<float>, dim3(nb), dim3(kSumThreads), 0, s, n, k, (const float *)x, rpb,
-                           partial);
+        launch_column_means<float>((const float *)x, n, k, partial, mean, s);
     else
         fail(SFG_EUNSUPPORTED, "column_means: F64 or F32 block required");
-    SFG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_colsum_final, dim3(1), dim3(64), 0, s, nb, k, partial, n, mean);
-    SFG_LAUNCH_CHECK();
 }
 
 size_t column_means_partial_bytes(int64_t n, int32_t k) { return (size_t)colsum_blocks(n) * k * sizeof(DD); }

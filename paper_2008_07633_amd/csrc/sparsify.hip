@@ -29,7 +29,8 @@ size_t affinity_workspace_bytes(int64_t n, int32_t k);
 size_t coarsen_workspace_bytes(int64_t n, int64_t m);
 void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, const double *x0, int64_t n_cand,
                   const int32_t *cand, const int32_t *u, const int32_t *v, const double *w64, const float *score_lo,
-                  int64_t k_sel, double tau_lo, double band, uint8_t *sel, sfg_level_report *rep, hipStream_t s);
+                  int64_t k_sel, double tau_lo, double band, uint8_t *sel, sfg_level_report *rep, DevArena &A,
+                  hipStream_t s);
 void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
                          const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep, hipStream_t s);
 
@@ -314,6 +315,7 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
         rep->band = 0;
         rep->band_above = 0;
         rep->band_rounds = 0;
+        rep->cone_rows = 0;
     }
     if (!f64 && p->band > 0.0 && ksel > 0 && ksel < nc) {
         // precision form: FP64 re-scoring of the edges near the threshold
@@ -328,7 +330,7 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
         build_csr(n, m, u, v, w64, SFG_F64, hmask, rowptr64, col64, val64, eid64, deg64, ws, wsb, s);
         sfg_csr H64{n, nnz, rowptr64, col64, val64, eid64, deg64, SFG_F64};
         band_rescore(&H64, p->k, p->sweeps, p->omega, x0, nc, cand, u, v, w64, (const float *)score, ksel, tau_h,
-                     p->band, sel, rep, s);
+                     p->band, sel, rep, A, s);
     }
     hipLaunchKernelGGL(k_keep_init, dim3(grid_for(m, 256)), dim3(256), 0, s, m, base, keep);
     SFG_LAUNCH_CHECK();

@@ -1,0 +1,79 @@
+"""Precision form: reduced-precision embedding plus FP64 re-scoring of the
+candidates near the threshold must select exactly the FP64 oracle's set."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_07633_amd import sfg
+
+    sfg.lib()
+    return sfg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+CASES = [
+    # (graph, k, sweeps, frac, storage, final_f32, band)
+    ("knn", 32, 20, 0.10, torch.float16, True, 0.01),
+    ("knn", 32, 20, 0.10, torch.bfloat16, True, 0.01),
+    ("knn", 16, 12, 0.10, torch.float16, False, 0.01),
+    ("pgrid", 16, 20, 0.10, torch.float32, False, 0.001),
+    ("mesh", 16, 20, 0.10, torch.float16, True, 0.01),
+]
+
+
+def graph_of(name):
+    if name == "knn":
+        return W.knn3d(30000, 10, seed=3)
+    if name == "pgrid":
+        return W.powergrid(150, 140, 0.02, seed=2)
+    return W.mesh3d(24, 22, 20, seed=5, wdist=("lognormal", 0.0, 1.5))
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[4]}-ff{c[5]}-k{c[1]}")
+def test_band_rescoring_gives_fp64_set(S, orc, case):
+    name, k, T, f, storage, ff, band = case
+    g = graph_of(name)
+    X0 = W.random_block(g.n, k, 500 + k)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, T, f)
+    p = S.make_params(k=k, sweeps=T, frac=f, storage=storage, final_f32=ff, band=band)
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), p)
+    got = keep.cpu().numpy()
+    r = rep[0]
+    assert r["band"] > 0 and r["cone_rows"] > 0
+    assert r["band_above"] + r["band"] >= r["k_sel"]
+    assert np.array_equal(got, ref.keep), (int((got != ref.keep).sum()), r)
+    assert r["tau"] == ref.levels[0].tau
+
+
+def test_low_precision_score_errors_reported(S, orc):
+    # the scores the band logic starts from: error measures against FP64
+    g = W.knn3d(30000, 10, seed=3)
+    k, T = 32, 20
+    X0 = W.random_block(g.n, k, 532)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, T, 0.1)
+    lr = ref.levels[0]
+    u, v = dev(g.u), dev(g.v)
+    tree = dev(orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0])
+    w32 = dev(g.w.astype(np.float32))
+    H = S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree)
+    cand = dev(lr.cand)
+    out = {}
+    for storage, ff in ((torch.float16, True), (torch.float16, False), (torch.bfloat16, True), (torch.float32, False)):
+        X = S.sfg_smooth(H, dev(X0), T, 0.5, storage=storage, final_f32=ff)
+        s = S.sfg_edge_scores(X, u, v, w32, cand=cand).cpu().numpy().astype(np.float64)
+        out[(str(storage), ff)] = orc.score_errors(s, lr.score, lr.tau)
+    # FP32 storage is close; FP16 with an FP32 last iterate meets 1e-2 in the selected region
+    assert out[("torch.float32", False)]["max_abs_over_tau"] < 1e-4
+    assert out[("torch.float16", True)]["max_rel_selected_region"] < 1e-2, out
