@@ -32,7 +32,8 @@ void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, c
                   int64_t k_sel, double tau_lo, double band, uint8_t *sel, sfg_level_report *rep, DevArena &A,
                   hipStream_t s);
 void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
-                         const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep, hipStream_t s);
+                         const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep, DevArena &A,
+                         hipStream_t s);
 
 // ------------------------------------------------------------------ device arena (sfg_sparsify only)
 
@@ -415,7 +416,7 @@ extern "C" sfg_status sfg_sparsify(int64_t n, int64_t m, const int32_t *u, const
         if (p->levels == 1)
             sfg::single_level_sparsify(n, m, u, v, w, wt, p, x0, keep, rep, A, s);
         else
-            sfg::multilevel_sparsify(n, m, u, v, w, wt, p, x0, keep, rep, s);
+            sfg::multilevel_sparsify(n, m, u, v, w, wt, p, x0, keep, rep, A, s);
         SFG_HIP(hipStreamSynchronize(s));
     });
 }
