@@ -69,7 +69,9 @@ typedef enum {
     SFG_OP_SMOOTH = 1,
     SFG_OP_SELECT_TOPK = 2,
     SFG_OP_AFFINITY = 3,
-    SFG_OP_COARSEN = 4
+    SFG_OP_COARSEN = 4,
+    SFG_OP_MPNN_FORWARD = 5,   /* n nodes, t = activation dtype */
+    SFG_OP_MPNN_TRAIN = 6      /* n nodes, m = scored edges */
 } sfg_op;
 
 /* Which graph's embedding scores the candidates (Sec. 3.5 derives the score
@@ -257,6 +259,51 @@ typedef struct {
 sfg_status sfg_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w,
                         sfg_dtype wt, const sfg_params *p, const double *x0, uint8_t *keep,
                         sfg_report *rep, void *stream);
+
+/*
+ * Learned edge-criticality surrogate (not in the paper: an addition that
+ * predicts which candidates the scores of Eq. 18 will rank highest, so that
+ * most of them can be pruned before exact scoring).  Two message-passing
+ * layers of width 32 over G, with the row-normalised aggregation D^-1 A of
+ * Sec. 3.2's smoothing, then an edge head:
+ *   H1 = relu([X | D^-1 A X | 1] W1),  H2 = relu([H1 | D^-1 A H1 | 1] W2),
+ *   yhat_e = [relu([|H2_p - H2_q| | H2_p * H2_q | f_e | 1] W3) | 1] . w4
+ * Parameters: one F32 vector [W1 (17x32) | W2 (65x32) | W3 (69x32) | w4 (33)],
+ * row-major, sfg_mpnn_param_count() values.  The graph CSR must be F32.
+ */
+int64_t sfg_mpnn_param_count(void);
+
+/* Features from a cheap smoothed block xc (n x kc, F32):
+ *   node (n x 8): 1, log D_G, log D_T, log deg_G, log deg_T, log |xc_p|^2,
+ *                 log local energy sum_q w_pq |xc_p - xc_q|^2 / D_p on G, on T
+ *   edge (ne x 4): log w, log w |xc_p - xc_q|^2, min and max of log D_T at the ends
+ * standardised as (f - mean) * inv_std with norm = [node means (8), node
+ * inverse stds (8), edge means (4), edge inverse stds (4)] (NULL: raw;
+ * node feature 0 stays 1).  cand (NULL = all edges) selects the edges. */
+sfg_status sfg_mpnn_features(const sfg_csr *G, const sfg_csr *T, const float *xc, int32_t kc, int64_t ne,
+                             const int32_t *cand, const int32_t *u, const int32_t *v, const float *w,
+                             const float *norm, float *node_feat, float *edge_feat, void *stream);
+
+/* Inference: predictions pred[ne] for the candidate edges; activations are
+ * stored as act (F32 or BF16) with FP32 arithmetic.  Workspace:
+ * sfg_workspace_bytes(SFG_OP_MPNN_FORWARD, n, 0, 0, act). */
+sfg_status sfg_mpnn_forward(const sfg_csr *G, const float *params, const float *node_feat, int64_t ne,
+                            const int32_t *cand, const int32_t *u, const int32_t *v, const float *edge_feat,
+                            sfg_dtype act, float *pred, void *ws, size_t ws_bytes, void *stream);
+
+/* Training step core, FP32: forward, loss = mean_e (pred_e - target_e)^2
+ * (device scalar), and its gradient grad[param_count] with respect to the
+ * parameters.  Deterministic (no floating-point atomics).  Workspace:
+ * sfg_workspace_bytes(SFG_OP_MPNN_TRAIN, n, ne, 0, SFG_F32). */
+sfg_status sfg_mpnn_loss_grad(const sfg_csr *G, const float *params, const float *node_feat, int64_t ne,
+                              const int32_t *cand, const int32_t *u, const int32_t *v, const float *edge_feat,
+                              const float *target, float *pred, float *loss, float *grad, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* Adam update (Kingma & Ba) with bias correction, step >= 1, in place on
+ * params, m, v (all F32, n values). */
+sfg_status sfg_mpnn_adam(float *params, const float *grad, float *m, float *v, int64_t n, int64_t step,
+                         double lr, double beta1, double beta2, double eps, void *stream);
 
 #ifdef __cplusplus
 }

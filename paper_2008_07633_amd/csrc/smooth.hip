@@ -378,6 +378,20 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
 // Returns the buffer that holds the final iterate.
 size_t cone_partial_bytes(int64_t n, int32_t k) { return (size_t)colsum_blocks(n) * k * sizeof(DD); }
 
+// Row-normalised aggregation y = D^-1 A x of an n-by-k block (the sweep with
+// omega = 1; FP32 arithmetic).  x and y are F32 or BF16; H must be F32.
+// With H->deg pointing at ones it is the plain product A x.
+void spmm_rownorm(const sfg_csr *H, int32_t k, sfg_dtype t, const void *x, void *y, hipStream_t s) {
+    SFG_REQUIRE(H->vt == SFG_F32, SFG_EUNSUPPORTED, "aggregation needs an F32 graph");
+    if (t == SFG_F32)
+        launch_sweep<float, float, float, float, float, false>(H, k, (const float *)x, nullptr, (float *)y, 1.0, s);
+    else if (t == SFG_BF16)
+        launch_sweep<__hip_bfloat16, __hip_bfloat16, __hip_bfloat16, float, float, false>(
+            H, k, (const __hip_bfloat16 *)x, nullptr, (__hip_bfloat16 *)y, 1.0, s);
+    else
+        fail(SFG_EUNSUPPORTED, "aggregation: F32 or BF16 activations only");
+}
+
 double *smooth_cone_f64(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0,
                         const int32_t *rows_by_dist, const int64_t *active, double *buf0, double *buf1,
                         void *partial_ws, double *mean, hipStream_t s) {

@@ -27,6 +27,8 @@ void select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t
                  size_t ws_bytes, hipStream_t s);
 size_t affinity_workspace_bytes(int64_t n, int32_t k);
 size_t coarsen_workspace_bytes(int64_t n, int64_t m);
+size_t mpnn_forward_workspace_bytes(int64_t n, sfg_dtype act);
+size_t mpnn_train_workspace_bytes(int64_t n, int64_t ne);
 void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, const double *x0, int64_t n_cand,
                   const int32_t *cand, const int32_t *u, const int32_t *v, const double *w64, const float *score_lo,
                   int64_t k_sel, double tau_lo, double band, uint8_t *sel, sfg_level_report *rep, DevArena &A,
@@ -388,6 +390,8 @@ extern "C" size_t sfg_workspace_bytes(int op, int64_t n, int64_t m, int32_t k, s
         case SFG_OP_SELECT_TOPK: return sfg::select_workspace_bytes(m < 0 ? 0 : m);
         case SFG_OP_AFFINITY: return sfg::affinity_workspace_bytes(n < 1 ? 1 : n, k < 1 ? 1 : k);
         case SFG_OP_COARSEN: return sfg::coarsen_workspace_bytes(n < 1 ? 1 : n, m < 0 ? 0 : m);
+        case SFG_OP_MPNN_FORWARD: return sfg::mpnn_forward_workspace_bytes(n < 1 ? 1 : n, t);
+        case SFG_OP_MPNN_TRAIN: return sfg::mpnn_train_workspace_bytes(n < 1 ? 1 : n, m < 1 ? 1 : m);
         default: return 0;
     }
 }

@@ -30,8 +30,11 @@ EMBED_SPARSIFIER, EMBED_GRAPH = 0, 1
 STATUS = {0: "SFG_OK", 1: "SFG_EINVAL", 2: "SFG_ENOTCONN", 3: "SFG_ENOMEM", 4: "SFG_EHIP",
           5: "SFG_EWORKSPACE", 6: "SFG_EUNSUPPORTED", 7: "SFG_ENUMERIC"}
 
+OP_MPNN_FORWARD, OP_MPNN_TRAIN = 5, 6
+
 EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores",
-            "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify"]
+            "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify",
+            "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam"]
 
 
 class SfgError(RuntimeError):
@@ -89,8 +92,14 @@ def lib() -> ctypes.CDLL:
         L.sfg_affinity.argtypes = [P, I, I64, I32, I64, P, P, P, I, P, S, P]
         L.sfg_coarsen.argtypes = [P, I64, P, P, P, I, P, I, P, P, P, P, P, P, P, P, S, P]
         L.sfg_sparsify.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P]
+        L.sfg_mpnn_param_count.argtypes = []
+        L.sfg_mpnn_param_count.restype = I64
+        L.sfg_mpnn_features.argtypes = [P, P, P, I32, I64, P, P, P, P, P, P, P, P]
+        L.sfg_mpnn_forward.argtypes = [P, P, P, I64, P, P, P, P, I, P, P, S, P]
+        L.sfg_mpnn_loss_grad.argtypes = [P, P, P, I64, P, P, P, P, P, P, P, P, P, S, P]
+        L.sfg_mpnn_adam.argtypes = [P, P, P, P, I64, I64, D, D, D, D, P]
         for name in EXPORTED:
-            if name not in ("sfg_workspace_bytes", "sfg_last_error"):
+            if name not in ("sfg_workspace_bytes", "sfg_last_error", "sfg_mpnn_param_count"):
                 getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -282,3 +291,62 @@ def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: 
         L = rep.level[i]
         levels.append({f: getattr(L, f) for f, _ in LevelReport._fields_})
     return keep, levels
+
+
+# ----------------------------------------------------------------------------- learned surrogate
+
+def sfg_mpnn_param_count() -> int:
+    return int(lib().sfg_mpnn_param_count())
+
+
+def sfg_mpnn_features(G: Csr, T: Csr, xc: torch.Tensor, u: torch.Tensor, v: torch.Tensor, w32: torch.Tensor,
+                      cand: Optional[torch.Tensor] = None, norm: Optional[torch.Tensor] = None):
+    """Node (n x 8) and candidate-edge (ne x 4) features of the surrogate."""
+    n, kc = int(xc.shape[0]), int(xc.shape[1])
+    ne = int(cand.shape[0]) if cand is not None else int(u.shape[0])
+    nf = torch.empty((n, 8), dtype=torch.float32, device=xc.device)
+    ef = torch.empty((max(ne, 1), 4), dtype=torch.float32, device=xc.device)[:ne]
+    gs, ts = G.struct(), T.struct()
+    _check(lib().sfg_mpnn_features(ctypes.byref(gs), ctypes.byref(ts), _ptr(xc), kc, ne, _ptr(cand), _ptr(u),
+                                   _ptr(v), _ptr(w32), _ptr(norm), _ptr(nf), _ptr(ef), _stream()))
+    return nf, ef
+
+
+def sfg_mpnn_forward(G: Csr, params: torch.Tensor, node_feat: torch.Tensor, u: torch.Tensor, v: torch.Tensor,
+                     edge_feat: torch.Tensor, cand: Optional[torch.Tensor] = None, act=torch.bfloat16,
+                     out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    ne = int(edge_feat.shape[0])
+    if out is None:
+        out = torch.empty(max(ne, 1), dtype=torch.float32, device=params.device)[:ne]
+    a = _TORCH_TO_SFG[act]
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_MPNN_FORWARD, G.n, 0, 0, a), params.device)
+    gs = G.struct()
+    _check(lib().sfg_mpnn_forward(ctypes.byref(gs), _ptr(params), _ptr(node_feat), ne, _ptr(cand), _ptr(u), _ptr(v),
+                                  _ptr(edge_feat), a, _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def sfg_mpnn_loss_grad(G: Csr, params: torch.Tensor, node_feat: torch.Tensor, u: torch.Tensor, v: torch.Tensor,
+                       edge_feat: torch.Tensor, target: torch.Tensor, cand: Optional[torch.Tensor] = None,
+                       ws: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None):
+    """FP32 forward + backward.  Returns (pred, loss (device scalar), grad)."""
+    ne = int(edge_feat.shape[0])
+    dev = params.device
+    pred = torch.empty(ne, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    if grad is None:
+        grad = torch.empty_like(params)
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_MPNN_TRAIN, G.n, ne, 0, F32), dev)
+    gs = G.struct()
+    _check(lib().sfg_mpnn_loss_grad(ctypes.byref(gs), _ptr(params), _ptr(node_feat), ne, _ptr(cand), _ptr(u), _ptr(v),
+                                    _ptr(edge_feat), _ptr(target), _ptr(pred), _ptr(loss), _ptr(grad), _ptr(ws),
+                                    ws.numel(), _stream()))
+    return pred, loss, grad
+
+
+def sfg_mpnn_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
+                  lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    _check(lib().sfg_mpnn_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(params.numel()), int(step),
+                               float(lr), float(beta1), float(beta2), float(eps), _stream()))

@@ -1,0 +1,258 @@
+"""Learned edge-criticality surrogate: training, model files, pruning.
+
+The network and its kernels are in ``csrc/mpnn.hip`` (C ABI ``sfg_mpnn_*``).
+This module drives them.  It only marshals and orchestrates; every numeric step runs
+in libsfg:
+  * a cheap embedding (``KC`` vectors smoothed on the spanning tree, BF16
+    storage with an FP32 last iterate) feeds the features;
+  * training targets are the plain method's own scores (``K`` vectors, ``T``
+    sweeps, FP32), as standardised logs;
+  * inference predicts every off-tree edge, keeps the top ``cand_frac`` as
+    candidates, and the plain scorer ranks the candidates exactly.
+
+Model files are ``.npz`` with a version, the shapes, the standardisation
+constants and a SHA-256 checksum of the parameters; a file that fails any
+check raises :class:`SurrogateInvalid`, and callers fall back to the plain
+scorer.
+"""
+from __future__ import annotations
+
+import hashlib
+import math
+from dataclasses import dataclass, field
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import sfg as S
+
+VERSION = 1
+KC = 4                 # vectors of the cheap embedding
+N_NODE_FEAT, N_EDGE_FEAT = 8, 4
+
+
+class SurrogateInvalid(RuntimeError):
+    """The model cannot be used (missing, corrupted, incompatible or not finite)."""
+
+
+@dataclass
+class Model:
+    params: torch.Tensor                 # F32 [param_count] on the device
+    norm: torch.Tensor                   # F32 [24]: node means, node inv stds, edge means, edge inv stds
+    y_mean: float = 0.0                  # target standardisation (log score)
+    y_std: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    def checksum(self) -> str:
+        h = hashlib.sha256()
+        h.update(self.params.detach().cpu().numpy().astype(np.float32).tobytes())
+        h.update(self.norm.detach().cpu().numpy().astype(np.float32).tobytes())
+        h.update(np.array([self.y_mean, self.y_std], dtype=np.float64).tobytes())
+        return h.hexdigest()
+
+    def save(self, path: str) -> None:
+        np.savez(path, version=np.int64(VERSION), params=self.params.detach().cpu().numpy(),
+                 norm=self.norm.detach().cpu().numpy(), y=np.array([self.y_mean, self.y_std]),
+                 checksum=np.array(self.checksum()))
+
+
+def load(path: str, device="cuda") -> Model:
+    try:
+        z = np.load(path, allow_pickle=False)
+        ver = int(z["version"])
+        params, norm, y, cs = z["params"], z["norm"], z["y"], str(z["checksum"])
+    except Exception as e:   # unreadable or missing fields
+        raise SurrogateInvalid(f"cannot read surrogate model {path}: {e}") from e
+    if ver != VERSION:
+        raise SurrogateInvalid(f"surrogate model version {ver}, expected {VERSION}")
+    if params.shape != (S.sfg_mpnn_param_count(),) or norm.shape != (2 * (N_NODE_FEAT + N_EDGE_FEAT),):
+        raise SurrogateInvalid("surrogate model has the wrong shapes")
+    if not (np.all(np.isfinite(params)) and np.all(np.isfinite(norm)) and np.all(np.isfinite(y))):
+        raise SurrogateInvalid("surrogate model holds non-finite values")
+    m = Model(torch.from_numpy(params.astype(np.float32)).to(device),
+              torch.from_numpy(norm.astype(np.float32)).to(device), float(y[0]), float(y[1]))
+    if m.checksum() != cs:
+        raise SurrogateInvalid("surrogate model checksum mismatch")
+    return m
+
+
+def init_params(seed: int, device="cuda") -> torch.Tensor:
+    """Seeded He-style initial weights and zero biases, in the flat layout of sfg.h."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    blocks = []
+    for rows, fan_in in ((17, 8), (65, 32), (69, 68)):
+        w = rng.standard_normal((rows, 32)) * math.sqrt(2.0 / fan_in)
+        w[-1, :] = 0.0           # bias row
+        blocks.append(w.reshape(-1))
+    w4 = rng.standard_normal(33) * math.sqrt(1.0 / 32)
+    w4[-1] = 0.0
+    blocks.append(w4)
+    return torch.from_numpy(np.concatenate(blocks).astype(np.float32)).to(device)
+
+
+# ----------------------------------------------------------------------------- per-graph preparation
+
+@dataclass
+class Prepared:
+    n: int
+    u: torch.Tensor
+    v: torch.Tensor
+    w32: torch.Tensor
+    tree: torch.Tensor
+    cand: torch.Tensor            # off-tree edge ids, ascending
+    G: S.Csr                      # F32 CSR of the graph
+    T: S.Csr                      # F32 CSR of the tree
+    xc: torch.Tensor              # cheap embedding (n x KC, F32)
+    raw_nf: Optional[torch.Tensor] = None
+    raw_ef: Optional[torch.Tensor] = None
+
+
+def prepare(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0c: torch.Tensor, sweeps: int,
+            tree: Optional[torch.Tensor] = None) -> Prepared:
+    """Tree, CSRs of G and of the tree, and the cheap embedding from x0c (n x KC, FP64)."""
+    w32 = w.float()
+    if tree is None:
+        tree, comps = S.sfg_spanning_tree(n, u, v, w)
+        if comps != 1:
+            raise S.SfgError(2, "graph is not connected")
+    cand = torch.nonzero(tree == 0).reshape(-1).to(torch.int32)
+    G = S.sfg_laplacian_csr(n, u, v, w32)
+    T = S.sfg_laplacian_csr(n, u, v, w32, mask=tree)
+    xc = S.sfg_smooth(T, x0c, sweeps, 0.5, storage=torch.bfloat16, final_f32=True)
+    return Prepared(n, u, v, w32, tree, cand, G, T, xc)
+
+
+def features(pp: Prepared, norm: Optional[torch.Tensor]):
+    return S.sfg_mpnn_features(pp.G, pp.T, pp.xc, pp.u, pp.v, pp.w32, cand=pp.cand, norm=norm)
+
+
+def plain_scores(pp: Prepared, x0: torch.Tensor, sweeps: int, storage=torch.float32) -> torch.Tensor:
+    """The plain method's scores of the off-tree edges (the training target and the judge)."""
+    X = S.sfg_smooth(pp.T, x0, sweeps, 0.5, storage=storage)
+    return S.sfg_edge_scores(X, pp.u, pp.v, pp.w32, cand=pp.cand, score_dtype=torch.float32)
+
+
+# ----------------------------------------------------------------------------- training
+
+@dataclass
+class TrainSet:
+    graphs: list                  # Prepared (with raw features)
+    targets: list                 # raw log scores (device F32)
+
+
+def fit_norm(ts: TrainSet):
+    """Feature and target standardisation from the training set (host statistics)."""
+    nf = np.concatenate([g.raw_nf.cpu().numpy() for g in ts.graphs])
+    ef = np.concatenate([g.raw_ef.cpu().numpy() for g in ts.graphs])
+    y = np.concatenate([t.cpu().numpy() for t in ts.targets]).astype(np.float64)
+    nm, ns = nf.mean(0), nf.std(0)
+    em, es = ef.mean(0), ef.std(0)
+    nm[0], ns[0] = 0.0, 1.0
+    norm = np.concatenate([nm, 1.0 / np.maximum(ns, 1e-6), em, 1.0 / np.maximum(es, 1e-6)]).astype(np.float32)
+    return norm, float(y.mean()), float(y.std())
+
+
+def train(ts: TrainSet, epochs: int = 20, lr: float = 3e-3, seed: int = 7, lr_min: float = 3e-4,
+          log=None) -> tuple[Model, list]:
+    """Full-batch Adam over the training graphs, one step per graph per epoch,
+    cosine-decayed learning rate.  Returns the model and the per-epoch mean loss."""
+    dev = ts.targets[0].device
+    norm_np, ym, ysd = fit_norm(ts)
+    norm = torch.from_numpy(norm_np).to(dev)
+    feats = []
+    for g, t in zip(ts.graphs, ts.targets):
+        nf, ef = features(g, norm)
+        feats.append((nf, ef, ((t - ym) / ysd).contiguous()))
+    params = init_params(seed, dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    grad = torch.empty_like(params)
+    ws_cache = {}
+    history = []
+    step = 0
+    total = epochs * len(ts.graphs)
+    for ep in range(epochs):
+        losses = []
+        for gi, (g, (nf, ef, y)) in enumerate(zip(ts.graphs, feats)):
+            key = (g.n, int(ef.shape[0]))
+            if key not in ws_cache:
+                ws_cache[key] = torch.empty(S.sfg_workspace_bytes(S.OP_MPNN_TRAIN, g.n, key[1], 0, S.F32),
+                                            dtype=torch.uint8, device=dev)
+            _, loss, _ = S.sfg_mpnn_loss_grad(g.G, params, nf, g.u, g.v, ef, y, cand=g.cand, ws=ws_cache[key],
+                                              grad=grad)
+            step += 1
+            lr_t = lr_min + 0.5 * (lr - lr_min) * (1 + math.cos(math.pi * (step - 1) / max(total - 1, 1)))
+            S.sfg_mpnn_adam(params, grad, m, v, step, lr=lr_t)
+            losses.append(loss)
+        ep_loss = float(torch.stack(losses).mean().item())
+        history.append(ep_loss)
+        if log:
+            log(f"epoch {ep}: loss {ep_loss:.4f}")
+    return Model(params, norm, ym, ysd, {"epochs": epochs, "lr": lr, "seed": seed}), history
+
+
+# ----------------------------------------------------------------------------- inference
+
+def predict(model: Model, pp: Prepared, act=torch.bfloat16) -> torch.Tensor:
+    nf, ef = features(pp, model.norm)
+    return S.sfg_mpnn_forward(pp.G, model.params, nf, pp.u, pp.v, ef, cand=pp.cand, act=act)
+
+
+def prune(model: Model, pp: Prepared, cand_frac: float, act=torch.bfloat16):
+    """Positions (into pp.cand) of the top cand_frac of the off-tree edges by prediction."""
+    pred = predict(model, pp, act)
+    k = int(math.ceil(cand_frac * int(pp.cand.numel())))
+    sel, _ = S.sfg_select_topk(pred, k)
+    return torch.nonzero(sel).reshape(-1).to(torch.int32), pred
+
+
+def recall(chosen_plain_pos: torch.Tensor, cand_pos: torch.Tensor, n_cand: int) -> float:
+    """Fraction of the plain method's chosen edges that are among the surrogate's candidates."""
+    if chosen_plain_pos.numel() == 0:
+        return 1.0
+    mark = torch.zeros(n_cand, dtype=torch.bool, device=cand_pos.device)
+    mark[cand_pos.long()] = True
+    return float(mark[chosen_plain_pos.long()].float().mean().item())
+
+
+# ----------------------------------------------------------------------------- pruned sparsifier
+
+@dataclass
+class PrunedResult:
+    keep: torch.Tensor            # uint8 [m]: 1 tree, 2 recovered
+    fallback: bool
+    reason: str
+    n_cand: int                   # off-tree edges
+    n_scored: int                 # edges scored exactly
+    k_sel: int
+
+
+def sparsify_pruned(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: torch.Tensor,
+                    x0c: torch.Tensor, model, sweeps: int, frac: float, cand_frac: float,
+                    storage=torch.float32) -> PrunedResult:
+    """Spanning tree + top f of the off-tree edges, where only the surrogate's
+    top cand_frac candidates are scored exactly.  ``model`` is a Model or a
+    path; if it cannot be used the plain single-level path runs instead."""
+    m = int(u.shape[0])
+    try:
+        mdl = load(model, u.device) if isinstance(model, str) else model
+        if not bool(torch.isfinite(mdl.params).all().item()):
+            raise SurrogateInvalid("surrogate parameters are not finite")
+    except SurrogateInvalid as e:
+        keep, rep = S.sfg_sparsify(n, u, v, w, x0, S.make_params(k=int(x0.shape[1]), sweeps=sweeps, frac=frac,
+                                                                 storage=storage))
+        r = rep[0]
+        return PrunedResult(keep, True, str(e), int(r["n_cand"]), int(r["n_cand"]), int(r["k_sel"]))
+    pp = prepare(n, u, v, w, x0c, sweeps)
+    cand_pos, _ = prune(mdl, pp, cand_frac)
+    cand_e = pp.cand[cand_pos.long()].contiguous()
+    X = S.sfg_smooth(pp.T, x0, sweeps, 0.5, storage=storage)
+    s = S.sfg_edge_scores(X, pp.u, pp.v, pp.w32, cand=cand_e, score_dtype=torch.float32)
+    n_cand = int(pp.cand.numel())
+    k_sel = int(math.ceil(frac * n_cand))
+    k_take = min(k_sel, int(cand_e.numel()))
+    sel, _ = S.sfg_select_topk(s, k_take)
+    keep = pp.tree.clone()
+    keep[cand_e[sel.bool()].long()] = 2
+    return PrunedResult(keep, False, "", n_cand, int(cand_e.numel()), k_take)

@@ -1,0 +1,166 @@
+"""Learned surrogate: GPU features, forward, gradient and Adam against the CPU
+FP64 reference; training; recall against the plain scorer; fallback."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import mpnn as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_07633_amd import sfg
+
+    sfg.lib()
+    return sfg
+
+
+@pytest.fixture(scope="module")
+def SG(S):
+    from paper_2008_07633_amd import surrogate
+
+    return surrogate
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _prep(SG, g, seed=1, sweeps=20):
+    x0c = dev(W.random_block(g.n, SG.KC, seed))
+    return SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), x0c, sweeps)
+
+
+def test_features_match_oracle(S, SG, orc):
+    g = W.mesh3d(9, 8, 7, seed=11, wdist=("lognormal", 0.0, 1.5))
+    pp = _prep(SG, g)
+    nf, ef = SG.features(pp, None)
+    tree = pp.tree.cpu().numpy().astype(bool)
+    xc = pp.xc.cpu().numpy().astype(np.float64)
+    cand = pp.cand.cpu().numpy()
+    w32 = g.w.astype(np.float32).astype(np.float64)
+    rn, re = M.raw_features(g.n, g.u, g.v, w32, tree, xc, cand)
+    np.testing.assert_allclose(nf.cpu().numpy(), rn, rtol=0, atol=2e-4)
+    np.testing.assert_allclose(ef.cpu().numpy(), re, rtol=0, atol=2e-4)
+
+
+def _random_case(SG, seed=3):
+    g = W.mesh3d(8, 9, 10, seed=12, wdist=("lognormal", 0.0, 1.0))
+    pp = _prep(SG, g, seed)
+    nf_raw, ef_raw = SG.features(pp, None)
+    rn, re = nf_raw.cpu().numpy().astype(np.float64), ef_raw.cpu().numpy().astype(np.float64)
+    norm = np.concatenate([rn.mean(0), 1 / (rn.std(0) + 1e-3), re.mean(0), 1 / (re.std(0) + 1e-3)])
+    norm[0], norm[8] = 0.0, 1.0
+    norm = norm.astype(np.float32)
+    nf, ef = SG.features(pp, dev(norm))
+    theta = (M.init_params(seed) + 0.02).astype(np.float32)
+    y = np.random.default_rng(seed).standard_normal(pp.cand.numel()).astype(np.float32)
+    return g, pp, nf, ef, theta, y
+
+
+def test_forward_and_gradient_match_oracle(S, SG):
+    g, pp, nf, ef, theta, y = _random_case(SG)
+    A, d = M.norm_adjacency(g.n, g.u, g.v, g.w.astype(np.float32).astype(np.float64))
+    X = nf.cpu().numpy().astype(np.float64)
+    E = ef.cpu().numpy().astype(np.float64)
+    cand = pp.cand.cpu().numpy()
+    th64 = theta.astype(np.float64)
+    yhat_ref, cache = M.forward(th64, A, d, X, g.u, g.v, cand, E)
+    grad_ref = M.backward(th64, A, d, X, y.astype(np.float64), yhat_ref, cache)
+    pred, loss, grad = S.sfg_mpnn_loss_grad(pp.G, dev(theta), nf, pp.u, pp.v, ef, dev(y), cand=pp.cand)
+    pred, grad = pred.cpu().numpy(), grad.cpu().numpy()
+    scale = np.max(np.abs(yhat_ref))
+    assert np.max(np.abs(pred - yhat_ref)) < 2e-5 * scale
+    assert abs(loss.item() - M.loss(yhat_ref, y)) < 1e-4 * M.loss(yhat_ref, y)
+    # per block of parameters, relative to that block's largest gradient
+    o = 0
+    for name, shape in M.LAYOUT:
+        c = int(np.prod(shape))
+        gr, gg = grad_ref[o:o + c], grad[o:o + c]
+        assert np.max(np.abs(gg - gr)) <= 1e-4 * max(np.max(np.abs(gr)), 1e-12), name
+        o += c
+    # BF16 activations (inference): close to the FP64 reference
+    pb = S.sfg_mpnn_forward(pp.G, dev(theta), nf, pp.u, pp.v, ef, cand=pp.cand, act=torch.bfloat16).cpu().numpy()
+    assert np.max(np.abs(pb - yhat_ref)) < 3e-2 * scale
+    pf = S.sfg_mpnn_forward(pp.G, dev(theta), nf, pp.u, pp.v, ef, cand=pp.cand, act=torch.float32).cpu().numpy()
+    assert np.max(np.abs(pf - yhat_ref)) < 2e-5 * scale
+
+
+def test_training_is_deterministic(S, SG):
+    g, pp, nf, ef, theta, y = _random_case(SG, 4)
+    a = S.sfg_mpnn_loss_grad(pp.G, dev(theta), nf, pp.u, pp.v, ef, dev(y), cand=pp.cand)[2]
+    b = S.sfg_mpnn_loss_grad(pp.G, dev(theta), nf, pp.u, pp.v, ef, dev(y), cand=pp.cand)[2]
+    assert torch.equal(a, b)
+
+
+def test_adam_matches_oracle(S):
+    rng = np.random.default_rng(0)
+    th = rng.standard_normal(4865)
+    m = np.zeros(4865)
+    v = np.zeros(4865)
+    tg, mg, vg = dev(th.astype(np.float32)), torch.zeros(4865, device="cuda"), torch.zeros(4865, device="cuda")
+    for step in range(1, 6):
+        gr = rng.standard_normal(4865)
+        th, m, v = M.adam_step(th, gr, m, v, step, lr=1e-2)
+        S.sfg_mpnn_adam(tg, dev(gr.astype(np.float32)), mg, vg, step, lr=1e-2)
+    np.testing.assert_allclose(tg.cpu().numpy(), th, rtol=0, atol=1e-5)
+
+
+def _train_small(S, SG, n_train=6, side=16, epochs=15):
+    graphs, targets = [], []
+    for i in range(n_train):
+        g = W.mesh3d(side, side, side, seed=300 + i, wdist=("lognormal", 0.0, 1.5))
+        pp = _prep(SG, g, seed=400 + i)
+        pp.raw_nf, pp.raw_ef = SG.features(pp, None)
+        s = SG.plain_scores(pp, dev(W.random_block(g.n, 16, 500 + i)), 20)
+        graphs.append(pp)
+        targets.append(torch.log(s + 1e-30))
+    return SG.train(SG.TrainSet(graphs, targets), epochs=epochs)
+
+
+def test_training_learns_and_beats_the_cheap_score(S, SG):
+    model, hist = _train_small(S, SG)
+    assert hist[-1] < 0.5 * hist[0]
+    # held-out mesh: recall of the plain method's top 10% inside the top 20% candidates
+    g = W.mesh3d(16, 16, 16, seed=350, wdist=("lognormal", 0.0, 1.5))
+    pp = _prep(SG, g, seed=450)
+    s = SG.plain_scores(pp, dev(W.random_block(g.n, 16, 550)), 20)
+    nc = int(pp.cand.numel())
+    ksel = int(np.ceil(0.1 * nc))
+    chosen = torch.nonzero(S.sfg_select_topk(s, ksel)[0]).reshape(-1)
+    cand_pos, pred = SG.prune(model, pp, 0.2)
+    r_net = SG.recall(chosen, cand_pos, nc)
+    # the method without the network: rank by the cheap embedding's own score
+    cheap = S.sfg_edge_scores(pp.xc, pp.u, pp.v, pp.w32, cand=pp.cand, score_dtype=torch.float32)
+    cheap_pos = torch.nonzero(S.sfg_select_topk(cheap, int(np.ceil(0.2 * nc)))[0]).reshape(-1)
+    r_cheap = SG.recall(chosen, cheap_pos, nc)
+    assert r_net >= r_cheap - 1e-9, (r_net, r_cheap)
+    assert r_net > 0.9, r_net
+
+
+def test_model_file_roundtrip_and_fallback(S, SG, tmp_path):
+    model = SG.Model(SG.init_params(1), torch.ones(24, device="cuda"), 0.0, 1.0)
+    p = str(tmp_path / "m.npz")
+    model.save(p)
+    m2 = SG.load(p)
+    assert torch.equal(m2.params, model.params)
+    # corrupted parameters: checksum mismatch
+    z = dict(np.load(p, allow_pickle=False))
+    z["params"] = z["params"].copy()
+    z["params"][5] += 1.0
+    np.savez(str(tmp_path / "bad.npz"), **z)
+    with pytest.raises(SG.SurrogateInvalid, match="checksum"):
+        SG.load(str(tmp_path / "bad.npz"))
+    z["params"][5] = np.nan
+    np.savez(str(tmp_path / "nan.npz"), **z)
+    with pytest.raises(SG.SurrogateInvalid, match="non-finite"):
+        SG.load(str(tmp_path / "nan.npz"))
+    with pytest.raises(SG.SurrogateInvalid):
+        SG.load(str(tmp_path / "missing.npz"))
