@@ -150,11 +150,12 @@ sfg_status sfg_edge_scores(const void *x, sfg_dtype xt, int64_t n, int32_t k, in
  * order the ne scores by value descending, then position ascending (callers
  * keep candidates in ascending edge id, so this is edge id ascending), and
  * mark the first k.
- *   score, st  [ne] non-negative F64 or F32 scores
+ *   score, st  [ne] F64 or F32 values (any sign; NaN is an error)
  *   sel        out [ne] uint8: 1 if chosen else 0
  *   tau        out (device, 1 double): the k-th largest score (+inf if k = 0)
  *   tau_host   (host, may be NULL) receives tau; synchronises when non-NULL
- * Errors: SFG_EINVAL when k > ne; SFG_ENUMERIC on a NaN or negative score.
+ * Errors: SFG_EINVAL when k > ne; SFG_ENUMERIC on a NaN (reported through
+ * tau_host, or as a NaN tau when tau_host is NULL).
  */
 sfg_status sfg_select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel,
                            double *tau, double *tau_host, void *ws, size_t ws_bytes, void *stream);

@@ -2,11 +2,10 @@
 // distortion"): order by score descending, then position ascending, keep the
 // first k.
 //
-// Scores are non-negative IEEE numbers, whose bit patterns order like the
-// values, so the k-th largest key is found by most-significant-digit radix
-// select: per pass, a histogram (LDS, integer atomics) of the keys that
-// still match the digits fixed so far, then one workgroup picks the digit
-// that contains rank k.  Passes stay on the device (no host round trips).
+// IEEE values map to unsigned keys that order like the values, so the k-th
+// largest key is found by most-significant-digit radix select: per pass, a
+// histogram (LDS, integer atomics) of the keys that still match the digits
+// fixed so far, then one workgroup picks the digit that contains rank k.  Passes stay on the device (no host round trips).
 // Ties at the threshold take the lowest positions: a scan over the tie flags
 // gives each tied key its rank.
 #include "common.hpp"
@@ -37,22 +36,40 @@ template <> struct KeyOf<float> {
     static constexpr int bits = 32;
 };
 
+// Order-preserving map of IEEE values to unsigned keys: negative values have
+// all bits flipped, non-negative ones only the sign bit.
 template <typename TS>
-__device__ __forceinline__ typename KeyOf<TS>::K key_of(TS x) {
+__device__ __forceinline__ typename KeyOf<TS>::K raw_bits(TS x) {
     typename KeyOf<TS>::K k;
     __builtin_memcpy(&k, &x, sizeof(k));
     return k;
 }
 
 template <typename TS>
-__device__ __forceinline__ bool bad_key(typename KeyOf<TS>::K k) {
+__device__ __forceinline__ typename KeyOf<TS>::K key_of(TS x) {
+    using K = typename KeyOf<TS>::K;
+    const K sign = K(1) << (KeyOf<TS>::bits - 1);
+    const K b = raw_bits(x);
+    return (b & sign) ? ~b : (b | sign);
+}
+
+template <typename TS>
+__device__ __forceinline__ TS value_of(typename KeyOf<TS>::K k) {
+    using K = typename KeyOf<TS>::K;
+    const K sign = K(1) << (KeyOf<TS>::bits - 1);
+    const K b = (k & sign) ? (k & ~sign) : ~k;
+    TS x;
+    __builtin_memcpy(&x, &b, sizeof(x));
+    return x;
+}
+
+template <typename TS>
+__device__ __forceinline__ bool is_nan_bits(typename KeyOf<TS>::K k) {
     using K = typename KeyOf<TS>::K;
     constexpr int B = KeyOf<TS>::bits;
     constexpr int mant = (B == 64) ? 52 : 23;
-    const K sign = K(1) << (B - 1);
     const K expmask = ((K(1) << (B - 1 - mant)) - 1) << mant;
-    // negative (including -0) or NaN
-    return (k & sign) || (((k & expmask) == expmask) && (k & ((K(1) << mant) - 1)));
+    return ((k & expmask) == expmask) && (k & ((K(1) << mant) - 1));
 }
 
 __global__ void k_sel_init(SelState *st, int64_t k, uint32_t *hist) {
@@ -78,11 +95,12 @@ __global__ __launch_bounds__(kHistThreads) void k_sel_hist(int64_t ne, const TS 
     const K dmask = (K(1) << width) - 1;
     uint32_t bad = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += (int64_t)gridDim.x * blockDim.x) {
-        const K key = key_of(score[i]);
-        if (check) bad |= bad_key<TS>(key) ? 1u : 0u;
+        const TS sv = score[i];
+        if (check) bad |= is_nan_bits<TS>(raw_bits(sv)) ? 1u : 0u;
+        const K key = key_of(sv);
         if ((key & fixed) == prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
     }
-    if (bad) atomicOr(&stw->err, 1u);
+    if (bad) atomicOr(&stw->err, 1u);   // NaN
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += blockDim.x)
         if (h[b]) atomicAdd(&hist[b], h[b]);
@@ -152,9 +170,7 @@ __global__ void k_sel_mark(int64_t ne, const TS *__restrict__ score, const SelSt
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const K thr = (K)st->prefix;
     if (i == 0) {
-        TS tv;
-        __builtin_memcpy(&tv, &thr, sizeof(tv));
-        *tau = st->err ? __builtin_nan("") : (double)tv;
+        *tau = st->err ? __builtin_nan("") : (double)value_of<TS>(thr);
     }
     if (i >= ne) return;
     const K key = key_of(score[i]);

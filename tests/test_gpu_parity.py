@@ -165,7 +165,7 @@ def test_scores_reduced_precision(S, orc):
 def test_select_topk_matches_sort(S, orc, dt):
     rng = np.random.default_rng(8)
     for ne, ties in ((1, False), (5000, True), (123457, False), (300000, True)):
-        s = rng.random(ne) * 10
+        s = rng.random(ne) * 10 - 2.0
         if ties:
             s = np.round(s * 16) / 16
         s = s.astype(dt == torch.float64 and np.float64 or np.float32).astype(np.float64)
@@ -186,9 +186,11 @@ def test_select_rejects_bad_scores(S):
     s = torch.tensor([1.0, float("nan"), 3.0], dtype=torch.float64, device="cuda")
     with pytest.raises(S.SfgError, match="SFG_ENUMERIC"):
         S.sfg_select_topk(s, 1)
-    s = torch.tensor([1.0, -2.0, 3.0], dtype=torch.float64, device="cuda")
-    with pytest.raises(S.SfgError, match="SFG_ENUMERIC"):
-        S.sfg_select_topk(s, 2)
+    s = torch.tensor([1.0, -2.0, 3.0, -0.5, 0.0], dtype=torch.float64, device="cuda")
+    sel, tau = S.sfg_select_topk(s, 3)          # signed values are ordered too
+    assert sel.cpu().tolist() == [1, 0, 1, 0, 1] and tau == 0.0
+    sel, tau = S.sfg_select_topk(s.float(), 4)
+    assert sel.cpu().tolist() == [1, 0, 1, 1, 1] and tau == -0.5
     with pytest.raises(S.SfgError, match="SFG_EINVAL"):
         S.sfg_select_topk(s, 4)
 
