@@ -3,8 +3,10 @@
 The network and its kernels are in ``csrc/mpnn.hip`` (C ABI ``sfg_mpnn_*``).
 This module drives them.  It only marshals and orchestrates; every numeric step runs
 in libsfg:
-  * a cheap embedding (``KC`` vectors smoothed on the spanning tree, BF16
-    storage with an FP32 last iterate) feeds the features;
+  * a cheap embedding -- the first ``KC`` of the method's own random
+    vectors, smoothed on the spanning tree with BF16 storage and an FP32
+    last iterate -- feeds the features (sharing the vectors makes the cheap
+    scores partial sums of the exact ones);
   * training targets are the plain method's own scores (``K`` vectors, ``T``
     sweeps, FP32), as standardised logs;
   * inference predicts every off-tree edge, keeps the top ``cand_frac`` as
@@ -228,9 +230,8 @@ class PrunedResult:
     k_sel: int
 
 
-def sparsify_pruned(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: torch.Tensor,
-                    x0c: torch.Tensor, model, sweeps: int, frac: float, cand_frac: float,
-                    storage=torch.float32) -> PrunedResult:
+def sparsify_pruned(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: torch.Tensor, model,
+                    sweeps: int, frac: float, cand_frac: float, storage=torch.float32) -> PrunedResult:
     """Spanning tree + top f of the off-tree edges, where only the surrogate's
     top cand_frac candidates are scored exactly.  ``model`` is a Model or a
     path; if it cannot be used the plain single-level path runs instead."""
@@ -244,7 +245,7 @@ def sparsify_pruned(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x
                                                                  storage=storage))
         r = rep[0]
         return PrunedResult(keep, True, str(e), int(r["n_cand"]), int(r["n_cand"]), int(r["k_sel"]))
-    pp = prepare(n, u, v, w, x0c, sweeps)
+    pp = prepare(n, u, v, w, x0[:, :KC].contiguous(), sweeps)
     cand_pos, _ = prune(mdl, pp, cand_frac)
     cand_e = pp.cand[cand_pos.long()].contiguous()
     X = S.sfg_smooth(pp.T, x0, sweeps, 0.5, storage=storage)

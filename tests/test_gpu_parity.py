@@ -192,7 +192,7 @@ def test_select_rejects_bad_scores(S):
     sel, tau = S.sfg_select_topk(s.float(), 4)
     assert sel.cpu().tolist() == [1, 0, 1, 1, 1] and tau == -0.5
     with pytest.raises(S.SfgError, match="SFG_EINVAL"):
-        S.sfg_select_topk(s, 4)
+        S.sfg_select_topk(s, 6)
 
 
 # --------------------------------------------------------------------------- spanning tree

@@ -113,36 +113,42 @@ def test_adam_matches_oracle(S):
     np.testing.assert_allclose(tg.cpu().numpy(), th, rtol=0, atol=1e-5)
 
 
-def _train_small(S, SG, n_train=6, side=16, epochs=15):
-    graphs, targets = [], []
-    for i in range(n_train):
-        g = W.mesh3d(side, side, side, seed=300 + i, wdist=("lognormal", 0.0, 1.5))
-        pp = _prep(SG, g, seed=400 + i)
-        pp.raw_nf, pp.raw_ef = SG.features(pp, None)
-        s = SG.plain_scores(pp, dev(W.random_block(g.n, 16, 500 + i)), 20)
-        graphs.append(pp)
-        targets.append(torch.log(s + 1e-30))
-    return SG.train(SG.TrainSet(graphs, targets), epochs=epochs)
+def _mesh_case(S, SG, seed, side):
+    g = W.mesh3d(side, side, side, seed=seed, wdist=("lognormal", 0.0, 1.5))
+    X0 = W.random_block(g.n, 16, 500 + seed)
+    pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0[:, :SG.KC]), 20)
+    pp.raw_nf, pp.raw_ef = SG.features(pp, None)
+    return g, X0, pp, SG.plain_scores(pp, dev(X0), 20)
+
+
+def _train_small(S, SG, n_train=10, side=20, epochs=30):
+    cases = [_mesh_case(S, SG, 300 + i, side) for i in range(n_train)]
+    ts = SG.TrainSet([c[2] for c in cases], [torch.log(c[3] + 1e-30) for c in cases])
+    return SG.train(ts, epochs=epochs)
 
 
 def test_training_learns_and_beats_the_cheap_score(S, SG):
     model, hist = _train_small(S, SG)
-    assert hist[-1] < 0.5 * hist[0]
-    # held-out mesh: recall of the plain method's top 10% inside the top 20% candidates
-    g = W.mesh3d(16, 16, 16, seed=350, wdist=("lognormal", 0.0, 1.5))
-    pp = _prep(SG, g, seed=450)
-    s = SG.plain_scores(pp, dev(W.random_block(g.n, 16, 550)), 20)
+    assert hist[-1] < 0.1 * hist[0]
+    # held-out mesh: recall of the plain method's top 10% inside the top candidates
+    g, X0, pp, s = _mesh_case(S, SG, 350, 20)
     nc = int(pp.cand.numel())
-    ksel = int(np.ceil(0.1 * nc))
-    chosen = torch.nonzero(S.sfg_select_topk(s, ksel)[0]).reshape(-1)
-    cand_pos, pred = SG.prune(model, pp, 0.2)
-    r_net = SG.recall(chosen, cand_pos, nc)
+    chosen = torch.nonzero(S.sfg_select_topk(s, int(np.ceil(0.1 * nc)))[0]).reshape(-1)
+    pred = SG.predict(model, pp)
     # the method without the network: rank by the cheap embedding's own score
     cheap = S.sfg_edge_scores(pp.xc, pp.u, pp.v, pp.w32, cand=pp.cand, score_dtype=torch.float32)
-    cheap_pos = torch.nonzero(S.sfg_select_topk(cheap, int(np.ceil(0.2 * nc)))[0]).reshape(-1)
-    r_cheap = SG.recall(chosen, cheap_pos, nc)
-    assert r_net >= r_cheap - 1e-9, (r_net, r_cheap)
-    assert r_net > 0.9, r_net
+    rec = {}
+    for cf in (0.2, 0.5):
+        kk = int(np.ceil(cf * nc))
+        rec[("net", cf)] = SG.recall(chosen, torch.nonzero(S.sfg_select_topk(pred, kk)[0]).reshape(-1), nc)
+        rec[("cheap", cf)] = SG.recall(chosen, torch.nonzero(S.sfg_select_topk(cheap, kk)[0]).reshape(-1), nc)
+    assert rec[("net", 0.2)] > rec[("cheap", 0.2)] + 0.03, rec
+    assert rec[("net", 0.5)] >= 0.98, rec
+    # the pruned pipeline scores only the candidates and keeps the tree
+    res = SG.sparsify_pruned(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), model, 20, 0.1, 0.5)
+    assert not res.fallback and res.n_scored == int(np.ceil(0.5 * nc))
+    kp = res.keep.cpu().numpy()
+    assert (kp == 1).sum() == g.n - 1 and (kp == 2).sum() == res.k_sel
 
 
 def test_model_file_roundtrip_and_fallback(S, SG, tmp_path):
@@ -164,3 +170,11 @@ def test_model_file_roundtrip_and_fallback(S, SG, tmp_path):
         SG.load(str(tmp_path / "nan.npz"))
     with pytest.raises(SG.SurrogateInvalid):
         SG.load(str(tmp_path / "missing.npz"))
+    # the pruned path falls back to the plain scorer on a bad model
+    g = W.mesh3d(10, 10, 10, seed=360)
+    X0 = W.random_block(g.n, 16, 1)
+    res = SG.sparsify_pruned(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), str(tmp_path / "nan.npz"), 20, 0.1, 0.2)
+    assert res.fallback and "non-finite" in res.reason
+    keep, _ = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), S.make_params(k=16, sweeps=20, frac=0.1,
+                                                                                       storage=torch.float32))
+    assert torch.equal(res.keep, keep)
