@@ -56,6 +56,9 @@ def main():
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=10)
+    ap.add_argument("--workload", choices=["powergrid", "knn", "chunglu", "mesh"], default="powergrid",
+                    help="powergrid: the headline line; the others print their own lines (bench_workloads.py)")
+    ap.add_argument("--no-oracle", action="store_true", help="skip the oracle comparison of the extra workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
@@ -72,6 +75,11 @@ def main():
         sys.exit(1)
     S.lib()
     dev = torch.device("cuda:0")
+    if args.workload != "powergrid":
+        import bench_workloads
+
+        bench_workloads.run(args)
+        return
 
     cfg = 2
     prm = W.config_params(cfg)

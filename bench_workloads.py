@@ -1,0 +1,273 @@
+"""Extra benchmark lines for the other synthetic workloads (called by bench.py).
+
+    python bench.py --workload knn      # 2M-point 3-D kNN, FP16/BF16 storage + FP64 band re-scoring
+    python bench.py --workload chunglu  # 4M-node power-law graph, 5-level hierarchy (Alg. 1)
+    python bench.py --workload mesh     # 200^3 mesh, plain FP32 path and the learned surrogate
+
+Each prints one JSON line; all inputs are seeded and synthetic.  Accuracy
+against the oracle at these sizes is checked by tests/test_gpu_workloads.py.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+import workloads as W
+from paper_2008_07633_amd import sfg as S
+
+CACHE = os.environ.get("SFG_CACHE", "/tmp/sfg_cache")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cached_graph(cfg: int) -> W.Graph:
+    os.makedirs(CACHE, exist_ok=True)
+    path = os.path.join(CACHE, f"cfg{cfg}.npz")
+    if os.path.exists(path):
+        z = np.load(path, allow_pickle=False)
+        w32 = z["w32"] if "w32" in z else None
+        return W.Graph(int(z["n"]), z["u"], z["v"], z["w"], name=str(z["name"]), w32=w32)
+    t = time.time()
+    g = W.config_graph(cfg)
+    log(f"generated config {cfg} ({g.name}: {g.n} nodes, {g.m} edges) in {time.time() - t:.1f} s")
+    extra = {"w32": g.w32} if g.w32 is not None else {}
+    np.savez(path, n=g.n, u=g.u, v=g.v, w=g.w, name=g.name, **extra)
+    return g
+
+
+def ev_time(fn, reps: int) -> float:
+    fn()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def sweep_roofline(H, x0, sweeps, storage, final_f32, n, nnz, k, sx, sw, reps=5):
+    t_all = ev_time(lambda: S.sfg_smooth(H, x0, sweeps, 0.5, storage=storage, final_f32=final_f32), reps)
+    t_one = ev_time(lambda: S.sfg_smooth(H, x0, 1, 0.5, storage=storage, final_f32=final_f32), reps)
+    t_sw = (t_all - t_one) / (sweeps - 1)
+    b = 4 * (n + 1) + nnz * (4 + sw) + n * sw + 2 * n * k * sx
+    ach = b / (t_sw * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "algorithmic_bytes_per_launch": b,
+            "avg_launch_us": round(t_sw * 1e3, 2)}
+
+
+def to_dev(g: W.Graph, f32: bool = False):
+    u = torch.from_numpy(g.u).cuda()
+    v = torch.from_numpy(g.v).cuda()
+    w = torch.from_numpy(g.w32 if (f32 and g.w32 is not None) else (g.w.astype(np.float32) if f32 else g.w)).cuda()
+    return u, v, w
+
+
+# ----------------------------------------------------------------------------- kNN: precision form
+
+def run_knn(args) -> dict:
+    g = cached_graph(3)
+    prm = W.config_params(3)
+    k, T, f, band = prm["k"], prm["sweeps"], prm["frac"], prm["band"]
+    X0 = W.config_block(3, g.n)
+    u, v, w64 = to_dev(g)
+    x0 = torch.from_numpy(X0).cuda()
+    res = {}
+    for name, storage, ff in (("f16+f32last", torch.float16, True), ("bf16+f32last", torch.bfloat16, True),
+                              ("f32", torch.float32, False)):
+        p = S.make_params(k=k, sweeps=T, frac=f, storage=storage, final_f32=ff, band=band)
+        S.sfg_sparsify(g.n, u, v, w64, x0, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep, rep = S.sfg_sparsify(g.n, u, v, w64, x0, p)
+        t1 = time.perf_counter()
+        r = rep[0]
+        res[name] = {"ms_total": round((t1 - t0) * 1e3, 2), "ms_smooth": round(r["ms_smooth"], 3),
+                     "ms_score": round(r["ms_score"], 3), "ms_select_and_band": round(r["ms_select"], 3),
+                     "band_edges": r["band"], "band_doublings": r["band_rounds"], "cone_row_updates": r["cone_rows"]}
+        log(f"knn {name}: {res[name]}")
+    p = S.make_params(k=k, sweeps=T, frac=f)
+    S.sfg_sparsify(g.n, u, v, w64, x0, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = S.sfg_sparsify(g.n, u, v, w64, x0, p)
+    t1 = time.perf_counter()
+    res["f64"] = {"ms_total": round((t1 - t0) * 1e3, 2), "ms_smooth": round(rep[0]["ms_smooth"], 3)}
+    n_cand = rep[0]["n_cand"]
+    # FP16 sweep roofline on the tree
+    tree, _ = S.sfg_spanning_tree(g.n, u, v, w64)
+    H = S.sfg_laplacian_csr(g.n, u, v, w64.float(), mask=tree)
+    roof = sweep_roofline(H, x0, T, torch.float16, True, g.n, H.nnz, k, 2, 4)
+    best = min(res["f16+f32last"]["ms_total"], res["f64"]["ms_total"])
+    return {"metric": "off-tree edges scored/s (precision form, FP16 storage + FP64 band re-scoring)",
+            "value": round(n_cand / (res["f16+f32last"]["ms_total"] * 1e-3), 1), "unit": "edges/s",
+            "dtype": "f16", "data": "synthetic",
+            "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "off_tree_edges": n_cand, "vectors": k,
+                       "sweeps": T, "frac": f, "band": band},
+            "runs": res, "roofline_f16_sweep": roof, "fastest_ms": best}
+
+
+# ----------------------------------------------------------------------------- Chung-Lu: multilevel
+
+def run_chunglu(args) -> dict:
+    g = cached_graph(4)
+    prm = W.config_params(4)
+    k, T, f, L = prm["k"], prm["sweeps"], prm["frac"], prm["levels"]
+    u, v, w32 = to_dev(g, f32=True)
+    log("drawing the per-level random blocks")
+    x0 = torch.empty((L, g.n, k), dtype=torch.float64, device="cuda")
+    for l in range(L):
+        x0[l] = torch.from_numpy(W.config_block(4, g.n, level=l)).cuda()
+    out = {}
+    for name, storage in (("f32", torch.float32), ("f64", torch.float64)):
+        p = S.make_params(levels=L, k=k, sweeps=T, frac=f, storage=storage)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep, rep = S.sfg_sparsify(g.n, u, v, w32, x0, p)
+        t1 = time.perf_counter()
+        out[name] = {"ms_total": round((t1 - t0) * 1e3, 1),
+                     "levels": [{"n": r["n"], "m": r["m"], "n_cand": r["n_cand"], "k_sel": r["k_sel"],
+                                 "ms_smooth": round(r["ms_smooth"], 3), "ms_score": round(r["ms_score"], 3),
+                                 "ms_select": round(r["ms_select"], 3)} for r in rep],
+                     "kept_edges": int((keep > 0).sum().item())}
+        log(f"chunglu {name}: {out[name]['ms_total']} ms, sizes {[r['n'] for r in rep]}")
+    G = S.sfg_laplacian_csr(g.n, u, v, w32)
+    roof = sweep_roofline(G, x0[0], T, torch.float32, False, g.n, G.nnz, k, 4, 4)
+    lv = out["f32"]["levels"]
+    ratio = [round(lv[i]["n"] / lv[i + 1]["n"], 2) for i in range(len(lv) - 1) if lv[i + 1]["n"] > 0]
+    return {"metric": "edges per second through the 5-level hierarchy (coarsening + scoring at every level)",
+            "value": round(g.m / (out["f32"]["ms_total"] * 1e-3), 1), "unit": "edges/s", "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "vectors": k, "sweeps": T, "frac": f,
+                       "levels": L},
+            "runs": out, "coarsening_ratio": ratio, "roofline_f32_sweep_level0_graph": roof,
+            "note": "host Kruskal spanning forests are included in ms_total"}
+
+
+# ----------------------------------------------------------------------------- 3-D mesh: plain vs surrogate
+
+def run_mesh(args) -> dict:
+    from paper_2008_07633_amd import surrogate as SG
+
+    prm = W.config_params(5)
+    k, T, f, cf = prm["k"], prm["sweeps"], prm["frac"], prm["cand_frac"]
+    # ---- train on 50 seeded 40^3 meshes with the plain method's own FP32 scores
+    t0 = time.time()
+    graphs, targets = [], []
+    for i in range(50):
+        gm = W.mesh3d(40, 40, 40, seed=100 + i, wdist=("lognormal", 0.0, 1.5))
+        X0m = W.random_block(gm.n, k, 2000 + i)
+        um, vm, wm = to_dev(gm)
+        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :SG.KC]).cuda(), T)
+        pp.raw_nf, pp.raw_ef = SG.features(pp, None)
+        s = SG.plain_scores(pp, torch.from_numpy(X0m).cuda(), T)
+        graphs.append(pp)
+        targets.append(torch.log(s + 1e-30))
+    t_data = time.time() - t0
+    t0 = time.time()
+    model, hist = SG.train(SG.TrainSet(graphs, targets), epochs=60)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+    log(f"surrogate trained: loss {hist[0]:.3f} -> {hist[-1]:.3f} in {t_train:.1f} s (data {t_data:.1f} s)")
+    del graphs, targets
+    # ---- held-out 40^3 meshes: recall of the plain selection inside the candidates
+    rec = {"net": {}, "cheap": {}}
+    for i in range(5):
+        gm = W.mesh3d(40, 40, 40, seed=200 + i, wdist=("lognormal", 0.0, 1.5))
+        X0m = W.random_block(gm.n, k, 3000 + i)
+        um, vm, wm = to_dev(gm)
+        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :SG.KC]).cuda(), T)
+        s = SG.plain_scores(pp, torch.from_numpy(X0m).cuda(), T)
+        nc = int(pp.cand.numel())
+        chosen = torch.nonzero(S.sfg_select_topk(s, int(math.ceil(f * nc)))[0]).reshape(-1)
+        pred = SG.predict(model, pp)
+        cheap = S.sfg_edge_scores(pp.xc, pp.u, pp.v, pp.w32, cand=pp.cand, score_dtype=torch.float32)
+        for c in (0.2, 0.3, 0.5):
+            kk = int(math.ceil(c * nc))
+            for nm, r in (("net", pred), ("cheap", cheap)):
+                pos = torch.nonzero(S.sfg_select_topk(r, kk)[0]).reshape(-1)
+                rec[nm].setdefault(str(c), []).append(SG.recall(chosen, pos, nc))
+    recall = {nm: {c: round(float(np.mean(x)), 4) for c, x in d.items()} for nm, d in rec.items()}
+    log(f"recall on held-out meshes: {recall}")
+    # ---- full 200^3 mesh: plain path vs pruned path, end to end on the device
+    g = cached_graph(5)
+    X0 = W.config_block(5, g.n)
+    u, v, w64 = to_dev(g)
+    x0 = torch.from_numpy(X0).cuda()
+    w32 = w64.float()
+    tree, _ = S.sfg_spanning_tree(g.n, u, v, w64)
+    cand = torch.nonzero(tree == 0).reshape(-1).to(torch.int32)
+    nc = int(cand.numel())
+    ksel = int(math.ceil(f * nc))
+    nnz = 2 * (g.n - 1)
+    H = S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree)
+    ws_sm = torch.empty(S.sfg_workspace_bytes(S.OP_SMOOTH, g.n, 0, k, torch.float32), dtype=torch.uint8,
+                        device="cuda")
+    X = torch.empty((g.n, k), dtype=torch.float32, device="cuda")
+    score = torch.empty(nc, dtype=torch.float32, device="cuda")
+
+    def plain_step():
+        S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree, out=H, nnz=nnz)
+        S.sfg_smooth(H, x0, T, 0.5, storage=torch.float32, out=X, ws=ws_sm)
+        S.sfg_edge_scores(X, u, v, w32, cand=cand, out=score)
+        return S.sfg_select_topk(score, ksel, sync=False)
+
+    t_plain = ev_time(plain_step, 3)
+    plain_sel = plain_step()[0]
+    chosen = torch.nonzero(plain_sel).reshape(-1)
+    G = S.sfg_laplacian_csr(g.n, u, v, w32)
+    x0c = x0[:, :SG.KC].contiguous()
+    ws_f = torch.empty(S.sfg_workspace_bytes(S.OP_MPNN_FORWARD, g.n, 0, 0, torch.bfloat16), dtype=torch.uint8,
+                       device="cuda")
+    kc = int(math.ceil(cf * nc))
+
+    def pruned_step():
+        S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree, out=H, nnz=nnz)
+        xc = S.sfg_smooth(H, x0c, T, 0.5, storage=torch.bfloat16, final_f32=True)
+        pp = SG.Prepared(g.n, u, v, w32, tree, cand, G, H, xc)
+        nf, ef = SG.features(pp, model.norm)
+        pred = S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
+        csel, _ = S.sfg_select_topk(pred, kc, sync=False)
+        cpos = torch.nonzero(csel).reshape(-1)
+        ce = cand[cpos].contiguous()
+        S.sfg_smooth(H, x0, T, 0.5, storage=torch.float32, out=X, ws=ws_sm)
+        s2 = S.sfg_edge_scores(X, u, v, w32, cand=ce)
+        sel2, _ = S.sfg_select_topk(s2, min(ksel, int(ce.numel())), sync=False)
+        return cpos, sel2
+
+    t_pruned = ev_time(pruned_step, 3)
+    cpos, sel2 = pruned_step()
+    r_full = SG.recall(chosen, cpos, nc)
+    final_pos = cpos[sel2.bool()]
+    mark = torch.zeros(nc, dtype=torch.bool, device="cuda")
+    mark[final_pos.long()] = True
+    set_agree = float(mark[chosen.long()].float().mean().item())
+    roof = sweep_roofline(H, x0, T, torch.float32, False, g.n, nnz, k, 4, 4)
+    return {"metric": "surrogate vs plain: recall of the plain selection and end-to-end time",
+            "value": round(nc / (t_plain * 1e-3), 1), "unit": "edges/s (plain path)", "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "off_tree_edges": nc, "vectors": k,
+                       "sweeps": T, "frac": f, "cand_frac": cf, "train": "50 meshes 40^3, 60 epochs"},
+            "plain_ms": round(t_plain, 3), "surrogate_pruned_ms": round(t_pruned, 3),
+            "surrogate_vs_plain_time": round(t_pruned / t_plain, 3),
+            "recall_full_mesh_at_cand_frac": round(r_full, 4), "selected_set_agreement": round(set_agree, 4),
+            "recall_heldout_40cubed": recall, "train_loss": [round(hist[0], 4), round(hist[-1], 4)],
+            "train_s": round(t_train, 2), "roofline_f32_sweep_tree": roof}
+
+
+def run(args) -> None:
+    fn = {"knn": run_knn, "chunglu": run_chunglu, "mesh": run_mesh}[args.workload]
+    out = fn(args)
+    out["n_gpus"] = 1
+    print(json.dumps(out), flush=True)

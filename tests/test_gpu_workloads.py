@@ -1,0 +1,94 @@
+"""Full-size checks of the extra workloads against the oracle.
+
+* 2M-point kNN graph (32 vectors, 20 sweeps, 10%): reduced-precision scores
+  against the FP64 oracle (three error measures), and the selected set after
+  FP64 re-scoring of the 1% band identical to the oracle's.
+* Surrogate on 3-D meshes: the condition number reached by the pruned
+  sparsifier against the plain one (the oracle's kappa estimator).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_07633_amd import sfg
+
+    sfg.lib()
+    return sfg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_knn_full_size_precision(S, orc):
+    g = W.config_graph(3)
+    prm = W.config_params(3)
+    k, T, f, band = prm["k"], prm["sweeps"], prm["frac"], prm["band"]
+    X0 = W.config_block(3, g.n)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, T, f)
+    lr = ref.levels[0]
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    x0 = dev(X0)
+    tree = dev((ref.keep == 1).astype(np.uint8))
+    H = S.sfg_laplacian_csr(g.n, u, v, w.float(), mask=tree)
+    cand = dev(lr.cand)
+    errs = {}
+    for name, storage, ff in (("f16+f32last", torch.float16, True), ("f16", torch.float16, False),
+                              ("bf16+f32last", torch.bfloat16, True), ("f32", torch.float32, False)):
+        X = S.sfg_smooth(H, x0, T, 0.5, storage=storage, final_f32=ff)
+        s = S.sfg_edge_scores(X, u, v, w.float(), cand=cand).cpu().numpy().astype(np.float64)
+        errs[name] = orc.score_errors(s, lr.score, lr.tau)
+    print("score errors vs FP64 oracle:", errs, flush=True)
+    assert errs["f16+f32last"]["max_rel_selected_region"] <= 1e-2
+    assert errs["f32"]["max_abs_over_tau"] <= 1e-4
+    for name, storage, ff in (("f16+f32last", torch.float16, True), ("bf16+f32last", torch.bfloat16, True)):
+        p = S.make_params(k=k, sweeps=T, frac=f, storage=storage, final_f32=ff, band=band)
+        keep, rep = S.sfg_sparsify(g.n, u, v, w, x0, p)
+        got = keep.cpu().numpy()
+        print(name, "band", rep[0]["band"], "doublings", rep[0]["band_rounds"], "cone rows", rep[0]["cone_rows"],
+              "differing edges", int((got != ref.keep).sum()), flush=True)
+        assert np.array_equal(got, ref.keep), name
+
+
+def _kappa_pair(S, orc, model, SG, seed, side=24):
+    g = W.mesh3d(side, side, side, seed=seed, wdist=("lognormal", 0.0, 1.5))
+    X0 = W.random_block(g.n, 16, 7000 + seed)
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    plain, _ = S.sfg_sparsify(g.n, u, v, w, dev(X0), S.make_params(k=16, sweeps=20, frac=0.1,
+                                                                    storage=torch.float32))
+    res = SG.sparsify_pruned(g.n, u, v, w, dev(X0), model, 20, 0.1, 0.2)
+    kp = orc.kappa_sparse(g.n, g.u, g.v, g.w, plain.cpu().numpy() > 0)[0]
+    ks = orc.kappa_sparse(g.n, g.u, g.v, g.w, res.keep.cpu().numpy() > 0)[0]
+    tree = plain.cpu().numpy() == 1
+    kt = orc.kappa_sparse(g.n, g.u, g.v, g.w, tree)[0]
+    return kp, ks, kt
+
+
+def test_surrogate_condition_number(S, orc):
+    from paper_2008_07633_amd import surrogate as SG
+
+    graphs, targets = [], []
+    for i in range(12):
+        g = W.mesh3d(24, 24, 24, seed=100 + i, wdist=("lognormal", 0.0, 1.5))
+        X0 = W.random_block(g.n, 16, 2000 + i)
+        pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0[:, :SG.KC]), 20)
+        pp.raw_nf, pp.raw_ef = SG.features(pp, None)
+        graphs.append(pp)
+        targets.append(torch.log(SG.plain_scores(pp, dev(X0), 20) + 1e-30))
+    model, hist = SG.train(SG.TrainSet(graphs, targets), epochs=40)
+    rows = [_kappa_pair(S, orc, model, SG, 200 + i) for i in range(3)]
+    print("kappa plain / pruned-surrogate / tree only:", rows, flush=True)
+    for kp, ks, kt in rows:
+        assert ks < kt / 5          # far better than the tree alone
+        assert ks <= 1.5 * kp       # close to the plain sparsifier
