@@ -169,7 +169,8 @@ sfg_status sfg_select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t 
  *   in_tree    out [m] uint8: 1 for tree edges
  *   n_comp     (host) receives the number of components of the forest;
  *              synchronises
- * Errors: SFG_ENOMEM, SFG_EHIP.  (Allocates internally.)
+ * Runs Boruvka rounds on the device (integer atomics only, deterministic).
+ * Errors: SFG_ENOMEM, SFG_EHIP.  (Allocates internally, stream-ordered.)
  */
 sfg_status sfg_spanning_tree(int64_t n, int64_t m, const int32_t *u, const int32_t *v,
                              const void *w, sfg_dtype wt, const uint8_t *allowed,

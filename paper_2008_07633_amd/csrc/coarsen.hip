@@ -36,8 +36,8 @@ size_t affinity_workspace_bytes(int64_t n, int32_t k);
 void affinity(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t m, const int32_t *u, const int32_t *v,
               void *aff, sfg_dtype at, void *ws, size_t ws_bytes, hipStream_t s);
 void convert_weights(const void *w, sfg_dtype wt, sfg_dtype want, int64_t m, void *out, hipStream_t s);
-int64_t spanning_tree_host(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
-                           const uint8_t *allowed, uint8_t *in_tree, hipStream_t s);
+int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                          const uint8_t *allowed, uint8_t *in_tree, DevArena &A, hipStream_t s);
 void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
                  const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
                  DevArena &A, hipStream_t s);
@@ -344,7 +344,7 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
     }
     {
         uint8_t *t = A.alloc<uint8_t>(m + 1);
-        const int64_t comps = spanning_tree_host(n, m, u, v, lv[0].w64, SFG_F64, nullptr, t, s);
+        const int64_t comps = spanning_tree_gpu(n, m, u, v, lv[0].w64, SFG_F64, nullptr, t, A, s);
         if (comps != 1) fail(SFG_ENOTCONN, "sparsify: graph has " + std::to_string(comps) + " components");
     }
     // ---- coarsening: G_0 .. G_{L-1}
@@ -404,7 +404,7 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
         hipLaunchKernelGGL(k_intra_mask, dim3(grid_for(F.m, 256)), dim3(256), 0, s, F.m, F.u, F.v, F.agg, intra);
         SFG_LAUNCH_CHECK();
         uint8_t *base = A.alloc<uint8_t>(F.m + 1);
-        spanning_tree_host(F.n, F.m, F.u, F.v, F.w64, SFG_F64, intra, base, s);   // per-aggregate trees
+        spanning_tree_gpu(F.n, F.m, F.u, F.v, F.w64, SFG_F64, intra, base, A, s);   // per-aggregate trees
         if (C.m > 0) {
             hipLaunchKernelGGL(k_map_inter, dim3(grid_for(C.m, 256)), dim3(256), 0, s, C.m, P, F.crep, base);
             SFG_LAUNCH_CHECK();

@@ -1,6 +1,5 @@
-// Sparsifier driver (the problem of Sec. 2.2, Alg. 1) and its host-side
-// helpers: input validation, candidate compaction, the maximum-weight
-// spanning tree, and workspace sizing.
+// Sparsifier driver (the problem of Sec. 2.2, Alg. 1) and its helpers:
+// input validation, candidate compaction, and workspace sizing.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
@@ -170,64 +169,8 @@ void convert_weights(const void *w, sfg_dtype wt, sfg_dtype want, int64_t m, voi
     SFG_LAUNCH_CHECK();
 }
 
-// ------------------------------------------------------------------ maximum-weight spanning tree
-// Kruskal on the host over (weight desc, edge id asc).  The tree is input
-// preparation for the scoring passes, computed once per graph.
-
-int64_t spanning_tree_host(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
-                           const uint8_t *allowed, uint8_t *in_tree, hipStream_t s) {
-    std::vector<int32_t> hu(m), hv(m);
-    std::vector<double> hw(m);
-    std::vector<uint8_t> hal;
-    if (m > 0) {
-        SFG_HIP(hipMemcpyAsync(hu.data(), u, m * 4, hipMemcpyDeviceToHost, s));
-        SFG_HIP(hipMemcpyAsync(hv.data(), v, m * 4, hipMemcpyDeviceToHost, s));
-        if (wt == SFG_F64) {
-            SFG_HIP(hipMemcpyAsync(hw.data(), w, m * 8, hipMemcpyDeviceToHost, s));
-        } else {
-            std::vector<float> f(m);
-            SFG_HIP(hipMemcpyAsync(f.data(), w, m * 4, hipMemcpyDeviceToHost, s));
-            SFG_HIP(hipStreamSynchronize(s));
-            for (int64_t e = 0; e < m; ++e) hw[e] = f[e];
-        }
-        if (allowed) {
-            hal.resize(m);
-            SFG_HIP(hipMemcpyAsync(hal.data(), allowed, m, hipMemcpyDeviceToHost, s));
-        }
-        SFG_HIP(hipStreamSynchronize(s));
-    }
-    std::vector<int32_t> ord;
-    ord.reserve(m);
-    for (int64_t e = 0; e < m; ++e)
-        if (!allowed || hal[e]) ord.push_back((int32_t)e);
-    std::sort(ord.begin(), ord.end(), [&](int32_t a, int32_t b) {
-        if (hw[a] != hw[b]) return hw[a] > hw[b];
-        return a < b;
-    });
-    std::vector<int32_t> par(n);
-    std::iota(par.begin(), par.end(), 0);
-    auto find = [&](int32_t x) {
-        while (par[x] != x) {
-            par[x] = par[par[x]];
-            x = par[x];
-        }
-        return x;
-    };
-    std::vector<uint8_t> t(m, 0);
-    int64_t comps = n;
-    for (int32_t e : ord) {
-        int32_t a = find(hu[e]), b = find(hv[e]);
-        if (a == b) continue;
-        if (a < b) par[b] = a; else par[a] = b;
-        t[e] = 1;
-        --comps;
-    }
-    if (m > 0) {
-        SFG_HIP(hipMemcpyAsync(in_tree, t.data(), m, hipMemcpyHostToDevice, s));
-        SFG_HIP(hipStreamSynchronize(s));
-    }
-    return comps;
-}
+int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                          const uint8_t *allowed, uint8_t *in_tree, DevArena &A, hipStream_t s);
 
 // ------------------------------------------------------------------ one scoring pass
 
@@ -361,7 +304,7 @@ void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t
         convert_weights(w, wt, SFG_F32, m, w32, s);
     }
     uint8_t *tree = A.alloc<uint8_t>(m + 1);
-    const int64_t comps = spanning_tree_host(n, m, u, v, w64, SFG_F64, nullptr, tree, s);
+    const int64_t comps = spanning_tree_gpu(n, m, u, v, w64, SFG_F64, nullptr, tree, A, s);
     if (comps != 1) fail(SFG_ENOTCONN, "sparsify: graph has " + std::to_string(comps) + " components");
     sfg_level_report *lr = rep ? &rep->level[0] : nullptr;
     if (rep) rep->levels = 1;
@@ -403,7 +346,8 @@ extern "C" sfg_status sfg_spanning_tree(int64_t n, int64_t m, const int32_t *u, 
         SFG_REQUIRE(n >= 1 && m >= 0, SFG_EINVAL, "spanning_tree: bad sizes");
         SFG_REQUIRE(wt == SFG_F64 || wt == SFG_F32, SFG_EINVAL, "spanning_tree: weights must be F64 or F32");
         SFG_REQUIRE(n_comp, SFG_EINVAL, "spanning_tree: n_comp is required");
-        *n_comp = sfg::spanning_tree_host(n, m, u, v, w, wt, allowed, in_tree, sfg::as_stream(stream));
+        sfg::DevArena A(sfg::as_stream(stream));
+        *n_comp = sfg::spanning_tree_gpu(n, m, u, v, w, wt, allowed, in_tree, A, sfg::as_stream(stream));
     });
 }
 

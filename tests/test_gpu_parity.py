@@ -269,3 +269,27 @@ def test_workspace_too_small(S):
     ws = torch.empty(16, dtype=torch.uint8, device="cuda")
     with pytest.raises(S.SfgError, match="SFG_EWORKSPACE"):
         S.sfg_smooth(H, dev(W.random_block(g.n, 4, 2)), 3, ws=ws)
+
+
+@pytest.mark.parametrize("case", ["unit_grid", "ties_f32", "forest", "chunglu"])
+def test_spanning_tree_ties_and_forests(S, orc, case):
+    if case == "unit_grid":
+        g = W.grid2d(37, 41, seed=90, wdist=("unit",))
+        w, allowed = g.w, None
+    elif case == "ties_f32":
+        g = W.random_connected(5000, 20000, seed=91)
+        w, allowed = np.round(g.w * 4) / 4, None            # heavy ties
+    elif case == "forest":
+        g = W.powergrid(60, 50, 0.02, seed=92)
+        w = g.w
+        allowed = (np.random.default_rng(1).random(g.m) < 0.6).astype(np.uint8)
+    else:
+        g = W.chung_lu(30000, 300000, 2.2, seed=93)
+        w, allowed = g.w32.astype(np.float64), None
+    ref, comps = orc.max_spanning_forest(g.n, g.u, g.v, w, allowed=allowed)
+    t, c = S.sfg_spanning_tree(g.n, dev(g.u), dev(g.v), dev(w), allowed=None if allowed is None else dev(allowed))
+    assert c == comps
+    assert np.array_equal(host(t), ref)
+    if case == "chunglu":   # FP32 weights give the same forest
+        t32, c32 = S.sfg_spanning_tree(g.n, dev(g.u), dev(g.v), dev(g.w32))
+        assert c32 == comps and np.array_equal(host(t32), ref)

@@ -52,8 +52,11 @@ def test_knn_full_size_precision(S, orc):
     print("score errors vs FP64 oracle:", errs, flush=True)
     assert errs["f16+f32last"]["max_rel_selected_region"] <= 1e-2
     assert errs["f32"]["max_abs_over_tau"] <= 1e-4
-    for name, storage, ff in (("f16+f32last", torch.float16, True), ("bf16+f32last", torch.bfloat16, True)):
-        p = S.make_params(k=k, sweeps=T, frac=f, storage=storage, final_f32=ff, band=band)
+    # the band must exceed the storage's threshold-normalised error: 1% covers FP16
+    # (measured 0.3%); BF16 (measured 3.2%) needs a 4% margin
+    for name, storage, ff, m in (("f16+f32last", torch.float16, True, band),
+                                 ("bf16+f32last", torch.bfloat16, True, 0.04)):
+        p = S.make_params(k=k, sweeps=T, frac=f, storage=storage, final_f32=ff, band=m)
         keep, rep = S.sfg_sparsify(g.n, u, v, w, x0, p)
         got = keep.cpu().numpy()
         print(name, "band", rep[0]["band"], "doublings", rep[0]["band_rounds"], "cone rows", rep[0]["cone_rows"],
