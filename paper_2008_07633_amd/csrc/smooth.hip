@@ -18,7 +18,9 @@
 //   - the first sweep reads the raw FP64 block and subtracts the column
 //     means on the fly (centring costs no extra pass);
 //   - workgroups are remapped so every XCD sweeps one contiguous row range
-//     and neighbour rows tend to hit its own L2.
+//     and neighbour rows tend to hit its own L2;
+//   - in reduced precision, rows longer than 256 entries (hubs of power-law
+//     graphs) are taken out and swept by a whole workgroup each.
 #include <cstdlib>
 
 #include "common.hpp"
@@ -150,17 +152,9 @@ __device__ __forceinline__ void load_row(const TIN *p, const double *mo, TA (&ou
     }
 }
 
-template <bool NT, typename T>
-__device__ __forceinline__ T stream_load(const T *p) {
-    if constexpr (NT)
-        return __builtin_nontemporal_load(p);
-    else
-        return *p;
-}
-
-template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, int U, bool CENTER, bool NT>
+template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, int U, bool CENTER>
 __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, int32_t lpr_log2, int32_t k,
-                                               const int32_t *__restrict__ rows,
+                                               int32_t max_len, const int32_t *__restrict__ rows,
                                                const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col, const TW *__restrict__ val,
                                                const TW *__restrict__ deg, const TIN *__restrict__ x,
@@ -176,10 +170,11 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, in
     double mo[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) mo[i] = CENTER ? mean[off + i] : 0.0;
-    const int32_t j0 = stream_load<NT>(rowptr + row), j1 = stream_load<NT>(rowptr + row + 1);
+    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    if (j1 - j0 > max_len) return;      // a long row: k_sweep_long handles it
     TA self[VPL];
     load_row<TIN, TX, TA, VPL, CENTER>(x + row * k + off, mo, self);
-    const TA d = cvt<TA>(stream_load<NT>(deg + row));
+    const TA d = cvt<TA>(deg[row]);
     TA acc[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
@@ -189,8 +184,8 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, in
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             const int32_t jj = (j + i < j1) ? j + i : j1 - 1;
-            cj[i] = stream_load<NT>(col + jj);
-            wj[i] = cvt<TA>(stream_load<NT>(val + jj));
+            cj[i] = col[jj];
+            wj[i] = cvt<TA>(val[jj]);
         }
         TA xv[U][VPL];
 #pragma unroll
@@ -214,15 +209,89 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, in
     *reinterpret_cast<Vec<TO, VPL> *>(y + row * k + off) = out;
 }
 
+// Rows longer than max_len (hubs of power-law graphs), reduced precision
+// only: one workgroup per row.  Its 256/lpr lane groups take interleaved
+// entries of the row, then their partial sums are combined in LDS by a
+// fixed-shape tree, so the result is deterministic (the order differs from
+// the sequential one, which FP64 keeps).
+template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, bool CENTER>
+__global__ __launch_bounds__(256) void k_sweep_long(int32_t lpr, int32_t k, const int32_t *__restrict__ long_rows,
+                                                    const int32_t *__restrict__ long_cnt,
+                                                    const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const TW *__restrict__ val,
+                                                    const TW *__restrict__ deg, const TIN *__restrict__ x,
+                                                    const double *__restrict__ mean, TO *__restrict__ y, TA keep,
+                                                    TA omega) {
+    __shared__ TA part[256 * VPL];
+    const int t = threadIdx.x;
+    const int ngroups = 256 / lpr;
+    const int g = t / lpr, l = t % lpr;
+    const int off = l * VPL;
+    const bool active = g < ngroups;
+    double mo[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) mo[i] = (CENTER && active) ? mean[off + i] : 0.0;
+    const int32_t cnt = *long_cnt;
+    for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const int64_t row = long_rows[r];
+        const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+        TA acc[VPL];
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
+        if (active) {
+            for (int32_t j = j0 + g; j < j1; j += ngroups) {
+                const int64_t c = col[j];
+                const TA wv = cvt<TA>(val[j]);
+                TA xv[VPL];
+                load_row<TIN, TX, TA, VPL, CENTER>(x + c * k + off, mo, xv);
+#pragma unroll
+                for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], wv, xv[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) part[t * VPL + i] = acc[i];
+        __syncthreads();
+        for (int st = 1; st < ngroups; st <<= 1) {
+            if (active && (g % (2 * st)) == 0 && g + st < ngroups) {
+#pragma unroll
+                for (int i = 0; i < VPL; ++i) part[t * VPL + i] += part[(t + st * lpr) * VPL + i];
+            }
+            __syncthreads();
+        }
+        if (g == 0) {
+            TA self[VPL];
+            load_row<TIN, TX, TA, VPL, CENTER>(x + row * k + off, mo, self);
+            const TA d = cvt<TA>(deg[row]);
+            Vec<TO, VPL> out;
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) {
+                const TA a = keep * self[i];
+                const TA q = part[l * VPL + i] / d;
+                const TA bo = omega * q;
+                out.v[i] = cvt<TO>(a + bo);
+            }
+            *reinterpret_cast<Vec<TO, VPL> *>(y + row * k + off) = out;
+        }
+        __syncthreads();
+    }
+}
+
+// Rows handled by k_sweep_long (device list and count), and the length above
+// which k_sweep skips a row.  Default: none, every row in k_sweep.
+struct LongRows {
+    const int32_t *rows = nullptr;
+    const int32_t *count = nullptr;
+    int32_t max_len = 0x7fffffff;
+};
+
 int ilog2_exact(int x) {
     for (int r = 0; r < 31; ++r)
         if ((1 << r) == x) return r;
     return -1;
 }
 
-// Tuning knobs (environment, read once): SFG_SWEEP_U = neighbour unroll
-// (2, 4 or 8; default 2 for FP64 rows averaging <= 3 entries, else 4) and
-// SFG_SWEEP_NT = 1 to stream the CSR arrays with nontemporal loads.
+// Tuning knob (environment, read once): SFG_SWEEP_U = neighbour unroll (2, 4
+// or 8; default 2 for FP64 rows averaging <= 3 entries, else 4).
 int env_int(const char *name, int dflt) {
     const char *e = getenv(name);
     return e ? atoi(e) : dflt;
@@ -230,34 +299,35 @@ int env_int(const char *name, int dflt) {
 
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, int U, bool CENTER>
 void launch_sweep_u(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
-                    const int32_t *rows, int64_t nrows, hipStream_t s) {
-    static const bool nt = env_int("SFG_SWEEP_NT", 0) != 0;
+                    const int32_t *rows, int64_t nrows, const LongRows &lr, hipStream_t s) {
     const int lpr = k / VPL;
     const int64_t nthreads = nrows * (int64_t)lpr;
     if (nthreads == 0) return;
-    const dim3 g(grid_for(nthreads, 256)), b(256);
-    if (nt)
-        hipLaunchKernelGGL((k_sweep<TIN, TX, TO, TW, TA, VPL, U, CENTER, true>), g, b, 0, s, nthreads, lpr,
-                           ilog2_exact(lpr), k, rows, H->rowptr, H->col, (const TW *)H->val, (const TW *)H->deg, x, mean,
-                           y, (TA)(1.0 - omega), (TA)omega);
-    else
-        hipLaunchKernelGGL((k_sweep<TIN, TX, TO, TW, TA, VPL, U, CENTER, false>), g, b, 0, s, nthreads, lpr,
-                           ilog2_exact(lpr), k, rows, H->rowptr, H->col, (const TW *)H->val, (const TW *)H->deg, x, mean,
-                           y, (TA)(1.0 - omega), (TA)omega);
+    hipLaunchKernelGGL((k_sweep<TIN, TX, TO, TW, TA, VPL, U, CENTER>), dim3(grid_for(nthreads, 256)), dim3(256), 0, s,
+                       nthreads, lpr, ilog2_exact(lpr), k, lr.max_len, rows, H->rowptr, H->col, (const TW *)H->val,
+                       (const TW *)H->deg, x, mean, y, (TA)(1.0 - omega), (TA)omega);
     SFG_LAUNCH_CHECK();
+    if constexpr (sizeof(TA) == 4) {
+        if (lr.rows) {
+            hipLaunchKernelGGL((k_sweep_long<TIN, TX, TO, TW, TA, VPL, CENTER>), dim3(1024), dim3(256), 0, s, lpr, k,
+                               lr.rows, lr.count, H->rowptr, H->col, (const TW *)H->val, (const TW *)H->deg, x, mean,
+                               y, (TA)(1.0 - omega), (TA)omega);
+            SFG_LAUNCH_CHECK();
+        }
+    }
 }
 
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, bool CENTER>
 void launch_sweep_v(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
-                    const int32_t *rows, int64_t nrows, hipStream_t s) {
+                    const int32_t *rows, int64_t nrows, const LongRows &lr, hipStream_t s) {
     static const int forced = env_int("SFG_SWEEP_U", 0);
     const int u = forced ? forced : ((sizeof(TX) == 8 && H->nnz <= 3 * H->n) ? 2 : 4);
     if (u <= 2)
-        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 2, CENTER>(H, k, x, mean, y, omega, rows, nrows, s);
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 2, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s);
     else if (u <= 4)
-        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 4, CENTER>(H, k, x, mean, y, omega, rows, nrows, s);
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 4, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s);
     else
-        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 8, CENTER>(H, k, x, mean, y, omega, rows, nrows, s);
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 8, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s);
 }
 
 // Columns per lane: the widest run that divides k, of at most 32 bytes for
@@ -280,18 +350,18 @@ int pick_vpl(int32_t k) {
 
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, bool CENTER>
 void launch_sweep(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
-                  hipStream_t s, const int32_t *rows = nullptr, int64_t nrows = -1) {
+                  hipStream_t s, const int32_t *rows = nullptr, int64_t nrows = -1, const LongRows &lr = LongRows()) {
     if (nrows < 0) nrows = H->n;
     const int vpl = pick_vpl<TX>(k);
     constexpr int maxv = 64 / (int)sizeof(TX);
     switch (vpl) {
-        case 1: launch_sweep_v<TIN, TX, TO, TW, TA, 1, CENTER>(H, k, x, mean, y, omega, rows, nrows, s); return;
-        case 2: launch_sweep_v<TIN, TX, TO, TW, TA, 2, CENTER>(H, k, x, mean, y, omega, rows, nrows, s); return;
-        case 4: launch_sweep_v<TIN, TX, TO, TW, TA, 4, CENTER>(H, k, x, mean, y, omega, rows, nrows, s); return;
-        case 8: launch_sweep_v<TIN, TX, TO, TW, TA, 8, CENTER>(H, k, x, mean, y, omega, rows, nrows, s); return;
+        case 1: launch_sweep_v<TIN, TX, TO, TW, TA, 1, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s); return;
+        case 2: launch_sweep_v<TIN, TX, TO, TW, TA, 2, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s); return;
+        case 4: launch_sweep_v<TIN, TX, TO, TW, TA, 4, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s); return;
+        case 8: launch_sweep_v<TIN, TX, TO, TW, TA, 8, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s); return;
         case 16:
             if constexpr (maxv >= 16) {
-                launch_sweep_v<TIN, TX, TO, TW, TA, 16, CENTER>(H, k, x, mean, y, omega, rows, nrows, s);
+                launch_sweep_v<TIN, TX, TO, TW, TA, 16, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s);
                 return;
             }
             break;
@@ -304,7 +374,21 @@ struct SmoothPlan {
     DD *partial;
     double *mean;
     void *buf0, *buf1;
+    int32_t *lflag, *lpos, *lrows, *lscan;
 };
+
+constexpr int32_t kLongRow = 256;   // reduced precision: rows above this go to k_sweep_long
+
+__global__ void k_long_flag(int64_t n, const int32_t *__restrict__ rowptr, int32_t len, int32_t *flag) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) flag[p] = (rowptr[p + 1] - rowptr[p] > len) ? 1 : 0;
+}
+
+__global__ void k_long_scatter(int64_t n, const int32_t *__restrict__ flag, const int32_t *__restrict__ pos,
+                               int32_t *rows) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n && flag[p]) rows[pos[p]] = (int32_t)p;
+}
 
 int colsum_blocks(int64_t n) {
     int64_t nb = (n + kSumThreads - 1) / kSumThreads;
@@ -318,6 +402,10 @@ SmoothPlan plan_smooth(Carver &c, int64_t n, int32_t k, sfg_dtype storage) {
     p.mean = c.take<double>(k);
     p.buf0 = c.take<char>((size_t)n * k * dtype_size(storage));
     p.buf1 = c.take<char>((size_t)n * k * dtype_size(storage));
+    p.lflag = c.take<int32_t>(n + 1);
+    p.lpos = c.take<int32_t>(n + 1);
+    p.lrows = c.take<int32_t>(n + 1);
+    p.lscan = c.take<int32_t>(scan_scratch_ints(n + 1));
     return p;
 }
 
@@ -349,22 +437,37 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
         return;
     }
     TX *b0 = (TX *)p.buf0, *b1 = (TX *)p.buf1;
+    // reduced precision: list the long rows once for all sweeps (device-side count)
+    LongRows lr;
+    if constexpr (sizeof(TA) == 4) {
+        hipLaunchKernelGGL(k_long_flag, dim3(grid_for(n, 256)), dim3(256), 0, s, n, H->rowptr, kLongRow, p.lflag);
+        SFG_LAUNCH_CHECK();
+        exclusive_scan_i32(p.lflag, p.lpos, n, p.lscan, s);
+        hipLaunchKernelGGL(k_long_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, n, p.lflag, p.lpos, p.lrows);
+        SFG_LAUNCH_CHECK();
+        lr.rows = p.lrows;
+        lr.count = p.lpos + n;
+        lr.max_len = kLongRow;
+    }
     // a3: sweeps; the first centres on the fly, the last writes xout
     for (int32_t t = 0; t < sweeps; ++t) {
         const bool last = (t == sweeps - 1);
         TX *dst = (t % 2 == 0) ? b0 : b1;
         if (t == 0) {
             if (last && final_f32)
-                launch_sweep<double, TX, float, TW, TA, true>(H, k, x0, p.mean, (float *)xout, omega, s);
+                launch_sweep<double, TX, float, TW, TA, true>(H, k, x0, p.mean, (float *)xout, omega, s, nullptr, -1,
+                                                              lr);
             else
-                launch_sweep<double, TX, TX, TW, TA, true>(H, k, x0, p.mean, last ? (TX *)xout : dst, omega, s);
+                launch_sweep<double, TX, TX, TW, TA, true>(H, k, x0, p.mean, last ? (TX *)xout : dst, omega, s,
+                                                           nullptr, -1, lr);
             continue;
         }
         const TX *src = (t % 2 == 0) ? b1 : b0;
         if (last && final_f32)
-            launch_sweep<TX, TX, float, TW, TA, false>(H, k, src, nullptr, (float *)xout, omega, s);
+            launch_sweep<TX, TX, float, TW, TA, false>(H, k, src, nullptr, (float *)xout, omega, s, nullptr, -1, lr);
         else
-            launch_sweep<TX, TX, TX, TW, TA, false>(H, k, src, nullptr, last ? (TX *)xout : dst, omega, s);
+            launch_sweep<TX, TX, TX, TW, TA, false>(H, k, src, nullptr, last ? (TX *)xout : dst, omega, s, nullptr,
+                                                    -1, lr);
     }
 }
 

@@ -293,3 +293,27 @@ def test_spanning_tree_ties_and_forests(S, orc, case):
     if case == "chunglu":   # FP32 weights give the same forest
         t32, c32 = S.sfg_spanning_tree(g.n, dev(g.u), dev(g.v), dev(g.w32))
         assert c32 == comps and np.array_equal(host(t32), ref)
+
+
+@pytest.mark.parametrize("storage,tol", [(torch.float32, 2e-5), (torch.float16, 6e-3)])
+def test_smooth_hub_rows(S, orc, storage, tol):
+    # power-law graph plus a star centre of degree 3000: rows longer than 256
+    # entries are swept by a whole workgroup in reduced precision
+    g = W.chung_lu(20000, 120000, 2.2, seed=94)
+    hub_v = np.arange(1, 3001, dtype=np.int32)
+    a = np.concatenate([g.u, np.zeros(3000, np.int32)])
+    b = np.concatenate([g.v, hub_v])
+    key = np.unique(a.astype(np.int64) * g.n + b)
+    u, v = (key // g.n).astype(np.int32), (key % g.n).astype(np.int32)
+    w = np.random.default_rng(3).uniform(1, 10, u.shape[0])
+    deg = np.bincount(u, minlength=g.n) + np.bincount(v, minlength=g.n)
+    assert deg.max() > 3000 and (deg > 256).sum() > 5
+    X0 = W.random_block(g.n, 16, 12)
+    ref = orc.smooth(orc.laplacian_csr(g.n, u, v, w), orc.center(X0)[0], 20, 0.5)
+    H = S.sfg_laplacian_csr(g.n, dev(u), dev(v), dev(w.astype(np.float32)))
+    X = S.sfg_smooth(H, dev(X0), 20, 0.5, storage=storage, final_f32=True)
+    err = np.max(np.abs(host(X.float()).astype(np.float64) - ref)) / np.max(np.abs(X0))
+    assert err < tol, err
+    # deterministic
+    X2 = S.sfg_smooth(H, dev(X0), 20, 0.5, storage=storage, final_f32=True)
+    assert torch.equal(X, X2)
