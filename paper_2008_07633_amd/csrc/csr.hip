@@ -7,73 +7,112 @@
 // sorted by (u, v), ascending column order inside a row is ascending edge id
 // order, and the degree is summed in that order in FP64.
 //
-//  1. count included edges per row (lower and upper parts) and all edges per
-//     u (to find each row's slice of the edge list)
-//  2. two exclusive scans: rowptr and the edge-list start of each row
-//  3. drop each lower entry's edge id into its row (unordered, atomic slot)
-//  4. order each row's lower part by edge id: rank = number of smaller ids
-//     in the segment (a thread per short row, a wavefront per long one)
-//  5. one thread per row writes col/val/eid and the degree, in column order
+//  1. the edge-list slice of every row by binary search over u (no atomics,
+//     so hub rows cost nothing extra); with a mask, a scan of it
+//  2. lower-part counts (integer atomics on v) and one scan: rowptr
+//  3. upper entries: one thread per edge writes its slot directly
+//  4. lower entries: each edge id is dropped into its row (atomic slot), then
+//     every row's lower part is ordered by edge id -- rank = number of smaller
+//     ids in the segment -- by a thread per short row or a workgroup per long
+//     row (segment staged in LDS), which writes col/val/eid
+//  5. one thread per row sums its weights in column order, in FP64
 #include "common.hpp"
 
 namespace sfg {
 
 namespace {
 
+constexpr int kShortSeg = 32;       // lower parts up to this length: one thread
+constexpr int kLdsSeg = 8192;       // longer ones are staged in LDS up to this length
+
 struct CsrPlan {
-    int32_t *cnt_lo, *cnt_hi, *cnt_all, *tmp, *estart, *fill, *scan, *long_cnt;
+    int32_t *estart, *inc, *incpos, *cnt_lo, *tot, *fill, *tmp, *long_rows, *long_cnt, *scan;
 };
 
 CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
-    (void)m;
     CsrPlan p;
-    p.cnt_lo = c.take<int32_t>(n + 1);
-    p.cnt_hi = c.take<int32_t>(n + 1);
-    p.cnt_all = c.take<int32_t>(n + 1);
-    p.tmp = c.take<int32_t>(n + 1);
     p.estart = c.take<int32_t>(n + 1);
+    p.inc = c.take<int32_t>(m + 1);
+    p.incpos = c.take<int32_t>(m + 1);
+    p.cnt_lo = c.take<int32_t>(n + 1);
+    p.tot = c.take<int32_t>(n + 1);
     p.fill = c.take<int32_t>(n + 1);
-    p.scan = c.take<int32_t>(scan_scratch_ints(n + 1));
+    p.tmp = c.take<int32_t>(2 * m + 1);
+    p.long_rows = c.take<int32_t>(n + 1);
     p.long_cnt = c.take<int32_t>(1);
+    p.scan = c.take<int32_t>(scan_scratch_ints((n > m ? n : m) + 1));
     return p;
 }
 
-__global__ void k_count(int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
-                        const uint8_t *__restrict__ mask, int32_t *cnt_lo, int32_t *cnt_hi,
-                        int32_t *cnt_all) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const int32_t a = u[e], b = v[e];
-    atomicAdd(&cnt_all[a], 1);
-    if (mask && mask[e] == 0) return;
-    atomicAdd(&cnt_hi[a], 1);
-    atomicAdd(&cnt_lo[b], 1);
+// estart[p] = first edge with u >= p (p = 0..n)
+__global__ void k_estart(int64_t n, int64_t m, const int32_t *__restrict__ u, int32_t *estart) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > n) return;
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (u[mid] < p) lo = mid + 1;
+        else hi = mid;
+    }
+    estart[p] = (int32_t)lo;
 }
 
-__global__ void k_row_total(int64_t n, const int32_t *cnt_lo, const int32_t *cnt_hi, int32_t *tot) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) tot[p] = cnt_lo[p] + cnt_hi[p];
+__global__ void k_inc(int64_t m, const uint8_t *__restrict__ mask, int32_t *inc) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) inc[e] = mask[e] != 0 ? 1 : 0;
+}
+
+__global__ void k_count_lo(int64_t m, const int32_t *__restrict__ v, const uint8_t *__restrict__ mask,
+                           int32_t *cnt_lo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    if (mask && mask[e] == 0) return;
+    atomicAdd(&cnt_lo[v[e]], 1);
+}
+
+__global__ void k_row_total(int64_t n, const int32_t *__restrict__ estart, const int32_t *__restrict__ incpos,
+                            const int32_t *__restrict__ cnt_lo, int32_t *tot) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t a = estart[p], b = estart[p + 1];
+    const int32_t hi = incpos ? incpos[b] - incpos[a] : b - a;
+    tot[p] = cnt_lo[p] + hi;
+}
+
+template <typename TW>
+__global__ void k_fill_upper(int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                             const TW *__restrict__ w, const uint8_t *__restrict__ mask,
+                             const int32_t *__restrict__ incpos, const int32_t *__restrict__ estart,
+                             const int32_t *__restrict__ rowptr, const int32_t *__restrict__ cnt_lo, int32_t *col,
+                             TW *val, int32_t *eid) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    if (mask && mask[e] == 0) return;
+    const int32_t p = u[e];
+    const int32_t k = incpos ? incpos[e] - incpos[estart[p]] : (int32_t)(e - estart[p]);
+    const int32_t j = rowptr[p] + cnt_lo[p] + k;
+    col[j] = v[e];
+    val[j] = w[e];
+    eid[j] = (int32_t)e;
 }
 
 __global__ void k_place_lower(int64_t m, const int32_t *__restrict__ v, const uint8_t *__restrict__ mask,
-                              const int32_t *__restrict__ rowptr, int32_t *fill, int32_t *eid) {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                              const int32_t *__restrict__ rowptr, int32_t *fill, int32_t *tmp) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     if (mask && mask[e] == 0) return;
     const int32_t b = v[e];
     const int32_t slot = atomicAdd(&fill[b], 1);
-    eid[rowptr[b] + slot] = (int32_t)e;
+    tmp[rowptr[b] + slot] = (int32_t)e;
 }
 
-// Order the lower part of each row by edge id.  Reads the unordered ids from
-// `eid`, writes them ordered into `col` (used as scratch here).  Ids in a
-// segment are distinct, so rank = count of smaller ids.  Short segments (the
-// common case) take one thread each; longer ones are queued for a wavefront.
-constexpr int kShortSeg = 32;
-
+// Ids in a segment are distinct, so the rank of an id is the number of
+// smaller ids; the entry goes to base + rank.
+template <typename TW>
 __global__ __launch_bounds__(256) void k_rank_short(int64_t n, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ cnt_lo,
-                                                    const int32_t *__restrict__ eid, int32_t *col,
+                                                    const int32_t *__restrict__ tmp, const int32_t *__restrict__ u,
+                                                    const TW *__restrict__ w, int32_t *col, TW *val, int32_t *eid,
                                                     int32_t *long_rows, int32_t *long_cnt) {
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= n) return;
@@ -84,64 +123,76 @@ __global__ __launch_bounds__(256) void k_rank_short(int64_t n, const int32_t *__
     }
     const int32_t base = rowptr[row];
     for (int32_t i = 0; i < len; ++i) {
-        const int32_t mine = eid[base + i];
+        const int32_t mine = tmp[base + i];
         int32_t rank = 0;
-        for (int32_t j = 0; j < len; ++j) rank += (eid[base + j] < mine) ? 1 : 0;
-        col[base + rank] = mine;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ cnt_lo,
-                                                   const int32_t *__restrict__ eid, int32_t *col,
-                                                   const int32_t *__restrict__ long_rows,
-                                                   const int32_t *__restrict__ long_cnt) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t nwaves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    const int32_t cnt = *long_cnt;
-    for (int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave; r < cnt; r += nwaves) {
-        const int32_t row = long_rows[r];
-        const int32_t len = cnt_lo[row];
-        const int32_t base = rowptr[row];
-        for (int32_t i = lane; i < len; i += kWave) {
-            const int32_t mine = eid[base + i];
-            int32_t rank = 0;
-            for (int32_t j = 0; j < len; ++j) rank += (eid[base + j] < mine) ? 1 : 0;
-            col[base + rank] = mine;
-        }
+        for (int32_t j = 0; j < len; ++j) rank += (tmp[base + j] < mine) ? 1 : 0;
+        col[base + rank] = u[mine];
+        val[base + rank] = w[mine];
+        eid[base + rank] = mine;
     }
 }
 
 template <typename TW>
-__global__ void k_fill_rows(int64_t n, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
-                            const TW *__restrict__ w, const uint8_t *__restrict__ mask,
-                            const int32_t *__restrict__ rowptr, const int32_t *__restrict__ cnt_lo,
-                            const int32_t *__restrict__ estart, int32_t *col, TW *val, int32_t *eid,
-                            TW *deg) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ cnt_lo,
+                                                   const int32_t *__restrict__ tmp, const int32_t *__restrict__ u,
+                                                   const TW *__restrict__ w, int32_t *col, TW *val, int32_t *eid,
+                                                   const int32_t *__restrict__ long_rows,
+                                                   const int32_t *__restrict__ long_cnt) {
+    __shared__ int32_t seg[kLdsSeg];
+    const int32_t cnt = *long_cnt;
+    for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const int32_t row = long_rows[r];
+        const int32_t len = cnt_lo[row];
+        const int32_t base = rowptr[row];
+        const bool in_lds = len <= kLdsSeg;
+        if (in_lds)
+            for (int32_t i = threadIdx.x; i < len; i += blockDim.x) seg[i] = tmp[base + i];
+        __syncthreads();
+        for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
+            const int32_t mine = tmp[base + i];
+            int32_t rank = 0;
+            if (in_lds)
+                for (int32_t j = 0; j < len; ++j) rank += (seg[j] < mine) ? 1 : 0;
+            else
+                for (int32_t j = 0; j < len; ++j) rank += (tmp[base + j] < mine) ? 1 : 0;
+            col[base + rank] = u[mine];
+            val[base + rank] = w[mine];
+            eid[base + rank] = mine;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename TW>
+__global__ void k_degree(int64_t n, const int32_t *__restrict__ rowptr, const TW *__restrict__ val, TW *deg) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    int32_t j = rowptr[p];
     double d = 0.0;
-    const int32_t nlo = cnt_lo[p];
-    for (int32_t t = 0; t < nlo; ++t, ++j) {
-        const int32_t e = col[j];          // ordered lower ids left by the rank kernels
-        eid[j] = e;
-        col[j] = u[e];
-        const TW we = w[e];
-        val[j] = we;
-        d = d + (double)we;
-    }
-    const int32_t e1 = estart[p + 1];
-    for (int32_t e = estart[p]; e < e1; ++e) {
-        if (mask && mask[e] == 0) continue;
-        eid[j] = e;
-        col[j] = v[e];
-        const TW we = w[e];
-        val[j] = we;
-        d = d + (double)we;
-        ++j;
-    }
+    for (int32_t j = rowptr[p]; j < rowptr[p + 1]; ++j) d = d + (double)val[j];
     deg[p] = (TW)d;
+}
+
+template <typename TW>
+void fill_entries(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const TW *w, const uint8_t *mask,
+                  const CsrPlan &p, const int32_t *rowptr, int32_t *col, TW *val, int32_t *eid, TW *deg,
+                  hipStream_t s) {
+    const dim3 gn(grid_for(n, 256)), gm(grid_for(m, 256)), b(256);
+    if (m > 0) {
+        hipLaunchKernelGGL(k_fill_upper<TW>, gm, b, 0, s, m, u, v, w, mask, mask ? p.incpos : nullptr, p.estart,
+                           rowptr, p.cnt_lo, col, val, eid);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_place_lower, gm, b, 0, s, m, v, mask, rowptr, p.fill, p.tmp);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_rank_short<TW>, gn, b, 0, s, n, rowptr, p.cnt_lo, p.tmp, u, w, col, val, eid,
+                           p.long_rows, p.long_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_rank_long<TW>, dim3(512), b, 0, s, rowptr, p.cnt_lo, p.tmp, u, w, col, val, eid,
+                           p.long_rows, p.long_cnt);
+        SFG_LAUNCH_CHECK();
+    }
+    hipLaunchKernelGGL(k_degree<TW>, gn, b, 0, s, n, rowptr, val, deg);
+    SFG_LAUNCH_CHECK();
 }
 
 }  // namespace
@@ -153,8 +204,8 @@ size_t csr_workspace_bytes(int64_t n, int64_t m) {
 }
 
 void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
-               const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val, int32_t *eid, void *deg,
-               void *ws, size_t ws_bytes, hipStream_t s) {
+               const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val, int32_t *eid, void *deg, void *ws,
+               size_t ws_bytes, hipStream_t s) {
     SFG_REQUIRE(n >= 1 && m >= 0, SFG_EINVAL, "laplacian_csr: need n >= 1 and m >= 0");
     SFG_REQUIRE(2 * m < (int64_t(1) << 31), SFG_EUNSUPPORTED, "laplacian_csr: 2*m must be < 2^31");
     SFG_REQUIRE(n < (int64_t(1) << 31) - 1, SFG_EUNSUPPORTED, "laplacian_csr: n must be < 2^31-1");
@@ -164,40 +215,29 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
                 "laplacian_csr: null pointer");
     Carver c(ws);
     CsrPlan p = plan_csr(c, n, m);
+    const dim3 gn(grid_for(n, 256)), gm(grid_for(m, 256)), b(256);
     fill_i32(p.cnt_lo, n + 1, 0, s);
-    fill_i32(p.cnt_hi, n + 1, 0, s);
-    fill_i32(p.cnt_all, n + 1, 0, s);
     fill_i32(p.fill, n + 1, 0, s);
-    if (m > 0) {
-        hipLaunchKernelGGL(k_count, dim3(grid_for(m, 256)), dim3(256), 0, s, m, u, v, mask, p.cnt_lo, p.cnt_hi,
-                           p.cnt_all);
-        SFG_LAUNCH_CHECK();
-    }
-    hipLaunchKernelGGL(k_row_total, dim3(grid_for(n, 256)), dim3(256), 0, s, n, p.cnt_lo, p.cnt_hi, p.tmp);
+    fill_i32(p.long_cnt, 1, 0, s);
+    hipLaunchKernelGGL(k_estart, dim3(grid_for(n + 1, 256)), b, 0, s, n, m, u, p.estart);
     SFG_LAUNCH_CHECK();
-    exclusive_scan_i32(p.tmp, rowptr, n, p.scan, s);
-    exclusive_scan_i32(p.cnt_all, p.estart, n, p.scan, s);
     if (m > 0) {
-        hipLaunchKernelGGL(k_place_lower, dim3(grid_for(m, 256)), dim3(256), 0, s, m, v, mask, rowptr, p.fill,
-                           eid);
-        SFG_LAUNCH_CHECK();
-        fill_i32(p.long_cnt, 1, 0, s);
-        // p.tmp (the row totals) is free once rowptr is scanned: it holds the long-row queue
-        hipLaunchKernelGGL(k_rank_short, dim3(grid_for(n, 256)), dim3(256), 0, s, n, rowptr, p.cnt_lo, eid, col,
-                           p.tmp, p.long_cnt);
-        SFG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_rank_long, dim3(256), dim3(256), 0, s, rowptr, p.cnt_lo, eid, col, p.tmp, p.long_cnt);
+        if (mask) {
+            hipLaunchKernelGGL(k_inc, gm, b, 0, s, m, mask, p.inc);
+            SFG_LAUNCH_CHECK();
+            exclusive_scan_i32(p.inc, p.incpos, m, p.scan, s);
+        }
+        hipLaunchKernelGGL(k_count_lo, gm, b, 0, s, m, v, mask, p.cnt_lo);
         SFG_LAUNCH_CHECK();
     }
+    hipLaunchKernelGGL(k_row_total, gn, b, 0, s, n, p.estart, (mask && m > 0) ? p.incpos : nullptr, p.cnt_lo, p.tot);
+    SFG_LAUNCH_CHECK();
+    exclusive_scan_i32(p.tot, rowptr, n, p.scan, s);
     if (wt == SFG_F64)
-        hipLaunchKernelGGL(k_fill_rows<double>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, u, v,
-                           (const double *)w, mask, rowptr, p.cnt_lo, p.estart, col, (double *)val, eid,
-                           (double *)deg);
+        fill_entries<double>(n, m, u, v, (const double *)w, mask, p, rowptr, col, (double *)val, eid, (double *)deg,
+                             s);
     else
-        hipLaunchKernelGGL(k_fill_rows<float>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, u, v,
-                           (const float *)w, mask, rowptr, p.cnt_lo, p.estart, col, (float *)val, eid,
-                           (float *)deg);
-    SFG_LAUNCH_CHECK();
+        fill_entries<float>(n, m, u, v, (const float *)w, mask, p, rowptr, col, (float *)val, eid, (float *)deg, s);
 }
 
 }  // namespace sfg

@@ -46,10 +46,12 @@ __global__ void k_mst_best_w(int64_t m, const int32_t *__restrict__ u, const int
     if (allowed && !allowed[e]) return;
     const int32_t a = comp[u[e]], b = comp[v[e]];
     if (a == b) return;
+    if (*live == 0) *live = 1;
     const uint64_t k = wkey(w[e]);
-    atomicMax((unsigned long long *)&best_w[a], (unsigned long long)k);
-    atomicMax((unsigned long long *)&best_w[b], (unsigned long long)k);
-    *live = 1;
+    // read first: on hub components most edges lose, and skipping their
+    // atomics removes the contention (the maximum is still exact)
+    if (k > best_w[a]) atomicMax((unsigned long long *)&best_w[a], (unsigned long long)k);
+    if (k > best_w[b]) atomicMax((unsigned long long *)&best_w[b], (unsigned long long)k);
 }
 
 template <typename TW>
@@ -63,8 +65,8 @@ __global__ void k_mst_best_e(int64_t m, const int32_t *__restrict__ u, const int
     const int32_t a = comp[u[e]], b = comp[v[e]];
     if (a == b) return;
     const uint64_t k = wkey(w[e]);
-    if (k == best_w[a]) atomicMin(&best_e[a], (int32_t)e);
-    if (k == best_w[b]) atomicMin(&best_e[b], (int32_t)e);
+    if (k == best_w[a] && (int32_t)e < best_e[a]) atomicMin(&best_e[a], (int32_t)e);
+    if (k == best_w[b] && (int32_t)e < best_e[b]) atomicMin(&best_e[b], (int32_t)e);
 }
 
 // Roots hook across their best edge and mark it as a tree edge.

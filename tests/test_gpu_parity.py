@@ -317,3 +317,21 @@ def test_smooth_hub_rows(S, orc, storage, tol):
     # deterministic
     X2 = S.sfg_smooth(H, dev(X0), 20, 0.5, storage=storage, final_f32=True)
     assert torch.equal(X, X2)
+
+
+@pytest.mark.parametrize("n,center", [(6000, 5000), (10000, 9999), (3000, 0)])
+def test_csr_long_lower_parts(S, orc, n, center):
+    # a star whose centre has a lower part of up to n-1 entries (LDS and global rank paths)
+    others = np.array([p for p in range(n) if p != center], dtype=np.int64)
+    a = np.minimum(others, center)
+    b = np.maximum(others, center)
+    extra = np.arange(0, n - 1, 7)
+    key = np.unique(np.concatenate([a * n + b, extra * n + extra + 1]))
+    u, v = (key // n).astype(np.int32), (key % n).astype(np.int32)
+    w = np.random.default_rng(n).uniform(0.5, 2.0, u.shape[0])
+    ref = orc.laplacian_csr(n, u, v, w)
+    H = S.sfg_laplacian_csr(n, dev(u), dev(v), dev(w))
+    assert np.array_equal(host(H.col)[:H.nnz], ref.col)
+    assert np.array_equal(host(H.eid)[:H.nnz], ref.eid)
+    assert np.array_equal(host(H.val)[:H.nnz], ref.val)
+    assert np.array_equal(host(H.deg), ref.deg)
