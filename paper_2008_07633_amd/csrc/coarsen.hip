@@ -46,15 +46,27 @@ namespace {
 
 // ------------------------------------------------------------------ aggregation
 
+// key order of a neighbour entry: larger affinity, then larger weight, then smaller column
+template <typename TA, typename TW>
+__device__ __forceinline__ bool key_better(TA a, TW w, int32_t c, TA ba, TW bw, int32_t bc) {
+    return a > ba || (a == ba && (w > bw || (w == bw && c < bc)));
+}
+
+constexpr int32_t kPtrLong = 256;   // rows above this length: one workgroup each
+
 template <typename TA, typename TW>
 __global__ void k_pointer(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                           const TW *__restrict__ val, const int32_t *__restrict__ eid, const TA *__restrict__ aff,
-                          int32_t *ptr) {
+                          int32_t *ptr, int32_t *long_rows, int32_t *long_cnt) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int32_t j0 = rowptr[p], j1 = rowptr[p + 1];
     if (j0 == j1) {
         ptr[p] = (int32_t)p;
+        return;
+    }
+    if (j1 - j0 > kPtrLong) {
+        long_rows[atomicAdd(long_cnt, 1)] = (int32_t)p;
         return;
     }
     int32_t best = j0;
@@ -71,6 +83,51 @@ __global__ void k_pointer(int64_t n, const int32_t *__restrict__ rowptr, const i
         }
     }
     ptr[p] = col[best];
+}
+
+template <typename TA, typename TW>
+__global__ __launch_bounds__(256) void k_pointer_long(const int32_t *__restrict__ rowptr,
+                                                      const int32_t *__restrict__ col, const TW *__restrict__ val,
+                                                      const int32_t *__restrict__ eid, const TA *__restrict__ aff,
+                                                      int32_t *ptr, const int32_t *__restrict__ long_rows,
+                                                      const int32_t *__restrict__ long_cnt) {
+    __shared__ TA sa[256];
+    __shared__ TW sw[256];
+    __shared__ int32_t sc[256];
+    const int t = threadIdx.x;
+    const int32_t cnt = *long_cnt;
+    for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const int32_t p = long_rows[r];
+        const int32_t j0 = rowptr[p], j1 = rowptr[p + 1];
+        TA ba = TA(-1);
+        TW bw = TW(0);
+        int32_t bc = 0x7fffffff;
+        for (int32_t j = j0 + t; j < j1; j += 256) {
+            const TA a = aff[eid[j]];
+            const TW w = val[j];
+            const int32_t c = col[j];
+            if (bc == 0x7fffffff || key_better(a, w, c, ba, bw, bc)) {
+                ba = a;
+                bw = w;
+                bc = c;
+            }
+        }
+        sa[t] = ba;
+        sw[t] = bw;
+        sc[t] = bc;
+        __syncthreads();
+        for (int st = 128; st > 0; st >>= 1) {
+            if (t < st && sc[t + st] != 0x7fffffff &&
+                (sc[t] == 0x7fffffff || key_better(sa[t + st], sw[t + st], sc[t + st], sa[t], sw[t], sc[t]))) {
+                sa[t] = sa[t + st];
+                sw[t] = sw[t + st];
+                sc[t] = sc[t + st];
+            }
+            __syncthreads();
+        }
+        if (t == 0) ptr[p] = sc[0];
+        __syncthreads();
+    }
 }
 
 __global__ void k_parent_init(int64_t n, const int32_t *__restrict__ ptr, int32_t *par) {
@@ -167,7 +224,8 @@ __global__ void k_seg_reduce(int64_t mc, int64_t mi, const int32_t *__restrict__
 }
 
 struct CoarsenPlan {
-    int32_t *ptr, *par, *minid, *flag, *rank, *changed, *eflag, *epos, *eids, *sflag, *spos, *sstart, *scan;
+    int32_t *ptr, *par, *minid, *flag, *rank, *changed, *eflag, *epos, *eids, *sflag, *spos, *sstart, *scan,
+        *long_rows, *long_cnt;
     uint64_t *keys;
     void *radix;
 };
@@ -180,6 +238,8 @@ CoarsenPlan plan_coarsen(Carver &c, int64_t n, int64_t m) {
     p.flag = c.take<int32_t>(n + 1);
     p.rank = c.take<int32_t>(n + 1);
     p.changed = c.take<int32_t>(1);
+    p.long_rows = c.take<int32_t>(n + 1);
+    p.long_cnt = c.take<int32_t>(1);
     p.eflag = c.take<int32_t>(m + 1);
     p.epos = c.take<int32_t>(m + 1);
     p.eids = c.take<int32_t>(m + 1);
@@ -229,19 +289,33 @@ void coarsen(const sfg_csr *G, int64_t m, const int32_t *u, const int32_t *v, co
     Carver c(ws);
     CoarsenPlan p = plan_coarsen(c, n, m);
     const dim3 gn(grid_for(n, 256)), gm(grid_for(m, 256)), b(256);
-    // pointers to the highest-key neighbour
-    if (at == SFG_F64 && G->vt == SFG_F64)
+    // pointers to the highest-key neighbour (long rows: one workgroup each)
+    fill_i32(p.long_cnt, 1, 0, s);
+    if (at == SFG_F64 && G->vt == SFG_F64) {
         hipLaunchKernelGGL((k_pointer<double, double>), gn, b, 0, s, n, G->rowptr, G->col, (const double *)G->val,
-                           G->eid, (const double *)aff, p.ptr);
-    else if (at == SFG_F64)
+                           G->eid, (const double *)aff, p.ptr, p.long_rows, p.long_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_pointer_long<double, double>), dim3(512), b, 0, s, G->rowptr, G->col,
+                           (const double *)G->val, G->eid, (const double *)aff, p.ptr, p.long_rows, p.long_cnt);
+    } else if (at == SFG_F64) {
         hipLaunchKernelGGL((k_pointer<double, float>), gn, b, 0, s, n, G->rowptr, G->col, (const float *)G->val,
-                           G->eid, (const double *)aff, p.ptr);
-    else if (G->vt == SFG_F64)
+                           G->eid, (const double *)aff, p.ptr, p.long_rows, p.long_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_pointer_long<double, float>), dim3(512), b, 0, s, G->rowptr, G->col,
+                           (const float *)G->val, G->eid, (const double *)aff, p.ptr, p.long_rows, p.long_cnt);
+    } else if (G->vt == SFG_F64) {
         hipLaunchKernelGGL((k_pointer<float, double>), gn, b, 0, s, n, G->rowptr, G->col, (const double *)G->val,
-                           G->eid, (const float *)aff, p.ptr);
-    else
+                           G->eid, (const float *)aff, p.ptr, p.long_rows, p.long_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_pointer_long<float, double>), dim3(512), b, 0, s, G->rowptr, G->col,
+                           (const double *)G->val, G->eid, (const float *)aff, p.ptr, p.long_rows, p.long_cnt);
+    } else {
         hipLaunchKernelGGL((k_pointer<float, float>), gn, b, 0, s, n, G->rowptr, G->col, (const float *)G->val,
-                           G->eid, (const float *)aff, p.ptr);
+                           G->eid, (const float *)aff, p.ptr, p.long_rows, p.long_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL((k_pointer_long<float, float>), dim3(512), b, 0, s, G->rowptr, G->col,
+                           (const float *)G->val, G->eid, (const float *)aff, p.ptr, p.long_rows, p.long_cnt);
+    }
     SFG_LAUNCH_CHECK();
     // components of the pointer graph
     hipLaunchKernelGGL(k_parent_init, gn, b, 0, s, n, p.ptr, p.par);
