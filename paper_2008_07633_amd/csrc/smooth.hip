@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, in
         TA wj[U];
 #pragma unroll
         for (int i = 0; i < U; ++i) {
-            const int32_t jj = (j + i < j1) ? j + i : j1 - 1;
+            const int32_t jj = (j + i < j1) ? j + i : j1 - 1;     // clamped: a valid, cached entry
             cj[i] = col[jj];
             wj[i] = cvt<TA>(val[jj]);
         }
@@ -291,7 +291,8 @@ int ilog2_exact(int x) {
 }
 
 // Tuning knob (environment, read once): SFG_SWEEP_U = neighbour unroll (2, 4
-// or 8; default 2 for FP64 rows averaging <= 3 entries, else 4).
+// or 8; default 2 for FP64 rows averaging <= 3 entries, else 4: measured
+// best on the power grid's spanning tree).
 int env_int(const char *name, int dflt) {
     const char *e = getenv(name);
     return e ? atoi(e) : dflt;
