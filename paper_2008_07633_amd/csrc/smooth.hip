@@ -19,6 +19,9 @@
 //     means on the fly (centring costs no extra pass);
 //   - workgroups are remapped so every XCD sweeps one contiguous row range
 //     and neighbour rows tend to hit its own L2;
+//   - an FP64 block on a tree-like graph is smoothed 8 columns at a time (all
+//     sweeps of one column part, then the next), so the working set of a part
+//     stays in the memory-side cache;
 //   - in reduced precision, rows longer than 256 entries (hubs of power-law
 //     graphs) are taken out and swept by a whole workgroup each.
 #include <cstdlib>
@@ -153,8 +156,8 @@ __device__ __forceinline__ void load_row(const TIN *p, const double *mo, TA (&ou
 }
 
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, int U, bool CENTER>
-__global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, int32_t lpr_log2, int32_t k,
-                                               int32_t max_len, const int32_t *__restrict__ rows,
+__global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, int32_t lpr_log2, int32_t ldx,
+                                               int32_t ldy, int32_t max_len, const int32_t *__restrict__ rows,
                                                const int32_t *__restrict__ rowptr,
                                                const int32_t *__restrict__ col, const TW *__restrict__ val,
                                                const TW *__restrict__ deg, const TIN *__restrict__ x,
@@ -173,7 +176,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, in
     const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
     if (j1 - j0 > max_len) return;      // a long row: k_sweep_long handles it
     TA self[VPL];
-    load_row<TIN, TX, TA, VPL, CENTER>(x + row * k + off, mo, self);
+    load_row<TIN, TX, TA, VPL, CENTER>(x + row * ldx + off, mo, self);
     const TA d = cvt<TA>(deg[row]);
     TA acc[VPL];
 #pragma unroll
@@ -189,7 +192,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, in
         }
         TA xv[U][VPL];
 #pragma unroll
-        for (int i = 0; i < U; ++i) load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)cj[i] * k + off, mo, xv[i]);
+        for (int i = 0; i < U; ++i) load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)cj[i] * ldx + off, mo, xv[i]);
 #pragma unroll
         for (int i = 0; i < U; ++i) {
             if (j + i < j1) {
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, in
         const TA bo = omega * q;
         out.v[i] = cvt<TO>(a + bo);
     }
-    *reinterpret_cast<Vec<TO, VPL> *>(y + row * k + off) = out;
+    *reinterpret_cast<Vec<TO, VPL> *>(y + row * ldy + off) = out;
 }
 
 // Rows longer than max_len (hubs of power-law graphs), reduced precision
@@ -215,7 +218,8 @@ __global__ __launch_bounds__(256) void k_sweep(int64_t nthreads, int32_t lpr, in
 // fixed-shape tree, so the result is deterministic (the order differs from
 // the sequential one, which FP64 keeps).
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, bool CENTER>
-__global__ __launch_bounds__(256) void k_sweep_long(int32_t lpr, int32_t k, const int32_t *__restrict__ long_rows,
+__global__ __launch_bounds__(256) void k_sweep_long(int32_t lpr, int32_t ldx, int32_t ldy,
+                                                    const int32_t *__restrict__ long_rows,
                                                     const int32_t *__restrict__ long_cnt,
                                                     const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ col, const TW *__restrict__ val,
@@ -243,7 +247,7 @@ __global__ __launch_bounds__(256) void k_sweep_long(int32_t lpr, int32_t k, cons
                 const int64_t c = col[j];
                 const TA wv = cvt<TA>(val[j]);
                 TA xv[VPL];
-                load_row<TIN, TX, TA, VPL, CENTER>(x + c * k + off, mo, xv);
+                load_row<TIN, TX, TA, VPL, CENTER>(x + c * ldx + off, mo, xv);
 #pragma unroll
                 for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], wv, xv[i]);
             }
@@ -260,7 +264,7 @@ __global__ __launch_bounds__(256) void k_sweep_long(int32_t lpr, int32_t k, cons
         }
         if (g == 0) {
             TA self[VPL];
-            load_row<TIN, TX, TA, VPL, CENTER>(x + row * k + off, mo, self);
+            load_row<TIN, TX, TA, VPL, CENTER>(x + row * ldx + off, mo, self);
             const TA d = cvt<TA>(deg[row]);
             Vec<TO, VPL> out;
 #pragma unroll
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(256) void k_sweep_long(int32_t lpr, int32_t k, cons
                 const TA bo = omega * q;
                 out.v[i] = cvt<TO>(a + bo);
             }
-            *reinterpret_cast<Vec<TO, VPL> *>(y + row * k + off) = out;
+            *reinterpret_cast<Vec<TO, VPL> *>(y + row * ldy + off) = out;
         }
         __syncthreads();
     }
@@ -290,85 +294,125 @@ int ilog2_exact(int x) {
     return -1;
 }
 
-// Tuning knob (environment, read once): SFG_SWEEP_U = neighbour unroll (2, 4
-// or 8; default 2 for FP64 rows averaging <= 3 entries, else 4: measured
-// best on the power grid's spanning tree).
 int env_int(const char *name, int dflt) {
     const char *e = getenv(name);
     return e ? atoi(e) : dflt;
 }
 
+// One sweep over the kw columns [c0, c0 + kw) of the block: x and y point at
+// column c0 of row 0, ldx and ldy are their row strides (elements), mean (when
+// centring) at the mean of column c0.  vpl columns per lane, u-fold neighbour
+// unroll.
+struct SweepShape {
+    int32_t kw, ldx, ldy, vpl, u;
+};
+
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, int U, bool CENTER>
-void launch_sweep_u(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
+void launch_sweep_u(const sfg_csr *H, const SweepShape &sh, const TIN *x, const double *mean, TO *y, double omega,
                     const int32_t *rows, int64_t nrows, const LongRows &lr, hipStream_t s) {
-    const int lpr = k / VPL;
+    const int lpr = sh.kw / VPL;
     const int64_t nthreads = nrows * (int64_t)lpr;
     if (nthreads == 0) return;
     hipLaunchKernelGGL((k_sweep<TIN, TX, TO, TW, TA, VPL, U, CENTER>), dim3(grid_for(nthreads, 256)), dim3(256), 0, s,
-                       nthreads, lpr, ilog2_exact(lpr), k, lr.max_len, rows, H->rowptr, H->col, (const TW *)H->val,
-                       (const TW *)H->deg, x, mean, y, (TA)(1.0 - omega), (TA)omega);
+                       nthreads, lpr, ilog2_exact(lpr), sh.ldx, sh.ldy, lr.max_len, rows, H->rowptr, H->col,
+                       (const TW *)H->val, (const TW *)H->deg, x, mean, y, (TA)(1.0 - omega), (TA)omega);
     SFG_LAUNCH_CHECK();
     if constexpr (sizeof(TA) == 4) {
         if (lr.rows) {
-            hipLaunchKernelGGL((k_sweep_long<TIN, TX, TO, TW, TA, VPL, CENTER>), dim3(1024), dim3(256), 0, s, lpr, k,
-                               lr.rows, lr.count, H->rowptr, H->col, (const TW *)H->val, (const TW *)H->deg, x, mean,
-                               y, (TA)(1.0 - omega), (TA)omega);
+            hipLaunchKernelGGL((k_sweep_long<TIN, TX, TO, TW, TA, VPL, CENTER>), dim3(1024), dim3(256), 0, s, lpr,
+                               sh.ldx, sh.ldy, lr.rows, lr.count, H->rowptr, H->col, (const TW *)H->val,
+                               (const TW *)H->deg, x, mean, y, (TA)(1.0 - omega), (TA)omega);
             SFG_LAUNCH_CHECK();
         }
     }
 }
 
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, bool CENTER>
-void launch_sweep_v(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
+void launch_sweep_v(const sfg_csr *H, const SweepShape &sh, const TIN *x, const double *mean, TO *y, double omega,
                     const int32_t *rows, int64_t nrows, const LongRows &lr, hipStream_t s) {
-    static const int forced = env_int("SFG_SWEEP_U", 0);
-    const int u = forced ? forced : ((sizeof(TX) == 8 && H->nnz <= 3 * H->n) ? 2 : 4);
-    if (u <= 2)
-        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 2, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s);
-    else if (u <= 4)
-        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 4, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s);
+    if (sh.u <= 2)
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 2, CENTER>(H, sh, x, mean, y, omega, rows, nrows, lr, s);
+    else if (sh.u <= 4)
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 4, CENTER>(H, sh, x, mean, y, omega, rows, nrows, lr, s);
     else
-        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 8, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s);
+        launch_sweep_u<TIN, TX, TO, TW, TA, VPL, 8, CENTER>(H, sh, x, mean, y, omega, rows, nrows, lr, s);
 }
 
-// Columns per lane: the widest run that divides k, of at most 32 bytes for
-// FP64 and 16 bytes otherwise (measured best on the 1M-node power grid:
-// 4 lanes per 16-vector row in both cases).  SFG_VPL overrides it, up to
-// 64 bytes, for tuning.
+// Columns per lane: the widest run that divides kw and spans at most maxb
+// bytes.  SFG_VPL overrides it, up to 64 bytes, for tuning.
 template <typename TX>
-int pick_vpl(int32_t k) {
-    static const int forced = [] {
-        const char *e = getenv("SFG_VPL");
-        return e ? atoi(e) : 0;
-    }();
-    if (forced > 0 && k % forced == 0 && forced * (int)sizeof(TX) <= 64) return forced;
-    const int maxb = sizeof(TX) == 8 ? 32 : 16;
+int pick_vpl(int32_t kw, int maxb) {
+    static const int forced = env_int("SFG_VPL", 0);
+    if (forced > 0 && kw % forced == 0 && forced * (int)sizeof(TX) <= 64) return forced;
     int best = 1;
     for (int v = 1; v * (int)sizeof(TX) <= maxb; v <<= 1)
-        if (k % v == 0) best = v;
+        if (kw % v == 0) best = v;
     return best;
 }
 
+// Launch shape of a sweep over the whole block (k columns, stride k).
+// Measured best on the 1M-node power grid's spanning tree: 4 lanes per
+// 16-vector row (32 bytes per lane in FP64, 16 otherwise), neighbour unroll 2
+// for FP64 rows averaging <= 3 entries, else 4.  SFG_SWEEP_U overrides the
+// unroll (2, 4 or 8).
+template <typename TX>
+SweepShape full_shape(const sfg_csr *H, int32_t k) {
+    static const int forced_u = env_int("SFG_SWEEP_U", 0);
+    SweepShape sh;
+    sh.kw = sh.ldx = sh.ldy = k;
+    sh.vpl = pick_vpl<TX>(k, sizeof(TX) == 8 ? 32 : 16);
+    sh.u = forced_u ? forced_u : ((sizeof(TX) == 8 && H->nnz <= 3 * H->n) ? 2 : 4);
+    return sh;
+}
+
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, bool CENTER>
-void launch_sweep(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega,
+void launch_sweep(const sfg_csr *H, const SweepShape &sh, const TIN *x, const double *mean, TO *y, double omega,
                   hipStream_t s, const int32_t *rows = nullptr, int64_t nrows = -1, const LongRows &lr = LongRows()) {
     if (nrows < 0) nrows = H->n;
-    const int vpl = pick_vpl<TX>(k);
     constexpr int maxv = 64 / (int)sizeof(TX);
-    switch (vpl) {
-        case 1: launch_sweep_v<TIN, TX, TO, TW, TA, 1, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s); return;
-        case 2: launch_sweep_v<TIN, TX, TO, TW, TA, 2, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s); return;
-        case 4: launch_sweep_v<TIN, TX, TO, TW, TA, 4, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s); return;
-        case 8: launch_sweep_v<TIN, TX, TO, TW, TA, 8, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s); return;
+    switch (sh.vpl) {
+        case 1: launch_sweep_v<TIN, TX, TO, TW, TA, 1, CENTER>(H, sh, x, mean, y, omega, rows, nrows, lr, s); return;
+        case 2: launch_sweep_v<TIN, TX, TO, TW, TA, 2, CENTER>(H, sh, x, mean, y, omega, rows, nrows, lr, s); return;
+        case 4: launch_sweep_v<TIN, TX, TO, TW, TA, 4, CENTER>(H, sh, x, mean, y, omega, rows, nrows, lr, s); return;
+        case 8: launch_sweep_v<TIN, TX, TO, TW, TA, 8, CENTER>(H, sh, x, mean, y, omega, rows, nrows, lr, s); return;
         case 16:
             if constexpr (maxv >= 16) {
-                launch_sweep_v<TIN, TX, TO, TW, TA, 16, CENTER>(H, k, x, mean, y, omega, rows, nrows, lr, s);
+                launch_sweep_v<TIN, TX, TO, TW, TA, 16, CENTER>(H, sh, x, mean, y, omega, rows, nrows, lr, s);
                 return;
             }
             break;
         default: break;
     }
     fail(SFG_EUNSUPPORTED, "smooth: no kernel for this lane split");
+}
+
+template <typename TIN, typename TX, typename TO, typename TW, typename TA, bool CENTER>
+void launch_sweep(const sfg_csr *H, int32_t k, const TIN *x, const double *mean, TO *y, double omega, hipStream_t s,
+                  const int32_t *rows = nullptr, int64_t nrows = -1, const LongRows &lr = LongRows()) {
+    launch_sweep<TIN, TX, TO, TW, TA, CENTER>(H, full_shape<TX>(H, k), x, mean, y, omega, s, rows, nrows, lr);
+}
+
+// Column parts for the full smoothing.  An FP64 block of k >= 16 vectors on a
+// sparse graph (<= 3 entries per row on average: spanning trees, sparsifiers)
+// is swept 8 columns (64-byte rows) at a time, all sweeps of one part before
+// the next: a part's two ping-pong buffers and the graph then fit in the
+// 256 MB memory-side cache together, and 64-byte rows take 4 lanes of 16
+// bytes with a 4-fold neighbour unroll (measured on the 1M-node power grid's
+// tree: 59 us per 16-vector sweep against 74 us unsplit).  Each column's
+// arithmetic is unchanged, so the result is bit-identical.  SFG_SWEEP_SPLIT=0
+// turns it off.
+template <typename TX>
+SweepShape part_shape(const sfg_csr *H, int32_t k) {
+    static const int split = env_int("SFG_SWEEP_SPLIT", 1);
+    if (split && sizeof(TX) == 8 && k >= 16 && k % 8 == 0 && H->nnz <= 3 * H->n) {
+        SweepShape sh;
+        sh.kw = 8;
+        sh.ldx = sh.ldy = 8;
+        sh.vpl = pick_vpl<TX>(8, 16);
+        sh.u = 4;
+        return sh;
+    }
+    return full_shape<TX>(H, k);
 }
 
 struct SmoothPlan {
@@ -450,25 +494,35 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
         lr.count = p.lpos + n;
         lr.max_len = kLongRow;
     }
-    // a3: sweeps; the first centres on the fly, the last writes xout
-    for (int32_t t = 0; t < sweeps; ++t) {
-        const bool last = (t == sweeps - 1);
-        TX *dst = (t % 2 == 0) ? b0 : b1;
-        if (t == 0) {
+    // a3: sweeps, column part by column part; the first sweep of a part
+    // centres on the fly from x0, the last writes the part's columns of xout
+    const SweepShape ps = part_shape<TX>(H, k);
+    for (int32_t c0 = 0; c0 < k; c0 += ps.kw) {
+        SweepShape first = ps, mid = ps;
+        first.ldx = k;
+        for (int32_t t = 0; t < sweeps; ++t) {
+            const bool last = (t == sweeps - 1);
+            SweepShape sh = (t == 0) ? first : mid;
+            if (last) sh.ldy = k;
+            TX *dst = (t % 2 == 0) ? b0 : b1;
+            if (t == 0) {
+                if (last && final_f32)
+                    launch_sweep<double, TX, float, TW, TA, true>(H, sh, x0 + c0, p.mean + c0,
+                                                                  (float *)xout + c0, omega, s, nullptr, -1, lr);
+                else
+                    launch_sweep<double, TX, TX, TW, TA, true>(H, sh, x0 + c0, p.mean + c0,
+                                                               last ? (TX *)xout + c0 : dst, omega, s, nullptr, -1,
+                                                               lr);
+                continue;
+            }
+            const TX *src = (t % 2 == 0) ? b1 : b0;
             if (last && final_f32)
-                launch_sweep<double, TX, float, TW, TA, true>(H, k, x0, p.mean, (float *)xout, omega, s, nullptr, -1,
-                                                              lr);
+                launch_sweep<TX, TX, float, TW, TA, false>(H, sh, src, nullptr, (float *)xout + c0, omega, s, nullptr,
+                                                           -1, lr);
             else
-                launch_sweep<double, TX, TX, TW, TA, true>(H, k, x0, p.mean, last ? (TX *)xout : dst, omega, s,
-                                                           nullptr, -1, lr);
-            continue;
+                launch_sweep<TX, TX, TX, TW, TA, false>(H, sh, src, nullptr, last ? (TX *)xout + c0 : dst, omega, s,
+                                                        nullptr, -1, lr);
         }
-        const TX *src = (t % 2 == 0) ? b1 : b0;
-        if (last && final_f32)
-            launch_sweep<TX, TX, float, TW, TA, false>(H, k, src, nullptr, (float *)xout, omega, s, nullptr, -1, lr);
-        else
-            launch_sweep<TX, TX, TX, TW, TA, false>(H, k, src, nullptr, last ? (TX *)xout : dst, omega, s, nullptr,
-                                                    -1, lr);
     }
 }
 

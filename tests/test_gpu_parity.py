@@ -103,6 +103,20 @@ def test_smooth_omega_and_tree(S, orc):
         np.testing.assert_array_equal(host(X), ref)
 
 
+@pytest.mark.parametrize("k,sweeps", [(16, 1), (16, 2), (24, 5), (40, 3), (8, 4)])
+def test_smooth_f64_tree_column_parts(S, orc, k, sweeps):
+    # FP64 blocks on tree-like graphs are swept in 8-column parts (first sweep
+    # from x0, middle sweeps in part buffers, last into the output columns)
+    g = W.powergrid(41, 53, 0.02, seed=76)
+    tree, _ = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    t = tree.astype(bool)
+    X0 = W.random_block(g.n, k, 300 + k)
+    ref = orc.smooth(orc.laplacian_csr(g.n, g.u[t], g.v[t], g.w[t]), orc.center(X0)[0], sweeps, 0.5)
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w), mask=dev(tree))
+    X = S.sfg_smooth(H, dev(X0), sweeps, 0.5, storage=torch.float64)
+    np.testing.assert_array_equal(host(X), ref)
+
+
 @pytest.mark.parametrize("storage,final_f32,tol", [
     (torch.float32, False, 2e-5),
     (torch.float16, True, 6e-3),
