@@ -152,7 +152,7 @@ def run_chunglu(args) -> dict:
             "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "vectors": k, "sweeps": T, "frac": f,
                        "levels": L},
             "runs": out, "coarsening_ratio": ratio, "roofline_f32_sweep_level0_graph": roof,
-            "note": "host Kruskal spanning forests are included in ms_total"}
+            "note": "ms_total includes the per-aggregate spanning forests (GPU Boruvka) and all coarsening"}
 
 
 # ----------------------------------------------------------------------------- 3-D mesh: plain vs surrogate

@@ -9,7 +9,12 @@
 // T sweeps depends on the T-hop neighbourhood of its endpoints, so a
 // multi-source BFS (capped at T hops) orders the rows by distance and sweep
 // t recomputes the rows within T - t hops, with the same per-row arithmetic
-// as the full FP64 pass.
+// as the full FP64 pass.  When the cone holds more than a quarter of the
+// full pass's row updates (T = 20 on meshes and kNN graphs reaches most of
+// the graph), the full FP64 smoothing runs instead: it sweeps rows in node
+// order, several times faster per row than the distance-ordered cone, and
+// gives the same bits.
+#include <algorithm>
 #include <vector>
 
 #include "common.hpp"
@@ -27,6 +32,9 @@ size_t cone_partial_bytes(int64_t n, int32_t k);
 double *smooth_cone_f64(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0,
                         const int32_t *rows_by_dist, const int64_t *active, double *buf0, double *buf1,
                         void *partial_ws, double *mean, hipStream_t s);
+size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
+void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
+            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s);
 
 namespace {
 
@@ -86,18 +94,60 @@ __global__ void k_bfs_level(int64_t n, const int32_t *__restrict__ rowptr, const
     }
 }
 
-__global__ void k_dist_hist(int64_t n, const int32_t *__restrict__ dist, int32_t cap, int32_t *hist) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n && dist[p] <= cap) atomicAdd(&hist[dist[p]], 1);
+// Rows per distance 0..cap: block-local counts in LDS, one global atomic per
+// bin and block (a global atomic per row serialises on the few bins).
+constexpr int kMaxBins = 1024;
+constexpr int kDistBlocks = 1024;
+
+__global__ __launch_bounds__(256) void k_dist_hist(int64_t n, const int32_t *__restrict__ dist, int32_t cap,
+                                                   int32_t *hist) {
+    __shared__ int32_t h[kMaxBins];
+    const int32_t nb = cap + 1;
+    const bool lds = nb <= kMaxBins;
+    if (lds)
+        for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0;
+    __syncthreads();
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t d = dist[p];
+        if (d <= cap) atomicAdd(lds ? &h[d] : &hist[d], 1);
+    }
+    __syncthreads();
+    if (lds)
+        for (int32_t b = threadIdx.x; b < nb; b += blockDim.x)
+            if (h[b]) atomicAdd(&hist[b], h[b]);
 }
 
-__global__ void k_dist_scatter(int64_t n, const int32_t *__restrict__ dist, int32_t cap,
-                               const int32_t *__restrict__ start, int32_t *fill, int32_t *rows) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t d = dist[p];
-    if (d > cap) return;
-    rows[start[d] + atomicAdd(&fill[d], 1)] = (int32_t)p;
+// Rows grouped by distance: each block reserves one range per bin for its
+// rows (counted in a first pass over its grid-stride share), then places
+// them (LDS cursors).  The order inside a distance group is irrelevant: the
+// cone sweeps read only the previous iterate.
+__global__ __launch_bounds__(256) void k_dist_scatter(int64_t n, const int32_t *__restrict__ dist, int32_t cap,
+                                                      const int32_t *__restrict__ start, int32_t *fill,
+                                                      int32_t *rows) {
+    __shared__ int32_t cur[kMaxBins];
+    const int32_t nb = cap + 1;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (nb > kMaxBins) {       // many bins: one global atomic per row
+        for (int64_t p = p0; p < n; p += stride) {
+            const int32_t d = dist[p];
+            if (d <= cap) rows[start[d] + atomicAdd(&fill[d], 1)] = (int32_t)p;
+        }
+        return;
+    }
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = 0;
+    __syncthreads();
+    for (int64_t p = p0; p < n; p += stride) {
+        const int32_t d = dist[p];
+        if (d <= cap) atomicAdd(&cur[d], 1);
+    }
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = cur[b] ? start[b] + atomicAdd(&fill[b], cur[b]) : 0;
+    __syncthreads();
+    for (int64_t p = p0; p < n; p += stride) {
+        const int32_t d = dist[p];
+        if (d <= cap) rows[atomicAdd(&cur[d], 1)] = (int32_t)p;
+    }
 }
 
 __global__ void k_band_final(int64_t nc, const uint8_t *__restrict__ cls, uint8_t *sel) {
@@ -154,6 +204,7 @@ void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, c
     }
     int64_t cone_rows = 0;
     double *sB = A.alloc<double>(nB + 1);
+    std::vector<int32_t> st;     // distance-group starts (host; outlives the async copy below)
     if (nB > 0) {
         // dependency cone: hop distance (capped at sweeps+1) from the band's endpoints
         int32_t *dist = A.alloc<int32_t>(n + 1);
@@ -166,34 +217,42 @@ void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, c
             SFG_LAUNCH_CHECK();
         }
         int32_t *hist = A.alloc<int32_t>(sweeps + 2);
-        int32_t *fill = A.alloc<int32_t>(sweeps + 2);
-        int32_t *start = A.alloc<int32_t>(sweeps + 2);
         fill_i32(hist, sweeps + 2, 0, s);
-        fill_i32(fill, sweeps + 2, 0, s);
-        hipLaunchKernelGGL(k_dist_hist, dim3(grid_for(n, 256)), dim3(256), 0, s, n, dist, sweeps, hist);
+        const dim3 gd(std::min<uint32_t>(grid_for(n, 256), (uint32_t)kDistBlocks));
+        hipLaunchKernelGGL(k_dist_hist, gd, dim3(256), 0, s, n, dist, sweeps, hist);
         SFG_LAUNCH_CHECK();
         std::vector<int32_t> hh(sweeps + 1);
         SFG_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * (sweeps + 1), hipMemcpyDeviceToHost, s));
         SFG_HIP(hipStreamSynchronize(s));
-        std::vector<int32_t> st(sweeps + 2, 0);
+        st.assign(sweeps + 2, 0);
         for (int32_t d = 0; d <= sweeps; ++d) st[d + 1] = st[d] + hh[d];
-        SFG_HIP(hipMemcpyAsync(start, st.data(), sizeof(int32_t) * (sweeps + 2), hipMemcpyHostToDevice, s));
-        const int64_t in_cone = st[sweeps + 1];
-        int32_t *rows = A.alloc<int32_t>(in_cone + 1);
-        hipLaunchKernelGGL(k_dist_scatter, dim3(grid_for(n, 256)), dim3(256), 0, s, n, dist, sweeps, start, fill,
-                           rows);
-        SFG_LAUNCH_CHECK();
         // sweep t (0-based) recomputes the rows within sweeps-1-t hops
         std::vector<int64_t> active(sweeps > 0 ? sweeps : 1);
         for (int32_t t = 0; t < sweeps; ++t) {
             active[t] = st[sweeps - t];   // rows with dist <= sweeps-1-t
             cone_rows += active[t];
         }
-        double *b0 = A.alloc<double>((size_t)n * k);
-        double *b1 = A.alloc<double>((size_t)n * k);
-        double *mean = A.alloc<double>(k);
-        void *partial = A.raw(cone_partial_bytes(n, k));
-        double *X = smooth_cone_f64(H64, k, sweeps, omega, x0, rows, active.data(), b0, b1, partial, mean, s);
+        double *X = nullptr;
+        if (4 * cone_rows <= (int64_t)sweeps * n) {
+            // rows ordered by distance
+            int32_t *start = A.alloc<int32_t>(sweeps + 2);
+            int32_t *fill = A.alloc<int32_t>(sweeps + 2);
+            fill_i32(fill, sweeps + 2, 0, s);
+            SFG_HIP(hipMemcpyAsync(start, st.data(), sizeof(int32_t) * (sweeps + 2), hipMemcpyHostToDevice, s));
+            int32_t *rows = A.alloc<int32_t>(st[sweeps + 1] + 1);
+            hipLaunchKernelGGL(k_dist_scatter, gd, dim3(256), 0, s, n, dist, sweeps, start, fill, rows);
+            SFG_LAUNCH_CHECK();
+            double *b0 = A.alloc<double>((size_t)n * k);
+            double *b1 = A.alloc<double>((size_t)n * k);
+            double *mean = A.alloc<double>(k);
+            void *partial = A.raw(cone_partial_bytes(n, k));
+            X = smooth_cone_f64(H64, k, sweeps, omega, x0, rows, active.data(), b0, b1, partial, mean, s);
+        } else {
+            cone_rows = (int64_t)sweeps * n;
+            X = A.alloc<double>((size_t)n * k);
+            const size_t wsb = smooth_workspace_bytes(n, k, SFG_F64);
+            smooth(H64, k, sweeps, omega, x0, SFG_F64, 0, X, A.raw(wsb), wsb, s);
+        }
         edge_scores(X, SFG_F64, n, k, nB, eB, u, v, w64, SFG_F64, sB, SFG_F64, s);
     }
     // final: A, plus the best `need` of B by FP64 score

@@ -12,10 +12,12 @@
 //  2. lower-part counts (integer atomics on v) and one scan: rowptr
 //  3. upper entries: one thread per edge writes its slot directly
 //  4. lower entries: each edge id is dropped into its row (atomic slot), then
-//     every row's lower part is ordered by edge id -- rank = number of smaller
-//     ids in the segment -- by a thread per short row or a workgroup per long
-//     row (segment staged in LDS), which writes col/val/eid
-//  5. one thread per row sums its weights in column order, in FP64
+//     every row's lower part is ordered by edge id: a thread per short row
+//     ranks its ids (rank = number of smaller ids), a workgroup per long row
+//     bitonic-sorts the segment in LDS; both write col/val/eid
+//  5. one thread per row sums its weights in column order, in FP64; rows
+//     over 256 entries (hubs) are staged through LDS by a wavefront and
+//     summed by one of its lanes in the same order
 #include "common.hpp"
 
 namespace sfg {
@@ -23,10 +25,11 @@ namespace sfg {
 namespace {
 
 constexpr int kShortSeg = 32;       // lower parts up to this length: one thread
-constexpr int kLdsSeg = 8192;       // longer ones are staged in LDS up to this length
+constexpr int kLdsSeg = 8192;       // longer ones are sorted in LDS up to this length
+constexpr int kDegLong = 256;       // rows longer than this: degree summed by a workgroup
 
 struct CsrPlan {
-    int32_t *estart, *inc, *incpos, *cnt_lo, *tot, *fill, *tmp, *long_rows, *long_cnt, *scan;
+    int32_t *estart, *inc, *incpos, *cnt_lo, *tot, *fill, *tmp, *long_rows, *long_cnt, *deg_rows, *deg_cnt, *scan;
 };
 
 CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
@@ -40,6 +43,8 @@ CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
     p.tmp = c.take<int32_t>(2 * m + 1);
     p.long_rows = c.take<int32_t>(n + 1);
     p.long_cnt = c.take<int32_t>(1);
+    p.deg_rows = c.take<int32_t>(n + 1);
+    p.deg_cnt = c.take<int32_t>(1);
     p.scan = c.take<int32_t>(scan_scratch_ints((n > m ? n : m) + 1));
     return p;
 }
@@ -133,6 +138,16 @@ __global__ __launch_bounds__(256) void k_rank_short(int64_t n, const int32_t *__
 }
 
 template <typename TW>
+__device__ __forceinline__ void put_lower(int32_t j, int32_t e, const int32_t *__restrict__ u,
+                                          const TW *__restrict__ w, int32_t *col, TW *val, int32_t *eid) {
+    col[j] = u[e];
+    val[j] = w[e];
+    eid[j] = e;
+}
+
+// Long lower parts: up to kLdsSeg ids are bitonic-sorted in LDS (padded to a
+// power of two with INT32_MAX); longer ones are ranked from global memory.
+template <typename TW>
 __global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ cnt_lo,
                                                    const int32_t *__restrict__ tmp, const int32_t *__restrict__ u,
@@ -145,32 +160,96 @@ __global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ r
         const int32_t row = long_rows[r];
         const int32_t len = cnt_lo[row];
         const int32_t base = rowptr[row];
-        const bool in_lds = len <= kLdsSeg;
-        if (in_lds)
-            for (int32_t i = threadIdx.x; i < len; i += blockDim.x) seg[i] = tmp[base + i];
-        __syncthreads();
-        for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
-            const int32_t mine = tmp[base + i];
-            int32_t rank = 0;
-            if (in_lds)
-                for (int32_t j = 0; j < len; ++j) rank += (seg[j] < mine) ? 1 : 0;
-            else
+        if (len <= kLdsSeg) {
+            int32_t pw = 1;
+            while (pw < len) pw <<= 1;
+            for (int32_t i = threadIdx.x; i < pw; i += blockDim.x) seg[i] = i < len ? tmp[base + i] : INT32_MAX;
+            __syncthreads();
+            for (int32_t kk = 2; kk <= pw; kk <<= 1) {
+                for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
+                    for (int32_t i = threadIdx.x; i < pw; i += blockDim.x) {
+                        const int32_t ixj = i ^ jj;
+                        if (ixj > i) {
+                            const int32_t a = seg[i], b = seg[ixj];
+                            const bool ascending = (i & kk) == 0;
+                            if ((a > b) == ascending) {
+                                seg[i] = b;
+                                seg[ixj] = a;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int32_t i = threadIdx.x; i < len; i += blockDim.x) put_lower(base + i, seg[i], u, w, col, val, eid);
+        } else {
+            for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
+                const int32_t mine = tmp[base + i];
+                int32_t rank = 0;
                 for (int32_t j = 0; j < len; ++j) rank += (tmp[base + j] < mine) ? 1 : 0;
-            col[base + rank] = u[mine];
-            val[base + rank] = w[mine];
-            eid[base + rank] = mine;
+                put_lower(base + rank, mine, u, w, col, val, eid);
+            }
         }
         __syncthreads();
     }
 }
 
+// d + a[0] + a[1] + ... + a[n-1], added left to right in FP64, with 8 loads
+// in flight before the 8 dependent adds (the same additions as the plain loop).
+template <typename T>
+__device__ __forceinline__ double seq_sum(double d, const T *__restrict__ a, int32_t n) {
+    int32_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+        double t[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t[q] = (double)a[i + q];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d = d + t[q];
+    }
+    for (; i < n; ++i) d = d + (double)a[i];
+    return d;
+}
+
 template <typename TW>
-__global__ void k_degree(int64_t n, const int32_t *__restrict__ rowptr, const TW *__restrict__ val, TW *deg) {
+__global__ void k_degree(int64_t n, const int32_t *__restrict__ rowptr, const TW *__restrict__ val, TW *deg,
+                         int32_t *long_rows, int32_t *long_cnt) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    double d = 0.0;
-    for (int32_t j = rowptr[p]; j < rowptr[p + 1]; ++j) d = d + (double)val[j];
-    deg[p] = (TW)d;
+    const int32_t j0 = rowptr[p], j1 = rowptr[p + 1];
+    if (j1 - j0 > kDegLong) {
+        long_rows[atomicAdd(long_cnt, 1)] = (int32_t)p;
+        return;
+    }
+    deg[p] = (TW)seq_sum(0.0, val + j0, j1 - j0);
+}
+
+// Hub rows: a wavefront stages the row's weights in LDS, chunk by chunk
+// (coalesced), and its first lane adds them in column order -- the same sum
+// as k_degree's.  One wavefront per row, four rows per workgroup.
+template <typename TW>
+__global__ __launch_bounds__(256) void k_degree_long(const int32_t *__restrict__ rowptr, const TW *__restrict__ val,
+                                                     TW *deg, const int32_t *__restrict__ long_rows,
+                                                     const int32_t *__restrict__ long_cnt) {
+    constexpr int kChunk = 1024;
+    __shared__ double buf[4][kChunk];
+    const int wv = threadIdx.x / 64, lane = threadIdx.x % 64;
+    double *b = buf[wv];
+    const int32_t cnt = *long_cnt;
+    for (int32_t r = blockIdx.x * 4 + wv; r < cnt; r += gridDim.x * 4) {
+        const int32_t row = long_rows[r];
+        const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+        double d = 0.0;
+        for (int32_t c = j0; c < j1; c += kChunk) {
+            const int32_t len = (j1 - c) < kChunk ? (j1 - c) : kChunk;
+            // one wavefront runs in program order: the first lane reads what
+            // all lanes wrote, and the next chunk is written after it is done
+            for (int32_t i = lane; i < len; i += 64) b[i] = (double)val[c + i];
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) d = seq_sum(d, b, len);
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (lane == 0) deg[row] = (TW)d;
+    }
 }
 
 template <typename TW>
@@ -191,7 +270,9 @@ void fill_entries(int64_t n, int64_t m, const int32_t *u, const int32_t *v, cons
                            p.long_rows, p.long_cnt);
         SFG_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_degree<TW>, gn, b, 0, s, n, rowptr, val, deg);
+    hipLaunchKernelGGL(k_degree<TW>, gn, b, 0, s, n, rowptr, val, deg, p.deg_rows, p.deg_cnt);
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_degree_long<TW>, dim3(1024), b, 0, s, rowptr, val, deg, p.deg_rows, p.deg_cnt);
     SFG_LAUNCH_CHECK();
 }
 
@@ -219,6 +300,7 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
     fill_i32(p.cnt_lo, n + 1, 0, s);
     fill_i32(p.fill, n + 1, 0, s);
     fill_i32(p.long_cnt, 1, 0, s);
+    fill_i32(p.deg_cnt, 1, 0, s);
     hipLaunchKernelGGL(k_estart, dim3(grid_for(n + 1, 256)), b, 0, s, n, m, u, p.estart);
     SFG_LAUNCH_CHECK();
     if (m > 0) {

@@ -394,17 +394,27 @@ void launch_sweep(const sfg_csr *H, int32_t k, const TIN *x, const double *mean,
 
 // Column parts for the full smoothing.  An FP64 block of k >= 16 vectors on a
 // sparse graph (<= 3 entries per row on average: spanning trees, sparsifiers)
-// is swept 8 columns (64-byte rows) at a time, all sweeps of one part before
-// the next: a part's two ping-pong buffers and the graph then fit in the
-// 256 MB memory-side cache together, and 64-byte rows take 4 lanes of 16
-// bytes with a 4-fold neighbour unroll (measured on the 1M-node power grid's
-// tree: 59 us per 16-vector sweep against 74 us unsplit).  Each column's
-// arithmetic is unchanged, so the result is bit-identical.  SFG_SWEEP_SPLIT=0
-// turns it off.
+// whose sweep working set (X_t, X_t+1 and the graph) exceeds the 256 MB
+// memory-side cache, while that of an 8-column part stays within 192 MB of
+// it, is swept 8 columns (64-byte rows) at a time, all sweeps of one part
+// before the next: the part's two ping-pong buffers and the graph then stay
+// cache-resident, and 64-byte rows take 4 lanes of 16 bytes with a 4-fold
+// neighbour unroll (measured on the 1M-node power grid's tree: 59 us per
+// 16-vector sweep against 74 us unsplit).  A part that does not fit gains
+// nothing and repeats the neighbour gathers (measured slower on a 2M-node kNN
+// tree with random node order), so it is not split.  Each column's arithmetic
+// is unchanged: the result is bit-identical.  SFG_SWEEP_SPLIT (read at every
+// call) = 0 turns it off, 2 forces it for any FP64 block of k >= 16, k % 8 == 0
+// (tests use it to cover the part sweeps on small graphs).
 template <typename TX>
 SweepShape part_shape(const sfg_csr *H, int32_t k) {
-    static const int split = env_int("SFG_SWEEP_SPLIT", 1);
-    if (split && sizeof(TX) == 8 && k >= 16 && k % 8 == 0 && H->nnz <= 3 * H->n) {
+    const int split = env_int("SFG_SWEEP_SPLIT", 1);
+    constexpr double kCache = 256.0 * (1 << 20), kPartBudget = 192.0 * (1 << 20);
+    const double sx = (double)sizeof(TX), sw = (double)dtype_size(H->vt);
+    const double graph = 4.0 * (H->n + 1) + (double)H->nnz * (4.0 + sw) + (double)H->n * sw;
+    const double full = 2.0 * H->n * k * sx + graph, part = 2.0 * H->n * 8 * sx + graph;
+    const bool fits = H->nnz <= 3 * H->n && full > kCache && part <= kPartBudget;
+    if (sizeof(TX) == 8 && k >= 16 && k % 8 == 0 && (split == 2 || (split == 1 && fits))) {
         SweepShape sh;
         sh.kw = 8;
         sh.ldx = sh.ldy = 8;

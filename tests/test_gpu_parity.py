@@ -104,9 +104,12 @@ def test_smooth_omega_and_tree(S, orc):
 
 
 @pytest.mark.parametrize("k,sweeps", [(16, 1), (16, 2), (24, 5), (40, 3), (8, 4)])
-def test_smooth_f64_tree_column_parts(S, orc, k, sweeps):
-    # FP64 blocks on tree-like graphs are swept in 8-column parts (first sweep
-    # from x0, middle sweeps in part buffers, last into the output columns)
+def test_smooth_f64_tree_column_parts(S, orc, k, sweeps, monkeypatch):
+    # FP64 blocks are swept in 8-column parts when a part's working set fits the
+    # memory-side cache (the 1M-node power grid); SFG_SWEEP_SPLIT=2 forces the
+    # part sweeps (first sweep from x0, middle sweeps in part buffers, last into
+    # the output columns) on a small tree
+    monkeypatch.setenv("SFG_SWEEP_SPLIT", "2")
     g = W.powergrid(41, 53, 0.02, seed=76)
     tree, _ = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
     t = tree.astype(bool)
@@ -115,6 +118,10 @@ def test_smooth_f64_tree_column_parts(S, orc, k, sweeps):
     H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w), mask=dev(tree))
     X = S.sfg_smooth(H, dev(X0), sweeps, 0.5, storage=torch.float64)
     np.testing.assert_array_equal(host(X), ref)
+    # the graph itself (4 entries per row) under the forced split
+    ref_g = orc.smooth(orc.laplacian_csr(g.n, g.u, g.v, g.w), orc.center(X0)[0], sweeps, 0.5)
+    Hg = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w))
+    np.testing.assert_array_equal(host(S.sfg_smooth(Hg, dev(X0), sweeps, 0.5, storage=torch.float64)), ref_g)
 
 
 @pytest.mark.parametrize("storage,final_f32,tol", [

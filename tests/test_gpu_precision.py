@@ -24,12 +24,14 @@ def dev(a):
 
 
 CASES = [
-    # (graph, k, sweeps, frac, storage, final_f32, band)
-    ("knn", 32, 20, 0.10, torch.float16, True, 0.01),
-    ("knn", 32, 20, 0.10, torch.bfloat16, True, 0.01),
-    ("knn", 16, 12, 0.10, torch.float16, False, 0.01),
-    ("pgrid", 16, 20, 0.10, torch.float32, False, 0.001),
-    ("mesh", 16, 20, 0.10, torch.float16, True, 0.01),
+    # (graph, k, sweeps, frac, storage, final_f32, band, FP64 re-smoothing: "cone", "full" or None = either)
+    ("knn", 32, 20, 0.10, torch.float16, True, 0.01, None),
+    ("knn", 32, 20, 0.10, torch.bfloat16, True, 0.01, None),
+    ("knn", 16, 12, 0.10, torch.float16, False, 0.01, None),
+    ("pgrid", 16, 20, 0.10, torch.float32, False, 0.001, None),
+    ("mesh", 16, 20, 0.10, torch.float16, True, 0.01, None),
+    # 3 sweeps on a 300x300 power grid: the cone is under 1% of the full pass
+    ("pgrid300", 16, 3, 0.10, torch.float16, True, 0.01, "cone"),
 ]
 
 
@@ -38,12 +40,14 @@ def graph_of(name):
         return W.knn3d(30000, 10, seed=3)
     if name == "pgrid":
         return W.powergrid(150, 140, 0.02, seed=2)
+    if name == "pgrid300":
+        return W.powergrid(300, 300, 0.02, seed=2)
     return W.mesh3d(24, 22, 20, seed=5, wdist=("lognormal", 0.0, 1.5))
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[4]}-ff{c[5]}-k{c[1]}")
 def test_band_rescoring_gives_fp64_set(S, orc, case):
-    name, k, T, f, storage, ff, band = case
+    name, k, T, f, storage, ff, band, path = case
     g = graph_of(name)
     X0 = W.random_block(g.n, k, 500 + k)
     ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, T, f)
@@ -55,6 +59,11 @@ def test_band_rescoring_gives_fp64_set(S, orc, case):
     assert r["band_above"] + r["band"] >= r["k_sel"]
     assert np.array_equal(got, ref.keep), (int((got != ref.keep).sum()), r)
     assert r["tau"] == ref.levels[0].tau
+    # the FP64 re-smoothing takes the dependency cone unless it exceeds a quarter of the full pass
+    if path == "cone":
+        assert 0 < r["cone_rows"] < T * g.n // 4, r
+    elif path == "full":
+        assert r["cone_rows"] == T * g.n, r
 
 
 def test_low_precision_score_errors_reported(S, orc):
