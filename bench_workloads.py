@@ -169,7 +169,7 @@ def run_mesh(args) -> dict:
         gm = W.mesh3d(40, 40, 40, seed=100 + i, wdist=("lognormal", 0.0, 1.5))
         X0m = W.random_block(gm.n, k, 2000 + i)
         um, vm, wm = to_dev(gm)
-        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :SG.KC]).cuda(), T)
+        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :SG.KC]).cuda())
         pp.raw_nf, pp.raw_ef = SG.features(pp, None)
         s = SG.plain_scores(pp, torch.from_numpy(X0m).cuda(), T)
         graphs.append(pp)
@@ -187,7 +187,7 @@ def run_mesh(args) -> dict:
         gm = W.mesh3d(40, 40, 40, seed=200 + i, wdist=("lognormal", 0.0, 1.5))
         X0m = W.random_block(gm.n, k, 3000 + i)
         um, vm, wm = to_dev(gm)
-        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :SG.KC]).cuda(), T)
+        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :SG.KC]).cuda())
         s = SG.plain_scores(pp, torch.from_numpy(X0m).cuda(), T)
         nc = int(pp.cand.numel())
         chosen = torch.nonzero(S.sfg_select_topk(s, int(math.ceil(f * nc)))[0]).reshape(-1)
@@ -232,9 +232,14 @@ def run_mesh(args) -> dict:
                        device="cuda")
     kc = int(math.ceil(cf * nc))
 
+    ws_g = torch.empty(S.sfg_workspace_bytes(S.OP_LAPLACIAN_CSR, g.n, g.m, 0, torch.float32), dtype=torch.uint8,
+                       device="cuda")
+
+    # the surrogate paths also build the CSR of G (the network aggregates over G)
     def pruned_step():
+        S.sfg_laplacian_csr(g.n, u, v, w32, ws=ws_g, out=G, nnz=2 * g.m)
         S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree, out=H, nnz=nnz)
-        xc = S.sfg_smooth(H, x0c, T, 0.5, storage=torch.bfloat16, final_f32=True)
+        xc = S.sfg_smooth(H, x0c, SG.TC, 0.5, storage=torch.bfloat16, final_f32=True)
         pp = SG.Prepared(g.n, u, v, w32, tree, cand, G, H, xc)
         nf, ef = SG.features(pp, model.norm)
         pred = S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
@@ -246,6 +251,22 @@ def run_mesh(args) -> dict:
         sel2, _ = S.sfg_select_topk(s2, min(ksel, int(ce.numel())), sync=False)
         return cpos, sel2
 
+    # the ranked path takes 15% of the off-tree edges: the fraction at which it
+    # reaches the plain default's median condition number on held-out meshes
+    ksel_r = int(math.ceil(0.15 * nc))
+
+    def ranked_step():
+        S.sfg_laplacian_csr(g.n, u, v, w32, ws=ws_g, out=G, nnz=2 * g.m)
+        S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree, out=H, nnz=nnz)
+        xc = S.sfg_smooth(H, x0c, SG.TC, 0.5, storage=torch.bfloat16, final_f32=True)
+        pp = SG.Prepared(g.n, u, v, w32, tree, cand, G, H, xc)
+        nf, ef = SG.features(pp, model.norm)
+        pred = S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
+        return S.sfg_select_topk(pred, ksel_r, sync=False)
+
+    t_ranked = ev_time(ranked_step, 3)
+    rsel = ranked_step()[0]
+    ranked_overlap = float(rsel.bool()[chosen].float().mean().item())
     t_pruned = ev_time(pruned_step, 3)
     cpos, sel2 = pruned_step()
     r_full = SG.recall(chosen, cpos, nc)
@@ -261,6 +282,8 @@ def run_mesh(args) -> dict:
                        "sweeps": T, "frac": f, "cand_frac": cf, "train": "50 meshes 40^3, 60 epochs"},
             "plain_ms": round(t_plain, 3), "surrogate_pruned_ms": round(t_pruned, 3),
             "surrogate_vs_plain_time": round(t_pruned / t_plain, 3),
+            "surrogate_ranked_ms": round(t_ranked, 3), "ranked_vs_plain_time": round(t_ranked / t_plain, 3),
+            "ranked_frac": 0.15, "ranked_overlap_with_plain_selection": round(ranked_overlap, 4),
             "recall_full_mesh_at_cand_frac": round(r_full, 4), "selected_set_agreement": round(set_agree, 4),
             "recall_heldout_40cubed": recall, "train_loss": [round(hist[0], 4), round(hist[-1], 4)],
             "train_s": round(t_train, 2), "roofline_f32_sweep_tree": roof}

@@ -12,13 +12,17 @@
 // block stacks the self weights, the neighbour weights and the bias, so a
 // weight gradient is one product U^T dP of the layer's input [x | a | 1].
 //
-// Kernels: the aggregations reuse the smoothing sweep (omega = 1); dense
-// layers and the edge head keep their weights in LDS and give each thread
-// one node or edge (32-wide FP32 accumulators); backward sends per-edge
-// gradients to nodes through an incidence CSR in ascending edge order and
-// reduces weight gradients by fixed-shape block partials: no FP atomics, so
-// training is deterministic.  Inference stores activations in BF16 (FP32
-// arithmetic); training runs in FP32.
+// Kernels: the aggregations reuse the smoothing sweep (omega = 1).
+// Inference (BF16 activations) runs the dense layers and the edge head on the
+// matrix cores: a wavefront takes 32 nodes or edges, builds their [x | a | 1]
+// or z rows as BF16 MFMA operands (K padded to a multiple of 8), multiplies
+// by the BF16 weights with v_mfma_f32_32x32x8_bf16 into FP32 accumulators,
+// and applies the ReLU (and the head's last dot product) in FP32.  Training
+// runs in FP32 on the vector units: weights in LDS, one node or edge per
+// thread, 32-wide accumulators; backward sends per-edge gradients to nodes
+// through an incidence CSR in ascending edge order and reduces weight
+// gradients by fixed-shape block partials: no FP atomics, so training is
+// deterministic.
 #include <cmath>
 #include <vector>
 
@@ -208,6 +212,142 @@ __global__ __launch_bounds__(256) void k_head_fwd(int64_t ne, const int32_t *__r
         out = __builtin_fmaf(fmaxf(g[j], 0.f), s4[j], out);
     }
     pred[i] = out;
+}
+
+// ------------------------------------------------------------------ inference on the matrix cores
+//
+// v_mfma_f32_32x32x8_bf16 (one 32 x 32 x 8 block per wavefront), lane l:
+//   A (32 x 8):  row l % 32, columns 4 * (l / 32) + 0..3
+//   B (8 x 32):  column l % 32, rows 4 * (l / 32) + 0..3
+//   D (32 x 32): column l % 32, rows 8 * (r / 4) + 4 * (l / 32) + r % 4, r = 0..15
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ short bf16_bits(float x) {
+    const __hip_bfloat16 b = cvt<__hip_bfloat16>(x);
+    short r;
+    __builtin_memcpy(&r, &b, sizeof(r));
+    return r;
+}
+
+__device__ __forceinline__ float bits_float(short r) {
+    __hip_bfloat16 b;
+    __builtin_memcpy(&b, &r, sizeof(r));
+    return cvt<float>(b);
+}
+
+// four consecutive values as BF16 operand bits
+__device__ __forceinline__ bf16x4 load4(const float *p) {
+    const float4 f = *reinterpret_cast<const float4 *>(p);
+    return bf16x4{bf16_bits(f.x), bf16_bits(f.y), bf16_bits(f.z), bf16_bits(f.w)};
+}
+__device__ __forceinline__ bf16x4 load4(const __hip_bfloat16 *p) {
+    return *reinterpret_cast<const bf16x4 *>(p);
+}
+
+// B operands of a (rows x 32) FP32 weight block, K padded with zeros
+template <int NCH>
+__device__ __forceinline__ void load_weights(const float *__restrict__ W, int rows, int half, int col,
+                                             bf16x4 (&wb)[NCH]) {
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int k = 8 * t + 4 * half + i;
+            wb[t][i] = bf16_bits(k < rows ? W[k * kH + col] : 0.f);
+        }
+    }
+}
+
+// h = relu([x | a | 1] W) for 32 nodes per wavefront; BF16 output.
+template <typename TIN, int FIN>
+__global__ __launch_bounds__(256) void k_dense_mfma(int64_t n, const TIN *__restrict__ x, const TIN *__restrict__ a,
+                                                    const float *__restrict__ W, __hip_bfloat16 *__restrict__ h) {
+    static_assert(FIN % 8 == 0, "feature width must be a multiple of 8");
+    constexpr int NX = FIN / 8, NCH = 2 * NX + 1;
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31;
+    bf16x4 wb[NCH];
+    load_weights<NCH>(W, 2 * FIN + 1, half, col, wb);
+    const int64_t base = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32;
+    if (base >= n) return;
+    const int64_t row = base + col;
+    const bool valid = row < n;
+    const bf16x4 zero = {0, 0, 0, 0};
+    f32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+        const bf16x4 av = valid ? load4(x + row * FIN + 8 * t + 4 * half) : zero;
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, wb[t], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+        const bf16x4 av = valid ? load4(a + row * FIN + 8 * t + 4 * half) : zero;
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, wb[NX + t], acc, 0, 0, 0);
+    }
+    {   // the bias column: k = 2 FIN
+        const bf16x4 av = (valid && half == 0) ? bf16x4{bf16_bits(1.f), 0, 0, 0} : zero;
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, wb[2 * NX], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int64_t node = base + 8 * (r / 4) + 4 * half + (r % 4);
+        if (node < n) h[node * kH + col] = cvt<__hip_bfloat16>(fmaxf(acc[r], 0.f));
+    }
+}
+
+// yhat_e = relu(z_e W3) . w4[0:32] + w4[32] for 32 candidate edges per wavefront.
+__global__ __launch_bounds__(256) void k_head_mfma(int64_t ne, const int32_t *__restrict__ cand,
+                                                   const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                                                   const __hip_bfloat16 *__restrict__ h,
+                                                   const float *__restrict__ ef, const float *__restrict__ W3,
+                                                   const float *__restrict__ w4, float *__restrict__ pred) {
+    constexpr int NCH = (kZ1 + 7) / 8;      // 9: |hp - hq| (4), hp * hq (4), edge features + bias (1)
+    static_assert(kH == 32 && kE == 4 && NCH == 9, "head layout");
+    __shared__ float red[4][32][33];
+    const int lane = threadIdx.x & 63, half = lane >> 5, col = lane & 31, wv = threadIdx.x >> 6;
+    bf16x4 wb[NCH];
+    load_weights<NCH>(W3, kZ1, half, col, wb);
+    const float w4c = w4[col];
+    const int64_t base = ((int64_t)blockIdx.x * 4 + wv) * 32;
+    if (base >= ne) return;
+    const int64_t i = base + col;
+    const bool valid = i < ne;
+    const int32_t e = valid ? (cand ? cand[i] : (int32_t)i) : 0;
+    const __hip_bfloat16 *hp = h + (int64_t)(valid ? u[e] : 0) * kH;
+    const __hip_bfloat16 *hq = h + (int64_t)(valid ? v[e] : 0) * kH;
+    const bf16x4 zero = {0, 0, 0, 0};
+    f32x16 acc = {};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        bf16x4 d = zero, p = zero;
+        if (valid) {
+            const bf16x4 ra = load4(hp + 8 * t + 4 * half), rb = load4(hq + 8 * t + 4 * half);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float fa = bits_float(ra[q]), fb = bits_float(rb[q]);
+                d[q] = bf16_bits(fabsf(fa - fb));
+                p[q] = bf16_bits(fa * fb);
+            }
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(d, wb[t], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(p, wb[4 + t], acc, 0, 0, 0);
+    }
+    {   // k = 64..67 edge features (lanes of the first half), k = 68 bias
+        bf16x4 z = zero;
+        if (valid) z = half == 0 ? load4(ef + i * kE) : bf16x4{bf16_bits(1.f), 0, 0, 0};
+        acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(z, wb[8], acc, 0, 0, 0);
+    }
+    // the last layer: each lane scales its column, then lane m < 32 adds row m
+    // in column order
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[wv][8 * (r / 4) + 4 * half + (r % 4)][col] = fmaxf(acc[r], 0.f) * w4c;
+    __builtin_amdgcn_wave_barrier();
+    if (half == 0 && valid) {
+        float o = w4[kH];
+        for (int j = 0; j < kH; ++j) o += red[wv][col][j];
+        pred[i] = o;
+    }
 }
 
 // ------------------------------------------------------------------ backward
@@ -550,8 +690,8 @@ extern "C" sfg_status sfg_mpnn_forward(const sfg_csr *G, const float *params, co
             hipLaunchKernelGGL((k_dense_fwd<float, float, kF>), gn, b, 0, s, n, node_feat, a1, params + kOffW1,
                                (float *)p.h1, nullptr, nullptr);
         else
-            hipLaunchKernelGGL((k_dense_fwd<float, __hip_bfloat16, kF>), gn, b, 0, s, n, node_feat, a1,
-                               params + kOffW1, (__hip_bfloat16 *)p.h1, nullptr, nullptr);
+            hipLaunchKernelGGL((k_dense_mfma<float, kF>), dim3(grid_for(n, 128)), b, 0, s, n, node_feat, a1,
+                               params + kOffW1, (__hip_bfloat16 *)p.h1);
         SFG_LAUNCH_CHECK();
         // layer 2
         spmm_rownorm(G, kH, act, p.h1, p.a, s);
@@ -559,9 +699,9 @@ extern "C" sfg_status sfg_mpnn_forward(const sfg_csr *G, const float *params, co
             hipLaunchKernelGGL((k_dense_fwd<float, float, kH>), gn, b, 0, s, n, (const float *)p.h1,
                                (const float *)p.a, params + kOffW2, (float *)p.h2, nullptr, nullptr);
         else
-            hipLaunchKernelGGL((k_dense_fwd<__hip_bfloat16, __hip_bfloat16, kH>), gn, b, 0, s, n,
+            hipLaunchKernelGGL((k_dense_mfma<__hip_bfloat16, kH>), dim3(grid_for(n, 128)), b, 0, s, n,
                                (const __hip_bfloat16 *)p.h1, (const __hip_bfloat16 *)p.a, params + kOffW2,
-                               (__hip_bfloat16 *)p.h2, nullptr, nullptr);
+                               (__hip_bfloat16 *)p.h2);
         SFG_LAUNCH_CHECK();
         if (ne == 0) return;
         SFG_REQUIRE(u && v && edge_feat && pred, SFG_EINVAL, "mpnn_forward: null pointer");
@@ -570,9 +710,8 @@ extern "C" sfg_status sfg_mpnn_forward(const sfg_csr *G, const float *params, co
             hipLaunchKernelGGL(k_head_fwd<float>, ge, b, 0, s, ne, cand, u, v, (const float *)p.h2, edge_feat,
                                params + kOffW3, params + kOffW4, pred, nullptr, nullptr);
         else
-            hipLaunchKernelGGL(k_head_fwd<__hip_bfloat16>, ge, b, 0, s, ne, cand, u, v,
-                               (const __hip_bfloat16 *)p.h2, edge_feat, params + kOffW3, params + kOffW4, pred,
-                               nullptr, nullptr);
+            hipLaunchKernelGGL(k_head_mfma, dim3(grid_for(ne, 128)), b, 0, s, ne, cand, u, v,
+                               (const __hip_bfloat16 *)p.h2, edge_feat, params + kOffW3, params + kOffW4, pred);
         SFG_LAUNCH_CHECK();
     });
 }

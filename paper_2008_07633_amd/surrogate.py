@@ -4,9 +4,9 @@ The network and its kernels are in ``csrc/mpnn.hip`` (C ABI ``sfg_mpnn_*``).
 This module drives them.  It only marshals and orchestrates; every numeric step runs
 in libsfg:
   * a cheap embedding -- the first ``KC`` of the method's own random
-    vectors, smoothed on the spanning tree with BF16 storage and an FP32
-    last iterate -- feeds the features (sharing the vectors makes the cheap
-    scores partial sums of the exact ones);
+    vectors, smoothed ``TC`` times on the spanning tree with BF16 storage and
+    an FP32 last iterate -- feeds the features (sharing the vectors makes the
+    cheap scores close relatives of the exact ones);
   * training targets are the plain method's own scores (``K`` vectors, ``T``
     sweeps, FP32), as standardised logs;
   * inference predicts every off-tree edge, keeps the top ``cand_frac`` as
@@ -31,6 +31,7 @@ from . import sfg as S
 
 VERSION = 1
 KC = 4                 # vectors of the cheap embedding
+TC = 10                # sweeps of the cheap embedding (half of the plain method's 20)
 N_NODE_FEAT, N_EDGE_FEAT = 8, 4
 
 
@@ -110,9 +111,10 @@ class Prepared:
     raw_ef: Optional[torch.Tensor] = None
 
 
-def prepare(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0c: torch.Tensor, sweeps: int,
+def prepare(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0c: torch.Tensor, sweeps: int = TC,
             tree: Optional[torch.Tensor] = None) -> Prepared:
-    """Tree, CSRs of G and of the tree, and the cheap embedding from x0c (n x KC, FP64)."""
+    """Tree, CSRs of G and of the tree, and the cheap embedding from x0c (n x KC,
+    FP64) smoothed ``sweeps`` times on the tree (the model is trained for TC)."""
     w32 = w.float()
     if tree is None:
         tree, comps = S.sfg_spanning_tree(n, u, v, w)
@@ -245,7 +247,7 @@ def sparsify_pruned(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x
                                                                  storage=storage))
         r = rep[0]
         return PrunedResult(keep, True, str(e), int(r["n_cand"]), int(r["n_cand"]), int(r["k_sel"]))
-    pp = prepare(n, u, v, w, x0[:, :KC].contiguous(), sweeps)
+    pp = prepare(n, u, v, w, x0[:, :KC].contiguous())
     cand_pos, _ = prune(mdl, pp, cand_frac)
     cand_e = pp.cand[cand_pos.long()].contiguous()
     X = S.sfg_smooth(pp.T, x0, sweeps, 0.5, storage=storage)
@@ -257,3 +259,29 @@ def sparsify_pruned(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x
     keep = pp.tree.clone()
     keep[cand_e[sel.bool()].long()] = 2
     return PrunedResult(keep, False, "", n_cand, int(cand_e.numel()), k_take)
+
+
+def sparsify_ranked(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: torch.Tensor, model,
+                    sweeps: int, frac: float, storage=torch.float32) -> PrunedResult:
+    """Spanning tree + the top ``frac`` of the off-tree edges ranked by the
+    surrogate's prediction alone: no K-vector smoothing and no exact scoring,
+    only the cheap ``KC``-vector embedding, the features and one inference.
+    ``model`` is a Model or a path; if it cannot be used the plain
+    single-level path runs instead (``storage`` is its precision)."""
+    try:
+        mdl = load(model, u.device) if isinstance(model, str) else model
+        if not bool(torch.isfinite(mdl.params).all().item()):
+            raise SurrogateInvalid("surrogate parameters are not finite")
+    except SurrogateInvalid as e:
+        keep, rep = S.sfg_sparsify(n, u, v, w, x0, S.make_params(k=int(x0.shape[1]), sweeps=sweeps, frac=frac,
+                                                                 storage=storage))
+        r = rep[0]
+        return PrunedResult(keep, True, str(e), int(r["n_cand"]), int(r["n_cand"]), int(r["k_sel"]))
+    pp = prepare(n, u, v, w, x0[:, :KC].contiguous())
+    pred = predict(mdl, pp)
+    n_cand = int(pp.cand.numel())
+    k_sel = int(math.ceil(frac * n_cand))
+    sel, _ = S.sfg_select_topk(pred, k_sel)
+    keep = pp.tree.clone()
+    keep[pp.cand[sel.bool()].long()] = 2
+    return PrunedResult(keep, False, "", n_cand, 0, k_sel)

@@ -116,7 +116,7 @@ def test_adam_matches_oracle(S):
 def _mesh_case(S, SG, seed, side):
     g = W.mesh3d(side, side, side, seed=seed, wdist=("lognormal", 0.0, 1.5))
     X0 = W.random_block(g.n, 16, 500 + seed)
-    pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0[:, :SG.KC]), 20)
+    pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0[:, :SG.KC]))
     pp.raw_nf, pp.raw_ef = SG.features(pp, None)
     return g, X0, pp, SG.plain_scores(pp, dev(X0), 20)
 
