@@ -64,6 +64,48 @@ __device__ __forceinline__ float ld<float>(const float *p) {
 
 // ------------------------------------------------------------------ features
 
+// |x_p - x_q|^2 over the kc cheap vectors (KC > 0: kc = KC, one vector load per row)
+template <int KC>
+__device__ __forceinline__ float dist2(const float *__restrict__ xc, int32_t kc, const float *xp, int64_t q) {
+    float d2 = 0.f;
+    if constexpr (KC == 4) {
+        const float4 b = *reinterpret_cast<const float4 *>(xc + q * 4);
+        const float bq[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float d = xp[c] - bq[c];
+            d2 = __builtin_fmaf(d, d, d2);
+        }
+    } else {
+        const float *xq = xc + q * kc;
+        for (int c = 0; c < kc; ++c) {
+            const float d = xp[c] - xq[c];
+            d2 = __builtin_fmaf(d, d, d2);
+        }
+    }
+    return d2;
+}
+
+// sum_j w_j |x_p - x_col[j]|^2 over a row, in entry order, two entries in flight
+template <int KC>
+__device__ __forceinline__ float row_energy(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                            const float *__restrict__ val, const float *__restrict__ xc, int32_t kc,
+                                            const float *xp, int64_t p) {
+    float e = 0.f;
+    const int32_t j0 = rp[p], j1 = rp[p + 1];
+    int32_t j = j0;
+    for (; j + 2 <= j1; j += 2) {
+        const int64_t q0 = col[j], q1 = col[j + 1];
+        const float w0 = val[j], w1 = val[j + 1];
+        const float d0 = dist2<KC>(xc, kc, xp, q0), d1 = dist2<KC>(xc, kc, xp, q1);
+        e = __builtin_fmaf(w0, d0, e);
+        e = __builtin_fmaf(w1, d1, e);
+    }
+    if (j < j1) e = __builtin_fmaf(val[j], dist2<KC>(xc, kc, xp, col[j]), e);
+    return e;
+}
+
+template <int KC>
 __global__ void k_node_feat(int64_t n, const int32_t *__restrict__ grp, const int32_t *__restrict__ gcol,
                             const float *__restrict__ gval, const float *__restrict__ gdeg,
                             const int32_t *__restrict__ trp, const int32_t *__restrict__ tcol,
@@ -71,28 +113,20 @@ __global__ void k_node_feat(int64_t n, const int32_t *__restrict__ grp, const in
                             const float *__restrict__ xc, int32_t kc, const float *__restrict__ norm, float *nf) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const float *xp = xc + p * kc;
+    float xp[KC > 0 ? KC : 64];
+    if constexpr (KC == 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(xc + p * 4);
+        xp[0] = a.x;
+        xp[1] = a.y;
+        xp[2] = a.z;
+        xp[3] = a.w;
+    } else {
+        for (int c = 0; c < kc; ++c) xp[c] = xc[p * kc + c];
+    }
     float amp = 0.f;
-    for (int c = 0; c < kc; ++c) amp = __builtin_fmaf(xp[c], xp[c], amp);
-    float eg = 0.f, et = 0.f;
-    for (int32_t j = grp[p]; j < grp[p + 1]; ++j) {
-        const float *xq = xc + (int64_t)gcol[j] * kc;
-        float d2 = 0.f;
-        for (int c = 0; c < kc; ++c) {
-            const float d = xp[c] - xq[c];
-            d2 = __builtin_fmaf(d, d, d2);
-        }
-        eg = __builtin_fmaf(gval[j], d2, eg);
-    }
-    for (int32_t j = trp[p]; j < trp[p + 1]; ++j) {
-        const float *xq = xc + (int64_t)tcol[j] * kc;
-        float d2 = 0.f;
-        for (int c = 0; c < kc; ++c) {
-            const float d = xp[c] - xq[c];
-            d2 = __builtin_fmaf(d, d, d2);
-        }
-        et = __builtin_fmaf(tval[j], d2, et);
-    }
+    for (int c = 0; c < (KC > 0 ? KC : kc); ++c) amp = __builtin_fmaf(xp[c], xp[c], amp);
+    const float eg = row_energy<KC>(grp, gcol, gval, xc, kc, xp, p);
+    const float et = row_energy<KC>(trp, tcol, tval, xc, kc, xp, p);
     float f[kF];
     f[0] = 1.f;
     f[1] = logf(gdeg[p]);
@@ -102,14 +136,19 @@ __global__ void k_node_feat(int64_t n, const int32_t *__restrict__ grp, const in
     f[5] = logf(amp + kTiny);
     f[6] = logf(eg / gdeg[p] + kTiny);
     f[7] = logf(et / tdeg[p] + kTiny);
+    float o[kF];
 #pragma unroll
-    for (int i = 0; i < kF; ++i) {
-        float v = f[i];
-        if (norm && i > 0) v = (v - norm[i]) * norm[kF + i];
-        nf[p * kF + i] = v;
+    for (int i = 0; i < kF; ++i) o[i] = (norm && i > 0) ? (f[i] - norm[i]) * norm[kF + i] : f[i];
+    if constexpr (KC == 4) {
+        *reinterpret_cast<float4 *>(nf + p * kF) = make_float4(o[0], o[1], o[2], o[3]);
+        *reinterpret_cast<float4 *>(nf + p * kF + 4) = make_float4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+        for (int i = 0; i < kF; ++i) nf[p * kF + i] = o[i];
     }
 }
 
+template <int KC>
 __global__ void k_edge_feat(int64_t ne, const int32_t *__restrict__ cand, const int32_t *__restrict__ u,
                             const int32_t *__restrict__ v, const float *__restrict__ w, const float *__restrict__ xc,
                             int32_t kc, const float *__restrict__ tdeg, const float *__restrict__ norm, float *ef) {
@@ -117,11 +156,17 @@ __global__ void k_edge_feat(int64_t ne, const int32_t *__restrict__ cand, const 
     if (i >= ne) return;
     const int32_t e = cand ? cand[i] : (int32_t)i;
     const int32_t p = u[e], q = v[e];
-    float d2 = 0.f;
-    for (int c = 0; c < kc; ++c) {
-        const float d = xc[(int64_t)p * kc + c] - xc[(int64_t)q * kc + c];
-        d2 = __builtin_fmaf(d, d, d2);
+    float xp[KC > 0 ? KC : 64];
+    if constexpr (KC == 4) {
+        const float4 a = *reinterpret_cast<const float4 *>(xc + (int64_t)p * 4);
+        xp[0] = a.x;
+        xp[1] = a.y;
+        xp[2] = a.z;
+        xp[3] = a.w;
+    } else {
+        for (int c = 0; c < kc; ++c) xp[c] = xc[(int64_t)p * kc + c];
     }
+    const float d2 = dist2<KC>(xc, kc, xp, q);
     const float lp = logf(tdeg[p]), lq = logf(tdeg[q]);
     float f[kE] = {logf(w[e]), logf(w[e] * d2 + kTiny), fminf(lp, lq), fmaxf(lp, lq)};
 #pragma unroll
@@ -655,13 +700,24 @@ extern "C" sfg_status sfg_mpnn_features(const sfg_csr *G, const sfg_csr *T, cons
         SFG_REQUIRE(xc && kc >= 1 && kc <= 64 && node_feat, SFG_EINVAL, "mpnn_features: bad block");
         SFG_REQUIRE(ne >= 0 && (ne == 0 || (u && v && w && edge_feat)), SFG_EINVAL, "mpnn_features: null pointer");
         const int64_t n = G->n;
-        hipLaunchKernelGGL(k_node_feat, dim3(grid_for(n, 256)), dim3(256), 0, s, n, G->rowptr, G->col,
-                           (const float *)G->val, (const float *)G->deg, T->rowptr, T->col, (const float *)T->val,
-                           (const float *)T->deg, xc, kc, norm, node_feat);
+        // the 4-vector cheap embedding with 16-byte aligned rows takes vector loads
+        const bool v4 = kc == 4 && (uintptr_t)xc % 16 == 0 && (uintptr_t)node_feat % 16 == 0;
+        if (v4)
+            hipLaunchKernelGGL(k_node_feat<4>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, G->rowptr, G->col,
+                               (const float *)G->val, (const float *)G->deg, T->rowptr, T->col,
+                               (const float *)T->val, (const float *)T->deg, xc, kc, norm, node_feat);
+        else
+            hipLaunchKernelGGL(k_node_feat<0>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, G->rowptr, G->col,
+                               (const float *)G->val, (const float *)G->deg, T->rowptr, T->col,
+                               (const float *)T->val, (const float *)T->deg, xc, kc, norm, node_feat);
         SFG_LAUNCH_CHECK();
         if (ne > 0) {
-            hipLaunchKernelGGL(k_edge_feat, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, cand, u, v, w, xc, kc,
-                               (const float *)T->deg, norm, edge_feat);
+            if (v4)
+                hipLaunchKernelGGL(k_edge_feat<4>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, cand, u, v, w, xc,
+                                   kc, (const float *)T->deg, norm, edge_feat);
+            else
+                hipLaunchKernelGGL(k_edge_feat<0>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, cand, u, v, w, xc,
+                                   kc, (const float *)T->deg, norm, edge_feat);
             SFG_LAUNCH_CHECK();
         }
     });
