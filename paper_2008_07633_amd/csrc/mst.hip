@@ -10,10 +10,7 @@
 //   2. each component hooks onto the component across its best edge; a pair
 //      that chose the same edge is rooted at the smaller id (longer cycles
 //      cannot occur under a total order);
-//   3. pointer jumping flattens the hooks; nodes take their new roots;
-//   4. once at least half of the scanned edge list has become internal to
-//      components, the ids of the edges still joining two components are
-//      compacted (in ascending order), so later rounds scan only those.
+//   3. pointer jumping flattens the hooks; nodes take their new roots.
 // Rounds repeat until no component has an outgoing edge.  Only integer
 // atomics are used, so the result does not depend on scheduling.
 #include "common.hpp"
@@ -40,24 +37,16 @@ __device__ __forceinline__ uint64_t wkey(TW w) {
     return k;
 }
 
-// ids == nullptr: the list is 0..m-1.  live[0] += edges of the list that join
-// two components.
 template <typename TW>
-__global__ __launch_bounds__(256) void k_mst_best_w(int64_t m, const int32_t *__restrict__ ids,
-                                                    const int32_t *__restrict__ u, const int32_t *__restrict__ v,
-                                                    const TW *__restrict__ w, const int32_t *__restrict__ comp,
-                                                    uint64_t *best_w, int32_t *live) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t e = 0, a = 0, b = 0;
-    if (i < m) {
-        e = ids ? ids[i] : (int32_t)i;
-        a = comp[u[e]];
-        b = comp[v[e]];
-    }
-    const bool join = i < m && a != b;
-    const int nj = __syncthreads_count(join);
-    if (threadIdx.x == 0 && nj) atomicAdd(live, nj);
-    if (!join) return;
+__global__ void k_mst_best_w(int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                             const TW *__restrict__ w, const uint8_t *__restrict__ allowed,
+                             const int32_t *__restrict__ comp, uint64_t *best_w, int32_t *live) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    if (allowed && !allowed[e]) return;
+    const int32_t a = comp[u[e]], b = comp[v[e]];
+    if (a == b) return;
+    if (*live == 0) *live = 1;
     const uint64_t k = wkey(w[e]);
     // read first: on hub components most edges lose, and skipping their
     // atomics removes the contention (the maximum is still exact)
@@ -66,36 +55,18 @@ __global__ __launch_bounds__(256) void k_mst_best_w(int64_t m, const int32_t *__
 }
 
 template <typename TW>
-__global__ void k_mst_best_e(int64_t m, const int32_t *__restrict__ ids, const int32_t *__restrict__ u,
-                             const int32_t *__restrict__ v, const TW *__restrict__ w,
+__global__ void k_mst_best_e(int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                             const TW *__restrict__ w, const uint8_t *__restrict__ allowed,
                              const int32_t *__restrict__ comp, const uint64_t *__restrict__ best_w,
                              int32_t *best_e) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const int32_t e = ids ? ids[i] : (int32_t)i;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    if (allowed && !allowed[e]) return;
     const int32_t a = comp[u[e]], b = comp[v[e]];
     if (a == b) return;
     const uint64_t k = wkey(w[e]);
-    if (k == best_w[a] && e < best_e[a]) atomicMin(&best_e[a], e);
-    if (k == best_w[b] && e < best_e[b]) atomicMin(&best_e[b], e);
-}
-
-// keep[i]: edge i of the list is allowed (first pass) or still joins two
-// components (after a round)
-__global__ void k_mst_keep(int64_t m, const int32_t *__restrict__ ids, const uint8_t *__restrict__ allowed,
-                           const int32_t *__restrict__ u, const int32_t *__restrict__ v,
-                           const int32_t *__restrict__ comp, int32_t *keep) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    const int32_t e = ids ? ids[i] : (int32_t)i;
-    keep[i] = allowed ? (allowed[e] != 0) : (comp[u[e]] != comp[v[e]]);
-}
-
-__global__ void k_mst_compact(int64_t m, const int32_t *__restrict__ ids, const int32_t *__restrict__ keep,
-                              const int32_t *__restrict__ pos, int32_t *out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= m || !keep[i]) return;
-    out[pos[i]] = ids ? ids[i] : (int32_t)i;
+    if (k == best_w[a] && (int32_t)e < best_e[a]) atomicMin(&best_e[a], (int32_t)e);
+    if (k == best_w[b] && (int32_t)e < best_e[b]) atomicMin(&best_e[b], (int32_t)e);
 }
 
 // Roots hook across their best edge and mark it as a tree edge.
@@ -159,52 +130,28 @@ int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t 
     int32_t *best_e = A.alloc<int32_t>(n + 1);
     uint64_t *best_w = A.alloc<uint64_t>(n + 1);
     int32_t *flags = A.alloc<int32_t>(4);
-    int32_t *ids[2] = {A.alloc<int32_t>(m + 1), A.alloc<int32_t>(m + 1)};
-    int32_t *keep = A.alloc<int32_t>(m + 1);
-    int32_t *pos = A.alloc<int32_t>(m + 1);
-    int32_t *scan = A.alloc<int32_t>(scan_scratch_ints(m + 1));
-    const dim3 gn(grid_for(n, 256)), b(256);
+    const dim3 gn(grid_for(n, 256)), gm(grid_for(m, 256)), b(256);
     hipLaunchKernelGGL(k_mst_init, gn, b, 0, s, n, comp, best_w, best_e);
     SFG_LAUNCH_CHECK();
     if (m > 0) fill_u8(in_tree, m, 0, s);
-    // the live edge list: nullptr = all edges 0..m-1
-    const int32_t *live = nullptr;
-    int64_t nlive = m;
-    int cur = 0;
-    auto compact = [&](const uint8_t *allow) {
-        hipLaunchKernelGGL(k_mst_keep, dim3(grid_for(nlive, 256)), b, 0, s, nlive, live, allow, u, v, comp, keep);
-        SFG_LAUNCH_CHECK();
-        exclusive_scan_i32(keep, pos, nlive, scan, s);
-        hipLaunchKernelGGL(k_mst_compact, dim3(grid_for(nlive, 256)), b, 0, s, nlive, live, keep, pos, ids[cur]);
-        SFG_LAUNCH_CHECK();
-        int32_t cnt = 0;
-        SFG_HIP(hipMemcpyAsync(&cnt, pos + nlive, sizeof(cnt), hipMemcpyDeviceToHost, s));
-        SFG_HIP(hipStreamSynchronize(s));
-        live = ids[cur];
-        cur ^= 1;
-        nlive = cnt;
-    };
-    if (allowed && m > 0) compact(allowed);
-    for (int round = 0; nlive > 0; ++round) {
+    for (int round = 0; m > 0; ++round) {
         SFG_REQUIRE(round < 64, SFG_EHIP, "spanning_tree: too many rounds");
-        const dim3 gm(grid_for(nlive, 256));
         fill_i32(flags, 1, 0, s);
         if (wt == SFG_F64) {
-            hipLaunchKernelGGL(k_mst_best_w<double>, gm, b, 0, s, nlive, live, u, v, (const double *)w, comp, best_w,
+            hipLaunchKernelGGL(k_mst_best_w<double>, gm, b, 0, s, m, u, v, (const double *)w, allowed, comp, best_w,
                                flags);
             SFG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_mst_best_e<double>, gm, b, 0, s, nlive, live, u, v, (const double *)w, comp, best_w,
+            hipLaunchKernelGGL(k_mst_best_e<double>, gm, b, 0, s, m, u, v, (const double *)w, allowed, comp, best_w,
                                best_e);
         } else {
-            hipLaunchKernelGGL(k_mst_best_w<float>, gm, b, 0, s, nlive, live, u, v, (const float *)w, comp, best_w,
+            hipLaunchKernelGGL(k_mst_best_w<float>, gm, b, 0, s, m, u, v, (const float *)w, allowed, comp, best_w,
                                flags);
             SFG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_mst_best_e<float>, gm, b, 0, s, nlive, live, u, v, (const float *)w, comp, best_w,
+            hipLaunchKernelGGL(k_mst_best_e<float>, gm, b, 0, s, m, u, v, (const float *)w, allowed, comp, best_w,
                                best_e);
         }
         SFG_LAUNCH_CHECK();
-        const int32_t joining = read_flag(flags, s);
-        if (joining == 0) break;     // no component has an outgoing edge
+        if (read_flag(flags, s) == 0) break;     // no component has an outgoing edge
         hipLaunchKernelGGL(k_mst_hook, gn, b, 0, s, n, u, v, comp, best_e, parent, in_tree);
         SFG_LAUNCH_CHECK();
         for (int it = 0;; ++it) {
@@ -216,7 +163,6 @@ int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t 
         }
         hipLaunchKernelGGL(k_mst_relabel, gn, b, 0, s, n, comp, parent, best_w, best_e);
         SFG_LAUNCH_CHECK();
-        if (2 * (int64_t)joining <= nlive) compact(nullptr);
     }
     fill_i32(flags + 2, 1, 0, s);
     hipLaunchKernelGGL(k_mst_roots, gn, b, 0, s, n, comp, flags + 2);
