@@ -250,10 +250,11 @@ class Result:
     X: Optional[np.ndarray] = None  # smoothed block of the finest scoring pass
 
 
-def score_level(n, u, v, w, base_mask, X0, k_sweeps, omega, frac, embed="sparsifier"):
+def score_level(n, u, v, w, base_mask, X0, k_sweeps, omega, frac, embed="sparsifier", k_take=None):
     """One round of Alg. 1's embed / score / include-top-few on a graph whose
     current sparsifier is ``base_mask``.  ``embed`` selects the smoothed graph:
-    'sparsifier' (eigenvectors of L_P, Sec. 3.5) or 'graph' (Alg. 1, embed G)."""
+    'sparsifier' (eigenvectors of L_P, Sec. 3.5) or 'graph' (Alg. 1, embed G).
+    ``k_take`` (default ceil(frac * candidates)) is how many edges are added."""
     u, v, w = _i32(u), _i32(v), _f64(w)
     base_mask = np.asarray(base_mask, dtype=bool)
     if embed == "sparsifier":
@@ -267,7 +268,7 @@ def score_level(n, u, v, w, base_mask, X0, k_sweeps, omega, frac, embed="sparsif
     X = smooth(H, Xc, k_sweeps, omega)
     cand = np.nonzero(~base_mask)[0].astype(np.int32)
     s = edge_scores(X, u[cand], v[cand], w[cand])
-    k = ksel(frac, cand.shape[0])
+    k = ksel(frac, cand.shape[0]) if k_take is None else int(k_take)
     pos, tau = select_topk(s, cand, k)
     lr = LevelResult(n, u.shape[0], int(cand.shape[0]), k, tau, cand, s, cand[pos])
     return lr, X
@@ -282,6 +283,33 @@ def sparsify_single(n, u, v, w, X0, sweeps, frac, omega=0.5, embed="sparsifier")
     keep = intree.astype(np.uint8)
     keep[lr.chosen] = 2
     return Result(keep, [lr], X)
+
+
+def round_quotas(k_total, rounds):
+    """Near-equal shares of k_total over ``rounds`` rounds (they sum to k_total)."""
+    return [k_total * (r + 1) // rounds - k_total * r // rounds for r in range(rounds)]
+
+
+def sparsify_rounds(n, u, v, w, X0s, rounds, sweeps, frac, omega=0.5, embed="sparsifier") -> Result:
+    """Multi-round densification of the single-level method: the budget
+    k_sel = ceil(f * off-tree edges) is split into ``rounds`` near-equal quotas;
+    round r re-embeds the block X0s[r] on the current sparsifier (the tree plus
+    the edges added so far, whose Laplacian the perturbation analysis of
+    Sec. 3.5 is about), scores the edges outside it and adds its quota's top
+    edges.  rounds = 1 is sparsify_single."""
+    intree, comps = max_spanning_forest(n, u, v, w)
+    if comps != 1:
+        raise ValueError("graph is not connected")
+    base = intree.astype(bool)
+    keep = intree.astype(np.uint8)
+    k_total = ksel(frac, int((~base).sum()))
+    results, X = [], None
+    for r, q in enumerate(round_quotas(k_total, rounds)):
+        lr, X = score_level(n, u, v, w, base, X0s[r], sweeps, omega, frac, embed, k_take=q)
+        keep[lr.chosen] = 2
+        base[lr.chosen] = True
+        results.append(lr)
+    return Result(keep, results, X)
 
 
 @dataclass

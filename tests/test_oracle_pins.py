@@ -436,3 +436,74 @@ def test_multilevel_structure(orc):
     lr = r.levels[-1]
     assert (keep == 2).sum() == lr.k_sel
     assert (keep > 0).sum() < g.m
+
+
+# --------------------------------------------------------------------------- multi-round densification
+
+def test_round_quotas(orc):
+    for k_total in (0, 1, 7, 199, 103797):
+        for rounds in (1, 2, 3, 5, 16):
+            q = orc.round_quotas(k_total, rounds)
+            assert len(q) == rounds and sum(q) == k_total
+            assert max(q) - min(q) <= 1
+
+
+def test_rounds_one_is_single_pass(orc):
+    g = W.powergrid(30, 25, 0.02, seed=91)
+    X0 = W.random_block(g.n, 8, 92)
+    a = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, 6, 0.1)
+    b = orc.sparsify_rounds(g.n, g.u, g.v, g.w, [X0], 1, 6, 0.1)
+    assert np.array_equal(a.keep, b.keep)
+    assert a.levels[0].tau == b.levels[0].tau
+
+
+def _dense_rounds(n, u, v, w, X0s, rounds, sweeps, frac, omega):
+    """Brute force with dense matrices: Kruskal by sorting, the sweep as a
+    matrix product, scores from the dense block, top-k by a full sort."""
+    order = sorted(range(len(w)), key=lambda e: (-w[e], e))
+    parent = list(range(n))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    inP = np.zeros(len(w), bool)
+    for e in order:
+        a, b = find(u[e]), find(v[e])
+        if a != b:
+            parent[a] = b
+            inP[e] = True
+    k_total = math.ceil(frac * float((~inP).sum()))
+    added = []
+    for r in range(rounds):
+        q = k_total * (r + 1) // rounds - k_total * r // rounds
+        A = np.zeros((n, n))
+        for e in np.nonzero(inP)[0]:
+            A[u[e], v[e]] = A[v[e], u[e]] = w[e]
+        d = A.sum(1)
+        X = X0s[r] - X0s[r].mean(0)
+        for _ in range(sweeps):
+            X = (1 - omega) * X + omega * (A @ X) / d[:, None]
+        cand = np.nonzero(~inP)[0]
+        s = w[cand] * ((X[u[cand]] - X[v[cand]]) ** 2).sum(1)
+        take = sorted(range(len(cand)), key=lambda i: (-s[i], cand[i]))[:q]
+        inP[cand[take]] = True
+        added.append(set(cand[take].tolist()))
+    return inP, added
+
+
+def test_rounds_match_dense_brute_force(orc):
+    # a tiny graph where the rounds' choices depend on re-embedding the growing sparsifier
+    g = W.random_connected(40, 110, seed=93, wdist=("lognormal", 0.0, 1.0))
+    rounds, sweeps, frac = 4, 5, 0.3
+    X0s = [W.random_block(g.n, 6, 94 + r) for r in range(rounds)]
+    res = orc.sparsify_rounds(g.n, g.u, g.v, g.w, X0s, rounds, sweeps, frac)
+    inP, added = _dense_rounds(g.n, g.u, g.v, g.w, X0s, rounds, sweeps, frac, 0.5)
+    assert np.array_equal(res.keep > 0, inP)
+    for lr, ref in zip(res.levels, added):
+        assert set(lr.chosen.tolist()) == ref
+    # the rounds add disjoint sets that together are the whole budget
+    chosen = np.concatenate([lr.chosen for lr in res.levels])
+    assert len(set(chosen.tolist())) == len(chosen) == orc.ksel(frac, g.m - (g.n - 1))
