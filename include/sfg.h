@@ -222,6 +222,12 @@ typedef struct {
     sfg_dtype storage;     /* iterate storage: F64, F32, F16, BF16 */
     int32_t final_f32;     /* F16/BF16: last iterate in FP32 */
     double band;           /* F16/BF16/F32: relative margin m of FP64 re-scoring around the threshold (0 = none) */
+    int32_t rounds;        /* single level: multi-round densification, 1..16 (0 = 1).  The budget
+                              ceil(frac * off-tree edges) is split into near-equal quotas; round r smooths
+                              block r of x0 on the current sparsifier (tree + edges added so far; its
+                              Laplacian is the one the perturbation analysis of Sec. 3.5 is about) and adds
+                              its quota's top-scored edges outside it.  x0 then holds rounds * n * k values
+                              and the report has one entry per round. */
 } sfg_params;
 
 /* Per-level report (host). */
@@ -245,7 +251,9 @@ typedef struct {
 /*
  * Spectral sparsifier P of G (the problem of Sec. 2.2 and Alg. 1):
  * levels = 1: maximum-weight spanning tree, embed (sparsifier = the tree, or
- *   the graph), score the off-tree edges, add the top ceil(f * n_cand).
+ *   the graph), score the off-tree edges, add the top ceil(f * n_cand); with
+ *   rounds R > 1 that budget is added in R near-equal quotas, each after
+ *   re-embedding on the sparsifier grown so far (x0 holds R blocks).
  * levels > 1: Alg. 1 -- coarsen G_0..G_{levels-1}, P_last = G_last, then for
  *   each finer level map the sparsifier back (per-aggregate spanning trees and
  *   the heaviest fine edge of each coarse sparsifier edge) and add the top
@@ -254,7 +262,8 @@ typedef struct {
  *              block at x0 + l*n*k  (caller draws levels*n*k values)
  *   keep       out [m] uint8: 0 not in P, 1 in P before the final additions
  *              (the tree, or the mapped sparsifier), 2 recovered at level 0
- *   rep        (host, may be NULL) per-level report
+ *              (in any round)
+ *   rep        (host, may be NULL) per-level report (per round when R > 1)
  * Synchronises.  Errors: SFG_EINVAL, SFG_ENOTCONN, SFG_ENOMEM, SFG_EHIP,
  * SFG_EUNSUPPORTED.
  */

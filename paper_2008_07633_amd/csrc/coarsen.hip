@@ -40,7 +40,7 @@ int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t 
                           const uint8_t *allowed, uint8_t *in_tree, DevArena &A, hipStream_t s);
 void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
                  const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
-                 DevArena &A, hipStream_t s);
+                 DevArena &A, hipStream_t s, int64_t k_take);
 
 namespace {
 
@@ -485,7 +485,7 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
         }
         uint8_t *kp = (l == 1) ? keep : A.alloc<uint8_t>(F.m + 1);
         sfg_level_report *lr = rep ? &rep->level[l - 1] : nullptr;
-        score_level(F.n, F.m, F.u, F.v, F.w64, F.w32, base, p, x0 + (size_t)(l - 1) * n * p->k, kp, lr, A, s);
+        score_level(F.n, F.m, F.u, F.v, F.w64, F.w32, base, p, x0 + (size_t)(l - 1) * n * p->k, kp, lr, A, s, -1);
         P = kp;
     }
 }

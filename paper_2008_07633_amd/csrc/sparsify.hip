@@ -103,9 +103,11 @@ __global__ void k_f32_to_f64(int64_t m, const float *__restrict__ a, double *__r
     if (e < m) b[e] = (double)a[e];
 }
 
+// keep from the base sparsifier: 0 stays 0, an earlier round's addition (2)
+// stays 2, any other member is 1
 __global__ void k_keep_init(int64_t m, const uint8_t *__restrict__ base, uint8_t *keep) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < m) keep[e] = base[e] ? 1 : 0;
+    if (e < m) keep[e] = base[e] == 2 ? 2 : (base[e] ? 1 : 0);
 }
 
 __global__ void k_keep_add(int64_t nc, const int32_t *__restrict__ cand, const uint8_t *__restrict__ sel,
@@ -200,10 +202,11 @@ struct Timer {
 }  // namespace
 
 // Embed (smooth on the scoring graph), score the edges outside `base`, add
-// the top ceil(frac * n_cand) of them.  Writes keep (1 = base, 2 = added).
+// the top k_take of them (k_take < 0: ceil(frac * n_cand)).  Writes keep
+// (1 = base, 2 = added); keep may be base itself.
 void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
                  const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
-                 DevArena &A, hipStream_t s) {
+                 DevArena &A, hipStream_t s, int64_t k_take) {
     const bool f64 = p->storage == SFG_F64;
     const sfg_dtype vt = f64 ? SFG_F64 : SFG_F32;
     const void *wv = f64 ? (const void *)w64 : (const void *)w32;
@@ -242,7 +245,8 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
     edge_scores(x, xt, n, p->k, nc, cand, u, v, wv, vt, score, st, s);
     float ms_score = tm.stop();
     tm.start();
-    const int64_t ksel = (int64_t)std::ceil(p->frac * (double)nc);
+    const int64_t ksel = k_take >= 0 ? k_take : (int64_t)std::ceil(p->frac * (double)nc);
+    SFG_REQUIRE(ksel <= nc, SFG_EINVAL, "sparsify: more edges requested than candidates");
     uint8_t *sel = A.alloc<uint8_t>(nc + 1);
     double *tau = A.alloc<double>(1);
     size_t wsel = select_workspace_bytes(nc);
@@ -306,9 +310,22 @@ void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t
     uint8_t *tree = A.alloc<uint8_t>(m + 1);
     const int64_t comps = spanning_tree_gpu(n, m, u, v, w64, SFG_F64, nullptr, tree, A, s);
     if (comps != 1) fail(SFG_ENOTCONN, "sparsify: graph has " + std::to_string(comps) + " components");
-    sfg_level_report *lr = rep ? &rep->level[0] : nullptr;
-    if (rep) rep->levels = 1;
-    score_level(n, m, u, v, w64, w32, tree, p, x0, keep, lr, A, s);
+    const int32_t rounds = p->rounds > 1 ? p->rounds : 1;
+    if (rep) rep->levels = rounds;
+    if (rounds == 1) {
+        score_level(n, m, u, v, w64, w32, tree, p, x0, keep, rep ? &rep->level[0] : nullptr, A, s, -1);
+        return;
+    }
+    // multi-round densification: the budget of the single pass in near-equal
+    // quotas, each scored on the sparsifier grown so far (keep is its own base)
+    const int64_t k_total = (int64_t)std::ceil(p->frac * (double)(m - (n - 1)));
+    hipLaunchKernelGGL(k_keep_init, dim3(grid_for(m, 256)), dim3(256), 0, s, m, tree, keep);
+    SFG_LAUNCH_CHECK();
+    for (int32_t r = 0; r < rounds; ++r) {
+        const int64_t q = k_total * (r + 1) / rounds - k_total * r / rounds;
+        score_level(n, m, u, v, w64, w32, keep, p, x0 + (size_t)r * n * p->k, keep,
+                    rep ? &rep->level[r] : nullptr, A, s, q);
+    }
 }
 
 void check_params(const sfg_params *p) {
@@ -322,6 +339,8 @@ void check_params(const sfg_params *p) {
     SFG_REQUIRE(p->embed == SFG_EMBED_SPARSIFIER || p->embed == SFG_EMBED_GRAPH, SFG_EINVAL, "sparsify: bad embed");
     SFG_REQUIRE(valid_dtype(p->storage), SFG_EINVAL, "sparsify: bad storage dtype");
     SFG_REQUIRE(p->band >= 0.0 && p->band < 1.0, SFG_EINVAL, "sparsify: band must be in [0, 1)");
+    SFG_REQUIRE(p->rounds >= 0 && p->rounds <= 16, SFG_EINVAL, "sparsify: rounds must be in [0, 16]");
+    SFG_REQUIRE(p->rounds <= 1 || p->levels == 1, SFG_EUNSUPPORTED, "sparsify: rounds > 1 needs levels = 1");
 }
 
 }  // namespace sfg

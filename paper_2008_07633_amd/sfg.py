@@ -53,7 +53,8 @@ class CsrStruct(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("k", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("frac", ctypes.c_double), ("embed", ctypes.c_int32),
-                ("storage", ctypes.c_int), ("final_f32", ctypes.c_int32), ("band", ctypes.c_double)]
+                ("storage", ctypes.c_int), ("final_f32", ctypes.c_int32), ("band", ctypes.c_double),
+                ("rounds", ctypes.c_int32)]
 
 
 class LevelReport(ctypes.Structure):
@@ -272,9 +273,9 @@ def sfg_coarsen(G: Csr, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, aff: 
 
 
 def make_params(levels=1, k=8, sweeps=10, omega=0.5, frac=0.05, embed=EMBED_SPARSIFIER, storage=F64,
-                final_f32=False, band=0.0) -> Params:
+                final_f32=False, band=0.0, rounds=1) -> Params:
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
-    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band)
+    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds)
 
 
 def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: torch.Tensor,

@@ -243,6 +243,43 @@ def test_sparsify_single_level_matches_oracle(S, orc, graph, embed):
         assert rep[0]["tau"] == lr.tau
 
 
+@pytest.mark.parametrize("rounds", [2, 5])
+def test_sparsify_rounds_match_oracle(S, orc, graph, rounds):
+    # multi-round densification: each round re-embeds on the grown sparsifier
+    g = graph
+    k, T, f = 8, 6, 0.1
+    X0s = np.stack([W.random_block(g.n, k, 40 + r) for r in range(rounds)])
+    ref = orc.sparsify_rounds(g.n, g.u, g.v, g.w, list(X0s), rounds, T, f)
+    p = S.make_params(k=k, sweeps=T, frac=f, rounds=rounds)
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0s), p)
+    assert np.array_equal(host(keep), ref.keep)
+    assert len(rep) == rounds
+    for r, lr in zip(rep, ref.levels):
+        assert r["n_cand"] == lr.n_cand and r["k_sel"] == lr.k_sel
+        if lr.k_sel:
+            assert r["tau"] == lr.tau
+
+
+def test_sparsify_rounds_precision_form(S, orc):
+    # FP16 embedding with FP64 re-scoring of the band, round by round
+    g = W.powergrid(90, 80, 0.02, seed=95)
+    k, T, f, R = 16, 8, 0.1, 3
+    X0s = np.stack([W.random_block(g.n, k, 96 + r) for r in range(R)])
+    ref = orc.sparsify_rounds(g.n, g.u, g.v, g.w, list(X0s), R, T, f)
+    p = S.make_params(k=k, sweeps=T, frac=f, rounds=R, storage=torch.float16, final_f32=True, band=0.01)
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0s), p)
+    assert np.array_equal(host(keep), ref.keep)
+    assert all(r["band"] > 0 for r in rep)
+
+
+def test_sparsify_rounds_errors(S):
+    g = W.grid2d(10, 10, seed=97)
+    X0 = dev(W.random_block(g.n, 4, 98))
+    for kw in ({"rounds": 17}, {"rounds": -1}, {"rounds": 2, "levels": 2}):
+        with pytest.raises(S.SfgError):
+            S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), X0, S.make_params(k=4, sweeps=3, frac=0.1, **kw))
+
+
 def test_sparsify_deterministic(S):
     g = W.powergrid(120, 110, 0.02, seed=79)
     X0 = dev(W.random_block(g.n, 16, 3))

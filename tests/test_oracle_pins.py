@@ -507,3 +507,18 @@ def test_rounds_match_dense_brute_force(orc):
     # the rounds add disjoint sets that together are the whole budget
     chosen = np.concatenate([lr.chosen for lr in res.levels])
     assert len(set(chosen.tolist())) == len(chosen) == orc.ksel(frac, g.m - (g.n - 1))
+
+
+def test_rounds_lower_the_condition_number(orc):
+    # the 64x64 grid workload (K=8, T=10, f=5%): re-embedding on the grown
+    # sparsifier in 5 rounds beats one pass with the same budget on every seed
+    g = W.config_graph(1)
+    k1, k5 = [], []
+    for seed in range(5):
+        X0s = [W.random_block(g.n, 8, 500 + 10 * seed + r) for r in range(5)]
+        r1 = orc.sparsify_rounds(g.n, g.u, g.v, g.w, X0s[:1], 1, 10, 0.05)
+        r5 = orc.sparsify_rounds(g.n, g.u, g.v, g.w, X0s, 5, 10, 0.05)
+        assert (r1.keep == 2).sum() == (r5.keep == 2).sum()
+        k1.append(orc.kappa_sparse(g.n, g.u, g.v, g.w, r1.keep > 0)[0])
+        k5.append(orc.kappa_sparse(g.n, g.u, g.v, g.w, r5.keep > 0)[0])
+    assert all(b < a for a, b in zip(k1, k5)), (k1, k5)
