@@ -71,12 +71,14 @@ typedef enum {
     SFG_OP_AFFINITY = 3,
     SFG_OP_COARSEN = 4,
     SFG_OP_MPNN_FORWARD = 5,   /* n nodes, t = activation dtype */
-    SFG_OP_MPNN_TRAIN = 6      /* n nodes, m = scored edges */
+    SFG_OP_MPNN_TRAIN = 6,     /* n nodes, m = scored edges */
+    SFG_OP_COLOR = 7           /* n nodes */
 } sfg_op;
 
 /* Which graph's embedding scores the candidates (Sec. 3.5 derives the score
  * from eigenvectors of the current sparsifier; Alg. 1 embeds the graph). */
 typedef enum { SFG_EMBED_SPARSIFIER = 0, SFG_EMBED_GRAPH = 1 } sfg_embed;
+typedef enum { SFG_SMOOTH_JACOBI = 0, SFG_SMOOTH_GAUSS_SEIDEL = 1 } sfg_smoother;
 
 /* Workspace (bytes) needed by an operation.  For SFG_OP_LAPLACIAN_CSR, m is
  * the edge count; for SFG_OP_SMOOTH, n, k and t (the storage dtype); for
@@ -129,6 +131,42 @@ sfg_status sfg_laplacian_csr(int64_t n, int64_t m, const int32_t *u, const int32
 sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega,
                       const double *x0, sfg_dtype storage, int32_t final_f32, void *x,
                       void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Multicolouring for the Gauss-Seidel reading of the smoother (Sec. 3.2
+ * relaxes L x = 0 by Gauss-Seidel steps).  Jones-Plassmann rounds with the
+ * fixed priority (h(p), p), h(x) the integer mixer x ^= x>>16, x *= 0x7feb352d,
+ * x ^= x>>15, x *= 0x846ca68b, x ^= x>>16 (32-bit): in round r each uncoloured
+ * node whose priority exceeds that of all its uncoloured neighbours takes the
+ * smallest colour unused by neighbours coloured in earlier rounds.
+ *   H           graph (its structure only)
+ *   color       out [n] int32 colour of each node (adjacent nodes differ)
+ *   class_rows  out [n] int32: the nodes of colour 0, then 1, ..., each class
+ *               in ascending node order
+ *   class_ptr   out [n + 1] int32 (device): the first ncolors + 1 entries are
+ *               the class offsets into class_rows
+ *   ncolors     (host) out: number of colours
+ * Workspace: sfg_workspace_bytes(SFG_OP_COLOR, n, 0, 0, 0).  Synchronises
+ * once per round.  Errors: SFG_EINVAL, SFG_EWORKSPACE, SFG_EHIP.
+ */
+sfg_status sfg_color(const sfg_csr *H, int32_t *color, int32_t *class_rows, int32_t *class_ptr, int32_t *ncolors,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Gauss-Seidel reading of the smoother (Sec. 3.2): centre x0 as sfg_smooth
+ * does, then `sweeps` sweeps, each updating the colour classes in order, in
+ * place, every row with sfg_smooth's arithmetic over the current values:
+ *     x_p <- (1 - omega) x_p + omega * (sum_q A_pq x_q) / D_pp
+ * (omega = 1: plain Gauss-Seidel).  Rows of one class are never adjacent, so
+ * the order inside a class does not matter.
+ *   class_rows, class_ptr, ncolors   from sfg_color on the same H
+ *   storage    F64 or F32 (H's values of the same type); x out [n*k]
+ * Workspace: sfg_workspace_bytes(SFG_OP_SMOOTH, n, 0, k, storage).
+ * Synchronises once.  Errors: SFG_EINVAL, SFG_EUNSUPPORTED, SFG_EWORKSPACE.
+ */
+sfg_status sfg_smooth_gs(const sfg_csr *H, const int32_t *class_rows, const int32_t *class_ptr, int32_t ncolors,
+                         int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage, void *x,
+                         void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Edge scores (Eq. 18 with the smoothed block in place of eigenvectors;
@@ -228,6 +266,8 @@ typedef struct {
                               Laplacian is the one the perturbation analysis of Sec. 3.5 is about) and adds
                               its quota's top-scored edges outside it.  x0 then holds rounds * n * k values
                               and the report has one entry per round. */
+    int32_t smoother;      /* sfg_smoother: damped Jacobi (default) or multicolour Gauss-Seidel; Gauss-Seidel
+                              needs F64 or F32 storage and no band */
 } sfg_params;
 
 /* Per-level report (host). */

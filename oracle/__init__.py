@@ -55,6 +55,10 @@ def _L():
         lib.orc_laplacian_csr.restype = ctypes.c_int
         lib.orc_smooth.argtypes = [I64, P, P, P, P, I32, I32, D, P, P]
         lib.orc_smooth.restype = None
+        lib.orc_color.argtypes = [I64, P, P, P]
+        lib.orc_color.restype = I32
+        lib.orc_smooth_gs.argtypes = [I64, P, P, P, P, I32, I32, D, P, I32, P]
+        lib.orc_smooth_gs.restype = None
         lib.orc_smooth_masked.argtypes = [I64, P, P, P, P, I32, I32, D, P, P, P]
         lib.orc_smooth_masked.restype = None
         lib.orc_edge_scores.argtypes = [I32, P, I64, P, P, P, P]
@@ -142,6 +146,23 @@ def smooth(csr: CSR, X, sweeps: int, omega: float = 0.5) -> np.ndarray:
     k = X.shape[1]
     _L().orc_smooth(csr.n, _p(csr.rowptr), _p(csr.col), _p(csr.val), _p(csr.deg), k, sweeps, omega,
                     _p(X), _p(Y))
+    return X
+
+
+def color(csr: CSR):
+    """Multicolouring for the Gauss-Seidel smoother: Jones-Plassmann rounds with
+    a fixed hash priority, smallest free colour.  Returns (color[n], ncolors)."""
+    c = np.empty(csr.n, dtype=np.int32)
+    nc = _L().orc_color(csr.n, _p(csr.rowptr), _p(csr.col), _p(c))
+    return c, int(nc)
+
+
+def smooth_gs(csr: CSR, X, sweeps: int, omega: float, colors, ncolors: int) -> np.ndarray:
+    """Multicolour Gauss-Seidel reading of the smoother (Sec. 3.2): colour by
+    colour, in place, each row as in the Jacobi sweep."""
+    X = np.array(X, dtype=np.float64, order="C", copy=True)
+    _L().orc_smooth_gs(csr.n, _p(csr.rowptr), _p(csr.col), _p(csr.val), _p(csr.deg), X.shape[1], sweeps, omega,
+                       _p(_i32(colors)), ncolors, _p(X))
     return X
 
 
@@ -250,11 +271,13 @@ class Result:
     X: Optional[np.ndarray] = None  # smoothed block of the finest scoring pass
 
 
-def score_level(n, u, v, w, base_mask, X0, k_sweeps, omega, frac, embed="sparsifier", k_take=None):
+def score_level(n, u, v, w, base_mask, X0, k_sweeps, omega, frac, embed="sparsifier", k_take=None,
+                smoother="jacobi"):
     """One round of Alg. 1's embed / score / include-top-few on a graph whose
     current sparsifier is ``base_mask``.  ``embed`` selects the smoothed graph:
     'sparsifier' (eigenvectors of L_P, Sec. 3.5) or 'graph' (Alg. 1, embed G).
-    ``k_take`` (default ceil(frac * candidates)) is how many edges are added."""
+    ``k_take`` (default ceil(frac * candidates)) is how many edges are added.
+    ``smoother``: 'jacobi' (damped Jacobi) or 'gs' (multicolour Gauss-Seidel)."""
     u, v, w = _i32(u), _i32(v), _f64(w)
     base_mask = np.asarray(base_mask, dtype=bool)
     if embed == "sparsifier":
@@ -265,7 +288,13 @@ def score_level(n, u, v, w, base_mask, X0, k_sweeps, omega, frac, embed="sparsif
         raise ValueError(embed)
     H = laplacian_csr(n, hu, hv, hw)
     Xc, _ = center(X0)
-    X = smooth(H, Xc, k_sweeps, omega)
+    if smoother == "gs":
+        colors, ncolors = color(H)
+        X = smooth_gs(H, Xc, k_sweeps, omega, colors, ncolors)
+    elif smoother == "jacobi":
+        X = smooth(H, Xc, k_sweeps, omega)
+    else:
+        raise ValueError(smoother)
     cand = np.nonzero(~base_mask)[0].astype(np.int32)
     s = edge_scores(X, u[cand], v[cand], w[cand])
     k = ksel(frac, cand.shape[0]) if k_take is None else int(k_take)
@@ -274,12 +303,12 @@ def score_level(n, u, v, w, base_mask, X0, k_sweeps, omega, frac, embed="sparsif
     return lr, X
 
 
-def sparsify_single(n, u, v, w, X0, sweeps, frac, omega=0.5, embed="sparsifier") -> Result:
+def sparsify_single(n, u, v, w, X0, sweeps, frac, omega=0.5, embed="sparsifier", smoother="jacobi") -> Result:
     """Spanning tree plus the top f of off-tree edges by embedding-distance score."""
     intree, comps = max_spanning_forest(n, u, v, w)
     if comps != 1:
         raise ValueError("graph is not connected")
-    lr, X = score_level(n, u, v, w, intree.astype(bool), X0, sweeps, omega, frac, embed)
+    lr, X = score_level(n, u, v, w, intree.astype(bool), X0, sweeps, omega, frac, embed, smoother=smoother)
     keep = intree.astype(np.uint8)
     keep[lr.chosen] = 2
     return Result(keep, [lr], X)

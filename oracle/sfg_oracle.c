@@ -87,6 +87,100 @@ void orc_smooth(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Multicolouring for a Gauss-Seidel reading of the smoother (Sec. 3.2 names */
+/* Gauss-Seidel relaxations).  Jones-Plassmann rounds with a fixed priority: */
+/* a node's priority is the pair (h(p), p) with h the multiply-xorshift      */
+/* integer mixer below; in round r every uncoloured node whose priority      */
+/* exceeds that of all its uncoloured neighbours takes the smallest colour   */
+/* not used by a neighbour coloured in an earlier round.  Returns the number */
+/* of colours; color[p] >= 0.                                                */
+/* ------------------------------------------------------------------------ */
+static uint32_t orc_mix32(uint32_t x)
+{
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+static int orc_prio_greater(int64_t p, int64_t q)
+{
+    const uint32_t hp = orc_mix32((uint32_t)p), hq = orc_mix32((uint32_t)q);
+    return hp > hq || (hp == hq && p > q);
+}
+
+int32_t orc_color(int64_t n, const int64_t *rowptr, const int32_t *col, int32_t *color)
+{
+    int32_t *round = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    for (int64_t p = 0; p < n; ++p) { color[p] = -1; round[p] = -1; }
+    int64_t left = n;
+    int32_t ncolors = 0;
+    for (int32_t r = 0; left > 0; ++r) {
+        /* decide the whole round from the state before it */
+        for (int64_t p = 0; p < n; ++p) {
+            if (round[p] >= 0) continue;
+            int is_max = 1;
+            for (int64_t j = rowptr[p]; j < rowptr[p + 1] && is_max; ++j) {
+                const int64_t q = col[j];
+                /* uncoloured before this round (chosen earlier in this scan counts too) */
+                if ((round[q] < 0 || round[q] == r) && orc_prio_greater(q, p)) is_max = 0;
+            }
+            if (is_max) round[p] = r;   /* chosen in this round (not yet coloured) */
+        }
+        for (int64_t p = 0; p < n; ++p) {
+            if (round[p] != r) continue;
+            int32_t c = 0;
+            for (;;) {   /* smallest colour unused by neighbours coloured earlier */
+                int used = 0;
+                for (int64_t j = rowptr[p]; j < rowptr[p + 1]; ++j) {
+                    const int64_t q = col[j];
+                    if (round[q] >= 0 && round[q] < r && color[q] == c) { used = 1; break; }
+                }
+                if (!used) break;
+                ++c;
+            }
+            color[p] = c;
+            if (c + 1 > ncolors) ncolors = c + 1;
+            --left;
+        }
+    }
+    free(round);
+    return ncolors;
+}
+
+/* Gauss-Seidel reading of the smoother: one sweep updates the colours in    */
+/* order 0, 1, ..., in place; a row of colour c takes                        */
+/*   x_p = (1-omega) x_p + omega * (s_p / D_pp)                               */
+/* with s_p summed as in orc_smooth over the current values (its neighbours  */
+/* have other colours, so the order inside a colour does not matter).        */
+void orc_smooth_gs(int64_t n, const int64_t *rowptr, const int32_t *col, const double *val,
+                   const double *deg, int32_t k, int32_t sweeps, double omega, const int32_t *color,
+                   int32_t ncolors, double *X)
+{
+    const double keep = 1.0 - omega;
+    for (int32_t t = 0; t < sweeps; ++t) {
+        for (int32_t cc = 0; cc < ncolors; ++cc) {
+            for (int64_t p = 0; p < n; ++p) {
+                if (color[p] != cc) continue;
+                for (int32_t c = 0; c < k; ++c) {
+                    double s = 0.0;
+                    for (int64_t j = rowptr[p]; j < rowptr[p + 1]; ++j) {
+                        double prod = val[j] * X[(int64_t)col[j] * k + c];
+                        s = s + prod;
+                    }
+                    double a = keep * X[p * k + c];
+                    double b = s / deg[p];
+                    double bo = omega * b;
+                    X[p * k + c] = a + bo;
+                }
+            }
+        }
+    }
+}
+
 /* Same smoothing restricted to rows with dist[p] <= sweeps - t at sweep t   */
 /* (t = 1..sweeps).  Rows outside the window keep stale values; the rows a   */
 /* score at distance 0 depends on are exact.  Used to pin the GPU's           */

@@ -25,6 +25,7 @@
 //   - in reduced precision, rows longer than 256 entries (hubs of power-law
 //     graphs) are taken out and swept by a whole workgroup each.
 #include <cstdlib>
+#include <vector>
 
 #include "common.hpp"
 
@@ -278,6 +279,62 @@ __global__ __launch_bounds__(256) void k_sweep_long(int32_t lpr, int32_t ldx, in
         }
         __syncthreads();
     }
+}
+
+// Multicolour Gauss-Seidel reading of the smoother: the listed rows (one
+// colour class: no two adjacent) are updated in place from the current block,
+// each row with the Jacobi sweep's arithmetic.  x is read and written, so it
+// carries no restrict qualifier; the rows read are of other colours and are
+// not written by this launch.
+template <typename T, int VPL, int U>
+__global__ __launch_bounds__(256) void k_sweep_color(int64_t nthreads, int32_t lpr, int32_t lpr_log2, int32_t k,
+                                                     const int32_t *__restrict__ rows,
+                                                     const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, const T *__restrict__ val,
+                                                     const T *__restrict__ deg, T *x, T keep, T omega) {
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t t = (int64_t)b * 256 + threadIdx.x;
+    if (t >= nthreads) return;
+    const int64_t ri = lpr_log2 >= 0 ? (t >> lpr_log2) : t / lpr;
+    const int32_t off = (int32_t)(t - ri * lpr) * VPL;
+    const int64_t row = rows[ri];
+    const double mo[VPL] = {};
+    const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+    T self[VPL];
+    load_row<T, T, T, VPL, false>(x + row * k + off, mo, self);
+    const T d = deg[row];
+    T acc[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) acc[i] = T(0);
+    for (int32_t j = j0; j < j1; j += U) {
+        int32_t cj[U];
+        T wj[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            const int32_t jj = (j + i < j1) ? j + i : j1 - 1;
+            cj[i] = col[jj];
+            wj[i] = val[jj];
+        }
+        T xv[U][VPL];
+#pragma unroll
+        for (int i = 0; i < U; ++i) load_row<T, T, T, VPL, false>(x + (int64_t)cj[i] * k + off, mo, xv[i]);
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+            if (j + i < j1) {
+#pragma unroll
+                for (int q = 0; q < VPL; ++q) acc[q] = madd(acc[q], wj[i], xv[i][q]);
+            }
+        }
+    }
+    Vec<T, VPL> out;
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) {
+        const T a = keep * self[i];
+        const T q = acc[i] / d;
+        const T bo = omega * q;
+        out.v[i] = a + bo;
+    }
+    *reinterpret_cast<Vec<T, VPL> *>(x + row * k + off) = out;
 }
 
 // Rows handled by k_sweep_long (device list and count), and the length above
@@ -590,6 +647,72 @@ size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage) {
     plan_smooth(c, n, k, storage);
     return c.used + 256;
 }
+
+namespace {
+template <typename T, int VPL>
+void launch_color_v(const sfg_csr *H, int32_t k, const int32_t *rows, int64_t nrows, T *x, double omega,
+                    hipStream_t s) {
+    const int lpr = k / VPL;
+    const int64_t nthreads = nrows * (int64_t)lpr;
+    if (nthreads == 0) return;
+    hipLaunchKernelGGL((k_sweep_color<T, VPL, 4>), dim3(grid_for(nthreads, 256)), dim3(256), 0, s, nthreads, lpr,
+                       ilog2_exact(lpr), k, rows, H->rowptr, H->col, (const T *)H->val, (const T *)H->deg, x,
+                       (T)(1.0 - omega), (T)omega);
+    SFG_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_color(const sfg_csr *H, int32_t k, const int32_t *rows, int64_t nrows, T *x, double omega,
+                  hipStream_t s) {
+    switch (pick_vpl<T>(k, sizeof(T) == 8 ? 32 : 16)) {
+        case 1: launch_color_v<T, 1>(H, k, rows, nrows, x, omega, s); return;
+        case 2: launch_color_v<T, 2>(H, k, rows, nrows, x, omega, s); return;
+        case 4: launch_color_v<T, 4>(H, k, rows, nrows, x, omega, s); return;
+        case 8: launch_color_v<T, 8>(H, k, rows, nrows, x, omega, s); return;
+        default: break;
+    }
+    fail(SFG_EUNSUPPORTED, "smooth_gs: no kernel for this lane split");
+}
+
+}  // namespace
+
+// Multicolour Gauss-Seidel smoothing (F64 or F32 storage): centre x0 into x,
+// then `sweeps` sweeps, each the colour classes in order, in place.
+// class_ptr (host) has ncolors + 1 offsets into class_rows (device).
+void smooth_gs(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
+               const int32_t *class_rows, const std::vector<int32_t> &class_ptr, void *x, void *ws, size_t ws_bytes,
+               hipStream_t s) {
+    SFG_REQUIRE(H && H->rowptr && H->deg && x0 && x && class_rows, SFG_EINVAL, "smooth_gs: null pointer");
+    SFG_REQUIRE(k >= 1 && k <= 64, SFG_EINVAL, "smooth_gs: k must be in [1, 64]");
+    SFG_REQUIRE(sweeps >= 0, SFG_EINVAL, "smooth_gs: sweeps must be >= 0");
+    SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_gs: omega must be in (0, 1]");
+    SFG_REQUIRE(storage == SFG_F64 || storage == SFG_F32, SFG_EUNSUPPORTED, "smooth_gs: F64 or F32 storage");
+    SFG_REQUIRE(H->vt == storage, SFG_EUNSUPPORTED, "smooth_gs: graph values must match the storage");
+    SFG_REQUIRE(ws_bytes >= smooth_workspace_bytes(H->n, k, storage), SFG_EWORKSPACE, "smooth_gs: workspace too small");
+    const int64_t n = H->n, total = n * (int64_t)k;
+    Carver c(ws);
+    SmoothPlan p = plan_smooth(c, n, k, storage);
+    launch_column_means<double>(x0, n, k, p.partial, p.mean, s);
+    const int32_t ncolors = (int32_t)class_ptr.size() - 1;
+    if (storage == SFG_F64) {
+        hipLaunchKernelGGL(k_center_convert<double>, dim3(grid_for(total, 256)), dim3(256), 0, s, total, k, x0,
+                           p.mean, (double *)x);
+        SFG_LAUNCH_CHECK();
+        for (int32_t t = 0; t < sweeps; ++t)
+            for (int32_t cc = 0; cc < ncolors; ++cc)
+                launch_color<double>(H, k, class_rows + class_ptr[cc], class_ptr[cc + 1] - class_ptr[cc],
+                                     (double *)x, omega, s);
+    } else {
+        hipLaunchKernelGGL(k_center_convert<float>, dim3(grid_for(total, 256)), dim3(256), 0, s, total, k, x0,
+                           p.mean, (float *)x);
+        SFG_LAUNCH_CHECK();
+        for (int32_t t = 0; t < sweeps; ++t)
+            for (int32_t cc = 0; cc < ncolors; ++cc)
+                launch_color<float>(H, k, class_rows + class_ptr[cc], class_ptr[cc + 1] - class_ptr[cc],
+                                    (float *)x, omega, s);
+    }
+}
+
 
 void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
             int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s) {

@@ -16,6 +16,12 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
                const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val, int32_t *eid, void *deg, void *ws,
                size_t ws_bytes, hipStream_t s);
 size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
+size_t color_workspace_bytes(int64_t n);
+void color_graph(const sfg_csr *H, int32_t *color, int32_t *class_rows, std::vector<int32_t> &class_ptr, void *ws,
+                 size_t ws_bytes, hipStream_t s);
+void smooth_gs(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
+               const int32_t *class_rows, const std::vector<int32_t> &class_ptr, void *x, void *ws, size_t ws_bytes,
+               hipStream_t s);
 void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
             int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s);
 void edge_scores(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t ne, const int32_t *cand,
@@ -234,7 +240,16 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
     void *wsm = A.raw(wss);
     float ms_other = tm.stop();
     tm.start();
-    smooth(&H, p->k, p->sweeps, p->omega, x0, p->storage, p->final_f32, x, wsm, wss, s);
+    if (p->smoother == SFG_SMOOTH_GAUSS_SEIDEL) {
+        int32_t *color = A.alloc<int32_t>(n + 1);
+        int32_t *class_rows = A.alloc<int32_t>(n + 1);
+        const size_t wsc = color_workspace_bytes(n);
+        std::vector<int32_t> class_ptr;
+        color_graph(&H, color, class_rows, class_ptr, A.raw(wsc), wsc, s);
+        smooth_gs(&H, p->k, p->sweeps, p->omega, x0, p->storage, class_rows, class_ptr, x, wsm, wss, s);
+    } else {
+        smooth(&H, p->k, p->sweeps, p->omega, x0, p->storage, p->final_f32, x, wsm, wss, s);
+    }
     float ms_smooth = tm.stop();
     // candidates: edges outside the current sparsifier, ascending id
     tm.start();
@@ -341,6 +356,11 @@ void check_params(const sfg_params *p) {
     SFG_REQUIRE(p->band >= 0.0 && p->band < 1.0, SFG_EINVAL, "sparsify: band must be in [0, 1)");
     SFG_REQUIRE(p->rounds >= 0 && p->rounds <= 16, SFG_EINVAL, "sparsify: rounds must be in [0, 16]");
     SFG_REQUIRE(p->rounds <= 1 || p->levels == 1, SFG_EUNSUPPORTED, "sparsify: rounds > 1 needs levels = 1");
+    SFG_REQUIRE(p->smoother == SFG_SMOOTH_JACOBI || p->smoother == SFG_SMOOTH_GAUSS_SEIDEL, SFG_EINVAL,
+                "sparsify: bad smoother");
+    SFG_REQUIRE(p->smoother == SFG_SMOOTH_JACOBI ||
+                    ((p->storage == SFG_F64 || p->storage == SFG_F32) && p->band == 0.0),
+                SFG_EUNSUPPORTED, "sparsify: Gauss-Seidel needs F64 or F32 storage and no band");
 }
 
 }  // namespace sfg
@@ -354,6 +374,7 @@ extern "C" size_t sfg_workspace_bytes(int op, int64_t n, int64_t m, int32_t k, s
         case SFG_OP_COARSEN: return sfg::coarsen_workspace_bytes(n < 1 ? 1 : n, m < 0 ? 0 : m);
         case SFG_OP_MPNN_FORWARD: return sfg::mpnn_forward_workspace_bytes(n < 1 ? 1 : n, t);
         case SFG_OP_MPNN_TRAIN: return sfg::mpnn_train_workspace_bytes(n < 1 ? 1 : n, m < 1 ? 1 : m);
+        case SFG_OP_COLOR: return sfg::color_workspace_bytes(n < 1 ? 1 : n);
         default: return 0;
     }
 }

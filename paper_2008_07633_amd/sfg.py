@@ -30,11 +30,13 @@ EMBED_SPARSIFIER, EMBED_GRAPH = 0, 1
 STATUS = {0: "SFG_OK", 1: "SFG_EINVAL", 2: "SFG_ENOTCONN", 3: "SFG_ENOMEM", 4: "SFG_EHIP",
           5: "SFG_EWORKSPACE", 6: "SFG_EUNSUPPORTED", 7: "SFG_ENUMERIC"}
 
-OP_MPNN_FORWARD, OP_MPNN_TRAIN = 5, 6
+OP_MPNN_FORWARD, OP_MPNN_TRAIN, OP_COLOR = 5, 6, 7
+SMOOTH_JACOBI, SMOOTH_GAUSS_SEIDEL = 0, 1
 
 EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores",
             "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify",
-            "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam"]
+            "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam",
+            "sfg_color", "sfg_smooth_gs"]
 
 
 class SfgError(RuntimeError):
@@ -54,7 +56,7 @@ class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("k", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("frac", ctypes.c_double), ("embed", ctypes.c_int32),
                 ("storage", ctypes.c_int), ("final_f32", ctypes.c_int32), ("band", ctypes.c_double),
-                ("rounds", ctypes.c_int32)]
+                ("rounds", ctypes.c_int32), ("smoother", ctypes.c_int32)]
 
 
 class LevelReport(ctypes.Structure):
@@ -99,6 +101,8 @@ def lib() -> ctypes.CDLL:
         L.sfg_mpnn_forward.argtypes = [P, P, P, I64, P, P, P, P, I, P, P, S, P]
         L.sfg_mpnn_loss_grad.argtypes = [P, P, P, I64, P, P, P, P, P, P, P, P, P, S, P]
         L.sfg_mpnn_adam.argtypes = [P, P, P, P, I64, I64, D, D, D, D, P]
+        L.sfg_color.argtypes = [P, P, P, P, P, P, S, P]
+        L.sfg_smooth_gs.argtypes = [P, P, P, I32, I32, I32, D, P, I, P, P, S, P]
         for name in EXPORTED:
             if name not in ("sfg_workspace_bytes", "sfg_last_error", "sfg_mpnn_param_count"):
                 getattr(L, name).restype = I
@@ -195,6 +199,38 @@ def sfg_smooth(H: Csr, x0: torch.Tensor, sweeps: int, omega: float = 0.5, storag
     return out
 
 
+def sfg_color(H: Csr, ws: Optional[torch.Tensor] = None):
+    """Multicolouring for the Gauss-Seidel smoother: (color[n], class_rows[n],
+    class_ptr[n+1] with the first ncolors+1 entries used, ncolors)."""
+    dev = H.rowptr.device
+    color = torch.empty(H.n, dtype=torch.int32, device=dev)
+    rows = torch.empty(H.n, dtype=torch.int32, device=dev)
+    ptr = torch.empty(H.n + 1, dtype=torch.int32, device=dev)
+    nc = ctypes.c_int32(0)
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_COLOR, H.n, 0, 0, F64), dev)
+    hs = H.struct()
+    _check(lib().sfg_color(ctypes.byref(hs), _ptr(color), _ptr(rows), _ptr(ptr), ctypes.byref(nc), _ptr(ws),
+                           ws.numel(), _stream()))
+    return color, rows, ptr, int(nc.value)
+
+
+def sfg_smooth_gs(H: Csr, classes, x0: torch.Tensor, sweeps: int, omega: float = 1.0, storage=torch.float64,
+                  out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Centre x0 and smooth it by multicolour Gauss-Seidel sweeps (classes from sfg_color)."""
+    _, rows, ptr, nc = classes
+    n, k = int(x0.shape[0]), int(x0.shape[1])
+    st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
+    if out is None:
+        out = torch.empty((n, k), dtype=_SFG_TO_TORCH[st], device=x0.device)
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_SMOOTH, n, 0, k, st), x0.device)
+    hs = H.struct()
+    _check(lib().sfg_smooth_gs(ctypes.byref(hs), _ptr(rows), _ptr(ptr), nc, k, sweeps, float(omega), _ptr(x0), st,
+                               _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
 def sfg_edge_scores(x: torch.Tensor, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
                     cand: Optional[torch.Tensor] = None, score_dtype=None,
                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -273,9 +309,9 @@ def sfg_coarsen(G: Csr, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, aff: 
 
 
 def make_params(levels=1, k=8, sweeps=10, omega=0.5, frac=0.05, embed=EMBED_SPARSIFIER, storage=F64,
-                final_f32=False, band=0.0, rounds=1) -> Params:
+                final_f32=False, band=0.0, rounds=1, smoother=SMOOTH_JACOBI) -> Params:
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
-    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds)
+    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds, smoother)
 
 
 def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: torch.Tensor,

@@ -393,3 +393,63 @@ def test_csr_long_lower_parts(S, orc, n, center):
     assert np.array_equal(host(H.eid)[:H.nnz], ref.eid)
     assert np.array_equal(host(H.val)[:H.nnz], ref.val)
     assert np.array_equal(host(H.deg), ref.deg)
+
+
+# --------------------------------------------------------------------------- Gauss-Seidel reading
+
+def test_color_matches_oracle(S, orc, graph):
+    g = graph
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w))
+    color, rows, ptr, nc = S.sfg_color(H)
+    ref, nref = orc.color(orc.laplacian_csr(g.n, g.u, g.v, g.w))
+    assert nc == nref
+    assert np.array_equal(host(color), ref)
+    want = np.concatenate([np.nonzero(ref == c)[0] for c in range(nref)]).astype(np.int32)
+    assert np.array_equal(host(rows), want)
+    assert np.array_equal(host(ptr)[:nc + 1], np.concatenate([[0], np.cumsum(np.bincount(ref, minlength=nref))]))
+
+
+@pytest.mark.parametrize("k,sweeps,omega", [(8, 5, 1.0), (16, 3, 0.5), (3, 4, 1.0), (16, 0, 1.0)])
+def test_smooth_gs_f64_bitwise(S, orc, graph, k, sweeps, omega):
+    g = graph
+    X0 = W.random_block(g.n, k, 60 + k)
+    ref_csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    c, nc = orc.color(ref_csr)
+    ref = orc.smooth_gs(ref_csr, orc.center(X0)[0], sweeps, omega, c, nc)
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w))
+    X = S.sfg_smooth_gs(H, S.sfg_color(H), dev(X0), sweeps, omega)
+    np.testing.assert_array_equal(host(X), ref)
+
+
+def test_smooth_gs_f32(S, orc):
+    g = W.powergrid(70, 60, 0.02, seed=61)
+    X0 = W.random_block(g.n, 16, 62)
+    ref_csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    c, nc = orc.color(ref_csr)
+    ref = orc.smooth_gs(ref_csr, orc.center(X0)[0], 10, 1.0, c, nc)
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w.astype(np.float32)))
+    X = S.sfg_smooth_gs(H, S.sfg_color(H), dev(X0), 10, 1.0, storage=torch.float32)
+    err = np.max(np.abs(host(X).astype(np.float64) - ref)) / np.max(np.abs(X0))
+    assert err < 2e-5, err
+
+
+@pytest.mark.parametrize("omega", [1.0, 0.5])
+def test_sparsify_gauss_seidel_matches_oracle(S, orc, graph, omega):
+    g = graph
+    k, T, f = 8, 6, 0.1
+    X0 = W.random_block(g.n, k, 63)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, T, f, omega=omega, smoother="gs")
+    p = S.make_params(k=k, sweeps=T, frac=f, omega=omega, smoother=S.SMOOTH_GAUSS_SEIDEL)
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), p)
+    assert np.array_equal(host(keep), ref.keep)
+    if ref.levels[0].k_sel:
+        assert rep[0]["tau"] == ref.levels[0].tau
+
+
+def test_gauss_seidel_unsupported_combinations(S):
+    g = W.grid2d(10, 10, seed=64)
+    X0 = dev(W.random_block(g.n, 4, 65))
+    for kw in ({"storage": torch.float16}, {"storage": torch.float32, "band": 0.01}, {"smoother": 2}):
+        kw.setdefault("smoother", S.SMOOTH_GAUSS_SEIDEL)
+        with pytest.raises(S.SfgError):
+            S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), X0, S.make_params(k=4, sweeps=3, frac=0.1, **kw))

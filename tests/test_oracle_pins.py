@@ -522,3 +522,69 @@ def test_rounds_lower_the_condition_number(orc):
         k1.append(orc.kappa_sparse(g.n, g.u, g.v, g.w, r1.keep > 0)[0])
         k5.append(orc.kappa_sparse(g.n, g.u, g.v, g.w, r5.keep > 0)[0])
     assert all(b < a for a, b in zip(k1, k5)), (k1, k5)
+
+
+# --------------------------------------------------------------------------- Gauss-Seidel reading
+
+def _mix32(x):
+    x &= 0xFFFFFFFF
+    x ^= x >> 16
+    x = (x * 0x7FEB352D) & 0xFFFFFFFF
+    x ^= x >> 15
+    x = (x * 0x846CA68B) & 0xFFFFFFFF
+    x ^= x >> 16
+    return x
+
+
+def _jp_brute(n, adj):
+    """Jones-Plassmann by sets: local maxima of (hash, id) among the uncoloured,
+    smallest colour free among earlier-coloured neighbours."""
+    prio = {p: (_mix32(p), p) for p in range(n)}
+    color, left = {}, set(range(n))
+    while left:
+        chosen = [p for p in left if all(prio[p] > prio[q] for q in adj[p] if q in left)]
+        for p in chosen:
+            used = {color[q] for q in adj[p] if q in color}
+            c = 0
+            while c in used:
+                c += 1
+            color[p] = c
+        left -= set(chosen)
+    return np.array([color[p] for p in range(n)], np.int32)
+
+
+@pytest.mark.parametrize("g", [W.grid2d(1, 30, seed=1), W.grid2d(9, 11, seed=2),
+                               W.random_connected(60, 200, seed=3),
+                               W.Graph(40, np.zeros(39, np.int32), np.arange(1, 40, dtype=np.int32), np.ones(39))],
+                         ids=["path", "grid", "random", "star"])
+def test_coloring_matches_brute_force(orc, g):
+    H = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    c, nc = orc.color(H)
+    adj = [set() for _ in range(g.n)]
+    for a, b in zip(g.u, g.v):
+        adj[a].add(int(b))
+        adj[b].add(int(a))
+    assert np.array_equal(c, _jp_brute(g.n, adj))
+    assert nc == c.max() + 1
+    assert np.all(c[g.u] != c[g.v])                       # proper
+    deg = np.bincount(np.concatenate([g.u, g.v]), minlength=g.n)
+    assert nc <= deg.max() + 1
+
+
+def test_gauss_seidel_matches_dense(orc):
+    g = W.random_connected(50, 140, seed=4, wdist=("lognormal", 0.0, 1.0))
+    H = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    c, nc = orc.color(H)
+    X0 = W.random_block(g.n, 5, 6)
+    A = np.zeros((g.n, g.n))
+    A[g.u, g.v] = g.w
+    A[g.v, g.u] = g.w
+    d = A.sum(1)
+    for omega in (1.0, 0.5):
+        X = X0.copy()
+        for _ in range(4):
+            for cc in range(nc):
+                rows = np.nonzero(c == cc)[0]
+                X[rows] = (1 - omega) * X[rows] + omega * (A[rows] @ X) / d[rows, None]
+        got = orc.smooth_gs(H, X0, 4, omega, c, nc)
+        assert np.max(np.abs(got - X)) < 1e-12 * np.max(np.abs(X0))
