@@ -55,6 +55,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--smoother", choices=["jacobi", "gs"], default="jacobi",
+                    help="gs: multicolour Gauss-Seidel (omega 1; colouring of the tree prepared once, like the tree)")
     ap.add_argument("--sweep-reps", type=int, default=10)
     ap.add_argument("--workload", choices=["powergrid", "knn", "chunglu", "mesh"], default="powergrid",
                     help="powergrid: the headline line; the others print their own lines (bench_workloads.py)")
@@ -115,9 +117,18 @@ def main():
     sel = torch.empty(ncand, dtype=torch.uint8, device=dev)
     tau = torch.empty(1, dtype=torch.float64, device=dev)
 
+    gs = args.smoother == "gs"
+    if gs:
+        omega = 1.0
+        S.sfg_laplacian_csr(g.n, u, v, w, mask=tree, ws=ws_csr, out=H, nnz=nnz)
+        classes = S.sfg_color(H)
+
     def step():
         S.sfg_laplacian_csr(g.n, u, v, w, mask=tree, ws=ws_csr, out=H, nnz=nnz)       # a1
-        S.sfg_smooth(H, x0, T, omega, storage=wdt, out=X, ws=ws_sm)                    # a2 + a3
+        if gs:
+            S.sfg_smooth_gs(H, classes, x0, T, omega, storage=wdt, out=X, ws=ws_sm)
+        else:
+            S.sfg_smooth(H, x0, T, omega, storage=wdt, out=X, ws=ws_sm)                # a2 + a3
         S.sfg_edge_scores(X, u, v, w, cand=cand, out=score)                            # a4
         S.sfg_select_topk(score, ksel, sel=sel, tau=tau, ws=ws_sel, sync=False)         # a5
 
@@ -145,9 +156,14 @@ def main():
         return a.elapsed_time(b) / reps
 
     reps = args.sweep_reps
-    t_smooth = ev_time(lambda: S.sfg_smooth(H, x0, T, omega, storage=wdt, out=X, ws=ws_sm), reps)
-    t_one = ev_time(lambda: S.sfg_smooth(H, x0, 1, omega, storage=wdt, out=X, ws=ws_sm), reps)
-    S.sfg_smooth(H, x0, T, omega, storage=wdt, out=X, ws=ws_sm)
+    def smooth_fn(sweeps):
+        if gs:
+            return S.sfg_smooth_gs(H, classes, x0, sweeps, omega, storage=wdt, out=X, ws=ws_sm)
+        return S.sfg_smooth(H, x0, sweeps, omega, storage=wdt, out=X, ws=ws_sm)
+
+    t_smooth = ev_time(lambda: smooth_fn(T), reps)
+    t_one = ev_time(lambda: smooth_fn(1), reps)
+    smooth_fn(T)
     # the first sweep also centres (reads the FP64 block); the other T-1 are plain sweeps
     t_sweep = (t_smooth - t_one) / (T - 1)
     # attainable bandwidth on this machine: a plain device copy of 1 GiB
@@ -165,7 +181,7 @@ def main():
     # The library sweeps an FP64 block of >= 16 vectors on a tree-like graph in
     # 8-column parts (one launch per part and sweep), so a launch moves its
     # part of X and the whole tree CSR.
-    parts = k // 8 if (f64 and k >= 16 and k % 8 == 0 and nnz <= 3 * g.n) else 1
+    parts = k // 8 if (f64 and k >= 16 and k % 8 == 0 and nnz <= 3 * g.n and not gs) else 1
     b_launch = sweep_bytes(g.n, nnz, k // parts, sx, sw)
     t_launch = t_sweep / parts
     achieved = b_launch / (t_launch * 1e-3) / 1e9
@@ -175,15 +191,17 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         tr = json.load(open(TRAFFIC_FILE))
         ent = tr.get(args.dtype)
-        if ent and ent.get("src_hash") == src_hash(SWEEP_SRC):
+        if ent and ent.get("src_hash") == src_hash(SWEEP_SRC) and not gs:
             traffic = ent["hbm_bytes_per_launch"]
 
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": ("k_sweep (one damped-Jacobi sweep of an 8-vector column part of the block on the tree)"
+                "kernel": (f"k_sweep_color (one Gauss-Seidel sweep: {classes[3]} colour classes of the tree, in place)"
+                           if gs else
+                           "k_sweep (one damped-Jacobi sweep of an 8-vector column part of the block on the tree)"
                            if parts > 1 else "k_sweep (one damped-Jacobi sweep of the 16-vector block on the tree)"),
                 "algorithmic_bytes_per_launch": b_launch, "avg_launch_us": round(t_launch * 1e3, 2),
-                "launches_per_sweep": parts,
+                "launches_per_sweep": classes[3] if gs else parts,
                 # the smoothing rate with the graph counted once per sweep of the whole block
                 "smoothing_gbs": round(smoothing_gbs, 1), "smoothing_frac": round(smoothing_gbs / HBM_PEAK_GBS, 4)}
 
@@ -199,7 +217,11 @@ def main():
         c0 = time.perf_counter()
         Hc = oracle.laplacian_csr(g.n, g.u[tmask], g.v[tmask], wnp[tmask])
         Xc, _ = oracle.center(X0)
-        Xs = oracle.smooth(Hc, Xc, T, omega)
+        if gs:
+            cl, ncl = oracle.color(Hc)
+            Xs = oracle.smooth_gs(Hc, Xc, T, omega, cl, ncl)
+        else:
+            Xs = oracle.smooth(Hc, Xc, T, omega)
         sc = oracle.edge_scores(Xs, g.u[cnp], g.v[cnp], wnp[cnp])
         oracle.select_topk(sc, cnp, ksel)
         c1 = time.perf_counter()
@@ -222,7 +244,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "powergrid1000x1000+2%diag", "nodes": g.n, "edges": g.m, "off_tree_edges": ncand,
                    "k_sel": ksel, "vectors": k, "sweeps": T, "omega": omega, "embed": "spanning tree",
-                   "parallelism": "single GPU"},
+                   "smoother": "multicolour Gauss-Seidel" if gs else "damped Jacobi", "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "copy_gbs": round(copy_gbs, 1),
