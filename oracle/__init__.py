@@ -452,6 +452,43 @@ def kappa_sparse(n, u, v, w, mask, tol=1e-8) -> tuple[float, float, float]:
     return lmax / lmin, lmax, lmin
 
 
+def pcg_iterations(n, u, v, w, mask=None, tol=1e-3, maxiter=20000, seed=0) -> int:
+    """Iterations of preconditioned CG on the grounded system L_G x = b (node 0
+    grounded, b standard normal from ``seed``) until ||r|| <= tol ||b||, with the
+    grounded sparsifier Laplacian L_P (the edges of ``mask``) solved exactly by a
+    sparse LU as the preconditioner (mask None: plain CG).  The sparsifier's
+    downstream use in the paper's evaluation (Sec. 4, Table 3)."""
+    import scipy.sparse.linalg as sla
+
+    LG = laplacian_sparse(n, u, v, w)[1:, 1:].tocsr()
+    if mask is None:
+        def solve(r):
+            return r.copy()
+    else:
+        mask = np.asarray(mask, dtype=bool)
+        LP = laplacian_sparse(n, np.asarray(u)[mask], np.asarray(v)[mask], np.asarray(w)[mask])[1:, 1:].tocsc()
+        solve = sla.splu(LP).solve
+    b = np.random.default_rng(seed).standard_normal(n - 1)
+    nb = float(np.linalg.norm(b))
+    x = np.zeros(n - 1)
+    r = b.copy()
+    z = solve(r)
+    p = z.copy()
+    rz = float(r @ z)
+    for it in range(1, maxiter + 1):
+        Ap = LG @ p
+        alpha = rz / float(p @ Ap)
+        x += alpha * p
+        r -= alpha * Ap
+        if float(np.linalg.norm(r)) <= tol * nb:
+            return it
+        z = solve(r)
+        rz_new = float(r @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return maxiter
+
+
 # ----------------------------------------------------------------------------
 # precision form: reference for the reduced-precision selection
 # ----------------------------------------------------------------------------

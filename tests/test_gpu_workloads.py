@@ -103,3 +103,20 @@ def test_surrogate_condition_number(S, orc):
     assert np.all(k[:, 2] < k[:, 3] / 5)       # far better than the tree alone
     assert med[1] <= 1.25 * med[0]            # pruning keeps the plain condition number
     assert med[2] <= med[0]                   # ranking reaches the plain default's median
+
+
+def test_pcg_iterations_fall_with_recovered_edges(S, orc):
+    """Downstream use (the paper's PCG evaluation): CG on the grounded Laplacian
+    of a 30^3 log-normal mesh, preconditioned by the FP32 GPU sparsifier."""
+    g = W.mesh3d(30, 30, 30, seed=300, wdist=("lognormal", 0.0, 1.5))
+    X0 = dev(W.random_block(g.n, 16, 301))
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    plain = orc.pcg_iterations(g.n, g.u, g.v, g.w, None)
+    its = []
+    for f in (0.0, 0.02, 0.05, 0.1, 0.2):
+        keep, _ = S.sfg_sparsify(g.n, u, v, w, X0, S.make_params(k=16, sweeps=20, frac=f, storage=torch.float32))
+        its.append(orc.pcg_iterations(g.n, g.u, g.v, g.w, keep.cpu().numpy() > 0))
+    print("PCG iterations: plain", plain, "tree / 2% / 5% / 10% / 20%:", its, flush=True)
+    assert its[0] < plain / 3
+    assert all(b < a for a, b in zip(its, its[1:]))
+    assert its[3] < its[0] / 8

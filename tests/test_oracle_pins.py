@@ -603,3 +603,26 @@ def test_gauss_seidel_against_jacobi_on_grid(orc):
             out.append(orc.kappa_sparse(g.n, g.u, g.v, g.w, r.keep > 0)[0])
     mj, m1, m5 = np.median(kj), np.median(kg1), np.median(kg5)
     assert m5 < mj < m1, (mj, m1, m5)
+
+
+# --------------------------------------------------------------------------- downstream PCG
+
+def test_pcg_special_cases(orc):
+    g = W.mesh3d(8, 7, 6, seed=5, wdist=("lognormal", 0.0, 1.0))
+    # the graph preconditioning itself: one iteration
+    assert orc.pcg_iterations(g.n, g.u, g.v, g.w, np.ones(g.m, bool)) == 1
+    # plain CG counts the same iterations as SciPy's CG with the same stopping rule
+    import scipy.sparse.linalg as sla
+
+    LG = orc.laplacian_sparse(g.n, g.u, g.v, g.w)[1:, 1:].tocsr()
+    b = np.random.default_rng(0).standard_normal(g.n - 1)
+    count = [0]
+
+    def cb(_):
+        count[0] += 1
+
+    sla.cg(LG, b, rtol=1e-3, atol=0.0, maxiter=10000, callback=cb)
+    assert abs(orc.pcg_iterations(g.n, g.u, g.v, g.w, None) - count[0]) <= 1
+    # a spanning-tree preconditioner beats none
+    tree = orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0] > 0
+    assert orc.pcg_iterations(g.n, g.u, g.v, g.w, tree) < count[0]
