@@ -133,6 +133,21 @@ sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega,
                       void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Random test vectors for the embedding (Sec. 3.2 smooths random vectors),
+ * drawn on the device: x0[i][c] (row-major, n-by-k, FP64) standard normal from
+ * the counter-based generator Philox4x32-10 (Salmon, Moraes, Dror, Shaw,
+ * SC'11) with Box-Muller.  Element pair j (elements 2j, 2j+1) takes counter
+ * (lo32 j, hi32 j, block, 0) and key (lo32 seed, hi32 seed); with output words
+ * r0..r3, u1 = ((r0:r1) >> 11) 2^-53, u2 = ((r2:r3) >> 11) 2^-53,
+ * rho = sqrt(-2 log(1 - u1)), z0 = rho cos(2 pi u2), z1 = rho sin(2 pi u2).
+ * The integer part is exact; the logarithm and trigonometric functions are
+ * the device math library's (within a few ulp of a host libm).
+ *   x0   out [n*k] FP64 (device)
+ * Errors: SFG_EINVAL.
+ */
+sfg_status sfg_random_block(int64_t n, int32_t k, uint64_t seed, uint32_t block, double *x0, void *stream);
+
+/*
  * Multicolouring for the Gauss-Seidel reading of the smoother (Sec. 3.2
  * relaxes L x = 0 by Gauss-Seidel steps).  Jones-Plassmann rounds with the
  * fixed priority (h(p), p), h(x) the integer mixer x ^= x>>16, x *= 0x7feb352d,
@@ -268,6 +283,7 @@ typedef struct {
                               and the report has one entry per round. */
     int32_t smoother;      /* sfg_smoother: damped Jacobi (default) or multicolour Gauss-Seidel; Gauss-Seidel
                               needs F64 or F32 storage and no band */
+    uint64_t seed;         /* with x0 == NULL: blocks drawn on the device by sfg_random_block(seed, index) */
 } sfg_params;
 
 /* Per-level report (host). */
@@ -299,7 +315,9 @@ typedef struct {
  *   the heaviest fine edge of each coarse sparsifier edge) and add the top
  *   f of that level's off-subgraph edges.
  *   x0         random blocks, FP64: level l uses rows [0, N_l) of the n-by-k
- *              block at x0 + l*n*k  (caller draws levels*n*k values)
+ *              block at x0 + l*n*k  (caller draws levels*n*k values; with
+ *              rounds R > 1, block r for round r); NULL: block i is drawn
+ *              on the device by sfg_random_block(n, k, p->seed, i)
  *   keep       out [m] uint8: 0 not in P, 1 in P before the final additions
  *              (the tree, or the mapped sparsifier), 2 recovered at level 0
  *              (in any round)

@@ -55,6 +55,10 @@ def _L():
         lib.orc_laplacian_csr.restype = ctypes.c_int
         lib.orc_smooth.argtypes = [I64, P, P, P, P, I32, I32, D, P, P]
         lib.orc_smooth.restype = None
+        lib.orc_philox4x32_10.argtypes = [P, P, P]
+        lib.orc_philox4x32_10.restype = None
+        lib.orc_random_block.argtypes = [I64, I32, ctypes.c_uint64, ctypes.c_uint32, P]
+        lib.orc_random_block.restype = None
         lib.orc_color.argtypes = [I64, P, P, P]
         lib.orc_color.restype = I32
         lib.orc_smooth_gs.argtypes = [I64, P, P, P, P, I32, I32, D, P, I32, P]
@@ -146,6 +150,22 @@ def smooth(csr: CSR, X, sweeps: int, omega: float = 0.5) -> np.ndarray:
     k = X.shape[1]
     _L().orc_smooth(csr.n, _p(csr.rowptr), _p(csr.col), _p(csr.val), _p(csr.deg), k, sweeps, omega,
                     _p(X), _p(Y))
+    return X
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block: 4 counter words and 2 key words to 4 words."""
+    c = np.asarray(ctr, dtype=np.uint32)
+    kk = np.asarray(key, dtype=np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    _L().orc_philox4x32_10(_p(c), _p(kk), _p(out))
+    return out
+
+
+def random_block(n: int, k: int, seed: int, block: int = 0) -> np.ndarray:
+    """n-by-k standard normals from (seed, block): Philox4x32-10 counters and Box-Muller."""
+    X = np.empty((n, k), dtype=np.float64)
+    _L().orc_random_block(n, k, ctypes.c_uint64(seed), ctypes.c_uint32(block), _p(X))
     return X
 
 

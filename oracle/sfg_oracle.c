@@ -502,3 +502,50 @@ void orc_center(int64_t n, int32_t k, double *X, double *mean)
     for (int64_t p = 0; p < n; ++p)
         for (int32_t c = 0; c < k; ++c) X[p * k + c] = X[p * k + c] - mean[c];
 }
+
+/* ------------------------------------------------------------------------ */
+/* Random test vectors (Sec. 3.2 starts from random vectors).  Counter-based */
+/* generator Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds   */
+/* of two 32x32->64-bit multiplies (constants 0xD2511F53, 0xCD9E8D57) mixing */
+/* the counter words with the key, the key bumped by (0x9E3779B9,            */
+/* 0xBB67AE85) between rounds.  Standard normals by Box-Muller: element pair */
+/* j of block b (row-major n-by-k, elements 2j and 2j+1) uses counter        */
+/* (lo32 j, hi32 j, b, 0) and key (lo32 seed, hi32 seed); with words r0..r3, */
+/* u1 = ((r0:r1) >> 11) 2^-53, u2 = ((r2:r3) >> 11) 2^-53,                   */
+/* rho = sqrt(-2 log(1 - u1)), z0 = rho cos(2 pi u2), z1 = rho sin(2 pi u2).  */
+/* ------------------------------------------------------------------------ */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) { k0 += 0x9E3779B9U; k1 += 0xBB67AE85U; }
+        const uint64_t p0 = (uint64_t)0xD2511F53U * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57U * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+void orc_random_block(int64_t n, int32_t k, uint64_t seed, uint32_t block, double *X)
+{
+    const int64_t total = n * (int64_t)k;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    const double two_pi = 6.283185307179586476925286766559;
+    for (int64_t j = 0; 2 * j < total; ++j) {
+        const uint32_t ctr[4] = {(uint32_t)j, (uint32_t)((uint64_t)j >> 32), block, 0};
+        uint32_t r[4];
+        orc_philox4x32_10(ctr, key, r);
+        const double u1 = (double)(((((uint64_t)r[0]) << 32) | r[1]) >> 11) * 0x1.0p-53;
+        const double u2 = (double)(((((uint64_t)r[2]) << 32) | r[3]) >> 11) * 0x1.0p-53;
+        const double rho = sqrt(-2.0 * log(1.0 - u1));
+        const double th = two_pi * u2;
+        X[2 * j] = rho * cos(th);
+        if (2 * j + 1 < total) X[2 * j + 1] = rho * sin(th);
+    }
+}

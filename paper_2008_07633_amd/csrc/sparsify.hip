@@ -17,6 +17,7 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
                size_t ws_bytes, hipStream_t s);
 size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
 size_t color_workspace_bytes(int64_t n);
+void random_block(int64_t n, int32_t k, uint64_t seed, uint32_t block, double *x, hipStream_t s);
 void color_graph(const sfg_csr *H, int32_t *color, int32_t *class_rows, std::vector<int32_t> &class_ptr, void *ws,
                  size_t ws_bytes, hipStream_t s);
 void smooth_gs(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
@@ -397,9 +398,16 @@ extern "C" sfg_status sfg_sparsify(int64_t n, int64_t m, const int32_t *u, const
     return sfg::guard([&] {
         hipStream_t s = sfg::as_stream(stream);
         sfg::check_params(p);
-        SFG_REQUIRE(x0 && keep, SFG_EINVAL, "sparsify: null pointer");
+        SFG_REQUIRE(keep, SFG_EINVAL, "sparsify: null pointer");
         sfg::DevArena A(s);
         sfg::validate_edges(n, m, u, v, w, wt, A, s);
+        if (!x0) {   // draw the blocks on the device: one per level or per round
+            const int32_t nb = p->levels > 1 ? p->levels : (p->rounds > 1 ? p->rounds : 1);
+            double *gen = A.alloc<double>((size_t)nb * n * p->k);
+            for (int32_t b = 0; b < nb; ++b)
+                sfg::random_block(n, p->k, p->seed, (uint32_t)b, gen + (size_t)b * n * p->k, s);
+            x0 = gen;
+        }
         if (rep) std::memset(rep, 0, sizeof(*rep));
         if (p->levels == 1)
             sfg::single_level_sparsify(n, m, u, v, w, wt, p, x0, keep, rep, A, s);

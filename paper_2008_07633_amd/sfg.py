@@ -36,7 +36,7 @@ SMOOTH_JACOBI, SMOOTH_GAUSS_SEIDEL = 0, 1
 EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores",
             "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify",
             "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam",
-            "sfg_color", "sfg_smooth_gs"]
+            "sfg_color", "sfg_smooth_gs", "sfg_random_block"]
 
 
 class SfgError(RuntimeError):
@@ -56,7 +56,7 @@ class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("k", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("frac", ctypes.c_double), ("embed", ctypes.c_int32),
                 ("storage", ctypes.c_int), ("final_f32", ctypes.c_int32), ("band", ctypes.c_double),
-                ("rounds", ctypes.c_int32), ("smoother", ctypes.c_int32)]
+                ("rounds", ctypes.c_int32), ("smoother", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class LevelReport(ctypes.Structure):
@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         L.sfg_mpnn_loss_grad.argtypes = [P, P, P, I64, P, P, P, P, P, P, P, P, P, S, P]
         L.sfg_mpnn_adam.argtypes = [P, P, P, P, I64, I64, D, D, D, D, P]
         L.sfg_color.argtypes = [P, P, P, P, P, P, S, P]
+        L.sfg_random_block.argtypes = [I64, I32, ctypes.c_uint64, ctypes.c_uint32, P, P]
         L.sfg_smooth_gs.argtypes = [P, P, P, I32, I32, I32, D, P, I, P, P, S, P]
         for name in EXPORTED:
             if name not in ("sfg_workspace_bytes", "sfg_last_error", "sfg_mpnn_param_count"):
@@ -196,6 +197,15 @@ def sfg_smooth(H: Csr, x0: torch.Tensor, sweeps: int, omega: float = 0.5, storag
     hs = H.struct()
     _check(lib().sfg_smooth(ctypes.byref(hs), k, sweeps, float(omega), _ptr(x0), st, int(bool(final_f32)),
                             _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out
+
+
+def sfg_random_block(n: int, k: int, seed: int, block: int = 0, device="cuda",
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """n-by-k FP64 standard normals drawn on the device (Philox4x32-10, Box-Muller)."""
+    if out is None:
+        out = torch.empty((n, k), dtype=torch.float64, device=device)
+    _check(lib().sfg_random_block(n, k, ctypes.c_uint64(seed), ctypes.c_uint32(block), _ptr(out), _stream()))
     return out
 
 
@@ -309,14 +319,15 @@ def sfg_coarsen(G: Csr, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, aff: 
 
 
 def make_params(levels=1, k=8, sweeps=10, omega=0.5, frac=0.05, embed=EMBED_SPARSIFIER, storage=F64,
-                final_f32=False, band=0.0, rounds=1, smoother=SMOOTH_JACOBI) -> Params:
+                final_f32=False, band=0.0, rounds=1, smoother=SMOOTH_JACOBI, seed=0) -> Params:
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
-    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds, smoother)
+    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds, smoother, seed)
 
 
-def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: torch.Tensor,
+def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: Optional[torch.Tensor],
                  params: Params, keep: Optional[torch.Tensor] = None):
-    """Sparsifier keep mask (0 off, 1 base sparsifier, 2 recovered) and the per-level report."""
+    """Sparsifier keep mask (0 off, 1 base sparsifier, 2 recovered) and the per-level report.
+    x0 None: the random blocks are drawn on the device from params.seed."""
     m = int(u.shape[0])
     if keep is None:
         keep = torch.empty(max(m, 1), dtype=torch.uint8, device=u.device)[:m]

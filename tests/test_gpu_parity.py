@@ -453,3 +453,26 @@ def test_gauss_seidel_unsupported_combinations(S):
         kw.setdefault("smoother", S.SMOOTH_GAUSS_SEIDEL)
         with pytest.raises(S.SfgError):
             S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), X0, S.make_params(k=4, sweeps=3, frac=0.1, **kw))
+
+
+# --------------------------------------------------------------------------- random blocks on the device
+
+@pytest.mark.parametrize("n,k,seed,block", [(1000, 16, 7, 0), (333, 3, 2 ** 40 + 5, 3), (1, 1, 0, 0)])
+def test_random_block_matches_oracle(S, orc, n, k, seed, block):
+    # the integer generator is exact; log/cos/sin are the device math library's
+    got = host(S.sfg_random_block(n, k, seed, block))
+    ref = orc.random_block(n, k, seed, block)
+    assert np.max(np.abs(got - ref) / np.maximum(1.0, np.abs(ref))) < 1e-14
+
+
+def test_sparsify_draws_blocks_from_the_seed(S, orc):
+    g = W.powergrid(80, 70, 0.02, seed=66)
+    k, T, f, seed = 16, 10, 0.1, 99
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), None, S.make_params(k=k, sweeps=T, frac=f, seed=seed))
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, orc.random_block(g.n, k, seed, 0), T, f)
+    assert np.array_equal(host(keep), ref.keep)
+    # rounds draw block r for round r
+    keep2, _ = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), None,
+                              S.make_params(k=k, sweeps=T, frac=f, seed=seed, rounds=3))
+    ref2 = orc.sparsify_rounds(g.n, g.u, g.v, g.w, [orc.random_block(g.n, k, seed, r) for r in range(3)], 3, T, f)
+    assert np.array_equal(host(keep2), ref2.keep)

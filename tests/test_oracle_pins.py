@@ -626,3 +626,41 @@ def test_pcg_special_cases(orc):
     # a spanning-tree preconditioner beats none
     tree = orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0] > 0
     assert orc.pcg_iterations(g.n, g.u, g.v, g.w, tree) < count[0]
+
+
+# --------------------------------------------------------------------------- random test vectors
+
+def test_philox_known_answers(orc):
+    # the known-answer values published with Philox4x32-10 (Salmon et al., SC'11)
+    cases = [([0, 0, 0, 0], [0, 0], [0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8]),
+             ([0xFFFFFFFF] * 4, [0xFFFFFFFF] * 2, [0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD]),
+             ([0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344], [0xA4093822, 0x299F31D0],
+              [0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1])]
+    for ctr, key, want in cases:
+        assert orc.philox4x32_10(ctr, key).tolist() == want
+
+
+def test_random_block_box_muller(orc):
+    n, k, seed, block = 1001, 3, 0x123456789ABCDEF, 7      # odd total: the last pair keeps z0 only
+    X = orc.random_block(n, k, seed, block).reshape(-1)
+    for j in (0, 1, 17, (n * k - 1) // 2):
+        r = orc.philox4x32_10([j & 0xFFFFFFFF, j >> 32, block, 0], [seed & 0xFFFFFFFF, seed >> 32])
+        u1 = float(((int(r[0]) << 32 | int(r[1])) >> 11)) * 2.0 ** -53
+        u2 = float(((int(r[2]) << 32 | int(r[3])) >> 11)) * 2.0 ** -53
+        rho = math.sqrt(-2.0 * math.log(1.0 - u1))
+        assert abs(X[2 * j] - rho * math.cos(2 * math.pi * u2)) <= 4e-16 * max(1.0, rho)
+        if 2 * j + 1 < n * k:
+            assert abs(X[2 * j + 1] - rho * math.sin(2 * math.pi * u2)) <= 4e-16 * max(1.0, rho)
+
+
+def test_random_block_is_standard_normal(orc):
+    from scipy import stats
+
+    X = orc.random_block(250000, 4, 2024, 0).reshape(-1)
+    N = X.size
+    assert abs(X.mean()) < 5 / math.sqrt(N)
+    assert abs(X.var() - 1) < 5 * math.sqrt(2 / N)
+    assert stats.kstest(X, "norm").pvalue > 1e-3
+    # blocks and seeds give different streams
+    assert not np.allclose(orc.random_block(100, 4, 2024, 1), orc.random_block(100, 4, 2024, 0))
+    assert not np.allclose(orc.random_block(100, 4, 2025, 0), orc.random_block(100, 4, 2024, 0))
