@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle comparison of the extra workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+        print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
 
@@ -83,11 +83,10 @@ def main():
         bench_workloads.run(args)
         return
 
-    cfg = 2
-    prm = W.config_params(cfg)
+    prm = W.workload_params("powergrid")
     k, T, frac, omega = prm["k"], prm["sweeps"], prm["frac"], 0.5
-    g = W.config_graph(cfg)
-    X0 = W.config_block(cfg, g.n)
+    g = W.workload_graph("powergrid")
+    X0 = W.workload_block("powergrid", g.n)
     f64 = args.dtype == "f64"
     wdt = torch.float64 if f64 else torch.float32
     sx = sw = 8 if f64 else 4

@@ -29,16 +29,16 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def cached_graph(cfg: int) -> W.Graph:
+def cached_graph(name: str) -> W.Graph:
     os.makedirs(CACHE, exist_ok=True)
-    path = os.path.join(CACHE, f"cfg{cfg}.npz")
+    path = os.path.join(CACHE, f"{name}.npz")
     if os.path.exists(path):
         z = np.load(path, allow_pickle=False)
         w32 = z["w32"] if "w32" in z else None
         return W.Graph(int(z["n"]), z["u"], z["v"], z["w"], name=str(z["name"]), w32=w32)
     t = time.time()
-    g = W.config_graph(cfg)
-    log(f"generated config {cfg} ({g.name}: {g.n} nodes, {g.m} edges) in {time.time() - t:.1f} s")
+    g = W.workload_graph(name)
+    log(f"generated workload {name} ({g.name}: {g.n} nodes, {g.m} edges) in {time.time() - t:.1f} s")
     extra = {"w32": g.w32} if g.w32 is not None else {}
     np.savez(path, n=g.n, u=g.u, v=g.v, w=g.w, name=g.name, **extra)
     return g
@@ -77,10 +77,10 @@ def to_dev(g: W.Graph, f32: bool = False):
 # ----------------------------------------------------------------------------- kNN: precision form
 
 def run_knn(args) -> dict:
-    g = cached_graph(3)
-    prm = W.config_params(3)
+    g = cached_graph("knn")
+    prm = W.workload_params("knn")
     k, T, f, band = prm["k"], prm["sweeps"], prm["frac"], prm["band"]
-    X0 = W.config_block(3, g.n)
+    X0 = W.workload_block("knn", g.n)
     u, v, w64 = to_dev(g)
     x0 = torch.from_numpy(X0).cuda()
     res = {}
@@ -121,14 +121,14 @@ def run_knn(args) -> dict:
 # ----------------------------------------------------------------------------- Chung-Lu: multilevel
 
 def run_chunglu(args) -> dict:
-    g = cached_graph(4)
-    prm = W.config_params(4)
+    g = cached_graph("chunglu")
+    prm = W.workload_params("chunglu")
     k, T, f, L = prm["k"], prm["sweeps"], prm["frac"], prm["levels"]
     u, v, w32 = to_dev(g, f32=True)
     log("drawing the per-level random blocks")
     x0 = torch.empty((L, g.n, k), dtype=torch.float64, device="cuda")
     for l in range(L):
-        x0[l] = torch.from_numpy(W.config_block(4, g.n, level=l)).cuda()
+        x0[l] = torch.from_numpy(W.workload_block("chunglu", g.n, level=l)).cuda()
     out = {}
     for name, storage in (("f32", torch.float32), ("f64", torch.float64)):
         p = S.make_params(levels=L, k=k, sweeps=T, frac=f, storage=storage)
@@ -160,7 +160,7 @@ def run_chunglu(args) -> dict:
 def run_mesh(args) -> dict:
     from paper_2008_07633_amd import surrogate as SG
 
-    prm = W.config_params(5)
+    prm = W.workload_params("mesh")
     k, T, f, cf = prm["k"], prm["sweeps"], prm["frac"], prm["cand_frac"]
     # ---- train on 50 seeded 40^3 meshes with the plain method's own FP32 scores
     t0 = time.time()
@@ -201,8 +201,8 @@ def run_mesh(args) -> dict:
     recall = {nm: {c: round(float(np.mean(x)), 4) for c, x in d.items()} for nm, d in rec.items()}
     log(f"recall on held-out meshes: {recall}")
     # ---- full 200^3 mesh: plain path vs pruned path, end to end on the device
-    g = cached_graph(5)
-    X0 = W.config_block(5, g.n)
+    g = cached_graph("mesh")
+    X0 = W.workload_block("mesh", g.n)
     u, v, w64 = to_dev(g)
     x0 = torch.from_numpy(X0).cuda()
     w32 = w64.float()

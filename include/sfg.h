@@ -43,7 +43,7 @@ typedef enum {
     SFG_ENOMEM = 3,        /* device allocation failed (sfg_sparsify only) */
     SFG_EHIP = 4,          /* HIP runtime error; message has the HIP error string */
     SFG_EWORKSPACE = 5,    /* workspace smaller than sfg_workspace_bytes() */
-    SFG_EUNSUPPORTED = 6,  /* valid request this build does not support (e.g. k > 64) */
+    SFG_EUNSUPPORTED = 6,  /* valid request the library does not support (e.g. k > 64) */
     SFG_ENUMERIC = 7       /* NaN/Inf met in scores */
 } sfg_status;
 

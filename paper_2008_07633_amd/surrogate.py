@@ -132,7 +132,7 @@ def features(pp: Prepared, norm: Optional[torch.Tensor]):
 
 
 def plain_scores(pp: Prepared, x0: torch.Tensor, sweeps: int, storage=torch.float32) -> torch.Tensor:
-    """The plain method's scores of the off-tree edges (the training target and the judge)."""
+    """The plain method's scores of the off-tree edges (the training target and the reference for recall)."""
     X = S.sfg_smooth(pp.T, x0, sweeps, 0.5, storage=storage)
     return S.sfg_edge_scores(X, pp.u, pp.v, pp.w32, cand=pp.cand, score_dtype=torch.float32)
 

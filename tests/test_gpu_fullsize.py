@@ -15,9 +15,9 @@ def test_powergrid_full_size_f64_identical(orc):
         pytest.skip("no GPU")
     from paper_2008_07633_amd import sfg as S
 
-    g = W.config_graph(2)
-    prm = W.config_params(2)
-    X0 = W.config_block(2, g.n)
+    g = W.workload_graph("powergrid")
+    prm = W.workload_params("powergrid")
+    X0 = W.workload_block("powergrid", g.n)
     ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, prm["sweeps"], prm["frac"])
     u, v, w = (torch.from_numpy(a).cuda() for a in (g.u, g.v, g.w))
     x0 = torch.from_numpy(X0).cuda()
@@ -46,9 +46,9 @@ def test_powergrid_full_size_f32_close(orc):
         pytest.skip("no GPU")
     from paper_2008_07633_amd import sfg as S
 
-    g = W.config_graph(2)
-    prm = W.config_params(2)
-    X0 = W.config_block(2, g.n)
+    g = W.workload_graph("powergrid")
+    prm = W.workload_params("powergrid")
+    X0 = W.workload_block("powergrid", g.n)
     ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, prm["sweeps"], prm["frac"])
     lr = ref.levels[0]
     u, v = torch.from_numpy(g.u).cuda(), torch.from_numpy(g.v).cuda()

@@ -39,7 +39,7 @@ def host(t):
 
 
 GRAPHS = {
-    "grid64": lambda: W.config_graph(1),
+    "grid64": lambda: W.workload_graph("grid64"),
     "rand1500": lambda: W.random_connected(1500, 4000, seed=71, wdist=("lognormal", 0.0, 1.0)),
     "pgrid_97": lambda: W.powergrid(97, 103, 0.02, seed=72),
     "mesh_13": lambda: W.mesh3d(13, 11, 9, seed=73),

@@ -32,10 +32,10 @@ def dev(a):
 
 
 def test_knn_full_size_precision(S, orc):
-    g = W.config_graph(3)
-    prm = W.config_params(3)
+    g = W.workload_graph("knn")
+    prm = W.workload_params("knn")
     k, T, f, band = prm["k"], prm["sweeps"], prm["frac"], prm["band"]
-    X0 = W.config_block(3, g.n)
+    X0 = W.workload_block("knn", g.n)
     ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, T, f)
     lr = ref.levels[0]
     u, v, w = dev(g.u), dev(g.v), dev(g.w)

@@ -412,8 +412,8 @@ def test_kappa_monotone_and_tree_bounds(orc):
 
 
 def test_sparsifier_structure(orc):
-    g = W.config_graph(1)
-    r = orc.sparsify_single(g.n, g.u, g.v, g.w, W.config_block(1, g.n), 10, 0.05)
+    g = W.workload_graph("grid64")
+    r = orc.sparsify_single(g.n, g.u, g.v, g.w, W.workload_block("grid64", g.n), 10, 0.05)
     lr = r.levels[0]
     assert lr.n_cand == 3969 and lr.k_sel == 199
     assert (r.keep == 1).sum() == g.n - 1 and (r.keep == 2).sum() == 199
@@ -512,7 +512,7 @@ def test_rounds_match_dense_brute_force(orc):
 def test_rounds_lower_the_condition_number(orc):
     # the 64x64 grid workload (K=8, T=10, f=5%): re-embedding on the grown
     # sparsifier in 5 rounds beats one pass with the same budget on every seed
-    g = W.config_graph(1)
+    g = W.workload_graph("grid64")
     k1, k5 = [], []
     for seed in range(5):
         X0s = [W.random_block(g.n, 8, 500 + 10 * seed + r) for r in range(5)]
@@ -594,7 +594,7 @@ def test_gauss_seidel_against_jacobi_on_grid(orc):
     # the 64x64 grid workload (K=8, T=10, f=5%), 5 seeds: plain Gauss-Seidel
     # (omega 1, the paper's wording) against the damped Jacobi reading at equal
     # sweeps; measured medians 543 (GS, omega 1), 457 (Jacobi), 429 (GS, omega 1/2)
-    g = W.config_graph(1)
+    g = W.workload_graph("grid64")
     kj, kg1, kg5 = [], [], []
     for seed in range(5):
         X0 = W.random_block(g.n, 8, 700 + seed)

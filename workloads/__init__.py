@@ -30,8 +30,8 @@ from .graphs import (  # noqa: F401
     mesh3d,
     random_connected,
     random_block,
-    config_graph,
-    config_params,
-    CONFIGS,
-    config_block,
+    workload_graph,
+    workload_params,
+    WORKLOADS,
+    workload_block,
 )

@@ -233,40 +233,42 @@ def random_block(n: int, k: int, seed: int) -> np.ndarray:
 
 
 # ----------------------------------------------------------------------------
-# named configurations
+# named workloads (graph seed; random blocks use seed 1000 + 10 * seed + index)
 # ----------------------------------------------------------------------------
 
-CONFIGS = {
-    1: dict(name="grid64x64", k=8, sweeps=10, frac=0.05, dtype="f64"),
-    2: dict(name="powergrid1000x1000+2%diag", k=16, sweeps=20, frac=0.10, dtype="f64"),
-    3: dict(name="knn3d_2M_k10", k=32, sweeps=20, frac=0.10, dtype="f16", band=0.01),
-    4: dict(name="chunglu_4M_g2.2", k=16, sweeps=20, frac=0.10, dtype="f32", levels=5),
-    5: dict(name="mesh200x200x200", k=16, sweeps=20, frac=0.10, dtype="f32", cand_frac=0.20),
+WORKLOADS = {
+    "grid64": dict(name="grid64x64", seed=1, k=8, sweeps=10, frac=0.05, dtype="f64"),
+    "powergrid": dict(name="powergrid1000x1000+2%diag", seed=2, k=16, sweeps=20, frac=0.10, dtype="f64"),
+    "knn": dict(name="knn3d_2M_k10", seed=3, k=32, sweeps=20, frac=0.10, dtype="f16", band=0.01),
+    "chunglu": dict(name="chunglu_4M_g2.2", seed=4, k=16, sweeps=20, frac=0.10, dtype="f32", levels=5),
+    "mesh": dict(name="mesh200x200x200", seed=5, k=16, sweeps=20, frac=0.10, dtype="f32", cand_frac=0.20),
 }
 
 
-def config_params(cfg: int) -> dict:
-    return dict(CONFIGS[cfg])
+def workload_params(name: str) -> dict:
+    return dict(WORKLOADS[name])
 
 
-def config_graph(cfg: int, scale: float = 1.0) -> Graph:
-    """Graph of configuration ``cfg``; ``scale`` < 1 gives a same-shaped smaller case."""
-    if cfg == 1:
-        return grid2d(64, 64, seed=1)
-    if cfg == 2:
+def workload_graph(name: str, scale: float = 1.0) -> Graph:
+    """Graph of a named workload; ``scale`` < 1 gives a same-shaped smaller case."""
+    seed = WORKLOADS[name]["seed"]
+    if name == "grid64":
+        return grid2d(64, 64, seed=seed)
+    if name == "powergrid":
         s = max(8, int(round(1000 * scale)))
-        return powergrid(s, s, 0.02, seed=2)
-    if cfg == 3:
-        return knn3d(max(2000, int(round(2_000_000 * scale))), 10, seed=3)
-    if cfg == 4:
+        return powergrid(s, s, 0.02, seed=seed)
+    if name == "knn":
+        return knn3d(max(2000, int(round(2_000_000 * scale))), 10, seed=seed)
+    if name == "chunglu":
         nn = max(4000, int(round(4_000_000 * scale)))
-        return chung_lu(nn, int(round(40_000_000 * scale)), 2.2, seed=4)
-    if cfg == 5:
+        return chung_lu(nn, int(round(40_000_000 * scale)), 2.2, seed=seed)
+    if name == "mesh":
         s = max(4, int(round(200 * scale ** (1.0 / 3.0))))
-        return mesh3d(s, s, s, seed=5)
-    raise ValueError(cfg)
+        return mesh3d(s, s, s, seed=seed)
+    raise ValueError(name)
 
 
-def config_block(cfg: int, n: int, level: int = 0, k: Optional[int] = None) -> np.ndarray:
-    kk = CONFIGS[cfg]["k"] if k is None else k
-    return random_block(n, kk, 1000 + 10 * cfg + level)
+def workload_block(name: str, n: int, level: int = 0, k: Optional[int] = None) -> np.ndarray:
+    """The workload's random block number ``level`` (a level or a round)."""
+    kk = WORKLOADS[name]["k"] if k is None else k
+    return random_block(n, kk, 1000 + 10 * WORKLOADS[name]["seed"] + level)
