@@ -510,6 +510,167 @@ def pcg_iterations(n, u, v, w, mask=None, tol=1e-3, maxiter=20000, seed=0) -> in
 
 
 # ----------------------------------------------------------------------------
+# sigma-driven stopping: spanning-tree solves and the condition-number estimate
+# ----------------------------------------------------------------------------
+
+@dataclass
+class Tree:
+    """A spanning tree rooted at node 0, laid out in depth-first preorder."""
+    n: int
+    order: np.ndarray    # int32[n]: node at each preorder position (order[0] = 0)
+    parent: np.ndarray   # int32[n]: preorder position of the parent (-1 at the root)
+    size: np.ndarray     # int32[n]: nodes in the subtree
+    pw: np.ndarray       # float64[n]: weight of the edge to the parent (0 at the root)
+    tdown: np.ndarray    # int32[n]: walk step that enters the node (-1 at the root)
+    tup: np.ndarray      # int32[n]: walk step that leaves it (-1 at the root)
+
+
+def tree_dfs(n: int, u, v, w, tree_mask) -> Tree:
+    """Depth-first walk of the spanning tree given by ``tree_mask`` from node 0.
+    A node's children are taken in ascending id order starting after its
+    parent and wrapping round (the root starts at its smallest neighbour).
+    Every traversal of a tree edge, down or up, is one walk step."""
+    u, v, w = _i32(u), _i32(v), _f64(w)
+    mk = np.asarray(tree_mask, dtype=bool)
+    tu, tv, tw = u[mk], v[mk], w[mk]
+    if tu.shape[0] != n - 1:
+        raise ValueError("tree must have n - 1 edges")
+    adj = [[] for _ in range(n)]
+    for a, b, c in zip(tu.tolist(), tv.tolist(), tw.tolist()):
+        adj[a].append((b, c))
+        adj[b].append((a, c))
+    for lst in adj:
+        lst.sort()
+    order, parent, size, pw, tdown, tup = [], [], [], [], [], []
+    pre = np.full(n, -1, dtype=np.int64)
+    step = 0
+
+    def visit(q, par_pre, weight, enter_step):
+        pre[q] = len(order)
+        order.append(q)
+        parent.append(par_pre)
+        size.append(1)
+        pw.append(weight)
+        tdown.append(enter_step)
+        tup.append(-1)
+
+    visit(0, -1, 0.0, -1)
+    # stack entries: [node, neighbours in visiting order, next index]
+    stack = [[0, [b for b, _ in adj[0]], 0]]
+    wt = [dict(lst) for lst in adj]
+    while stack:
+        top = stack[-1]
+        q, nbrs, i = top
+        if i < len(nbrs):
+            top[2] += 1
+            c = nbrs[i]
+            if pre[c] >= 0:
+                raise ValueError("tree edges contain a cycle")
+            visit(c, int(pre[q]), wt[q][c], step)
+            step += 1
+            ids = [b for b, _ in adj[c]]
+            j = ids.index(q)
+            stack.append([c, ids[j + 1:] + ids[:j], 0])
+        else:
+            stack.pop()
+            if stack:
+                tup[pre[q]] = step
+                step += 1
+                size[int(pre[stack[-1][0]])] += size[pre[q]]
+    if len(order) != n:
+        raise ValueError("tree edges do not span the graph")
+    return Tree(n, np.array(order, np.int32), np.array(parent, np.int32), np.array(size, np.int32),
+                np.array(pw, np.float64), np.array(tdown, np.int32), np.array(tup, np.int32))
+
+
+def tree_solve(tree: Tree, B) -> np.ndarray:
+    """x = L_T^+ b for every column: the tree Laplacian system with b projected
+    onto the complement of the all-one vector, solved by eliminating leaves
+    upward (each edge carries the net demand of the subtree below it) and
+    back-substituting potentials downward; the result has zero mean."""
+    B = _f64(B)
+    one = B.ndim == 1
+    B2 = B.reshape(B.shape[0], -1)
+    F = B2[tree.order] - B2.mean(axis=0)
+    for i in range(tree.n - 1, 0, -1):
+        F[tree.parent[i]] += F[i]
+    Xp = np.zeros_like(F)
+    for i in range(1, tree.n):
+        Xp[i] = Xp[tree.parent[i]] + F[i] / tree.pw[i]
+    X = np.empty_like(Xp)
+    X[tree.order] = Xp
+    X -= X.mean(axis=0)
+    return X.reshape(-1) if one else X
+
+
+def kappa_estimate(n, u, v, w, mask, Y0, steps: int) -> list:
+    """Lower estimate of lambda_max of the pencil (L_G, L_P), P the edges of
+    ``mask`` (a connected spanning subgraph of G with G's weights), by subspace
+    iteration Y <- L_P^+ L_G Y with Rayleigh-Ritz after every step.  Because
+    L_P <= L_G, lambda_min >= 1 and the relative condition number of Eq. 2 is
+    at most lambda_max; any Ritz value is at most lambda_max (Courant-Fischer).
+    L_P systems are solved exactly (sparse LU, node 0 grounded).  Returns the
+    largest Ritz value after each step."""
+    import scipy.linalg as dla
+    import scipy.sparse.linalg as sla
+
+    mask = np.asarray(mask, dtype=bool)
+    u, v, w = _i32(u), _i32(v), _f64(w)
+    LG = laplacian_sparse(n, u, v, w).tocsr()
+    LP = laplacian_sparse(n, u[mask], v[mask], w[mask]).tocsr()
+    lu = sla.splu(LP[1:, 1:].tocsc())
+
+    def solve(Z):
+        X = np.zeros_like(Z)
+        X[1:] = lu.solve(Z[1:])
+        return X - X.mean(axis=0)
+
+    Y = _f64(Y0).copy()
+    Y -= Y.mean(axis=0)
+    out = []
+    for _ in range(steps):
+        Yn = solve(LG @ Y)
+        A = Yn.T @ (LG @ Yn)
+        Bm = Yn.T @ (LP @ Yn)
+        A = 0.5 * (A + A.T)
+        Bm = 0.5 * (Bm + Bm.T)
+        theta, V = dla.eigh(A, Bm)
+        out.append(float(theta[-1]))
+        Y = Yn @ V
+    return out
+
+
+def sparsify_sigma(n, u, v, w, X0s, Y0s, sigma, frac, max_rounds, sweeps, est_steps, omega=0.5,
+                   embed="sparsifier"):
+    """Sigma-driven stopping (Alg. 1 takes sigma but never uses it): start
+    from the maximum-weight spanning tree and, while the condition-number
+    estimate exceeds sigma^2 (Eq. 2) and rounds remain, add the next
+    ceil(frac * off-tree edges) top-scored edges, each batch scored on the
+    sparsifier grown so far.  X0s[r] is round r's smoothing block, Y0s[j]
+    the starting block of the j-th estimate.  Returns (Result, estimates)."""
+    intree, comps = max_spanning_forest(n, u, v, w)
+    if comps != 1:
+        raise ValueError("graph is not connected")
+    base = intree.astype(bool)
+    keep = intree.astype(np.uint8)
+    q = ksel(frac, int((~base).sum()))
+    kappas = [kappa_estimate(n, u, v, w, base, Y0s[0], est_steps)[-1]]
+    results, X = [], None
+    r = 0
+    while kappas[-1] > sigma * sigma and r < max_rounds:
+        take = min(q, int((~base).sum()))
+        if take == 0:
+            break
+        lr, X = score_level(n, u, v, w, base, X0s[r], sweeps, omega, frac, embed, k_take=take)
+        keep[lr.chosen] = 2
+        base[lr.chosen] = True
+        results.append(lr)
+        r += 1
+        kappas.append(kappa_estimate(n, u, v, w, base, Y0s[r], est_steps)[-1])
+    return Result(keep, results, X), kappas
+
+
+# ----------------------------------------------------------------------------
 # precision form: reference for the reduced-precision selection
 # ----------------------------------------------------------------------------
 

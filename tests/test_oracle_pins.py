@@ -664,3 +664,145 @@ def test_random_block_is_standard_normal(orc):
     # blocks and seeds give different streams
     assert not np.allclose(orc.random_block(100, 4, 2024, 1), orc.random_block(100, 4, 2024, 0))
     assert not np.allclose(orc.random_block(100, 4, 2025, 0), orc.random_block(100, 4, 2024, 0))
+
+
+# --------------------------------------------------------------------------- sigma-driven stopping
+
+def _canon(n, pairs, w):
+    pairs = np.array(pairs, dtype=np.int64)
+    a, b = np.minimum(pairs[:, 0], pairs[:, 1]), np.maximum(pairs[:, 0], pairs[:, 1])
+    o = np.lexsort((b, a))
+    return a[o].astype(np.int32), b[o].astype(np.int32), np.asarray(w, dtype=np.float64)[o]
+
+
+def test_tree_dfs_hand_example(orc):
+    # node 4 is entered from 2; its neighbours 1, 2, 3, 5 are taken after 2 and wrap round: 3, 5, 1
+    u, v, w = _canon(6, [(0, 2), (1, 4), (2, 4), (3, 4), (4, 5)], [1.0, 2.0, 3.0, 4.0, 5.0])
+    t = orc.tree_dfs(6, u, v, w, np.ones(5, bool))
+    assert t.order.tolist() == [0, 2, 4, 3, 5, 1]
+    assert t.parent.tolist() == [-1, 0, 1, 2, 2, 2]
+    assert t.size.tolist() == [6, 5, 4, 1, 1, 1]
+    assert t.pw.tolist() == [0.0, 1.0, 3.0, 4.0, 5.0, 2.0]
+    assert t.tdown.tolist() == [-1, 0, 1, 2, 4, 6]
+    assert t.tup.tolist() == [-1, 9, 8, 3, 5, 7]
+
+
+@pytest.mark.parametrize("g", TINY + [W.grid2d(30, 30, seed=21)])
+def test_tree_dfs_invariants(orc, g):
+    tree = orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0] > 0
+    t = orc.tree_dfs(g.n, g.u, g.v, g.w, tree)
+    n = g.n
+    assert sorted(t.order.tolist()) == list(range(n)) and t.order[0] == 0
+    assert np.all(t.parent[1:] < np.arange(1, n)) and t.parent[0] == -1
+    # every subtree is the contiguous preorder range [i, i + size)
+    sizes = np.ones(n, dtype=np.int64)
+    for i in range(n - 1, 0, -1):
+        sizes[t.parent[i]] += sizes[i]
+    assert np.array_equal(sizes, t.size)
+    for i in range(1, n):
+        assert t.parent[i] <= i - 1 and i < t.parent[i] + t.size[t.parent[i]]
+    # the walk crosses each edge once each way: 2(n-1) distinct steps, a subtree's
+    # walk spans 2 size - 1 steps
+    steps = np.concatenate([t.tdown[1:], t.tup[1:]])
+    assert sorted(steps.tolist()) == list(range(2 * (n - 1)))
+    assert np.array_equal(t.tup[1:] - t.tdown[1:], 2 * t.size[1:] - 1)
+    # the parent edges are the tree edges, with their weights
+    pe = {(min(a, b), max(a, b)): c for a, b, c in zip(g.u[tree], g.v[tree], g.w[tree])}
+    for i in range(1, n):
+        a, b = int(t.order[i]), int(t.order[t.parent[i]])
+        assert pe[(min(a, b), max(a, b))] == t.pw[i]
+
+
+def test_tree_solve_against_pseudo_inverse(orc):
+    g = W.random_connected(40, 60, seed=31, wdist=("lognormal", 0.0, 1.0))
+    tree = orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0] > 0
+    t = orc.tree_dfs(g.n, g.u, g.v, g.w, tree)
+    B = np.random.default_rng(5).standard_normal((g.n, 3))
+    L = csgraph_laplacian(adjacency(g.n, g.u[tree], g.v[tree], g.w[tree]))
+    X = orc.tree_solve(t, B)
+    assert np.allclose(X, np.linalg.pinv(L) @ B, rtol=0, atol=1e-10 * np.abs(X).max())
+
+
+def test_tree_solve_path_closed_form(orc):
+    # unit path 0-1-...-(n-1), demand +1 at 0 and -1 at n-1: potentials fall by 1 per edge
+    n = 25
+    u, v, w = _canon(n, [(i, i + 1) for i in range(n - 1)], np.ones(n - 1))
+    t = orc.tree_dfs(n, u, v, w, np.ones(n - 1, bool))
+    b = np.zeros(n)
+    b[0], b[-1] = 1.0, -1.0
+    x = orc.tree_solve(t, b)
+    want = (n - 1) / 2.0 - np.arange(n)
+    assert np.allclose(x, want, rtol=0, atol=1e-13)
+
+
+def test_tree_solve_residual_on_grid(orc):
+    g = W.grid2d(40, 40, seed=22, wdist=("lognormal", 0.0, 1.0))
+    tree = orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0] > 0
+    t = orc.tree_dfs(g.n, g.u, g.v, g.w, tree)
+    B = np.random.default_rng(6).standard_normal((g.n, 4))
+    X = orc.tree_solve(t, B)
+    L = orc.laplacian_sparse(g.n, g.u[tree], g.v[tree], g.w[tree])
+    R = L @ X - (B - B.mean(axis=0))
+    assert np.abs(R).max() <= 1e-11 * np.abs(B).max() * math.sqrt(g.n)
+    assert np.abs(X.mean(axis=0)).max() <= 1e-12 * np.abs(X).max()
+
+
+def test_kappa_estimate_one_edge_closed_form(orc):
+    # G = cycle, P = G minus one edge e: L_G = L_P + w_e b b^T, so the pencil has one
+    # eigenvalue 1 + w_e * R_P(e) (R_P: the path's resistance) and all others 1
+    n = 60
+    rng = np.random.default_rng(7)
+    u, v, w = _canon(n, [(i, i + 1) for i in range(n - 1)] + [(0, n - 1)], rng.uniform(0.5, 2.0, n))
+    off = int(np.nonzero((u == 0) & (v == n - 1))[0][0])
+    mask = np.ones(n, bool)
+    mask[off] = False
+    want = 1.0 + w[off] * float(np.sum(1.0 / w[mask]))
+    th = orc.kappa_estimate(n, u, v, w, mask, rng.standard_normal((n, 3)), 12)
+    assert abs(th[-1] - want) <= 1e-10 * want
+    assert all(t <= want * (1 + 1e-12) for t in th)
+
+
+@pytest.mark.parametrize("frac", [0.0, 0.1])
+def test_kappa_estimate_bounds_dense(orc, frac):
+    g = W.grid2d(14, 14, seed=23, wdist=("lognormal", 0.0, 1.0))
+    base = orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0] > 0
+    mask = base.copy()
+    if frac:
+        lr, _ = orc.score_level(g.n, g.u, g.v, g.w, base, orc.random_block(g.n, 8, 3), 10, 0.5, frac)
+        mask[lr.chosen] = True
+    _, lmax, lmin = orc.kappa_dense(g.n, g.u, g.v, g.w, mask)
+    assert abs(lmin - 1.0) < 1e-9       # P inside G with G's weights: lambda_min = 1 here
+    th = orc.kappa_estimate(g.n, g.u, g.v, g.w, mask, orc.random_block(g.n, 8, 4), 40)
+    assert all(t <= lmax * (1 + 1e-9) for t in th)          # Ritz values never exceed lambda_max
+    assert th[-1] >= lmax * (1 - 1e-6)                      # and converge to it
+    assert th[4] >= 0.5 * lmax
+
+
+def test_sigma_stopping(orc):
+    g = W.grid2d(16, 16, seed=24, wdist=("lognormal", 0.0, 1.0))
+    n, k, frac, sweeps, est = g.n, 8, 0.05, 10, 8
+    X0s = [orc.random_block(n, k, 9, r) for r in range(16)]
+    Y0s = [orc.random_block(n, 4, 9, 64 + j) for j in range(17)]
+    base = orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0] > 0
+    q = orc.ksel(frac, int((~base).sum()))
+    # sigma large enough: the tree alone is accepted
+    res, kap = orc.sparsify_sigma(n, g.u, g.v, g.w, X0s, Y0s, 1e4, frac, 16, sweeps, est)
+    assert len(kap) == 1 and res.levels == [] and np.array_equal(res.keep, base.astype(np.uint8))
+    # a tight sigma: batches of q edges until the estimate drops below sigma^2 or the cap
+    sigma = math.sqrt(0.3 * kap[0])
+    res, kap = orc.sparsify_sigma(n, g.u, g.v, g.w, X0s, Y0s, sigma, frac, 16, sweeps, est)
+    r = len(res.levels)
+    assert r >= 1 and len(kap) == r + 1
+    assert kap[-1] <= sigma ** 2 and all(x > sigma ** 2 for x in kap[:-1])
+    assert int((res.keep == 2).sum()) == r * q
+    # the true condition number never rises as edges are added (L_P grows in the Loewner order)
+    mask = base.copy()
+    prev = orc.kappa_dense(n, g.u, g.v, g.w, mask)[1]
+    for lr in res.levels:
+        mask[lr.chosen] = True
+        cur = orc.kappa_dense(n, g.u, g.v, g.w, mask)[1]
+        assert cur <= prev * (1 + 1e-9)
+        prev = cur
+    # the round cap bounds the additions
+    res2, kap2 = orc.sparsify_sigma(n, g.u, g.v, g.w, X0s, Y0s, 1.0, frac, 2, sweeps, est)
+    assert len(res2.levels) == 2 and len(kap2) == 3
