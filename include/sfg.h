@@ -72,7 +72,9 @@ typedef enum {
     SFG_OP_COARSEN = 4,
     SFG_OP_MPNN_FORWARD = 5,   /* n nodes, t = activation dtype */
     SFG_OP_MPNN_TRAIN = 6,     /* n nodes, m = scored edges */
-    SFG_OP_COLOR = 7           /* n nodes */
+    SFG_OP_COLOR = 7,          /* n nodes */
+    SFG_OP_TREE_ORDER = 8,     /* n nodes, m edges */
+    SFG_OP_TREE_SOLVE = 9      /* n nodes, k columns */
 } sfg_op;
 
 /* Which graph's embedding scores the candidates (Sec. 3.5 derives the score
@@ -264,6 +266,97 @@ sfg_status sfg_coarsen(const sfg_csr *G, int64_t m, const int32_t *u, const int3
                        int32_t *cv, void *cw, int32_t *crep, void *ws, size_t ws_bytes,
                        void *stream);
 
+/*
+ * Spanning tree rooted at node 0, in depth-first preorder (views; owns
+ * nothing).  The walk from the root crosses every tree edge once down and
+ * once up; at each node it takes the neighbours in ascending id order,
+ * starting after the neighbour it came from (the root starts at its smallest
+ * neighbour).  A subtree is the contiguous preorder range [i, i + size[i]).
+ * Used by the condition-number estimate (Eq. 2) as the preconditioner of
+ * solves with the sparsifier Laplacian.
+ */
+typedef struct {
+    int64_t n;
+    const int32_t *order;  /* [n] node at preorder position i; order[0] = 0 */
+    const int32_t *parent; /* [n] preorder position of the parent; -1 at the root */
+    const int32_t *size;   /* [n] nodes in the subtree */
+    const double *pw;      /* [n] weight of the edge to the parent; 0 at the root */
+    const int32_t *tdown;  /* [n] walk step (0 .. 2n-3) entering the node; -1 at the root */
+    const int32_t *tup;    /* [n] walk step leaving it; -1 at the root */
+} sfg_tree;
+
+/*
+ * Preorder layout of the spanning tree formed by the edges with keep[e] == 1
+ * (the marking sfg_sparsify gives its tree).
+ *   n, m, u, v       canonical edge list; w of wt (must be SFG_F64)
+ *   keep             [m] uint8; exactly n - 1 edges equal 1
+ *   order, parent, size, tdown, tup  out [n] int32; pw out [n] double
+ *   ws               >= sfg_workspace_bytes(SFG_OP_TREE_ORDER, n, m, 0, SFG_F64)
+ * Synchronises.  Errors: SFG_EINVAL (count of marked edges is not n - 1,
+ * bad sizes, null pointer), SFG_ENOTCONN (the marked edges do not form a
+ * spanning tree), SFG_EWORKSPACE, SFG_EHIP.
+ */
+sfg_status sfg_tree_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                          const uint8_t *keep, int32_t *order, int32_t *parent, int32_t *size, double *pw,
+                          int32_t *tdown, int32_t *tup, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * x = L_T^+ b for each of the k columns (the pseudo-inverse of the tree
+ * Laplacian, Sec. 2.1): b is projected onto the complement of the all-one
+ * vector, the system is solved exactly (net demand below each edge, then
+ * potentials down from the root) and x has zero column means.
+ *   T      tree from sfg_tree_order
+ *   b, x   n-by-k FP64, node order; x may alias b
+ *   ws     >= sfg_workspace_bytes(SFG_OP_TREE_SOLVE, n, 0, k, SFG_F64)
+ * Asynchronous.  Errors: SFG_EINVAL (k outside 1..64, null pointer),
+ * SFG_EWORKSPACE.
+ */
+sfg_status sfg_tree_solve(const sfg_tree *T, int32_t k, const double *b, double *x, void *ws, size_t ws_bytes,
+                          void *stream);
+
+/* Parameters of the condition-number estimate (host struct). */
+typedef struct {
+    int32_t k;             /* block width, 1..32 and <= n - 1 (0 = 8) */
+    int32_t steps;         /* subspace-iteration steps, 1..64 (0 = 6) */
+    double tol;            /* inner solves: stop a column when ||r|| <= tol ||rhs|| (0 = 1e-2) */
+    int32_t max_iter;      /* inner solves: iteration cap per solve (0 = 20000) */
+    uint64_t seed;         /* with y0 == NULL: starting block sfg_random_block(n, k, seed, block) */
+    uint32_t block;
+} sfg_kappa_params;
+
+typedef struct {
+    double kappa;          /* estimate after the last step */
+    double ritz[64];       /* largest Ritz value after each step */
+    int32_t steps;
+    int64_t inner_iters;   /* preconditioned CG iterations over all steps */
+    int32_t max_inner;     /* most iterations of one solve */
+    int32_t unconverged;   /* solves that reached max_iter */
+    float ms;              /* wall time of the call */
+} sfg_kappa_report;
+
+/*
+ * Estimate of the relative condition number kappa(L_G, L_P) of Eq. 2 for a
+ * sparsifier P of G (P = the edges with keep[e] != 0, kept with G's
+ * weights).  Since L_P <= L_G the smallest eigenvalue of the pencil is at
+ * least 1, so kappa <= lambda_max; the estimate is the largest Ritz value of
+ * the pencil on the subspace after `steps` steps of Y <- L_P^+ L_G Y, which
+ * never exceeds lambda_max (Courant-Fischer) and approaches it from below.
+ * Solves with L_P run preconditioned conjugate gradients, the preconditioner
+ * being the exact solve with P's spanning tree (edges with keep[e] == 1).
+ *   n, m, u, v, w    canonical edge list of G, w of wt (F64 or F32)
+ *   keep             [m] uint8: 0 not in P, 1 tree edge of P, 2 other edge of P
+ *   kp               (host) parameters
+ *   y0               n-by-k FP64 starting block, or NULL (drawn from kp->seed)
+ *   rep              (host, may be NULL) per-step values and iteration counts
+ *   kappa            (host) out: the estimate
+ * Allocates its buffers (stream-ordered) and frees them before it returns.
+ * Synchronises.  Errors: SFG_EINVAL, SFG_ENOTCONN (the edges marked 1 are not
+ * a spanning tree), SFG_ENUMERIC (the block lost rank), SFG_ENOMEM, SFG_EHIP.
+ */
+sfg_status sfg_kappa_estimate(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w,
+                              sfg_dtype wt, const uint8_t *keep, const sfg_kappa_params *kp, const double *y0,
+                              double *kappa, sfg_kappa_report *rep, void *stream);
+
 /* Parameters of sfg_sparsify (host struct). */
 typedef struct {
     int32_t levels;        /* 1 = spanning tree + one scoring pass; >1 = Alg. 1 hierarchy */
@@ -284,6 +377,12 @@ typedef struct {
     int32_t smoother;      /* sfg_smoother: damped Jacobi (default) or multicolour Gauss-Seidel; Gauss-Seidel
                               needs F64 or F32 storage and no band */
     uint64_t seed;         /* with x0 == NULL: blocks drawn on the device by sfg_random_block(seed, index) */
+    double sigma;          /* > 0: sigma-driven stopping (single level).  Starting from the tree, while the
+                              condition-number estimate exceeds sigma^2 (Eq. 2) and fewer than `rounds`
+                              batches (0 = 16) were added, add the next ceil(frac * off-tree edges) top-scored
+                              edges, scored on the sparsifier grown so far; batch r smooths block r of x0.
+                              Estimate j starts from sfg_random_block(n, est.k, seed, 64 + j). */
+    sfg_kappa_params est;  /* estimate parameters (seed and block are ignored here) */
 } sfg_params;
 
 /* Per-level report (host). */
@@ -302,6 +401,10 @@ typedef struct {
 typedef struct {
     int32_t levels;
     sfg_level_report level[16];   /* index 0 = finest */
+    int32_t n_kappa;              /* sigma mode: estimates made (batches added + 1) */
+    double kappa[17];             /* sigma mode: estimate of the tree, then after each batch */
+    int64_t kappa_inner_iters;    /* sigma mode: inner iterations of all estimates */
+    float ms_kappa;               /* sigma mode: time spent estimating */
 } sfg_report;
 
 /*

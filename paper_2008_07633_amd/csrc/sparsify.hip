@@ -17,6 +17,8 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
                size_t ws_bytes, hipStream_t s);
 size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
 size_t color_workspace_bytes(int64_t n);
+size_t tree_order_workspace_bytes(int64_t n, int64_t m);
+size_t tree_solve_workspace_bytes(int64_t n, int32_t k);
 void random_block(int64_t n, int32_t k, uint64_t seed, uint32_t block, double *x, hipStream_t s);
 void color_graph(const sfg_csr *H, int32_t *color, int32_t *class_rows, std::vector<int32_t> &class_ptr, void *ws,
                  size_t ws_bytes, hipStream_t s);
@@ -313,6 +315,10 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
     }
 }
 
+void sigma_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
+                    const uint8_t *tree, const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep,
+                    DevArena &A, hipStream_t s);
+
 void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
                            const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep, DevArena &A,
                            hipStream_t s) {
@@ -326,6 +332,10 @@ void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t
     uint8_t *tree = A.alloc<uint8_t>(m + 1);
     const int64_t comps = spanning_tree_gpu(n, m, u, v, w64, SFG_F64, nullptr, tree, A, s);
     if (comps != 1) fail(SFG_ENOTCONN, "sparsify: graph has " + std::to_string(comps) + " components");
+    if (p->sigma > 0.0) {
+        sigma_sparsify(n, m, u, v, w64, w32, tree, p, x0, keep, rep, A, s);
+        return;
+    }
     const int32_t rounds = p->rounds > 1 ? p->rounds : 1;
     if (rep) rep->levels = rounds;
     if (rounds == 1) {
@@ -342,6 +352,62 @@ void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t
         score_level(n, m, u, v, w64, w32, keep, p, x0 + (size_t)r * n * p->k, keep,
                     rep ? &rep->level[r] : nullptr, A, s, q);
     }
+}
+
+struct KappaEstimator;
+KappaEstimator *make_kappa_estimator(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64,
+                                     const uint8_t *tree_marks, int32_t k, DevArena &A, hipStream_t s);
+double run_kappa_estimator(KappaEstimator *e, const uint8_t *keep, const sfg_kappa_params &kp, uint64_t seed,
+                           uint32_t block, sfg_kappa_report *rep);
+void free_kappa_estimator(KappaEstimator *e);
+sfg_kappa_params kappa_defaults(const sfg_kappa_params *in);
+void check_kappa_params(const sfg_kappa_params &p, int64_t n);
+
+// Sigma-driven stopping: from the tree, batches of ceil(frac * off-tree
+// edges) top-scored edges (each scored on the sparsifier grown so far) until
+// the estimate of kappa(L_G, L_P) is at most sigma^2 (Eq. 2) or the batch cap
+// is reached.  Estimate j starts from random block (seed, 64 + j).
+void sigma_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
+                    const uint8_t *tree, const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep,
+                    DevArena &A, hipStream_t s) {
+    hipLaunchKernelGGL(k_keep_init, dim3(grid_for(m, 256)), dim3(256), 0, s, m, tree, keep);
+    SFG_LAUNCH_CHECK();
+    const sfg_kappa_params kp = kappa_defaults(&p->est);
+    struct Holder {
+        KappaEstimator *e;
+        ~Holder() { free_kappa_estimator(e); }
+    } h{make_kappa_estimator(n, m, u, v, w64, keep, kp.k, A, s)};
+    const int32_t cap = p->rounds > 0 ? p->rounds : 16;
+    const int64_t n_off = m - (n - 1);
+    const int64_t q = (int64_t)std::ceil(p->frac * (double)n_off);
+    const double target = p->sigma * p->sigma;
+    int32_t j = 0;
+    auto estimate = [&]() {
+        sfg_kappa_report kr;
+        std::memset(&kr, 0, sizeof(kr));
+        const double kap = run_kappa_estimator(h.e, keep, kp, p->seed, 64u + (uint32_t)j, &kr);
+        if (rep) {
+            rep->kappa[j] = kap;
+            rep->n_kappa = j + 1;
+            rep->kappa_inner_iters += kr.inner_iters;
+            rep->ms_kappa += kr.ms;
+        }
+        ++j;
+        return kap;
+    };
+    double kap = estimate();
+    int32_t r = 0;
+    int64_t added = 0;
+    while (kap > target && r < cap) {
+        const int64_t take = std::min(q, n_off - added);
+        if (take <= 0) break;
+        score_level(n, m, u, v, w64, w32, keep, p, x0 + (size_t)r * n * p->k, keep,
+                    rep ? &rep->level[r] : nullptr, A, s, take);
+        added += take;
+        ++r;
+        kap = estimate();
+    }
+    if (rep) rep->levels = r;
 }
 
 void check_params(const sfg_params *p) {
@@ -362,6 +428,9 @@ void check_params(const sfg_params *p) {
     SFG_REQUIRE(p->smoother == SFG_SMOOTH_JACOBI ||
                     ((p->storage == SFG_F64 || p->storage == SFG_F32) && p->band == 0.0),
                 SFG_EUNSUPPORTED, "sparsify: Gauss-Seidel needs F64 or F32 storage and no band");
+    SFG_REQUIRE(p->sigma >= 0.0 && p->sigma == p->sigma, SFG_EINVAL, "sparsify: sigma must be >= 0");
+    SFG_REQUIRE(p->sigma == 0.0 || p->levels == 1, SFG_EUNSUPPORTED, "sparsify: sigma needs levels = 1");
+    SFG_REQUIRE(p->sigma == 0.0 || p->frac > 0.0, SFG_EINVAL, "sparsify: sigma needs frac > 0 (the batch size)");
 }
 
 }  // namespace sfg
@@ -376,6 +445,8 @@ extern "C" size_t sfg_workspace_bytes(int op, int64_t n, int64_t m, int32_t k, s
         case SFG_OP_MPNN_FORWARD: return sfg::mpnn_forward_workspace_bytes(n < 1 ? 1 : n, t);
         case SFG_OP_MPNN_TRAIN: return sfg::mpnn_train_workspace_bytes(n < 1 ? 1 : n, m < 1 ? 1 : m);
         case SFG_OP_COLOR: return sfg::color_workspace_bytes(n < 1 ? 1 : n);
+        case SFG_OP_TREE_ORDER: return sfg::tree_order_workspace_bytes(n < 1 ? 1 : n, m < 0 ? 0 : m);
+        case SFG_OP_TREE_SOLVE: return sfg::tree_solve_workspace_bytes(n < 1 ? 1 : n, k < 1 ? 1 : k);
         default: return 0;
     }
 }
@@ -399,10 +470,13 @@ extern "C" sfg_status sfg_sparsify(int64_t n, int64_t m, const int32_t *u, const
         hipStream_t s = sfg::as_stream(stream);
         sfg::check_params(p);
         SFG_REQUIRE(keep, SFG_EINVAL, "sparsify: null pointer");
+        if (p->sigma > 0.0) sfg::check_kappa_params(sfg::kappa_defaults(&p->est), n);
         sfg::DevArena A(s);
         sfg::validate_edges(n, m, u, v, w, wt, A, s);
         if (!x0) {   // draw the blocks on the device: one per level or per round
-            const int32_t nb = p->levels > 1 ? p->levels : (p->rounds > 1 ? p->rounds : 1);
+            const int32_t nb = p->levels > 1   ? p->levels
+                               : p->sigma > 0.0 ? (p->rounds > 0 ? p->rounds : 16)
+                                                : (p->rounds > 1 ? p->rounds : 1);
             double *gen = A.alloc<double>((size_t)nb * n * p->k);
             for (int32_t b = 0; b < nb; ++b)
                 sfg::random_block(n, p->k, p->seed, (uint32_t)b, gen + (size_t)b * n * p->k, s);

@@ -30,13 +30,14 @@ EMBED_SPARSIFIER, EMBED_GRAPH = 0, 1
 STATUS = {0: "SFG_OK", 1: "SFG_EINVAL", 2: "SFG_ENOTCONN", 3: "SFG_ENOMEM", 4: "SFG_EHIP",
           5: "SFG_EWORKSPACE", 6: "SFG_EUNSUPPORTED", 7: "SFG_ENUMERIC"}
 
-OP_MPNN_FORWARD, OP_MPNN_TRAIN, OP_COLOR = 5, 6, 7
+OP_MPNN_FORWARD, OP_MPNN_TRAIN, OP_COLOR, OP_TREE_ORDER, OP_TREE_SOLVE = 5, 6, 7, 8, 9
 SMOOTH_JACOBI, SMOOTH_GAUSS_SEIDEL = 0, 1
 
 EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores",
             "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify",
             "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam",
-            "sfg_color", "sfg_smooth_gs", "sfg_random_block"]
+            "sfg_color", "sfg_smooth_gs", "sfg_random_block", "sfg_tree_order", "sfg_tree_solve",
+            "sfg_kappa_estimate"]
 
 
 class SfgError(RuntimeError):
@@ -52,11 +53,29 @@ class CsrStruct(ctypes.Structure):
                 ("deg", ctypes.c_void_p), ("vt", ctypes.c_int)]
 
 
+class KappaParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("steps", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("block", ctypes.c_uint32)]
+
+
+class KappaReport(ctypes.Structure):
+    _fields_ = [("kappa", ctypes.c_double), ("ritz", ctypes.c_double * 64), ("steps", ctypes.c_int32),
+                ("inner_iters", ctypes.c_int64), ("max_inner", ctypes.c_int32), ("unconverged", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
+
+
+class TreeStruct(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("order", ctypes.c_void_p), ("parent", ctypes.c_void_p),
+                ("size", ctypes.c_void_p), ("pw", ctypes.c_void_p), ("tdown", ctypes.c_void_p),
+                ("tup", ctypes.c_void_p)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("k", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("frac", ctypes.c_double), ("embed", ctypes.c_int32),
                 ("storage", ctypes.c_int), ("final_f32", ctypes.c_int32), ("band", ctypes.c_double),
-                ("rounds", ctypes.c_int32), ("smoother", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("rounds", ctypes.c_int32), ("smoother", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("sigma", ctypes.c_double), ("est", KappaParams)]
 
 
 class LevelReport(ctypes.Structure):
@@ -68,7 +87,9 @@ class LevelReport(ctypes.Structure):
 
 
 class Report(ctypes.Structure):
-    _fields_ = [("levels", ctypes.c_int32), ("level", LevelReport * 16)]
+    _fields_ = [("levels", ctypes.c_int32), ("level", LevelReport * 16), ("n_kappa", ctypes.c_int32),
+                ("kappa", ctypes.c_double * 17), ("kappa_inner_iters", ctypes.c_int64),
+                ("ms_kappa", ctypes.c_float)]
 
 
 _lib = None
@@ -104,6 +125,9 @@ def lib() -> ctypes.CDLL:
         L.sfg_color.argtypes = [P, P, P, P, P, P, S, P]
         L.sfg_random_block.argtypes = [I64, I32, ctypes.c_uint64, ctypes.c_uint32, P, P]
         L.sfg_smooth_gs.argtypes = [P, P, P, I32, I32, I32, D, P, I, P, P, S, P]
+        L.sfg_tree_order.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P, P, P, P, S, P]
+        L.sfg_tree_solve.argtypes = [P, I32, P, P, P, S, P]
+        L.sfg_kappa_estimate.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P, P]
         for name in EXPORTED:
             if name not in ("sfg_workspace_bytes", "sfg_last_error", "sfg_mpnn_param_count"):
                 getattr(L, name).restype = I
@@ -318,16 +342,23 @@ def sfg_coarsen(G: Csr, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, aff: 
     return agg, int(nc.value), cu[:mc], cv[:mc], cw[:mc], crep[:mc]
 
 
+def make_kappa_params(k=8, steps=6, tol=1e-2, max_iter=20000, seed=0, block=0) -> KappaParams:
+    return KappaParams(k, steps, tol, max_iter, seed, block)
+
+
 def make_params(levels=1, k=8, sweeps=10, omega=0.5, frac=0.05, embed=EMBED_SPARSIFIER, storage=F64,
-                final_f32=False, band=0.0, rounds=1, smoother=SMOOTH_JACOBI, seed=0) -> Params:
+                final_f32=False, band=0.0, rounds=1, smoother=SMOOTH_JACOBI, seed=0, sigma=0.0,
+                est: Optional[KappaParams] = None) -> Params:
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
-    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds, smoother, seed)
+    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds, smoother, seed,
+                  sigma, est if est is not None else make_kappa_params())
 
 
 def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: Optional[torch.Tensor],
-                 params: Params, keep: Optional[torch.Tensor] = None):
+                 params: Params, keep: Optional[torch.Tensor] = None, info: Optional[dict] = None):
     """Sparsifier keep mask (0 off, 1 base sparsifier, 2 recovered) and the per-level report.
-    x0 None: the random blocks are drawn on the device from params.seed."""
+    x0 None: the random blocks are drawn on the device from params.seed.  ``info`` (a dict)
+    receives the condition-number estimates of sigma mode."""
     m = int(u.shape[0])
     if keep is None:
         keep = torch.empty(max(m, 1), dtype=torch.uint8, device=u.device)[:m]
@@ -338,7 +369,68 @@ def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: 
     for i in range(rep.levels):
         L = rep.level[i]
         levels.append({f: getattr(L, f) for f, _ in LevelReport._fields_})
+    if info is not None:
+        info["kappa"] = [float(rep.kappa[j]) for j in range(rep.n_kappa)]
+        info["kappa_inner_iters"] = int(rep.kappa_inner_iters)
+        info["ms_kappa"] = float(rep.ms_kappa)
     return keep, levels
+
+
+# ----------------------------------------------------------------------------- sigma-driven stopping
+
+class Tree:
+    """Device arrays of sfg_tree_order (preorder layout of a spanning tree rooted at 0)."""
+
+    def __init__(self, n, order, parent, size, pw, tdown, tup):
+        self.n, self.order, self.parent, self.size = n, order, parent, size
+        self.pw, self.tdown, self.tup = pw, tdown, tup
+
+    def struct(self) -> TreeStruct:
+        return TreeStruct(self.n, self.order.data_ptr(), self.parent.data_ptr(), self.size.data_ptr(),
+                          self.pw.data_ptr(), self.tdown.data_ptr(), self.tup.data_ptr())
+
+
+def sfg_tree_order(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, keep: torch.Tensor) -> Tree:
+    """Preorder layout of the spanning tree of the edges with keep == 1 (w must be float64)."""
+    dev = u.device
+    m = int(u.shape[0])
+    arr = [torch.empty(n, dtype=torch.int32, device=dev) for _ in range(5)]
+    pw = torch.empty(n, dtype=torch.float64, device=dev)
+    ws = _ws(sfg_workspace_bytes(OP_TREE_ORDER, n, m, 0, F64), dev)
+    order, parent, size, tdown, tup = arr
+    _check(lib().sfg_tree_order(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(keep), _ptr(order), _ptr(parent),
+                                _ptr(size), _ptr(pw), _ptr(tdown), _ptr(tup), _ptr(ws), ws.numel(), _stream()))
+    return Tree(n, order, parent, size, pw, tdown, tup)
+
+
+def sfg_tree_solve(tree: Tree, b: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = L_T^+ b per column (b: n-by-k float64, node order)."""
+    b2 = b.reshape(b.shape[0], -1)
+    k = int(b2.shape[1])
+    if out is None:
+        out = torch.empty_like(b2)
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_TREE_SOLVE, tree.n, 0, k, F64), b.device)
+    ts = tree.struct()
+    _check(lib().sfg_tree_solve(ctypes.byref(ts), k, _ptr(b2), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    return out.reshape(b.shape)
+
+
+def sfg_kappa_estimate(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, keep: torch.Tensor,
+                       params: Optional[KappaParams] = None, y0: Optional[torch.Tensor] = None):
+    """Estimate of kappa(L_G, L_P) for P = edges with keep != 0 (tree edges marked 1).
+    Returns (kappa, report dict)."""
+    m = int(u.shape[0])
+    kp = params if params is not None else make_kappa_params()
+    kap = ctypes.c_double(0.0)
+    rep = KappaReport()
+    _check(lib().sfg_kappa_estimate(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(keep), ctypes.byref(kp),
+                                    _ptr(y0), ctypes.byref(kap), ctypes.byref(rep), _stream()))
+    steps = int(rep.steps)
+    return float(kap.value), {"ritz": [float(rep.ritz[i]) for i in range(min(steps, 64))],
+                              "inner_iters": int(rep.inner_iters), "max_inner": int(rep.max_inner),
+                              "unconverged": int(rep.unconverged), "ms": float(rep.ms)}
 
 
 # ----------------------------------------------------------------------------- learned surrogate
