@@ -3,6 +3,7 @@
     python bench.py --workload knn      # 2M-point 3-D kNN, FP16/BF16 storage + FP64 band re-scoring
     python bench.py --workload chunglu  # 4M-node power-law graph, 5-level hierarchy (Alg. 1)
     python bench.py --workload mesh     # 200^3 mesh, plain FP32 path and the learned surrogate
+    python bench.py --workload sigma    # power grid: condition-number estimate and sigma-driven stopping
 
 Each prints one JSON line; all inputs are seeded and synthetic.  Accuracy
 against the oracle at these sizes is checked by tests/test_gpu_workloads.py.
@@ -289,8 +290,70 @@ def run_mesh(args) -> dict:
             "train_s": round(t_train, 2), "roofline_f32_sweep_tree": roof}
 
 
+# ----------------------------------------------------------------------------- power grid: sigma-driven stopping
+
+def cg_iteration_bytes(n: int, nnz_p: int, k: int) -> int:
+    """Algorithmic HBM bytes of one tree-preconditioned CG iteration on an n x k FP64 block: the
+    Laplacian product on P (CSR once, p read, Ap written), the update (p, Ap, x, r read; x, r
+    written), the tree solve (prefix sum of r: 2 passes; edge drops: S read, the 2n-row walk array
+    written, 20 B of tree layout per node; prefix sum of the walk: 2 passes of 2n rows; potentials:
+    walk, r read, z written, 4 B per node) and the direction update (z, p read; p written)."""
+    blk = 8 * n * k
+    lap = 4 * (n + 1) + 12 * nnz_p + 8 * n + 2 * blk
+    upd = 6 * blk
+    tree = 2 * blk + (blk + 20 * n + 2 * blk) + 4 * blk + (3 * blk + 4 * n)
+    return lap + upd + tree + 3 * blk
+
+
+def run_sigma(args) -> dict:
+    g = cached_graph("powergrid")
+    prm = W.workload_params("powergrid")
+    u, v, w = to_dev(g)
+    p = S.make_params(k=prm["k"], sweeps=prm["sweeps"], frac=prm["frac"], seed=1)
+    keep, _ = S.sfg_sparsify(g.n, u, v, w, None, p)
+    nnz_p = 2 * int((keep > 0).sum().item())
+    est = S.make_kappa_params()          # library defaults: 8 vectors, 6 steps, inner tol 1e-2
+    S.sfg_kappa_estimate(g.n, u, v, w, keep, est)    # warm-up
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(3):
+        kap, rep = S.sfg_kappa_estimate(g.n, u, v, w, keep, est)
+        runs.append((rep["ms"], kap, rep))
+    ms, kap, rep = sorted(runs, key=lambda r: r[0])[1]
+    it = rep["inner_iters"]
+    b_it = cg_iteration_bytes(g.n, nnz_p, est.k)
+    ms_it = ms / it
+    ach = b_it / (ms_it * 1e-3) / 1e9
+    log(f"kappa estimate: {kap:.2f} in {ms:.1f} ms, {it} CG iterations, {ms_it * 1e3:.1f} us each")
+    tree_keep = (keep == 1).to(torch.uint8)
+    kap_t, rep_t = S.sfg_kappa_estimate(g.n, u, v, w, tree_keep, est)
+    sig = []
+    for sigma2 in (400.0, 150.0):
+        info = {}
+        ps = S.make_params(k=prm["k"], sweeps=prm["sweeps"], frac=0.05, seed=1, sigma=math.sqrt(sigma2), rounds=16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        keep2, lv = S.sfg_sparsify(g.n, u, v, w, None, ps, info=info)
+        t1 = time.perf_counter()
+        sig.append({"sigma2": sigma2, "batches": len(lv), "kappa_estimates": [round(x, 2) for x in info["kappa"]],
+                    "recovered_edges": int((keep2 == 2).sum().item()), "ms_total": round((t1 - t0) * 1e3, 1),
+                    "ms_estimating": round(info["ms_kappa"], 1), "cg_iterations": info["kappa_inner_iters"]})
+        log(f"sigma^2 = {sigma2}: {len(lv)} batches, estimates {sig[-1]['kappa_estimates']}")
+    return {"metric": "condition-number estimate of the 10% sparsifier (sigma-driven stopping)",
+            "value": round(ms, 1), "unit": "ms", "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "sparsifier_edges": nnz_p // 2,
+                       "vectors": est.k, "steps": est.steps, "inner_tol": est.tol},
+            "kappa_estimate": round(kap, 3), "ritz_per_step": [round(x, 3) for x in rep["ritz"]],
+            "kappa_estimate_tree": round(kap_t, 1), "cg_iterations": it, "max_cg_per_solve": rep["max_inner"],
+            "us_per_cg_iteration": round(ms_it * 1e3, 1),
+            "roofline_cg_iteration": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                                      "algorithmic_bytes_per_iteration": b_it},
+            "sigma_runs": sig}
+
+
 def run(args) -> None:
-    fn = {"knn": run_knn, "chunglu": run_chunglu, "mesh": run_mesh}[args.workload]
+    fn = {"knn": run_knn, "chunglu": run_chunglu, "mesh": run_mesh, "sigma": run_sigma}[args.workload]
     out = fn(args)
     out["n_gpus"] = 1
     print(json.dumps(out), flush=True)

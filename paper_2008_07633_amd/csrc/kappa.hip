@@ -12,9 +12,13 @@
 //
 // Inner solves L_P Y = Z: conjugate gradients on all k columns at once
 // (per-column scalars in device memory, columns frozen once converged),
-// preconditioned by the exact solve with P's spanning tree (tree.hip).
-// HBM-bound: per iteration one Laplacian product on P, one tree solve and
-// three column reductions over n x k FP64 blocks.
+// preconditioned by the exact solve with P's spanning tree (tree.hip), each
+// solve after the first started from the Ritz pairs (X = Y diag(theta)).
+// Every block lives in the tree's preorder: G and P are relabelled once, so
+// the tree solve needs no gathers and tree neighbours sit in nearby rows.
+// HBM-bound: per iteration one Laplacian product on P (with p . Ap fused),
+// the CG update (with r . r fused) and the tree solve (two block prefix sums,
+// with r . z fused).
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -34,15 +38,17 @@ void tree_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const 
                 int32_t *tup, void *ws, size_t ws_bytes, hipStream_t s);
 size_t tree_solve_workspace_bytes(int64_t n, int32_t k);
 void tree_solve(const sfg_tree *T, int32_t k, const double *b, double *x, void *ws, size_t ws_bytes, hipStream_t s);
-size_t colsum_scratch_doubles(int32_t k);
-void block_colsum(int64_t rows, int32_t k, const double *x, double scale, double *out, double *scratch,
-                  hipStream_t s);
 void block_dot(int64_t rows, int32_t k, const double *x, const double *y, double *out, double *scratch,
                hipStream_t s);
 size_t gram_scratch_doubles(int32_t k);
 void block_gram(int64_t rows, int32_t k, const double *x, const double *y, double *out, double *scratch,
                 hipStream_t s);
 void convert_weights(const void *w, sfg_dtype wt, sfg_dtype want, int64_t m, void *out, hipStream_t s);
+uint32_t lane_grid(int64_t rows, int32_t k);
+size_t lane_partial_doubles(int32_t k);
+void finish_partials(int32_t nb, int32_t k, const double *partial, double *out, hipStream_t s);
+size_t tree_precond_workspace_bytes(int64_t n, int32_t k);
+void tree_precond_pre(const sfg_tree *T, int32_t k, const double *r, double *z, double *rz, void *ws, hipStream_t s);
 
 namespace {
 
@@ -63,19 +69,6 @@ __global__ void k_lap(int64_t n, int32_t k, const int32_t *__restrict__ rowptr, 
 
 __device__ __forceinline__ double safe_div(double a, double b) { return b != 0.0 ? a / b : 0.0; }
 
-// x += alpha p, r -= alpha Ap with alpha_c = rz_c / pAp_c on active columns
-__global__ void k_cg_step(int64_t n, int32_t k, uint32_t active, const double *__restrict__ rz,
-                          const double *__restrict__ pap, const double *__restrict__ p, const double *__restrict__ ap,
-                          double *__restrict__ x, double *__restrict__ r) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * k) return;
-    const int c = (int)(t % k);
-    if (!((active >> c) & 1u)) return;
-    const double a = safe_div(rz[c], pap[c]);
-    x[t] += a * p[t];
-    r[t] -= a * ap[t];
-}
-
 // p = z + beta p with beta_c = rz_new_c / rz_c on active columns
 __global__ void k_cg_dir(int64_t n, int32_t k, uint32_t active, const double *__restrict__ rz_new,
                          const double *__restrict__ rz, const double *__restrict__ z, double *__restrict__ p) {
@@ -91,10 +84,170 @@ __global__ void k_zero(int64_t cnt, double *__restrict__ x) {
     if (t < cnt) x[t] = 0.0;
 }
 
-__global__ void k_subtract_mean(int64_t n, int32_t k, const double *__restrict__ mean, double *__restrict__ x) {
+// ---- preorder relabelling: row i of the new CSR is row order[i] of the old
+// one, entries in the same order with columns renamed; sums per row keep
+// their order
+
+__global__ void k_inverse(int64_t n, const int32_t *__restrict__ order, int32_t *__restrict__ inv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) inv[order[i]] = (int32_t)i;
+}
+
+__global__ void k_perm_len(int64_t n, const int32_t *__restrict__ order, const int32_t *__restrict__ rowptr,
+                           int32_t *__restrict__ len) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t p = order[i];
+    len[i] = rowptr[p + 1] - rowptr[p];
+}
+
+__global__ void k_perm_fill(int64_t n, const int32_t *__restrict__ order, const int32_t *__restrict__ inv,
+                            const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                            const double *__restrict__ val, const double *__restrict__ deg,
+                            const int32_t *__restrict__ nrowptr, int32_t *__restrict__ ncol,
+                            double *__restrict__ nval, double *__restrict__ ndeg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t p = order[i];
+    const int32_t a = rowptr[p], e = rowptr[p + 1], b = nrowptr[i];
+    for (int32_t j = a; j < e; ++j) {
+        ncol[b + (j - a)] = inv[col[j]];
+        nval[b + (j - a)] = val[j];
+    }
+    ndeg[i] = deg[p];
+}
+
+__global__ void k_gather_rows(int64_t n, int32_t k, const int32_t *__restrict__ order, const double *__restrict__ src,
+                              double *__restrict__ dst) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * k) return;
-    x[t] -= mean[t % k];
+    const int64_t i = t / k;
+    const int c = (int)(t - i * k);
+    dst[t] = src[(int64_t)order[i] * k + c];
+}
+
+// ---- conjugate-gradient kernels in the row-lane layout: a workgroup is
+// G x k threads (G = 256 / k), thread (g, c) owns column c of rows
+// blockIdx * G + g + j * gridDim * G; per-workgroup column partial sums of a
+// product go to partial[blockIdx][c] (reduced in a fixed order afterwards)
+
+__device__ __forceinline__ void lane_reduce(double acc, int32_t k, double *sh, double *partial) {
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        const int G = kB / k;
+        double t = 0.0;
+        for (int g = 0; g < G; ++g) t += sh[g * k + threadIdx.x];
+        partial[(int64_t)blockIdx.x * k + threadIdx.x] = t;
+    }
+}
+
+// y = L_H x and partial sums of x . y
+__global__ __launch_bounds__(kB) void k_lap_dot(int64_t n, int32_t k, const int32_t *__restrict__ rowptr,
+                                                const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                const double *__restrict__ deg, const double *__restrict__ x,
+                                                double *__restrict__ y, double *__restrict__ partial) {
+    __shared__ double sh[kB];
+    const int G = kB / k;
+    const int g = threadIdx.x / k, c = threadIdx.x % k;
+    double acc = 0.0;
+    if (g < G)
+        for (int64_t p = (int64_t)blockIdx.x * G + g; p < n; p += (int64_t)gridDim.x * G) {
+            double a = 0.0;
+            for (int32_t j = rowptr[p], e = rowptr[p + 1]; j < e; ++j) a += val[j] * x[(int64_t)col[j] * k + c];
+            const double xp = x[p * k + c];
+            const double yp = deg[p] * xp - a;
+            y[p * k + c] = yp;
+            acc += xp * yp;
+        }
+    lane_reduce(acc, k, sh, partial);
+}
+
+// Same for even k, two adjacent columns per thread (16-byte loads and stores);
+// the sums are added in the same order as k_lap_dot's
+__global__ __launch_bounds__(kB) void k_lap_dot2(int64_t n, int32_t k, const int32_t *__restrict__ rowptr,
+                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                 const double *__restrict__ deg, const double *__restrict__ x,
+                                                 double *__restrict__ y, double *__restrict__ partial) {
+    __shared__ double sh[2 * kB];
+    const int kv = k >> 1;
+    const int G = kB / kv;
+    const int g = threadIdx.x / kv, c2 = threadIdx.x % kv;
+    double acc0 = 0.0, acc1 = 0.0;
+    if (g < G)
+        for (int64_t p = (int64_t)blockIdx.x * G + g; p < n; p += (int64_t)gridDim.x * G) {
+            double a0 = 0.0, a1 = 0.0;
+            for (int32_t j = rowptr[p], e = rowptr[p + 1]; j < e; ++j) {
+                const double w = val[j];
+                const double2 xv = *reinterpret_cast<const double2 *>(x + (int64_t)col[j] * k + 2 * c2);
+                a0 += w * xv.x;
+                a1 += w * xv.y;
+            }
+            const double2 xp = *reinterpret_cast<const double2 *>(x + p * k + 2 * c2);
+            const double d = deg[p];
+            double2 yp;
+            yp.x = d * xp.x - a0;
+            yp.y = d * xp.y - a1;
+            *reinterpret_cast<double2 *>(y + p * k + 2 * c2) = yp;
+            acc0 += xp.x * yp.x;
+            acc1 += xp.y * yp.y;
+        }
+    sh[2 * threadIdx.x] = acc0;
+    sh[2 * threadIdx.x + 1] = acc1;
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        const int cc = threadIdx.x >> 1, half = threadIdx.x & 1;
+        double t = 0.0;
+        for (int gg = 0; gg < G; ++gg) t += sh[2 * (gg * kv + cc) + half];
+        partial[(int64_t)blockIdx.x * k + threadIdx.x] = t;
+    }
+}
+
+// r = z - L_H x
+__global__ void k_lap_resid(int64_t n, int32_t k, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                            const double *__restrict__ val, const double *__restrict__ deg,
+                            const double *__restrict__ x, const double *__restrict__ z, double *__restrict__ r) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    const int64_t p = t / k;
+    const int c = (int)(t - p * k);
+    double a = 0.0;
+    for (int32_t j = rowptr[p], e = rowptr[p + 1]; j < e; ++j) a += val[j] * x[(int64_t)col[j] * k + c];
+    r[t] = z[t] - (deg[p] * x[t] - a);
+}
+
+// x += alpha p, r -= alpha Ap (alpha_c = rz_c / pAp_c on active columns) and partial sums of r . r
+__global__ __launch_bounds__(kB) void k_cg_step_rr(int64_t n, int32_t k, uint32_t active,
+                                                   const double *__restrict__ rz, const double *__restrict__ pap,
+                                                   const double *__restrict__ p, const double *__restrict__ ap,
+                                                   double *__restrict__ x, double *__restrict__ r,
+                                                   double *__restrict__ partial) {
+    __shared__ double sh[kB];
+    const int G = kB / k;
+    const int g = threadIdx.x / k, c = threadIdx.x % k;
+    const bool on = (active >> c) & 1u;
+    const double a = on ? safe_div(rz[c], pap[c]) : 0.0;
+    double acc = 0.0;
+    if (g < G)
+        for (int64_t i = (int64_t)blockIdx.x * G + g; i < n; i += (int64_t)gridDim.x * G) {
+            const int64_t t = i * k + c;
+            double ri = r[t];
+            if (on) {
+                x[t] += a * p[t];
+                ri -= a * ap[t];
+                r[t] = ri;
+            }
+            acc += ri * ri;
+        }
+    lane_reduce(acc, k, sh, partial);
+}
+
+// x = y diag(theta): the Ritz pairs' image under L_P^+ L_G, a warm start
+__global__ void k_scale_cols(int64_t n, int32_t k, const double *__restrict__ y, const double *__restrict__ theta,
+                             double *__restrict__ x) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    x[t] = y[t] * theta[t % k];
 }
 
 // out = X V for an n x k block and a k x k matrix V (row-major)
@@ -206,26 +359,53 @@ bool gen_eig(int k, std::vector<double> A, std::vector<double> B, std::vector<do
 
 // ------------------------------------------------------------------ estimator
 
+// Preorder CSR (F64) of one graph.
+struct PreCsr {
+    int32_t *rowptr, *col, *len;
+    double *val, *deg;
+};
+
 struct KappaEstimator {
     int64_t n, m;
     int32_t k;
     const int32_t *u, *v;
     const double *w64;
     hipStream_t s;
-    // G and P (F64 CSR), the tree
-    int32_t *g_rowptr, *g_col, *g_eid, *p_rowptr, *p_col, *p_eid;
-    double *g_val, *g_deg, *p_val, *p_deg;
-    int32_t *t_order, *t_parent, *t_size, *t_tdown, *t_tup;
+    // CSR in node order (build target) and in the tree's preorder
+    int32_t *o_rowptr, *o_col, *o_eid;
+    double *o_val, *o_deg;
+    PreCsr G, P;
+    int32_t *scan_scr;
+    int32_t *t_order, *t_parent, *t_size, *t_tdown, *t_tup, *inv;
     double *t_pw;
     sfg_tree T;
-    void *csr_ws;
+    void *csr_ws, *pre_ws;
     size_t csr_wsb;
-    void *ts_ws;
-    size_t ts_wsb;
-    // n x k blocks
+    // n x k blocks in preorder
     double *Y, *Z, *X, *R, *Zp, *Pd, *AP, *W, *VP;
-    double *dev_small;   // rz (2 x 64), pap, rr, rr0, means, A, B, V
-    double *red_scr, *gram_scr;
+    double *small, *part, *gram_scr;
+
+    PreCsr alloc_pre(DevArena &A) {
+        PreCsr c;
+        c.rowptr = A.alloc<int32_t>(n + 1);
+        c.len = A.alloc<int32_t>(n + 1);
+        c.col = A.alloc<int32_t>(2 * m + 1);
+        c.val = A.alloc<double>(2 * m + 1);
+        c.deg = A.alloc<double>(n + 1);
+        return c;
+    }
+
+    // node-order CSR of the edges with mask != 0 (NULL = all), relabelled into preorder
+    void build_pre(const uint8_t *mask, PreCsr &c) {
+        build_csr(n, m, u, v, w64, SFG_F64, mask, o_rowptr, o_col, o_val, o_eid, o_deg, csr_ws, csr_wsb, s);
+        const dim3 gn(grid_for(n, kB)), b(kB);
+        hipLaunchKernelGGL(k_perm_len, gn, b, 0, s, n, t_order, o_rowptr, c.len);
+        SFG_LAUNCH_CHECK();
+        exclusive_scan_i32(c.len, c.rowptr, n, scan_scr, s);
+        hipLaunchKernelGGL(k_perm_fill, gn, b, 0, s, n, t_order, inv, o_rowptr, o_col, o_val, o_deg, c.rowptr,
+                           c.col, c.val, c.deg);
+        SFG_LAUNCH_CHECK();
+    }
 
     KappaEstimator(int64_t n_, int64_t m_, const int32_t *u_, const int32_t *v_, const double *w64_,
                    const uint8_t *tree_marks, int32_t k_, DevArena &A, hipStream_t s_)
@@ -233,41 +413,41 @@ struct KappaEstimator {
         const size_t nk = (size_t)n * k;
         csr_wsb = csr_workspace_bytes(n, m);
         csr_ws = A.raw(csr_wsb);
-        g_rowptr = A.alloc<int32_t>(n + 1);
-        g_col = A.alloc<int32_t>(2 * m + 1);
-        g_eid = A.alloc<int32_t>(2 * m + 1);
-        g_val = A.alloc<double>(2 * m + 1);
-        g_deg = A.alloc<double>(n + 1);
-        p_rowptr = A.alloc<int32_t>(n + 1);
-        p_col = A.alloc<int32_t>(2 * m + 1);
-        p_eid = A.alloc<int32_t>(2 * m + 1);
-        p_val = A.alloc<double>(2 * m + 1);
-        p_deg = A.alloc<double>(n + 1);
-        build_csr(n, m, u, v, w64, SFG_F64, nullptr, g_rowptr, g_col, g_val, g_eid, g_deg, csr_ws, csr_wsb, s);
+        o_rowptr = A.alloc<int32_t>(n + 1);
+        o_col = A.alloc<int32_t>(2 * m + 1);
+        o_eid = A.alloc<int32_t>(2 * m + 1);
+        o_val = A.alloc<double>(2 * m + 1);
+        o_deg = A.alloc<double>(n + 1);
+        scan_scr = A.alloc<int32_t>(scan_scratch_ints(n + 1));
         t_order = A.alloc<int32_t>(n + 1);
         t_parent = A.alloc<int32_t>(n + 1);
         t_size = A.alloc<int32_t>(n + 1);
         t_tdown = A.alloc<int32_t>(n + 1);
         t_tup = A.alloc<int32_t>(n + 1);
         t_pw = A.alloc<double>(n + 1);
+        inv = A.alloc<int32_t>(n + 1);
         {
             const size_t b = tree_order_workspace_bytes(n, m);
             tree_order(n, m, u, v, w64, SFG_F64, tree_marks, t_order, t_parent, t_size, t_pw, t_tdown, t_tup,
                        A.raw(b), b, s);
         }
         T = sfg_tree{n, t_order, t_parent, t_size, t_pw, t_tdown, t_tup};
-        ts_wsb = tree_solve_workspace_bytes(n, k);
-        ts_ws = A.raw(ts_wsb);
+        hipLaunchKernelGGL(k_inverse, dim3(grid_for(n, kB)), dim3(kB), 0, s, n, t_order, inv);
+        SFG_LAUNCH_CHECK();
+        G = alloc_pre(A);
+        P = alloc_pre(A);
+        build_pre(nullptr, G);
+        pre_ws = A.raw(tree_precond_workspace_bytes(n, k));
         double **blocks[] = {&Y, &Z, &X, &R, &Zp, &Pd, &AP, &W, &VP};
-        for (double **b : blocks) *b = A.alloc<double>(nk + 1);
-        dev_small = A.alloc<double>(16 * 64 + 3 * 32 * 32);
-        red_scr = A.alloc<double>(colsum_scratch_doubles(k));
+        for (double **bl : blocks) *bl = A.alloc<double>(nk + 1);
+        small = A.alloc<double>(16 * 64 + 3 * 32 * 32);
+        part = A.alloc<double>(lane_partial_doubles(k));
         gram_scr = A.alloc<double>(gram_scratch_doubles(k));
     }
 
-    void lap(bool on_g, const double *x, double *y) {
-        hipLaunchKernelGGL(k_lap, dim3(grid_for(n * k, kB)), dim3(kB), 0, s, n, k, on_g ? g_rowptr : p_rowptr,
-                           on_g ? g_col : p_col, on_g ? g_val : p_val, on_g ? g_deg : p_deg, x, y);
+    void lap(const PreCsr &c, const double *x, double *y) {
+        hipLaunchKernelGGL(k_lap, dim3(grid_for(n * k, kB)), dim3(kB), 0, s, n, k, c.rowptr, c.col, c.val, c.deg, x,
+                           y);
         SFG_LAUNCH_CHECK();
     }
 
@@ -278,25 +458,34 @@ struct KappaEstimator {
         return h;
     }
 
-    // X = L_P^+ Z by tree-preconditioned CG, all columns at once.  Returns
-    // the iterations taken; *hit_cap set when the cap was reached.
-    int64_t solve(double tol, int32_t max_iter, bool *hit_cap) {
-        double *rz0 = dev_small, *rz1 = dev_small + 64, *pap = dev_small + 128, *rr = dev_small + 192,
-               *rr0 = dev_small + 256;
+    // X = L_P^+ Z (up to constants) by tree-preconditioned CG on all columns,
+    // from X = Y diag(theta) when theta is given, else from 0.  A column stops
+    // when ||r|| <= tol ||Z||.  Returns the iterations; *hit_cap at the cap.
+    int64_t solve(double tol, int32_t max_iter, const double *theta, bool *hit_cap) {
+        double *rz0 = small, *rz1 = small + 64, *pap = small + 128, *rr = small + 192, *zz = small + 256;
         const dim3 g(grid_for(n * k, kB)), b(kB);
-        hipLaunchKernelGGL(k_zero, g, b, 0, s, n * k, X);
-        SFG_LAUNCH_CHECK();
-        SFG_HIP(hipMemcpyAsync(R, Z, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
-        block_dot(n, k, R, R, rr0, red_scr, s);
-        const std::vector<double> h0 = to_host(rr0, k);
+        const uint32_t lg = lane_grid(n, k);
+        const uint32_t lg2 = k % 2 == 0 ? lane_grid(n, k / 2) : lg;   // two columns per thread
+        block_dot(n, k, Z, Z, zz, part, s);
+        if (theta) {
+            hipLaunchKernelGGL(k_scale_cols, g, b, 0, s, n, k, Y, theta, X);
+            SFG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_lap_resid, g, b, 0, s, n, k, P.rowptr, P.col, P.val, P.deg, X, Z, R);
+            SFG_LAUNCH_CHECK();
+        } else {
+            hipLaunchKernelGGL(k_zero, g, b, 0, s, n * k, X);
+            SFG_LAUNCH_CHECK();
+            SFG_HIP(hipMemcpyAsync(R, Z, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+        }
+        block_dot(n, k, R, R, rr, part, s);
+        const std::vector<double> hz = to_host(zz, k), h0 = to_host(rr, k);
         uint32_t active = 0;
         for (int c = 0; c < k; ++c)
-            if (h0[c] > 0.0) active |= 1u << c;
+            if (h0[c] > tol * tol * hz[c]) active |= 1u << c;
         *hit_cap = false;
         if (!active) return 0;
-        tree_solve(&T, k, R, Zp, ts_ws, ts_wsb, s);
+        tree_precond_pre(&T, k, R, Zp, rz0, pre_ws, s);
         SFG_HIP(hipMemcpyAsync(Pd, Zp, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
-        block_dot(n, k, R, Zp, rz0, red_scr, s);
         const int kCheck = 4;
         int64_t it = 0;
         while (active) {
@@ -305,53 +494,60 @@ struct KappaEstimator {
                 break;
             }
             ++it;
-            lap(false, Pd, AP);
-            block_dot(n, k, Pd, AP, pap, red_scr, s);
-            hipLaunchKernelGGL(k_cg_step, g, b, 0, s, n, k, active, rz0, pap, Pd, AP, X, R);
+            if (k % 2 == 0)
+                hipLaunchKernelGGL(k_lap_dot2, dim3(lg2), dim3(kB), 0, s, n, k, P.rowptr, P.col, P.val, P.deg, Pd, AP,
+                                   part);
+            else
+                hipLaunchKernelGGL(k_lap_dot, dim3(lg), dim3(kB), 0, s, n, k, P.rowptr, P.col, P.val, P.deg, Pd, AP,
+                                   part);
             SFG_LAUNCH_CHECK();
-            tree_solve(&T, k, R, Zp, ts_ws, ts_wsb, s);
-            block_dot(n, k, R, Zp, rz1, red_scr, s);
+            finish_partials((int32_t)(k % 2 == 0 ? lg2 : lg), k, part, pap, s);
+            hipLaunchKernelGGL(k_cg_step_rr, dim3(lg), dim3(kB), 0, s, n, k, active, rz0, pap, Pd, AP, X, R, part);
+            SFG_LAUNCH_CHECK();
+            finish_partials((int32_t)lg, k, part, rr, s);
+            tree_precond_pre(&T, k, R, Zp, rz1, pre_ws, s);
             hipLaunchKernelGGL(k_cg_dir, g, b, 0, s, n, k, active, rz1, rz0, Zp, Pd);
             SFG_LAUNCH_CHECK();
             std::swap(rz0, rz1);
             if (it % kCheck == 0 || it == max_iter) {
-                block_dot(n, k, R, R, rr, red_scr, s);
                 const std::vector<double> h = to_host(rr, k);
                 for (int c = 0; c < k; ++c)
-                    if (((active >> c) & 1u) && !(h[c] > tol * tol * h0[c])) active &= ~(1u << c);
+                    if (((active >> c) & 1u) && !(h[c] > tol * tol * hz[c])) active &= ~(1u << c);
             }
         }
         return it;
     }
 
     // one estimate for the sparsifier keep != 0 (its edges marked 1 must be
-    // the tree this estimator was built with)
+    // the tree this estimator was built with); y0 in node order or NULL
     double run(const uint8_t *keep, const sfg_kappa_params &kp, const double *y0, uint64_t seed, uint32_t block,
                sfg_kappa_report *rep) {
         const auto t0 = std::chrono::steady_clock::now();
-        build_csr(n, m, u, v, w64, SFG_F64, keep, p_rowptr, p_col, p_val, p_eid, p_deg, csr_ws, csr_wsb, s);
-        const size_t nk = (size_t)n * k;
-        if (y0)
-            SFG_HIP(hipMemcpyAsync(Y, y0, nk * sizeof(double), hipMemcpyDeviceToDevice, s));
-        else
-            random_block(n, k, seed, block, Y, s);
-        double *mean = dev_small + 320, *Ad = dev_small + 16 * 64, *Bd = Ad + 32 * 32, *Vd = Bd + 32 * 32;
+        build_pre(keep, P);
         const dim3 g(grid_for(n * k, kB)), b(kB);
-        block_colsum(n, k, Y, 1.0 / (double)n, mean, red_scr, s);
-        hipLaunchKernelGGL(k_subtract_mean, g, b, 0, s, n, k, mean, Y);
+        // starting block (node order) into preorder; constants need no removal: they
+        // are in the kernel of both Laplacians
+        if (y0) {
+            hipLaunchKernelGGL(k_gather_rows, g, b, 0, s, n, k, t_order, y0, Y);
+        } else {
+            random_block(n, k, seed, block, W, s);
+            hipLaunchKernelGGL(k_gather_rows, g, b, 0, s, n, k, t_order, W, Y);
+        }
         SFG_LAUNCH_CHECK();
-        lap(true, Y, Z);
+        lap(G, Y, Z);
+        double *Ad = small + 16 * 64, *Bd = Ad + 32 * 32, *Vd = Bd + 32 * 32, *thd = small + 320;
         double est = 0.0;
         int64_t iters = 0;
         int32_t max_inner = 0, uncon = 0;
+        bool warm = false;
         for (int32_t t = 0; t < kp.steps; ++t) {
             bool cap = false;
-            const int64_t it = solve(kp.tol, kp.max_iter, &cap);
+            const int64_t it = solve(kp.tol, kp.max_iter, warm ? thd : nullptr, &cap);
             iters += it;
             max_inner = std::max<int32_t>(max_inner, (int32_t)it);
             uncon += cap ? 1 : 0;
-            lap(true, X, W);
-            lap(false, X, VP);
+            lap(G, X, W);
+            lap(P, X, VP);
             block_gram(n, k, X, W, Ad, gram_scr, s);
             block_gram(n, k, X, VP, Bd, gram_scr, s);
             const std::vector<double> Ah = to_host(Ad, k * k), Bh = to_host(Bd, k * k);
@@ -362,11 +558,13 @@ struct KappaEstimator {
             if (!(est == est) || std::isinf(est)) fail(SFG_ENUMERIC, "kappa_estimate: NaN or Inf Ritz value");
             if (rep && t < 64) rep->ritz[t] = est;
             SFG_HIP(hipMemcpyAsync(Vd, V.data(), k * k * sizeof(double), hipMemcpyHostToDevice, s));
+            SFG_HIP(hipMemcpyAsync(thd, theta.data(), k * sizeof(double), hipMemcpyHostToDevice, s));
             hipLaunchKernelGGL(k_rotate, g, b, 0, s, n, k, X, Vd, Y);
             SFG_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_rotate, g, b, 0, s, n, k, W, Vd, Z);
             SFG_LAUNCH_CHECK();
-            SFG_HIP(hipStreamSynchronize(s));   // V lives on the host stack
+            SFG_HIP(hipStreamSynchronize(s));   // V and theta live on the host stack
+            warm = true;
         }
         if (rep) {
             rep->kappa = est;

@@ -265,33 +265,71 @@ __global__ __launch_bounds__(kB) void k_scan_tiles(int64_t rows, int32_t k, cons
     }
 }
 
-// exclusive scan of the tile totals, one workgroup: lane (g, c) takes a
-// contiguous chunk of tiles of column c
-__global__ __launch_bounds__(kB) void k_scan_offsets(int64_t tiles, int32_t k, double *__restrict__ tile_sum) {
+// Exclusive scan of the tile totals in two levels.  k_scan_mid: a workgroup
+// takes a group of G * kTpl tiles (lane (g, c): kTpl consecutive tiles of
+// column c), replaces each tile total by its exclusive offset inside the
+// group and writes the group total.  k_scan_top (one workgroup): exclusive
+// offsets of the group totals, and the column totals after them.
+constexpr int kTpl = 8;
+
+__device__ __forceinline__ int64_t tiles_per_group(int k) { return (int64_t)lanes_g(k) * kTpl; }
+
+__global__ __launch_bounds__(kB) void k_scan_mid(int64_t tiles, int32_t k, double *__restrict__ tile_sum,
+                                                 double *__restrict__ group_sum) {
     __shared__ double sh[kB];
     const int G = lanes_g(k);
     const int g = threadIdx.x / k, c = threadIdx.x % k;
-    const int64_t chunk = (tiles + G - 1) / G;
-    const int64_t t0 = (int64_t)g * chunk, t1 = t0 + chunk < tiles ? t0 + chunk : tiles;
+    const int64_t t0 = (int64_t)blockIdx.x * G * kTpl + (int64_t)g * kTpl;
+    double v[kTpl];
     double acc = 0.0;
-    if (g < G)
-        for (int64_t t = t0; t < t1; ++t) acc += tile_sum[t * k + c];
+#pragma unroll
+    for (int q = 0; q < kTpl; ++q) {
+        v[q] = (g < G && t0 + q < tiles) ? tile_sum[(t0 + q) * k + c] : 0.0;
+        acc += v[q];
+    }
     sh[threadIdx.x] = acc;
     __syncthreads();
-    if (g < G) {
-        double off = 0.0;
-        for (int gg = 0; gg < g; ++gg) off += sh[gg * k + c];
-        for (int64_t t = t0; t < t1; ++t) {
-            const double v = tile_sum[t * k + c];
-            tile_sum[t * k + c] = off;
-            off += v;
-        }
+    if (g >= G) return;
+    double off = 0.0;
+    for (int gg = 0; gg < g; ++gg) off += sh[gg * k + c];
+#pragma unroll
+    for (int q = 0; q < kTpl; ++q) {
+        if (t0 + q < tiles) tile_sum[(t0 + q) * k + c] = off;
+        off += v[q];
+    }
+    if (g == G - 1) group_sum[(int64_t)blockIdx.x * k + c] = off;
+}
+
+__global__ __launch_bounds__(kB) void k_scan_top(int64_t groups, int32_t k, double *__restrict__ group_sum) {
+    __shared__ double sh[kB];
+    const int G = lanes_g(k);
+    const int g = threadIdx.x / k, c = threadIdx.x % k;
+    const int64_t chunk = (groups + G - 1) / G;
+    const int64_t t0 = (int64_t)g * chunk, t1 = t0 + chunk < groups ? t0 + chunk : groups;
+    double acc = 0.0;
+    if (g < G)
+        for (int64_t t = t0; t < t1; ++t) acc += group_sum[t * k + c];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (g >= G) return;
+    double off = 0.0;
+    for (int gg = 0; gg < g; ++gg) off += sh[gg * k + c];
+    for (int64_t t = t0; t < t1; ++t) {
+        const double x = group_sum[t * k + c];
+        group_sum[t * k + c] = off;
+        off += x;
+    }
+    if (g == 0) {   // column totals after the offsets
+        double tot = 0.0;
+        for (int gg = 0; gg < G; ++gg) tot += sh[gg * k + c];
+        group_sum[groups * k + c] = tot;
     }
 }
 
 // inclusive prefix sums over rows: tile offset + lane offset + running sum
 __global__ __launch_bounds__(kB) void k_scan_apply(int64_t rows, int32_t k, const double *__restrict__ x,
-                                                   const double *__restrict__ tile_off, double *__restrict__ y) {
+                                                   const double *__restrict__ tile_off,
+                                                   const double *__restrict__ group_off, double *__restrict__ y) {
     __shared__ double sh[kB];
     const int G = lanes_g(k);
     const int g = threadIdx.x / k, c = threadIdx.x % k;
@@ -306,7 +344,7 @@ __global__ __launch_bounds__(kB) void k_scan_apply(int64_t rows, int32_t k, cons
     sh[threadIdx.x] = acc;
     __syncthreads();
     if (g >= G) return;
-    double run = tile_off[(int64_t)blockIdx.x * k + c];
+    double run = group_off[((int64_t)blockIdx.x / tiles_per_group(k)) * k + c] + tile_off[(int64_t)blockIdx.x * k + c];
     for (int gg = 0; gg < g; ++gg) run += sh[gg * k + c];
 #pragma unroll
     for (int r = 0; r < kRpt; ++r) {
@@ -363,6 +401,79 @@ __global__ void k_scatter_centre(int64_t n, int32_t k, const int32_t *__restrict
     x[(int64_t)order[i] * k + c] = xp[t] - mean[c];
 }
 
+// Preconditioner form (blocks already in preorder): the edge drops use the
+// column means from the scan totals instead of a centred copy of b.
+__global__ void k_edge_drop_pre(int64_t n, int32_t k, const int32_t *__restrict__ size, const double *__restrict__ pw,
+                                const int32_t *__restrict__ tdown, const int32_t *__restrict__ tup,
+                                const double *__restrict__ S, const double *__restrict__ totals,
+                                double *__restrict__ walk) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k || t < k) return;
+    const int64_t i = t / k;
+    const int c = (int)(t - i * k);
+    const int32_t sz = size[i];
+    const double mean = totals[c] / (double)n;
+    const double f = (S[(i + sz - 1) * k + c] - S[(i - 1) * k + c]) - (double)sz * mean;
+    const double d = f / pw[i];
+    walk[(int64_t)tdown[i] * k + c] = d;
+    walk[(int64_t)tup[i] * k + c] = -d;
+}
+
+// z[i] = prefix of the walk at i's down step (0 at the root), and per-column
+// partial sums of r . z.  Row-lane layout: workgroup of G x k threads,
+// thread (g, c) walks rows blockIdx * G + g + j * gridDim * G.
+__global__ __launch_bounds__(kB) void k_potential_dot(int64_t n, int32_t k, const int32_t *__restrict__ tdown,
+                                                      const double *__restrict__ U, const double *__restrict__ r,
+                                                      double *__restrict__ z, double *__restrict__ partial) {
+    __shared__ double sh[kB];
+    const int G = lanes_g(k);
+    const int g = threadIdx.x / k, c = threadIdx.x % k;
+    double acc = 0.0;
+    if (g < G)
+        for (int64_t i = (int64_t)blockIdx.x * G + g; i < n; i += (int64_t)gridDim.x * G) {
+            const double zi = i == 0 ? 0.0 : U[(int64_t)tdown[i] * k + c];
+            z[i * k + c] = zi;
+            acc += r[i * k + c] * zi;
+        }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < k) {
+        double t = 0.0;
+        for (int gg = 0; gg < G; ++gg) t += sh[gg * k + threadIdx.x];
+        partial[(int64_t)blockIdx.x * k + threadIdx.x] = t;
+    }
+}
+
+// out[c] = sum of nb partials of column c: one workgroup of 1024 threads,
+// lane (g, c) adds partials g, g + G, ... into four accumulators (loads in
+// flight), then a fixed pairwise tree over the lanes
+constexpr int kFinish = 1024;
+
+__global__ __launch_bounds__(kFinish) void k_partials_finish(int32_t nb, int32_t k, const double *__restrict__ partial,
+                                                             double *__restrict__ out) {
+    __shared__ double sh[kFinish];
+    const int G = kFinish / k;
+    const int g = threadIdx.x / k, c = threadIdx.x % k;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (g < G) {
+        int b = g;
+        for (; b + 3 * G < nb; b += 4 * G) {
+            a0 += partial[(int64_t)b * k + c];
+            a1 += partial[(int64_t)(b + G) * k + c];
+            a2 += partial[(int64_t)(b + 2 * G) * k + c];
+            a3 += partial[(int64_t)(b + 3 * G) * k + c];
+        }
+        for (; b < nb; b += G) a0 += partial[(int64_t)b * k + c];
+    }
+    sh[threadIdx.x] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    for (int st = 1; st < G; st <<= 1) {
+        if (g < G && (g % (2 * st)) == 0 && g + st < G) sh[g * k + c] += sh[(g + st) * k + c];
+        __syncthreads();
+    }
+    if ((int)threadIdx.x < k) out[threadIdx.x] = sh[threadIdx.x];
+}
+
 constexpr int kSumBlocks = 512;
 
 int64_t scan_tiles(int64_t rows, int32_t k) {
@@ -416,7 +527,20 @@ void block_gram(int64_t rows, int32_t k, const double *x, const double *y, doubl
     SFG_LAUNCH_CHECK();
 }
 
-size_t scan_scratch_doubles(int64_t rows, int32_t k) { return (size_t)scan_tiles(rows, k) * k + 64; }
+int64_t scan_groups(int64_t rows, int32_t k) {
+    const int64_t tpg = (int64_t)(kB / k) * kTpl;
+    return (scan_tiles(rows, k) + tpg - 1) / tpg;
+}
+
+// scratch: tile totals/offsets, then group totals/offsets and the column totals
+size_t scan_scratch_doubles(int64_t rows, int32_t k) {
+    return (size_t)(scan_tiles(rows, k) + scan_groups(rows, k) + 1) * k + 64;
+}
+
+// column totals of the last block_scan that used this scratch
+const double *scan_totals(int64_t rows, int32_t k, const double *scratch) {
+    return scratch + (size_t)(scan_tiles(rows, k) + scan_groups(rows, k)) * k;
+}
 
 // inclusive prefix sums down the rows of a rows x k block; y must not alias x
 void block_scan(int64_t rows, int32_t k, const double *x, double *y, double *scratch, hipStream_t s) {
@@ -424,10 +548,73 @@ void block_scan(int64_t rows, int32_t k, const double *x, double *y, double *scr
     const int64_t tiles = scan_tiles(rows, k);
     hipLaunchKernelGGL(k_scan_tiles, dim3((uint32_t)tiles), dim3(kB), 0, s, rows, k, x, scratch);
     SFG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_offsets, dim3(1), dim3(kB), 0, s, tiles, k, scratch);
+    const int64_t groups = scan_groups(rows, k);
+    double *gsum = scratch + (size_t)tiles * k;
+    hipLaunchKernelGGL(k_scan_mid, dim3((uint32_t)groups), dim3(kB), 0, s, tiles, k, scratch, gsum);
     SFG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)tiles), dim3(kB), 0, s, rows, k, x, scratch, y);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kB), 0, s, groups, k, gsum);
     SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_scan_apply, dim3((uint32_t)tiles), dim3(kB), 0, s, rows, k, x, scratch, gsum, y);
+    SFG_LAUNCH_CHECK();
+}
+
+// Grid of a row-lane kernel over `rows` rows (at most kLaneBlocks workgroups).
+constexpr int kLaneBlocks = 4096;
+
+uint32_t lane_grid(int64_t rows, int32_t k) {
+    const int64_t G = kB / k;
+    int64_t nb = (rows + G - 1) / G;
+    return (uint32_t)(nb < 1 ? 1 : (nb > kLaneBlocks ? kLaneBlocks : nb));
+}
+
+size_t lane_partial_doubles(int32_t k) { return (size_t)kLaneBlocks * k + 64; }
+
+void finish_partials(int32_t nb, int32_t k, const double *partial, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_partials_finish, dim3(1), dim3(kFinish), 0, s, nb, k, partial, out);
+    SFG_LAUNCH_CHECK();
+}
+
+size_t tree_precond_workspace_bytes(int64_t n, int32_t k) {
+    Carver c(nullptr);
+    const int64_t A = 2 * (n - 1) > 0 ? 2 * (n - 1) : 1;
+    c.take<double>((size_t)n * k);
+    c.take<double>((size_t)A * k);
+    c.take<double>((size_t)A * k);
+    c.take<double>(scan_scratch_doubles(A > n ? A : n, k));
+    c.take<double>(lane_partial_doubles(k));
+    return c.used + 256;
+}
+
+// z = L_T^+ r up to a constant per column, for blocks in the tree's preorder
+// (row i is node order[i]), and rz[c] = sum_i r[i][c] z[i][c]: the
+// conjugate-gradient preconditioner (constants are in the kernel of every
+// Laplacian, so they change neither the iterates' residuals nor r . z for r
+// orthogonal to the all-one vector).
+void tree_precond_pre(const sfg_tree *T, int32_t k, const double *r, double *z, double *rz, void *ws,
+                      hipStream_t s) {
+    const int64_t n = T->n;
+    const int64_t A = 2 * (n - 1) > 0 ? 2 * (n - 1) : 1;
+    Carver c(ws);
+    double *S = c.take<double>((size_t)n * k);
+    double *walk = c.take<double>((size_t)A * k);
+    double *U = c.take<double>((size_t)A * k);
+    double *sscr = c.take<double>(scan_scratch_doubles(A > n ? A : n, k));
+    double *part = c.take<double>(lane_partial_doubles(k));
+    if (n > 1) {
+        block_scan(n, k, r, S, sscr, s);
+        // column totals of r; copied before the walk scan reuses the scratch
+        double *tot = part + (size_t)kLaneBlocks * k;
+        hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(64), 0, s, 1, k, scan_totals(n, k, sscr), 1.0, tot);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_edge_drop_pre, dim3(grid_for(n * k, kB)), dim3(kB), 0, s, n, k, T->size, T->pw,
+                           T->tdown, T->tup, S, tot, walk);
+        SFG_LAUNCH_CHECK();
+        block_scan(A, k, walk, U, sscr, s);
+    }
+    const uint32_t nb = lane_grid(n, k);
+    hipLaunchKernelGGL(k_potential_dot, dim3(nb), dim3(kB), 0, s, n, k, T->tdown, U, r, z, part);
+    SFG_LAUNCH_CHECK();
+    finish_partials((int32_t)nb, k, part, rz, s);
 }
 
 // ------------------------------------------------------------------ tree layout
