@@ -602,12 +602,9 @@ void tree_precond_pre(const sfg_tree *T, int32_t k, const double *r, double *z, 
     double *part = c.take<double>(lane_partial_doubles(k));
     if (n > 1) {
         block_scan(n, k, r, S, sscr, s);
-        // column totals of r; copied before the walk scan reuses the scratch
-        double *tot = part + (size_t)kLaneBlocks * k;
-        hipLaunchKernelGGL(k_colsum_finish, dim3(1), dim3(64), 0, s, 1, k, scan_totals(n, k, sscr), 1.0, tot);
-        SFG_LAUNCH_CHECK();
+        // the column totals of r stay in the scratch until the walk scan reuses it
         hipLaunchKernelGGL(k_edge_drop_pre, dim3(grid_for(n * k, kB)), dim3(kB), 0, s, n, k, T->size, T->pw,
-                           T->tdown, T->tup, S, tot, walk);
+                           T->tdown, T->tup, S, scan_totals(n, k, sscr), walk);
         SFG_LAUNCH_CHECK();
         block_scan(A, k, walk, U, sscr, s);
     }
