@@ -4,6 +4,7 @@
     python bench.py --workload chunglu  # 4M-node power-law graph, 5-level hierarchy (Alg. 1)
     python bench.py --workload mesh     # 200^3 mesh, plain FP32 path and the learned surrogate
     python bench.py --workload sigma    # power grid: condition-number estimate and sigma-driven stopping
+    python bench.py --workload scaling  # 3-D meshes 50^3 .. 200^3: time per edge of the whole method
 
 Each prints one JSON line; all inputs are seeded and synthetic.  Accuracy
 against the oracle at these sizes is checked by tests/test_gpu_workloads.py.
@@ -352,8 +353,43 @@ def run_sigma(args) -> dict:
             "sigma_runs": sig}
 
 
+# ----------------------------------------------------------------------------- linear scaling (Sec. 3.6, Fig. 8)
+
+def run_scaling(args) -> dict:
+    """One sfg_sparsify call (spanning tree, tree CSR, 20 sweeps of 16 FP32 vectors drawn on the device,
+    scores, top 10%) on 7-point log-normal meshes of growing size: the paper states O(|E|) work per level."""
+    prm = W.workload_params("mesh")
+    rows = []
+    for side in (50, 100, 150, 200):
+        g = W.mesh3d(side, side, side, seed=W.WORKLOADS["mesh"]["seed"])
+        u, v, w = to_dev(g, f32=True)
+        p = S.make_params(k=prm["k"], sweeps=prm["sweeps"], frac=prm["frac"], storage=torch.float32, seed=1)
+        S.sfg_sparsify(g.n, u, v, w, None, p)     # warm-up
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.sfg_sparsify(g.n, u, v, w, None, p)
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        ms = sorted(ts)[1]
+        rows.append({"mesh": f"{side}^3", "nodes": g.n, "edges": g.m, "ms": round(ms, 3),
+                     "ns_per_edge": round(ms * 1e6 / g.m, 3)})
+        log(f"mesh {side}^3: {ms:.3f} ms, {ms * 1e6 / g.m:.3f} ns per edge")
+        del u, v, w
+    return {"metric": "time per edge of one sparsify call on meshes of growing size (linear scaling)",
+            "value": rows[-1]["ns_per_edge"], "unit": "ns/edge", "higher_is_better": False, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "7-point meshes 50^3..200^3, log-normal(0, 1.5) weights", "vectors": prm["k"],
+                       "sweeps": prm["sweeps"], "frac": prm["frac"]},
+            "sizes": rows,
+            "note": "each call builds the spanning tree, the tree CSR and the candidate list, draws the block on the "
+                    "device, smooths, scores and selects; allocations are stream-ordered inside the call"}
+
+
 def run(args) -> None:
-    fn = {"knn": run_knn, "chunglu": run_chunglu, "mesh": run_mesh, "sigma": run_sigma}[args.workload]
+    fn = {"knn": run_knn, "chunglu": run_chunglu, "mesh": run_mesh, "sigma": run_sigma,
+          "scaling": run_scaling}[args.workload]
     out = fn(args)
     out["n_gpus"] = 1
     print(json.dumps(out), flush=True)

@@ -47,9 +47,27 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
 
 // ------------------------------------------------------------------ device arena (sfg_sparsify only)
 
+// The default pool of stream-ordered allocations returns freed memory to the
+// driver at every synchronisation unless told to keep some: each call would
+// then map its buffers afresh.  Keep up to 16 GiB cached per device (set once
+// per device; the memory is reused by later calls, not by other allocators).
+static void keep_pool_memory() {
+    static bool done[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = uint64_t(16) << 30;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    done[dev] = true;
+}
+
 DevArena::DevArena(hipStream_t st) : s(st) {
     const char *e = getenv("SFG_FAIL_ALLOC_AFTER");
     fail_after = e ? atol(e) : -1;
+    keep_pool_memory();
 }
 
 DevArena::~DevArena() {

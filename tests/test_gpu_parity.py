@@ -329,18 +329,33 @@ def test_workspace_too_small(S):
         S.sfg_smooth(H, dev(W.random_block(g.n, 4, 2)), 3, ws=ws)
 
 
-@pytest.mark.parametrize("case", ["unit_grid", "ties_f32", "forest", "chunglu"])
+# the *_large cases have >= 65536 edges, so later Boruvka rounds run on compacted edge lists
+@pytest.mark.parametrize("case", ["unit_grid", "ties_f32", "forest", "chunglu", "ties_large", "forest_large",
+                                  "mesh_large", "unit_large"])
 def test_spanning_tree_ties_and_forests(S, orc, case):
     if case == "unit_grid":
         g = W.grid2d(37, 41, seed=90, wdist=("unit",))
         w, allowed = g.w, None
+    elif case == "unit_large":
+        g = W.grid2d(300, 310, seed=95, wdist=("unit",))    # every weight tied: ids decide
+        w, allowed = g.w, None
     elif case == "ties_f32":
         g = W.random_connected(5000, 20000, seed=91)
         w, allowed = np.round(g.w * 4) / 4, None            # heavy ties
+    elif case == "ties_large":
+        g = W.random_connected(60000, 200000, seed=96)
+        w, allowed = np.round(g.w * 4) / 4, None
     elif case == "forest":
         g = W.powergrid(60, 50, 0.02, seed=92)
         w = g.w
         allowed = (np.random.default_rng(1).random(g.m) < 0.6).astype(np.uint8)
+    elif case == "forest_large":
+        g = W.powergrid(250, 240, 0.02, seed=97)
+        w = g.w
+        allowed = (np.random.default_rng(2).random(g.m) < 0.7).astype(np.uint8)
+    elif case == "mesh_large":
+        g = W.mesh3d(40, 38, 36, seed=98)
+        w, allowed = g.w, None
     else:
         g = W.chung_lu(30000, 300000, 2.2, seed=93)
         w, allowed = g.w32.astype(np.float64), None
