@@ -146,12 +146,22 @@ void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *scr
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
-// Stream-ordered device allocations owned by one sfg_sparsify call, freed
-// (stream-ordered) when it returns.  SFG_FAIL_ALLOC_AFTER=n makes the
-// (n+1)-th allocation fail, to test the error path.
+// Device buffers owned by one allocating call (sfg_sparsify, ...), carved
+// from chunks of at least 256 MB.  A call that ends with finish() (its stream
+// drained) hands its chunks to a per-device cache (up to 16 GiB) that later
+// calls reuse; otherwise (an error path, work possibly in flight) they are
+// freed stream-ordered.  SFG_FAIL_ALLOC_AFTER=n makes the (n+1)-th buffer
+// request fail, to test the error path.
 struct DevArena {
+    struct Chunk {
+        void *p;
+        size_t size;
+    };
     hipStream_t s;
-    std::vector<void *> ptrs;
+    std::vector<Chunk> chunks;
+    size_t used = 0;   // bytes carved from the last chunk
+    int dev = 0;
+    bool synced = false;
     long fail_after = -1;
     long count = 0;
     explicit DevArena(hipStream_t st);
@@ -159,6 +169,7 @@ struct DevArena {
     DevArena(const DevArena &) = delete;
     DevArena &operator=(const DevArena &) = delete;
     void *raw(size_t bytes);
+    void finish();   // wait for the stream; the chunks may then be cached
     template <typename T>
     T *alloc(size_t n) {
         return static_cast<T *>(raw(n * sizeof(T)));

@@ -629,6 +629,6 @@ extern "C" sfg_status sfg_kappa_estimate(int64_t n, int64_t m, const int32_t *u,
         sfg::convert_weights(w, wt, SFG_F64, m, w64, s);
         sfg::KappaEstimator e(n, m, u, v, w64, keep, p.k, A, s);
         *kappa = e.run(keep, p, y0, p.seed, p.block, rep);
-        SFG_HIP(hipStreamSynchronize(s));
+        A.finish();
     });
 }

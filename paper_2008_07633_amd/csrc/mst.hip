@@ -154,9 +154,11 @@ int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t 
         if (read_flag(flags, s) == 0) break;     // no component has an outgoing edge
         hipLaunchKernelGGL(k_mst_hook, gn, b, 0, s, n, u, v, comp, best_e, parent, in_tree);
         SFG_LAUNCH_CHECK();
-        for (int it = 0;; ++it) {
+        for (int it = 0;; it += 2) {   // two jumps per check of the flag (one host sync)
             SFG_REQUIRE(it < 64, SFG_EHIP, "spanning_tree: pointer jumping did not converge");
             fill_i32(flags + 1, 1, 0, s);
+            hipLaunchKernelGGL(k_mst_jump, gn, b, 0, s, n, comp, parent, flags + 1);
+            SFG_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_mst_jump, gn, b, 0, s, n, comp, parent, flags + 1);
             SFG_LAUNCH_CHECK();
             if (read_flag(flags + 1, s) == 0) break;

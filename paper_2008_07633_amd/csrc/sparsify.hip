@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -64,28 +65,82 @@ static void keep_pool_memory() {
     done[dev] = true;
 }
 
+namespace {
+
+constexpr size_t kChunkBytes = size_t(256) << 20;
+constexpr size_t kCacheBytes = size_t(16) << 30;
+constexpr int kMaxDevices = 64;
+
+std::mutex g_cache_mu;
+std::vector<DevArena::Chunk> g_cache[kMaxDevices];
+size_t g_cached[kMaxDevices];
+
+}  // namespace
+
 DevArena::DevArena(hipStream_t st) : s(st) {
     const char *e = getenv("SFG_FAIL_ALLOC_AFTER");
     fail_after = e ? atol(e) : -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) dev = -1;
+    (void)hipGetLastError();
     keep_pool_memory();
 }
 
+void DevArena::finish() {
+    SFG_HIP(hipStreamSynchronize(s));
+    synced = true;
+}
+
 DevArena::~DevArena() {
-    for (void *p : ptrs) (void)hipFreeAsync(p, s);
+    if (synced && dev >= 0) {
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        for (const Chunk &c : chunks) {
+            if (g_cached[dev] + c.size <= kCacheBytes) {
+                g_cache[dev].push_back(c);
+                g_cached[dev] += c.size;
+            } else {
+                (void)hipFreeAsync(c.p, s);
+            }
+        }
+    } else {
+        for (const Chunk &c : chunks) (void)hipFreeAsync(c.p, s);
+    }
+    (void)hipGetLastError();
 }
 
 void *DevArena::raw(size_t bytes) {
     if (fail_after >= 0 && count >= fail_after) fail(SFG_ENOMEM, "device allocation failed (SFG_FAIL_ALLOC_AFTER)");
-    void *p = nullptr;
-    hipError_t e = hipMallocAsync(&p, bytes < 256 ? 256 : bytes, s);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(SFG_ENOMEM, std::string("device allocation of ") + std::to_string(bytes) + " bytes failed: " +
-                             hipGetErrorString(e));
-    }
-    ptrs.push_back(p);
     ++count;
-    return p;
+    const size_t need = ((bytes < 256 ? 256 : bytes) + 255) & ~size_t(255);
+    if (!chunks.empty() && used + need <= chunks.back().size) {
+        void *p = static_cast<char *>(chunks.back().p) + used;
+        used += need;
+        return p;
+    }
+    Chunk c{nullptr, 0};
+    if (dev >= 0) {   // the smallest cached chunk that fits
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        auto &cache = g_cache[dev];
+        size_t best = cache.size();
+        for (size_t i = 0; i < cache.size(); ++i)
+            if (cache[i].size >= need && (best == cache.size() || cache[i].size < cache[best].size)) best = i;
+        if (best < cache.size()) {
+            c = cache[best];
+            cache.erase(cache.begin() + (long)best);
+            g_cached[dev] -= c.size;
+        }
+    }
+    if (!c.p) {
+        c.size = need > kChunkBytes ? need : kChunkBytes;
+        hipError_t e = hipMallocAsync(&c.p, c.size, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(SFG_ENOMEM, std::string("device allocation of ") + std::to_string(c.size) + " bytes failed: " +
+                                 hipGetErrorString(e));
+        }
+    }
+    chunks.push_back(c);
+    used = need;
+    return c.p;
 }
 
 // ------------------------------------------------------------------ validation
@@ -478,6 +533,7 @@ extern "C" sfg_status sfg_spanning_tree(int64_t n, int64_t m, const int32_t *u, 
         SFG_REQUIRE(n_comp, SFG_EINVAL, "spanning_tree: n_comp is required");
         sfg::DevArena A(sfg::as_stream(stream));
         *n_comp = sfg::spanning_tree_gpu(n, m, u, v, w, wt, allowed, in_tree, A, sfg::as_stream(stream));
+        A.finish();
     });
 }
 
@@ -505,6 +561,6 @@ extern "C" sfg_status sfg_sparsify(int64_t n, int64_t m, const int32_t *u, const
             sfg::single_level_sparsify(n, m, u, v, w, wt, p, x0, keep, rep, A, s);
         else
             sfg::multilevel_sparsify(n, m, u, v, w, wt, p, x0, keep, rep, A, s);
-        SFG_HIP(hipStreamSynchronize(s));
+        A.finish();
     });
 }
