@@ -159,19 +159,16 @@ def run_chunglu(args) -> dict:
 
 # ----------------------------------------------------------------------------- 3-D mesh: plain vs surrogate
 
-def run_mesh(args) -> dict:
-    from paper_2008_07633_amd import surrogate as SG
-
-    prm = W.workload_params("mesh")
-    k, T, f, cf = prm["k"], prm["sweeps"], prm["frac"], prm["cand_frac"]
-    # ---- train on 50 seeded 40^3 meshes with the plain method's own FP32 scores
+def _train_surrogate(SG, k, T, f, kc, tc):
+    """Train on 50 seeded 40^3 meshes (targets: the plain method's own FP32 scores) with a cheap embedding of
+    kc vectors and tc sweeps; recall of the plain selection on 5 held-out 40^3 meshes."""
     t0 = time.time()
     graphs, targets = [], []
     for i in range(50):
         gm = W.mesh3d(40, 40, 40, seed=100 + i, wdist=("lognormal", 0.0, 1.5))
         X0m = W.random_block(gm.n, k, 2000 + i)
         um, vm, wm = to_dev(gm)
-        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :SG.KC]).cuda())
+        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :kc]).cuda(), tc)
         pp.raw_nf, pp.raw_ef = SG.features(pp, None)
         s = SG.plain_scores(pp, torch.from_numpy(X0m).cuda(), T)
         graphs.append(pp)
@@ -181,15 +178,15 @@ def run_mesh(args) -> dict:
     model, hist = SG.train(SG.TrainSet(graphs, targets), epochs=60)
     torch.cuda.synchronize()
     t_train = time.time() - t0
-    log(f"surrogate trained: loss {hist[0]:.3f} -> {hist[-1]:.3f} in {t_train:.1f} s (data {t_data:.1f} s)")
+    log(f"surrogate ({kc} vectors, {tc} sweeps) trained: loss {hist[0]:.3f} -> {hist[-1]:.3f} in {t_train:.1f} s "
+        f"(data {t_data:.1f} s)")
     del graphs, targets
-    # ---- held-out 40^3 meshes: recall of the plain selection inside the candidates
     rec = {"net": {}, "cheap": {}}
     for i in range(5):
         gm = W.mesh3d(40, 40, 40, seed=200 + i, wdist=("lognormal", 0.0, 1.5))
         X0m = W.random_block(gm.n, k, 3000 + i)
         um, vm, wm = to_dev(gm)
-        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :SG.KC]).cuda())
+        pp = SG.prepare(gm.n, um, vm, wm, torch.from_numpy(X0m[:, :kc]).cuda(), tc)
         s = SG.plain_scores(pp, torch.from_numpy(X0m).cuda(), T)
         nc = int(pp.cand.numel())
         chosen = torch.nonzero(S.sfg_select_topk(s, int(math.ceil(f * nc)))[0]).reshape(-1)
@@ -202,7 +199,15 @@ def run_mesh(args) -> dict:
                 rec[nm].setdefault(str(c), []).append(SG.recall(chosen, pos, nc))
     recall = {nm: {c: round(float(np.mean(x)), 4) for c, x in d.items()} for nm, d in rec.items()}
     log(f"recall on held-out meshes: {recall}")
-    # ---- full 200^3 mesh: plain path vs pruned path, end to end on the device
+    return model, hist, t_train, recall
+
+
+def run_mesh(args) -> dict:
+    from paper_2008_07633_amd import surrogate as SG
+
+    prm = W.workload_params("mesh")
+    k, T, f, cf = prm["k"], prm["sweeps"], prm["frac"], prm["cand_frac"]
+    # ---- full 200^3 mesh: the plain path, end to end on the device
     g = cached_graph("mesh")
     X0 = W.workload_block("mesh", g.n)
     u, v, w64 = to_dev(g)
@@ -229,66 +234,71 @@ def run_mesh(args) -> dict:
     plain_sel = plain_step()[0]
     chosen = torch.nonzero(plain_sel).reshape(-1)
     G = S.sfg_laplacian_csr(g.n, u, v, w32)
-    x0c = x0[:, :SG.KC].contiguous()
     ws_f = torch.empty(S.sfg_workspace_bytes(S.OP_MPNN_FORWARD, g.n, 0, 0, torch.bfloat16), dtype=torch.uint8,
                        device="cuda")
-    kc = int(math.ceil(cf * nc))
-
     ws_g = torch.empty(S.sfg_workspace_bytes(S.OP_LAPLACIAN_CSR, g.n, g.m, 0, torch.float32), dtype=torch.uint8,
                        device="cuda")
-
-    # the surrogate paths also build the CSR of G (the network aggregates over G)
-    def pruned_step():
-        S.sfg_laplacian_csr(g.n, u, v, w32, ws=ws_g, out=G, nnz=2 * g.m)
-        S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree, out=H, nnz=nnz)
-        xc = S.sfg_smooth(H, x0c, SG.TC, 0.5, storage=torch.bfloat16, final_f32=True)
-        pp = SG.Prepared(g.n, u, v, w32, tree, cand, G, H, xc)
-        nf, ef = SG.features(pp, model.norm)
-        pred = S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
-        csel, _ = S.sfg_select_topk(pred, kc, sync=False)
-        cpos = torch.nonzero(csel).reshape(-1)
-        ce = cand[cpos].contiguous()
-        S.sfg_smooth(H, x0, T, 0.5, storage=torch.float32, out=X, ws=ws_sm)
-        s2 = S.sfg_edge_scores(X, u, v, w32, cand=ce)
-        sel2, _ = S.sfg_select_topk(s2, min(ksel, int(ce.numel())), sync=False)
-        return cpos, sel2
-
-    # the ranked path takes 15% of the off-tree edges: the fraction at which it
-    # reaches the plain default's median condition number on held-out meshes
+    kcand = int(math.ceil(cf * nc))
+    # the ranked path takes 15% of the off-tree edges: the fraction at which the fast model reaches the plain
+    # default's median condition number on held-out meshes
     ksel_r = int(math.ceil(0.15 * nc))
+    configs = {}
+    for name, kc in (("fast", SG.KC), ("recall", SG.KC_RECALL)):
+        model, hist, t_train, recall = _train_surrogate(SG, k, T, f, kc, SG.TC)
+        x0c = x0[:, :model.kc].contiguous()
 
-    def ranked_step():
-        S.sfg_laplacian_csr(g.n, u, v, w32, ws=ws_g, out=G, nnz=2 * g.m)
-        S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree, out=H, nnz=nnz)
-        xc = S.sfg_smooth(H, x0c, SG.TC, 0.5, storage=torch.bfloat16, final_f32=True)
-        pp = SG.Prepared(g.n, u, v, w32, tree, cand, G, H, xc)
-        nf, ef = SG.features(pp, model.norm)
-        pred = S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
-        return S.sfg_select_topk(pred, ksel_r, sync=False)
+        # the surrogate paths also build the CSR of G (the network aggregates over G)
+        def surrogate_pred():
+            S.sfg_laplacian_csr(g.n, u, v, w32, ws=ws_g, out=G, nnz=2 * g.m)
+            S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree, out=H, nnz=nnz)
+            xc = S.sfg_smooth(H, x0c, model.tc, 0.5, storage=torch.bfloat16, final_f32=True)
+            pp = SG.Prepared(g.n, u, v, w32, tree, cand, G, H, xc, model.tc)
+            nf, ef = SG.features(pp, model.norm)
+            return S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
 
-    t_ranked = ev_time(ranked_step, 3)
-    rsel = ranked_step()[0]
-    ranked_overlap = float(rsel.bool()[chosen].float().mean().item())
-    t_pruned = ev_time(pruned_step, 3)
-    cpos, sel2 = pruned_step()
-    r_full = SG.recall(chosen, cpos, nc)
-    final_pos = cpos[sel2.bool()]
-    mark = torch.zeros(nc, dtype=torch.bool, device="cuda")
-    mark[final_pos.long()] = True
-    set_agree = float(mark[chosen.long()].float().mean().item())
+        def pruned_step():
+            pred = surrogate_pred()
+            csel, _ = S.sfg_select_topk(pred, kcand, sync=False)
+            cpos = torch.nonzero(csel).reshape(-1)
+            ce = cand[cpos].contiguous()
+            S.sfg_smooth(H, x0, T, 0.5, storage=torch.float32, out=X, ws=ws_sm)
+            s2 = S.sfg_edge_scores(X, u, v, w32, cand=ce)
+            sel2, _ = S.sfg_select_topk(s2, min(ksel, int(ce.numel())), sync=False)
+            return cpos, sel2
+
+        def ranked_step():
+            return S.sfg_select_topk(surrogate_pred(), ksel_r, sync=False)
+
+        t_ranked = ev_time(ranked_step, 3)
+        rsel = ranked_step()[0]
+        ranked_overlap = float(rsel.bool()[chosen].float().mean().item())
+        t_pruned = ev_time(pruned_step, 3)
+        cpos, sel2 = pruned_step()
+        r_full = SG.recall(chosen, cpos, nc)
+        mark = torch.zeros(nc, dtype=torch.bool, device="cuda")
+        mark[cpos[sel2.bool()].long()] = True
+        set_agree = float(mark[chosen.long()].float().mean().item())
+        configs[name] = {"cheap_vectors": model.kc, "cheap_sweeps": model.tc,
+                         "surrogate_pruned_ms": round(t_pruned, 3),
+                         "surrogate_vs_plain_time": round(t_pruned / t_plain, 3),
+                         "surrogate_ranked_ms": round(t_ranked, 3),
+                         "ranked_vs_plain_time": round(t_ranked / t_plain, 3), "ranked_frac": 0.15,
+                         "ranked_overlap_with_plain_selection": round(ranked_overlap, 4),
+                         "recall_full_mesh_at_cand_frac": round(r_full, 4),
+                         "selected_set_agreement": round(set_agree, 4), "recall_heldout_40cubed": recall,
+                         "train_loss": [round(hist[0], 4), round(hist[-1], 4)], "train_s": round(t_train, 2)}
+        log(f"{name}: {configs[name]}")
+        del model
     roof = sweep_roofline(H, x0, T, torch.float32, False, g.n, nnz, k, 4, 4)
-    return {"metric": "surrogate vs plain: recall of the plain selection and end-to-end time",
-            "value": round(nc / (t_plain * 1e-3), 1), "unit": "edges/s (plain path)", "dtype": "f32",
-            "data": "synthetic",
-            "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "off_tree_edges": nc, "vectors": k,
-                       "sweeps": T, "frac": f, "cand_frac": cf, "train": "50 meshes 40^3, 60 epochs"},
-            "plain_ms": round(t_plain, 3), "surrogate_pruned_ms": round(t_pruned, 3),
-            "surrogate_vs_plain_time": round(t_pruned / t_plain, 3),
-            "surrogate_ranked_ms": round(t_ranked, 3), "ranked_vs_plain_time": round(t_ranked / t_plain, 3),
-            "ranked_frac": 0.15, "ranked_overlap_with_plain_selection": round(ranked_overlap, 4),
-            "recall_full_mesh_at_cand_frac": round(r_full, 4), "selected_set_agreement": round(set_agree, 4),
-            "recall_heldout_40cubed": recall, "train_loss": [round(hist[0], 4), round(hist[-1], 4)],
-            "train_s": round(t_train, 2), "roofline_f32_sweep_tree": roof}
+    out = {"metric": "surrogate vs plain: recall of the plain selection and end-to-end time",
+           "value": round(nc / (t_plain * 1e-3), 1), "unit": "edges/s (plain path)", "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "off_tree_edges": nc, "vectors": k,
+                      "sweeps": T, "frac": f, "cand_frac": cf, "train": "50 meshes 40^3, 60 epochs"},
+           "plain_ms": round(t_plain, 3), "roofline_f32_sweep_tree": roof}
+    out.update(configs["fast"])
+    out["recall_config"] = configs["recall"]
+    return out
 
 
 # ----------------------------------------------------------------------------- power grid: sigma-driven stopping

@@ -26,6 +26,8 @@
 #include <cmath>
 #include <vector>
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace sfg {
@@ -64,17 +66,21 @@ __device__ __forceinline__ float ld<float>(const float *p) {
 
 // ------------------------------------------------------------------ features
 
-// |x_p - x_q|^2 over the kc cheap vectors (KC > 0: kc = KC, one vector load per row)
+// |x_p - x_q|^2 over the kc cheap vectors, added in column order (KC > 0: kc =
+// KC, a multiple of 4, loaded as 16-byte vectors)
 template <int KC>
 __device__ __forceinline__ float dist2(const float *__restrict__ xc, int32_t kc, const float *xp, int64_t q) {
     float d2 = 0.f;
-    if constexpr (KC == 4) {
-        const float4 b = *reinterpret_cast<const float4 *>(xc + q * 4);
-        const float bq[4] = {b.x, b.y, b.z, b.w};
+    if constexpr (KC > 0) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const float d = xp[c] - bq[c];
-            d2 = __builtin_fmaf(d, d, d2);
+        for (int c4 = 0; c4 < KC / 4; ++c4) {
+            const float4 b = *reinterpret_cast<const float4 *>(xc + q * KC + 4 * c4);
+            const float bq[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const float d = xp[4 * c4 + c] - bq[c];
+                d2 = __builtin_fmaf(d, d, d2);
+            }
         }
     } else {
         const float *xq = xc + q * kc;
@@ -114,12 +120,15 @@ __global__ void k_node_feat(int64_t n, const int32_t *__restrict__ grp, const in
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     float xp[KC > 0 ? KC : 64];
-    if constexpr (KC == 4) {
-        const float4 a = *reinterpret_cast<const float4 *>(xc + p * 4);
-        xp[0] = a.x;
-        xp[1] = a.y;
-        xp[2] = a.z;
-        xp[3] = a.w;
+    if constexpr (KC > 0) {
+#pragma unroll
+        for (int c4 = 0; c4 < KC / 4; ++c4) {
+            const float4 a = *reinterpret_cast<const float4 *>(xc + p * KC + 4 * c4);
+            xp[4 * c4] = a.x;
+            xp[4 * c4 + 1] = a.y;
+            xp[4 * c4 + 2] = a.z;
+            xp[4 * c4 + 3] = a.w;
+        }
     } else {
         for (int c = 0; c < kc; ++c) xp[c] = xc[p * kc + c];
     }
@@ -139,7 +148,7 @@ __global__ void k_node_feat(int64_t n, const int32_t *__restrict__ grp, const in
     float o[kF];
 #pragma unroll
     for (int i = 0; i < kF; ++i) o[i] = (norm && i > 0) ? (f[i] - norm[i]) * norm[kF + i] : f[i];
-    if constexpr (KC == 4) {
+    if constexpr (KC > 0) {
         *reinterpret_cast<float4 *>(nf + p * kF) = make_float4(o[0], o[1], o[2], o[3]);
         *reinterpret_cast<float4 *>(nf + p * kF + 4) = make_float4(o[4], o[5], o[6], o[7]);
     } else {
@@ -157,12 +166,15 @@ __global__ void k_edge_feat(int64_t ne, const int32_t *__restrict__ cand, const 
     const int32_t e = cand ? cand[i] : (int32_t)i;
     const int32_t p = u[e], q = v[e];
     float xp[KC > 0 ? KC : 64];
-    if constexpr (KC == 4) {
-        const float4 a = *reinterpret_cast<const float4 *>(xc + (int64_t)p * 4);
-        xp[0] = a.x;
-        xp[1] = a.y;
-        xp[2] = a.z;
-        xp[3] = a.w;
+    if constexpr (KC > 0) {
+#pragma unroll
+        for (int c4 = 0; c4 < KC / 4; ++c4) {
+            const float4 a = *reinterpret_cast<const float4 *>(xc + (int64_t)p * KC + 4 * c4);
+            xp[4 * c4] = a.x;
+            xp[4 * c4 + 1] = a.y;
+            xp[4 * c4 + 2] = a.z;
+            xp[4 * c4 + 3] = a.w;
+        }
     } else {
         for (int c = 0; c < kc; ++c) xp[c] = xc[(int64_t)p * kc + c];
     }
@@ -700,26 +712,27 @@ extern "C" sfg_status sfg_mpnn_features(const sfg_csr *G, const sfg_csr *T, cons
         SFG_REQUIRE(xc && kc >= 1 && kc <= 64 && node_feat, SFG_EINVAL, "mpnn_features: bad block");
         SFG_REQUIRE(ne >= 0 && (ne == 0 || (u && v && w && edge_feat)), SFG_EINVAL, "mpnn_features: null pointer");
         const int64_t n = G->n;
-        // the 4-vector cheap embedding with 16-byte aligned rows takes vector loads
-        const bool v4 = kc == 4 && (uintptr_t)xc % 16 == 0 && (uintptr_t)node_feat % 16 == 0;
-        if (v4)
-            hipLaunchKernelGGL(k_node_feat<4>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, G->rowptr, G->col,
+        // 4- and 16-vector cheap embeddings with 16-byte aligned rows take vector loads
+        const bool aligned = (uintptr_t)xc % 16 == 0 && (uintptr_t)node_feat % 16 == 0;
+        const int kv = aligned && (kc == 4 || kc == 16) ? kc : 0;
+        auto node = [&](auto kt) {
+            constexpr int KC = decltype(kt)::value;
+            hipLaunchKernelGGL(k_node_feat<KC>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, G->rowptr, G->col,
                                (const float *)G->val, (const float *)G->deg, T->rowptr, T->col,
                                (const float *)T->val, (const float *)T->deg, xc, kc, norm, node_feat);
-        else
-            hipLaunchKernelGGL(k_node_feat<0>, dim3(grid_for(n, 256)), dim3(256), 0, s, n, G->rowptr, G->col,
-                               (const float *)G->val, (const float *)G->deg, T->rowptr, T->col,
-                               (const float *)T->val, (const float *)T->deg, xc, kc, norm, node_feat);
-        SFG_LAUNCH_CHECK();
-        if (ne > 0) {
-            if (v4)
-                hipLaunchKernelGGL(k_edge_feat<4>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, cand, u, v, w, xc,
-                                   kc, (const float *)T->deg, norm, edge_feat);
-            else
-                hipLaunchKernelGGL(k_edge_feat<0>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, cand, u, v, w, xc,
-                                   kc, (const float *)T->deg, norm, edge_feat);
             SFG_LAUNCH_CHECK();
-        }
+            if (ne > 0) {
+                hipLaunchKernelGGL(k_edge_feat<KC>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, cand, u, v, w, xc,
+                                   kc, (const float *)T->deg, norm, edge_feat);
+                SFG_LAUNCH_CHECK();
+            }
+        };
+        if (kv == 4)
+            node(std::integral_constant<int, 4>());
+        else if (kv == 16)
+            node(std::integral_constant<int, 16>());
+        else
+            node(std::integral_constant<int, 0>());
     });
 }
 

@@ -33,14 +33,15 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _prep(SG, g, seed=1, sweeps=20):
-    x0c = dev(W.random_block(g.n, SG.KC, seed))
+def _prep(SG, g, seed=1, sweeps=20, kc=None):
+    x0c = dev(W.random_block(g.n, SG.KC if kc is None else kc, seed))
     return SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), x0c, sweeps)
 
 
-def test_features_match_oracle(S, SG, orc):
+@pytest.mark.parametrize("kc", [4, 16, 6])   # the two vector-load paths and the generic one
+def test_features_match_oracle(S, SG, orc, kc):
     g = W.mesh3d(9, 8, 7, seed=11, wdist=("lognormal", 0.0, 1.5))
-    pp = _prep(SG, g)
+    pp = _prep(SG, g, kc=kc)
     nf, ef = SG.features(pp, None)
     tree = pp.tree.cpu().numpy().astype(bool)
     xc = pp.xc.cpu().numpy().astype(np.float64)
@@ -113,16 +114,16 @@ def test_adam_matches_oracle(S):
     np.testing.assert_allclose(tg.cpu().numpy(), th, rtol=0, atol=1e-5)
 
 
-def _mesh_case(S, SG, seed, side):
+def _mesh_case(S, SG, seed, side, kc=None):
     g = W.mesh3d(side, side, side, seed=seed, wdist=("lognormal", 0.0, 1.5))
     X0 = W.random_block(g.n, 16, 500 + seed)
-    pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0[:, :SG.KC]))
+    pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0[:, :(SG.KC if kc is None else kc)]))
     pp.raw_nf, pp.raw_ef = SG.features(pp, None)
     return g, X0, pp, SG.plain_scores(pp, dev(X0), 20)
 
 
-def _train_small(S, SG, n_train=10, side=20, epochs=30):
-    cases = [_mesh_case(S, SG, 300 + i, side) for i in range(n_train)]
+def _train_small(S, SG, n_train=10, side=20, epochs=30, kc=None):
+    cases = [_mesh_case(S, SG, 300 + i, side, kc) for i in range(n_train)]
     ts = SG.TrainSet([c[2] for c in cases], [torch.log(c[3] + 1e-30) for c in cases])
     return SG.train(ts, epochs=epochs)
 
@@ -151,12 +152,42 @@ def test_training_learns_and_beats_the_cheap_score(S, SG):
     assert (kp == 1).sum() == g.n - 1 and (kp == 2).sum() == res.k_sel
 
 
+def test_recall_configuration(S, SG):
+    # all 16 of the method's vectors in the cheap embedding: the candidates hold the plain selection
+    model, hist = _train_small(S, SG, kc=SG.KC_RECALL)
+    assert model.kc == SG.KC_RECALL and model.tc == SG.TC
+    g, X0, pp, s = _mesh_case(S, SG, 351, 20, kc=SG.KC_RECALL)
+    nc = int(pp.cand.numel())
+    chosen = torch.nonzero(S.sfg_select_topk(s, int(np.ceil(0.1 * nc)))[0]).reshape(-1)
+    pred = SG.predict(model, pp)
+    rec = {cf: SG.recall(chosen, torch.nonzero(S.sfg_select_topk(pred, int(np.ceil(cf * nc)))[0]).reshape(-1), nc)
+           for cf in (0.2, 0.3)}
+    assert rec[0.2] >= 0.97 and rec[0.3] >= 0.99, rec
+    # the pruned path takes the model's cheap embedding from the block
+    res = SG.sparsify_pruned(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), model, 20, 0.1, 0.3)
+    assert not res.fallback and res.n_scored == int(np.ceil(0.3 * nc))
+
+
 def test_model_file_roundtrip_and_fallback(S, SG, tmp_path):
-    model = SG.Model(SG.init_params(1), torch.ones(24, device="cuda"), 0.0, 1.0)
+    model = SG.Model(SG.init_params(1), torch.ones(24, device="cuda"), 0.0, 1.0, kc=16, tc=6)
     p = str(tmp_path / "m.npz")
     model.save(p)
     m2 = SG.load(p)
-    assert torch.equal(m2.params, model.params)
+    assert torch.equal(m2.params, model.params) and (m2.kc, m2.tc) == (16, 6)
+    # the cheap embedding is part of the checksum, and must be sane
+    z = dict(np.load(p, allow_pickle=False))
+    z["cheap"] = np.array([4, 6], dtype=np.int64)
+    np.savez(str(tmp_path / "kc.npz"), **z)
+    with pytest.raises(SG.SurrogateInvalid, match="checksum"):
+        SG.load(str(tmp_path / "kc.npz"))
+    z["cheap"] = np.array([0, 6], dtype=np.int64)
+    np.savez(str(tmp_path / "kc0.npz"), **z)
+    with pytest.raises(SG.SurrogateInvalid, match="cheap embedding"):
+        SG.load(str(tmp_path / "kc0.npz"))
+    z["version"] = np.int64(1)
+    np.savez(str(tmp_path / "v1.npz"), **z)
+    with pytest.raises(SG.SurrogateInvalid, match="version"):
+        SG.load(str(tmp_path / "v1.npz"))
     # corrupted parameters: checksum mismatch
     z = dict(np.load(p, allow_pickle=False))
     z["params"] = z["params"].copy()
