@@ -22,8 +22,13 @@
  * - The four primitives (sfg_laplacian_csr, sfg_smooth, sfg_edge_scores,
  *   sfg_select_topk and the affinity / coarsening calls) allocate nothing:
  *   the caller passes a workspace of at least sfg_workspace_bytes() bytes.
- *   sfg_sparsify allocates its intermediate buffers itself (stream-ordered)
- *   and frees them before it returns.
+ *   sfg_sparsify, sfg_spanning_tree and sfg_kappa_estimate allocate their
+ *   buffers themselves, stream-ordered, in chunks of at least 256 MB.  When
+ *   a call completes (its stream drained) its chunks go to a per-device
+ *   cache of at most 16 GiB that later calls reuse, held until the process
+ *   ends; a call that fails frees its chunks (stream-ordered) instead.  The
+ *   device's default pool of stream-ordered memory is set to keep up to
+ *   16 GiB of freed memory for reuse.
  * - Sizes: nnz = 2*(number of edges in the graph) must be < 2^31.
  */
 #ifndef SFG_H_
@@ -225,7 +230,7 @@ sfg_status sfg_select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t 
  *   n_comp     (host) receives the number of components of the forest;
  *              synchronises
  * Runs Boruvka rounds on the device (integer atomics only, deterministic).
- * Errors: SFG_ENOMEM, SFG_EHIP.  (Allocates internally, stream-ordered.)
+ * Errors: SFG_ENOMEM, SFG_EHIP.  (Allocates internally: see the conventions.)
  */
 sfg_status sfg_spanning_tree(int64_t n, int64_t m, const int32_t *u, const int32_t *v,
                              const void *w, sfg_dtype wt, const uint8_t *allowed,
@@ -349,7 +354,7 @@ typedef struct {
  *   y0               n-by-k FP64 starting block, or NULL (drawn from kp->seed)
  *   rep              (host, may be NULL) per-step values and iteration counts
  *   kappa            (host) out: the estimate
- * Allocates its buffers (stream-ordered) and frees them before it returns.
+ * Allocates its buffers internally (see the conventions).
  * Synchronises.  Errors: SFG_EINVAL, SFG_ENOTCONN (the edges marked 1 are not
  * a spanning tree), SFG_ENUMERIC (the block lost rank), SFG_ENOMEM, SFG_EHIP.
  */
