@@ -49,17 +49,18 @@ CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
     return p;
 }
 
-// estart[p] = first edge with u >= p (p = 0..n)
+// estart[p] = first edge with u >= p (p = 0..n).  The edge list is sorted by
+// u, so edge e (e = 0..m, with u[-1] = -1 and u[m] = n) is that first edge for
+// exactly the p in (u[e-1], u[e]]: one coalesced pass over the edges.  The
+// range is clamped to [0, n], so an unsorted list cannot write out of bounds.
 __global__ void k_estart(int64_t n, int64_t m, const int32_t *__restrict__ u, int32_t *estart) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > n) return;
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (u[mid] < p) lo = mid + 1;
-        else hi = mid;
-    }
-    estart[p] = (int32_t)lo;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e > m) return;
+    int64_t lo = e == 0 ? 0 : (int64_t)u[e - 1] + 1;
+    int64_t hi = e == m ? n : (int64_t)u[e];
+    if (lo < 0) lo = 0;
+    if (hi > n) hi = n;
+    for (int64_t p = lo; p <= hi; ++p) estart[p] = (int32_t)e;
 }
 
 __global__ void k_inc(int64_t m, const uint8_t *__restrict__ mask, int32_t *inc) {
@@ -301,7 +302,7 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
     fill_i32(p.fill, n + 1, 0, s);
     fill_i32(p.long_cnt, 1, 0, s);
     fill_i32(p.deg_cnt, 1, 0, s);
-    hipLaunchKernelGGL(k_estart, dim3(grid_for(n + 1, 256)), b, 0, s, n, m, u, p.estart);
+    hipLaunchKernelGGL(k_estart, dim3(grid_for(m + 1, 256)), b, 0, s, n, m, u, p.estart);
     SFG_LAUNCH_CHECK();
     if (m > 0) {
         if (mask) {
