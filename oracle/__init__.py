@@ -641,7 +641,7 @@ def kappa_estimate(n, u, v, w, mask, Y0, steps: int) -> list:
 
 
 def sparsify_sigma(n, u, v, w, X0s, Y0s, sigma, frac, max_rounds, sweeps, est_steps, omega=0.5,
-                   embed="sparsifier"):
+                   embed="sparsifier", smoother="jacobi"):
     """Sigma-driven stopping (Alg. 1 takes sigma but never uses it): start
     from the maximum-weight spanning tree and, while the condition-number
     estimate exceeds sigma^2 (Eq. 2) and rounds remain, add the next
@@ -661,7 +661,7 @@ def sparsify_sigma(n, u, v, w, X0s, Y0s, sigma, frac, max_rounds, sweeps, est_st
         take = min(q, int((~base).sum()))
         if take == 0:
             break
-        lr, X = score_level(n, u, v, w, base, X0s[r], sweeps, omega, frac, embed, k_take=take)
+        lr, X = score_level(n, u, v, w, base, X0s[r], sweeps, omega, frac, embed, k_take=take, smoother=smoother)
         keep[lr.chosen] = 2
         base[lr.chosen] = True
         results.append(lr)

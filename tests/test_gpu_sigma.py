@@ -252,13 +252,17 @@ def test_kappa_errors(S, orc):
 
 # --------------------------------------------------------------------------- sigma-driven sparsify
 
-def sigma_case(S, orc, g, sigma, frac, k=8, sweeps=10, rounds=16, est_k=4, est_steps=6):
+def sigma_case(S, orc, g, sigma, frac, k=8, sweeps=10, rounds=16, est_k=4, est_steps=6, omega=0.5,
+               embed="sparsifier", smoother="jacobi"):
     seed = 31
     X0s = [orc.random_block(g.n, k, seed, r) for r in range(16)]
     Y0s = [orc.random_block(g.n, est_k, seed, 64 + j) for j in range(17)]
-    res, kaps = orc.sparsify_sigma(g.n, g.u, g.v, g.w, X0s, Y0s, sigma, frac, rounds, sweeps, est_steps)
+    res, kaps = orc.sparsify_sigma(g.n, g.u, g.v, g.w, X0s, Y0s, sigma, frac, rounds, sweeps, est_steps, omega,
+                                   embed, smoother)
     est = S.make_kappa_params(k=est_k, steps=est_steps, tol=1e-11)
-    p = S.make_params(k=k, sweeps=sweeps, frac=frac, rounds=rounds, seed=seed, sigma=sigma, est=est)
+    p = S.make_params(k=k, sweeps=sweeps, frac=frac, rounds=rounds, seed=seed, sigma=sigma, est=est, omega=omega,
+                      embed=S.EMBED_GRAPH if embed == "graph" else S.EMBED_SPARSIFIER,
+                      smoother=S.SMOOTH_GAUSS_SEIDEL if smoother == "gs" else S.SMOOTH_JACOBI)
     info = {}
     keep, levels = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), None, p, info=info)
     return res, kaps, host(keep), levels, info
@@ -316,4 +320,38 @@ def test_sigma_param_errors(S, orc):
     p = S.make_params(sigma=3.0, est=S.make_kappa_params(k=40))
     with pytest.raises(S.SfgError) as e:
         S.sfg_sparsify(g.n, U, V, Wt, None, p)
+    assert e.value.name == "SFG_EINVAL"
+
+
+@pytest.mark.parametrize("embed,smoother,omega", [("graph", "jacobi", 0.5), ("sparsifier", "gs", 1.0)])
+def test_sigma_with_other_embeddings_and_smoothers(S, orc, embed, smoother, omega):
+    g = TREES["grid64"]()
+    base = tree_mask(orc, g)
+    k0 = orc.kappa_estimate(g.n, g.u, g.v, g.w, base, orc.random_block(g.n, 4, 31, 64), 6)[-1]
+    sigma = math.sqrt(0.25 * k0)
+    res, kaps, keep, levels, info = sigma_case(S, orc, g, sigma, 0.03, omega=omega, embed=embed, smoother=smoother)
+    assert len(levels) == len(res.levels) >= 1
+    assert all(abs(x - sigma ** 2) > 1e-4 * sigma ** 2 for x in kaps)
+    assert np.array_equal(keep, res.keep)
+    for a, b in zip(kaps, info["kappa"]):
+        assert abs(a - b) <= 1e-6 * a
+
+
+def test_sigma_degenerate_graphs(S, orc):
+    # a graph that is its own spanning tree: no candidates, the estimate is exactly the identity pencil's 1
+    g = W.grid2d(1, 40, seed=92)                 # a path
+    keep, levels = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), None,
+                                  S.make_params(k=4, sweeps=5, frac=0.1, sigma=1.5,
+                                                est=S.make_kappa_params(k=3, steps=3, tol=1e-11)),
+                                  info=(info := {}))
+    assert levels == [] and len(info["kappa"]) == 1 and abs(info["kappa"][0] - 1.0) < 1e-12
+    assert int((host(keep) == 1).sum()) == g.n - 1
+    # two nodes, one edge: the estimate needs k <= n - 1 = 1
+    g2 = W.grid2d(1, 2, seed=93)
+    kap, _ = S.sfg_kappa_estimate(2, dev(g2.u), dev(g2.v), dev(g2.w), dev(np.ones(1, np.uint8)),
+                                  S.make_kappa_params(k=1, steps=2, tol=1e-11))
+    assert abs(kap - 1.0) < 1e-12
+    with pytest.raises(S.SfgError) as e:
+        S.sfg_kappa_estimate(2, dev(g2.u), dev(g2.v), dev(g2.w), dev(np.ones(1, np.uint8)),
+                             S.make_kappa_params(k=2, steps=2))
     assert e.value.name == "SFG_EINVAL"
