@@ -462,7 +462,8 @@ void launch_sweep(const sfg_csr *H, int32_t k, const TIN *x, const double *mean,
 // tree with random node order), so it is not split.  Each column's arithmetic
 // is unchanged: the result is bit-identical.  SFG_SWEEP_SPLIT (read at every
 // call) = 0 turns it off, 2 forces it for any FP64 block of k >= 16, k % 8 == 0
-// (tests use it to cover the part sweeps on small graphs).
+// (tests use it to cover the part sweeps on small graphs).  SFG_SWEEP_U
+// overrides the part sweeps' unroll too, for tuning.
 template <typename TX>
 SweepShape part_shape(const sfg_csr *H, int32_t k) {
     const int split = env_int("SFG_SWEEP_SPLIT", 1);
@@ -476,7 +477,8 @@ SweepShape part_shape(const sfg_csr *H, int32_t k) {
         sh.kw = 8;
         sh.ldx = sh.ldy = 8;
         sh.vpl = pick_vpl<TX>(8, 16);
-        sh.u = 4;
+        static const int forced_u = env_int("SFG_SWEEP_U", 0);
+        sh.u = forced_u ? forced_u : 4;
         return sh;
     }
     return full_shape<TX>(H, k);
