@@ -85,19 +85,47 @@ def run_knn(args) -> dict:
     X0 = W.workload_block("knn", g.n)
     u, v, w64 = to_dev(g)
     x0 = torch.from_numpy(X0).cuda()
+    # FP64 reference: the library's FP64 path, bit-identical to the oracle's (tests/test_gpu_workloads.py and the
+    # FP64 parity tests check that); its scores on the spanning tree's off-tree edges and its sparsifier
+    keep64, rep64 = S.sfg_sparsify(g.n, u, v, w64, x0, S.make_params(k=k, sweeps=T, frac=f))
+    keep64_h = keep64.cpu().numpy()
+    tree_t = (keep64 == 1).to(torch.uint8)
+    cand_t = torch.nonzero(tree_t == 0).reshape(-1).to(torch.int32)
+    H64 = S.sfg_laplacian_csr(g.n, u, v, w64, mask=tree_t)
+    s64 = S.sfg_edge_scores(S.sfg_smooth(H64, x0, T, 0.5, storage=torch.float64), u, v, w64, cand=cand_t)
+    s64 = s64.cpu().numpy()
+    tau64 = float(rep64[0]["tau"])
+    H32 = S.sfg_laplacian_csr(g.n, u, v, w64.float(), mask=tree_t)
     res = {}
-    for name, storage, ff in (("f16+f32last", torch.float16, True), ("bf16+f32last", torch.bfloat16, True),
-                              ("f32", torch.float32, False)):
-        p = S.make_params(k=k, sweeps=T, frac=f, storage=storage, final_f32=ff, band=band)
+    # BF16's threshold-normalised error (3.2% on this graph) needs a 4% margin; FP16 and FP32 take the 1% band
+    for name, storage, ff, bd in (("f16+f32last", torch.float16, True, band),
+                                  ("bf16+f32last", torch.bfloat16, True, 0.04), ("f32", torch.float32, False, band)):
+        p = S.make_params(k=k, sweeps=T, frac=f, storage=storage, final_f32=ff, band=bd)
         S.sfg_sparsify(g.n, u, v, w64, x0, p)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         keep, rep = S.sfg_sparsify(g.n, u, v, w64, x0, p)
         t1 = time.perf_counter()
         r = rep[0]
+        # score error of this storage before re-scoring, against the FP64 scores
+        sr = S.sfg_edge_scores(S.sfg_smooth(H32, x0, T, 0.5, storage=storage, final_f32=ff), u, v, w64.float(),
+                               cand=cand_t).cpu().numpy().astype(np.float64)
+        d = np.abs(sr - s64)
+        pos = s64 > 0
+        top = s64 >= tau64
+        kh = keep.cpu().numpy()
+        sel, sel64 = kh == 2, keep64_h == 2
         res[name] = {"ms_total": round((t1 - t0) * 1e3, 2), "ms_smooth": round(r["ms_smooth"], 3),
                      "ms_score": round(r["ms_score"], 3), "ms_select_and_band": round(r["ms_select"], 3),
-                     "band_edges": r["band"], "band_doublings": r["band_rounds"], "cone_row_updates": r["cone_rows"]}
+                     "band": bd, "band_edges": r["band"], "band_doublings": r["band_rounds"],
+                     "cone_row_updates": r["cone_rows"],
+                     # over all candidates the relative error is unbounded (the smallest FP64 scores are near 0);
+                     # selection depends on the two measures after it
+                     "score_max_rel_err": float(np.max(d[pos] / s64[pos])),
+                     "score_max_rel_err_above_tau": float(np.max(d[top] / s64[top])),
+                     "score_max_err_over_tau": float(np.max(d) / tau64),
+                     "selected_set_identical_to_f64": bool(np.array_equal(kh, keep64_h)),
+                     "selected_set_agreement": float((sel & sel64).sum() / max(int(sel64.sum()), 1))}
         log(f"knn {name}: {res[name]}")
     p = S.make_params(k=k, sweeps=T, frac=f)
     S.sfg_sparsify(g.n, u, v, w64, x0, p)
