@@ -112,7 +112,7 @@ def test_tree_order_errors(S, orc):
     assert e.value.name == "SFG_EINVAL"
 
 
-@pytest.mark.parametrize("k", [1, 3, 8])
+@pytest.mark.parametrize("k", [1, 3, 8, 17, 64])   # 17 does not divide the 256-thread workgroup; 64 is the largest
 def test_tree_solve_matches_oracle(S, orc, tgraph, k):
     g = tgraph
     print(f"tree_solve {g.name} k={k}", flush=True)
@@ -196,6 +196,21 @@ def test_kappa_steps_match_oracle(S, orc, name, frac):
     assert rep["unconverged"] == 0
     assert np.allclose(rep["ritz"], want, rtol=1e-6, atol=0)
     assert kap == rep["ritz"][-1]
+
+
+@pytest.mark.parametrize("k", [5, 32])   # odd: one column per thread in the Laplacian product; 32: the largest
+def test_kappa_block_widths(S, orc, k):
+    g = TREES["rand1500"]()
+    base = tree_mask(orc, g)
+    keep = base.astype(np.uint8)
+    lr, _ = orc.score_level(g.n, g.u, g.v, g.w, base, orc.random_block(g.n, 8, 5), 10, 0.5, 0.1)
+    keep[lr.chosen] = 2
+    Y0 = orc.random_block(g.n, k, 22, 1)
+    want = orc.kappa_estimate(g.n, g.u, g.v, g.w, keep > 0, Y0, 4)
+    kap, rep = S.sfg_kappa_estimate(g.n, dev(g.u), dev(g.v), dev(g.w), dev(keep),
+                                    S.make_kappa_params(k=k, steps=4, tol=1e-11), y0=dev(Y0))
+    assert rep["unconverged"] == 0
+    assert np.allclose(rep["ritz"], want, rtol=1e-6, atol=0)
 
 
 def test_kappa_seeded_start(S, orc):
