@@ -117,7 +117,8 @@ def run_knn(args) -> dict:
         sel, sel64 = kh == 2, keep64_h == 2
         res[name] = {"ms_total": round((t1 - t0) * 1e3, 2), "ms_smooth": round(r["ms_smooth"], 3),
                      "ms_score": round(r["ms_score"], 3), "ms_select_and_band": round(r["ms_select"], 3),
-                     "band": bd, "band_edges": r["band"], "band_doublings": r["band_rounds"],
+                     "band": bd, "precision_fallback": r["precision_fallback"], "band_edges": r["band"],
+                     "band_doublings": r["band_rounds"],
                      "cone_row_updates": r["cone_rows"],
                      # over all candidates the relative error is unbounded (the smallest FP64 scores are near 0);
                      # selection depends on the two measures after it

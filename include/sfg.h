@@ -401,6 +401,9 @@ typedef struct {
     int32_t band_rounds;   /* margin doublings needed */
     float ms_smooth, ms_score, ms_select, ms_other;
     int64_t cone_rows;     /* row updates spent on FP64 re-scoring (sum over sweeps) */
+    int32_t precision_fallback;   /* F16/BF16/F32 with a band: 1 when the re-scoring cone predicted for the
+                                     expected band exceeded a quarter of the full pass, so the level ran the
+                                     FP64 path instead (same selection, no reduced-precision pass) */
 } sfg_level_report;
 
 typedef struct {

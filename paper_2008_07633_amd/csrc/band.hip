@@ -13,8 +13,11 @@
 // full pass's row updates (T = 20 on meshes and kNN graphs reaches most of
 // the graph), the full FP64 smoothing runs instead: it sweeps rows in node
 // order, several times faster per row than the distance-ordered cone, and
-// gives the same bits.
+// gives the same bits.  predicted_cone_share makes that call before any
+// smoothing, from a sample standing in for the band, so that the driver can
+// skip the reduced-precision pass when the full FP64 pass is coming anyway.
 #include <algorithm>
+#include <cmath>
 #include <vector>
 
 #include "common.hpp"
@@ -162,6 +165,51 @@ __global__ void k_band_apply(int64_t nb, const int32_t *__restrict__ pos, const 
 }
 
 }  // namespace
+
+// Evenly strided sample of the candidates: nb edge ids (stride nc / nb)
+__global__ void k_stride_sample(int64_t nb, int64_t nc, const int32_t *__restrict__ cand, int32_t *eids) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) eids[i] = cand[(int64_t)((double)i * (double)nc / (double)nb)];
+}
+
+// Predicted share of the full pass's row updates that the FP64 re-scoring
+// cone would take, before any smoothing: the band is not known yet, so its
+// endpoints are stood in for by an evenly strided sample of the candidates
+// of the expected band size (about band * n_cand / 2: 0.4-0.6% of the
+// candidates for a 1% band on grids, meshes and kNN graphs), and the same
+// capped BFS measures their T-hop neighbourhood.  Synchronises.
+double predicted_cone_share(const sfg_csr *H, int32_t sweeps, int64_t n_cand, const int32_t *cand,
+                            const int32_t *u, const int32_t *v, double band, DevArena &A, hipStream_t s) {
+    const int64_t n = H->n;
+    if (n_cand <= 0 || sweeps <= 0) return 0.0;
+    int64_t nb = (int64_t)std::ceil(0.5 * band * (double)n_cand);
+    nb = std::max<int64_t>(1, std::min(nb, n_cand));
+    int32_t *eids = A.alloc<int32_t>(nb + 1);
+    hipLaunchKernelGGL(k_stride_sample, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, n_cand, cand, eids);
+    SFG_LAUNCH_CHECK();
+    int32_t *dist = A.alloc<int32_t>(n + 1);
+    fill_i32(dist, n, sweeps + 1, s);
+    hipLaunchKernelGGL(k_seed_dist, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, eids, u, v, dist);
+    SFG_LAUNCH_CHECK();
+    for (int32_t lvl = 0; lvl < sweeps; ++lvl) {
+        hipLaunchKernelGGL(k_bfs_level, dim3(grid_for(n, 256)), dim3(256), 0, s, n, H->rowptr, H->col, lvl, dist);
+        SFG_LAUNCH_CHECK();
+    }
+    int32_t *hist = A.alloc<int32_t>(sweeps + 2);
+    fill_i32(hist, sweeps + 2, 0, s);
+    const dim3 gd(std::min<uint32_t>(grid_for(n, 256), (uint32_t)kDistBlocks));
+    hipLaunchKernelGGL(k_dist_hist, gd, dim3(256), 0, s, n, dist, sweeps, hist);
+    SFG_LAUNCH_CHECK();
+    std::vector<int32_t> hh(sweeps + 1);
+    SFG_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * (sweeps + 1), hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    // sweep t recomputes the rows within sweeps-1-t hops
+    int64_t within = 0, cone = 0;
+    std::vector<int64_t> upto(sweeps + 1);
+    for (int32_t d = 0; d <= sweeps; ++d) upto[d] = (within += hh[d]);
+    for (int32_t t = 0; t < sweeps; ++t) cone += upto[sweeps - 1 - t];
+    return (double)cone / ((double)sweeps * (double)n);
+}
 
 void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, const double *x0, int64_t n_cand,
                   const int32_t *cand, const int32_t *u, const int32_t *v, const double *w64, const float *score_lo,

@@ -38,6 +38,8 @@ size_t affinity_workspace_bytes(int64_t n, int32_t k);
 size_t coarsen_workspace_bytes(int64_t n, int64_t m);
 size_t mpnn_forward_workspace_bytes(int64_t n, sfg_dtype act);
 size_t mpnn_train_workspace_bytes(int64_t n, int64_t ne);
+double predicted_cone_share(const sfg_csr *H, int32_t sweeps, int64_t n_cand, const int32_t *cand,
+                            const int32_t *u, const int32_t *v, double band, DevArena &A, hipStream_t s);
 void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, const double *x0, int64_t n_cand,
                   const int32_t *cand, const int32_t *u, const int32_t *v, const double *w64, const float *score_lo,
                   int64_t k_sel, double tau_lo, double band, uint8_t *sel, sfg_level_report *rep, DevArena &A,
@@ -308,6 +310,33 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
     SFG_HIP(hipMemcpyAsync(&nnz, rowptr + n, 4, hipMemcpyDeviceToHost, s));
     SFG_HIP(hipStreamSynchronize(s));
     sfg_csr H{n, nnz, rowptr, col, val, eid, deg, vt};
+    // Precision form: when the FP64 re-scoring cone of the expected band would
+    // cover more than a quarter of the full pass's row updates, the full FP64
+    // smoothing would run after the reduced-precision one anyway; take the FP64
+    // path directly (the same selection as the precision form reaches whenever
+    // its margin covers the error, and always the FP64 oracle's).
+    // SFG_PRECISION_PREDICT=0 (read at every call) keeps the precision form
+    // regardless (tests use it to exercise the band re-scoring).
+    const char *pe = getenv("SFG_PRECISION_PREDICT");
+    const bool predict = !(pe && atoi(pe) == 0);
+    if (predict && !f64 && p->band > 0.0 && p->smoother == SFG_SMOOTH_JACOBI) {
+        int32_t *cand0 = A.alloc<int32_t>(m + 1);
+        const int64_t nc0 = compact_ids(base, 0, m, cand0, A, s);
+        const int64_t ks0 = k_take >= 0 ? k_take : (int64_t)std::ceil(p->frac * (double)nc0);
+        if (ks0 > 0 && ks0 < nc0 &&
+            4.0 * predicted_cone_share(&H, p->sweeps, nc0, cand0, u, v, p->band, A, s) > 1.0) {
+            sfg_params p64 = *p;
+            p64.storage = SFG_F64;
+            p64.band = 0.0;
+            p64.final_f32 = 0;
+            score_level(n, m, u, v, w64, w32, base, &p64, x0, keep, rep, A, s, k_take);
+            if (rep) {
+                rep->precision_fallback = 1;
+                rep->cone_rows = (int64_t)p->sweeps * n;
+            }
+            return;
+        }
+    }
     // embedding
     const bool f32last = p->final_f32 && (p->storage == SFG_F16 || p->storage == SFG_BF16);
     const sfg_dtype xt = f32last ? SFG_F32 : p->storage;

@@ -260,8 +260,9 @@ def test_sparsify_rounds_match_oracle(S, orc, graph, rounds):
             assert r["tau"] == lr.tau
 
 
-def test_sparsify_rounds_precision_form(S, orc):
-    # FP16 embedding with FP64 re-scoring of the band, round by round
+def test_sparsify_rounds_precision_form(S, orc, monkeypatch):
+    # FP16 embedding with FP64 re-scoring of the band, round by round (the predicted-cone shortcut is off)
+    monkeypatch.setenv("SFG_PRECISION_PREDICT", "0")
     g = W.powergrid(90, 80, 0.02, seed=95)
     k, T, f, R = 16, 8, 0.1, 3
     X0s = np.stack([W.random_block(g.n, k, 96 + r) for r in range(R)])

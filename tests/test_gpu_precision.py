@@ -46,7 +46,9 @@ def graph_of(name):
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[4]}-ff{c[5]}-k{c[1]}")
-def test_band_rescoring_gives_fp64_set(S, orc, case):
+def test_band_rescoring_gives_fp64_set(S, orc, case, monkeypatch):
+    # the band re-scoring itself: the predicted-cone shortcut to the FP64 path is switched off
+    monkeypatch.setenv("SFG_PRECISION_PREDICT", "0")
     name, k, T, f, storage, ff, band, path = case
     g = graph_of(name)
     X0 = W.random_block(g.n, k, 500 + k)
@@ -64,6 +66,27 @@ def test_band_rescoring_gives_fp64_set(S, orc, case):
         assert 0 < r["cone_rows"] < T * g.n // 4, r
     elif path == "full":
         assert r["cone_rows"] == T * g.n, r
+
+
+@pytest.mark.parametrize("case,fallback", [(CASES[0], True), (CASES[4], True), (CASES[5], False)],
+                         ids=["knn-T20", "mesh-T20", "pgrid300-T3"])
+def test_predicted_cone_takes_fp64_path(S, orc, case, fallback):
+    # before smoothing, the cone of a band-sized sample of candidates decides: T = 20 hops cover most of a kNN
+    # graph or a mesh, so the level runs the FP64 path; 3 sweeps on a power grid keep the precision form
+    name, k, T, f, storage, ff, band, path = case
+    g = graph_of(name)
+    X0 = W.random_block(g.n, k, 500 + k)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, T, f)
+    p = S.make_params(k=k, sweeps=T, frac=f, storage=storage, final_f32=ff, band=band)
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), p)
+    r = rep[0]
+    assert r["precision_fallback"] == (1 if fallback else 0), r
+    assert np.array_equal(keep.cpu().numpy(), ref.keep)
+    assert r["tau"] == ref.levels[0].tau
+    if fallback:
+        assert r["band"] == 0 and r["cone_rows"] == T * g.n
+    else:
+        assert r["band"] > 0 and 0 < r["cone_rows"] < T * g.n // 4
 
 
 def test_low_precision_score_errors_reported(S, orc):

@@ -62,8 +62,8 @@ def test_knn_full_size_precision(S, orc):
         print(name, "band", rep[0]["band"], "doublings", rep[0]["band_rounds"], "cone rows", rep[0]["cone_rows"],
               "differing edges", int((got != ref.keep).sum()), flush=True)
         assert np.array_equal(got, ref.keep), name
-        # 20 hops of the tree reach most of the graph: the full FP64 smoothing is taken
-        assert rep[0]["cone_rows"] == T * g.n
+        # 20 hops of the tree reach most of the graph: the predicted cone sends the level to the FP64 path
+        assert rep[0]["cone_rows"] == T * g.n and rep[0]["precision_fallback"] == 1
 
 
 def test_surrogate_condition_number(S, orc):
