@@ -352,7 +352,7 @@ def run_sigma(args) -> dict:
     p = S.make_params(k=prm["k"], sweeps=prm["sweeps"], frac=prm["frac"], seed=1)
     keep, _ = S.sfg_sparsify(g.n, u, v, w, None, p)
     nnz_p = 2 * int((keep > 0).sum().item())
-    est = S.make_kappa_params()          # library defaults: 8 vectors, 6 steps, inner tol 1e-2
+    est = S.make_kappa_params()          # library defaults: 8 vectors, 6 steps, inner tol 1e-1
     S.sfg_kappa_estimate(g.n, u, v, w, keep, est)    # warm-up
     torch.cuda.synchronize()
     runs = []

@@ -583,7 +583,7 @@ sfg_kappa_params kappa_defaults(const sfg_kappa_params *in) {
     if (in) p = *in;
     if (p.k == 0) p.k = 8;
     if (p.steps == 0) p.steps = 6;
-    if (p.tol == 0.0) p.tol = 1e-2;
+    if (p.tol == 0.0) p.tol = 1e-1;
     if (p.max_iter == 0) p.max_iter = 20000;
     return p;
 }

@@ -342,13 +342,16 @@ def sfg_coarsen(G: Csr, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, aff: 
     return agg, int(nc.value), cu[:mc], cv[:mc], cw[:mc], crep[:mc]
 
 
-def make_kappa_params(k=8, steps=6, tol=1e-2, max_iter=20000, seed=0, block=0) -> KappaParams:
+def make_kappa_params(k=8, steps=6, tol=1e-1, max_iter=20000, seed=0, block=0) -> KappaParams:
     return KappaParams(k, steps, tol, max_iter, seed, block)
 
 
 def make_params(levels=1, k=8, sweeps=10, omega=0.5, frac=0.05, embed=EMBED_SPARSIFIER, storage=F64,
-                final_f32=False, band=0.0, rounds=1, smoother=SMOOTH_JACOBI, seed=0, sigma=0.0,
+                final_f32=False, band=0.0, rounds=None, smoother=SMOOTH_JACOBI, seed=0, sigma=0.0,
                 est: Optional[KappaParams] = None) -> Params:
+    """rounds: multi-round densification (default 1); with sigma > 0 the cap on batches (default 0 = 16)."""
+    if rounds is None:
+        rounds = 0 if sigma > 0 else 1
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
     return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds, smoother, seed,
                   sigma, est if est is not None else make_kappa_params())
