@@ -405,6 +405,12 @@ typedef struct {
     int32_t precision_fallback;   /* F16/BF16/F32 with a band: 1 when the re-scoring cone predicted for the
                                      expected band exceeded a quarter of the full pass, so the level ran the
                                      FP64 path instead (same selection, no reduced-precision pass) */
+    int32_t node_order;   /* numbering the level was swept in: 0 the input's, 1 the spanning tree's preorder
+                             (Jacobi smoother, single level; taken when the call plans at least 512 sweep
+                             launches of 8-column parts over all its batches, n >= 65536, and more than a
+                             quarter of the scoring graph's entries lie over 4096 rows from their own row;
+                             the environment variable SFG_NODE_ORDER=0 / 1 forces either).  Results are
+                             bit-identical either way: rows keep their entry order */
 } sfg_level_report;
 
 typedef struct {

@@ -38,9 +38,10 @@ void affinity(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t m, cons
 void convert_weights(const void *w, sfg_dtype wt, sfg_dtype want, int64_t m, void *out, hipStream_t s);
 int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
                           const uint8_t *allowed, uint8_t *in_tree, DevArena &A, hipStream_t s);
+struct NodeOrder;
 void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
                  const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
-                 DevArena &A, hipStream_t s, int64_t k_take);
+                 DevArena &A, hipStream_t s, int64_t k_take, NodeOrder *no);
 
 namespace {
 
@@ -485,7 +486,8 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
         }
         uint8_t *kp = (l == 1) ? keep : A.alloc<uint8_t>(F.m + 1);
         sfg_level_report *lr = rep ? &rep->level[l - 1] : nullptr;
-        score_level(F.n, F.m, F.u, F.v, F.w64, F.w32, base, p, x0 + (size_t)(l - 1) * n * p->k, kp, lr, A, s, -1);
+        score_level(F.n, F.m, F.u, F.v, F.w64, F.w32, base, p, x0 + (size_t)(l - 1) * n * p->k, kp, lr, A, s, -1,
+                    nullptr);
         P = kp;
     }
 }

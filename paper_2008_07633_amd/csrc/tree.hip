@@ -35,13 +35,28 @@ namespace {
 constexpr int kB = 256;
 constexpr uint32_t kNil = 0xFFFFFFFFu;
 
+// Grid-stride over a bounded grid, one atomic per workgroup: a single
+// counter takes same-address atomics one at a time, so one per wave over
+// millions of edges would cost milliseconds.
+constexpr uint32_t kMaskBlocks = 1024;
+
 __global__ void k_mask_eq(int64_t m, const uint8_t *__restrict__ keep, uint8_t want, uint8_t *__restrict__ out,
                           int32_t *__restrict__ count) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool in = e < m && keep[e] == want;
-    if (e < m) out[e] = in ? 1 : 0;
-    const uint64_t b = __ballot(in);
-    if ((threadIdx.x & (kWave - 1)) == 0 && b) atomicAdd(count, (int32_t)__popcll(b));
+    __shared__ int32_t part[kB / kWave];
+    int32_t c = 0;
+    for (int64_t e0 = (int64_t)blockIdx.x * blockDim.x; e0 < m; e0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t e = e0 + threadIdx.x;
+        const bool in = e < m && keep[e] == want;
+        if (e < m) out[e] = in ? 1 : 0;
+        c += (int32_t)__popcll(__ballot(in));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < kB / kWave; ++w) t += part[w];
+        if (t) atomicAdd(count, t);
+    }
 }
 
 __device__ __forceinline__ int32_t upper_row(const int32_t *__restrict__ rowptr, int64_t n, int32_t a) {
@@ -675,7 +690,8 @@ void tree_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const 
     const int64_t A = 2 * (n - 1);
     fill_i32(p.count, 2, 0, s);
     if (m > 0) {
-        hipLaunchKernelGGL(k_mask_eq, dim3(grid_for(m, kB)), dim3(kB), 0, s, m, keep, (uint8_t)1, p.mask, p.count);
+        hipLaunchKernelGGL(k_mask_eq, dim3(std::min(grid_for(m, kB), kMaskBlocks)), dim3(kB), 0, s, m, keep,
+                           (uint8_t)1, p.mask, p.count);
         SFG_LAUNCH_CHECK();
     }
     int32_t cnt = 0;

@@ -83,7 +83,8 @@ class LevelReport(ctypes.Structure):
                 ("k_sel", ctypes.c_int64), ("tau", ctypes.c_double), ("band", ctypes.c_int64),
                 ("band_above", ctypes.c_int64), ("band_rounds", ctypes.c_int32),
                 ("ms_smooth", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_select", ctypes.c_float),
-                ("ms_other", ctypes.c_float), ("cone_rows", ctypes.c_int64), ("precision_fallback", ctypes.c_int32)]
+                ("ms_other", ctypes.c_float), ("cone_rows", ctypes.c_int64), ("precision_fallback", ctypes.c_int32),
+                ("node_order", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
