@@ -10,9 +10,9 @@
 //  1. the edge-list slice of every row by binary search over u (no atomics,
 //     so hub rows cost nothing extra); with a mask, a scan of it
 //  2. lower-part counts (integer atomics on v) and one scan: rowptr
-//  3. upper entries: one thread per edge writes its slot directly
-//  4. lower entries: each edge id is dropped into its row (atomic slot), then
-//     every row's lower part is ordered by edge id: a thread per short row
+//  3. upper entries: one thread per edge writes its slot directly, and drops
+//     the edge id into the lower part of its other row (atomic slot)
+//  4. lower entries: every row's lower part is ordered by edge id: a thread per short row
 //     ranks its ids (rank = number of smaller ids), a workgroup per long row
 //     bitonic-sorts the segment in LDS; both write col/val/eid
 //  5. one thread per row sums its weights in column order, in FP64; rows
@@ -30,6 +30,8 @@ constexpr int kDegLong = 256;       // rows longer than this: degree summed by a
 
 struct CsrPlan {
     int32_t *estart, *inc, *incpos, *cnt_lo, *tot, *fill, *tmp, *long_rows, *long_cnt, *deg_rows, *deg_cnt, *scan;
+    int32_t *zeroed;      // cnt_lo, fill, long_cnt, deg_cnt: one contiguous range, cleared by one fill
+    int64_t zeroed_len;
 };
 
 CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
@@ -37,14 +39,16 @@ CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
     p.estart = c.take<int32_t>(n + 1);
     p.inc = c.take<int32_t>(m + 1);
     p.incpos = c.take<int32_t>(m + 1);
-    p.cnt_lo = c.take<int32_t>(n + 1);
+    p.zeroed_len = 2 * (n + 1) + 2;
+    p.zeroed = c.take<int32_t>(p.zeroed_len);
+    p.cnt_lo = p.zeroed;
+    p.fill = p.zeroed + (n + 1);
+    p.long_cnt = p.zeroed + 2 * (n + 1);
+    p.deg_cnt = p.long_cnt + 1;
     p.tot = c.take<int32_t>(n + 1);
-    p.fill = c.take<int32_t>(n + 1);
     p.tmp = c.take<int32_t>(2 * m + 1);
     p.long_rows = c.take<int32_t>(n + 1);
-    p.long_cnt = c.take<int32_t>(1);
     p.deg_rows = c.take<int32_t>(n + 1);
-    p.deg_cnt = c.take<int32_t>(1);
     p.scan = c.take<int32_t>(scan_scratch_ints((n > m ? n : m) + 1));
     return p;
 }
@@ -63,9 +67,15 @@ __global__ void k_estart(int64_t n, int64_t m, const int32_t *__restrict__ u, in
     for (int64_t p = lo; p <= hi; ++p) estart[p] = (int32_t)e;
 }
 
-__global__ void k_inc(int64_t m, const uint8_t *__restrict__ mask, int32_t *inc) {
+// Mask flags for the scan of included edges, and (like k_count_lo) the
+// lower-part count of every row, in one pass over the edges.
+__global__ void k_inc_count(int64_t m, const int32_t *__restrict__ v, const uint8_t *__restrict__ mask, int32_t *inc,
+                            int32_t *cnt_lo) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < m) inc[e] = mask[e] != 0 ? 1 : 0;
+    if (e >= m) return;
+    const bool in = mask[e] != 0;
+    inc[e] = in ? 1 : 0;
+    if (in) atomicAdd(&cnt_lo[v[e]], 1);
 }
 
 __global__ void k_count_lo(int64_t m, const int32_t *__restrict__ v, const uint8_t *__restrict__ mask,
@@ -85,31 +95,26 @@ __global__ void k_row_total(int64_t n, const int32_t *__restrict__ estart, const
     tot[p] = cnt_lo[p] + hi;
 }
 
+// One pass over the edges: edge e is the upper entry of row u[e], written in
+// place, and a lower entry of row v[e], whose id is dropped into that row's
+// lower range (atomic slot; the ranking kernels order it by id).
 template <typename TW>
 __global__ void k_fill_upper(int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
                              const TW *__restrict__ w, const uint8_t *__restrict__ mask,
                              const int32_t *__restrict__ incpos, const int32_t *__restrict__ estart,
                              const int32_t *__restrict__ rowptr, const int32_t *__restrict__ cnt_lo, int32_t *col,
-                             TW *val, int32_t *eid) {
+                             TW *val, int32_t *eid, int32_t *fill, int32_t *tmp) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= m) return;
     if (mask && mask[e] == 0) return;
-    const int32_t p = u[e];
+    const int32_t p = u[e], q = v[e];
     const int32_t k = incpos ? incpos[e] - incpos[estart[p]] : (int32_t)(e - estart[p]);
     const int32_t j = rowptr[p] + cnt_lo[p] + k;
-    col[j] = v[e];
+    col[j] = q;
     val[j] = w[e];
     eid[j] = (int32_t)e;
-}
-
-__global__ void k_place_lower(int64_t m, const int32_t *__restrict__ v, const uint8_t *__restrict__ mask,
-                              const int32_t *__restrict__ rowptr, int32_t *fill, int32_t *tmp) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    if (mask && mask[e] == 0) return;
-    const int32_t b = v[e];
-    const int32_t slot = atomicAdd(&fill[b], 1);
-    tmp[rowptr[b] + slot] = (int32_t)e;
+    const int32_t slot = atomicAdd(&fill[q], 1);
+    tmp[rowptr[q] + slot] = (int32_t)e;
 }
 
 // Ids in a segment are distinct, so the rank of an id is the number of
@@ -260,9 +265,7 @@ void fill_entries(int64_t n, int64_t m, const int32_t *u, const int32_t *v, cons
     const dim3 gn(grid_for(n, 256)), gm(grid_for(m, 256)), b(256);
     if (m > 0) {
         hipLaunchKernelGGL(k_fill_upper<TW>, gm, b, 0, s, m, u, v, w, mask, mask ? p.incpos : nullptr, p.estart,
-                           rowptr, p.cnt_lo, col, val, eid);
-        SFG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_place_lower, gm, b, 0, s, m, v, mask, rowptr, p.fill, p.tmp);
+                           rowptr, p.cnt_lo, col, val, eid, p.fill, p.tmp);
         SFG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_rank_short<TW>, gn, b, 0, s, n, rowptr, p.cnt_lo, p.tmp, u, w, col, val, eid,
                            p.long_rows, p.long_cnt);
@@ -298,20 +301,18 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
     Carver c(ws);
     CsrPlan p = plan_csr(c, n, m);
     const dim3 gn(grid_for(n, 256)), gm(grid_for(m, 256)), b(256);
-    fill_i32(p.cnt_lo, n + 1, 0, s);
-    fill_i32(p.fill, n + 1, 0, s);
-    fill_i32(p.long_cnt, 1, 0, s);
-    fill_i32(p.deg_cnt, 1, 0, s);
+    fill_i32(p.zeroed, p.zeroed_len, 0, s);
     hipLaunchKernelGGL(k_estart, dim3(grid_for(m + 1, 256)), b, 0, s, n, m, u, p.estart);
     SFG_LAUNCH_CHECK();
     if (m > 0) {
         if (mask) {
-            hipLaunchKernelGGL(k_inc, gm, b, 0, s, m, mask, p.inc);
+            hipLaunchKernelGGL(k_inc_count, gm, b, 0, s, m, v, mask, p.inc, p.cnt_lo);
             SFG_LAUNCH_CHECK();
             exclusive_scan_i32(p.inc, p.incpos, m, p.scan, s);
+        } else {
+            hipLaunchKernelGGL(k_count_lo, gm, b, 0, s, m, v, mask, p.cnt_lo);
+            SFG_LAUNCH_CHECK();
         }
-        hipLaunchKernelGGL(k_count_lo, gm, b, 0, s, m, v, mask, p.cnt_lo);
-        SFG_LAUNCH_CHECK();
     }
     hipLaunchKernelGGL(k_row_total, gn, b, 0, s, n, p.estart, (mask && m > 0) ? p.incpos : nullptr, p.cnt_lo, p.tot);
     SFG_LAUNCH_CHECK();
