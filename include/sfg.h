@@ -79,7 +79,8 @@ typedef enum {
     SFG_OP_MPNN_TRAIN = 6,     /* n nodes, m = scored edges */
     SFG_OP_COLOR = 7,          /* n nodes */
     SFG_OP_TREE_ORDER = 8,     /* n nodes, m edges */
-    SFG_OP_TREE_SOLVE = 9      /* n nodes, k columns */
+    SFG_OP_TREE_SOLVE = 9,     /* n nodes, k columns */
+    SFG_OP_CSR_SELECT = 10     /* n nodes, m = edges of the whole graph */
 } sfg_op;
 
 /* Which graph's embedding scores the candidates (Sec. 3.5 derives the score
@@ -115,6 +116,29 @@ sfg_status sfg_laplacian_csr(int64_t n, int64_t m, const int32_t *u, const int32
                              const void *w, sfg_dtype wt, const uint8_t *mask,
                              int32_t *rowptr, int32_t *col, void *val, int32_t *eid, void *deg,
                              int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * The CSR of a subgraph of G (the edges e with mask[e] != 0; L = D - A as in
+ * Sec. 2.1), taken from G's CSR instead of the edge list: row p keeps, in
+ * their stored order, the entries whose edge id is in the mask, and its
+ * degree is their sum, added in FP64 in column order and rounded once.  The
+ * result is bit-identical to sfg_laplacian_csr with the same mask (same
+ * rowptr, col, val, eid and deg).  Used where G's CSR exists already (the
+ * surrogate aggregates over G and embeds on the spanning tree).
+ *   G        device CSR of the whole graph as sfg_laplacian_csr builds it
+ *            (eid required), F64 or F32
+ *   mask     [m] uint8, edge e kept iff mask[e] != 0 (m = the number of edges
+ *            G was built from; every eid of G must index it)
+ *   rowptr   out [n+1]; col, val (G's dtype), eid: out, room for the kept
+ *            entries (2 x kept edges; G->nnz always suffices); deg out [n]
+ *   nnz_out  host, may be NULL: if given, the call synchronises and returns
+ *            rowptr[n]
+ * Workspace: sfg_workspace_bytes(SFG_OP_CSR_SELECT, n, m, 0, 0) with m =
+ * G->nnz / 2.  Errors: SFG_EINVAL (null pointers, a CSR without eid, an odd
+ * nnz, a weight type other than F64 or F32), SFG_EWORKSPACE.
+ */
+sfg_status sfg_csr_select(const sfg_csr *G, const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val,
+                          int32_t *eid, void *deg, int64_t *nnz_out, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Local spectral embedding (Sec. 3.2): make the k random vectors x0

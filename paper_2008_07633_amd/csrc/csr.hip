@@ -280,7 +280,108 @@ void fill_entries(int64_t n, int64_t m, const int32_t *u, const int32_t *v, cons
     SFG_LAUNCH_CHECK();
 }
 
+// ---- the CSR of a subgraph, taken from the CSR of the whole graph: row p
+// keeps, in their stored (ascending column) order, the entries whose edge is
+// in the mask -- exactly the rows build_csr makes from the masked edge list --
+// and its degree is summed by the same kernels as build_csr's.  Entry-parallel:
+// keep flags, their exclusive scan (the new position of every kept entry),
+// new row starts = scan at the old row starts, a scatter of the kept entries.
+__global__ void k_sub_flag(int64_t nnz, const int32_t *__restrict__ eid, const uint8_t *__restrict__ mask,
+                           int32_t *keep) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < nnz) keep[j] = mask[eid[j]] != 0 ? 1 : 0;
+}
+
+__global__ void k_sub_rowptr(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ pos,
+                             int32_t *nrowptr) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p <= n) nrowptr[p] = pos[rowptr[p]];
+}
+
+template <typename TW>
+__global__ void k_sub_scatter(int64_t nnz, const int32_t *__restrict__ keep, const int32_t *__restrict__ pos,
+                              const int32_t *__restrict__ col, const TW *__restrict__ val,
+                              const int32_t *__restrict__ eid, int32_t *__restrict__ ncol, TW *__restrict__ nval,
+                              int32_t *__restrict__ neid) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nnz || keep[j] == 0) return;
+    const int32_t o = pos[j];
+    ncol[o] = col[j];
+    nval[o] = val[j];
+    neid[o] = eid[j];
+}
+
 }  // namespace
+
+namespace {
+
+struct SelectPlan {
+    int32_t *keep, *pos, *scan, *long_rows, *long_cnt;
+};
+
+SelectPlan plan_select_csr(Carver &c, int64_t n, int64_t nnz) {
+    SelectPlan p;
+    p.keep = c.take<int32_t>(nnz + 1);
+    p.pos = c.take<int32_t>(nnz + 1);
+    p.scan = c.take<int32_t>(scan_scratch_ints(nnz + 1));
+    p.long_rows = c.take<int32_t>(n + 1);
+    p.long_cnt = c.take<int32_t>(1);
+    return p;
+}
+
+template <typename TW>
+void select_entries(const sfg_csr *G, const uint8_t *mask, const SelectPlan &p, int32_t *rowptr, int32_t *col,
+                    TW *val, int32_t *eid, TW *deg, hipStream_t s) {
+    const int64_t n = G->n, nnz = G->nnz;
+    const dim3 b(256);
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_sub_flag, dim3(grid_for(nnz, 256)), b, 0, s, nnz, G->eid, mask, p.keep);
+        SFG_LAUNCH_CHECK();
+        exclusive_scan_i32(p.keep, p.pos, nnz, p.scan, s);
+    } else {
+        fill_i32(p.pos, 1, 0, s);
+    }
+    hipLaunchKernelGGL(k_sub_rowptr, dim3(grid_for(n + 1, 256)), b, 0, s, n, G->rowptr, p.pos, rowptr);
+    SFG_LAUNCH_CHECK();
+    if (nnz > 0) {
+        hipLaunchKernelGGL(k_sub_scatter<TW>, dim3(grid_for(nnz, 256)), b, 0, s, nnz, p.keep, p.pos, G->col,
+                           (const TW *)G->val, G->eid, col, val, eid);
+        SFG_LAUNCH_CHECK();
+    }
+    fill_i32(p.long_cnt, 1, 0, s);
+    hipLaunchKernelGGL(k_degree<TW>, dim3(grid_for(n, 256)), b, 0, s, n, rowptr, val, deg, p.long_rows, p.long_cnt);
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_degree_long<TW>, dim3(1024), b, 0, s, rowptr, val, deg, p.long_rows, p.long_cnt);
+    SFG_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+size_t csr_select_workspace_bytes(int64_t n, int64_t m) {
+    Carver c(nullptr);
+    plan_select_csr(c, n < 1 ? 1 : n, 2 * (m < 0 ? 0 : m));
+    return c.used + 256;
+}
+
+void csr_select(const sfg_csr *G, const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val, int32_t *eid,
+                void *deg, void *ws, size_t ws_bytes, hipStream_t s) {
+    SFG_REQUIRE(G && G->n >= 1 && G->nnz >= 0, SFG_EINVAL, "csr_select: need a graph with n >= 1");
+    SFG_REQUIRE(G->nnz % 2 == 0 && G->nnz < (int64_t(1) << 31) - 1, SFG_EINVAL,
+                "csr_select: nnz must be even (two entries per edge) and < 2^31-1");
+    SFG_REQUIRE(G->vt == SFG_F64 || G->vt == SFG_F32, SFG_EINVAL, "csr_select: weights must be F64 or F32");
+    SFG_REQUIRE(G->rowptr && G->deg && (G->nnz == 0 || (G->col && G->val && G->eid)), SFG_EINVAL,
+                "csr_select: the graph CSR needs rowptr, col, val, eid and deg");
+    SFG_REQUIRE(rowptr && deg && (G->nnz == 0 || (mask && col && val && eid)), SFG_EINVAL,
+                "csr_select: null pointer");
+    SFG_REQUIRE(ws_bytes >= csr_select_workspace_bytes(G->n, G->nnz / 2), SFG_EWORKSPACE,
+                "csr_select: workspace too small");
+    Carver c(ws);
+    const SelectPlan p = plan_select_csr(c, G->n, G->nnz);
+    if (G->vt == SFG_F64)
+        select_entries<double>(G, mask, p, rowptr, col, (double *)val, eid, (double *)deg, s);
+    else
+        select_entries<float>(G, mask, p, rowptr, col, (float *)val, eid, (float *)deg, s);
+}
 
 size_t csr_workspace_bytes(int64_t n, int64_t m) {
     Carver c(nullptr);
@@ -325,6 +426,21 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
 }
 
 }  // namespace sfg
+
+extern "C" sfg_status sfg_csr_select(const sfg_csr *G, const uint8_t *mask, int32_t *rowptr, int32_t *col,
+                                     void *val, int32_t *eid, void *deg, int64_t *nnz_out, void *ws,
+                                     size_t ws_bytes, void *stream) {
+    return sfg::guard([&] {
+        hipStream_t s = sfg::as_stream(stream);
+        sfg::csr_select(G, mask, rowptr, col, val, eid, deg, ws, ws_bytes, s);
+        if (nnz_out) {
+            int32_t nnz = 0;
+            SFG_HIP(hipMemcpyAsync(&nnz, rowptr + G->n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            SFG_HIP(hipStreamSynchronize(s));
+            *nnz_out = nnz;
+        }
+    });
+}
 
 extern "C" sfg_status sfg_laplacian_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v,
                                         const void *w, sfg_dtype wt, const uint8_t *mask, int32_t *rowptr,

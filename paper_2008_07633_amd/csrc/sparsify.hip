@@ -13,6 +13,7 @@ namespace sfg {
 
 // from the other translation units
 size_t csr_workspace_bytes(int64_t n, int64_t m);
+size_t csr_select_workspace_bytes(int64_t n, int64_t m);
 void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
                const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val, int32_t *eid, void *deg, void *ws,
                size_t ws_bytes, hipStream_t s);
@@ -651,6 +652,7 @@ extern "C" size_t sfg_workspace_bytes(int op, int64_t n, int64_t m, int32_t k, s
         case SFG_OP_COLOR: return sfg::color_workspace_bytes(n < 1 ? 1 : n);
         case SFG_OP_TREE_ORDER: return sfg::tree_order_workspace_bytes(n < 1 ? 1 : n, m < 0 ? 0 : m);
         case SFG_OP_TREE_SOLVE: return sfg::tree_solve_workspace_bytes(n < 1 ? 1 : n, k < 1 ? 1 : k);
+        case SFG_OP_CSR_SELECT: return sfg::csr_select_workspace_bytes(n, m);
         default: return 0;
     }
 }

@@ -30,14 +30,14 @@ EMBED_SPARSIFIER, EMBED_GRAPH = 0, 1
 STATUS = {0: "SFG_OK", 1: "SFG_EINVAL", 2: "SFG_ENOTCONN", 3: "SFG_ENOMEM", 4: "SFG_EHIP",
           5: "SFG_EWORKSPACE", 6: "SFG_EUNSUPPORTED", 7: "SFG_ENUMERIC"}
 
-OP_MPNN_FORWARD, OP_MPNN_TRAIN, OP_COLOR, OP_TREE_ORDER, OP_TREE_SOLVE = 5, 6, 7, 8, 9
+OP_MPNN_FORWARD, OP_MPNN_TRAIN, OP_COLOR, OP_TREE_ORDER, OP_TREE_SOLVE, OP_CSR_SELECT = 5, 6, 7, 8, 9, 10
 SMOOTH_JACOBI, SMOOTH_GAUSS_SEIDEL = 0, 1
 
 EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores",
             "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify",
             "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam",
             "sfg_color", "sfg_smooth_gs", "sfg_random_block", "sfg_tree_order", "sfg_tree_solve",
-            "sfg_kappa_estimate"]
+            "sfg_kappa_estimate", "sfg_csr_select"]
 
 
 class SfgError(RuntimeError):
@@ -129,6 +129,7 @@ def lib() -> ctypes.CDLL:
         L.sfg_tree_order.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P, P, P, P, S, P]
         L.sfg_tree_solve.argtypes = [P, I32, P, P, P, S, P]
         L.sfg_kappa_estimate.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P, P]
+        L.sfg_csr_select.argtypes = [P, P, P, P, P, P, P, P, P, S, P]
         for name in EXPORTED:
             if name not in ("sfg_workspace_bytes", "sfg_last_error", "sfg_mpnn_param_count"):
                 getattr(L, name).restype = I
@@ -204,6 +205,31 @@ def sfg_laplacian_csr(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
                                    _ptr(out.col), _ptr(out.val), _ptr(out.eid), _ptr(out.deg),
                                    None if nnz is not None else ctypes.byref(got), _ptr(ws), ws.numel(),
                                    _stream()))
+    out.nnz = int(nnz) if nnz is not None else int(got.value)
+    return out
+
+
+def sfg_csr_select(G: Csr, mask: torch.Tensor, out: Optional[Csr] = None, nnz: Optional[int] = None,
+                   ws: Optional[torch.Tensor] = None) -> Csr:
+    """CSR of the subgraph of the edges with mask != 0, taken from G's CSR (bit-identical to
+    sfg_laplacian_csr with the mask).  With ``out`` and ``nnz`` given nothing is allocated and the
+    call does not synchronise."""
+    n = G.n
+    dev = G.rowptr.device
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_CSR_SELECT, n, G.nnz // 2, 0, G.val.dtype), dev)
+    if out is None:
+        cap = G.nnz
+        out = Csr(n, cap, torch.empty(n + 1, dtype=torch.int32, device=dev),
+                  torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                  torch.empty(max(cap, 1), dtype=G.val.dtype, device=dev),
+                  torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
+                  torch.empty(n, dtype=G.val.dtype, device=dev))
+    got = ctypes.c_int64(0)
+    gs = G.struct()
+    _check(lib().sfg_csr_select(ctypes.byref(gs), _ptr(mask), _ptr(out.rowptr), _ptr(out.col), _ptr(out.val),
+                                _ptr(out.eid), _ptr(out.deg), None if nnz is not None else ctypes.byref(got),
+                                _ptr(ws), ws.numel(), _stream()))
     out.nnz = int(nnz) if nnz is not None else int(got.value)
     return out
 

@@ -138,7 +138,7 @@ def prepare(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0c: torc
             raise S.SfgError(2, "graph is not connected")
     cand = torch.nonzero(tree == 0).reshape(-1).to(torch.int32)
     G = S.sfg_laplacian_csr(n, u, v, w32)
-    T = S.sfg_laplacian_csr(n, u, v, w32, mask=tree)
+    T = S.sfg_csr_select(G, tree)
     xc = S.sfg_smooth(T, x0c, sweeps, 0.5, storage=torch.bfloat16, final_f32=True)
     return Prepared(n, u, v, w32, tree, cand, G, T, xc, sweeps)
 

@@ -59,6 +59,9 @@ def test_argument_errors_before_device_work(L):
     st = L.sfg_smooth(ctypes.byref(H), 4, 1, 0.5, None, sfg.F64, 0, None, None, 0, None)
     assert sfg.STATUS[st] == "SFG_EINVAL"
     assert b"null pointer" in L.sfg_last_error()
+    st = L.sfg_csr_select(ctypes.byref(H), None, None, None, None, None, None, None, None, 0, None)
+    assert sfg.STATUS[st] == "SFG_EINVAL"
+    assert b"csr_select" in L.sfg_last_error()
     p = sfg.make_params(k=100)
     st = L.sfg_sparsify(10, 0, None, None, None, sfg.F64, ctypes.byref(p), None, None, None, None)
     assert sfg.STATUS[st] == "SFG_EUNSUPPORTED"
@@ -78,3 +81,12 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(sfg, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="missing"):
         sfg.lib()
+
+
+def test_every_entry_point_has_a_signature(L):
+    # without argtypes ctypes passes Python ints as 32-bit C ints, and a size_t
+    # passed on the stack arrives with undefined upper bits
+    from paper_2008_07633_amd import sfg
+
+    for name in sfg.EXPORTED:
+        assert getattr(L, name).argtypes is not None, name

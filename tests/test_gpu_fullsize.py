@@ -26,6 +26,13 @@ def test_powergrid_full_size_f64_identical(orc):
     assert comps == 1
     cand = torch.nonzero(tree == 0).reshape(-1).to(torch.int32)
     H = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
+    # the tree's CSR taken from the graph's is the same, bit for bit
+    Hs = S.sfg_csr_select(S.sfg_laplacian_csr(g.n, u, v, w), tree)
+    assert Hs.nnz == H.nnz == 2 * (g.n - 1)
+    for f in ("rowptr", "col", "val", "eid", "deg"):
+        assert torch.equal(getattr(Hs, f)[:H.nnz if f in ("col", "val", "eid") else None],
+                           getattr(H, f)[:H.nnz if f in ("col", "val", "eid") else None]), f
+    del Hs
     X = S.sfg_smooth(H, x0, prm["sweeps"], 0.5, storage=torch.float64)
     s = S.sfg_edge_scores(X, u, v, w, cand=cand)
     k = orc.ksel(prm["frac"], int(cand.numel()))

@@ -76,6 +76,37 @@ def test_laplacian_csr_bitwise(S, orc, graph, masked):
         assert np.array_equal(host(H.deg), ref.deg.astype(wdt))
 
 
+@pytest.mark.parametrize("which", ["tree", "half", "none", "all"])
+def test_csr_select_bitwise(S, orc, graph, which):
+    # the CSR of a subgraph taken from G's CSR equals the one built from the masked edge list
+    g = graph
+    rng = np.random.default_rng(41)
+    mask = {"tree": orc.max_spanning_forest(g.n, g.u, g.v, g.w)[0].astype(np.uint8),
+            "half": (rng.random(g.m) < 0.5).astype(np.uint8),
+            "none": np.zeros(g.m, np.uint8), "all": np.full(g.m, 3, np.uint8)}[which]
+    for wdt in (np.float64, np.float32):
+        u, v, w = dev(g.u), dev(g.v), dev(g.w.astype(wdt))
+        G = S.sfg_laplacian_csr(g.n, u, v, w)
+        ref = S.sfg_laplacian_csr(g.n, u, v, w, mask=dev(mask))
+        got = S.sfg_csr_select(G, dev(mask))
+        assert got.nnz == ref.nnz == 2 * int((mask != 0).sum())
+        for f in ("rowptr", "deg"):
+            assert np.array_equal(host(getattr(got, f)), host(getattr(ref, f))), f
+        for f in ("col", "val", "eid"):
+            assert np.array_equal(host(getattr(got, f))[:got.nnz], host(getattr(ref, f))[:ref.nnz]), f
+
+
+def test_csr_select_errors(S):
+    g = W.grid2d(5, 5, seed=42)
+    G = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w))
+    mask = dev(np.ones(g.m, np.uint8))
+    with pytest.raises(S.SfgError):
+        S.sfg_csr_select(G, mask, ws=torch.empty(8, dtype=torch.uint8, device="cuda"))
+    G.eid = None
+    with pytest.raises((S.SfgError, AttributeError, TypeError)):
+        S.sfg_csr_select(G, mask)
+
+
 # --------------------------------------------------------------------------- a2+a3: smoothing
 
 @pytest.mark.parametrize("k,sweeps", [(1, 3), (3, 5), (8, 10), (16, 20), (32, 4), (64, 2), (16, 0)])

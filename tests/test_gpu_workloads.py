@@ -71,7 +71,8 @@ def test_surrogate_condition_number(S, orc):
     meshes, 60 epochs), on 5 held-out 24^3 meshes: the pruned path (exact
     scores of the top 20%) keeps the plain path's condition number, and the
     ranked path (surrogate order alone, 15% of the off-tree edges) reaches at
-    least the plain default's median condition number."""
+    least the plain default's median condition number; so does the 16-vector
+    model ranked at 20%."""
     from paper_2008_07633_amd import surrogate as SG
     from kappa_pool import kappa_many
 
@@ -85,6 +86,17 @@ def test_surrogate_condition_number(S, orc):
         targets.append(torch.log(SG.plain_scores(pp, dev(X0), 20) + 1e-30))
     model, hist = SG.train(SG.TrainSet(graphs, targets), epochs=60)
     del graphs, targets
+    # the recall configuration: all 16 vectors in the cheap embedding
+    graphs, targets = [], []
+    for i in range(50):
+        g = W.mesh3d(40, 40, 40, seed=100 + i, wdist=("lognormal", 0.0, 1.5))
+        X0 = W.random_block(g.n, 16, 2000 + i)
+        pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0[:, :SG.KC_RECALL]))
+        pp.raw_nf, pp.raw_ef = SG.features(pp, None)
+        graphs.append(pp)
+        targets.append(torch.log(SG.plain_scores(pp, dev(X0), 20) + 1e-30))
+    model16, _ = SG.train(SG.TrainSet(graphs, targets), epochs=60)
+    del graphs, targets
     side, jobs = 24, []
     for i in range(5):
         g = W.mesh3d(side, side, side, seed=200 + i, wdist=("lognormal", 0.0, 1.5))
@@ -93,16 +105,19 @@ def test_surrogate_condition_number(S, orc):
         plain, _ = S.sfg_sparsify(g.n, u, v, w, X0, S.make_params(k=16, sweeps=20, frac=0.1, storage=torch.float32))
         pruned = SG.sparsify_pruned(g.n, u, v, w, X0, model, 20, 0.1, 0.2)
         ranked = SG.sparsify_ranked(g.n, u, v, w, X0, model, 20, 0.15)
-        assert not pruned.fallback and not ranked.fallback
-        for keep in (plain, pruned.keep, ranked.keep):
+        ranked16 = SG.sparsify_ranked(g.n, u, v, w, X0, model16, 20, 0.2)
+        assert not pruned.fallback and not ranked.fallback and not ranked16.fallback
+        for keep in (plain, pruned.keep, ranked.keep, ranked16.keep):
             jobs.append((side, 200 + i, keep.cpu().numpy() > 0))
         jobs.append((side, 200 + i, plain.cpu().numpy() == 1))
-    k = np.array(kappa_many(jobs)).reshape(5, 4)
-    print("kappa plain / pruned / ranked(15%) / tree:", k.round(2).tolist(), flush=True)
+    k = np.array(kappa_many(jobs)).reshape(5, 5)
+    print("kappa plain / pruned / ranked(15%) / ranked 16-vector model (20%) / tree:", k.round(2).tolist(),
+          flush=True)
     med = np.median(k, axis=0)
-    assert np.all(k[:, 2] < k[:, 3] / 5)       # far better than the tree alone
+    assert np.all(k[:, 2] < k[:, 4] / 5)       # far better than the tree alone
     assert med[1] <= 1.25 * med[0]            # pruning keeps the plain condition number
     assert med[2] <= med[0]                   # ranking reaches the plain default's median
+    assert med[3] <= med[0]                   # so does the recall configuration at 20%
 
 
 def test_pcg_iterations_fall_with_recovered_edges(S, orc):
