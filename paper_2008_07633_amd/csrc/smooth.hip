@@ -364,6 +364,14 @@ struct SweepShape {
     int32_t kw, ldx, ldy, vpl, u;
 };
 
+// Workgroups of the hub-row kernel (a grid-stride loop over the device-side
+// list of rows over 256 entries).  Graphs averaging 8 or more entries per row
+// (power-law graphs and their dense coarse levels) get 16,384, so that many
+// hub rows are in flight at once: 355 against 377 ms for the 4M-node Chung-Lu
+// hierarchy.  Others get 1,024, since every launch dispatches its workgroups
+// even when the list is empty: 16,384 there cost 1.4 us per sweep.
+inline unsigned long_row_blocks(const sfg_csr *H) { return H->nnz >= 8 * H->n ? 16384u : 1024u; }
+
 template <typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, int U, bool CENTER>
 void launch_sweep_u(const sfg_csr *H, const SweepShape &sh, const TIN *x, const double *mean, TO *y, double omega,
                     const int32_t *rows, int64_t nrows, const LongRows &lr, hipStream_t s) {
@@ -376,8 +384,8 @@ void launch_sweep_u(const sfg_csr *H, const SweepShape &sh, const TIN *x, const 
     SFG_LAUNCH_CHECK();
     if constexpr (sizeof(TA) == 4) {
         if (lr.rows) {
-            hipLaunchKernelGGL((k_sweep_long<TIN, TX, TO, TW, TA, VPL, CENTER>), dim3(1024), dim3(256), 0, s, lpr,
-                               sh.ldx, sh.ldy, lr.rows, lr.count, H->rowptr, H->col, (const TW *)H->val,
+            hipLaunchKernelGGL((k_sweep_long<TIN, TX, TO, TW, TA, VPL, CENTER>), dim3(long_row_blocks(H)), dim3(256),
+                               0, s, lpr, sh.ldx, sh.ldy, lr.rows, lr.count, H->rowptr, H->col, (const TW *)H->val,
                                (const TW *)H->deg, x, mean, y, (TA)(1.0 - omega), (TA)omega);
             SFG_LAUNCH_CHECK();
         }
