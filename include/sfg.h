@@ -413,7 +413,32 @@ typedef struct {
                               edges, scored on the sparsifier grown so far; batch r smooths block r of x0.
                               Estimate j starts from sfg_random_block(n, est.k, seed, 64 + j). */
     sfg_kappa_params est;  /* estimate parameters (seed and block are ignored here) */
+    const struct sfg_surrogate *surrogate;   /* host, may be NULL: see sfg_surrogate */
+    double cand_frac;      /* with a surrogate: fraction of the off-tree edges scored exactly (0 < cand_frac <= 1) */
 } sfg_params;
+
+/* A trained edge-criticality model (not in the paper) that prunes the candidates
+ * of a single-level sparsify.  Callers: those who trade a little recall of the
+ * plain selection for skipping exact scores of most off-tree edges.  With
+ * sfg_params.surrogate set, sfg_sparsify (levels = 1, one round, no sigma,
+ * Jacobi, the sparsifier embedding, no band, F32 or F64 storage):
+ *   1. G's CSR and the spanning tree's, FP32 weights;
+ *   2. the cheap embedding: the first kc columns of x0, centred and smoothed
+ *      tc times on the tree (omega 1/2, BF16 storage, FP32 last iterate);
+ *   3. node and edge features (sfg_mpnn_features with `norm`) and one BF16
+ *      inference (sfg_mpnn_forward) over the off-tree edges;
+ *   4. the top ceil(cand_frac * off-tree edges) by prediction (ties: lower
+ *      edge id) are scored exactly as the plain path scores them (k vectors,
+ *      `sweeps` sweeps on the tree, storage and omega of sfg_params);
+ *   5. of those, the top min(ceil(frac * off-tree edges), scored) are kept.
+ * If a parameter or normalisation value is not finite, the plain path runs
+ * instead and the level report says so (surrogate_fallback = 1). */
+typedef struct sfg_surrogate {
+    const float *params;   /* device [sfg_mpnn_param_count()] FP32 */
+    const float *norm;     /* device [24] FP32: node feature means, inverse stds, edge means, inverse stds */
+    int32_t kc;            /* vectors of the cheap embedding, 1..k */
+    int32_t tc;            /* its sweeps, >= 0 */
+} sfg_surrogate;
 
 /* Per-level report (host). */
 typedef struct {
@@ -435,6 +460,8 @@ typedef struct {
                              quarter of the scoring graph's entries lie over 4096 rows from their own row;
                              the environment variable SFG_NODE_ORDER=0 / 1 forces either).  Results are
                              bit-identical either way: rows keep their entry order */
+    int64_t n_scored;      /* candidates scored exactly (n_cand, or the surrogate's share) */
+    int32_t surrogate_fallback;   /* a surrogate was given but was not usable: the plain path ran */
 } sfg_level_report;
 
 typedef struct {

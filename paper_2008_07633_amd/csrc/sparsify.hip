@@ -33,6 +33,8 @@ void edge_scores(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t ne, 
                  const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt, void *score, sfg_dtype st,
                  hipStream_t s);
 size_t select_workspace_bytes(int64_t ne);
+void csr_select(const sfg_csr *G, const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val, int32_t *eid,
+                void *deg, void *ws, size_t ws_bytes, hipStream_t s);
 void select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel, double *tau, void *ws,
                  size_t ws_bytes, hipStream_t s);
 size_t affinity_workspace_bytes(int64_t n, int32_t k);
@@ -482,6 +484,7 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
         rep->band_rounds = 0;
         rep->cone_rows = 0;
         rep->node_order = (no && no->use) ? 1 : 0;
+        rep->n_scored = nc;
     }
     if (!f64 && p->band > 0.0 && ksel > 0 && ksel < nc) {
         // precision form: FP64 re-scoring of the edges near the threshold
@@ -518,13 +521,17 @@ void sigma_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, co
                     const uint8_t *tree, const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep,
                     DevArena &A, hipStream_t s);
 
+bool surrogate_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64,
+                        const float *w32, const uint8_t *tree, const sfg_params *p, const double *x0, uint8_t *keep,
+                        sfg_level_report *rep, DevArena &A, hipStream_t s);
+
 void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
                            const sfg_params *p, const double *x0, uint8_t *keep, sfg_report *rep, DevArena &A,
                            hipStream_t s) {
     double *w64 = A.alloc<double>(m + 1);
     convert_weights(w, wt, SFG_F64, m, w64, s);
     float *w32 = nullptr;
-    if (p->storage != SFG_F64) {
+    if (p->storage != SFG_F64 || p->surrogate) {
         w32 = A.alloc<float>(m + 1);
         convert_weights(w, wt, SFG_F32, m, w32, s);
     }
@@ -534,6 +541,12 @@ void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t
     if (p->sigma > 0.0) {
         sigma_sparsify(n, m, u, v, w64, w32, tree, p, x0, keep, rep, A, s);
         return;
+    }
+    if (p->surrogate) {
+        if (rep) rep->levels = 1;
+        if (surrogate_sparsify(n, m, u, v, w64, w32, tree, p, x0, keep, rep ? &rep->level[0] : nullptr, A, s))
+            return;
+        if (rep) rep->level[0].surrogate_fallback = 1;
     }
     const int32_t rounds = p->rounds > 1 ? p->rounds : 1;
     if (rep) rep->levels = rounds;
@@ -555,6 +568,149 @@ void single_level_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t
         score_level(n, m, u, v, w64, w32, keep, p, x0 + (size_t)r * n * p->k, keep,
                     rep ? &rep->level[r] : nullptr, A, s, q, &no);
     }
+}
+
+// ---------------------------------------------------------------- learned candidate pruning
+
+namespace {
+
+__global__ void k_first_cols(int64_t n, int32_t k, int32_t kc, const double *__restrict__ x, double *__restrict__ y) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * kc) return;
+    const int64_t i = t / kc;
+    y[t] = x[i * k + (t - i * kc)];
+}
+
+__global__ void k_nonfinite(int64_t len, const float *__restrict__ a, int32_t *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len && !__builtin_isfinite(a[i])) atomicOr(bad, 1);
+}
+
+__global__ void k_take_ids(int64_t nb, const int32_t *__restrict__ pos, const int32_t *__restrict__ ids,
+                           int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) out[i] = ids[pos[i]];
+}
+
+void check_status(sfg_status st) {
+    if (st != SFG_OK) fail(st, sfg_last_error());
+}
+
+}  // namespace
+
+// The plain single-level pass with the exact scoring restricted to the
+// surrogate's top cand_frac of the off-tree edges (the steps are listed with
+// sfg_surrogate in the header).  Returns false, having done nothing, when the
+// model is not usable.
+bool surrogate_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64,
+                        const float *w32, const uint8_t *tree, const sfg_params *p, const double *x0, uint8_t *keep,
+                        sfg_level_report *rep, DevArena &A, hipStream_t s) {
+    const sfg_surrogate &sg = *p->surrogate;
+    const int64_t np = sfg_mpnn_param_count();
+    int32_t *bad = A.alloc<int32_t>(1);
+    fill_i32(bad, 1, 0, s);
+    hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(np, 256)), dim3(256), 0, s, np, sg.params, bad);
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_nonfinite, dim3(1), dim3(256), 0, s, (int64_t)24, sg.norm, bad);
+    SFG_LAUNCH_CHECK();
+    int32_t bad_h = 0;
+    SFG_HIP(hipMemcpyAsync(&bad_h, bad, 4, hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    if (bad_h) return false;
+    Timer tm(s);
+    tm.start();
+    // candidates: the off-tree edges, ascending id
+    int32_t *cand = A.alloc<int32_t>(m + 1);
+    const int64_t nc = compact_ids(tree, 0, m, cand, A, s);
+    // G's CSR and the tree's, FP32 weights
+    const size_t wsb = csr_workspace_bytes(n, m);
+    void *ws = A.raw(wsb);
+    int32_t *grp = A.alloc<int32_t>(n + 1), *gcol = A.alloc<int32_t>(2 * m + 1), *geid = A.alloc<int32_t>(2 * m + 1);
+    float *gval = A.alloc<float>(2 * m + 1), *gdeg = A.alloc<float>(n + 1);
+    build_csr(n, m, u, v, w32, SFG_F32, nullptr, grp, gcol, gval, geid, gdeg, ws, wsb, s);
+    const sfg_csr G{n, 2 * m, grp, gcol, gval, geid, gdeg, SFG_F32};
+    int32_t *trp = A.alloc<int32_t>(n + 1), *tcol = A.alloc<int32_t>(2 * n), *teid = A.alloc<int32_t>(2 * n);
+    float *tval = A.alloc<float>(2 * n), *tdeg = A.alloc<float>(n + 1);
+    const size_t wss = csr_select_workspace_bytes(n, m);
+    csr_select(&G, tree, trp, tcol, tval, teid, tdeg, A.raw(wss), wss, s);
+    const sfg_csr T{n, 2 * (n - 1), trp, tcol, tval, teid, tdeg, SFG_F32};
+    // cheap embedding, features, prediction
+    double *x0c = A.alloc<double>((size_t)n * sg.kc);
+    hipLaunchKernelGGL(k_first_cols, dim3(grid_for(n * (int64_t)sg.kc, 256)), dim3(256), 0, s, n, p->k, sg.kc, x0,
+                       x0c);
+    SFG_LAUNCH_CHECK();
+    float *xc = A.alloc<float>((size_t)n * sg.kc);
+    const size_t wsc = smooth_workspace_bytes(n, sg.kc, SFG_BF16);
+    smooth(&T, sg.kc, sg.tc, 0.5, x0c, SFG_BF16, 1, xc, A.raw(wsc), wsc, s);
+    float *nf = A.alloc<float>((size_t)n * 8);
+    float *ef = A.alloc<float>((size_t)(nc + 1) * 4);
+    check_status(sfg_mpnn_features(&G, &T, xc, sg.kc, nc, cand, u, v, w32, sg.norm, nf, ef, s));
+    float *pred = A.alloc<float>(nc + 1);
+    const size_t wsf = mpnn_forward_workspace_bytes(n, SFG_BF16);
+    check_status(sfg_mpnn_forward(&G, sg.params, nf, nc, cand, u, v, ef, SFG_BF16, pred, A.raw(wsf), wsf, s));
+    // the candidates scored exactly: the top cand_frac by prediction
+    const int64_t kcand = std::min<int64_t>(nc, (int64_t)std::ceil(p->cand_frac * (double)nc));
+    uint8_t *csel = A.alloc<uint8_t>(nc + 1);
+    double *tau = A.alloc<double>(1);
+    size_t wsel = select_workspace_bytes(nc);
+    select_topk(pred, SFG_F32, nc, kcand, csel, tau, A.raw(wsel), wsel, s);
+    int32_t *cpos = A.alloc<int32_t>(nc + 1);
+    const int64_t ne = compact_ids(csel, 1, nc, cpos, A, s);
+    int32_t *cand_e = A.alloc<int32_t>(ne + 1);
+    if (ne > 0) {
+        hipLaunchKernelGGL(k_take_ids, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, cpos, cand, cand_e);
+        SFG_LAUNCH_CHECK();
+    }
+    float ms_other = tm.stop();
+    // exact scores on the tree embedding, as the plain path computes them
+    tm.start();
+    const bool f64 = p->storage == SFG_F64;
+    const sfg_dtype vt = f64 ? SFG_F64 : SFG_F32;
+    const void *wv = f64 ? (const void *)w64 : (const void *)w32;
+    sfg_csr H = T;
+    if (f64) {
+        int32_t *hrp = A.alloc<int32_t>(n + 1), *hcol = A.alloc<int32_t>(2 * n), *heid = A.alloc<int32_t>(2 * n);
+        double *hval = A.alloc<double>(2 * n), *hdeg = A.alloc<double>(n + 1);
+        build_csr(n, m, u, v, w64, SFG_F64, tree, hrp, hcol, hval, heid, hdeg, ws, wsb, s);
+        H = sfg_csr{n, 2 * (n - 1), hrp, hcol, hval, heid, hdeg, SFG_F64};
+    }
+    void *x = A.raw((size_t)n * p->k * dtype_size(p->storage));
+    const size_t wsm = smooth_workspace_bytes(n, p->k, p->storage);
+    smooth(&H, p->k, p->sweeps, p->omega, x0, p->storage, 0, x, A.raw(wsm), wsm, s);
+    float ms_smooth = tm.stop();
+    tm.start();
+    void *score = A.raw((ne + 1) * dtype_size(vt));
+    edge_scores(x, p->storage, n, p->k, ne, cand_e, u, v, wv, vt, score, vt, s);
+    float ms_score = tm.stop();
+    tm.start();
+    const int64_t ktake = std::min<int64_t>(ne, (int64_t)std::ceil(p->frac * (double)nc));
+    uint8_t *sel = A.alloc<uint8_t>(ne + 1);
+    wsel = select_workspace_bytes(ne);
+    select_topk(score, vt, ne, ktake, sel, tau, A.raw(wsel), wsel, s);
+    double tau_h = 0;
+    SFG_HIP(hipMemcpyAsync(&tau_h, tau, 8, hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    if (tau_h != tau_h) fail(SFG_ENUMERIC, "sparsify: NaN or negative edge score");
+    hipLaunchKernelGGL(k_keep_init, dim3(grid_for(m, 256)), dim3(256), 0, s, m, tree, keep);
+    SFG_LAUNCH_CHECK();
+    if (ne > 0) {
+        hipLaunchKernelGGL(k_keep_add, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, cand_e, sel, keep);
+        SFG_LAUNCH_CHECK();
+    }
+    float ms_select = tm.stop();
+    if (rep) {
+        rep->n = n;
+        rep->m = m;
+        rep->n_cand = nc;
+        rep->k_sel = ktake;
+        rep->tau = tau_h;
+        rep->n_scored = ne;
+        rep->ms_smooth = ms_smooth;
+        rep->ms_score = ms_score;
+        rep->ms_select = ms_select;
+        rep->ms_other = ms_other;
+    }
+    return true;
 }
 
 struct KappaEstimator;
@@ -636,6 +792,19 @@ void check_params(const sfg_params *p) {
     SFG_REQUIRE(p->sigma >= 0.0 && p->sigma == p->sigma, SFG_EINVAL, "sparsify: sigma must be >= 0");
     SFG_REQUIRE(p->sigma == 0.0 || p->levels == 1, SFG_EUNSUPPORTED, "sparsify: sigma needs levels = 1");
     SFG_REQUIRE(p->sigma == 0.0 || p->frac > 0.0, SFG_EINVAL, "sparsify: sigma needs frac > 0 (the batch size)");
+    if (p->surrogate) {
+        const sfg_surrogate &sg = *p->surrogate;
+        SFG_REQUIRE(p->levels == 1 && p->rounds <= 1 && p->sigma == 0.0 && p->smoother == SFG_SMOOTH_JACOBI &&
+                        p->embed == SFG_EMBED_SPARSIFIER && p->band == 0.0 &&
+                        (p->storage == SFG_F64 || p->storage == SFG_F32),
+                    SFG_EUNSUPPORTED,
+                    "sparsify: a surrogate needs one level, one round, no sigma, Jacobi, the sparsifier embedding, "
+                    "no band and F64 or F32 storage");
+        SFG_REQUIRE(sg.params && sg.norm, SFG_EINVAL, "sparsify: surrogate parameters or normalisation missing");
+        SFG_REQUIRE(sg.kc >= 1 && sg.kc <= p->k && sg.tc >= 0, SFG_EINVAL,
+                    "sparsify: surrogate needs 1 <= kc <= k and tc >= 0");
+        SFG_REQUIRE(p->cand_frac > 0.0 && p->cand_frac <= 1.0, SFG_EINVAL, "sparsify: cand_frac must be in (0, 1]");
+    }
 }
 
 }  // namespace sfg

@@ -70,12 +70,18 @@ class TreeStruct(ctypes.Structure):
                 ("tup", ctypes.c_void_p)]
 
 
+class SurrogateStruct(ctypes.Structure):
+    _fields_ = [("params", ctypes.c_void_p), ("norm", ctypes.c_void_p), ("kc", ctypes.c_int32),
+                ("tc", ctypes.c_int32)]
+
+
 class Params(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("k", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("omega", ctypes.c_double), ("frac", ctypes.c_double), ("embed", ctypes.c_int32),
                 ("storage", ctypes.c_int), ("final_f32", ctypes.c_int32), ("band", ctypes.c_double),
                 ("rounds", ctypes.c_int32), ("smoother", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("sigma", ctypes.c_double), ("est", KappaParams)]
+                ("sigma", ctypes.c_double), ("est", KappaParams), ("surrogate", ctypes.POINTER(SurrogateStruct)),
+                ("cand_frac", ctypes.c_double)]
 
 
 class LevelReport(ctypes.Structure):
@@ -84,7 +90,7 @@ class LevelReport(ctypes.Structure):
                 ("band_above", ctypes.c_int64), ("band_rounds", ctypes.c_int32),
                 ("ms_smooth", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_select", ctypes.c_float),
                 ("ms_other", ctypes.c_float), ("cone_rows", ctypes.c_int64), ("precision_fallback", ctypes.c_int32),
-                ("node_order", ctypes.c_int32)]
+                ("node_order", ctypes.c_int32), ("n_scored", ctypes.c_int64), ("surrogate_fallback", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):
@@ -375,13 +381,20 @@ def make_kappa_params(k=8, steps=6, tol=1e-1, max_iter=20000, seed=0, block=0) -
 
 def make_params(levels=1, k=8, sweeps=10, omega=0.5, frac=0.05, embed=EMBED_SPARSIFIER, storage=F64,
                 final_f32=False, band=0.0, rounds=None, smoother=SMOOTH_JACOBI, seed=0, sigma=0.0,
-                est: Optional[KappaParams] = None) -> Params:
-    """rounds: multi-round densification (default 1); with sigma > 0 the cap on batches (default 0 = 16)."""
+                est: Optional[KappaParams] = None, surrogate=None, cand_frac=0.2) -> Params:
+    """rounds: multi-round densification (default 1); with sigma > 0 the cap on batches (default 0 = 16).
+    surrogate: anything with device tensors ``params`` and ``norm`` and ints ``kc``, ``tc`` (a trained
+    surrogate.Model): sfg_sparsify then scores exactly only its top ``cand_frac`` of the off-tree edges."""
     if rounds is None:
         rounds = 0 if sigma > 0 else 1
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
-    return Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds, smoother, seed,
-                  sigma, est if est is not None else make_kappa_params())
+    p = Params(levels, k, sweeps, omega, frac, embed, st, int(bool(final_f32)), band, rounds, smoother, seed,
+               sigma, est if est is not None else make_kappa_params(), None, cand_frac)
+    if surrogate is not None:
+        sg = SurrogateStruct(_ptr(surrogate.params), _ptr(surrogate.norm), int(surrogate.kc), int(surrogate.tc))
+        p.surrogate = ctypes.pointer(sg)
+        p._keep = (sg, surrogate)      # the struct and the tensors it points to live as long as the params
+    return p
 
 
 def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: Optional[torch.Tensor],

@@ -90,3 +90,35 @@ def test_every_entry_point_has_a_signature(L):
 
     for name in sfg.EXPORTED:
         assert getattr(L, name).argtypes is not None, name
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the ctypes mirrors of the header's structs: same size and field offsets as the C compiler gives
+    import shutil
+    import subprocess
+
+    from paper_2008_07633_amd import sfg
+
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    mirrors = {"sfg_csr": sfg.CsrStruct, "sfg_kappa_params": sfg.KappaParams, "sfg_kappa_report": sfg.KappaReport,
+               "sfg_tree": sfg.TreeStruct, "sfg_surrogate": sfg.SurrogateStruct, "sfg_params": sfg.Params,
+               "sfg_level_report": sfg.LevelReport, "sfg_report": sfg.Report}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sfg.h"', "int main(void) {"]
+    for c, py in mirrors.items():
+        lines.append(f'printf("{c} (sizeof) %zu\\n", sizeof({c}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{c} {f} %zu\\n", offsetof({c}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        c, f, val = line.split()
+        got[(c, f)] = int(val)
+    for c, py in mirrors.items():
+        assert got[(c, "(sizeof)")] == ctypes.sizeof(py), c
+        for f, _ in py._fields_:
+            assert got[(c, f)] == getattr(py, f).offset, (c, f)

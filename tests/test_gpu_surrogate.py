@@ -209,3 +209,58 @@ def test_model_file_roundtrip_and_fallback(S, SG, tmp_path):
     keep, _ = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), S.make_params(k=16, sweeps=20, frac=0.1,
                                                                                        storage=torch.float32))
     assert torch.equal(res.keep, keep)
+
+
+def test_sparsify_with_surrogate_in_the_library(S, SG):
+    # sfg_sparsify with sfg_params.surrogate runs the pruned path in the library: the same keep mask as the
+    # Python composition of the primitives (surrogate.sparsify_pruned), for both models
+    for kc in (SG.KC, SG.KC_RECALL):
+        model, _ = _train_small(S, SG, n_train=6, side=16, epochs=10, kc=kc)
+        for side, seed in ((18, 371), (23, 372)):
+            g = W.mesh3d(side, side, side, seed=seed, wdist=("lognormal", 0.0, 1.5))
+            X0 = dev(W.random_block(g.n, 16, seed))
+            u, v, w = dev(g.u), dev(g.v), dev(g.w)
+            ref = SG.sparsify_pruned(g.n, u, v, w, X0, model, 20, 0.1, 0.2)
+            p = S.make_params(k=16, sweeps=20, frac=0.1, storage=torch.float32, surrogate=model, cand_frac=0.2)
+            keep, rep = S.sfg_sparsify(g.n, u, v, w, X0, p)
+            assert not ref.fallback and rep[0]["surrogate_fallback"] == 0
+            assert torch.equal(keep, ref.keep), (kc, side)
+            assert rep[0]["n_scored"] == ref.n_scored and rep[0]["k_sel"] == ref.k_sel
+            assert rep[0]["n_cand"] == ref.n_cand
+
+
+@pytest.mark.parametrize("storage", [torch.float64, torch.float32])
+def test_surrogate_scoring_everything_is_the_plain_path(S, SG, storage):
+    # cand_frac = 1: every off-tree edge is scored exactly, so the result is the plain sparsifier's
+    model = SG.Model(SG.init_params(3), torch.ones(24, device="cuda"), 0.0, 1.0, kc=4, tc=5)
+    g = W.mesh3d(14, 15, 16, seed=373, wdist=("lognormal", 0.0, 1.5))
+    X0 = dev(W.random_block(g.n, 8, 374))
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    plain, r0 = S.sfg_sparsify(g.n, u, v, w, X0, S.make_params(k=8, sweeps=12, frac=0.1, storage=storage))
+    keep, r1 = S.sfg_sparsify(g.n, u, v, w, X0, S.make_params(k=8, sweeps=12, frac=0.1, storage=storage,
+                                                              surrogate=model, cand_frac=1.0))
+    assert torch.equal(keep, plain)
+    assert r1[0]["tau"] == r0[0]["tau"] and r1[0]["n_scored"] == r0[0]["n_cand"] == r0[0]["n_scored"]
+
+
+def test_surrogate_in_the_library_falls_back_and_checks(S, SG):
+    g = W.mesh3d(10, 11, 12, seed=375)
+    X0 = dev(W.random_block(g.n, 8, 376))
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    params = SG.init_params(4)
+    params[7] = float("nan")
+    bad = SG.Model(params, torch.ones(24, device="cuda"), 0.0, 1.0, kc=4, tc=5)
+    plain, _ = S.sfg_sparsify(g.n, u, v, w, X0, S.make_params(k=8, sweeps=6, frac=0.1, storage=torch.float32))
+    keep, rep = S.sfg_sparsify(g.n, u, v, w, X0, S.make_params(k=8, sweeps=6, frac=0.1, storage=torch.float32,
+                                                               surrogate=bad))
+    assert rep[0]["surrogate_fallback"] == 1 and torch.equal(keep, plain)
+    good = SG.Model(SG.init_params(4), torch.ones(24, device="cuda"), 0.0, 1.0, kc=4, tc=5)
+    for kw, status in (({"levels": 2}, "SFG_EUNSUPPORTED"), ({"band": 0.01, "storage": torch.float16},
+                                                              "SFG_EUNSUPPORTED"),
+                       ({"rounds": 2}, "SFG_EUNSUPPORTED"), ({"cand_frac": 0.0}, "SFG_EINVAL"),
+                       ({"cand_frac": 1.5}, "SFG_EINVAL"), ({"k": 2}, "SFG_EINVAL")):
+        args = dict(k=8, sweeps=6, frac=0.1, storage=torch.float32, surrogate=good)
+        args.update(kw)
+        with pytest.raises(S.SfgError, match=status):
+            S.sfg_sparsify(g.n, u, v, w, X0 if args["k"] == 8 else X0[:, :args["k"]].contiguous(),
+                           S.make_params(**args))
