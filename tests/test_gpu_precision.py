@@ -109,3 +109,17 @@ def test_low_precision_score_errors_reported(S, orc):
     # FP32 storage is close; FP16 with an FP32 last iterate meets 1e-2 in the selected region
     assert out[("torch.float32", False)]["max_abs_over_tau"] < 1e-4
     assert out[("torch.float16", True)]["max_rel_selected_region"] < 1e-2, out
+
+
+def test_band_always_holds_the_threshold(S, orc, monkeypatch):
+    # the reduced threshold is the k_sel-th largest reduced score, so however small the margin the band holds it
+    # and k_sel - |A| lies in [1, |B|]: the margin never has to double (that loop is a guard)
+    monkeypatch.setenv("SFG_PRECISION_PREDICT", "0")
+    g = W.powergrid(120, 110, 0.02, seed=7)
+    X0 = W.random_block(g.n, 16, 77)
+    for band in (1e-5, 1e-3, 0.04):
+        p = S.make_params(k=16, sweeps=8, frac=0.1, storage=torch.bfloat16, final_f32=True, band=band)
+        _, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), p)
+        r = rep[0]
+        assert r["band_rounds"] == 0 and r["band"] >= 1, r
+        assert 1 <= r["k_sel"] - r["band_above"] <= r["band"], r

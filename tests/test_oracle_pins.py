@@ -120,6 +120,27 @@ def test_smoothing_closed_form(orc, g, omega):
     assert np.max(np.abs(X - Xref)) <= 1e-12 * np.max(np.abs(X0))
 
 
+def test_fp64_summation_order_noise_floor(orc):
+    # not a pin: the oracle adds each row in ascending column order; the same sweeps with every row added in
+    # the reverse order differ only by rounding, about 1e-16 of the values, far below the 1e-12 tolerance
+    g = W.grid2d(20, 20, seed=12, wdist=("lognormal", 0.0, 1.0))
+    csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    X0, _ = orc.center(W.random_block(g.n, 3, 13))
+    T, omega = 10, 0.5
+    ref = orc.smooth(csr, X0, T, omega)
+    X = X0.copy()
+    for _ in range(T):
+        Y = np.empty_like(X)
+        for p in range(g.n):
+            acc = np.zeros(X.shape[1])
+            for j in range(csr.rowptr[p + 1] - 1, csr.rowptr[p] - 1, -1):
+                acc = acc + csr.val[j] * X[csr.col[j]]
+            Y[p] = (1 - omega) * X[p] + omega * (acc / csr.deg[p])
+        X = Y
+    rel = np.max(np.abs(X - ref)) / np.max(np.abs(ref))
+    assert 0 <= rel < 1e-14, rel
+
+
 def test_smoothing_invariants(orc):
     g = W.grid2d(12, 9, seed=4, wdist=("lognormal", 0.0, 1.0))
     csr = orc.laplacian_csr(g.n, g.u, g.v, g.w)
