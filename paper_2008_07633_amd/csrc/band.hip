@@ -37,7 +37,7 @@ double *smooth_cone_f64(const sfg_csr *H, int32_t k, int32_t sweeps, double omeg
                         void *partial_ws, double *mean, hipStream_t s);
 size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
 void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
-            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s);
+            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s, int32_t max_row);
 
 namespace {
 
@@ -299,7 +299,7 @@ void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, c
             cone_rows = (int64_t)sweeps * n;
             X = A.alloc<double>((size_t)n * k);
             const size_t wsb = smooth_workspace_bytes(n, k, SFG_F64);
-            smooth(H64, k, sweeps, omega, x0, SFG_F64, 0, X, A.raw(wsb), wsb, s);
+            smooth(H64, k, sweeps, omega, x0, SFG_F64, 0, X, A.raw(wsb), wsb, s, -1);
         }
         edge_scores(X, SFG_F64, n, k, nB, eB, u, v, w64, SFG_F64, sB, SFG_F64, s);
     }

@@ -31,7 +31,8 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
                size_t ws_bytes, hipStream_t s);
 size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
 void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
-            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s);
+            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s, int32_t max_row);
+void max_row_length(const sfg_csr *H, int32_t *out, hipStream_t s);
 size_t affinity_workspace_bytes(int64_t n, int32_t k);
 void affinity(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t m, const int32_t *u, const int32_t *v,
               void *aff, sfg_dtype at, void *ws, size_t ws_bytes, hipStream_t s);
@@ -438,7 +439,15 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
         sfg_csr G{F.n, 2 * F.m, rowptr, col, val, eid, deg, vt};
         void *x = A.raw((size_t)F.n * p->k * dtype_size(vt));
         const size_t wss = smooth_workspace_bytes(F.n, p->k, vt);
-        smooth(&G, p->k, p->sweeps, p->omega, x0 + (size_t)l * n * p->k, vt, 0, x, A.raw(wss), wss, s);
+        int32_t max_row = -1;
+        if (f64) {
+            // FP64 sums hub rows through LDS only where they are known to exist
+            int32_t *mr = A.alloc<int32_t>(1);
+            max_row_length(&G, mr, s);
+            SFG_HIP(hipMemcpyAsync(&max_row, mr, 4, hipMemcpyDeviceToHost, s));
+            SFG_HIP(hipStreamSynchronize(s));
+        }
+        smooth(&G, p->k, p->sweeps, p->omega, x0 + (size_t)l * n * p->k, vt, 0, x, A.raw(wss), wss, s, max_row);
         void *aff = A.raw((F.m + 1) * dtype_size(vt));
         const size_t wsa = affinity_workspace_bytes(F.n, p->k);
         affinity(x, vt, F.n, p->k, F.m, F.u, F.v, aff, vt, A.raw(wsa), wsa, s);

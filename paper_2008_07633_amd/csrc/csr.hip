@@ -383,6 +383,39 @@ void csr_select(const sfg_csr *G, const uint8_t *mask, int32_t *rowptr, int32_t 
         select_entries<float>(G, mask, p, rowptr, col, (float *)val, eid, (float *)deg, s);
 }
 
+namespace {
+
+__global__ void k_row_max(int64_t n, const int32_t *__restrict__ rowptr, int32_t *out) {
+    __shared__ int32_t part[4];
+    int32_t mx = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t len = rowptr[i + 1] - rowptr[i];
+        mx = len > mx ? len : mx;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const int32_t o = __shfl_down(mx, off, 64);
+        mx = o > mx ? o : mx;
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int w = 0; w < 4; ++w) t = part[w] > t ? part[w] : t;
+        if (t) atomicMax(out, t);
+    }
+}
+
+}  // namespace
+
+// *out = the longest row of H (out is cleared first; one atomic per workgroup
+// of a bounded grid).
+void max_row_length(const sfg_csr *H, int32_t *out, hipStream_t s) {
+    fill_i32(out, 1, 0, s);
+    hipLaunchKernelGGL(k_row_max, dim3(std::min<uint32_t>(grid_for(H->n, 256), 1024u)), dim3(256), 0, s, H->n,
+                       H->rowptr, out);
+    SFG_LAUNCH_CHECK();
+}
+
 size_t csr_workspace_bytes(int64_t n, int64_t m) {
     Carver c(nullptr);
     plan_csr(c, n, m);

@@ -339,6 +339,62 @@ __global__ __launch_bounds__(256) void k_sweep_color(int64_t nthreads, int32_t l
 
 // Rows handled by k_sweep_long (device list and count), and the length above
 // which k_sweep skips a row.  Default: none, every row in k_sweep.
+// FP64 hub rows (listed only when the caller knows the graph has rows over
+// 256 entries): the sum k_sweep's lane group would form -- entries in stored
+// order, acc = acc + w * x, one rounding per operation, then the same
+// epilogue -- so the result is bit-identical, but the row's weights and
+// neighbour values are gathered by the whole workgroup into LDS, chunk by
+// chunk, and lane c adds column c from there: the dependent chain is over
+// LDS reads instead of over global gathers.
+constexpr int kHubLds = 4096;   // doubles of staged neighbour values per chunk (32 KB)
+
+template <typename TIN, typename TX, typename TO, bool CENTER>
+__global__ __launch_bounds__(256) void k_sweep_hub64(int32_t kw, int32_t ldx, int32_t ldy,
+                                                     const int32_t *__restrict__ hub_rows,
+                                                     const int32_t *__restrict__ hub_cnt,
+                                                     const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val, const double *__restrict__ deg,
+                                                     const TIN *__restrict__ x, const double *__restrict__ mean,
+                                                     TO *__restrict__ y, double keep, double omega) {
+    __shared__ double sx[kHubLds];
+    __shared__ double sw[256];
+    const int chunk = kHubLds / kw < 256 ? kHubLds / kw : 256;
+    const int t = threadIdx.x;
+    const int32_t cnt = *hub_cnt;
+    for (int32_t r = blockIdx.x; r < cnt; r += gridDim.x) {
+        const int64_t row = hub_rows[r];
+        const int32_t j0 = rowptr[row], j1 = rowptr[row + 1];
+        double mo[1] = {0.0};
+        if (CENTER && t < kw) mo[0] = mean[t];
+        double acc = 0.0;
+        for (int32_t jc = j0; jc < j1; jc += chunk) {
+            const int32_t len = (j1 - jc) < chunk ? (j1 - jc) : chunk;
+            for (int32_t i = t; i < len * kw; i += 256) {
+                const int32_t e = i / kw, c = i - e * kw;
+                double v[1];
+                const double m1[1] = {CENTER ? mean[c] : 0.0};
+                load_row<TIN, TX, double, 1, CENTER>(x + (int64_t)col[jc + e] * ldx + c, m1, v);
+                sx[i] = v[0];
+            }
+            for (int32_t e = t; e < len; e += 256) sw[e] = val[jc + e];
+            __syncthreads();
+            if (t < kw)
+                for (int32_t e = 0; e < len; ++e) acc = madd(acc, sw[e], sx[e * kw + t]);
+            __syncthreads();
+        }
+        if (t < kw) {
+            double self[1];
+            load_row<TIN, TX, double, 1, CENTER>(x + row * ldx + t, mo, self);
+            const double d = deg[row];
+            const double a = keep * self[0];
+            const double q = acc / d;
+            const double bo = omega * q;
+            y[row * ldy + t] = cvt<TO>(a + bo);
+        }
+    }
+}
+
 struct LongRows {
     const int32_t *rows = nullptr;
     const int32_t *count = nullptr;
@@ -382,6 +438,14 @@ void launch_sweep_u(const sfg_csr *H, const SweepShape &sh, const TIN *x, const 
                        nthreads, lpr, ilog2_exact(lpr), sh.ldx, sh.ldy, lr.max_len, rows, H->rowptr, H->col,
                        (const TW *)H->val, (const TW *)H->deg, x, mean, y, (TA)(1.0 - omega), (TA)omega);
     SFG_LAUNCH_CHECK();
+    if constexpr (sizeof(TA) == 8) {
+        if (lr.rows) {
+            hipLaunchKernelGGL((k_sweep_hub64<TIN, TX, TO, CENTER>), dim3(long_row_blocks(H)), dim3(256), 0, s, sh.kw,
+                               sh.ldx, sh.ldy, lr.rows, lr.count, H->rowptr, H->col, (const double *)H->val,
+                               (const double *)H->deg, x, mean, y, 1.0 - omega, omega);
+            SFG_LAUNCH_CHECK();
+        }
+    }
     if constexpr (sizeof(TA) == 4) {
         if (lr.rows) {
             hipLaunchKernelGGL((k_sweep_long<TIN, TX, TO, TW, TA, VPL, CENTER>), dim3(long_row_blocks(H)), dim3(256),
@@ -543,7 +607,7 @@ void launch_column_means(const TIN *x, int64_t n, int32_t k, DD *partial, double
 
 template <typename TX, typename TW, typename TA>
 void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, bool final_f32,
-                void *xout, const SmoothPlan &p, hipStream_t s) {
+                bool hub_rows, void *xout, const SmoothPlan &p, hipStream_t s) {
     const int64_t n = H->n;
     const int64_t total = n * (int64_t)k;
     // a2: column means (the block becomes orthogonal to the all-one vector)
@@ -559,9 +623,10 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
         return;
     }
     TX *b0 = (TX *)p.buf0, *b1 = (TX *)p.buf1;
-    // reduced precision: list the long rows once for all sweeps (device-side count)
+    // reduced precision, and FP64 when the caller knows there are hub rows: list
+    // the rows over kLongRow entries once for all sweeps (device-side count)
     LongRows lr;
-    if constexpr (sizeof(TA) == 4) {
+    if (sizeof(TA) == 4 || hub_rows) {
         hipLaunchKernelGGL(k_long_flag, dim3(grid_for(n, 256)), dim3(256), 0, s, n, H->rowptr, kLongRow, p.lflag);
         SFG_LAUNCH_CHECK();
         exclusive_scan_i32(p.lflag, p.lpos, n, p.lscan, s);
@@ -724,8 +789,11 @@ void smooth_gs(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const 
 }
 
 
+// max_row: the longest row of H if the caller knows it, else -1.  FP64 hub
+// rows (over 256 entries) go to k_sweep_hub64 only when it is known, since
+// listing them costs launches on every call.
 void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
-            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s) {
+            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s, int32_t max_row) {
     SFG_REQUIRE(H && H->rowptr && H->deg && x0 && x, SFG_EINVAL, "smooth: null pointer");
     SFG_REQUIRE(H->n >= 1, SFG_EINVAL, "smooth: empty graph");
     SFG_REQUIRE(k >= 1, SFG_EINVAL, "smooth: k must be >= 1");
@@ -742,19 +810,19 @@ void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const dou
     switch (storage) {
         case SFG_F64:
             SFG_REQUIRE(H->vt == SFG_F64, SFG_EUNSUPPORTED, "smooth: F64 storage needs an F64 graph");
-            run_smooth<double, double, double>(H, k, sweeps, omega, x0, false, x, p, s);
+            run_smooth<double, double, double>(H, k, sweeps, omega, x0, false, max_row > kLongRow, x, p, s);
             break;
         case SFG_F32:
             SFG_REQUIRE(H->vt == SFG_F32, SFG_EUNSUPPORTED, "smooth: F32 storage needs an F32 graph");
-            run_smooth<float, float, float>(H, k, sweeps, omega, x0, false, x, p, s);
+            run_smooth<float, float, float>(H, k, sweeps, omega, x0, false, false, x, p, s);
             break;
         case SFG_F16:
             SFG_REQUIRE(H->vt == SFG_F32, SFG_EUNSUPPORTED, "smooth: F16 storage needs an F32 graph");
-            run_smooth<__half, float, float>(H, k, sweeps, omega, x0, f32last, x, p, s);
+            run_smooth<__half, float, float>(H, k, sweeps, omega, x0, f32last, false, x, p, s);
             break;
         case SFG_BF16:
             SFG_REQUIRE(H->vt == SFG_F32, SFG_EUNSUPPORTED, "smooth: BF16 storage needs an F32 graph");
-            run_smooth<__hip_bfloat16, float, float>(H, k, sweeps, omega, x0, f32last, x, p, s);
+            run_smooth<__hip_bfloat16, float, float>(H, k, sweeps, omega, x0, f32last, false, x, p, s);
             break;
     }
 }
@@ -780,6 +848,6 @@ extern "C" sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, do
                                  sfg_dtype storage, int32_t final_f32, void *x, void *ws, size_t ws_bytes,
                                  void *stream) {
     return sfg::guard([&] {
-        sfg::smooth(H, k, sweeps, omega, x0, storage, final_f32, x, ws, ws_bytes, sfg::as_stream(stream));
+        sfg::smooth(H, k, sweeps, omega, x0, storage, final_f32, x, ws, ws_bytes, sfg::as_stream(stream), -1);
     });
 }

@@ -28,7 +28,8 @@ void smooth_gs(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const 
                const int32_t *class_rows, const std::vector<int32_t> &class_ptr, void *x, void *ws, size_t ws_bytes,
                hipStream_t s);
 void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, sfg_dtype storage,
-            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s);
+            int32_t final_f32, void *x, void *ws, size_t ws_bytes, hipStream_t s, int32_t max_row);
+void max_row_length(const sfg_csr *H, int32_t *out, hipStream_t s);
 void edge_scores(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t ne, const int32_t *cand,
                  const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt, void *score, sfg_dtype st,
                  hipStream_t s);
@@ -385,10 +386,18 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
         fill_i32((int32_t *)far, 2, 0, s);
         far_entries(&H, kNearRows, far, s);
     }
-    int32_t nnz = 0;
+    // FP64 sums hub rows through LDS only where they are known to exist: the
+    // longest row comes back with the entry count
+    int32_t *mr = nullptr;
+    if (f64) {
+        mr = A.alloc<int32_t>(1);
+        max_row_length(&H, mr, s);
+    }
+    int32_t nnz = 0, max_row = -1;
     unsigned long long far_h = 0;
     SFG_HIP(hipMemcpyAsync(&nnz, rowptr + n, 4, hipMemcpyDeviceToHost, s));
     if (far) SFG_HIP(hipMemcpyAsync(&far_h, far, 8, hipMemcpyDeviceToHost, s));
+    if (mr) SFG_HIP(hipMemcpyAsync(&max_row, mr, 4, hipMemcpyDeviceToHost, s));
     SFG_HIP(hipStreamSynchronize(s));
     H.nnz = nnz;
     if (no && !no->decided) {
@@ -450,7 +459,7 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
         color_graph(&H, color, class_rows, class_ptr, A.raw(wsc), wsc, s);
         smooth_gs(&H, p->k, p->sweeps, p->omega, sx0, p->storage, class_rows, class_ptr, x, wsm, wss, s);
     } else {
-        smooth(&H, p->k, p->sweeps, p->omega, sx0, p->storage, p->final_f32, x, wsm, wss, s);
+        smooth(&H, p->k, p->sweeps, p->omega, sx0, p->storage, p->final_f32, x, wsm, wss, s, max_row);
     }
     float ms_smooth = tm.stop();
     // candidates: edges outside the current sparsifier, ascending id
@@ -641,7 +650,7 @@ bool surrogate_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v
     SFG_LAUNCH_CHECK();
     float *xc = A.alloc<float>((size_t)n * sg.kc);
     const size_t wsc = smooth_workspace_bytes(n, sg.kc, SFG_BF16);
-    smooth(&T, sg.kc, sg.tc, 0.5, x0c, SFG_BF16, 1, xc, A.raw(wsc), wsc, s);
+    smooth(&T, sg.kc, sg.tc, 0.5, x0c, SFG_BF16, 1, xc, A.raw(wsc), wsc, s, -1);
     float *nf = A.alloc<float>((size_t)n * 8);
     float *ef = A.alloc<float>((size_t)(nc + 1) * 4);
     check_status(sfg_mpnn_features(&G, &T, xc, sg.kc, nc, cand, u, v, w32, sg.norm, nf, ef, s));
@@ -676,7 +685,7 @@ bool surrogate_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *v
     }
     void *x = A.raw((size_t)n * p->k * dtype_size(p->storage));
     const size_t wsm = smooth_workspace_bytes(n, p->k, p->storage);
-    smooth(&H, p->k, p->sweeps, p->omega, x0, p->storage, 0, x, A.raw(wsm), wsm, s);
+    smooth(&H, p->k, p->sweeps, p->omega, x0, p->storage, 0, x, A.raw(wsm), wsm, s, -1);
     float ms_smooth = tm.stop();
     tm.start();
     void *score = A.raw((ne + 1) * dtype_size(vt));

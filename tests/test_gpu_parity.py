@@ -523,3 +523,35 @@ def test_sparsify_draws_blocks_from_the_seed(S, orc):
                               S.make_params(k=k, sweeps=T, frac=f, seed=seed, rounds=3))
     ref2 = orc.sparsify_rounds(g.n, g.u, g.v, g.w, [orc.random_block(g.n, k, seed, r) for r in range(3)], 3, T, f)
     assert np.array_equal(host(keep2), ref2.keep)
+
+
+def _hub_graph(seed):
+    # a random connected graph plus three hubs joined to 1,500 random nodes each (rows far over 256 entries)
+    base = W.random_connected(3000, 6000, seed=seed, wdist=("lognormal", 0.0, 1.0))
+    rng = np.random.default_rng(seed)
+    a = [base.u.astype(np.int64)]
+    b = [base.v.astype(np.int64)]
+    for h in (5, 1700, 2999):
+        nb = rng.choice(np.setdiff1d(np.arange(3000), [h]), 1500, replace=False)
+        a.append(np.minimum(nb, h))
+        b.append(np.maximum(nb, h))
+    key = np.unique(np.concatenate(a) * 3000 + np.concatenate(b))
+    u, v = (key // 3000).astype(np.int32), (key % 3000).astype(np.int32)
+    w = rng.lognormal(0.0, 1.0, u.shape[0])
+    return W.Graph(3000, u, v, w, name="hubs")
+
+
+@pytest.mark.parametrize("embed", ["sparsifier", "graph"])
+def test_fp64_hub_rows_match_oracle(S, orc, embed):
+    # sfg_sparsify knows its scoring graph's longest row, so FP64 hub rows are summed through LDS
+    # (k_sweep_hub64), in the oracle's order: bit for bit
+    g = _hub_graph(81)
+    X0 = W.random_block(g.n, 16, 82)
+    ref = orc.sparsify_single(g.n, g.u, g.v, g.w, X0, 12, 0.1, embed=embed)
+    p = S.make_params(k=16, sweeps=12, frac=0.1, embed=S.EMBED_GRAPH if embed == "graph" else S.EMBED_SPARSIFIER)
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), p)
+    assert np.array_equal(host(keep), ref.keep)
+    assert rep[0]["tau"] == ref.levels[0].tau
+    # the graph embedding's rows: the hubs are over 256 entries
+    Gc = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    assert embed == "sparsifier" or np.diff(Gc.rowptr).max() > 1000
