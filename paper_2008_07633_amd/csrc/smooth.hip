@@ -25,6 +25,7 @@
 //   - in reduced precision, rows longer than 256 entries (hubs of power-law
 //     graphs) are taken out and swept by a whole workgroup each.
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -399,7 +400,25 @@ struct LongRows {
     const int32_t *rows = nullptr;
     const int32_t *count = nullptr;
     int32_t max_len = 0x7fffffff;
+    // with a side stream, the hub rows of an iterate run there beside the main
+    // sweep of the same iterate (they write disjoint rows): es marks the last
+    // main sweep done, ez the last hub-row sweep
+    hipStream_t side = nullptr;
+    hipEvent_t es = nullptr, ez = nullptr;
 };
+
+// One side stream per device (default priority), created on first use and
+// kept for the process.
+hipStream_t side_stream() {
+    static std::mutex mu;
+    static hipStream_t streams[64] = {};
+    int dev = 0;
+    SFG_HIP(hipGetDevice(&dev));
+    SFG_REQUIRE(dev >= 0 && dev < 64, SFG_EUNSUPPORTED, "smooth: device index over 63");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[dev]) SFG_HIP(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+    return streams[dev];
+}
 
 int ilog2_exact(int x) {
     for (int r = 0; r < 31; ++r)
@@ -434,13 +453,23 @@ void launch_sweep_u(const sfg_csr *H, const SweepShape &sh, const TIN *x, const 
     const int lpr = sh.kw / VPL;
     const int64_t nthreads = nrows * (int64_t)lpr;
     if (nthreads == 0) return;
+    // the previous iterate's hub rows must be done before the main sweep reads
+    // them or overwrites the rows they read (waiting on a never-recorded event
+    // is a no-op)
+    if (lr.side) SFG_HIP(hipStreamWaitEvent(s, lr.ez, 0));
     hipLaunchKernelGGL((k_sweep<TIN, TX, TO, TW, TA, VPL, U, CENTER>), dim3(grid_for(nthreads, 256)), dim3(256), 0, s,
                        nthreads, lpr, ilog2_exact(lpr), sh.ldx, sh.ldy, lr.max_len, rows, H->rowptr, H->col,
                        (const TW *)H->val, (const TW *)H->deg, x, mean, y, (TA)(1.0 - omega), (TA)omega);
     SFG_LAUNCH_CHECK();
+    // hub rows: on the side stream after the previous main sweep, beside this one
+    hipStream_t zs = s;
+    if (lr.side && lr.rows) {
+        zs = lr.side;
+        SFG_HIP(hipStreamWaitEvent(zs, lr.es, 0));
+    }
     if constexpr (sizeof(TA) == 8) {
         if (lr.rows) {
-            hipLaunchKernelGGL((k_sweep_hub64<TIN, TX, TO, CENTER>), dim3(long_row_blocks(H)), dim3(256), 0, s, sh.kw,
+            hipLaunchKernelGGL((k_sweep_hub64<TIN, TX, TO, CENTER>), dim3(long_row_blocks(H)), dim3(256), 0, zs, sh.kw,
                                sh.ldx, sh.ldy, lr.rows, lr.count, H->rowptr, H->col, (const double *)H->val,
                                (const double *)H->deg, x, mean, y, 1.0 - omega, omega);
             SFG_LAUNCH_CHECK();
@@ -449,10 +478,14 @@ void launch_sweep_u(const sfg_csr *H, const SweepShape &sh, const TIN *x, const 
     if constexpr (sizeof(TA) == 4) {
         if (lr.rows) {
             hipLaunchKernelGGL((k_sweep_long<TIN, TX, TO, TW, TA, VPL, CENTER>), dim3(long_row_blocks(H)), dim3(256),
-                               0, s, lpr, sh.ldx, sh.ldy, lr.rows, lr.count, H->rowptr, H->col, (const TW *)H->val,
+                               0, zs, lpr, sh.ldx, sh.ldy, lr.rows, lr.count, H->rowptr, H->col, (const TW *)H->val,
                                (const TW *)H->deg, x, mean, y, (TA)(1.0 - omega), (TA)omega);
             SFG_LAUNCH_CHECK();
         }
+    }
+    if (lr.side && lr.rows) {
+        SFG_HIP(hipEventRecord(lr.ez, zs));
+        SFG_HIP(hipEventRecord(lr.es, s));
     }
 }
 
@@ -636,6 +669,23 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
         lr.count = p.lpos + n;
         lr.max_len = kLongRow;
     }
+    // graphs whose hub rows take long (power-law graphs, their dense coarse
+    // levels; FP64 hub rows when listed) sweep them on a side stream
+    struct Side {
+        hipEvent_t es = nullptr, ez = nullptr;
+        ~Side() {
+            if (es) (void)hipEventDestroy(es);
+            if (ez) (void)hipEventDestroy(ez);
+        }
+    } side;
+    if (lr.rows && sweeps > 0 && (sizeof(TA) == 8 || H->nnz >= 8 * H->n)) {
+        lr.side = side_stream();
+        SFG_HIP(hipEventCreateWithFlags(&side.es, hipEventDisableTiming));
+        SFG_HIP(hipEventCreateWithFlags(&side.ez, hipEventDisableTiming));
+        lr.es = side.es;
+        lr.ez = side.ez;
+        SFG_HIP(hipEventRecord(lr.es, s));   // the side stream starts after everything so far
+    }
     // a3: sweeps, column part by column part; the first sweep of a part
     // centres on the fly from x0, the last writes the part's columns of xout
     const SweepShape ps = part_shape<TX>(H, k);
@@ -666,6 +716,7 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
                                                         nullptr, -1, lr);
         }
     }
+    if (lr.side) SFG_HIP(hipStreamWaitEvent(s, lr.ez, 0));   // join: the last hub rows before anything after
 }
 
 }  // namespace
