@@ -81,3 +81,19 @@ def test_multilevel_fp32_is_a_valid_sparsifier(S, orc):
     assert (kp == 2).sum() == rep[0]["k_sel"]
     ns = [r["n"] for r in rep]
     assert all(a > b for a, b in zip(ns, ns[1:]))
+
+
+@pytest.mark.parametrize("storage", [torch.float32, torch.float64])
+def test_power_law_hierarchy_is_deterministic(S, storage):
+    # the hub-row sweeps of a power-law graph's dense levels run on a side stream beside the main sweep; the
+    # ordering between them (two events per iterate) must make every run give the same bits
+    g = W.chung_lu(20000, 200000, 2.2, seed=4)
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    p = S.make_params(levels=5, k=16, sweeps=12, frac=0.1, storage=storage, seed=9)
+    keeps, taus = [], []
+    for _ in range(3):
+        keep, rep = S.sfg_sparsify(g.n, u, v, w, None, p)
+        keeps.append(keep.cpu().numpy())
+        taus.append([r["tau"] for r in rep])
+    assert all(np.array_equal(keeps[0], k) for k in keeps[1:])
+    assert all(t == taus[0] for t in taus[1:])
