@@ -58,7 +58,8 @@ def main():
     ap.add_argument("--smoother", choices=["jacobi", "gs"], default="jacobi",
                     help="gs: multicolour Gauss-Seidel (omega 1; colouring of the tree prepared once, like the tree)")
     ap.add_argument("--sweep-reps", type=int, default=10)
-    ap.add_argument("--workload", choices=["powergrid", "knn", "chunglu", "mesh", "sigma", "scaling"], default="powergrid",
+    ap.add_argument("--workload", choices=["powergrid", "knn", "chunglu", "mesh", "sigma", "scaling", "pcg"],
+                    default="powergrid",
                     help="powergrid: the headline line; the others print their own lines (bench_workloads.py)")
     ap.add_argument("--no-oracle", action="store_true", help="skip the oracle comparison of the extra workloads")
     args = ap.parse_args()

@@ -387,6 +387,40 @@ sfg_status sfg_kappa_estimate(int64_t n, int64_t m, const int32_t *u, const int3
                               sfg_dtype wt, const uint8_t *keep, const sfg_kappa_params *kp, const double *y0,
                               double *kappa, sfg_kappa_report *rep, void *stream);
 
+/* Report of sfg_pcg (host). */
+typedef struct {
+    int64_t iters;         /* outer CG iterations */
+    int64_t inner_iters;   /* tree-preconditioned CG iterations of all preconditioner solves */
+    double relres;         /* ||r|| / ||b|| at the end */
+    float ms;              /* wall time of the call */
+    int32_t converged;     /* relres <= tol */
+    int32_t inner_capped;  /* a preconditioner solve reached its iteration cap */
+} sfg_pcg_report;
+
+/*
+ * The sparsifier's downstream use in the paper's evaluation (Sec. 4, Table 3):
+ * conjugate gradients on L_G x = b grounded at node 0 (row and column 0
+ * removed, x_0 = 0), preconditioned by the sparsifier: every preconditioner
+ * application solves the grounded L_P system, by the tree-preconditioned
+ * conjugate gradients of sfg_kappa_estimate to a relative residual of 1e-6
+ * (in effect an exact solve for an outer tolerance of 1e-3 or more; an FP64
+ * solve of a large tree Laplacian cannot go much below that in residual).  Stops when ||r|| <= tol ||b|| or after
+ * max_iter iterations.  FP64 throughout.
+ *   u, v, w, wt  the graph's canonical edge list (F64 or F32 weights)
+ *   keep     [m] uint8: sparsifier edges != 0, its spanning tree marked 1
+ *            (the output of sfg_sparsify)
+ *   b        device [n] FP64 right-hand side; b[0] is ignored
+ *   x        device [n] FP64 out (x[0] = 0), may be NULL
+ *   tol      in (0, 1); max_iter >= 1
+ *   rep      host, may be NULL
+ * Allocates stream-ordered and synchronises (a host check per iteration).
+ * Errors: SFG_EINVAL (arguments; the edges marked 1 not a spanning tree),
+ * SFG_EUNSUPPORTED (2m >= 2^31).
+ */
+sfg_status sfg_pcg(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                   const uint8_t *keep, const double *b, double *x, double tol, int32_t max_iter,
+                   sfg_pcg_report *rep, void *stream);
+
 /* Parameters of sfg_sparsify (host struct). */
 typedef struct {
     int32_t levels;        /* 1 = spanning tree + one scoring pass; >1 = Alg. 1 hierarchy */

@@ -40,6 +40,9 @@ size_t tree_solve_workspace_bytes(int64_t n, int32_t k);
 void tree_solve(const sfg_tree *T, int32_t k, const double *b, double *x, void *ws, size_t ws_bytes, hipStream_t s);
 void block_dot(int64_t rows, int32_t k, const double *x, const double *y, double *out, double *scratch,
                hipStream_t s);
+size_t colsum_scratch_doubles(int32_t k);
+void block_colsum(int64_t rows, int32_t k, const double *x, double scale, double *out, double *scratch,
+                  hipStream_t s);
 size_t gram_scratch_doubles(int32_t k);
 void block_gram(int64_t rows, int32_t k, const double *x, const double *y, double *out, double *scratch,
                 hipStream_t s);
@@ -461,7 +464,9 @@ struct KappaEstimator {
     // X = L_P^+ Z (up to constants) by tree-preconditioned CG on all columns,
     // from X = Y diag(theta) when theta is given, else from 0.  A column stops
     // when ||r|| <= tol ||Z||.  Returns the iterations; *hit_cap at the cap.
-    int64_t solve(double tol, int32_t max_iter, const double *theta, bool *hit_cap) {
+    // check_every: convergence test every so many iterations (each costs a wait
+    // for the host); an exact preconditioner (P = its tree) converges in one
+    int64_t solve(double tol, int32_t max_iter, const double *theta, bool *hit_cap, int check_every = 4) {
         double *rz0 = small, *rz1 = small + 64, *pap = small + 128, *rr = small + 192, *zz = small + 256;
         const dim3 g(grid_for(n * k, kB)), b(kB);
         const uint32_t lg = lane_grid(n, k);
@@ -486,7 +491,7 @@ struct KappaEstimator {
         if (!active) return 0;
         tree_precond_pre(&T, k, R, Zp, rz0, pre_ws, s);
         SFG_HIP(hipMemcpyAsync(Pd, Zp, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
-        const int kCheck = 4;
+        const int kCheck = check_every < 1 ? 1 : check_every;
         int64_t it = 0;
         while (active) {
             if (it == max_iter) {
@@ -611,6 +616,155 @@ double run_kappa_estimator(KappaEstimator *e, const uint8_t *keep, const sfg_kap
 void free_kappa_estimator(KappaEstimator *e) { delete e; }
 
 }  // namespace sfg
+
+// ------------------------------------------------------------------ downstream PCG (Sec. 4)
+
+namespace sfg {
+
+namespace {
+
+// grounded right-hand side for the preconditioner: the consistent singular
+// system L_P z = rt with rt = r off node 0 and rt_0 = -sum(r) (r_0 = 0)
+__global__ void k_ground_rhs(int64_t n, const double *__restrict__ r, const double *__restrict__ sum,
+                             double *__restrict__ rt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rt[i] = i == 0 ? -sum[0] : r[i];
+}
+
+// z = x - x_0: the solution grounded at node 0 (preorder position 0)
+__global__ void k_shift0(int64_t n, const double *__restrict__ x, double *__restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = x[i] - x[0];
+}
+
+__global__ void k_zero_first(double *a) { a[0] = 0.0; }
+
+// x += alpha p, r -= alpha q with alpha = rz / pq
+__global__ void k_pcg_step(int64_t n, const double *__restrict__ rz, const double *__restrict__ pq,
+                           const double *__restrict__ p, const double *__restrict__ q, double *__restrict__ x,
+                           double *__restrict__ r) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double alpha = rz[0] / pq[0];
+    x[i] += alpha * p[i];
+    r[i] -= alpha * q[i];
+}
+
+// p = z + (rz_new / rz) p
+__global__ void k_pcg_dir(int64_t n, const double *__restrict__ rzn, const double *__restrict__ rz,
+                          const double *__restrict__ z, double *__restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = z[i] + (rzn[0] / rz[0]) * p[i];
+}
+
+}  // namespace
+
+// Conjugate gradients on L_G x = b grounded at node 0 (row and column 0
+// removed; x_0 = 0), preconditioned by solves with the sparsifier's grounded
+// Laplacian, each done by the tree-preconditioned CG of the estimate to a
+// relative residual inner_tol: the downstream use of the sparsifier in the
+// paper's evaluation.  Stops when ||r|| <= tol ||b|| (b_0 ignored).
+int64_t run_pcg(KappaEstimator &e, const uint8_t *keep, const double *b, double *x_out, double tol,
+                int32_t max_iter, double inner_tol, int32_t inner_max, sfg_pcg_report *rep, DevArena &A) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = e.s;
+    const int64_t n = e.n;
+    e.build_pre(keep, e.P);
+    double *bx = A.alloc<double>(n + 1), *x = A.alloc<double>(n + 1), *r = A.alloc<double>(n + 1);
+    double *z = A.alloc<double>(n + 1), *pv = A.alloc<double>(n + 1), *q = A.alloc<double>(n + 1);
+    double *sc = A.alloc<double>(16);   // rz, rz_new, pq, rr, bb, sum
+    double *scr = A.alloc<double>(colsum_scratch_doubles(1) + 64);
+    double *rz = sc, *rzn = sc + 1, *pq = sc + 2, *rr = sc + 3, *bb = sc + 4, *sum = sc + 5;
+    const dim3 g(grid_for(n, kB)), blk(kB);
+    hipLaunchKernelGGL(k_gather_rows, g, blk, 0, s, n, 1, e.t_order, b, bx);   // node order -> preorder
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, s, bx);               // node 0 is preorder position 0
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_zero, g, blk, 0, s, n, x);
+    SFG_LAUNCH_CHECK();
+    SFG_HIP(hipMemcpyAsync(r, bx, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    block_dot(n, 1, bx, bx, bb, scr, s);
+    const double nb = std::sqrt(e.to_host(bb, 1)[0]);
+    int64_t inner = 0;
+    bool capped = false;
+    auto precond = [&](const double *rin, double *zout) {
+        block_colsum(n, 1, rin, 1.0, sum, scr, s);
+        hipLaunchKernelGGL(k_ground_rhs, g, blk, 0, s, n, rin, sum, e.Z);
+        SFG_LAUNCH_CHECK();
+        bool cap = false;
+        // checked every iteration: iterations past convergence would only add
+        // rounding noise, which the tree solve amplifies, to the preconditioner
+        inner += e.solve(inner_tol, inner_max, nullptr, &cap, 1);
+        capped = capped || cap;
+        hipLaunchKernelGGL(k_shift0, g, blk, 0, s, n, e.X, zout);
+        SFG_LAUNCH_CHECK();
+    };
+    int64_t it = 0;
+    double relres = nb > 0 ? 1.0 : 0.0;
+    bool converged = nb == 0.0;
+    if (!converged) {
+        precond(r, z);
+        SFG_HIP(hipMemcpyAsync(pv, z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        block_dot(n, 1, r, z, rz, scr, s);
+        while (it < max_iter) {
+            ++it;
+            e.lap(e.G, pv, q);
+            hipLaunchKernelGGL(k_zero_first, dim3(1), dim3(1), 0, s, q);       // row 0 removed
+            SFG_LAUNCH_CHECK();
+            block_dot(n, 1, pv, q, pq, scr, s);
+            hipLaunchKernelGGL(k_pcg_step, g, blk, 0, s, n, rz, pq, pv, q, x, r);
+            SFG_LAUNCH_CHECK();
+            block_dot(n, 1, r, r, rr, scr, s);
+            relres = std::sqrt(e.to_host(rr, 1)[0]) / nb;
+            if (relres <= tol) {
+                converged = true;
+                break;
+            }
+            precond(r, z);
+            block_dot(n, 1, r, z, rzn, scr, s);
+            hipLaunchKernelGGL(k_pcg_dir, g, blk, 0, s, n, rzn, rz, z, pv);
+            SFG_LAUNCH_CHECK();
+            std::swap(rz, rzn);
+        }
+    }
+    if (x_out) {
+        hipLaunchKernelGGL(k_gather_rows, g, blk, 0, s, n, 1, e.inv, x, x_out);   // preorder -> node order
+        SFG_LAUNCH_CHECK();
+    }
+    SFG_HIP(hipStreamSynchronize(s));
+    if (rep) {
+        rep->iters = it;
+        rep->inner_iters = inner;
+        rep->relres = relres;
+        rep->converged = converged ? 1 : 0;
+        rep->inner_capped = capped ? 1 : 0;
+        rep->ms = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return it;
+}
+
+}  // namespace sfg
+
+extern "C" sfg_status sfg_pcg(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
+                              const uint8_t *keep, const double *b, double *x, double tol, int32_t max_iter,
+                              sfg_pcg_report *rep, void *stream) {
+    return sfg::guard([&] {
+        hipStream_t s = sfg::as_stream(stream);
+        SFG_REQUIRE(n >= 2 && m >= 1, SFG_EINVAL, "pcg: need n >= 2 and m >= 1");
+        SFG_REQUIRE(2 * m < (int64_t(1) << 31), SFG_EUNSUPPORTED, "pcg: 2*m must be < 2^31");
+        SFG_REQUIRE(wt == SFG_F64 || wt == SFG_F32, SFG_EINVAL, "pcg: weights must be F64 or F32");
+        SFG_REQUIRE(u && v && w && keep && b, SFG_EINVAL, "pcg: null pointer");
+        SFG_REQUIRE(tol > 0.0 && tol < 1.0, SFG_EINVAL, "pcg: tol must be in (0, 1)");
+        SFG_REQUIRE(max_iter >= 1, SFG_EINVAL, "pcg: max_iter must be >= 1");
+        if (rep) std::memset(rep, 0, sizeof(*rep));
+        sfg::DevArena A(s);
+        double *w64 = A.alloc<double>(m + 1);
+        sfg::convert_weights(w, wt, SFG_F64, m, w64, s);
+        sfg::KappaEstimator e(n, m, u, v, w64, keep, 1, A, s);
+        sfg::run_pcg(e, keep, b, x, tol, max_iter, 1e-6, 20000, rep, A);
+        A.finish();
+    });
+}
 
 extern "C" sfg_status sfg_kappa_estimate(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w,
                                          sfg_dtype wt, const uint8_t *keep, const sfg_kappa_params *kp,

@@ -37,7 +37,7 @@ EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_s
             "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify",
             "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam",
             "sfg_color", "sfg_smooth_gs", "sfg_random_block", "sfg_tree_order", "sfg_tree_solve",
-            "sfg_kappa_estimate", "sfg_csr_select"]
+            "sfg_kappa_estimate", "sfg_csr_select", "sfg_pcg"]
 
 
 class SfgError(RuntimeError):
@@ -68,6 +68,11 @@ class TreeStruct(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("order", ctypes.c_void_p), ("parent", ctypes.c_void_p),
                 ("size", ctypes.c_void_p), ("pw", ctypes.c_void_p), ("tdown", ctypes.c_void_p),
                 ("tup", ctypes.c_void_p)]
+
+
+class PcgReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("inner_iters", ctypes.c_int64), ("relres", ctypes.c_double),
+                ("ms", ctypes.c_float), ("converged", ctypes.c_int32), ("inner_capped", ctypes.c_int32)]
 
 
 class SurrogateStruct(ctypes.Structure):
@@ -136,6 +141,7 @@ def lib() -> ctypes.CDLL:
         L.sfg_tree_solve.argtypes = [P, I32, P, P, P, S, P]
         L.sfg_kappa_estimate.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P, P]
         L.sfg_csr_select.argtypes = [P, P, P, P, P, P, P, P, P, S, P]
+        L.sfg_pcg.argtypes = [I64, I64, P, P, P, I, P, P, P, D, I32, P, P]
         for name in EXPORTED:
             if name not in ("sfg_workspace_bytes", "sfg_last_error", "sfg_mpnn_param_count"):
                 getattr(L, name).restype = I
@@ -458,6 +464,18 @@ def sfg_tree_solve(tree: Tree, b: torch.Tensor, out: Optional[torch.Tensor] = No
     ts = tree.struct()
     _check(lib().sfg_tree_solve(ctypes.byref(ts), k, _ptr(b2), _ptr(out), _ptr(ws), ws.numel(), _stream()))
     return out.reshape(b.shape)
+
+
+def sfg_pcg(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, keep: torch.Tensor, b: torch.Tensor,
+            tol: float = 1e-3, max_iter: int = 20000, want_x: bool = True):
+    """CG on L_G x = b grounded at node 0, preconditioned by the sparsifier ``keep`` (its tree marked 1).
+    Returns (x or None, report dict)."""
+    m = int(u.shape[0])
+    x = torch.empty(n, dtype=torch.float64, device=b.device) if want_x else None
+    rep = PcgReport()
+    _check(lib().sfg_pcg(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(keep), _ptr(b.to(torch.float64).contiguous()),
+                         _ptr(x), float(tol), int(max_iter), ctypes.byref(rep), _stream()))
+    return x, {f: getattr(rep, f) for f, _ in PcgReport._fields_}
 
 
 def sfg_kappa_estimate(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, keep: torch.Tensor,

@@ -103,7 +103,8 @@ def test_struct_layouts_match_the_header(tmp_path):
         pytest.skip("no C compiler")
     mirrors = {"sfg_csr": sfg.CsrStruct, "sfg_kappa_params": sfg.KappaParams, "sfg_kappa_report": sfg.KappaReport,
                "sfg_tree": sfg.TreeStruct, "sfg_surrogate": sfg.SurrogateStruct, "sfg_params": sfg.Params,
-               "sfg_level_report": sfg.LevelReport, "sfg_report": sfg.Report}
+               "sfg_level_report": sfg.LevelReport, "sfg_report": sfg.Report,
+               "sfg_pcg_report": sfg.PcgReport}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sfg.h"', "int main(void) {"]
     for c, py in mirrors.items():
         lines.append(f'printf("{c} (sizeof) %zu\\n", sizeof({c}));')

@@ -370,3 +370,55 @@ def test_sigma_degenerate_graphs(S, orc):
         S.sfg_kappa_estimate(2, dev(g2.u), dev(g2.v), dev(g2.w), dev(np.ones(1, np.uint8)),
                              S.make_kappa_params(k=2, steps=2))
     assert e.value.name == "SFG_EINVAL"
+
+
+# --------------------------------------------------------------------------- downstream PCG (Sec. 4)
+
+def test_pcg_matches_oracle(S, orc):
+    # CG on the grounded L_G preconditioned by the sparsifier: the GPU solves L_P by tree-preconditioned CG to
+    # 1e-6, the oracle by sparse LU: both are exact for an outer tolerance of 1e-3, and over some 80 iterations
+    # finite-precision CG drifts by an iteration or two, so the counts agree within max(2, 5%)
+    import scipy.sparse as sp
+
+    g = W.mesh3d(14, 14, 14, seed=401, wdist=("lognormal", 0.0, 1.5))
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    seed = 5
+    bfull = np.zeros(g.n)
+    bfull[1:] = np.random.default_rng(seed).standard_normal(g.n - 1)
+    its = []
+    for f in (0.0, 0.05, 0.2):
+        keep, _ = S.sfg_sparsify(g.n, u, v, w, dev(W.random_block(g.n, 16, 402)),
+                                 S.make_params(k=16, sweeps=20, frac=f))
+        ref = orc.pcg_iterations(g.n, g.u, g.v, g.w, host(keep) > 0, tol=1e-3, seed=seed)
+        x, rep = S.sfg_pcg(g.n, u, v, w, keep, dev(bfull), tol=1e-3)
+        assert rep["converged"] == 1 and rep["inner_capped"] == 0, rep
+        print("f", f, "gpu", rep["iters"], "oracle", ref, "inner", rep["inner_iters"], "ms", round(rep["ms"], 1),
+              flush=True)
+        assert abs(rep["iters"] - ref) <= max(2, 0.05 * ref), (f, rep["iters"], ref)
+        assert rep["relres"] <= 1e-3
+        # the returned solution: grounded residual below the tolerance
+        L = sp.coo_matrix((np.r_[-g.w, -g.w], (np.r_[g.u, g.v], np.r_[g.v, g.u])), shape=(g.n, g.n)).tocsr()
+        L = L + sp.diags(-np.asarray(L.sum(axis=1)).ravel())
+        xh = host(x)
+        assert xh[0] == 0.0
+        res = L[1:, 1:] @ xh[1:] - bfull[1:]
+        assert np.linalg.norm(res) <= 1.001e-3 * np.linalg.norm(bfull[1:])
+        its.append(rep["iters"])
+    assert its[0] > its[1] > its[2]
+
+
+def test_pcg_errors(S):
+    g = W.grid2d(8, 8, seed=403)
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    keep, _ = S.sfg_sparsify(g.n, u, v, w, dev(W.random_block(g.n, 4, 404)), S.make_params(k=4, sweeps=4, frac=0.1))
+    b = dev(np.ones(g.n))
+    for kw in ({"tol": 0.0}, {"tol": 1.0}, {"max_iter": 0}):
+        with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+            S.sfg_pcg(g.n, u, v, w, keep, b, **kw)
+    no_tree = keep.clone()
+    no_tree[no_tree == 1] = 2
+    with pytest.raises(S.SfgError):
+        S.sfg_pcg(g.n, u, v, w, no_tree, b)
+    # the iteration cap is reported, not an error
+    x, rep = S.sfg_pcg(g.n, u, v, w, keep, b, tol=1e-12, max_iter=2)
+    assert rep["iters"] == 2 and rep["converged"] == 0
