@@ -273,7 +273,7 @@ def run_mesh(args) -> dict:
     # the ranked path takes 15% of the off-tree edges: the fraction at which the fast model reaches the plain
     # default's median condition number on held-out meshes
     ksel_r = int(math.ceil(0.15 * nc))
-    configs = {}
+    by_model = {}
     for name, kc in (("fast", SG.KC), ("recall", SG.KC_RECALL)):
         model, hist, t_train, recall = _train_surrogate(SG, k, T, f, kc, SG.TC)
         x0c = x0[:, :model.kc].contiguous()
@@ -312,7 +312,7 @@ def run_mesh(args) -> dict:
         mark = torch.zeros(nc, dtype=torch.bool, device="cuda")
         mark[cpos[sel2.bool()].long()] = True
         set_agree = float(mark[chosen.long()].float().mean().item())
-        configs[name] = {"cheap_vectors": model.kc, "cheap_sweeps": model.tc,
+        by_model[name] = {"cheap_vectors": model.kc, "cheap_sweeps": model.tc,
                          "surrogate_pruned_ms": round(t_pruned, 3),
                          "surrogate_vs_plain_time": round(t_pruned / t_plain, 3),
                          "surrogate_ranked_ms": round(t_ranked, 3),
@@ -324,7 +324,7 @@ def run_mesh(args) -> dict:
                          "recall_full_mesh_at_cand_frac": round(r_full, 4),
                          "selected_set_agreement": round(set_agree, 4), "recall_heldout_40cubed": recall,
                          "train_loss": [round(hist[0], 4), round(hist[-1], 4)], "train_s": round(t_train, 2)}
-        log(f"{name}: {configs[name]}")
+        log(f"{name}: {by_model[name]}")
         del model
     roof = sweep_roofline(H, x0, T, torch.float32, False, g.n, nnz, k, 4, 4)
     out = {"metric": "surrogate vs plain: recall of the plain selection and end-to-end time",
@@ -333,8 +333,8 @@ def run_mesh(args) -> dict:
            "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "off_tree_edges": nc, "vectors": k,
                       "sweeps": T, "frac": f, "cand_frac": cf, "train": "50 meshes 40^3, 60 epochs"},
            "plain_ms": round(t_plain, 3), "roofline_f32_sweep_tree": roof}
-    out.update(configs["fast"])
-    out["recall_config"] = configs["recall"]
+    out.update(by_model["fast"])
+    out["recall_config"] = by_model["recall"]
     return out
 
 
