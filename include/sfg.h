@@ -19,10 +19,11 @@
  *   last non-OK status on the calling thread.  Asynchronous device faults
  *   surface as SFG_EHIP at the next call that checks the stream.  No C++
  *   exception crosses the ABI.
- * - The four primitives (sfg_laplacian_csr, sfg_smooth, sfg_edge_scores,
- *   sfg_select_topk and the affinity / coarsening calls) allocate nothing:
- *   the caller passes a workspace of at least sfg_workspace_bytes() bytes.
- *   sfg_sparsify, sfg_spanning_tree and sfg_kappa_estimate allocate their
+ * - The primitives (sfg_laplacian_csr, sfg_csr_select, sfg_smooth,
+ *   sfg_edge_scores, sfg_select_topk and the affinity / coarsening calls)
+ *   allocate nothing: the caller passes a workspace of at least
+ *   sfg_workspace_bytes() bytes.  sfg_sparsify, sfg_spanning_tree,
+ *   sfg_kappa_estimate and sfg_pcg allocate their
  *   buffers themselves, stream-ordered, in chunks of at least 256 MB.  When
  *   a call completes (its stream drained) its chunks go to a per-device
  *   cache of at most 16 GiB that later calls reuse, held until the process
@@ -45,7 +46,7 @@ typedef enum {
     SFG_OK = 0,
     SFG_EINVAL = 1,        /* bad argument or malformed edge list */
     SFG_ENOTCONN = 2,      /* graph (or candidate sparsifier) is not connected */
-    SFG_ENOMEM = 3,        /* device allocation failed (sfg_sparsify only) */
+    SFG_ENOMEM = 3,        /* device allocation failed (the calls that allocate) */
     SFG_EHIP = 4,          /* HIP runtime error; message has the HIP error string */
     SFG_EWORKSPACE = 5,    /* workspace smaller than sfg_workspace_bytes() */
     SFG_EUNSUPPORTED = 6,  /* valid request the library does not support (e.g. k > 64) */
