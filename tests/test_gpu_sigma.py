@@ -422,3 +422,14 @@ def test_pcg_errors(S):
     # the iteration cap is reported, not an error
     x, rep = S.sfg_pcg(g.n, u, v, w, keep, b, tol=1e-12, max_iter=2)
     assert rep["iters"] == 2 and rep["converged"] == 0
+
+
+def test_pcg_two_nodes(S):
+    # the grounded system is 1 x 1: w x_1 = b_1, solved in one iteration
+    g = W.grid2d(1, 2, seed=405)
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    keep = dev(np.ones(1, np.uint8))
+    x, rep = S.sfg_pcg(g.n, u, v, w, keep, dev(np.array([7.0, 3.0])), tol=1e-6)
+    assert rep["iters"] == 1 and rep["converged"] == 1
+    xh = host(x)
+    assert xh[0] == 0.0 and abs(xh[1] - 3.0 / g.w[0]) <= 1e-14 * abs(3.0 / g.w[0])
