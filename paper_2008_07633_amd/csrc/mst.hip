@@ -151,16 +151,20 @@ int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t 
                                best_e);
         }
         SFG_LAUNCH_CHECK();
-        if (read_flag(flags, s) == 0) break;     // no component has an outgoing edge
+        // no component with an outgoing edge: done.  Read every other round
+        // only (each read is a host sync): a round without outgoing edges hooks
+        // nothing, and its jumps and relabelling change nothing, so at most one
+        // idle round runs past the end
+        if (round % 2 == 1 && read_flag(flags, s) == 0) break;
         hipLaunchKernelGGL(k_mst_hook, gn, b, 0, s, n, u, v, comp, best_e, parent, in_tree);
         SFG_LAUNCH_CHECK();
-        for (int it = 0;; it += 2) {   // two jumps per check of the flag (one host sync)
+        for (int it = 0;; it += 4) {   // four jumps per check of the flag (one host sync); extra jumps are no-ops
             SFG_REQUIRE(it < 64, SFG_EHIP, "spanning_tree: pointer jumping did not converge");
             fill_i32(flags + 1, 1, 0, s);
-            hipLaunchKernelGGL(k_mst_jump, gn, b, 0, s, n, comp, parent, flags + 1);
-            SFG_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_mst_jump, gn, b, 0, s, n, comp, parent, flags + 1);
-            SFG_LAUNCH_CHECK();
+            for (int j = 0; j < 4; ++j) {
+                hipLaunchKernelGGL(k_mst_jump, gn, b, 0, s, n, comp, parent, flags + 1);
+                SFG_LAUNCH_CHECK();
+            }
             if (read_flag(flags + 1, s) == 0) break;
         }
         hipLaunchKernelGGL(k_mst_relabel, gn, b, 0, s, n, comp, parent, best_w, best_e);
