@@ -123,3 +123,26 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(c, "(sizeof)")] == ctypes.sizeof(py), c
         for f, _ in py._fields_:
             assert got[(c, f)] == getattr(py, f).offset, (c, f)
+
+
+def test_size_limits_before_device_work(L):
+    # 32-bit row pointers and edge ids: 2m and n must stay below 2^31, rejected
+    # as unsupported before any pointer is looked at or any device work is queued
+    from paper_2008_07633_amd import sfg
+
+    big_m, big_n = 1 << 30, (1 << 31) - 1
+    cases = [
+        (lambda: L.sfg_laplacian_csr(10, big_m, *[None] * 3, sfg.F64, *[None] * 8, 0, None), b"2*m"),
+        (lambda: L.sfg_laplacian_csr(big_n, 0, *[None] * 3, sfg.F64, *[None] * 8, 0, None), b"n must"),
+        (lambda: L.sfg_tree_order(10, big_m, *[None] * 3, sfg.F64, *[None] * 8, 0, None), b"2*m"),
+        (lambda: L.sfg_pcg(10, big_m, *[None] * 3, sfg.F64, None, None, None, 1e-6, 10, None, None), b"2*m"),
+        (lambda: L.sfg_kappa_estimate(10, big_m, *[None] * 3, sfg.F64, *[None] * 6), b"2*m"),
+        (lambda: L.sfg_select_topk(None, sfg.F64, 1 << 31, 1, None, None, None, None, 0, None), b"ne must"),
+    ]
+    for call, msg in cases:
+        st = call()
+        assert sfg.STATUS[st] == "SFG_EUNSUPPORTED", L.sfg_last_error()
+        assert msg in L.sfg_last_error()
+    # one below the limit passes the size check and fails on the next argument
+    st = L.sfg_laplacian_csr(10, (1 << 30) - 1, *[None] * 3, sfg.F64, *[None] * 8, 0, None)
+    assert sfg.STATUS[st] == "SFG_EWORKSPACE"
