@@ -48,6 +48,31 @@ def src_hash(path: str) -> str:
     return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
+def cpu_baseline(g, tree, cand, X0, k: int, T: int, omega: float, ksel: int, f64: bool, gs: bool) -> dict:
+    """The oracle (single-threaded C, FP64) timed on one full step of the same workload."""
+    import oracle
+
+    oracle.build(force=False)
+    tmask = tree.cpu().numpy().astype(bool)
+    cnp = cand.cpu().numpy()
+    wnp = g.w if f64 else g.w.astype(np.float32).astype(np.float64)
+    c0 = time.perf_counter()
+    Hc = oracle.laplacian_csr(g.n, g.u[tmask], g.v[tmask], wnp[tmask])
+    Xc, _ = oracle.center(X0)
+    if gs:
+        cl, ncl = oracle.color(Hc)
+        Xs = oracle.smooth_gs(Hc, Xc, T, omega, cl, ncl)
+    else:
+        Xs = oracle.smooth(Hc, Xc, T, omega)
+    sc = oracle.edge_scores(Xs, g.u[cnp], g.v[cnp], wnp[cnp])
+    oracle.select_topk(sc, cnp, ksel)
+    c1 = time.perf_counter()
+    ncand = int(cnp.size)
+    return {"value": round(ncand / (c1 - c0), 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full step of the same workload (tree CSR, centring, {T} sweeps of {k} FP64 vectors, "
+                      f"{ncand} scores, top-{ksel} sort), single-threaded C, {c1 - c0:.2f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,7 +86,6 @@ def main():
     ap.add_argument("--workload", choices=["powergrid", "knn", "chunglu", "mesh", "sigma", "scaling", "pcg"],
                     default="powergrid",
                     help="powergrid: the headline line; the others print their own lines (bench_workloads.py)")
-    ap.add_argument("--no-oracle", action="store_true", help="skip the oracle comparison of the extra workloads")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path (run with --gpus 1)",
@@ -206,28 +230,7 @@ def main():
                 "smoothing_gbs": round(smoothing_gbs, 1), "smoothing_frac": round(smoothing_gbs / HBM_PEAK_GBS, 4)}
 
     # ---- CPU baseline: the oracle on one full step of the same workload
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-
-        oracle.build(force=False)
-        tmask = tree.cpu().numpy().astype(bool)
-        cnp = cand.cpu().numpy()
-        wnp = g.w if f64 else g.w.astype(np.float32).astype(np.float64)
-        c0 = time.perf_counter()
-        Hc = oracle.laplacian_csr(g.n, g.u[tmask], g.v[tmask], wnp[tmask])
-        Xc, _ = oracle.center(X0)
-        if gs:
-            cl, ncl = oracle.color(Hc)
-            Xs = oracle.smooth_gs(Hc, Xc, T, omega, cl, ncl)
-        else:
-            Xs = oracle.smooth(Hc, Xc, T, omega)
-        sc = oracle.edge_scores(Xs, g.u[cnp], g.v[cnp], wnp[cnp])
-        oracle.select_topk(sc, cnp, ksel)
-        c1 = time.perf_counter()
-        cpu = {"value": round(ncand / (c1 - c0), 1), "unit": "edges/s", "cores": 1, "kind": "oracle",
-               "sample": "one full step of the same workload (tree CSR, centring, 20 sweeps of 16 FP64 vectors, "
-                         f"{ncand} scores, top-{ksel} sort), single-threaded C, {c1 - c0:.2f} s"}
+    cpu = None if args.no_cpu_baseline else cpu_baseline(g, tree, cand, X0, k, T, omega, ksel, f64, gs)
 
     out = {
         "metric": METRIC,

@@ -1,0 +1,60 @@
+"""The oracle and the GPU path share no code: neither imports the other.
+
+The product (the package, the shared input generators, the extra bench
+workloads) never imports the oracle; bench.py does so only in its CPU-baseline
+leg; the oracle never imports the package.  Runs without a GPU.
+"""
+import ast
+import glob
+import os
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def imported_modules(path):
+    tree = ast.parse(open(path).read(), path)
+    for node in ast.walk(tree):
+        if isinstance(node, ast.Import):
+            for a in node.names:
+                yield a.name.split(".")[0], node
+        elif isinstance(node, ast.ImportFrom) and node.module and node.level == 0:
+            yield node.module.split(".")[0], node
+
+
+def py_files(*patterns):
+    out = []
+    for p in patterns:
+        out += glob.glob(os.path.join(ROOT, p), recursive=True)
+    return sorted(out)
+
+
+def test_product_never_imports_the_oracle():
+    files = py_files("paper_2008_07633_amd/**/*.py", "workloads/**/*.py", "bench_workloads.py")
+    assert files
+    for f in files:
+        assert "oracle" not in {m for m, _ in imported_modules(f)}, f
+
+
+def test_oracle_never_imports_the_product():
+    for f in py_files("oracle/**/*.py"):
+        assert "paper_2008_07633_amd" not in {m for m, _ in imported_modules(f)}, f
+
+
+def test_bench_imports_the_oracle_only_for_the_cpu_baseline():
+    path = os.path.join(ROOT, "bench.py")
+    tree = ast.parse(open(path).read(), path)
+    for fn in ast.walk(tree):
+        if not isinstance(fn, ast.FunctionDef):
+            continue
+        uses = [n for n in ast.walk(fn) if isinstance(n, ast.Import) and any(a.name == "oracle" for a in n.names)]
+        if uses:
+            assert "cpu" in fn.name or "baseline" in fn.name, fn.name
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))]
+    assert all("oracle" not in ast.dump(n) for n in top)
+
+
+def test_hip_sources_include_no_oracle_code():
+    for f in glob.glob(os.path.join(ROOT, "paper_2008_07633_amd", "csrc", "*")):
+        for line in open(f):
+            if line.lstrip().startswith("#include"):
+                assert "oracle" not in line, (f, line)
