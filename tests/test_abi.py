@@ -146,3 +146,34 @@ def test_size_limits_before_device_work(L):
     # one below the limit passes the size check and fails on the next argument
     st = L.sfg_laplacian_csr(10, (1 << 30) - 1, *[None] * 3, sfg.F64, *[None] * 8, 0, None)
     assert sfg.STATUS[st] == "SFG_EWORKSPACE"
+
+
+def test_header_declares_every_export(L):
+    # the reverse of the export check: no sfg_ entry point exists that the header does not document
+    import shutil
+    import subprocess
+
+    from paper_2008_07633_amd import sfg
+
+    if shutil.which("nm") is None:
+        pytest.skip("no nm")
+    out = subprocess.run(["nm", "-D", "--defined-only", sfg.LIB_PATH], check=True, capture_output=True,
+                         text=True).stdout
+    exported = sorted({f[2] for f in (line.split() for line in out.splitlines())
+                       if len(f) == 3 and f[1] == "T" and f[2].startswith("sfg_")})
+    assert exported == declared_symbols()
+
+
+def test_header_compiles_as_c_and_cpp(tmp_path):
+    import shutil
+    import subprocess
+
+    src_c = tmp_path / "h.c"
+    src_c.write_text('#include "sfg.h"\nint main(void) { return (int)sizeof(sfg_params) == 0; }\n')
+    src_cc = tmp_path / "h.cc"
+    src_cc.write_text('#include "sfg.h"\nint main() { sfg_status s = SFG_OK; return (int)s; }\n')
+    inc = os.path.join(ROOT, "include")
+    for cc, src, std in (("gcc", src_c, "-std=c99"), ("g++", src_cc, "-std=c++17")):
+        if shutil.which(cc) is None:
+            pytest.skip(f"no {cc}")
+        subprocess.run([cc, std, "-Wall", "-Werror", "-pedantic", "-fsyntax-only", "-I", inc, str(src)], check=True)
