@@ -58,3 +58,26 @@ def test_hip_sources_include_no_oracle_code():
         for line in open(f):
             if line.lstrip().startswith("#include"):
                 assert "oracle" not in line, (f, line)
+
+
+def test_build_flags():
+    # gfx950 only; FP64 rounds every operation as written (bitwise parity with
+    # the oracle); packed FP32 instructions are switched off in device code
+    from paper_2008_07633_amd import build
+
+    f = build.FLAGS
+    assert "--offload-arch=gfx950" in f and [a for a in f if a.startswith("--offload-arch")] == ["--offload-arch=gfx950"]
+    assert "-ffp-contract=off" in f
+    i = f.index("-packed-fp32-ops")
+    assert f[i - 3:i] == ["-Xclang", "-target-feature", "-Xclang"]
+
+
+def test_device_sources_avoid_unsafe_runtime_calls():
+    # no memset nodes (capturable code clears memory with fill kernels), default
+    # stream priorities only, no registration of existing host memory
+    banned = ("hipMemsetAsync", "hipMemset(", "hipStreamCreateWithPriority", "hipHostRegister",
+              "__HIP_PLATFORM", "cuda_runtime")
+    for f in glob.glob(os.path.join(ROOT, "paper_2008_07633_amd", "csrc", "*")):
+        text = open(f).read()
+        for b in banned:
+            assert b not in text, (f, b)
