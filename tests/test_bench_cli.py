@@ -1,15 +1,18 @@
-"""bench.py's command line: it measures one GPU, and says so for more (no GPU needed)."""
+"""bench.py's command line: it measures one GPU and says so for more; its
+oracle leg; and (GPU) the one JSON line of a short run with the contract's fields."""
 import os
 import subprocess
 import sys
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def run(args, env_extra=None):
+def run(args, env_extra=None, timeout=120):
     env = dict(os.environ, **(env_extra or {}))
     return subprocess.run([sys.executable, os.path.join(ROOT, "bench.py")] + args, capture_output=True, text=True,
-                          env=env, timeout=120, cwd=ROOT)
+                          env=env, timeout=timeout, cwd=ROOT)
 
 
 def test_more_than_one_gpu_exits_with_a_message():
@@ -50,3 +53,30 @@ def test_cpu_baseline_leg_on_a_tiny_graph():
     r = bench.cpu_baseline(g, tree, cand, X0, 4, 3, 0.5, ksel, True, False)
     assert r["kind"] == "oracle" and r["cores"] == 1 and r["unit"] == "edges/s" and r["value"] > 0
     assert f"3 sweeps of 4 FP64 vectors, {cand.numel()} scores, top-{ksel}" in r["sample"]
+
+
+@pytest.mark.gpu
+def test_bench_json_line_on_the_gpu():
+    # a short run of the default workload in a child process: one JSON line with the contract's fields
+    import json
+
+    import torch
+
+    if torch.cuda.device_count() == 0:   # counts devices without initialising the runtime in this process
+        pytest.skip("no GPU")
+    r = run(["--steps", "2", "--warmup", "1", "--no-cpu-baseline", "--sweep-reps", "2"], timeout=300)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+                "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert key in d, key
+    assert d["n_gpus"] == 1 and d["steps"] == 2 and d["warmup"] == 1 and d["higher_is_better"] is True
+    assert d["dtype"] == "f64" and d["data"] == "synthetic" and d["cpu_baseline"] is None
+    assert d["config"]["workload"].startswith("powergrid1000x1000")
+    assert d["value"] > 0 and abs(d["value"] * d["ms_per_step"] * 1e-3 - d["config"]["off_tree_edges"]) < 1e-3 * d[
+        "config"]["off_tree_edges"]
+    roof = d["roofline"]
+    assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
+    assert 0 < roof["frac"] <= 1 and abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
