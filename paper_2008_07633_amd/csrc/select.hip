@@ -113,6 +113,10 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, 
     const int t = threadIdx.x;
     const int nb = 1 << width;
     const int per = (nb + 255) / 256;
+    // Every thread reads the sought rank before the first barrier; the one
+    // thread that updates the state below does so only after the scan's
+    // barriers, so no thread can see its new value.
+    const int64_t krem = st->krem;
     int64_t mine = 0;
     for (int i = 0; i < per; ++i) {
         const int b = t * per + i;
@@ -128,7 +132,6 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, 
         suffix[t] += add;
         __syncthreads();
     }
-    const int64_t krem = st->krem;
     const int64_t above = suffix[t + 1];   // suffix[256] stays 0
     if (above < krem && krem <= above + mine) {
         int64_t acc = above;

@@ -234,6 +234,30 @@ def test_select_topk_matches_sort(S, orc, dt):
                 assert tau == float("inf")
 
 
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_select_many_equal_keys_at_the_threshold(S, orc, dt):
+    """A large run of equal keys straddles the k-th position, so the digit pick
+    of every radix pass lands in the same crowded bucket; the marked set must
+    still be the first k by (score desc, position asc)."""
+    rng = np.random.default_rng(81)
+    for ne, share in ((200003, 0.6), (70001, 0.99)):
+        s = rng.random(ne) + 2.0
+        tied = rng.random(ne) < share
+        s[tied] = 1.5
+        s[rng.random(ne) < 0.2] = 0.25
+        s = s.astype(dt == torch.float64 and np.float64 or np.float32).astype(np.float64)
+        eid = np.arange(ne, dtype=np.int32)
+        n_above = int((s > 1.5).sum())
+        n_tied = int((s == 1.5).sum())
+        for k in (n_above + 1, n_above + n_tied // 2, n_above + n_tied - 1, n_above + n_tied):
+            sel, tau = S.sfg_select_topk(dev(s, dt), k)
+            pos, tau_ref = orc.select_topk(s, eid, k)
+            want = np.zeros(ne, np.uint8)
+            want[pos] = 1
+            assert np.array_equal(host(sel), want), (ne, k)
+            assert tau == tau_ref == 1.5
+
+
 def test_select_rejects_bad_scores(S):
     s = torch.tensor([1.0, float("nan"), 3.0], dtype=torch.float64, device="cuda")
     with pytest.raises(S.SfgError, match="SFG_ENUMERIC"):
