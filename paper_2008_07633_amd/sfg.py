@@ -155,12 +155,76 @@ def _check(status: int):
         raise SfgError(status, msg.decode() if msg else "")
 
 
-def _ptr(t: Optional[torch.Tensor]):
+_I32, _U8, _F32, _F64 = (torch.int32,), (torch.uint8,), (torch.float32,), (torch.float64,)
+_W = (torch.float64, torch.float32)                        # weight / score types
+_X = (torch.float64, torch.float32, torch.float16, torch.bfloat16)   # block storage types
+
+
+def _chk(t: Optional[torch.Tensor], name: str = "tensor", dtypes=None, numel: Optional[int] = None,
+         optional: bool = False) -> None:
+    """Check what the C ABI assumes of ``t`` apart from its device: one of
+    ``dtypes``, contiguous, at least ``numel`` elements."""
+    if t is None:
+        if optional:
+            return
+        raise ValueError(f"{name}: required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {' or '.join(str(d) for d in dtypes)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: holds {t.numel()} elements, the call needs {numel}")
+
+
+def _ptr(t: Optional[torch.Tensor], name: str = "tensor", dtypes=None, numel: Optional[int] = None,
+         optional: bool = False):
+    """Device pointer of ``t`` after the checks of :func:`_chk` and a check
+    that it lives on a GPU.  Every binding runs these before it calls the
+    library, so a wrong tensor raises ValueError instead of letting a kernel
+    read or write past its end."""
+    _chk(t, name, dtypes, numel, optional)
     if t is None:
         return None
     if not t.is_cuda:
-        raise ValueError("libsfg takes device tensors")
+        raise ValueError(f"{name}: libsfg takes device tensors")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _ptrs(*specs) -> list:
+    """Pointers of several (tensor, name, dtypes, numel) arguments: every one
+    is checked by :func:`_chk` before any is checked for its device."""
+    for t, name, dts, cnt in specs:
+        _chk(t, name, dts, cnt)
+    return [_ptr(t, name, dts, cnt) for t, name, dts, cnt in specs]
+
+
+def _block(x: torch.Tensor, name: str, dtypes, rows: Optional[int] = None) -> tuple[int, int]:
+    """(n, k) of an n-by-k row-major block, checked to be 2-D."""
+    if not isinstance(x, torch.Tensor) or x.dim() != 2:
+        raise ValueError(f"{name}: expected an n-by-k tensor")
+    if rows is not None and int(x.shape[0]) != rows:
+        raise ValueError(f"{name}: has {int(x.shape[0])} rows, the graph has {rows} nodes")
+    _chk(x, name, dtypes)
+    return int(x.shape[0]), int(x.shape[1])
+
+
+def _edges(u: torch.Tensor, v: torch.Tensor, w: Optional[torch.Tensor] = None) -> int:
+    """Edge count of an edge list (u, v int32 of equal length, w of F64/F32)."""
+    for name, t in (("u", u), ("v", v)):
+        if not isinstance(t, torch.Tensor) or t.dim() != 1:
+            raise ValueError(f"{name}: expected a 1-D tensor")
+    m = int(u.shape[0])
+    _chk(u, "u", _I32, m)
+    if int(v.shape[0]) != m:
+        raise ValueError(f"v: {int(v.shape[0])} entries, u has {m}")
+    _chk(v, "v", _I32, m)
+    if w is not None:
+        _chk(w, "w", _W, m)
+        if w.numel() != m:
+            raise ValueError(f"w: {w.numel()} entries, u has {m}")
+    return m
 
 
 def _stream():
@@ -192,8 +256,12 @@ class Csr:
     deg: torch.Tensor
 
     def struct(self) -> CsrStruct:
-        return CsrStruct(self.n, self.nnz, self.rowptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr(),
-                         self.eid.data_ptr(), self.deg.data_ptr(), _TORCH_TO_SFG[self.val.dtype])
+        """The C view, after checking every array against n and nnz."""
+        n, nnz = int(self.n), int(self.nnz)
+        ptrs = _ptrs((self.rowptr, "csr.rowptr", _I32, n + 1), (self.col, "csr.col", _I32, nnz),
+                     (self.val, "csr.val", _W, nnz), (self.eid, "csr.eid", _I32, nnz),
+                     (self.deg, "csr.deg", (self.val.dtype,), n))
+        return CsrStruct(n, nnz, *(p.value for p in ptrs), _TORCH_TO_SFG[self.val.dtype])
 
 
 def sfg_laplacian_csr(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
@@ -201,7 +269,8 @@ def sfg_laplacian_csr(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
                       out: Optional[Csr] = None, nnz: Optional[int] = None) -> Csr:
     """CSR of A and the degrees D of the graph (L = D - A).  With ``out`` and
     ``nnz`` given nothing is allocated and the call does not synchronise."""
-    m = int(u.shape[0])
+    m = _edges(u, v, w)
+    pm = _ptr(mask, "mask", _U8, m, optional=True)
     dev = u.device
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_LAPLACIAN_CSR, n, m, 0, w.dtype), dev)
@@ -212,11 +281,17 @@ def sfg_laplacian_csr(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
                   torch.empty(max(cap, 1), dtype=w.dtype, device=dev),
                   torch.empty(max(cap, 1), dtype=torch.int32, device=dev),
                   torch.empty(n, dtype=w.dtype, device=dev))
+    # the call writes 2 x (included edges) entries
+    need = int(nnz) if nnz is not None else (2 * m if mask is None else 2 * int(mask.sum().item()))
+    if out.val.dtype != w.dtype:
+        raise ValueError(f"out.val: dtype {out.val.dtype}, the weights are {w.dtype}")
+    outs = _ptrs((out.rowptr, "out.rowptr", _I32, n + 1), (out.col, "out.col", _I32, need),
+                 (out.val, "out.val", _W, need), (out.eid, "out.eid", _I32, need),
+                 (out.deg, "out.deg", (w.dtype,), n))
     got = ctypes.c_int64(0)
-    _check(lib().sfg_laplacian_csr(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(mask), _ptr(out.rowptr),
-                                   _ptr(out.col), _ptr(out.val), _ptr(out.eid), _ptr(out.deg),
-                                   None if nnz is not None else ctypes.byref(got), _ptr(ws), ws.numel(),
-                                   _stream()))
+    _check(lib().sfg_laplacian_csr(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), pm, *outs,
+                                   None if nnz is not None else ctypes.byref(got), _ptr(ws, "ws", _U8),
+                                   ws.numel(), _stream()))
     out.nnz = int(nnz) if nnz is not None else int(got.value)
     return out
 
@@ -239,9 +314,16 @@ def sfg_csr_select(G: Csr, mask: torch.Tensor, out: Optional[Csr] = None, nnz: O
                   torch.empty(n, dtype=G.val.dtype, device=dev))
     got = ctypes.c_int64(0)
     gs = G.struct()
-    _check(lib().sfg_csr_select(ctypes.byref(gs), _ptr(mask), _ptr(out.rowptr), _ptr(out.col), _ptr(out.val),
-                                _ptr(out.eid), _ptr(out.deg), None if nnz is not None else ctypes.byref(got),
-                                _ptr(ws), ws.numel(), _stream()))
+    need = int(nnz) if nnz is not None else G.nnz
+    if out.val.dtype != G.val.dtype:
+        raise ValueError(f"out.val: dtype {out.val.dtype}, G's values are {G.val.dtype}")
+    _chk(mask, "mask", _U8, G.nnz // 2)
+    outs = _ptrs((out.rowptr, "out.rowptr", _I32, n + 1), (out.col, "out.col", _I32, need),
+                 (out.val, "out.val", _W, need), (out.eid, "out.eid", _I32, need),
+                 (out.deg, "out.deg", (G.val.dtype,), n))
+    _check(lib().sfg_csr_select(ctypes.byref(gs), _ptr(mask, "mask", _U8, G.nnz // 2), *outs,
+                                None if nnz is not None else ctypes.byref(got), _ptr(ws, "ws", _U8), ws.numel(),
+                                _stream()))
     out.nnz = int(nnz) if nnz is not None else int(got.value)
     return out
 
@@ -250,16 +332,17 @@ def sfg_smooth(H: Csr, x0: torch.Tensor, sweeps: int, omega: float = 0.5, storag
                final_f32: bool = False, out: Optional[torch.Tensor] = None,
                ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Centre the n-by-k FP64 block x0 and smooth it with damped-Jacobi sweeps on H."""
-    n, k = int(x0.shape[0]), int(x0.shape[1])
+    n, k = _block(x0, "x0", _F64, rows=H.n)
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
     odt = torch.float32 if (final_f32 and st in (F16, BF16)) else _SFG_TO_TORCH[st]
     if out is None:
         out = torch.empty((n, k), dtype=odt, device=x0.device)
+    _chk(out, "out", (odt,), n * k)
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_SMOOTH, n, 0, k, st), x0.device)
     hs = H.struct()
     _check(lib().sfg_smooth(ctypes.byref(hs), k, sweeps, float(omega), _ptr(x0), st, int(bool(final_f32)),
-                            _ptr(out), _ptr(ws), ws.numel(), _stream()))
+                            _ptr(out, "out", (odt,), n * k), _ptr(ws, "ws", _U8), ws.numel(), _stream()))
     return out
 
 
@@ -268,7 +351,8 @@ def sfg_random_block(n: int, k: int, seed: int, block: int = 0, device="cuda",
     """n-by-k FP64 standard normals drawn on the device (Philox4x32-10, Box-Muller)."""
     if out is None:
         out = torch.empty((n, k), dtype=torch.float64, device=device)
-    _check(lib().sfg_random_block(n, k, ctypes.c_uint64(seed), ctypes.c_uint32(block), _ptr(out), _stream()))
+    _check(lib().sfg_random_block(n, k, ctypes.c_uint64(seed), ctypes.c_uint32(block),
+                                  _ptr(out, "out", _F64, n * k), _stream()))
     return out
 
 
@@ -283,8 +367,8 @@ def sfg_color(H: Csr, ws: Optional[torch.Tensor] = None):
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_COLOR, H.n, 0, 0, F64), dev)
     hs = H.struct()
-    _check(lib().sfg_color(ctypes.byref(hs), _ptr(color), _ptr(rows), _ptr(ptr), ctypes.byref(nc), _ptr(ws),
-                           ws.numel(), _stream()))
+    _check(lib().sfg_color(ctypes.byref(hs), _ptr(color), _ptr(rows), _ptr(ptr), ctypes.byref(nc),
+                           _ptr(ws, "ws", _U8), ws.numel(), _stream()))
     return color, rows, ptr, int(nc.value)
 
 
@@ -292,15 +376,17 @@ def sfg_smooth_gs(H: Csr, classes, x0: torch.Tensor, sweeps: int, omega: float =
                   out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Centre x0 and smooth it by multicolour Gauss-Seidel sweeps (classes from sfg_color)."""
     _, rows, ptr, nc = classes
-    n, k = int(x0.shape[0]), int(x0.shape[1])
+    n, k = _block(x0, "x0", _F64, rows=H.n)
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
     if out is None:
         out = torch.empty((n, k), dtype=_SFG_TO_TORCH[st], device=x0.device)
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_SMOOTH, n, 0, k, st), x0.device)
     hs = H.struct()
-    _check(lib().sfg_smooth_gs(ctypes.byref(hs), _ptr(rows), _ptr(ptr), nc, k, sweeps, float(omega), _ptr(x0), st,
-                               _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    _check(lib().sfg_smooth_gs(ctypes.byref(hs), _ptr(rows, "class_rows", _I32, n),
+                               _ptr(ptr, "class_ptr", _I32, int(nc) + 1), nc, k, sweeps, float(omega), _ptr(x0),
+                               st, _ptr(out, "out", (_SFG_TO_TORCH[st],), n * k), _ptr(ws, "ws", _U8),
+                               ws.numel(), _stream()))
     return out
 
 
@@ -308,20 +394,24 @@ def sfg_edge_scores(x: torch.Tensor, u: torch.Tensor, v: torch.Tensor, w: torch.
                     cand: Optional[torch.Tensor] = None, score_dtype=None,
                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """w_e * |x_u - x_v|^2 for every candidate edge (all edges if cand is None)."""
-    n, k = int(x.shape[0]), int(x.shape[1])
-    ne = int(cand.shape[0]) if cand is not None else int(u.shape[0])
+    n, k = _block(x, "x", _X)
+    m = _edges(u, v, w)
+    ne = int(cand.numel()) if cand is not None else m
+    _chk(cand, "cand", _I32, ne, optional=True)
     sdt = score_dtype or (torch.float64 if x.dtype == torch.float64 else torch.float32)
     if out is None:
         out = torch.empty(max(ne, 1), dtype=sdt, device=x.device)[:ne]
-    _check(lib().sfg_edge_scores(_ptr(x), _dt(x), n, k, ne, _ptr(cand), _ptr(u), _ptr(v), _ptr(w), _dt(w),
-                                 _ptr(out), _TORCH_TO_SFG[out.dtype], _stream()))
+    _chk(out, "out", _W, ne)
+    _check(lib().sfg_edge_scores(_ptr(x), _dt(x), n, k, ne, _ptr(cand, optional=True), _ptr(u), _ptr(v), _ptr(w),
+                                 _dt(w), _ptr(out), _TORCH_TO_SFG[out.dtype], _stream()))
     return out
 
 
 def sfg_select_topk(score: torch.Tensor, k: int, sel: Optional[torch.Tensor] = None,
                     tau: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None, sync: bool = True):
     """Mark the top k scores (ties: lower position first).  Returns (sel, tau)."""
-    ne = int(score.shape[0])
+    _chk(score, "score", _W)
+    ne = int(score.numel())
     dev = score.device
     if sel is None:
         sel = torch.empty(max(ne, 1), dtype=torch.uint8, device=dev)[:ne]
@@ -330,40 +420,45 @@ def sfg_select_topk(score: torch.Tensor, k: int, sel: Optional[torch.Tensor] = N
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_SELECT_TOPK, 0, ne, 0, score.dtype), dev)
     th = ctypes.c_double(0.0)
-    _check(lib().sfg_select_topk(_ptr(score), _dt(score), ne, int(k), _ptr(sel), _ptr(tau),
-                                 ctypes.byref(th) if sync else None, _ptr(ws), ws.numel(), _stream()))
+    _chk(sel, "sel", _U8, ne)
+    _chk(tau, "tau", _F64, 1)
+    _check(lib().sfg_select_topk(_ptr(score), _dt(score), ne, int(k), _ptr(sel, "sel", _U8, ne),
+                                 _ptr(tau, "tau", _F64, 1), ctypes.byref(th) if sync else None,
+                                 _ptr(ws, "ws", _U8), ws.numel(), _stream()))
     return sel, (th.value if sync else tau)
 
 
 def sfg_spanning_tree(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,
                       allowed: Optional[torch.Tensor] = None):
     """Maximum-weight spanning forest (weight desc, edge id asc).  Returns (in_tree, n_components)."""
-    m = int(u.shape[0])
+    m = _edges(u, v, w)
     out = torch.empty(max(m, 1), dtype=torch.uint8, device=u.device)[:m]
     nc = ctypes.c_int64(0)
-    _check(lib().sfg_spanning_tree(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(allowed), _ptr(out),
-                                   ctypes.byref(nc), _stream()))
+    _check(lib().sfg_spanning_tree(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w),
+                                   _ptr(allowed, "allowed", _U8, m, optional=True), _ptr(out), ctypes.byref(nc),
+                                   _stream()))
     return out, int(nc.value)
 
 
 def sfg_affinity(x: torch.Tensor, u: torch.Tensor, v: torch.Tensor, aff_dtype=None,
                  out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-    n, k = int(x.shape[0]), int(x.shape[1])
-    m = int(u.shape[0])
+    n, k = _block(x, "x", _W)
+    m = _edges(u, v)
     adt = aff_dtype or x.dtype
     if out is None:
         out = torch.empty(max(m, 1), dtype=adt, device=x.device)[:m]
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_AFFINITY, n, m, k, x.dtype), x.device)
-    _check(lib().sfg_affinity(_ptr(x), _dt(x), n, k, m, _ptr(u), _ptr(v), _ptr(out), _dt(out), _ptr(ws),
-                              ws.numel(), _stream()))
+    _check(lib().sfg_affinity(_ptr(x), _dt(x), n, k, m, _ptr(u), _ptr(v), _ptr(out, "out", _W, m), _dt(out),
+                              _ptr(ws, "ws", _U8), ws.numel(), _stream()))
     return out
 
 
 def sfg_coarsen(G: Csr, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, aff: torch.Tensor,
                 ws: Optional[torch.Tensor] = None):
     """One coarsening step.  Returns (agg, cu, cv, cw, crep) trimmed to the coarse sizes."""
-    m = int(u.shape[0])
+    m = _edges(u, v, w)
+    _chk(aff, "aff", _W, m)
     dev = u.device
     agg = torch.empty(G.n, dtype=torch.int32, device=dev)
     cu = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
@@ -376,7 +471,7 @@ def sfg_coarsen(G: Csr, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, aff: 
     gs = G.struct()
     _check(lib().sfg_coarsen(ctypes.byref(gs), m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(aff), _dt(aff),
                              _ptr(agg), ctypes.byref(nc), ctypes.byref(mc), _ptr(cu), _ptr(cv), _ptr(cw),
-                             _ptr(crep), _ptr(ws), ws.numel(), _stream()))
+                             _ptr(crep), _ptr(ws, "ws", _U8), ws.numel(), _stream()))
     mc = int(mc.value)
     return agg, int(nc.value), cu[:mc], cv[:mc], cw[:mc], crep[:mc]
 
@@ -408,12 +503,18 @@ def sfg_sparsify(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, x0: 
     """Sparsifier keep mask (0 off, 1 base sparsifier, 2 recovered) and the per-level report.
     x0 None: the random blocks are drawn on the device from params.seed.  ``info`` (a dict)
     receives the condition-number estimates of sigma mode."""
-    m = int(u.shape[0])
+    m = _edges(u, v, w)
     if keep is None:
         keep = torch.empty(max(m, 1), dtype=torch.uint8, device=u.device)[:m]
+    # x0 holds one n-by-k block per level, per round, or per batch of sigma mode (as the library reads it)
+    blocks = (params.levels if params.levels > 1 else
+              (params.rounds if params.rounds > 0 else 16) if params.sigma > 0 else max(params.rounds, 1))
+    _chk(x0, "x0", _F64, blocks * n * params.k, optional=True)
+    _chk(keep, "keep", _U8, m)
     rep = Report()
-    _check(lib().sfg_sparsify(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), ctypes.byref(params), _ptr(x0),
-                              _ptr(keep), ctypes.byref(rep), _stream()))
+    _check(lib().sfg_sparsify(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), ctypes.byref(params),
+                              _ptr(x0, "x0", _F64, blocks * n * params.k, optional=True),
+                              _ptr(keep, "keep", _U8, m), ctypes.byref(rep), _stream()))
     levels = []
     for i in range(rep.levels):
         L = rep.level[i]
@@ -435,14 +536,18 @@ class Tree:
         self.pw, self.tdown, self.tup = pw, tdown, tup
 
     def struct(self) -> TreeStruct:
-        return TreeStruct(self.n, self.order.data_ptr(), self.parent.data_ptr(), self.size.data_ptr(),
-                          self.pw.data_ptr(), self.tdown.data_ptr(), self.tup.data_ptr())
+        n = self.n
+        ptrs = _ptrs((self.order, "tree.order", _I32, n), (self.parent, "tree.parent", _I32, n),
+                     (self.size, "tree.size", _I32, n), (self.pw, "tree.pw", _F64, n),
+                     (self.tdown, "tree.tdown", _I32, n), (self.tup, "tree.tup", _I32, n))
+        return TreeStruct(n, *(p.value for p in ptrs))
 
 
 def sfg_tree_order(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, keep: torch.Tensor) -> Tree:
     """Preorder layout of the spanning tree of the edges with keep == 1 (w must be float64)."""
     dev = u.device
-    m = int(u.shape[0])
+    m = _edges(u, v, w)
+    _chk(keep, "keep", _U8, m)
     arr = [torch.empty(n, dtype=torch.int32, device=dev) for _ in range(5)]
     pw = torch.empty(n, dtype=torch.float64, device=dev)
     ws = _ws(sfg_workspace_bytes(OP_TREE_ORDER, n, m, 0, F64), dev)
@@ -455,6 +560,8 @@ def sfg_tree_order(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, ke
 def sfg_tree_solve(tree: Tree, b: torch.Tensor, out: Optional[torch.Tensor] = None,
                    ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     """x = L_T^+ b per column (b: n-by-k float64, node order)."""
+    if int(b.shape[0]) != tree.n:
+        raise ValueError(f"b: has {int(b.shape[0])} rows, the tree has {tree.n} nodes")
     b2 = b.reshape(b.shape[0], -1)
     k = int(b2.shape[1])
     if out is None:
@@ -462,7 +569,8 @@ def sfg_tree_solve(tree: Tree, b: torch.Tensor, out: Optional[torch.Tensor] = No
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_TREE_SOLVE, tree.n, 0, k, F64), b.device)
     ts = tree.struct()
-    _check(lib().sfg_tree_solve(ctypes.byref(ts), k, _ptr(b2), _ptr(out), _ptr(ws), ws.numel(), _stream()))
+    _check(lib().sfg_tree_solve(ctypes.byref(ts), k, _ptr(b2, "b", _F64, tree.n * k),
+                                _ptr(out, "out", _F64, tree.n * k), _ptr(ws, "ws", _U8), ws.numel(), _stream()))
     return out.reshape(b.shape)
 
 
@@ -470,11 +578,13 @@ def sfg_pcg(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor, keep: tor
             tol: float = 1e-3, max_iter: int = 20000, want_x: bool = True):
     """CG on L_G x = b grounded at node 0, preconditioned by the sparsifier ``keep`` (its tree marked 1).
     Returns (x or None, report dict)."""
-    m = int(u.shape[0])
+    m = _edges(u, v, w)
     x = torch.empty(n, dtype=torch.float64, device=b.device) if want_x else None
     rep = PcgReport()
-    _check(lib().sfg_pcg(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(keep), _ptr(b.to(torch.float64).contiguous()),
-                         _ptr(x), float(tol), int(max_iter), ctypes.byref(rep), _stream()))
+    b64 = b.to(torch.float64).contiguous()
+    _check(lib().sfg_pcg(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(keep, "keep", _U8, m),
+                         _ptr(b64, "b", _F64, n), _ptr(x, optional=True), float(tol), int(max_iter),
+                         ctypes.byref(rep), _stream()))
     return x, {f: getattr(rep, f) for f, _ in PcgReport._fields_}
 
 
@@ -482,12 +592,14 @@ def sfg_kappa_estimate(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor
                        params: Optional[KappaParams] = None, y0: Optional[torch.Tensor] = None):
     """Estimate of kappa(L_G, L_P) for P = edges with keep != 0 (tree edges marked 1).
     Returns (kappa, report dict)."""
-    m = int(u.shape[0])
+    m = _edges(u, v, w)
     kp = params if params is not None else make_kappa_params()
     kap = ctypes.c_double(0.0)
     rep = KappaReport()
-    _check(lib().sfg_kappa_estimate(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(keep), ctypes.byref(kp),
-                                    _ptr(y0), ctypes.byref(kap), ctypes.byref(rep), _stream()))
+    kb = kp.k if kp.k > 0 else 8
+    _check(lib().sfg_kappa_estimate(n, m, _ptr(u), _ptr(v), _ptr(w), _dt(w), _ptr(keep, "keep", _U8, m),
+                                    ctypes.byref(kp), _ptr(y0, "y0", _F64, n * kb, optional=True),
+                                    ctypes.byref(kap), ctypes.byref(rep), _stream()))
     steps = int(rep.steps)
     return float(kap.value), {"ritz": [float(rep.ritz[i]) for i in range(min(steps, 64))],
                               "inner_iters": int(rep.inner_iters), "max_inner": int(rep.max_inner),
@@ -500,16 +612,33 @@ def sfg_mpnn_param_count() -> int:
     return int(lib().sfg_mpnn_param_count())
 
 
+def _mpnn_args(G: Csr, params, node_feat, u, v, edge_feat, cand, ne: int) -> None:
+    """Checks shared by inference and training: parameter vector, n-by-8 node and ne-by-4 edge features."""
+    _chk(params, "params", _F32, sfg_mpnn_param_count())
+    _chk(node_feat, "node_feat", _F32, G.n * 8)
+    _chk(edge_feat, "edge_feat", _F32, ne * 4)
+    m = _edges(u, v)
+    _chk(cand, "cand", _I32, ne, optional=True)
+    if cand is None and ne > m:
+        raise ValueError(f"edge_feat: {ne} rows, the edge list has {m} edges")
+
+
 def sfg_mpnn_features(G: Csr, T: Csr, xc: torch.Tensor, u: torch.Tensor, v: torch.Tensor, w32: torch.Tensor,
                       cand: Optional[torch.Tensor] = None, norm: Optional[torch.Tensor] = None):
     """Node (n x 8) and candidate-edge (ne x 4) features of the surrogate."""
-    n, kc = int(xc.shape[0]), int(xc.shape[1])
-    ne = int(cand.shape[0]) if cand is not None else int(u.shape[0])
+    n, kc = _block(xc, "xc", _F32, rows=G.n)
+    m = _edges(u, v, w32)
+    if w32.dtype != torch.float32:
+        raise ValueError("w32: the surrogate takes F32 weights")
+    ne = int(cand.numel()) if cand is not None else m
+    _chk(cand, "cand", _I32, ne, optional=True)
+    _chk(norm, "norm", _F32, 24, optional=True)
     nf = torch.empty((n, 8), dtype=torch.float32, device=xc.device)
     ef = torch.empty((max(ne, 1), 4), dtype=torch.float32, device=xc.device)[:ne]
     gs, ts = G.struct(), T.struct()
-    _check(lib().sfg_mpnn_features(ctypes.byref(gs), ctypes.byref(ts), _ptr(xc), kc, ne, _ptr(cand), _ptr(u),
-                                   _ptr(v), _ptr(w32), _ptr(norm), _ptr(nf), _ptr(ef), _stream()))
+    _check(lib().sfg_mpnn_features(ctypes.byref(gs), ctypes.byref(ts), _ptr(xc), kc, ne,
+                                   _ptr(cand, optional=True), _ptr(u), _ptr(v), _ptr(w32),
+                                   _ptr(norm, optional=True), _ptr(nf), _ptr(ef), _stream()))
     return nf, ef
 
 
@@ -517,13 +646,16 @@ def sfg_mpnn_forward(G: Csr, params: torch.Tensor, node_feat: torch.Tensor, u: t
                      edge_feat: torch.Tensor, cand: Optional[torch.Tensor] = None, act=torch.bfloat16,
                      out: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None) -> torch.Tensor:
     ne = int(edge_feat.shape[0])
+    _mpnn_args(G, params, node_feat, u, v, edge_feat, cand, ne)
     if out is None:
         out = torch.empty(max(ne, 1), dtype=torch.float32, device=params.device)[:ne]
+    _chk(out, "out", _F32, ne)
     a = _TORCH_TO_SFG[act]
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_MPNN_FORWARD, G.n, 0, 0, a), params.device)
     gs = G.struct()
-    _check(lib().sfg_mpnn_forward(ctypes.byref(gs), _ptr(params), _ptr(node_feat), ne, _ptr(cand), _ptr(u), _ptr(v),
+    _check(lib().sfg_mpnn_forward(ctypes.byref(gs), _ptr(params), _ptr(node_feat), ne,
+                                  _ptr(cand, optional=True), _ptr(u), _ptr(v),
                                   _ptr(edge_feat), a, _ptr(out), _ptr(ws), ws.numel(), _stream()))
     return out
 
@@ -533,6 +665,10 @@ def sfg_mpnn_loss_grad(G: Csr, params: torch.Tensor, node_feat: torch.Tensor, u:
                        ws: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None):
     """FP32 forward + backward.  Returns (pred, loss (device scalar), grad)."""
     ne = int(edge_feat.shape[0])
+    _mpnn_args(G, params, node_feat, u, v, edge_feat, cand, ne)
+    _chk(target, "target", _F32, ne)
+    if grad is not None:
+        _chk(grad, "grad", _F32, sfg_mpnn_param_count())
     dev = params.device
     pred = torch.empty(ne, dtype=torch.float32, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)
@@ -541,7 +677,8 @@ def sfg_mpnn_loss_grad(G: Csr, params: torch.Tensor, node_feat: torch.Tensor, u:
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_MPNN_TRAIN, G.n, ne, 0, F32), dev)
     gs = G.struct()
-    _check(lib().sfg_mpnn_loss_grad(ctypes.byref(gs), _ptr(params), _ptr(node_feat), ne, _ptr(cand), _ptr(u), _ptr(v),
+    _check(lib().sfg_mpnn_loss_grad(ctypes.byref(gs), _ptr(params), _ptr(node_feat), ne,
+                                    _ptr(cand, optional=True), _ptr(u), _ptr(v),
                                     _ptr(edge_feat), _ptr(target), _ptr(pred), _ptr(loss), _ptr(grad), _ptr(ws),
                                     ws.numel(), _stream()))
     return pred, loss, grad
@@ -549,5 +686,8 @@ def sfg_mpnn_loss_grad(G: Csr, params: torch.Tensor, node_feat: torch.Tensor, u:
 
 def sfg_mpnn_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int,
                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    n = params.numel()
+    for name, t in (("params", params), ("grad", grad), ("m", m), ("v", v)):
+        _chk(t, name, _F32, n)
     _check(lib().sfg_mpnn_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(params.numel()), int(step),
                                float(lr), float(beta1), float(beta2), float(eps), _stream()))
