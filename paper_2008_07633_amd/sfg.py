@@ -193,11 +193,11 @@ def _ptr(t: Optional[torch.Tensor], name: str = "tensor", dtypes=None, numel: Op
 
 
 def _ptrs(*specs) -> list:
-    """Pointers of several (tensor, name, dtypes, numel) arguments: every one
-    is checked by :func:`_chk` before any is checked for its device."""
-    for t, name, dts, cnt in specs:
-        _chk(t, name, dts, cnt)
-    return [_ptr(t, name, dts, cnt) for t, name, dts, cnt in specs]
+    """Pointers of several (tensor, name, dtypes, numel[, optional]) arguments:
+    every one is checked by :func:`_chk` before any is checked for its device."""
+    for spec in specs:
+        _chk(*spec)
+    return [_ptr(*spec) for spec in specs]
 
 
 def _block(x: torch.Tensor, name: str, dtypes, rows: Optional[int] = None) -> tuple[int, int]:
@@ -259,9 +259,9 @@ class Csr:
         """The C view, after checking every array against n and nnz."""
         n, nnz = int(self.n), int(self.nnz)
         ptrs = _ptrs((self.rowptr, "csr.rowptr", _I32, n + 1), (self.col, "csr.col", _I32, nnz),
-                     (self.val, "csr.val", _W, nnz), (self.eid, "csr.eid", _I32, nnz),
+                     (self.val, "csr.val", _W, nnz), (self.eid, "csr.eid", _I32, nnz, True),
                      (self.deg, "csr.deg", (self.val.dtype,), n))
-        return CsrStruct(n, nnz, *(p.value for p in ptrs), _TORCH_TO_SFG[self.val.dtype])
+        return CsrStruct(n, nnz, *(None if p is None else p.value for p in ptrs), _TORCH_TO_SFG[self.val.dtype])
 
 
 def sfg_laplacian_csr(n: int, u: torch.Tensor, v: torch.Tensor, w: torch.Tensor,

@@ -330,7 +330,8 @@ def test_sparsify_rounds_precision_form(S, orc, monkeypatch):
 
 def test_sparsify_rounds_errors(S):
     g = W.grid2d(10, 10, seed=97)
-    X0 = dev(W.random_block(g.n, 4, 98))
+    # room for every block the parameters name, so the library itself rejects them
+    X0 = dev(np.stack([W.random_block(g.n, 4, 98 + r) for r in range(17)]))
     for kw in ({"rounds": 17}, {"rounds": -1}, {"rounds": 2, "levels": 2}):
         with pytest.raises(S.SfgError):
             S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), X0, S.make_params(k=4, sweeps=3, frac=0.1, **kw))

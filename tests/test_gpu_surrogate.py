@@ -261,6 +261,8 @@ def test_surrogate_in_the_library_falls_back_and_checks(S, SG):
                        ({"cand_frac": 1.5}, "SFG_EINVAL"), ({"k": 2}, "SFG_EINVAL")):
         args = dict(k=8, sweeps=6, frac=0.1, storage=torch.float32, surrogate=good)
         args.update(kw)
+        x = X0 if args["k"] == 8 else X0[:, :args["k"]].contiguous()
+        # room for every block the parameters name, so the library itself rejects them
+        x = torch.cat([x.reshape(-1)] * 2)
         with pytest.raises(S.SfgError, match=status):
-            S.sfg_sparsify(g.n, u, v, w, X0 if args["k"] == 8 else X0[:, :args["k"]].contiguous(),
-                           S.make_params(**args))
+            S.sfg_sparsify(g.n, u, v, w, x, S.make_params(**args))
