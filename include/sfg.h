@@ -246,6 +246,28 @@ sfg_status sfg_select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t 
                            double *tau, double *tau_host, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * sfg_select_topk without a workspace and without any allocation, for callers
+ * that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments (minus the
+ * workspace), same kernels, same results.  Its scratch (selection state,
+ * digit histogram, tie flags and ranks, scan partials) is a device array of
+ * 128 MiB (134217728 bytes) in the library, one copy per GPU, held from the
+ * first call on that GPU until the process ends.  The first call on a device
+ * looks up that copy's address (hipGetSymbolAddress) with the device current;
+ * later calls only launch kernels.  The current device must be the one that
+ * `stream` belongs to.
+ *   ne     accepted while sfg_workspace_bytes(SFG_OP_SELECT_TOPK, 0, ne, 0,
+ *          st) <= 134217728, i.e. up to about 16.7 million scores
+ * Every call on a GPU uses that GPU's one array, and each call clears what it
+ * needs: calls that overlap on one GPU (two streams, or two host threads)
+ * race on it and must be serialised by the caller.
+ * Errors: SFG_EUNSUPPORTED when ne is above the limit (nothing is launched),
+ * otherwise those of sfg_select_topk.
+ */
+sfg_status sfg_select_topk_noalloc(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel,
+                                   double *tau, double *tau_host, void *stream);
+
+/*
  * Maximum-weight spanning tree (the MST the paper uses in place of a
  * low-stretch tree, Sec. 3.4): the unique tree that Kruskal's rule picks
  * under the order (weight descending, edge id ascending).

@@ -96,6 +96,10 @@ inline bool valid_dtype(int t) { return t >= SFG_F64 && t <= SFG_BF16; }
 
 constexpr int kWave = 64;
 constexpr int kNumXcd = 8;
+constexpr int kMaxDevices = 64;
+
+// Size of the per-device scratch array of sfg_select_topk_noalloc.
+constexpr size_t kSelectNoallocBytes = size_t(128) << 20;
 
 // Workgroups are dealt round-robin to the 8 XCDs; remap so that each XCD
 // walks one contiguous range of logical blocks (neighbouring rows share that

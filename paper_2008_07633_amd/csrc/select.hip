@@ -8,7 +8,15 @@
 // fixed so far, then one workgroup picks the digit that contains rank k.  Passes stay on the device (no host round trips).
 // Ties at the threshold take the lowest positions: a scan over the tie flags
 // gives each tied key its rank.
+#include <mutex>
+
 #include "common.hpp"
+
+// Scratch of sfg_select_topk_noalloc: a device array of fixed size, one copy
+// per GPU, held until the process ends.  In host code this name stands for a
+// host-side shadow, not a device address: host code only ever passes it to
+// hipGetSymbolAddress and uses the address that returns.
+static __device__ __align__(256) unsigned char scratch[sfg::kSelectNoallocBytes];
 
 namespace sfg {
 
@@ -259,17 +267,58 @@ void select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t
         run_select<float>((const float *)score, ne, k, sel, tau, p, s);
 }
 
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this GPU's copy of `scratch`, looked up once per device
+// with the device current.
+void *select_scratch() {
+    int dev = 0;
+    SFG_HIP(hipGetDevice(&dev));
+    SFG_REQUIRE(dev >= 0 && dev < kMaxDevices, SFG_EUNSUPPORTED, "select_topk_noalloc: device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        SFG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        SFG_REQUIRE(p != nullptr, SFG_EHIP, "select_topk_noalloc: no device address for the scratch array");
+        g_scratch_dev[dev] = p;
+    }
+    return g_scratch_dev[dev];
+}
+
+void tau_to_host(const double *tau, double *tau_host, hipStream_t s) {
+    SFG_HIP(hipMemcpyAsync(tau_host, tau, sizeof(double), hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    if (*tau_host != *tau_host) fail(SFG_ENUMERIC, "select_topk: NaN or negative score");
+}
+
+}  // namespace
+
 }  // namespace sfg
+
+extern "C" sfg_status sfg_select_topk_noalloc(const void *score, sfg_dtype st, int64_t ne, int64_t k,
+                                              uint8_t *sel, double *tau, double *tau_host, void *stream) {
+    return sfg::guard([&] {
+        hipStream_t s = sfg::as_stream(stream);
+        SFG_REQUIRE(ne >= 0 && k >= 0 && k <= ne, SFG_EINVAL, "select_topk_noalloc: need 0 <= k <= ne");
+        const size_t need = sfg::select_workspace_bytes(ne);
+        SFG_REQUIRE(need <= sfg::kSelectNoallocBytes, SFG_EUNSUPPORTED,
+                    "select_topk_noalloc: " + std::to_string(ne) + " scores need " + std::to_string(need) +
+                        " bytes of scratch, above the " + std::to_string(sfg::kSelectNoallocBytes) +
+                        " the library holds per device (use sfg_select_topk with a workspace)");
+        void *ws = sfg::select_scratch();
+        sfg::select_topk(score, st, ne, k, sel, tau, ws, sfg::kSelectNoallocBytes, s);
+        if (tau_host) sfg::tau_to_host(tau, tau_host, s);
+    });
+}
 
 extern "C" sfg_status sfg_select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t k, uint8_t *sel,
                                       double *tau, double *tau_host, void *ws, size_t ws_bytes, void *stream) {
     return sfg::guard([&] {
         hipStream_t s = sfg::as_stream(stream);
         sfg::select_topk(score, st, ne, k, sel, tau, ws, ws_bytes, s);
-        if (tau_host) {
-            SFG_HIP(hipMemcpyAsync(tau_host, tau, sizeof(double), hipMemcpyDeviceToHost, s));
-            SFG_HIP(hipStreamSynchronize(s));
-            if (*tau_host != *tau_host) sfg::fail(SFG_ENUMERIC, "select_topk: NaN or negative score");
-        }
+        if (tau_host) sfg::tau_to_host(tau, tau_host, s);
     });
 }

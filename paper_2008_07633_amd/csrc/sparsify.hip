@@ -84,7 +84,6 @@ namespace {
 
 constexpr size_t kChunkBytes = size_t(256) << 20;
 constexpr size_t kCacheBytes = size_t(16) << 30;
-constexpr int kMaxDevices = 64;
 
 std::mutex g_cache_mu;
 std::vector<DevArena::Chunk> g_cache[kMaxDevices];

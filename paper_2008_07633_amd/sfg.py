@@ -37,7 +37,7 @@ EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_s
             "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify",
             "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam",
             "sfg_color", "sfg_smooth_gs", "sfg_random_block", "sfg_tree_order", "sfg_tree_solve",
-            "sfg_kappa_estimate", "sfg_csr_select", "sfg_pcg"]
+            "sfg_kappa_estimate", "sfg_csr_select", "sfg_pcg", "sfg_select_topk_noalloc"]
 
 
 class SfgError(RuntimeError):
@@ -124,6 +124,7 @@ def lib() -> ctypes.CDLL:
         L.sfg_smooth.argtypes = [P, I32, I32, D, P, I, I32, P, P, S, P]
         L.sfg_edge_scores.argtypes = [P, I, I64, I32, I64, P, P, P, P, I, P, I, P]
         L.sfg_select_topk.argtypes = [P, I, I64, I64, P, P, P, P, S, P]
+        L.sfg_select_topk_noalloc.argtypes = [P, I, I64, I64, P, P, P, P]
         L.sfg_spanning_tree.argtypes = [I64, I64, P, P, P, I, P, P, P, P]
         L.sfg_affinity.argtypes = [P, I, I64, I32, I64, P, P, P, I, P, S, P]
         L.sfg_coarsen.argtypes = [P, I64, P, P, P, I, P, I, P, P, P, P, P, P, P, P, S, P]
@@ -425,6 +426,25 @@ def sfg_select_topk(score: torch.Tensor, k: int, sel: Optional[torch.Tensor] = N
     _check(lib().sfg_select_topk(_ptr(score), _dt(score), ne, int(k), _ptr(sel, "sel", _U8, ne),
                                  _ptr(tau, "tau", _F64, 1), ctypes.byref(th) if sync else None,
                                  _ptr(ws, "ws", _U8), ws.numel(), _stream()))
+    return sel, (th.value if sync else tau)
+
+
+def sfg_select_topk_noalloc(score: torch.Tensor, k: int, sel: Optional[torch.Tensor] = None,
+                            tau: Optional[torch.Tensor] = None, sync: bool = True):
+    """sfg_select_topk on the library's per-device scratch array: no workspace, nothing allocated by
+    the library (pass ``sel`` and ``tau`` to allocate nothing at all).  Returns (sel, tau)."""
+    _chk(score, "score", _W)
+    ne = int(score.numel())
+    dev = score.device
+    if sel is None:
+        sel = torch.empty(max(ne, 1), dtype=torch.uint8, device=dev)[:ne]
+    if tau is None:
+        tau = torch.empty(1, dtype=torch.float64, device=dev)
+    _chk(sel, "sel", _U8, ne)
+    _chk(tau, "tau", _F64, 1)
+    th = ctypes.c_double(0.0)
+    _check(lib().sfg_select_topk_noalloc(_ptr(score), _dt(score), ne, int(k), _ptr(sel), _ptr(tau),
+                                         ctypes.byref(th) if sync else None, _stream()))
     return sel, (th.value if sync else tau)
 
 
