@@ -25,7 +25,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sfg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-_CFLAGS = ["-O3", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99",
+_CFLAGS = ["-O3", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99", "-fopenmp",
            "-Wall", "-Wextra"]
 
 
@@ -83,8 +83,23 @@ def _L():
         lib.orc_exact_sum.restype = D
         lib.orc_center.argtypes = [I64, I32, P, P]
         lib.orc_center.restype = None
+        lib.orc_set_threads.argtypes = [I32]
+        lib.orc_set_threads.restype = None
+        lib.orc_max_threads.argtypes = []
+        lib.orc_max_threads.restype = I32
         _lib = lib
     return _lib
+
+
+def set_threads(t: int) -> None:
+    """Threads of the row- and edge-parallel loops (smoothing sweeps, scores).
+    Each row or edge is computed by one thread in a fixed order, so results
+    are the same bits for any count."""
+    _L().orc_set_threads(int(t))
+
+
+def max_threads() -> int:
+    return int(_L().orc_max_threads())
 
 
 def _p(a: Optional[np.ndarray]):

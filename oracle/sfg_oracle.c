@@ -16,6 +16,30 @@
 #include <stdlib.h>
 #include <string.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Rows (and edges) are independent within a sweep (or a scoring pass), and  */
+/* each one is computed by one thread in the fixed order written below, so   */
+/* the results are bit-identical for any number of threads.                  */
+void orc_set_threads(int32_t t)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(t > 0 ? t : 1);
+#else
+    (void)t;
+#endif
+}
+
+int32_t orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return (int32_t)omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* ------------------------------------------------------------------------ */
 /* Graph Laplacian (Sec. 2.1, Eq. 1 and the definition L = D - A that        */
@@ -70,6 +94,7 @@ void orc_smooth(int64_t n, const int64_t *rowptr, const int32_t *col, const doub
 {
     const double keep = 1.0 - omega;
     for (int32_t t = 0; t < sweeps; ++t) {
+#pragma omp parallel for schedule(static)
         for (int64_t p = 0; p < n; ++p) {
             for (int32_t c = 0; c < k; ++c) {
                 double s = 0.0;
@@ -218,6 +243,7 @@ void orc_smooth_masked(int64_t n, const int64_t *rowptr, const int32_t *col, con
 void orc_edge_scores(int32_t k, const double *X, int64_t ne, const int32_t *u, const int32_t *v,
                      const double *w, double *score)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t e = 0; e < ne; ++e) {
         double acc = 0.0;
         for (int32_t c = 0; c < k; ++c) {

@@ -827,3 +827,25 @@ def test_sigma_stopping(orc):
     # the round cap bounds the additions
     res2, kap2 = orc.sparsify_sigma(n, g.u, g.v, g.w, X0s, Y0s, 1.0, frac, 2, sweeps, est)
     assert len(res2.levels) == 2 and len(kap2) == 3
+
+
+# --------------------------------------------------------------------------- threads
+
+def test_threads_give_the_same_bits(orc):
+    """Smoothing rows and edge scores are split over threads; each row or edge
+    is one thread's work in the fixed order, so any thread count gives the same
+    bits (the CPU baseline is timed on one thread and on all host cores)."""
+    g = W.powergrid(60, 70, 0.02, seed=91)
+    intree, _ = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    t = intree.astype(bool)
+    H = orc.laplacian_csr(g.n, g.u[t], g.v[t], g.w[t])
+    Xc, _ = orc.center(W.random_block(g.n, 16, 92))
+    cand = np.nonzero(~t)[0]
+    out = []
+    for threads in (1, 3, max(orc.max_threads(), 2)):
+        orc.set_threads(threads)
+        X = orc.smooth(H, Xc, 12)
+        out.append((X, orc.edge_scores(X, g.u[cand], g.v[cand], g.w[cand])))
+    orc.set_threads(orc.max_threads())
+    for X, s in out[1:]:
+        assert np.array_equal(X, out[0][0]) and np.array_equal(s, out[0][1])
