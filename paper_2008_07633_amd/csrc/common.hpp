@@ -130,9 +130,29 @@ template <> __device__ __forceinline__ __half cvt<__half, float>(float x) { retu
 template <> __device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16, float>(float x) {
     return __float2bfloat16(x);
 }
-template <> __device__ __forceinline__ __half cvt<__half, double>(double x) { return __float2half((float)x); }
+// FP64 to FP16 / BF16 with one rounding.  Rounding to float first and then to
+// the 16-bit type rounds twice and can land one unit off (a double just above
+// a 16-bit midpoint can round to that midpoint in float, then tie to even).
+// Rounding to float toward zero and setting the last bit when anything was
+// dropped ("round to odd") keeps the information the second rounding needs:
+// with at least two extra significand bits in the intermediate format (float
+// has 13 more than FP16 and 16 more than BF16, also in their subnormal ranges)
+// the round to nearest even that follows gives the correctly rounded result
+// (Boldo and Melquiond, "Emulation of FMA and correctly rounded sums: proved
+// algorithms using rounding to odd", IEEE Trans. Computers 57(4), 2008).
+__device__ __forceinline__ float round_to_odd_float(double x) {
+    float f = (float)x;
+    // rounded away from zero (also to infinity on overflow): one step back toward zero, which for a
+    // sign-magnitude encoding is the bit pattern minus one
+    if (__builtin_fabs((double)f) > __builtin_fabs(x)) f = __uint_as_float(__float_as_uint(f) - 1u);
+    if ((double)f != x && f == f) f = __uint_as_float(__float_as_uint(f) | 1u);
+    return f;
+}
+template <> __device__ __forceinline__ __half cvt<__half, double>(double x) {
+    return __float2half(round_to_odd_float(x));
+}
 template <> __device__ __forceinline__ __hip_bfloat16 cvt<__hip_bfloat16, double>(double x) {
-    return __float2bfloat16((float)x);
+    return __float2bfloat16(round_to_odd_float(x));
 }
 template <> __device__ __forceinline__ double cvt<double, __half>(__half x) { return (double)__half2float(x); }
 template <> __device__ __forceinline__ double cvt<double, __hip_bfloat16>(__hip_bfloat16 x) {

@@ -123,3 +123,44 @@ def test_band_always_holds_the_threshold(S, orc, monkeypatch):
         r = rep[0]
         assert r["band_rounds"] == 0 and r["band"] >= 1, r
         assert 1 <= r["k_sel"] - r["band_above"] <= r["band"], r
+
+
+def _rne(x: float, bits: int) -> float:
+    """x rounded to nearest even with `bits` significant bits (normal range, no overflow): exact, since
+    m * 2^bits is exact in FP64 and Python's round() ties to even."""
+    import math
+
+    m, e = math.frexp(x)
+    return math.ldexp(round(m * 2.0 ** bits), e - bits)
+
+
+@pytest.mark.parametrize("dt,bits", [(torch.float16, 11), (torch.bfloat16, 8)])
+def test_fp64_to_16bit_storage_rounds_once(S, dt, bits):
+    """The centred FP64 block is stored in FP16/BF16 with one rounding.  Values a quarter of a float unit
+    beside a 16-bit midpoint round to that midpoint in float, so a conversion through float would tie to
+    even and land one unit off in half of these cases."""
+    import math
+
+    rng = np.random.default_rng(404)
+    vals = []
+    for _ in range(400):
+        m = 1.0 + rng.integers(0, 2 ** (bits - 1)) * 2.0 ** (1 - bits)       # a 16-bit grid point in [1, 2)
+        e = int(rng.integers(-10, 10))
+        h = math.ldexp(m, e)
+        ulp = math.ldexp(1.0, e + 1 - bits)
+        tiny = math.ldexp(1.0, e - 24) / 4                                       # a quarter of a float unit
+        for x in (h + ulp / 2 + tiny, h + ulp / 2 - tiny, h + ulp / 2, h + tiny, h - tiny / 2):
+            vals.append(x if rng.random() < 0.5 else -x)
+    vals = np.array(vals)
+    col = np.concatenate([vals, -vals])              # the column sums to exactly 0, so its mean is 0
+    n = col.size
+    x0 = np.stack([col, col[::-1].copy()], axis=1)
+    g = W.grid2d(1, n, seed=1)
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w.astype(np.float32)))    # 16-bit storage: F32 graph
+    got = S.sfg_smooth(H, dev(x0), 0, storage=dt).float().cpu().numpy().astype(np.float64)
+    want = np.vectorize(lambda x: _rne(x, bits))(x0)
+    bad = np.nonzero(got != want)
+    assert bad[0].size == 0, (x0[bad][:5], got[bad][:5], want[bad][:5])
+    # the cases where rounding through float goes wrong are really there
+    via_float = np.vectorize(lambda x: _rne(float(np.float32(x)), bits))(x0)
+    assert (via_float != want).sum() > 100
