@@ -81,7 +81,8 @@ typedef enum {
     SFG_OP_COLOR = 7,          /* n nodes */
     SFG_OP_TREE_ORDER = 8,     /* n nodes, m edges */
     SFG_OP_TREE_SOLVE = 9,     /* n nodes, k columns */
-    SFG_OP_CSR_SELECT = 10     /* n nodes, m = edges of the whole graph */
+    SFG_OP_CSR_SELECT = 10,    /* n nodes, m = edges of the whole graph */
+    SFG_OP_MPNN_NORM = 11      /* no sizes: a fixed 512 bytes */
 } sfg_op;
 
 /* Which graph's embedding scores the candidates (Sec. 3.5 derives the score
@@ -599,6 +600,52 @@ sfg_status sfg_mpnn_loss_grad(const sfg_csr *G, const float *params, const float
  * params, m, v (all F32, n values). */
 sfg_status sfg_mpnn_adam(float *params, const float *grad, float *m, float *v, int64_t n, int64_t step,
                          double lr, double beta1, double beta2, double eps, void *stream);
+
+/* Standardisation of a training set of `ngraphs` graphs (host arrays of
+ * device pointers): per column, the mean and the population standard
+ * deviation over all rows of all graphs, summed in FP64 in a fixed order
+ * (deterministic), in two passes (means, then squared deviations).
+ *   node_feat[i]  device n_i x 8 F32 raw node features (sfg_mpnn_features with
+ *                 norm = NULL), node_rows[i] = n_i >= 1
+ *   edge_feat[i]  device e_i x 4 F32 raw edge features; target[i] device e_i F32
+ *                 targets; edge_rows[i] = e_i >= 1
+ *   norm          out, device 24 F32 in the layout sfg_mpnn_features takes:
+ *                 node means, node 1/max(std, 1e-6), edge means, edge
+ *                 1/max(std, 1e-6); node feature 0 (the constant) gets 0 and 1
+ *   ystat         out, device 2 doubles: target mean and standard deviation (1
+ *                 when every target is equal)
+ *   ws            >= sfg_workspace_bytes(SFG_OP_MPNN_NORM, 0, 0, 0, 0) bytes
+ * Errors: SFG_EINVAL, SFG_EWORKSPACE. */
+sfg_status sfg_mpnn_fit_norm(int32_t ngraphs, const float *const *node_feat, const int64_t *node_rows,
+                             const float *const *edge_feat, const float *const *target, const int64_t *edge_rows,
+                             float *norm, double *ystat, void *ws, size_t ws_bytes, void *stream);
+
+/* out[i] = (y[i] - ystat[0]) / ystat[1], in FP64 and rounded to F32 (the
+ * standardised training targets); out may alias y. */
+sfg_status sfg_mpnn_standardize(const float *y, int64_t n, const double *ystat, float *out, void *stream);
+
+/* What a model file records besides its parameters and normalisation. */
+typedef struct {
+    int32_t kc;            /* vectors of the cheap embedding, 1..64 */
+    int32_t tc;            /* its sweeps, 0..1000 */
+    double y_mean, y_std;  /* target standardisation the model was trained with */
+} sfg_mpnn_meta;
+
+/* Model file of the surrogate, so that a C caller can store and reuse a
+ * trained model.  Version 1, little-endian: magic "SFGMPNN1"; uint32 version,
+ * parameter count, normalisation count (24); int32 kc, tc; uint32 0; double
+ * y_mean, y_std; the F32 parameters (sfg_mpnn_param_count()) and the 24 F32
+ * normalisation values; then the 64-bit FNV-1a hash of every byte before it.
+ *   params, norm   device F32 arrays (read by save, written by load)
+ *   meta           host
+ * Both synchronise.  sfg_mpnn_load checks the magic, the version, the shapes,
+ * the length, the hash, the cheap-embedding ranges and that every value is
+ * finite, and writes nothing to the outputs unless all hold.
+ * Errors: SFG_EINVAL (unreadable or unwritable file, or a failed check; the
+ * message says which), SFG_EHIP. */
+sfg_status sfg_mpnn_save(const char *path, const float *params, const float *norm, const sfg_mpnn_meta *meta,
+                         void *stream);
+sfg_status sfg_mpnn_load(const char *path, float *params, float *norm, sfg_mpnn_meta *meta, void *stream);
 
 #ifdef __cplusplus
 }

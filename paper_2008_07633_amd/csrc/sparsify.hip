@@ -830,6 +830,7 @@ extern "C" size_t sfg_workspace_bytes(int op, int64_t n, int64_t m, int32_t k, s
         case SFG_OP_TREE_ORDER: return sfg::tree_order_workspace_bytes(n < 1 ? 1 : n, m < 0 ? 0 : m);
         case SFG_OP_TREE_SOLVE: return sfg::tree_solve_workspace_bytes(n < 1 ? 1 : n, k < 1 ? 1 : k);
         case SFG_OP_CSR_SELECT: return sfg::csr_select_workspace_bytes(n, m);
+        case SFG_OP_MPNN_NORM: return 512;
         default: return 0;
     }
 }

@@ -31,13 +31,15 @@ STATUS = {0: "SFG_OK", 1: "SFG_EINVAL", 2: "SFG_ENOTCONN", 3: "SFG_ENOMEM", 4: "
           5: "SFG_EWORKSPACE", 6: "SFG_EUNSUPPORTED", 7: "SFG_ENUMERIC"}
 
 OP_MPNN_FORWARD, OP_MPNN_TRAIN, OP_COLOR, OP_TREE_ORDER, OP_TREE_SOLVE, OP_CSR_SELECT = 5, 6, 7, 8, 9, 10
+OP_MPNN_NORM = 11
 SMOOTH_JACOBI, SMOOTH_GAUSS_SEIDEL = 0, 1
 
 EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores",
             "sfg_select_topk", "sfg_spanning_tree", "sfg_affinity", "sfg_coarsen", "sfg_sparsify",
             "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam",
             "sfg_color", "sfg_smooth_gs", "sfg_random_block", "sfg_tree_order", "sfg_tree_solve",
-            "sfg_kappa_estimate", "sfg_csr_select", "sfg_pcg", "sfg_select_topk_noalloc"]
+            "sfg_kappa_estimate", "sfg_csr_select", "sfg_pcg", "sfg_select_topk_noalloc", "sfg_mpnn_fit_norm",
+            "sfg_mpnn_standardize", "sfg_mpnn_save", "sfg_mpnn_load"]
 
 
 class SfgError(RuntimeError):
@@ -73,6 +75,11 @@ class TreeStruct(ctypes.Structure):
 class PcgReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("inner_iters", ctypes.c_int64), ("relres", ctypes.c_double),
                 ("ms", ctypes.c_float), ("converged", ctypes.c_int32), ("inner_capped", ctypes.c_int32)]
+
+
+class MpnnMeta(ctypes.Structure):
+    _fields_ = [("kc", ctypes.c_int32), ("tc", ctypes.c_int32), ("y_mean", ctypes.c_double),
+                ("y_std", ctypes.c_double)]
 
 
 class SurrogateStruct(ctypes.Structure):
@@ -143,6 +150,10 @@ def lib() -> ctypes.CDLL:
         L.sfg_kappa_estimate.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P, P]
         L.sfg_csr_select.argtypes = [P, P, P, P, P, P, P, P, P, S, P]
         L.sfg_pcg.argtypes = [I64, I64, P, P, P, I, P, P, P, D, I32, P, P]
+        L.sfg_mpnn_fit_norm.argtypes = [I32, P, P, P, P, P, P, P, P, S, P]
+        L.sfg_mpnn_standardize.argtypes = [P, I64, P, P, P]
+        L.sfg_mpnn_save.argtypes = [ctypes.c_char_p, P, P, P, P]
+        L.sfg_mpnn_load.argtypes = [ctypes.c_char_p, P, P, P, P]
         for name in EXPORTED:
             if name not in ("sfg_workspace_bytes", "sfg_last_error", "sfg_mpnn_param_count"):
                 getattr(L, name).restype = I
@@ -711,3 +722,60 @@ def sfg_mpnn_adam(params: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: 
         _chk(t, name, _F32, n)
     _check(lib().sfg_mpnn_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(params.numel()), int(step),
                                float(lr), float(beta1), float(beta2), float(eps), _stream()))
+
+
+def sfg_mpnn_fit_norm(node_feats, edge_feats, targets):
+    """Standardisation of a training set (lists of device tensors: raw n_i x 8 node features, raw e_i x 4
+    edge features, e_i targets).  Returns (norm: 24 F32 in sfg_mpnn_features' layout, ystat: target mean
+    and standard deviation as 2 F64), both on the device."""
+    g = len(node_feats)
+    if g < 1 or len(edge_feats) != g or len(targets) != g:
+        raise ValueError("mpnn_fit_norm: one node, edge and target array per graph")
+    for nf, ef, t in zip(node_feats, edge_feats, targets):
+        if nf.dim() != 2 or int(nf.shape[1]) != 8 or ef.dim() != 2 or int(ef.shape[1]) != 4:
+            raise ValueError("mpnn_fit_norm: node features are n x 8, edge features e x 4")
+        _chk(nf, "node_feat", _F32)
+        _chk(ef, "edge_feat", _F32)
+        _chk(t, "target", _F32, int(ef.shape[0]))
+    dev = node_feats[0].device
+    norm = torch.empty(24, dtype=torch.float32, device=dev)
+    ystat = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = _ws(sfg_workspace_bytes(OP_MPNN_NORM, 0, 0, 0, F64), dev)
+    ptrs = (ctypes.c_void_p * g)(*[_ptr(t).value for t in node_feats])
+    eptrs = (ctypes.c_void_p * g)(*[_ptr(t).value for t in edge_feats])
+    tptrs = (ctypes.c_void_p * g)(*[_ptr(t).value for t in targets])
+    nrows = (ctypes.c_int64 * g)(*[int(t.shape[0]) for t in node_feats])
+    erows = (ctypes.c_int64 * g)(*[int(t.shape[0]) for t in edge_feats])
+    _check(lib().sfg_mpnn_fit_norm(g, ptrs, nrows, eptrs, tptrs, erows, _ptr(norm), _ptr(ystat), _ptr(ws),
+                                   ws.numel(), _stream()))
+    return norm, ystat
+
+
+def sfg_mpnn_standardize(y: torch.Tensor, ystat: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """(y - mean) / std with the target statistics of sfg_mpnn_fit_norm."""
+    _chk(y, "y", _F32)
+    _chk(ystat, "ystat", _F64, 2)
+    if out is None:
+        out = torch.empty_like(y)
+    _chk(out, "out", _F32, y.numel())
+    _check(lib().sfg_mpnn_standardize(_ptr(y), int(y.numel()), _ptr(ystat), _ptr(out), _stream()))
+    return out
+
+
+def sfg_mpnn_save(path: str, params: torch.Tensor, norm: torch.Tensor, kc: int, tc: int, y_mean: float,
+                  y_std: float) -> None:
+    """Write a model file (the C ABI's format: versioned, shapes, FNV-1a hash)."""
+    _chk(params, "params", _F32, sfg_mpnn_param_count())
+    _chk(norm, "norm", _F32, 24)
+    meta = MpnnMeta(int(kc), int(tc), float(y_mean), float(y_std))
+    _check(lib().sfg_mpnn_save(os.fsencode(path), _ptr(params), _ptr(norm), ctypes.byref(meta), _stream()))
+
+
+def sfg_mpnn_load(path: str, device="cuda"):
+    """Read a model file.  Returns (params, norm) on the device and a dict with kc, tc, y_mean, y_std."""
+    params = torch.empty(sfg_mpnn_param_count(), dtype=torch.float32, device=device)
+    norm = torch.empty(24, dtype=torch.float32, device=device)
+    meta = MpnnMeta()
+    _check(lib().sfg_mpnn_load(os.fsencode(path), _ptr(params), _ptr(norm), ctypes.byref(meta), _stream()))
+    return params, norm, {"kc": int(meta.kc), "tc": int(meta.tc), "y_mean": float(meta.y_mean),
+                          "y_std": float(meta.y_std)}

@@ -17,14 +17,16 @@ in libsfg:
   * inference predicts every off-tree edge, keeps the top ``cand_frac`` as
     candidates, and the plain scorer ranks the candidates exactly.
 
-Model files are ``.npz`` with a version, the shapes, the standardisation
-constants and a SHA-256 checksum of the parameters; a file that fails any
-check raises :class:`SurrogateInvalid`, and callers fall back to the plain
-scorer.
+Model files are written and read by the library (``sfg_mpnn_save`` /
+``sfg_mpnn_load``: a versioned binary format with the shapes, the cheap
+embedding, the standardisation constants and a 64-bit FNV-1a hash), so a C
+caller can use a model trained here; a file that fails any check raises
+:class:`SurrogateInvalid`, and callers fall back to the plain scorer.  The
+feature and target standardisation of the training set is computed by the
+library too (``sfg_mpnn_fit_norm``, ``sfg_mpnn_standardize``).
 """
 from __future__ import annotations
 
-import hashlib
 import math
 from dataclasses import dataclass, field
 from typing import Optional
@@ -34,7 +36,6 @@ import torch
 
 from . import sfg as S
 
-VERSION = 2
 KC = 4                 # vectors of the cheap embedding (fast default)
 KC_RECALL = 16         # the recall configuration: every vector of the plain method
 TC = 10                # sweeps of the cheap embedding (half of the plain method's 20)
@@ -55,43 +56,18 @@ class Model:
     kc: int = KC                         # cheap embedding: vectors (the first kc of the method's block)
     tc: int = TC                         # cheap embedding: sweeps
 
-    def checksum(self) -> str:
-        h = hashlib.sha256()
-        h.update(self.params.detach().cpu().numpy().astype(np.float32).tobytes())
-        h.update(self.norm.detach().cpu().numpy().astype(np.float32).tobytes())
-        h.update(np.array([self.y_mean, self.y_std], dtype=np.float64).tobytes())
-        h.update(np.array([self.kc, self.tc], dtype=np.int64).tobytes())
-        return h.hexdigest()
-
     def save(self, path: str) -> None:
-        np.savez(path, version=np.int64(VERSION), params=self.params.detach().cpu().numpy(),
-                 norm=self.norm.detach().cpu().numpy(), y=np.array([self.y_mean, self.y_std]),
-                 cheap=np.array([self.kc, self.tc], dtype=np.int64), checksum=np.array(self.checksum()))
+        S.sfg_mpnn_save(path, self.params.contiguous(), self.norm.contiguous(), self.kc, self.tc, self.y_mean,
+                        self.y_std)
 
 
 def load(path: str, device="cuda") -> Model:
+    """A model file written by Model.save (or by a C caller through sfg_mpnn_save)."""
     try:
-        z = np.load(path, allow_pickle=False)
-        ver = int(z["version"])
-        params, norm, y, cs = z["params"], z["norm"], z["y"], str(z["checksum"])
-        if ver != VERSION:
-            raise SurrogateInvalid(f"surrogate model version {ver}, expected {VERSION}")
-        kc, tc = (int(x) for x in z["cheap"])
-    except SurrogateInvalid:
-        raise
-    except Exception as e:   # unreadable or missing fields
-        raise SurrogateInvalid(f"cannot read surrogate model {path}: {e}") from e
-    if not (1 <= kc <= 64 and 1 <= tc <= 1000):
-        raise SurrogateInvalid(f"surrogate model has a bad cheap embedding ({kc} vectors, {tc} sweeps)")
-    if params.shape != (S.sfg_mpnn_param_count(),) or norm.shape != (2 * (N_NODE_FEAT + N_EDGE_FEAT),):
-        raise SurrogateInvalid("surrogate model has the wrong shapes")
-    if not (np.all(np.isfinite(params)) and np.all(np.isfinite(norm)) and np.all(np.isfinite(y))):
-        raise SurrogateInvalid("surrogate model holds non-finite values")
-    m = Model(torch.from_numpy(params.astype(np.float32)).to(device),
-              torch.from_numpy(norm.astype(np.float32)).to(device), float(y[0]), float(y[1]), kc=kc, tc=tc)
-    if m.checksum() != cs:
-        raise SurrogateInvalid("surrogate model checksum mismatch")
-    return m
+        params, norm, meta = S.sfg_mpnn_load(path, device)
+    except S.SfgError as e:     # unreadable, or a failed check (the message says which)
+        raise SurrogateInvalid(str(e)) from e
+    return Model(params, norm, meta["y_mean"], meta["y_std"], kc=meta["kc"], tc=meta["tc"])
 
 
 def init_params(seed: int, device="cuda") -> torch.Tensor:
@@ -162,15 +138,11 @@ class TrainSet:
 
 
 def fit_norm(ts: TrainSet):
-    """Feature and target standardisation from the training set (host statistics)."""
-    nf = np.concatenate([g.raw_nf.cpu().numpy() for g in ts.graphs])
-    ef = np.concatenate([g.raw_ef.cpu().numpy() for g in ts.graphs])
-    y = np.concatenate([t.cpu().numpy() for t in ts.targets]).astype(np.float64)
-    nm, ns = nf.mean(0), nf.std(0)
-    em, es = ef.mean(0), ef.std(0)
-    nm[0], ns[0] = 0.0, 1.0
-    norm = np.concatenate([nm, 1.0 / np.maximum(ns, 1e-6), em, 1.0 / np.maximum(es, 1e-6)]).astype(np.float32)
-    return norm, float(y.mean()), float(y.std())
+    """Feature and target standardisation of the training set, computed by the library
+    (sfg_mpnn_fit_norm).  Returns the 24-value feature normalisation and the target mean and
+    standard deviation, on the device."""
+    return S.sfg_mpnn_fit_norm([g.raw_nf for g in ts.graphs], [g.raw_ef for g in ts.graphs],
+                               [t.contiguous() for t in ts.targets])
 
 
 def train(ts: TrainSet, epochs: int = 20, lr: float = 3e-3, seed: int = 7, lr_min: float = 3e-4,
@@ -182,12 +154,12 @@ def train(ts: TrainSet, epochs: int = 20, lr: float = 3e-3, seed: int = 7, lr_mi
     kc, tc = int(ts.graphs[0].xc.shape[1]), ts.graphs[0].tc
     if any(int(g.xc.shape[1]) != kc or g.tc != tc for g in ts.graphs):
         raise ValueError("training graphs must share one cheap embedding (vectors and sweeps)")
-    norm_np, ym, ysd = fit_norm(ts)
-    norm = torch.from_numpy(norm_np).to(dev)
+    norm, ystat = fit_norm(ts)
+    ym, ysd = (float(x) for x in ystat.cpu())
     feats = []
     for g, t in zip(ts.graphs, ts.targets):
         nf, ef = features(g, norm)
-        feats.append((nf, ef, ((t - ym) / ysd).contiguous()))
+        feats.append((nf, ef, S.sfg_mpnn_standardize(t.contiguous(), ystat)))
     params = init_params(seed, dev)
     m = torch.zeros_like(params)
     v = torch.zeros_like(params)

@@ -168,43 +168,79 @@ def test_recall_configuration(S, SG):
     assert not res.fallback and res.n_scored == int(np.ceil(0.3 * nc))
 
 
+def _fnv1a64(b: bytes) -> int:
+    h = 0xcbf29ce484222325
+    for x in b:
+        h = ((h ^ x) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _reseal(raw: bytes) -> bytes:
+    """A model file with its hash recomputed (to reach the checks after the hash)."""
+    import struct
+
+    return raw[:-8] + struct.pack("<Q", _fnv1a64(raw[:-8]))
+
+
 def test_model_file_roundtrip_and_fallback(S, SG, tmp_path):
-    model = SG.Model(SG.init_params(1), torch.ones(24, device="cuda"), 0.0, 1.0, kc=16, tc=6)
-    p = str(tmp_path / "m.npz")
+    import struct
+
+    model = SG.Model(SG.init_params(1), torch.linspace(0.5, 2.0, 24, device="cuda"), 0.25, 1.5, kc=16, tc=6)
+    p = str(tmp_path / "m.sfgm")
     model.save(p)
     m2 = SG.load(p)
-    assert torch.equal(m2.params, model.params) and (m2.kc, m2.tc) == (16, 6)
-    # the cheap embedding is part of the checksum, and must be sane
-    z = dict(np.load(p, allow_pickle=False))
-    z["cheap"] = np.array([4, 6], dtype=np.int64)
-    np.savez(str(tmp_path / "kc.npz"), **z)
+    assert torch.equal(m2.params, model.params) and torch.equal(m2.norm, model.norm)
+    assert (m2.kc, m2.tc, m2.y_mean, m2.y_std) == (16, 6, 0.25, 1.5)
+    raw = open(p, "rb").read()
+    npar = S.sfg_mpnn_param_count()
+    assert raw[:8] == b"SFGMPNN1" and len(raw) == 48 + 4 * (npar + 24) + 8
+    assert struct.unpack_from("<IIIii", raw, 8) == (1, npar, 24, 16, 6)
+    assert struct.unpack_from("<Q", raw, len(raw) - 8)[0] == _fnv1a64(raw[:-8])
+
+    def write(name, b):
+        q = str(tmp_path / name)
+        open(q, "wb").write(b)
+        return q
+
+    def patched(off, fmt, *vals):
+        b = bytearray(raw)
+        struct.pack_into(fmt, b, off, *vals)
+        return bytes(b)
+
+    # the cheap embedding is covered by the hash, and must be sane
     with pytest.raises(SG.SurrogateInvalid, match="checksum"):
-        SG.load(str(tmp_path / "kc.npz"))
-    z["cheap"] = np.array([0, 6], dtype=np.int64)
-    np.savez(str(tmp_path / "kc0.npz"), **z)
+        SG.load(write("kc.sfgm", patched(20, "<i", 4)))
     with pytest.raises(SG.SurrogateInvalid, match="cheap embedding"):
-        SG.load(str(tmp_path / "kc0.npz"))
-    z["version"] = np.int64(1)
-    np.savez(str(tmp_path / "v1.npz"), **z)
+        SG.load(write("kc0.sfgm", _reseal(patched(20, "<i", 0))))
     with pytest.raises(SG.SurrogateInvalid, match="version"):
-        SG.load(str(tmp_path / "v1.npz"))
-    # corrupted parameters: checksum mismatch
-    z = dict(np.load(p, allow_pickle=False))
-    z["params"] = z["params"].copy()
-    z["params"][5] += 1.0
-    np.savez(str(tmp_path / "bad.npz"), **z)
+        SG.load(write("v2.sfgm", _reseal(patched(8, "<I", 2))))
+    with pytest.raises(SG.SurrogateInvalid, match="shapes"):
+        SG.load(write("shape.sfgm", _reseal(patched(12, "<I", npar - 1))))
+    with pytest.raises(SG.SurrogateInvalid, match="length"):
+        SG.load(write("short.sfgm", _reseal(raw[:-12] + raw[-8:])))
+    with pytest.raises(SG.SurrogateInvalid, match="not a surrogate model"):
+        SG.load(write("magic.sfgm", b"NOTMODEL" + raw[8:]))
+    # corrupted parameters: hash mismatch; a NaN with a valid hash: refused as non-finite
     with pytest.raises(SG.SurrogateInvalid, match="checksum"):
-        SG.load(str(tmp_path / "bad.npz"))
-    z["params"][5] = np.nan
-    np.savez(str(tmp_path / "nan.npz"), **z)
+        SG.load(write("bad.sfgm", patched(48 + 4 * 5, "<f", 123.0)))
+    nan_path = write("nan.sfgm", _reseal(patched(48 + 4 * 5, "<f", float("nan"))))
     with pytest.raises(SG.SurrogateInvalid, match="non-finite"):
-        SG.load(str(tmp_path / "nan.npz"))
-    with pytest.raises(SG.SurrogateInvalid):
-        SG.load(str(tmp_path / "missing.npz"))
+        SG.load(nan_path)
+    with pytest.raises(SG.SurrogateInvalid, match="cannot open"):
+        SG.load(str(tmp_path / "missing.sfgm"))
+    # a failed load leaves the caller's buffers alone
+    params = torch.full((npar,), 7.0, device="cuda")
+    norm = torch.full((24,), 7.0, device="cuda")
+    meta = S.MpnnMeta()
+    import ctypes
+
+    st = S.lib().sfg_mpnn_load(nan_path.encode(), ctypes.c_void_p(params.data_ptr()),
+                               ctypes.c_void_p(norm.data_ptr()), ctypes.byref(meta), S._stream())
+    assert st == 1 and bool((params == 7.0).all()) and bool((norm == 7.0).all())
     # the pruned path falls back to the plain scorer on a bad model
     g = W.mesh3d(10, 10, 10, seed=360)
     X0 = W.random_block(g.n, 16, 1)
-    res = SG.sparsify_pruned(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), str(tmp_path / "nan.npz"), 20, 0.1, 0.2)
+    res = SG.sparsify_pruned(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), nan_path, 20, 0.1, 0.2)
     assert res.fallback and "non-finite" in res.reason
     keep, _ = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0), S.make_params(k=16, sweeps=20, frac=0.1,
                                                                                        storage=torch.float32))
@@ -266,3 +302,33 @@ def test_surrogate_in_the_library_falls_back_and_checks(S, SG):
         x = torch.cat([x.reshape(-1)] * 2)
         with pytest.raises(S.SfgError, match=status):
             S.sfg_sparsify(g.n, u, v, w, x, S.make_params(**args))
+
+
+def test_standardisation_in_the_library_matches_fp64(S, SG):
+    """sfg_mpnn_fit_norm and sfg_mpnn_standardize against the same statistics taken in FP64 by NumPy over
+    the concatenated training arrays (population deviation, floor 1e-6, node feature 0 kept as 1)."""
+    graphs, targets = [], []
+    for i in range(3):
+        g = W.mesh3d(9 + i, 10, 11, seed=390 + i)
+        pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(W.random_block(g.n, 4, 391 + i)), 5)
+        pp.raw_nf, pp.raw_ef = SG.features(pp, None)
+        graphs.append(pp)
+        targets.append(torch.log(SG.plain_scores(pp, dev(W.random_block(g.n, 8, 392 + i)), 6) + 1e-30))
+    norm, ystat = SG.fit_norm(SG.TrainSet(graphs, targets))
+    nf = np.concatenate([p.raw_nf.cpu().numpy() for p in graphs]).astype(np.float64)
+    ef = np.concatenate([p.raw_ef.cpu().numpy() for p in graphs]).astype(np.float64)
+    y = np.concatenate([t.cpu().numpy() for t in targets]).astype(np.float64)
+    nm, ns, em, es = nf.mean(0), nf.std(0), ef.mean(0), ef.std(0)
+    nm[0], ns[0] = 0.0, 1.0
+    want = np.concatenate([nm, 1 / np.maximum(ns, 1e-6), em, 1 / np.maximum(es, 1e-6)])
+    got = norm.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, want, rtol=2e-6, atol=1e-6)
+    ys = ystat.cpu().numpy()
+    assert abs(ys[0] - y.mean()) <= 1e-12 * max(1.0, abs(y.mean())) and abs(ys[1] - y.std()) <= 1e-10 * y.std()
+    z = S.sfg_mpnn_standardize(targets[1].contiguous(), ystat).cpu().numpy()
+    zr = ((targets[1].cpu().numpy().astype(np.float64) - ys[0]) / ys[1]).astype(np.float32)
+    assert np.array_equal(z, zr)
+    # deterministic: the same statistics twice
+    norm2, ystat2 = SG.fit_norm(SG.TrainSet(graphs, targets))
+    assert torch.equal(norm, norm2) and torch.equal(ystat, ystat2)
+
