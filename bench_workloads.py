@@ -1,8 +1,8 @@
 """Extra benchmark lines for the other synthetic workloads (called by bench.py).
 
-    python bench.py --workload knn      # 2M-point 3-D kNN, FP16/BF16 storage + FP64 band re-scoring
-    python bench.py --workload chunglu  # 4M-node power-law graph, 5-level hierarchy (Alg. 1)
-    python bench.py --workload mesh     # 200^3 mesh, plain FP32 path and the learned surrogate
+    python bench.py --workload knn        # 2M-point 3-D kNN, FP16/BF16 storage + FP64 band re-scoring
+    python bench.py --workload chunglu    # 4M-node power-law graph, 5-level hierarchy (Alg. 1)
+    python bench.py --workload surrogate  # 200^3 mesh, plain FP32 path and the learned surrogate (both models)
     python bench.py --workload sigma    # power grid: condition-number estimate and sigma-driven stopping
     python bench.py --workload scaling  # 3-D meshes 50^3 .. 200^3: time per edge of the whole method
 
@@ -56,6 +56,19 @@ def ev_time(fn, reps: int) -> float:
     b.record()
     b.synchronize()
     return a.elapsed_time(b) / reps
+
+
+def copy_rates(dev) -> dict:
+    """Attainable bandwidth on this machine: a 1 GiB device copy (HBM) and a 64 MiB copy repeated, whose two
+    buffers stay in the 256 MB memory-side cache."""
+    out = {}
+    for key, elems, reps in (("hbm_copy_gbs", 1 << 27, 5), ("in_cache_copy_gbs", 1 << 23, 50)):
+        src = torch.empty(elems, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        t = ev_time(lambda: dst.copy_(src), reps)
+        out[key] = round(2 * elems * 8 / (t * 1e-3) / 1e9, 1)
+        del src, dst
+    return out
 
 
 def sweep_roofline(H, x0, sweeps, storage, final_f32, n, nnz, k, sx, sw, reps=5):
@@ -231,7 +244,177 @@ def _train_surrogate(SG, k, T, f, kc, tc):
     return model, hist, t_train, recall
 
 
-def run_mesh(args) -> dict:
+def mesh_steps(SG, g, u, v, w32, tree, cand, x0, models):
+    """Step closures on one mesh, each returning (selection over the off-tree edges, threshold):
+    plain(kk, T, f): the plain method in FP32 with the first kk vectors; ranked(model, f): the top f by the
+    surrogate's prediction alone; pruned(model, cf, T, f): the top f of the exact scores of the surrogate's top
+    cf.  Buffers are preallocated; only the pruned path's candidate list is sized per call."""
+    n = g.n
+    nc = int(cand.numel())
+    dev = u.device
+    H = S.sfg_laplacian_csr(n, u, v, w32, mask=tree)
+    G = S.sfg_laplacian_csr(n, u, v, w32)
+    ws_sm = torch.empty(S.sfg_workspace_bytes(S.OP_SMOOTH, n, 0, int(x0.shape[1]), torch.float32),
+                        dtype=torch.uint8, device=dev)
+    ws_g = torch.empty(S.sfg_workspace_bytes(S.OP_LAPLACIAN_CSR, n, g.m, 0, torch.float32), dtype=torch.uint8,
+                       device=dev)
+    ws_cs = torch.empty(S.sfg_workspace_bytes(S.OP_CSR_SELECT, n, g.m, 0, torch.float32), dtype=torch.uint8,
+                        device=dev)
+    ws_f = torch.empty(S.sfg_workspace_bytes(S.OP_MPNN_FORWARD, n, 0, 0, torch.bfloat16), dtype=torch.uint8,
+                       device=dev)
+    ws_sel = torch.empty(S.sfg_workspace_bytes(S.OP_SELECT_TOPK, 0, nc, 0, torch.float32), dtype=torch.uint8,
+                         device=dev)
+    score = torch.empty(nc, dtype=torch.float32, device=dev)
+    sel = torch.empty(nc, dtype=torch.uint8, device=dev)
+    tau = torch.empty(1, dtype=torch.float64, device=dev)
+    blocks, X = {}, {}
+    nnz_t = 2 * (n - 1)
+
+    def block(kk):
+        """The first kk columns of the block and an output buffer, made once per width (outside timing:
+        ev_time runs each step once before its timed repetitions)."""
+        if kk not in blocks:
+            blocks[kk] = x0[:, :kk].contiguous()
+            X[kk] = torch.empty((n, kk), dtype=torch.float32, device=dev)
+        return blocks[kk], X[kk]
+
+    for kk in {int(x0.shape[1])} | {m.kc for m in models}:
+        block(kk)
+
+    def plain(kk, T, f):
+        xb, xo = block(kk)
+        S.sfg_laplacian_csr(n, u, v, w32, mask=tree, out=H, nnz=nnz_t)
+        S.sfg_smooth(H, xb, T, 0.5, storage=torch.float32, out=xo, ws=ws_sm)
+        S.sfg_edge_scores(xo, u, v, w32, cand=cand, out=score)
+        return S.sfg_select_topk(score, int(math.ceil(f * nc)), sel=sel, tau=tau, ws=ws_sel, sync=False)
+
+    def predict(model):
+        # the network aggregates over G: build G's CSR and take the tree's from it
+        S.sfg_laplacian_csr(n, u, v, w32, ws=ws_g, out=G, nnz=2 * g.m)
+        S.sfg_csr_select(G, tree, out=H, nnz=nnz_t, ws=ws_cs)
+        xc = S.sfg_smooth(H, block(model.kc)[0], model.tc, 0.5, storage=torch.bfloat16, final_f32=True)
+        pp = SG.Prepared(n, u, v, w32, tree, cand, G, H, xc, model.tc)
+        nf, ef = SG.features(pp, model.norm)
+        return S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
+
+    def ranked(model, f):
+        return S.sfg_select_topk(predict(model), int(math.ceil(f * nc)), sel=sel, tau=tau, ws=ws_sel, sync=False)
+
+    def pruned(model, cf, T, f):
+        csel, _ = S.sfg_select_topk(predict(model), int(math.ceil(cf * nc)), sync=False)
+        cpos = torch.nonzero(csel).reshape(-1)
+        ce = cand[cpos].contiguous()
+        xb, xo = block(int(x0.shape[1]))
+        S.sfg_smooth(H, xb, T, 0.5, storage=torch.float32, out=xo, ws=ws_sm)
+        s2 = S.sfg_edge_scores(xo, u, v, w32, cand=ce)
+        sel2, _ = S.sfg_select_topk(s2, min(int(math.ceil(f * nc)), int(ce.numel())), sync=False)
+        full = torch.zeros(nc, dtype=torch.uint8, device=dev)
+        full[cpos[sel2.bool()]] = 1
+        return full, None
+
+    return {"plain": plain, "ranked": ranked, "pruned": pruned, "predict": predict}
+
+
+# the paths of the equal-condition-number comparison: the plain default, the plain method at cheaper settings
+# (fewer vectors, fewer sweeps, the surrogate's own 4-vector 10-sweep embedding: the method without the
+# network), and the two surrogate paths
+EQK_PATHS = ("plain", "plain_k8", "plain_t10", "plain_k4_t10", "ranked", "pruned")
+EQK_LADDER = (0.06, 0.08, 0.10, 0.12, 0.14, 0.17, 0.20, 0.25, 0.30)
+
+
+def _eqk_keep(SG, name, gm, um, vm, wm, X0m, model, k, T, f, cf):
+    """The sparsifier (keep mask, spanning tree marked 1) of one path at fraction f on a held-out mesh."""
+    x0 = torch.from_numpy(X0m).cuda()
+    cfg = {"plain": (k, T), "plain_k8": (8, T), "plain_t10": (k, T // 2), "plain_k4_t10": (model.kc, model.tc)}
+    if name in cfg:
+        kk, tt = cfg[name]
+        keep, _ = S.sfg_sparsify(gm.n, um, vm, wm, x0[:, :kk].contiguous(),
+                                 S.make_params(k=kk, sweeps=tt, frac=f, storage=torch.float32))
+        return keep
+    if name == "ranked":
+        return SG.sparsify_ranked(gm.n, um, vm, wm, x0, model, T, f).keep
+    return SG.sparsify_pruned(gm.n, um, vm, wm, x0, model, T, f, cf).keep
+
+
+def equal_kappa_mesh(g, u, v, w64, tree, cand, dev, n_meshes: int = 5, side: int = 40) -> dict:
+    """Surrogate against plain at equal condition number (Eq. 2).  kappa* is the median, over held-out
+    meshes of the workload's family (side^3, seeds 200..204, log-normal(0, 1.5) weights), of the condition
+    number of the plain default sparsifier (16 FP32 vectors, 20 sweeps, 10%).  For every path the fraction
+    ladder is walked upwards until the median condition number over the same meshes is at most kappa*; that
+    fraction's step is then timed on the full 200^3 mesh: the path's time to reach kappa*.  Condition numbers
+    come from the library's estimate (largest Ritz value of the pencil after 10 steps of 8 vectors, inner
+    tolerance 1e-2; the same estimator for every path), which a full-size mesh makes too slow to repeat per
+    path, fraction and seed."""
+    from paper_2008_07633_amd import surrogate as SG
+
+    prm = W.workload_params("mesh")
+    k, T, f0, cf = prm["k"], prm["sweeps"], prm["frac"], prm["cand_frac"]
+    t0 = time.time()
+    model, hist, t_train, recall = _train_surrogate(SG, k, T, f0, SG.KC, SG.TC)
+    est = S.make_kappa_params(k=8, steps=10, tol=1e-2, seed=11)
+    meshes = []
+    for i in range(n_meshes):
+        gm = W.mesh3d(side, side, side, seed=200 + i, wdist=("lognormal", 0.0, 1.5))
+        um, vm, wm = to_dev(gm)
+        meshes.append((gm, um, vm, wm, W.random_block(gm.n, k, 3000 + i)))
+
+    def median_kappa(name, f):
+        ks = []
+        for gm, um, vm, wm, X0m in meshes:
+            keep = _eqk_keep(SG, name, gm, um, vm, wm, X0m, model, k, T, f, cf)
+            ks.append(S.sfg_kappa_estimate(gm.n, um, vm, wm, keep, est)[0])
+        return float(np.median(ks)), ks
+
+    kstar, k_plain = median_kappa("plain", f0)
+    log(f"kappa* = {kstar:.2f} (plain default on {n_meshes} held-out {side}^3 meshes: {np.round(k_plain, 2)})")
+    reach = {}
+    for name in EQK_PATHS:
+        curve, f_star = [], None
+        for f in EQK_LADDER:
+            med = kstar if (name == "plain" and f == f0) else median_kappa(name, f)[0]
+            curve.append([f, round(med, 2)])
+            if med <= kstar:
+                f_star = f
+                break
+        reach[name] = {"frac": f_star, "kappa_curve": curve}
+        log(f"{name}: reaches kappa* at f = {f_star} ({curve})")
+    t_eval = time.time() - t0
+
+    # times on the full 200^3 mesh at each path's fraction
+    w32 = w64.float()
+    X0 = W.workload_block("mesh", g.n)
+    x0 = torch.from_numpy(X0).to(dev)
+    st = mesh_steps(SG, g, u, v, w32, tree, cand, x0, [model])
+    steps = {"plain": lambda f: st["plain"](k, T, f), "plain_k8": lambda f: st["plain"](8, T, f),
+             "plain_t10": lambda f: st["plain"](k, T // 2, f),
+             "plain_k4_t10": lambda f: st["plain"](model.kc, model.tc, f),
+             "ranked": lambda f: st["ranked"](model, f), "pruned": lambda f: st["pruned"](model, cf, T, f)}
+    for name, r in reach.items():
+        if r["frac"] is not None:
+            r["ms_200cubed"] = round(ev_time(lambda: steps[name](r["frac"]), 3), 3)
+    t_plain = reach["plain"]["ms_200cubed"]
+    for r in reach.values():
+        if "ms_200cubed" in r:
+            r["vs_plain_time"] = round(r["ms_200cubed"] / t_plain, 3)
+    done = {n_: r["ms_200cubed"] for n_, r in reach.items() if "ms_200cubed" in r}
+    fastest = min(done, key=done.get)
+    del x0, st
+    torch.cuda.empty_cache()
+    return {"kappa_star": round(kstar, 2), "kappa_plain_per_mesh": [round(x, 2) for x in k_plain],
+            "heldout": f"{n_meshes} meshes {side}^3, seeds 200-{199 + n_meshes}, log-normal(0, 1.5) weights",
+            "estimator": {"vectors": est.k, "steps": est.steps, "inner_tol": est.tol},
+            "surrogate": {"model": f"{model.kc} vectors, {model.tc} sweeps (BF16) cheap embedding; 2 layers, "
+                                   f"hidden 32", "train_s": round(t_train, 1),
+                          "recall_heldout_at_cand_frac": recall["net"].get(str(cf))},
+            "paths": reach, "fastest_to_kappa_star": fastest,
+            "time_to_kappa_star_ms": {"plain": t_plain, "surrogate_ranked": reach["ranked"].get("ms_200cubed"),
+                                      "surrogate_pruned": reach["pruned"].get("ms_200cubed")},
+            "eval_s": round(t_eval, 1),
+            "note": "step times exclude the spanning tree and candidate list (input preparation shared by all "
+                    "paths); the surrogate paths include G's CSR, the cheap embedding, features and inference"}
+
+
+def run_surrogate(args) -> dict:
     from paper_2008_07633_amd import surrogate as SG
 
     prm = W.workload_params("mesh")
@@ -461,7 +644,7 @@ def run_pcg(args) -> dict:
 
 
 def run(args) -> None:
-    fn = {"knn": run_knn, "chunglu": run_chunglu, "mesh": run_mesh, "sigma": run_sigma,
+    fn = {"knn": run_knn, "chunglu": run_chunglu, "surrogate": run_surrogate, "sigma": run_sigma,
           "scaling": run_scaling, "pcg": run_pcg}[args.workload]
     out = fn(args)
     out["n_gpus"] = 1

@@ -144,11 +144,16 @@ sfg_status sfg_csr_select(const sfg_csr *G, const uint8_t *mask, int32_t *rowptr
 
 /*
  * Local spectral embedding (Sec. 3.2): make the k random vectors x0
- * orthogonal to the all-one vector (subtract each column's mean; the mean is
- * the column sum rounded once, divided by n), then apply `sweeps` damped
+ * orthogonal to the all-one vector (subtract each column's mean), then apply `sweeps` damped
  * Jacobi relaxations of L x = 0:
  *     x_p <- (1 - omega) x_p + omega * (sum_q A_pq x_q) / D_pp
  * with the row sum taken in ascending column order.
+ * Column mean: the column is summed in double-double arithmetic (Knuth's
+ * two-sum, about 106 significant bits), the double-double total rounded once
+ * to FP64 and divided by n.  That equals the exactly rounded sum divided by n
+ * unless the column cancels to within about 2^-100 of the magnitude of its
+ * partial sums (the error of the double-double sum then reaches the FP64
+ * rounding boundary); columns of random starting vectors are far from that.
  *   H          graph to smooth (vt F64 when storage is F64, else F32)
  *   k          1..64 vectors; sweeps >= 0; 0 < omega <= 1 (0.5 damps the
  *              top of the spectrum of bipartite graphs)

@@ -121,6 +121,33 @@ def test_smooth_f64_bitwise(S, orc, graph, k, sweeps):
     np.testing.assert_array_equal(host(X), ref)
 
 
+def test_column_mean_under_heavy_cancellation(S, orc):
+    """Centring subtracts each column's mean; the oracle takes the exactly rounded column sum (fsum).  These
+    columns defeat a plain FP64 sum (big values that cancel around small ones, near-opposite pairs that cancel
+    to 2^-50 of their size) and are spread over many blocks of the GPU's partial sums; the GPU's double-double
+    sum must still round to the same mean, so the centred block is bit-identical."""
+    import math
+
+    rng = np.random.default_rng(77)
+    n = 300_000
+    c0 = np.tile([2.0 ** 53, 1.0, -2.0 ** 53, 1.0], n // 4)
+    x = rng.standard_normal(n // 2) * 2.0 ** 20
+    a = x + rng.standard_normal(n // 2) * 2.0 ** -30         # rounded: the pair sums are what is left of delta
+    c1 = np.empty(n)
+    c1[0::2], c1[1::2] = a, -x
+    c2 = rng.permutation(c1)
+    c3 = rng.standard_normal(n)
+    X0 = np.ascontiguousarray(np.stack([c0, c1, c2, c3], axis=1))
+    for c in (0, 1, 2):
+        assert sum(X0[:, c].tolist()) != math.fsum(X0[:, c])       # a plain sequential sum is wrong here
+    g = W.grid2d(1, n, seed=78)
+    H = S.sfg_laplacian_csr(g.n, dev(g.u), dev(g.v), dev(g.w))
+    got = host(S.sfg_smooth(H, dev(X0), 0, storage=torch.float64))
+    ref, mean = orc.center(X0)
+    assert all(mean[c] == math.fsum(X0[:, c]) / n for c in range(4))
+    np.testing.assert_array_equal(got, ref)
+
+
 def test_smooth_omega_and_tree(S, orc):
     g = W.powergrid(60, 70, 0.02, seed=75)
     tree, _ = orc.max_spanning_forest(g.n, g.u, g.v, g.w)

@@ -332,3 +332,47 @@ def test_standardisation_in_the_library_matches_fp64(S, SG):
     norm2, ystat2 = SG.fit_norm(SG.TrainSet(graphs, targets))
     assert torch.equal(norm, norm2) and torch.equal(ystat, ystat2)
 
+
+def test_pruned_candidates_match_an_oracle_composition(S, SG, orc):
+    """The pruned path's candidate set (the top 20% of the off-tree edges by prediction) against the same
+    composition in FP64 on the CPU: the oracle's spanning tree, its FP64 cheap embedding (the first 4 vectors
+    centred and smoothed 10 times on the tree), the reference features and forward pass, and its top 20%.  The
+    library smooths the cheap embedding in BF16 and infers with BF16 activations, so the sets may differ, but
+    only by edges whose FP64 prediction lies within the measured prediction error of the cut."""
+    import math
+
+    g = W.mesh3d(24, 22, 20, seed=395, wdist=("lognormal", 0.0, 1.5))
+    kc, tc, cf = 4, 10, 0.2
+    X0 = W.random_block(g.n, 16, 396)
+    # oracle composition, FP64 (the surrogate works on the FP32 weights)
+    intree, comps = orc.max_spanning_forest(g.n, g.u, g.v, g.w)
+    assert comps == 1
+    t = intree.astype(bool)
+    w32 = g.w.astype(np.float32).astype(np.float64)
+    Hc = orc.laplacian_csr(g.n, g.u[t], g.v[t], w32[t])
+    xc = orc.smooth(Hc, orc.center(X0[:, :kc])[0], tc)
+    cand = np.nonzero(~t)[0].astype(np.int32)
+    rn, re = M.raw_features(g.n, g.u, g.v, w32, t, xc, cand)
+    norm = np.concatenate([rn.mean(0), 1 / np.maximum(rn.std(0), 1e-6), re.mean(0), 1 / np.maximum(re.std(0), 1e-6)])
+    norm[0], norm[8] = 0.0, 1.0
+    norm32 = norm.astype(np.float32)
+    nf, ef = M.standardise(rn, re, norm32.astype(np.float64))
+    theta32 = (M.init_params(5) * 0.5 + 0.01).astype(np.float32)
+    A, d = M.norm_adjacency(g.n, g.u, g.v, w32)
+    pred_ref, _ = M.forward(theta32.astype(np.float64), A, d, nf, g.u, g.v, cand, ef)
+    kcand = int(math.ceil(cf * cand.size))
+    pos_ref, cut = orc.select_topk(pred_ref, cand, kcand)
+    # the library's composition
+    model = SG.Model(dev(theta32), dev(norm32), 0.0, 1.0, kc=kc, tc=tc)
+    pp = SG.prepare(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0[:, :kc]), tc)
+    assert np.array_equal(pp.cand.cpu().numpy(), cand)
+    cpos, pred = SG.prune(model, pp, cf)
+    pred = pred.cpu().numpy().astype(np.float64)
+    delta = float(np.max(np.abs(pred - pred_ref)))
+    scale = float(np.max(np.abs(pred_ref)))
+    assert delta < 0.05 * scale, (delta, scale)
+    got, want = set(cpos.cpu().numpy().tolist()), set(pos_ref.tolist())
+    diff = np.array(sorted(got ^ want), dtype=np.int64)
+    assert diff.size <= 0.02 * kcand, (diff.size, kcand)
+    if diff.size:
+        assert np.max(np.abs(pred_ref[diff] - cut)) <= 2 * delta
