@@ -131,6 +131,8 @@ def main():
     ap.add_argument("--smoother", choices=["jacobi", "gs"], default="jacobi",
                     help="gs: multicolour Gauss-Seidel (omega 1; colouring of the tree prepared once, like the tree)")
     ap.add_argument("--sweep-reps", type=int, default=5)
+    ap.add_argument("--sweep-pairs", action="store_true",
+                    help="smooth two sweeps per launch in the tree's preorder (sfg_smooth_ordered)")
     ap.add_argument("--workload", choices=["mesh", "powergrid", "knn", "chunglu", "surrogate", "sigma", "scaling",
                                            "pcg"], default="mesh",
                     help="mesh: the headline line; powergrid: the same pass on the 1M-node power grid; "
@@ -157,15 +159,17 @@ def main():
     print(json.dumps(headline(args, S, BW)), flush=True)
 
 
-def scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, wdt, gs, dev):
-    """Preallocated buffers and the step function of one scoring pass in storage ``wdt``."""
+def scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, wdt, gs, dev, order=None):
+    """Preallocated buffers and the step function of one scoring pass in storage ``wdt``.  With ``order``
+    (the spanning tree's preorder) the smoothing takes two sweeps per pass (sfg_smooth_ordered)."""
     import torch
 
     w = w64 if wdt == torch.float64 else w64.float()
     nnz = 2 * (g.n - 1)
     ncand = int(cand.numel())
     ws_csr = torch.empty(S.sfg_workspace_bytes(S.OP_LAPLACIAN_CSR, g.n, g.m, 0, wdt), dtype=torch.uint8, device=dev)
-    ws_sm = torch.empty(S.sfg_workspace_bytes(S.OP_SMOOTH, g.n, 0, k, wdt), dtype=torch.uint8, device=dev)
+    ws_sm = torch.empty(S.sfg_workspace_bytes(S.OP_SMOOTH_ORDERED if order is not None else S.OP_SMOOTH, g.n, 0, k,
+                                              wdt), dtype=torch.uint8, device=dev)
     ws_sel = torch.empty(S.sfg_workspace_bytes(S.OP_SELECT_TOPK, 0, ncand, 0, wdt), dtype=torch.uint8, device=dev)
     H = S.Csr(g.n, nnz, torch.empty(g.n + 1, dtype=torch.int32, device=dev),
               torch.empty(nnz, dtype=torch.int32, device=dev), torch.empty(nnz, dtype=wdt, device=dev),
@@ -182,9 +186,13 @@ def scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, wdt, gs, de
     def csr():
         S.sfg_laplacian_csr(g.n, u, v, w, mask=tree, ws=ws_csr, out=H, nnz=nnz)
 
+    info = {}
+
     def smooth(sweeps=T):
         if gs:
             return S.sfg_smooth_gs(H, classes, x0, sweeps, omega, storage=wdt, out=X, ws=ws_sm)
+        if order is not None:
+            return S.sfg_smooth_ordered(H, order, x0, sweeps, omega, storage=wdt, out=X, ws=ws_sm, info=info)
         return S.sfg_smooth(H, x0, sweeps, omega, storage=wdt, out=X, ws=ws_sm)
 
     def scores():
@@ -200,7 +208,7 @@ def scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, wdt, gs, de
         select()       # a5
 
     return {"step": step, "csr": csr, "smooth": smooth, "scores": scores, "select": select, "H": H, "X": X,
-            "sel": sel, "tau": tau, "classes": classes, "nnz": nnz}
+            "sel": sel, "tau": tau, "classes": classes, "nnz": nnz, "info": info}
 
 
 def timed_steps(torch, step, steps, warmup):
@@ -241,18 +249,27 @@ def headline(args, S, BW) -> dict:
     gs = args.smoother == "gs"
     if gs:
         omega = 1.0
+    # input preparation too: the tree's preorder, the row order of the two-sweeps-per-pass smoothing
+    order = S.sfg_tree_order(g.n, u, v, w64, tree).order if (args.sweep_pairs and not gs) else None
 
-    P = scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, wdt, gs, dev)
+    P = scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, wdt, gs, dev, order)
     ms_step = timed_steps(torch, P["step"], args.steps, args.warmup)
     value = ncand / (ms_step * 1e-3)
     nnz = P["nnz"]
 
     reps = args.sweep_reps
     t_smooth = BW.ev_time(lambda: P["smooth"](T), reps)
-    t_one = BW.ev_time(lambda: P["smooth"](1), reps)
+    pairs = bool(P["info"].get("pairs", 0))
+    if pairs:
+        # a launch takes two sweeps; the pass over 2 sweeps holds one launch (which also centres) and the layout
+        t_two = BW.ev_time(lambda: P["smooth"](2), reps)
+        t_one = t_two
+        t_sweep = (t_smooth - t_two) / (T - 2)
+    else:
+        t_one = BW.ev_time(lambda: P["smooth"](1), reps)
+        # the first sweep also centres (reads the FP64 block); the other T-1 are plain sweeps
+        t_sweep = (t_smooth - t_one) / (T - 1)
     P["smooth"](T)          # X holds the full pass again before the edge pass and selection are timed
-    # the first sweep also centres (reads the FP64 block); the other T-1 are plain sweeps
-    t_sweep = (t_smooth - t_one) / (T - 1)
     t_score = BW.ev_time(P["scores"], reps)
     t_select = BW.ev_time(P["select"], reps)
     t_csr = BW.ev_time(P["csr"], reps)
@@ -260,12 +277,12 @@ def headline(args, S, BW) -> dict:
 
     bsw = sweep_bytes(g.n, nnz, k, sx, sw)
     bsc = score_bytes(ncand, g.n, k, sx, sw, sx)
-    parts = sweep_parts(g.n, nnz, k, sx, sw, gs)
-    b_launch = sweep_bytes(g.n, nnz, k // parts, sx, sw)
-    t_launch = t_sweep / parts
+    parts = 1 if pairs else sweep_parts(g.n, nnz, k, sx, sw, gs)
+    b_launch = (2 if pairs else 1) * sweep_bytes(g.n, nnz, k // parts, sx, sw)
+    t_launch = (2 if pairs else 1) * t_sweep / parts
     achieved = b_launch / (t_launch * 1e-3) / 1e9
     smoothing_gbs = bsw / (t_sweep * 1e-3) / 1e9
-    working_set = 2 * g.n * (k // parts) * sx + (b_launch - 2 * g.n * (k // parts) * sx)
+    working_set = sweep_bytes(g.n, nnz, k // parts, sx, sw)
     # a launch whose working set fits the memory-side cache is not bound by HBM: compare it with the
     # measured copy rate of a buffer that stays in that cache
     in_cache = working_set <= MALL_BYTES
@@ -274,11 +291,14 @@ def headline(args, S, BW) -> dict:
     traffic = None
     tf = HEADLINE[name]["traffic"]
     if os.path.exists(tf) and not gs:
-        ent = json.load(open(tf)).get(args.dtype)
+        ent = json.load(open(tf)).get(args.dtype + ("_pairs" if pairs else ""))
         if ent and ent.get("src_hash") == src_hash(SWEEP_SRC):
             traffic = ent["hbm_bytes_per_launch"]
     if gs:
         kname = f"k_sweep_color (one Gauss-Seidel sweep: {P['classes'][3]} colour classes of the tree, in place)"
+    elif pairs:
+        kname = (f"k_sweep2 (two damped-Jacobi sweeps of the {k}-vector block on the tree per launch, blocks of 64 "
+                 f"rows of the tree's preorder with their 2-hop neighbourhoods in LDS)")
     elif parts > 1:
         kname = f"k_sweep (one damped-Jacobi sweep of an 8-vector column part of the {k}-vector block on the tree)"
     else:
@@ -286,7 +306,8 @@ def headline(args, S, BW) -> dict:
     roofline = {"bound": bound, "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "GB/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kname,
                 "algorithmic_bytes_per_launch": b_launch, "avg_launch_us": round(t_launch * 1e3, 2),
-                "launches_per_sweep": P["classes"][3] if gs else parts, "working_set_bytes": working_set,
+                "launches_per_sweep": P["classes"][3] if gs else (0.5 if pairs else parts),
+                "working_set_bytes": working_set,
                 # the smoothing rate of the metric: the graph counted once per sweep of the whole block
                 "smoothing_gbs": round(smoothing_gbs, 1), "smoothing_frac_of_hbm_peak":
                     round(smoothing_gbs / HBM_PEAK_GBS, 4)}
@@ -310,7 +331,8 @@ def headline(args, S, BW) -> dict:
         "roofline": roofline,
         "cpu_baseline": None,
         "copy": copy,
-        "stages_ms": {"csr": round(t_csr, 4), "smooth": round(t_smooth, 4), "smooth_1sweep": round(t_one, 4),
+        "stages_ms": {"csr": round(t_csr, 4), "smooth": round(t_smooth, 4),
+                      ("smooth_2sweeps" if pairs else "smooth_1sweep"): round(t_one, 4),
                       "sweep": round(t_sweep, 4), "score": round(t_score, 4), "select": round(t_select, 4)},
         "edges_scored_per_s_score_kernel": round(ncand / (t_score * 1e-3), 1),
         "score_gbs": round(bsc / (t_score * 1e-3) / 1e9, 1),
@@ -318,13 +340,28 @@ def headline(args, S, BW) -> dict:
     sel_main = P["sel"].clone()
     del P
     torch.cuda.empty_cache()
+    if order is not None:
+        # the single-sweep kernel in node order, for comparison (the step above does not use it)
+        P1 = scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, wdt, gs, dev)
+        P1["csr"]()
+        t1T = BW.ev_time(lambda: P1["smooth"](T), reps)
+        t11 = BW.ev_time(lambda: P1["smooth"](1), reps)
+        ts1 = (t1T - t11) / (T - 1)
+        out["single_sweep"] = {"us": round(ts1 * 1e3, 2), "gbs": round(bsw / (ts1 * 1e-3) / 1e9, 1),
+                               "frac": round(bsw / (ts1 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                               "kernel": "k_sweep (one sweep per launch, node order)"}
+        del P1
+        torch.cuda.empty_cache()
 
     # the same pass in FP32 storage and arithmetic (the surrogate comparison's storage)
     if f64 and not gs:
-        P32 = scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, torch.float32, False, dev)
+        P32 = scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, torch.float32, False, dev, order)
         ms32 = timed_steps(torch, P32["step"], args.steps, args.warmup)
         # P32["sel"] holds the selection of the last timed step, made before these smoothing timings
-        t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](1), reps)) / (T - 1)
+        if order is not None:
+            t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](2), reps)) / (T - 2)
+        else:
+            t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](1), reps)) / (T - 1)
         b32 = sweep_bytes(g.n, nnz, k, 4, 4)
         agree = float((P32["sel"].bool() & sel_main.bool()).sum().item()) / max(ksel, 1)
         out["f32"] = {"ms_per_step": round(ms32, 4), "value": round(ncand / (ms32 * 1e-3), 1),

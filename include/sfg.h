@@ -82,7 +82,8 @@ typedef enum {
     SFG_OP_TREE_ORDER = 8,     /* n nodes, m edges */
     SFG_OP_TREE_SOLVE = 9,     /* n nodes, k columns */
     SFG_OP_CSR_SELECT = 10,    /* n nodes, m = edges of the whole graph */
-    SFG_OP_MPNN_NORM = 11      /* no sizes: a fixed 512 bytes */
+    SFG_OP_MPNN_NORM = 11,     /* no sizes: a fixed 512 bytes */
+    SFG_OP_SMOOTH_ORDERED = 12 /* n nodes, k columns, t = storage dtype */
 } sfg_op;
 
 /* Which graph's embedding scores the candidates (Sec. 3.5 derives the score
@@ -169,6 +170,33 @@ sfg_status sfg_csr_select(const sfg_csr *G, const uint8_t *mask, int32_t *rowptr
 sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega,
                       const double *x0, sfg_dtype storage, int32_t final_f32, void *x,
                       void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * sfg_smooth with the rows taken in a given order, two sweeps per pass where
+ * the graph allows: the same result, bit for bit.  The rows are split into
+ * blocks of 64 consecutive entries of `order`; for each block a workgroup
+ * loads the current iterate of the block's rows and of their 1- and 2-hop
+ * neighbours into LDS, forms the next iterate of the block and its 1-hop
+ * neighbours there, and writes the one after it for the block only, so the
+ * block X is read about once and written once per two sweeps.  Every row is
+ * formed with sfg_smooth's arithmetic (entries in stored order, the same
+ * epilogue, the intermediate iterate rounded to the storage type).  The order
+ * decides how small the neighbourhoods are: a spanning tree's preorder
+ * (sfg_tree_order) keeps them to a few dozen rows on meshes and power grids.
+ *   order      [n] int32 (device): a permutation of the nodes (checked)
+ *   pairs_out  (host, may be NULL): 1 if the sweeps ran two per pass, 0 if the
+ *              call ran sfg_smooth instead: storage other than F64/F32, k not
+ *              a multiple of 4 or over 128 bytes per row, fewer than 2 sweeps,
+ *              a row over 256 entries, or a block whose neighbourhood exceeds
+ *              the LDS capacity (176 rows, 112 of them within one hop)
+ *   other arguments as sfg_smooth
+ * Workspace: sfg_workspace_bytes(SFG_OP_SMOOTH_ORDERED, n, 0, k, storage).
+ * Synchronises once (to learn whether every block fits).
+ * Errors: those of sfg_smooth; SFG_EINVAL when order is not a permutation.
+ */
+sfg_status sfg_smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps, double omega,
+                              const double *x0, sfg_dtype storage, int32_t final_f32, void *x, int32_t *pairs_out,
+                              void *ws, size_t ws_bytes, void *stream);
 
 /*
  * Random test vectors for the embedding (Sec. 3.2 smooths random vectors),

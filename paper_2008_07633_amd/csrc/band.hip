@@ -77,80 +77,102 @@ __global__ void k_gather_ids(int64_t nb, const int32_t *__restrict__ pos, const 
     if (i < nb) eids[i] = cand[pos[i]];
 }
 
-__global__ void k_seed_dist(int64_t nb, const int32_t *__restrict__ eids, const int32_t *__restrict__ u,
-                            const int32_t *__restrict__ v, int32_t *dist) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nb) return;
-    const int32_t e = eids[i];
-    dist[u[e]] = 0;
-    dist[v[e]] = 0;
+// Multi-source BFS capped at `cap` hops, frontier by frontier.  rows[] receives
+// the reached rows grouped by distance (distance 0 first) and cnt[d] the size
+// of group d; a row joins the group of the level that first claims it
+// (compare-and-swap of its distance from cap + 1), so each row appears once.
+// Appends are aggregated per wavefront: one atomic per wave and level step.
+constexpr int kBfsBlocks = 2048;
+
+__device__ __forceinline__ int32_t wave_max_i32(int32_t x) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) x = max(x, __shfl_xor(x, d, kWave));
+    return x;
 }
 
-// One BFS level: rows at distance `level` lower their neighbours to level+1.
-__global__ void k_bfs_level(int64_t n, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                            int32_t level, int32_t *dist) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n || dist[p] != level) return;
-    for (int32_t j = rowptr[p]; j < rowptr[p + 1]; ++j) {
-        const int32_t q = col[j];
-        if (dist[q] > level + 1) atomicMin(&dist[q], level + 1);
-    }
+// Lane `mine` appends q to rows[base + slot] with slot from the group counter.
+__device__ __forceinline__ void wave_append(bool mine, int32_t q, int32_t *counter, int32_t base, int32_t *rows) {
+    const unsigned long long ball = __ballot(mine);
+    if (!ball) return;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int leader = __ffsll((long long)ball) - 1;
+    int32_t at = 0;
+    if (lane == leader) at = atomicAdd(counter, __popcll(ball));
+    at = __shfl(at, leader, kWave);
+    if (mine) rows[base + at + __popcll(ball & ((1ull << lane) - 1ull))] = q;
 }
 
-// Rows per distance 0..cap: block-local counts in LDS, one global atomic per
-// bin and block (a global atomic per row serialises on the few bins).
-constexpr int kMaxBins = 1024;
-constexpr int kDistBlocks = 1024;
-
-__global__ __launch_bounds__(256) void k_dist_hist(int64_t n, const int32_t *__restrict__ dist, int32_t cap,
-                                                   int32_t *hist) {
-    __shared__ int32_t h[kMaxBins];
-    const int32_t nb = cap + 1;
-    const bool lds = nb <= kMaxBins;
-    if (lds)
-        for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) h[b] = 0;
-    __syncthreads();
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t d = dist[p];
-        if (d <= cap) atomicAdd(lds ? &h[d] : &hist[d], 1);
-    }
-    __syncthreads();
-    if (lds)
-        for (int32_t b = threadIdx.x; b < nb; b += blockDim.x)
-            if (h[b]) atomicAdd(&hist[b], h[b]);
-}
-
-// Rows grouped by distance: each block reserves one range per bin for its
-// rows (counted in a first pass over its grid-stride share), then places
-// them (LDS cursors).  The order inside a distance group is irrelevant: the
-// cone sweeps read only the previous iterate.
-__global__ __launch_bounds__(256) void k_dist_scatter(int64_t n, const int32_t *__restrict__ dist, int32_t cap,
-                                                      const int32_t *__restrict__ start, int32_t *fill,
-                                                      int32_t *rows) {
-    __shared__ int32_t cur[kMaxBins];
-    const int32_t nb = cap + 1;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t p0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (nb > kMaxBins) {       // many bins: one global atomic per row
-        for (int64_t p = p0; p < n; p += stride) {
-            const int32_t d = dist[p];
-            if (d <= cap) rows[start[d] + atomicAdd(&fill[d], 1)] = (int32_t)p;
+__global__ __launch_bounds__(256) void k_bfs_seed(int64_t nseeds, const int32_t *__restrict__ eids,
+                                                  const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                                                  int32_t unreached, int32_t *dist, int32_t *cnt, int32_t *rows) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t b = wave * kWave; b < nseeds; b += nwaves * kWave) {    // uniform per wave
+        const int64_t i = b + lane;
+        const bool live = i < nseeds;
+        const int32_t e = live ? eids[i] : 0;
+#pragma unroll
+        for (int end = 0; end < 2; ++end) {
+            const int32_t x = live ? (end ? v[e] : u[e]) : 0;
+            const bool mine = live && atomicCAS(&dist[x], unreached, 0) == unreached;
+            wave_append(mine, x, &cnt[0], 0, rows);
         }
-        return;
     }
-    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = 0;
-    __syncthreads();
-    for (int64_t p = p0; p < n; p += stride) {
-        const int32_t d = dist[p];
-        if (d <= cap) atomicAdd(&cur[d], 1);
+}
+
+// Expands group `level` (rows[begin, end), begin = sum of the earlier groups) into group level + 1.
+__global__ __launch_bounds__(256) void k_bfs_expand(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                    int32_t level, int32_t unreached, int32_t *dist, int32_t *cnt,
+                                                    int32_t *rows) {
+    int32_t begin = 0;
+    for (int32_t d = 0; d < level; ++d) begin += cnt[d];
+    const int32_t end = begin + cnt[level];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    for (int64_t b = begin + wave * kWave; b < end; b += nwaves * kWave) {    // uniform per wave
+        const int64_t i = b + lane;
+        int32_t j0 = 0, len = 0;
+        if (i < end) {
+            const int32_t p = rows[i];
+            j0 = rowptr[p];
+            len = rowptr[p + 1] - j0;
+        }
+        const int32_t steps = wave_max_i32(len);
+        for (int32_t t = 0; t < steps; ++t) {
+            int32_t q = 0;
+            bool mine = false;
+            if (t < len) {
+                q = col[j0 + t];
+                mine = dist[q] == unreached && atomicCAS(&dist[q], unreached, level + 1) == unreached;
+            }
+            wave_append(mine, q, &cnt[level + 1], end, rows);
+        }
     }
-    __syncthreads();
-    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) cur[b] = cur[b] ? start[b] + atomicAdd(&fill[b], cur[b]) : 0;
-    __syncthreads();
-    for (int64_t p = p0; p < n; p += stride) {
-        const int32_t d = dist[p];
-        if (d <= cap) rows[atomicAdd(&cur[d], 1)] = (int32_t)p;
+}
+
+// Groups of rows by hop distance (0..cap) from the endpoints of the nseeds
+// edges eids[]: rows (capacity n) and cnt (cap + 2 entries) on the device,
+// cnt also returned on the host.  Synchronises once.
+std::vector<int32_t> bfs_groups(const sfg_csr *H, int64_t nseeds, const int32_t *eids, const int32_t *u,
+                                const int32_t *v, int32_t cap, int32_t *dist, int32_t *cnt, int32_t *rows,
+                                hipStream_t s) {
+    const int64_t n = H->n;
+    fill_i32(dist, n, cap + 1, s);
+    fill_i32(cnt, cap + 2, 0, s);
+    const uint32_t sb = std::min<uint32_t>(grid_for(nseeds, 256), kBfsBlocks);
+    hipLaunchKernelGGL(k_bfs_seed, dim3(sb), dim3(256), 0, s, nseeds, eids, u, v, cap + 1, dist, cnt, rows);
+    SFG_LAUNCH_CHECK();
+    const uint32_t eb = std::min<uint32_t>(grid_for(n, 256), kBfsBlocks);
+    for (int32_t lvl = 0; lvl < cap; ++lvl) {
+        hipLaunchKernelGGL(k_bfs_expand, dim3(eb), dim3(256), 0, s, H->rowptr, H->col, lvl, cap + 1, dist, cnt, rows);
+        SFG_LAUNCH_CHECK();
     }
+    std::vector<int32_t> hh(cap + 1);
+    SFG_HIP(hipMemcpyAsync(hh.data(), cnt, sizeof(int32_t) * (cap + 1), hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    return hh;
 }
 
 __global__ void k_band_final(int64_t nc, const uint8_t *__restrict__ cls, uint8_t *sel) {
@@ -188,21 +210,9 @@ double predicted_cone_share(const sfg_csr *H, int32_t sweeps, int64_t n_cand, co
     hipLaunchKernelGGL(k_stride_sample, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, n_cand, cand, eids);
     SFG_LAUNCH_CHECK();
     int32_t *dist = A.alloc<int32_t>(n + 1);
-    fill_i32(dist, n, sweeps + 1, s);
-    hipLaunchKernelGGL(k_seed_dist, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, eids, u, v, dist);
-    SFG_LAUNCH_CHECK();
-    for (int32_t lvl = 0; lvl < sweeps; ++lvl) {
-        hipLaunchKernelGGL(k_bfs_level, dim3(grid_for(n, 256)), dim3(256), 0, s, n, H->rowptr, H->col, lvl, dist);
-        SFG_LAUNCH_CHECK();
-    }
-    int32_t *hist = A.alloc<int32_t>(sweeps + 2);
-    fill_i32(hist, sweeps + 2, 0, s);
-    const dim3 gd(std::min<uint32_t>(grid_for(n, 256), (uint32_t)kDistBlocks));
-    hipLaunchKernelGGL(k_dist_hist, gd, dim3(256), 0, s, n, dist, sweeps, hist);
-    SFG_LAUNCH_CHECK();
-    std::vector<int32_t> hh(sweeps + 1);
-    SFG_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * (sweeps + 1), hipMemcpyDeviceToHost, s));
-    SFG_HIP(hipStreamSynchronize(s));
+    int32_t *cnt = A.alloc<int32_t>(sweeps + 2);
+    int32_t *rows = A.alloc<int32_t>(n + 1);
+    const std::vector<int32_t> hh = bfs_groups(H, nb, eids, u, v, sweeps, dist, cnt, rows, s);
     // sweep t recomputes the rows within sweeps-1-t hops
     int64_t within = 0, cone = 0;
     std::vector<int64_t> upto(sweeps + 1);
@@ -252,26 +262,13 @@ void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, c
     }
     int64_t cone_rows = 0;
     double *sB = A.alloc<double>(nB + 1);
-    std::vector<int32_t> st;     // distance-group starts (host; outlives the async copy below)
+    std::vector<int32_t> st;     // distance-group starts (host)
     if (nB > 0) {
-        // dependency cone: hop distance (capped at sweeps+1) from the band's endpoints
+        // dependency cone: the rows within `sweeps` hops of the band's endpoints, grouped by distance
         int32_t *dist = A.alloc<int32_t>(n + 1);
-        fill_i32(dist, n, sweeps + 1, s);
-        hipLaunchKernelGGL(k_seed_dist, dim3(grid_for(nB, 256)), dim3(256), 0, s, nB, eB, u, v, dist);
-        SFG_LAUNCH_CHECK();
-        for (int32_t lvl = 0; lvl < sweeps; ++lvl) {
-            hipLaunchKernelGGL(k_bfs_level, dim3(grid_for(n, 256)), dim3(256), 0, s, n, H64->rowptr, H64->col, lvl,
-                               dist);
-            SFG_LAUNCH_CHECK();
-        }
-        int32_t *hist = A.alloc<int32_t>(sweeps + 2);
-        fill_i32(hist, sweeps + 2, 0, s);
-        const dim3 gd(std::min<uint32_t>(grid_for(n, 256), (uint32_t)kDistBlocks));
-        hipLaunchKernelGGL(k_dist_hist, gd, dim3(256), 0, s, n, dist, sweeps, hist);
-        SFG_LAUNCH_CHECK();
-        std::vector<int32_t> hh(sweeps + 1);
-        SFG_HIP(hipMemcpyAsync(hh.data(), hist, sizeof(int32_t) * (sweeps + 1), hipMemcpyDeviceToHost, s));
-        SFG_HIP(hipStreamSynchronize(s));
+        int32_t *cnt = A.alloc<int32_t>(sweeps + 2);
+        int32_t *rows = A.alloc<int32_t>(n + 1);
+        const std::vector<int32_t> hh = bfs_groups(H64, nB, eB, u, v, sweeps, dist, cnt, rows, s);
         st.assign(sweeps + 2, 0);
         for (int32_t d = 0; d <= sweeps; ++d) st[d + 1] = st[d] + hh[d];
         // sweep t (0-based) recomputes the rows within sweeps-1-t hops
@@ -282,14 +279,7 @@ void band_rescore(const sfg_csr *H64, int32_t k, int32_t sweeps, double omega, c
         }
         double *X = nullptr;
         if (4 * cone_rows <= (int64_t)sweeps * n) {
-            // rows ordered by distance
-            int32_t *start = A.alloc<int32_t>(sweeps + 2);
-            int32_t *fill = A.alloc<int32_t>(sweeps + 2);
-            fill_i32(fill, sweeps + 2, 0, s);
-            SFG_HIP(hipMemcpyAsync(start, st.data(), sizeof(int32_t) * (sweeps + 2), hipMemcpyHostToDevice, s));
-            int32_t *rows = A.alloc<int32_t>(st[sweeps + 1] + 1);
-            hipLaunchKernelGGL(k_dist_scatter, gd, dim3(256), 0, s, n, dist, sweeps, start, fill, rows);
-            SFG_LAUNCH_CHECK();
+            // rows are already ordered by distance
             double *b0 = A.alloc<double>((size_t)n * k);
             double *b1 = A.alloc<double>((size_t)n * k);
             double *mean = A.alloc<double>(k);

@@ -26,6 +26,7 @@
 //     graphs) are taken out and swept by a whole workgroup each.
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "common.hpp"
@@ -719,6 +720,287 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
     if (lr.side) SFG_HIP(hipStreamWaitEvent(s, lr.ez, 0));   // join: the last hub rows before anything after
 }
 
+// ------------------------------------------------------------------ two sweeps per pass through LDS
+// Rows are taken in blocks of kMpkRows consecutive entries of a caller's
+// order (a permutation of the nodes; a spanning tree's preorder keeps a
+// block's neighbourhood small).  For block b with rows R0:
+//   R1 = neighbours of R0 outside R0,  R2 = neighbours of R1 outside R0 and R1.
+// One workgroup loads X_t for R0, R1 and R2 into LDS, computes X_t+1 for R0
+// and R1 (all their neighbours are loaded), then X_t+2 for R0 (all theirs are
+// in R0 and R1), and writes only that: X is read about (1 + |R1 ∪ R2| / |R0|)
+// times and written once per two sweeps instead of twice each.  Every row's
+// value is formed with the single sweep's arithmetic -- entries in stored
+// order, the same epilogue, the intermediate iterate rounded to the storage
+// type -- so the result is bit-identical.
+constexpr int kMpkRows = 64;      // R0 rows per block
+constexpr int kMpk01 = 112;       // capacity of R0 + R1
+constexpr int kMpkSlots = 176;    // capacity of R0 + R1 + R2
+constexpr int kMpkCand = 1024;    // halo candidates per discovery step
+constexpr int kMpkRowBytes = 128; // row width the LDS holds: 16 FP64 or 32 FP32 columns
+constexpr int kMpkLongRow = 256;  // rows longer than this are left to the single sweep (see k_sweep_long)
+
+__device__ __forceinline__ bool lds_contains(const int32_t *a, int len, int32_t key) {
+    int lo = 0, hi = len;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < len && a[lo] == key;
+}
+
+// In-place ascending bitonic sort of len (a power of two) keys by 256 threads.
+template <typename K>
+__device__ void lds_bitonic(K *a, int len) {
+    for (int size = 2; size <= len; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < len / 2; i += blockDim.x) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const K x = a[lo], y = a[hi];
+                if ((x > y) == up) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+}
+
+// Sorted unique keys of cand[0, nc) (sorted in place, padded with INT_MAX to
+// kMpkCand) into out[]; returns their number.  All 256 threads call it.
+__device__ int lds_sort_unique(int32_t *cand, int nc, int32_t *out, int cap, int32_t *scratch) {
+    for (int i = nc + threadIdx.x; i < kMpkCand; i += blockDim.x) cand[i] = 0x7fffffff;
+    __syncthreads();
+    lds_bitonic(cand, kMpkCand);
+    // keep the first of each run: 4 candidates per thread, then a scan of the per-thread counts
+    constexpr int per = kMpkCand / 256;
+    const int t = threadIdx.x;
+    int mine = 0;
+    for (int i = t * per; i < t * per + per; ++i)
+        mine += (i < nc && (i == 0 || cand[i] != cand[i - 1])) ? 1 : 0;
+    scratch[t] = mine;
+    __syncthreads();
+    if (t == 0) {
+        int run = 0;
+        for (int i = 0; i < 256; ++i) {
+            const int c = scratch[i];
+            scratch[i] = run;
+            run += c;
+        }
+        scratch[256] = run;
+    }
+    __syncthreads();
+    int at = scratch[t];
+    for (int i = t * per; i < t * per + per; ++i)
+        if (i < nc && (i == 0 || cand[i] != cand[i - 1])) {
+            if (at < cap) out[at] = cand[i];
+            ++at;
+        }
+    const int total = scratch[256];
+    __syncthreads();
+    return total;
+}
+
+// Order check: every order[i] in [0, n) and no node twice (seen[] zeroed by the caller).
+__global__ void k_mpk_check(int64_t n, const int32_t *__restrict__ order, int32_t *seen, int32_t *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = order[i];
+    if (v < 0 || v >= n || atomicExch(&seen[v], 1) != 0) atomicOr(flag, 1);
+}
+
+// Halo discovery for one block per workgroup.  fill == 0: the counts s0, s1,
+// s2 of every block (flag bit 2 when a block exceeds the capacities); fill ==
+// 1: the slots (R0 in order, then R1 and R2 ascending) from off[b] on, and the
+// node-sorted slot table (node << 16 | slot).
+__global__ __launch_bounds__(256) void k_mpk_build(int64_t n, const int32_t *__restrict__ order,
+                                                   const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, int fill, int32_t *cnt,
+                                                   int32_t *sizes, const int32_t *__restrict__ off,
+                                                   int32_t *slot_node, int64_t *table, int32_t *flag) {
+    __shared__ int32_t r0[kMpkRows];
+    __shared__ int32_t cand[kMpkCand];
+    __shared__ int32_t r1[kMpk01];
+    __shared__ int32_t r2[kMpkSlots];
+    __shared__ int32_t scratch[257];
+    __shared__ int64_t keys[256];
+    __shared__ int nc_sh;
+    const int64_t base = (int64_t)blockIdx.x * kMpkRows;
+    const int s0 = (int)(n - base < kMpkRows ? n - base : kMpkRows);
+    const int t = threadIdx.x;
+    // entries outside [0, n) are skipped here (k_mpk_check refuses such an order before the layout is used)
+    if (t < kMpkRows) {
+        const int32_t v = t < s0 ? order[base + t] : 0x7fffffff;
+        r0[t] = (v >= 0 && v < n) ? v : 0x7fffffff;
+    }
+    if (t == 0) nc_sh = 0;
+    __syncthreads();
+    lds_bitonic(r0, kMpkRows);
+    // R1: neighbours of R0 outside it.  A row over kMpkLongRow entries marks the
+    // block as not taken: the single sweep adds such rows of a reduced-precision
+    // block in another order, and hubs make large halos anyway.
+    __shared__ int long_sh;
+    if (t == 0) long_sh = 0;
+    __syncthreads();
+    for (int i = t; i < s0; i += blockDim.x) {
+        const int32_t p = order[base + i];
+        if (p < 0 || p >= n) continue;
+        if (rowptr[p + 1] - rowptr[p] > kMpkLongRow) long_sh = 1;
+        for (int32_t j = rowptr[p]; j < rowptr[p + 1]; ++j) {
+            const int32_t q = col[j];
+            if (!lds_contains(r0, s0, q)) {
+                const int at = atomicAdd(&nc_sh, 1);
+                if (at < kMpkCand) cand[at] = q;
+            }
+        }
+    }
+    __syncthreads();
+    int nc = nc_sh;
+    bool over = nc > kMpkCand || long_sh;
+    const int s1 = lds_sort_unique(cand, over ? kMpkCand : nc, r1, kMpk01 - s0, scratch);
+    over = over || s0 + s1 > kMpk01;
+    const int s1c = s0 + s1 > kMpk01 ? kMpk01 - s0 : s1;
+    // R2: neighbours of R1 outside R0 and R1
+    if (t == 0) nc_sh = 0;
+    __syncthreads();
+    for (int i = t; i < s1c; i += blockDim.x) {
+        const int32_t p = r1[i];
+        for (int32_t j = rowptr[p]; j < rowptr[p + 1]; ++j) {
+            const int32_t q = col[j];
+            if (!lds_contains(r0, s0, q) && !lds_contains(r1, s1c, q)) {
+                const int at = atomicAdd(&nc_sh, 1);
+                if (at < kMpkCand) cand[at] = q;
+            }
+        }
+    }
+    __syncthreads();
+    nc = nc_sh;
+    over = over || nc > kMpkCand;
+    const int s2 = lds_sort_unique(cand, nc > kMpkCand ? kMpkCand : nc, r2, kMpkSlots - s0 - s1c, scratch);
+    over = over || s0 + s1 + s2 > kMpkSlots;
+    if (!fill) {
+        if (t == 0) {
+            cnt[4 * blockIdx.x] = s0;
+            cnt[4 * blockIdx.x + 1] = s1;
+            cnt[4 * blockIdx.x + 2] = s2;
+            cnt[4 * blockIdx.x + 3] = s0 + s1 + s2;
+            sizes[blockIdx.x] = over ? 0 : s0 + s1 + s2;
+            if (over) atomicOr(flag, 2);
+        }
+        return;
+    }
+    if (over) return;     // the caller does not use the layout then
+    const int S = s0 + s1 + s2;
+    const int32_t o = off[blockIdx.x];
+    for (int i = t; i < 256; i += blockDim.x) {
+        int64_t key = 0x7fffffffffffffffll;
+        if (i < S) {
+            const int32_t v = i < s0 ? order[base + i] : (i < s0 + s1 ? r1[i - s0] : r2[i - s0 - s1]);
+            slot_node[o + i] = v;
+            key = ((int64_t)v << 16) | i;
+        }
+        keys[i] = key;
+    }
+    __syncthreads();
+    lds_bitonic(keys, 256);
+    for (int i = t; i < S; i += blockDim.x) table[o + i] = keys[i];
+}
+
+// Slot of node q in a block's node-sorted table (q is always there).
+__device__ __forceinline__ int mpk_slot(const int64_t *tab, int len, int32_t q) {
+    int lo = 0, hi = len - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int32_t)(tab[mid] >> 16) < q) lo = mid + 1;
+        else hi = mid;
+    }
+    return (int)(tab[lo] & 0xffff);
+}
+
+// Two sweeps of one block (see above).  k columns of TX, k * sizeof(TX) <=
+// kMpkRowBytes, VPL columns per lane; TIN the source block's type (the raw
+// FP64 block when CENTER: centred on load, as the single sweep does).
+template <typename TIN, typename TX, typename TW, typename TA, int VPL, bool CENTER>
+__global__ __launch_bounds__(256) void k_sweep2(int32_t k, const int32_t *__restrict__ cnt,
+                                                const int32_t *__restrict__ off,
+                                                const int32_t *__restrict__ slot_node,
+                                                const int64_t *__restrict__ table,
+                                                const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                                const TW *__restrict__ val, const TW *__restrict__ deg,
+                                                const TIN *__restrict__ x, const double *__restrict__ mean,
+                                                TX *__restrict__ y, TA keep, TA omega) {
+    __shared__ __align__(16) unsigned char xs_raw[kMpkSlots * kMpkRowBytes];
+    __shared__ __align__(16) unsigned char x1_raw[kMpk01 * kMpkRowBytes];
+    __shared__ int64_t tab[kMpkSlots];
+    __shared__ int32_t nodes[kMpkSlots];
+    TX *xs = reinterpret_cast<TX *>(xs_raw);
+    TX *x1 = reinterpret_cast<TX *>(x1_raw);
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int s0 = cnt[4 * b], s1 = cnt[4 * b + 1], S = cnt[4 * b + 3];
+    const int32_t o = off[b];
+    const int t = threadIdx.x;
+    const int lpr = k / VPL;
+    const int rows_per_pass = 256 / lpr;
+    const int ri0 = t / lpr, c = (t - ri0 * lpr) * VPL;
+    const bool lane_on = ri0 < rows_per_pass;       // 256 % lpr lanes idle
+    for (int i = t; i < S; i += 256) {
+        nodes[i] = slot_node[o + i];
+        tab[i] = table[o + i];
+    }
+    double mo[VPL];
+#pragma unroll
+    for (int i = 0; i < VPL; ++i) mo[i] = (CENTER && lane_on) ? mean[c + i] : 0.0;
+    __syncthreads();
+    // X_t of every slot
+    if (lane_on)
+        for (int r = ri0; r < S; r += rows_per_pass) {
+            TA v[VPL];
+            load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)nodes[r] * k + c, mo, v);
+            Vec<TX, VPL> st;
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) st.v[i] = cvt<TX>(v[i]);
+            *reinterpret_cast<Vec<TX, VPL> *>(xs + r * k + c) = st;
+        }
+    __syncthreads();
+    // X_t+1 of R0 and R1 (into x1), then X_t+2 of R0 (into y)
+    for (int phase = 0; phase < 2; ++phase) {
+        const TX *src = phase == 0 ? xs : x1;
+        const int nrows = phase == 0 ? s0 + s1 : s0;    // R0's neighbours all have slots below s0 + s1
+        if (lane_on)
+            for (int r = ri0; r < nrows; r += rows_per_pass) {
+                const int32_t p = nodes[r];
+                const int32_t j0 = rowptr[p], j1 = rowptr[p + 1];
+                TA acc[VPL];
+#pragma unroll
+                for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
+                for (int32_t j = j0; j < j1; ++j) {
+                    const int sl = mpk_slot(tab, S, col[j]);
+                    const TA w = cvt<TA>(val[j]);
+                    const Vec<TX, VPL> xv = *reinterpret_cast<const Vec<TX, VPL> *>(src + sl * k + c);
+#pragma unroll
+                    for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], w, cvt<TA>(xv.v[i]));
+                }
+                const Vec<TX, VPL> sv = *reinterpret_cast<const Vec<TX, VPL> *>(src + r * k + c);
+                const TA d = cvt<TA>(deg[p]);
+                Vec<TX, VPL> out;
+#pragma unroll
+                for (int i = 0; i < VPL; ++i) {
+                    const TA a = keep * cvt<TA>(sv.v[i]);
+                    const TA q = acc[i] / d;
+                    const TA bo = omega * q;
+                    out.v[i] = cvt<TX>(a + bo);
+                }
+                if (phase == 0)
+                    *reinterpret_cast<Vec<TX, VPL> *>(x1 + r * k + c) = out;
+                else
+                    *reinterpret_cast<Vec<TX, VPL> *>(y + (int64_t)p * k + c) = out;
+            }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 // FP64 smoothing restricted to a dependency cone (precision form).  rows_by_dist
@@ -878,6 +1160,120 @@ void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const dou
     }
 }
 
+// Two-sweeps-per-pass smoothing in a caller's row order (see k_sweep2).
+struct MpkPlan {
+    int32_t *cnt, *sizes, *off, *scan, *slot_node, *seen, *flag;
+    int64_t *table;
+};
+
+int64_t mpk_blocks(int64_t n) { return (n + kMpkRows - 1) / kMpkRows; }
+
+MpkPlan plan_mpk(Carver &c, int64_t n) {
+    const int64_t nb = mpk_blocks(n);
+    MpkPlan p;
+    p.cnt = c.take<int32_t>(4 * nb);
+    p.sizes = c.take<int32_t>(nb + 1);
+    p.off = c.take<int32_t>(nb + 1);
+    p.scan = c.take<int32_t>(scan_scratch_ints(nb + 1));
+    p.slot_node = c.take<int32_t>(nb * kMpkSlots);
+    p.table = c.take<int64_t>(nb * kMpkSlots);
+    p.seen = c.take<int32_t>(n + 1);
+    p.flag = c.take<int32_t>(1);
+    return p;
+}
+
+size_t smooth_ordered_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage) {
+    Carver c(nullptr);
+    plan_smooth(c, n, k, storage);
+    plan_mpk(c, n);
+    return c.used + 512;
+}
+
+namespace {
+
+template <typename TX, bool CENTER>
+void launch_sweep2(const sfg_csr *H, int32_t k, const MpkPlan &m, int64_t nb, const void *x, const double *mean,
+                   TX *y, double omega, hipStream_t s) {
+    using TIN = typename std::conditional<CENTER, double, TX>::type;
+    constexpr int VPL = 4;
+    hipLaunchKernelGGL((k_sweep2<TIN, TX, TX, TX, VPL, CENTER>), dim3((uint32_t)nb), dim3(256), 0, s, k, m.cnt, m.off,
+                       m.slot_node, m.table, H->rowptr, H->col, (const TX *)H->val, (const TX *)H->deg,
+                       (const TIN *)x, mean, y, (TX)(1.0 - omega), (TX)omega);
+    SFG_LAUNCH_CHECK();
+}
+
+template <typename TX>
+void run_smooth_pairs(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, void *xout,
+                      const SmoothPlan &p, const MpkPlan &m, int64_t nb, hipStream_t s) {
+    launch_column_means<double>(x0, H->n, k, p.partial, p.mean, s);
+    TX *b0 = (TX *)p.buf0, *b1 = (TX *)p.buf1;
+    const int32_t pairs = sweeps / 2;
+    const TX *src = nullptr;
+    for (int32_t q = 0; q < pairs; ++q) {
+        const bool last = (q == pairs - 1) && sweeps % 2 == 0;
+        TX *dst = last ? (TX *)xout : (q % 2 == 0 ? b0 : b1);
+        if (q == 0)
+            launch_sweep2<TX, true>(H, k, m, nb, x0, p.mean, dst, omega, s);
+        else
+            launch_sweep2<TX, false>(H, k, m, nb, src, nullptr, dst, omega, s);
+        src = dst;
+    }
+    if (sweeps % 2 == 1)    // the odd last sweep: a single sweep in node order
+        launch_sweep<TX, TX, TX, TX, TX, false>(H, k, src, nullptr, (TX *)xout, omega, s);
+}
+
+}  // namespace
+
+// Same result as smooth(); see sfg_smooth_ordered in the header.  Returns 1
+// when the sweeps ran two per pass, 0 when the plain path ran.
+int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps, double omega,
+                   const double *x0, sfg_dtype storage, int32_t final_f32, void *x, void *ws, size_t ws_bytes,
+                   hipStream_t s) {
+    SFG_REQUIRE(H && order, SFG_EINVAL, "smooth_ordered: null pointer");
+    SFG_REQUIRE(ws_bytes >= smooth_ordered_workspace_bytes(H->n, k < 1 ? 1 : k, storage), SFG_EWORKSPACE,
+                "smooth_ordered: workspace too small");
+    const int64_t n = H->n;
+    Carver c(ws);
+    SmoothPlan p = plan_smooth(c, n, k < 1 ? 1 : k, storage);
+    MpkPlan m = plan_mpk(c, n);
+    // the order must be a permutation of the nodes, whichever path runs
+    fill_i32(m.seen, n, 0, s);
+    fill_i32(m.flag, 1, 0, s);
+    hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, m.seen, m.flag);
+    SFG_LAUNCH_CHECK();
+    const size_t sx = dtype_size(storage);
+    const bool shape_ok = (storage == SFG_F64 || storage == SFG_F32) && H->vt == storage && k >= 1 &&
+                          k % 4 == 0 && (size_t)k * sx <= (size_t)kMpkRowBytes && sweeps >= 2 &&
+                          H->nnz >= 1 && H->col && H->val;
+    const int64_t nb = mpk_blocks(n);
+    if (shape_ok && env_int("SFG_SWEEP_PAIRS", 1) != 0) {
+        hipLaunchKernelGGL(k_mpk_build, dim3((uint32_t)nb), dim3(256), 0, s, n, order, H->rowptr, H->col, 0, m.cnt,
+                           m.sizes, m.off, m.slot_node, m.table, m.flag);
+        SFG_LAUNCH_CHECK();
+    }
+    int32_t flag = 0;
+    SFG_HIP(hipMemcpyAsync(&flag, m.flag, sizeof(flag), hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    SFG_REQUIRE(!(flag & 1), SFG_EINVAL, "smooth_ordered: order is not a permutation of the nodes");
+    if (!shape_ok || env_int("SFG_SWEEP_PAIRS", 1) == 0 || (flag & 2)) {
+        // the workspace starts with the plain smoothing's layout
+        smooth(H, k, sweeps, omega, x0, storage, final_f32, x, ws, smooth_workspace_bytes(n, k < 1 ? 1 : k, storage),
+               s, -1);
+        return 0;
+    }
+    exclusive_scan_i32(m.sizes, m.off, nb, m.scan, s);
+    hipLaunchKernelGGL(k_mpk_build, dim3((uint32_t)nb), dim3(256), 0, s, n, order, H->rowptr, H->col, 1, m.cnt,
+                       m.sizes, m.off, m.slot_node, m.table, m.flag);
+    SFG_LAUNCH_CHECK();
+    SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_ordered: omega must be in (0, 1]");
+    SFG_REQUIRE(x0 && x && H->deg && H->rowptr, SFG_EINVAL, "smooth_ordered: null pointer");
+    if (storage == SFG_F64)
+        run_smooth_pairs<double>(H, k, sweeps, omega, x0, x, p, m, nb, s);
+    else
+        run_smooth_pairs<float>(H, k, sweeps, omega, x0, x, p, m, nb, s);
+    return 1;
+}
+
 // Column means of a block (exact to double-double before one rounding);
 // used for the affinity's centring.
 void column_means(const void *x, sfg_dtype xt, int64_t n, int32_t k, double *mean, void *partial_ws,
@@ -894,6 +1290,16 @@ void column_means(const void *x, sfg_dtype xt, int64_t n, int32_t k, double *mea
 size_t column_means_partial_bytes(int64_t n, int32_t k) { return (size_t)colsum_blocks(n) * k * sizeof(DD); }
 
 }  // namespace sfg
+
+extern "C" sfg_status sfg_smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps,
+                                         double omega, const double *x0, sfg_dtype storage, int32_t final_f32,
+                                         void *x, int32_t *pairs_out, void *ws, size_t ws_bytes, void *stream) {
+    return sfg::guard([&] {
+        const int used = sfg::smooth_ordered(H, order, k, sweeps, omega, x0, storage, final_f32, x, ws, ws_bytes,
+                                             sfg::as_stream(stream));
+        if (pairs_out) *pairs_out = used;
+    });
+}
 
 extern "C" sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0,
                                  sfg_dtype storage, int32_t final_f32, void *x, void *ws, size_t ws_bytes,

@@ -18,6 +18,7 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
                const uint8_t *mask, int32_t *rowptr, int32_t *col, void *val, int32_t *eid, void *deg, void *ws,
                size_t ws_bytes, hipStream_t s);
 size_t smooth_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
+size_t smooth_ordered_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
 size_t color_workspace_bytes(int64_t n);
 size_t tree_order_workspace_bytes(int64_t n, int64_t m);
 size_t tree_solve_workspace_bytes(int64_t n, int32_t k);
@@ -831,6 +832,7 @@ extern "C" size_t sfg_workspace_bytes(int op, int64_t n, int64_t m, int32_t k, s
         case SFG_OP_TREE_SOLVE: return sfg::tree_solve_workspace_bytes(n < 1 ? 1 : n, k < 1 ? 1 : k);
         case SFG_OP_CSR_SELECT: return sfg::csr_select_workspace_bytes(n, m);
         case SFG_OP_MPNN_NORM: return 512;
+        case SFG_OP_SMOOTH_ORDERED: return sfg::smooth_ordered_workspace_bytes(n < 1 ? 1 : n, k < 1 ? 1 : k, t);
         default: return 0;
     }
 }

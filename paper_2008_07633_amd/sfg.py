@@ -31,7 +31,7 @@ STATUS = {0: "SFG_OK", 1: "SFG_EINVAL", 2: "SFG_ENOTCONN", 3: "SFG_ENOMEM", 4: "
           5: "SFG_EWORKSPACE", 6: "SFG_EUNSUPPORTED", 7: "SFG_ENUMERIC"}
 
 OP_MPNN_FORWARD, OP_MPNN_TRAIN, OP_COLOR, OP_TREE_ORDER, OP_TREE_SOLVE, OP_CSR_SELECT = 5, 6, 7, 8, 9, 10
-OP_MPNN_NORM = 11
+OP_MPNN_NORM, OP_SMOOTH_ORDERED = 11, 12
 SMOOTH_JACOBI, SMOOTH_GAUSS_SEIDEL = 0, 1
 
 EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_smooth", "sfg_edge_scores",
@@ -39,7 +39,7 @@ EXPORTED = ["sfg_workspace_bytes", "sfg_last_error", "sfg_laplacian_csr", "sfg_s
             "sfg_mpnn_param_count", "sfg_mpnn_features", "sfg_mpnn_forward", "sfg_mpnn_loss_grad", "sfg_mpnn_adam",
             "sfg_color", "sfg_smooth_gs", "sfg_random_block", "sfg_tree_order", "sfg_tree_solve",
             "sfg_kappa_estimate", "sfg_csr_select", "sfg_pcg", "sfg_select_topk_noalloc", "sfg_mpnn_fit_norm",
-            "sfg_mpnn_standardize", "sfg_mpnn_save", "sfg_mpnn_load"]
+            "sfg_mpnn_standardize", "sfg_mpnn_save", "sfg_mpnn_load", "sfg_smooth_ordered"]
 
 
 class SfgError(RuntimeError):
@@ -129,6 +129,7 @@ def lib() -> ctypes.CDLL:
         L.sfg_last_error.restype = ctypes.c_char_p
         L.sfg_laplacian_csr.argtypes = [I64, I64, P, P, P, I, P, P, P, P, P, P, P, P, S, P]
         L.sfg_smooth.argtypes = [P, I32, I32, D, P, I, I32, P, P, S, P]
+        L.sfg_smooth_ordered.argtypes = [P, P, I32, I32, D, P, I, I32, P, P, P, S, P]
         L.sfg_edge_scores.argtypes = [P, I, I64, I32, I64, P, P, P, P, I, P, I, P]
         L.sfg_select_topk.argtypes = [P, I, I64, I64, P, P, P, P, S, P]
         L.sfg_select_topk_noalloc.argtypes = [P, I, I64, I64, P, P, P, P]
@@ -355,6 +356,30 @@ def sfg_smooth(H: Csr, x0: torch.Tensor, sweeps: int, omega: float = 0.5, storag
     hs = H.struct()
     _check(lib().sfg_smooth(ctypes.byref(hs), k, sweeps, float(omega), _ptr(x0), st, int(bool(final_f32)),
                             _ptr(out, "out", (odt,), n * k), _ptr(ws, "ws", _U8), ws.numel(), _stream()))
+    return out
+
+
+def sfg_smooth_ordered(H: Csr, order: torch.Tensor, x0: torch.Tensor, sweeps: int, omega: float = 0.5,
+                       storage=torch.float64, final_f32: bool = False, out: Optional[torch.Tensor] = None,
+                       ws: Optional[torch.Tensor] = None, info: Optional[dict] = None) -> torch.Tensor:
+    """sfg_smooth with the rows taken in ``order`` (a permutation, e.g. a spanning tree's preorder), two
+    sweeps per pass where the graph allows; the same bits.  ``info["pairs"]`` tells which path ran."""
+    n, k = _block(x0, "x0", _F64, rows=H.n)
+    _chk(order, "order", _I32, n)
+    st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
+    odt = torch.float32 if (final_f32 and st in (F16, BF16)) else _SFG_TO_TORCH[st]
+    if out is None:
+        out = torch.empty((n, k), dtype=odt, device=x0.device)
+    _chk(out, "out", (odt,), n * k)
+    if ws is None:
+        ws = _ws(sfg_workspace_bytes(OP_SMOOTH_ORDERED, n, 0, k, st), x0.device)
+    hs = H.struct()
+    pairs = ctypes.c_int32(0)
+    _check(lib().sfg_smooth_ordered(ctypes.byref(hs), _ptr(order), k, sweeps, float(omega), _ptr(x0), st,
+                                    int(bool(final_f32)), _ptr(out), ctypes.byref(pairs), _ptr(ws, "ws", _U8),
+                                    ws.numel(), _stream()))
+    if info is not None:
+        info["pairs"] = int(pairs.value)
     return out
 
 

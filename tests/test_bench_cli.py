@@ -81,7 +81,8 @@ def test_bench_json_line_on_the_gpu():
     roof = d["roofline"]
     # the FP64 tree sweep of the 8M-node mesh moves 2.3 GB: far beyond the memory-side cache
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
-    assert roof["working_set_bytes"] > 256 << 20 and roof["launches_per_sweep"] == 1
+    # two sweeps per launch in the tree's preorder (k_sweep2), or one per launch
+    assert roof["working_set_bytes"] > 256 << 20 and roof["launches_per_sweep"] in (0.5, 1)
     assert 0 < roof["frac"] <= 1 and abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
     assert "f32" in d and d["f32"]["selection_agreement_with_f64"] > 0.99
 

@@ -1,0 +1,123 @@
+"""sfg_smooth_ordered: two sweeps per pass through LDS, in a given row order,
+bit-identical to sfg_smooth (and so to the oracle's smoothing) on every path
+it takes -- the fused pairs, the odd last sweep, and the plain fallback when a
+block's neighbourhood does not fit."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2008_07633_amd import sfg
+
+    sfg.lib()
+    return sfg
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def tree_and_order(S, g):
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    tree, comps = S.sfg_spanning_tree(g.n, u, v, w)
+    assert comps == 1
+    T = S.sfg_tree_order(g.n, u, v, w, tree)
+    return u, v, w, tree, T.order
+
+
+GRAPHS = {
+    "mesh_17x13x11": lambda: W.mesh3d(17, 13, 11, seed=501, wdist=("lognormal", 0.0, 1.5)),
+    "pgrid_150x140": lambda: W.powergrid(150, 140, 0.02, seed=502),
+    "knn_20k": lambda: W.knn3d(20000, 10, seed=503),
+    "path_50": lambda: W.grid2d(1, 50, seed=504),
+}
+
+
+@pytest.mark.parametrize("name", list(GRAPHS))
+@pytest.mark.parametrize("storage", [torch.float64, torch.float32])
+def test_ordered_tree_sweeps_are_bit_identical(S, name, storage):
+    g = GRAPHS[name]()
+    u, v, w, tree, order = tree_and_order(S, g)
+    H = S.sfg_laplacian_csr(g.n, u, v, w.to(storage), mask=tree)
+    for k, sweeps in ((16, 20), (16, 7), (8, 2), (4, 3), (12, 5)):
+        X0 = dev(W.random_block(g.n, k, 510 + k + sweeps))
+        ref = S.sfg_smooth(H, X0, sweeps, 0.5, storage=storage)
+        info = {}
+        got = S.sfg_smooth_ordered(H, order, X0, sweeps, 0.5, storage=storage, info=info)
+        assert torch.equal(got, ref), (name, k, sweeps)
+        # the tree's preorder keeps every block's neighbourhood within the LDS capacity
+        assert info["pairs"] == 1, (name, k, sweeps)
+
+
+@pytest.mark.parametrize("storage", [torch.float64, torch.float32])
+def test_ordered_sweeps_on_a_whole_graph(S, storage):
+    # the 3-D mesh itself in its tree's preorder: six neighbours per row, larger neighbourhoods
+    g = W.mesh3d(12, 11, 10, seed=520, wdist=("lognormal", 0.0, 1.0))
+    u, v, w, tree, order = tree_and_order(S, g)
+    H = S.sfg_laplacian_csr(g.n, u, v, w.to(storage))
+    X0 = dev(W.random_block(g.n, 16, 521))
+    ref = S.sfg_smooth(H, X0, 9, 0.5, storage=storage)
+    info = {}
+    got = S.sfg_smooth_ordered(H, order, X0, 9, 0.5, storage=storage, info=info)
+    assert torch.equal(got, ref) and info["pairs"] in (0, 1)
+
+
+def test_ordered_falls_back_and_checks(S, orc):
+    g = W.grid2d(64, 64, seed=530)
+    u, v, w = dev(g.u), dev(g.v), dev(g.w)
+    H = S.sfg_laplacian_csr(g.n, u, v, w)
+    X0 = dev(W.random_block(g.n, 8, 531))
+    ref = S.sfg_smooth(H, X0, 6, 0.5)
+    # node order on the whole grid: a block of 64 nodes is one grid row, whose neighbours above and below
+    # exceed the one-hop capacity, so the plain path runs
+    info = {}
+    ident = torch.arange(g.n, dtype=torch.int32, device="cuda")
+    got = S.sfg_smooth_ordered(H, ident, X0, 6, 0.5, info=info)
+    assert torch.equal(got, ref) and info["pairs"] == 0
+    # and it is the oracle's smoothing
+    Hc = orc.laplacian_csr(g.n, g.u, g.v, g.w)
+    assert np.array_equal(got.cpu().numpy(), orc.smooth(Hc, orc.center(X0.cpu().numpy())[0], 6, 0.5))
+    # shapes the pairs do not take: zero and one sweep, 16-bit storage, k not a multiple of 4
+    tree, _ = S.sfg_spanning_tree(g.n, u, v, w)
+    Ht = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
+    order = S.sfg_tree_order(g.n, u, v, w, tree).order
+    for sweeps, k in ((0, 8), (1, 8), (5, 6)):
+        X0k = dev(W.random_block(g.n, k, 532 + k))
+        info = {}
+        got = S.sfg_smooth_ordered(Ht, order, X0k, sweeps, 0.5, info=info)
+        assert torch.equal(got, S.sfg_smooth(Ht, X0k, sweeps, 0.5)) and info["pairs"] == 0
+    Ht32 = S.sfg_laplacian_csr(g.n, u, v, w.float(), mask=tree)
+    info = {}
+    got = S.sfg_smooth_ordered(Ht32, order, X0, 6, 0.5, storage=torch.float16, final_f32=True, info=info)
+    assert torch.equal(got, S.sfg_smooth(Ht32, X0, 6, 0.5, storage=torch.float16, final_f32=True))
+    assert info["pairs"] == 0
+    # an order that is not a permutation is refused
+    bad = order.clone()
+    bad[5] = bad[6]
+    with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+        S.sfg_smooth_ordered(Ht, bad, X0, 6, 0.5)
+    bad = order.clone()
+    bad[0] = g.n
+    with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+        S.sfg_smooth_ordered(Ht, bad, X0, 6, 0.5)
+
+
+def test_ordered_matches_the_oracle_on_a_power_grid_tree(S, orc):
+    g = W.powergrid(120, 110, 0.02, seed=540)
+    u, v, w, tree, order = tree_and_order(S, g)
+    t = tree.cpu().numpy().astype(bool)
+    H = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
+    X0 = W.random_block(g.n, 16, 541)
+    info = {}
+    got = S.sfg_smooth_ordered(H, order, dev(X0), 20, 0.5, info=info)
+    Hc = orc.laplacian_csr(g.n, g.u[t], g.v[t], g.w[t])
+    assert info["pairs"] == 1
+    assert np.array_equal(got.cpu().numpy(), orc.smooth(Hc, orc.center(X0)[0], 20, 0.5))
