@@ -725,82 +725,117 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
 // order (a permutation of the nodes; a spanning tree's preorder keeps a
 // block's neighbourhood small).  For block b with rows R0:
 //   R1 = neighbours of R0 outside R0,  R2 = neighbours of R1 outside R0 and R1.
-// One workgroup loads X_t for R0, R1 and R2 into LDS, computes X_t+1 for R0
-// and R1 (all their neighbours are loaded), then X_t+2 for R0 (all theirs are
-// in R0 and R1), and writes only that: X is read about (1 + |R1 ∪ R2| / |R0|)
-// times and written once per two sweeps instead of twice each.  Every row's
-// value is formed with the single sweep's arithmetic -- entries in stored
-// order, the same epilogue, the intermediate iterate rounded to the storage
-// type -- so the result is bit-identical.
-constexpr int kMpkRows = 64;      // R0 rows per block
+// A layout pass gives every block a slot per node of R0, R1 and R2 (R0 in
+// the order's sequence, then R1 and R2 ascending) and a local CSR of the rows
+// of R0 and R1: each entry's neighbour as a slot, its weight, in the row's
+// stored order, and the rows' degrees.  One workgroup then loads X_t of every
+// slot into LDS, forms X_t+1 of R0 and R1 there (all their neighbours have
+// slots) and X_t+2 of R0 (all theirs are in R0 and R1), and writes only that:
+// X is read about (1 + |R1 ∪ R2| / |R0|) times and written once per two
+// sweeps instead of twice each.  Every row's value is formed with the single
+// sweep's arithmetic -- entries in stored order, the same epilogue, the
+// intermediate iterate rounded to the storage type -- so the result is
+// bit-identical.
+constexpr int kMpkRows = 64;      // R0 rows per block (one lane each in the layout pass)
 constexpr int kMpk01 = 112;       // capacity of R0 + R1
-constexpr int kMpkSlots = 176;    // capacity of R0 + R1 + R2
-constexpr int kMpkCand = 1024;    // halo candidates per discovery step
+constexpr int kMpkSlots = 168;    // capacity of R0 + R1 + R2 (the FP64 sweep's LDS then fits four workgroups per CU)
+constexpr int kMpkEnt = 288;      // capacity of the local CSR (entries of the rows of R0 + R1)
+constexpr int kMpkCand = 256;     // halo candidates (with repeats) per discovery step: four per lane
+constexpr int kMpkList = 128;     // R1 or R2 nodes the layout pass holds
 constexpr int kMpkRowBytes = 128; // row width the LDS holds: 16 FP64 or 32 FP32 columns
 constexpr int kMpkLongRow = 256;  // rows longer than this are left to the single sweep (see k_sweep_long)
+constexpr int64_t kMpkPad = 0x7fffffffffffffffll;
 
-__device__ __forceinline__ bool lds_contains(const int32_t *a, int len, int32_t key) {
+// Per-block layout, fixed capacity per block (views into the workspace).
+struct MpkDev {
+    int32_t *meta;      // [4 nb]: s0, s1, s2, local entries
+    int32_t *node;      // [nb kMpkSlots]: node of each slot
+    uint16_t *rowoff;   // [nb (kMpk01 + 1)]: local CSR row starts of the slots of R0 + R1
+    uint8_t *lcol;      // [nb kMpkEnt]: slot of each entry's neighbour
+    void *lval;         // [nb kMpkEnt] of the graph's value type: entry weights
+    void *ldeg;         // [nb kMpk01] of that type: degrees of the rows of R0 + R1
+};
+
+__device__ __forceinline__ int wave_incl_sum(int x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// Ascending bitonic sort of 64 J keys held J per lane (element e = j * 64 + lane in k[j]).
+template <int J>
+__device__ __forceinline__ void wave_sort(int64_t (&k)[J]) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int size = 2; size <= 64 * J; size <<= 1)
+#pragma unroll
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            if (stride >= 64) {        // partners in registers j and j + stride / 64 of the same lane
+                const int js = stride >> 6;
+#pragma unroll
+                for (int j = 0; j < J; ++j)
+                    if ((j & js) == 0) {
+                        const bool up = ((j * 64 + lane) & size) == 0;
+                        const int64_t a = k[j], c = k[j | js];
+                        const int64_t lo = a < c ? a : c, hi = a < c ? c : a;
+                        k[j] = up ? lo : hi;
+                        k[j | js] = up ? hi : lo;
+                    }
+                continue;
+            }
+            const bool lower = (lane & stride) == 0;
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int64_t o = __shfl_xor(k[j], stride, 64);
+                const bool up = ((j * 64 + lane) & size) == 0;
+                k[j] = (lower == up) ? (k[j] < o ? k[j] : o) : (k[j] < o ? o : k[j]);
+            }
+        }
+}
+
+// The distinct keys (other than kMpkPad) of 64 J sorted keys into out[0, cap); returns their number.
+template <int J>
+__device__ __forceinline__ int wave_unique(const int64_t (&k)[J], int32_t *out, int cap) {
+    const int lane = threadIdx.x & 63;
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int before = 0;
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+        const int64_t up = __shfl_up(k[j], 1, 64);
+        const int64_t prev_last = __shfl(k[j > 0 ? j - 1 : 0], 63, 64);
+        const int64_t pred = lane > 0 ? up : prev_last;
+        const bool first = k[j] != kMpkPad && ((j == 0 && lane == 0) || k[j] != pred);
+        const unsigned long long bm = __ballot(first);
+        const int r = before + __popcll(bm & lt);
+        if (first && r < cap) out[r] = (int32_t)k[j];
+        before += __popcll(bm);
+    }
+    return before;
+}
+
+__device__ __forceinline__ int lds_find(const int32_t *a, int len, int32_t key) {
     int lo = 0, hi = len;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
         if (a[mid] < key) lo = mid + 1;
         else hi = mid;
     }
-    return lo < len && a[lo] == key;
+    return (lo < len && a[lo] == key) ? lo : -1;
 }
 
-// In-place ascending bitonic sort of len (a power of two) keys by 256 threads.
-template <typename K>
-__device__ void lds_bitonic(K *a, int len) {
-    for (int size = 2; size <= len; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = threadIdx.x; i < len / 2; i += blockDim.x) {
-                const int lo = 2 * i - (i & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const K x = a[lo], y = a[hi];
-                if ((x > y) == up) {
-                    a[lo] = y;
-                    a[hi] = x;
-                }
-            }
-            __syncthreads();
-        }
-}
-
-// Sorted unique keys of cand[0, nc) (sorted in place, padded with INT_MAX to
-// kMpkCand) into out[]; returns their number.  All 256 threads call it.
-__device__ int lds_sort_unique(int32_t *cand, int nc, int32_t *out, int cap, int32_t *scratch) {
-    for (int i = nc + threadIdx.x; i < kMpkCand; i += blockDim.x) cand[i] = 0x7fffffff;
-    __syncthreads();
-    lds_bitonic(cand, kMpkCand);
-    // keep the first of each run: 4 candidates per thread, then a scan of the per-thread counts
-    constexpr int per = kMpkCand / 256;
-    const int t = threadIdx.x;
-    int mine = 0;
-    for (int i = t * per; i < t * per + per; ++i)
-        mine += (i < nc && (i == 0 || cand[i] != cand[i - 1])) ? 1 : 0;
-    scratch[t] = mine;
-    __syncthreads();
-    if (t == 0) {
-        int run = 0;
-        for (int i = 0; i < 256; ++i) {
-            const int c = scratch[i];
-            scratch[i] = run;
-            run += c;
-        }
-        scratch[256] = run;
+// Slot of node q in R0 (keys node << 8 | slot, ascending), -1 if absent.
+__device__ __forceinline__ int r0_slot(const int64_t *r0key, int s0, int32_t q) {
+    int lo = 0, hi = s0;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int32_t)(r0key[mid] >> 8) < q) lo = mid + 1;
+        else hi = mid;
     }
-    __syncthreads();
-    int at = scratch[t];
-    for (int i = t * per; i < t * per + per; ++i)
-        if (i < nc && (i == 0 || cand[i] != cand[i - 1])) {
-            if (at < cap) out[at] = cand[i];
-            ++at;
-        }
-    const int total = scratch[256];
-    __syncthreads();
-    return total;
+    return (lo < s0 && (int32_t)(r0key[lo] >> 8) == q) ? (int)(r0key[lo] & 0xff) : -1;
 }
 
 // Order check: every order[i] in [0, n) and no node twice (seen[] zeroed by the caller).
@@ -811,194 +846,282 @@ __global__ void k_mpk_check(int64_t n, const int32_t *__restrict__ order, int32_
     if (v < 0 || v >= n || atomicExch(&seen[v], 1) != 0) atomicOr(flag, 1);
 }
 
-// Halo discovery for one block per workgroup.  fill == 0: the counts s0, s1,
-// s2 of every block (flag bit 2 when a block exceeds the capacities); fill ==
-// 1: the slots (R0 in order, then R1 and R2 ascending) from off[b] on, and the
-// node-sorted slot table (node << 16 | slot).
-__global__ __launch_bounds__(256) void k_mpk_build(int64_t n, const int32_t *__restrict__ order,
-                                                   const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ col, int fill, int32_t *cnt,
-                                                   int32_t *sizes, const int32_t *__restrict__ off,
-                                                   int32_t *slot_node, int64_t *table, int32_t *flag) {
-    __shared__ int32_t r0[kMpkRows];
+// Layout of one block per 64-lane workgroup.  A block that does not fit (a
+// halo over the capacities, a row over kMpkLongRow entries, an order entry
+// outside [0, n)) gets s0 = 0 and sets flag bit 2; the caller then runs the
+// single sweeps instead.
+template <typename TW>
+__global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__restrict__ order,
+                                                  const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const TW *__restrict__ val,
+                                                  const TW *__restrict__ deg, MpkDev L, int32_t *flag) {
+    __shared__ int64_t r0key[kMpkRows];
     __shared__ int32_t cand[kMpkCand];
-    __shared__ int32_t r1[kMpk01];
-    __shared__ int32_t r2[kMpkSlots];
-    __shared__ int32_t scratch[257];
-    __shared__ int64_t keys[256];
-    __shared__ int nc_sh;
-    const int64_t base = (int64_t)blockIdx.x * kMpkRows;
+    __shared__ int32_t r1n[kMpkList];
+    __shared__ int32_t r2n[kMpkList];
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t base = b * kMpkRows;
     const int s0 = (int)(n - base < kMpkRows ? n - base : kMpkRows);
-    const int t = threadIdx.x;
-    // entries outside [0, n) are skipped here (k_mpk_check refuses such an order before the layout is used)
-    if (t < kMpkRows) {
-        const int32_t v = t < s0 ? order[base + t] : 0x7fffffff;
-        r0[t] = (v >= 0 && v < n) ? v : 0x7fffffff;
+    const int32_t p = lane < s0 ? order[base + lane] : -1;
+    const bool bad = lane < s0 && (p < 0 || p >= n);
+    bool over = __ballot(bad) != 0ull;
+    const int plen = (lane < s0 && !bad) ? rowptr[p + 1] - rowptr[p] : 0;
+    over = over || __ballot(plen > kMpkLongRow) != 0ull;
+    // R0, node-sorted with its slots
+    {
+        int64_t key[1] = {(lane < s0 && !bad) ? (((int64_t)p << 8) | lane) : kMpkPad};
+        wave_sort<1>(key);
+        r0key[lane] = key[0];
     }
-    if (t == 0) nc_sh = 0;
     __syncthreads();
-    lds_bitonic(r0, kMpkRows);
-    // R1: neighbours of R0 outside it.  A row over kMpkLongRow entries marks the
-    // block as not taken: the single sweep adds such rows of a reduced-precision
-    // block in another order, and hubs make large halos anyway.
-    __shared__ int long_sh;
-    if (t == 0) long_sh = 0;
-    __syncthreads();
-    for (int i = t; i < s0; i += blockDim.x) {
-        const int32_t p = order[base + i];
-        if (p < 0 || p >= n) continue;
-        if (rowptr[p + 1] - rowptr[p] > kMpkLongRow) long_sh = 1;
-        for (int32_t j = rowptr[p]; j < rowptr[p + 1]; ++j) {
-            const int32_t q = col[j];
-            if (!lds_contains(r0, s0, q)) {
-                const int at = atomicAdd(&nc_sh, 1);
-                if (at < kMpkCand) cand[at] = q;
+    int s1 = 0, s2 = 0;
+    if (!over) {
+        // R1: neighbours of R0 outside R0
+        const int32_t j0 = lane < s0 ? rowptr[p] : 0;
+        int c = 0;
+        for (int32_t t = 0; t < plen; ++t) c += r0_slot(r0key, s0, col[j0 + t]) < 0 ? 1 : 0;
+        const int incl = wave_incl_sum(c);
+        const int total = __shfl(incl, 63, 64);
+        over = total > kMpkCand;
+        if (!over) {
+            int at = incl - c;
+            for (int32_t t = 0; t < plen; ++t) {
+                const int32_t q = col[j0 + t];
+                if (r0_slot(r0key, s0, q) < 0) cand[at++] = q;
             }
         }
+        __syncthreads();
+        if (!over) {
+            int64_t key[kMpkCand / 64];
+#pragma unroll
+            for (int j = 0; j < kMpkCand / 64; ++j) key[j] = j * 64 + lane < total ? cand[j * 64 + lane] : kMpkPad;
+            wave_sort<kMpkCand / 64>(key);
+            s1 = wave_unique<kMpkCand / 64>(key, r1n, kMpkList);
+            over = s0 + s1 > kMpk01;
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    int nc = nc_sh;
-    bool over = nc > kMpkCand || long_sh;
-    const int s1 = lds_sort_unique(cand, over ? kMpkCand : nc, r1, kMpk01 - s0, scratch);
-    over = over || s0 + s1 > kMpk01;
-    const int s1c = s0 + s1 > kMpk01 ? kMpk01 - s0 : s1;
-    // R2: neighbours of R1 outside R0 and R1
-    if (t == 0) nc_sh = 0;
-    __syncthreads();
-    for (int i = t; i < s1c; i += blockDim.x) {
-        const int32_t p = r1[i];
-        for (int32_t j = rowptr[p]; j < rowptr[p + 1]; ++j) {
-            const int32_t q = col[j];
-            if (!lds_contains(r0, s0, q) && !lds_contains(r1, s1c, q)) {
-                const int at = atomicAdd(&nc_sh, 1);
-                if (at < kMpkCand) cand[at] = q;
+    if (!over) {
+        // R2: neighbours of R1 outside R0 and R1 (R1 entries lane and 64 + lane)
+        int32_t j0[2] = {0, 0}, len[2] = {0, 0};
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (h * 64 + lane < s1) {
+                const int32_t q1 = r1n[h * 64 + lane];
+                j0[h] = rowptr[q1];
+                len[h] = rowptr[q1 + 1] - j0[h];
             }
+        over = __ballot(len[0] > kMpkLongRow || len[1] > kMpkLongRow) != 0ull;
+        int c = 0;
+        if (!over)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                for (int32_t t = 0; t < len[h]; ++t) {
+                    const int32_t x = col[j0[h] + t];
+                    c += (r0_slot(r0key, s0, x) < 0 && lds_find(r1n, s1, x) < 0) ? 1 : 0;
+                }
+        const int incl = wave_incl_sum(c);
+        const int total = __shfl(incl, 63, 64);
+        over = over || total > kMpkCand;
+        if (!over) {
+            int at = incl - c;
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                for (int32_t t = 0; t < len[h]; ++t) {
+                    const int32_t x = col[j0[h] + t];
+                    if (r0_slot(r0key, s0, x) < 0 && lds_find(r1n, s1, x) < 0) cand[at++] = x;
+                }
+        }
+        __syncthreads();
+        if (!over) {
+            int64_t key[kMpkCand / 64];
+#pragma unroll
+            for (int j = 0; j < kMpkCand / 64; ++j) key[j] = j * 64 + lane < total ? cand[j * 64 + lane] : kMpkPad;
+            wave_sort<kMpkCand / 64>(key);
+            s2 = wave_unique<kMpkCand / 64>(key, r2n, kMpkList);
+            over = s0 + s1 + s2 > kMpkSlots;
+        }
+        __syncthreads();
+    }
+    // local CSR of the rows of R0 and R1 (slots r = lane and 64 + lane)
+    const int s01 = s0 + s1;
+    int32_t na = 0, nb2 = 0, la = 0, lb = 0;
+    if (!over) {
+        if (lane < s01) {
+            na = lane < s0 ? p : r1n[lane - s0];
+            la = rowptr[na + 1] - rowptr[na];
+        }
+        if (64 + lane < s01) {
+            nb2 = r1n[64 + lane - s0];
+            lb = rowptr[nb2 + 1] - rowptr[nb2];
         }
     }
-    __syncthreads();
-    nc = nc_sh;
-    over = over || nc > kMpkCand;
-    const int s2 = lds_sort_unique(cand, nc > kMpkCand ? kMpkCand : nc, r2, kMpkSlots - s0 - s1c, scratch);
-    over = over || s0 + s1 + s2 > kMpkSlots;
-    if (!fill) {
-        if (t == 0) {
-            cnt[4 * blockIdx.x] = s0;
-            cnt[4 * blockIdx.x + 1] = s1;
-            cnt[4 * blockIdx.x + 2] = s2;
-            cnt[4 * blockIdx.x + 3] = s0 + s1 + s2;
-            sizes[blockIdx.x] = over ? 0 : s0 + s1 + s2;
-            if (over) atomicOr(flag, 2);
+    const int ia = wave_incl_sum(la);
+    const int tot_a = __shfl(ia, 63, 64);
+    const int ib = tot_a + wave_incl_sum(lb);
+    const int nent = __shfl(ib, 63, 64);
+    over = over || nent > kMpkEnt;
+    if (over) {
+        if (lane == 0) {
+            L.meta[4 * b] = 0;
+            L.meta[4 * b + 1] = L.meta[4 * b + 2] = L.meta[4 * b + 3] = 0;
+            atomicOr(flag, 2);
         }
         return;
     }
-    if (over) return;     // the caller does not use the layout then
-    const int S = s0 + s1 + s2;
-    const int32_t o = off[blockIdx.x];
-    for (int i = t; i < 256; i += blockDim.x) {
-        int64_t key = 0x7fffffffffffffffll;
-        if (i < S) {
-            const int32_t v = i < s0 ? order[base + i] : (i < s0 + s1 ? r1[i - s0] : r2[i - s0 - s1]);
-            slot_node[o + i] = v;
-            key = ((int64_t)v << 16) | i;
+    uint16_t *ro = L.rowoff + b * (kMpk01 + 1);
+    uint8_t *lc = L.lcol + b * kMpkEnt;
+    TW *lv = (TW *)L.lval + b * kMpkEnt;
+    TW *ld = (TW *)L.ldeg + b * kMpk01;
+    auto emit = [&](int r, int32_t node, int len, int start) {
+        ro[r] = (uint16_t)start;
+        ld[r] = deg[node];
+        const int32_t j0 = rowptr[node];
+        for (int t = 0; t < len; ++t) {
+            const int32_t q = col[j0 + t];
+            int sl = r0_slot(r0key, s0, q);
+            if (sl < 0) {
+                const int i1 = lds_find(r1n, s1, q);
+                sl = i1 >= 0 ? s0 + i1 : s01 + lds_find(r2n, s2, q);
+            }
+            lc[start + t] = (uint8_t)sl;
+            lv[start + t] = val[j0 + t];
         }
-        keys[i] = key;
+    };
+    if (lane < s01) emit(lane, na, la, ia - la);
+    if (64 + lane < s01) emit(64 + lane, nb2, lb, ib - lb);
+    if (lane == 0) ro[s01] = (uint16_t)nent;
+    int32_t *nd = L.node + b * kMpkSlots;
+    const int S = s01 + s2;
+    for (int i = lane; i < S; i += 64) nd[i] = i < s0 ? order[base + i] : (i < s01 ? r1n[i - s0] : r2n[i - s01]);
+    if (lane == 0) {
+        L.meta[4 * b] = s0;
+        L.meta[4 * b + 1] = s1;
+        L.meta[4 * b + 2] = s2;
+        L.meta[4 * b + 3] = nent;
     }
-    __syncthreads();
-    lds_bitonic(keys, 256);
-    for (int i = t; i < S; i += blockDim.x) table[o + i] = keys[i];
-}
-
-// Slot of node q in a block's node-sorted table (q is always there).
-__device__ __forceinline__ int mpk_slot(const int64_t *tab, int len, int32_t q) {
-    int lo = 0, hi = len - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int32_t)(tab[mid] >> 16) < q) lo = mid + 1;
-        else hi = mid;
-    }
-    return (int)(tab[lo] & 0xffff);
 }
 
 // Two sweeps of one block (see above).  k columns of TX, k * sizeof(TX) <=
 // kMpkRowBytes, VPL columns per lane; TIN the source block's type (the raw
-// FP64 block when CENTER: centred on load, as the single sweep does).
+// FP64 block when CENTER: centred on load, as the single sweep does).  The
+// LDS holds X of every slot; X_t+1 of R0 and R1 is formed in registers and
+// written over it after a barrier (no row of R0 reads R2), so a workgroup
+// needs about 26 KB and six fit a CU.  Two dependent rounds of global loads:
+// the block's sizes and slot nodes, then X of the slots and the local CSR.
+constexpr int kMpkPasses = 6;     // row passes over the slots at the narrowest lanes-per-row (32 rows a pass)
 template <typename TIN, typename TX, typename TW, typename TA, int VPL, bool CENTER>
-__global__ __launch_bounds__(256) void k_sweep2(int32_t k, const int32_t *__restrict__ cnt,
-                                                const int32_t *__restrict__ off,
-                                                const int32_t *__restrict__ slot_node,
-                                                const int64_t *__restrict__ table,
-                                                const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                                                const TW *__restrict__ val, const TW *__restrict__ deg,
-                                                const TIN *__restrict__ x, const double *__restrict__ mean,
-                                                TX *__restrict__ y, TA keep, TA omega) {
+__global__ __launch_bounds__(256) void k_sweep2(int32_t k, MpkDev L, const TIN *__restrict__ x,
+                                                const double *__restrict__ mean, TX *__restrict__ y, TA keep,
+                                                TA omega) {
     __shared__ __align__(16) unsigned char xs_raw[kMpkSlots * kMpkRowBytes];
-    __shared__ __align__(16) unsigned char x1_raw[kMpk01 * kMpkRowBytes];
-    __shared__ int64_t tab[kMpkSlots];
     __shared__ int32_t nodes[kMpkSlots];
+    __shared__ TW lval[kMpkEnt];
+    __shared__ TW ldeg[kMpk01];
+    __shared__ uint16_t rowoff[kMpk01 + 1];
+    __shared__ uint8_t lcol[kMpkEnt];
     TX *xs = reinterpret_cast<TX *>(xs_raw);
-    TX *x1 = reinterpret_cast<TX *>(x1_raw);
-    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int s0 = cnt[4 * b], s1 = cnt[4 * b + 1], S = cnt[4 * b + 3];
-    const int32_t o = off[b];
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int t = threadIdx.x;
-    const int lpr = k / VPL;
-    const int rows_per_pass = 256 / lpr;
-    const int ri0 = t / lpr, c = (t - ri0 * lpr) * VPL;
-    const bool lane_on = ri0 < rows_per_pass;       // 256 % lpr lanes idle
-    for (int i = t; i < S; i += 256) {
-        nodes[i] = slot_node[o + i];
-        tab[i] = table[o + i];
+    const int32_t *mp = L.meta + 4 * b;
+    const int s0 = mp[0], s1 = mp[1], s2 = mp[2], ne = mp[3];
+    const int s01 = s0 + s1, S = s01 + s2;
+    // round 1: slot nodes (read to capacity, used to S)
+    if (t < kMpkSlots) nodes[t] = L.node[b * kMpkSlots + t];
+    // round 2 issued early: the local CSR into registers
+    constexpr int kEntPer = (kMpkEnt + 255) / 256;
+    uint8_t ec[kEntPer];
+    TW ev[kEntPer];
+#pragma unroll
+    for (int j = 0; j < kEntPer; ++j) {
+        const int i = t + 256 * j;
+        if (i < ne) {
+            ec[j] = L.lcol[b * kMpkEnt + i];
+            ev[j] = ((const TW *)L.lval)[b * kMpkEnt + i];
+        }
     }
+    uint16_t ro = 0;
+    TW dg = TW(0);
+    if (t <= s01) ro = L.rowoff[b * (kMpk01 + 1) + t];
+    if (t < s01) dg = ((const TW *)L.ldeg)[b * kMpk01 + t];
+    const int lpr = k / VPL;
+    const int rpp = 256 / lpr;                      // rows a pass; 256 % lpr lanes idle
+    const int ri0 = t / lpr, c = (t - ri0 * lpr) * VPL;
+    const bool lane_on = ri0 < rpp;
     double mo[VPL];
 #pragma unroll
     for (int i = 0; i < VPL; ++i) mo[i] = (CENTER && lane_on) ? mean[c + i] : 0.0;
     __syncthreads();
-    // X_t of every slot
-    if (lane_on)
-        for (int r = ri0; r < S; r += rows_per_pass) {
-            TA v[VPL];
-            load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)nodes[r] * k + c, mo, v);
+    // X_t of every slot: all loads first, then the LDS stores
+    TA v[kMpkPasses][VPL];
+#pragma unroll
+    for (int j = 0; j < kMpkPasses; ++j) {
+        const int r = ri0 + j * rpp;
+        if (lane_on && r < S) load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)nodes[r] * k + c, mo, v[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < kEntPer; ++j) {
+        const int i = t + 256 * j;
+        if (i < ne) {
+            lcol[i] = ec[j];
+            lval[i] = ev[j];
+        }
+    }
+    if (t <= s01) rowoff[t] = ro;
+    if (t < s01) ldeg[t] = dg;
+#pragma unroll
+    for (int j = 0; j < kMpkPasses; ++j) {
+        const int r = ri0 + j * rpp;
+        if (lane_on && r < S) {
             Vec<TX, VPL> st;
 #pragma unroll
-            for (int i = 0; i < VPL; ++i) st.v[i] = cvt<TX>(v[i]);
+            for (int i = 0; i < VPL; ++i) st.v[i] = cvt<TX>(v[j][i]);
             *reinterpret_cast<Vec<TX, VPL> *>(xs + r * k + c) = st;
         }
-    __syncthreads();
-    // X_t+1 of R0 and R1 (into x1), then X_t+2 of R0 (into y)
-    for (int phase = 0; phase < 2; ++phase) {
-        const TX *src = phase == 0 ? xs : x1;
-        const int nrows = phase == 0 ? s0 + s1 : s0;    // R0's neighbours all have slots below s0 + s1
-        if (lane_on)
-            for (int r = ri0; r < nrows; r += rows_per_pass) {
-                const int32_t p = nodes[r];
-                const int32_t j0 = rowptr[p], j1 = rowptr[p + 1];
-                TA acc[VPL];
-#pragma unroll
-                for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
-                for (int32_t j = j0; j < j1; ++j) {
-                    const int sl = mpk_slot(tab, S, col[j]);
-                    const TA w = cvt<TA>(val[j]);
-                    const Vec<TX, VPL> xv = *reinterpret_cast<const Vec<TX, VPL> *>(src + sl * k + c);
-#pragma unroll
-                    for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], w, cvt<TA>(xv.v[i]));
-                }
-                const Vec<TX, VPL> sv = *reinterpret_cast<const Vec<TX, VPL> *>(src + r * k + c);
-                const TA d = cvt<TA>(deg[p]);
-                Vec<TX, VPL> out;
-#pragma unroll
-                for (int i = 0; i < VPL; ++i) {
-                    const TA a = keep * cvt<TA>(sv.v[i]);
-                    const TA q = acc[i] / d;
-                    const TA bo = omega * q;
-                    out.v[i] = cvt<TX>(a + bo);
-                }
-                if (phase == 0)
-                    *reinterpret_cast<Vec<TX, VPL> *>(x1 + r * k + c) = out;
-                else
-                    *reinterpret_cast<Vec<TX, VPL> *>(y + (int64_t)p * k + c) = out;
-            }
-        __syncthreads();
     }
+    __syncthreads();
+    // one sweep of row r from the LDS
+    auto row_sweep = [&](int r) {
+        TA acc[VPL];
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
+        for (int e = rowoff[r]; e < rowoff[r + 1]; ++e) {
+            const TA w = cvt<TA>(lval[e]);
+            const Vec<TX, VPL> xv = *reinterpret_cast<const Vec<TX, VPL> *>(xs + lcol[e] * k + c);
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], w, cvt<TA>(xv.v[i]));
+        }
+        const Vec<TX, VPL> sv = *reinterpret_cast<const Vec<TX, VPL> *>(xs + r * k + c);
+        const TA d = cvt<TA>(ldeg[r]);
+        Vec<TX, VPL> out;
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+            const TA a = keep * cvt<TA>(sv.v[i]);
+            const TA q = acc[i] / d;
+            const TA bo = omega * q;
+            out.v[i] = cvt<TX>(a + bo);
+        }
+        return out;
+    };
+    // X_t+1 of R0 and R1 into registers, then over X_t in the LDS
+    constexpr int kP01 = (kMpk01 + 31) / 32;
+    Vec<TX, VPL> x1[kP01];
+#pragma unroll
+    for (int j = 0; j < kP01; ++j) {
+        const int r = ri0 + j * rpp;
+        if (lane_on && r < s01) x1[j] = row_sweep(r);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kP01; ++j) {
+        const int r = ri0 + j * rpp;
+        if (lane_on && r < s01) *reinterpret_cast<Vec<TX, VPL> *>(xs + r * k + c) = x1[j];
+    }
+    __syncthreads();
+    // X_t+2 of R0 (its neighbours all lie in R0 and R1)
+    for (int r = ri0; lane_on && r < s0; r += rpp)
+        *reinterpret_cast<Vec<TX, VPL> *>(y + (int64_t)nodes[r] * k + c) = row_sweep(r);
 }
 
 }  // namespace
@@ -1162,21 +1285,21 @@ void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const dou
 
 // Two-sweeps-per-pass smoothing in a caller's row order (see k_sweep2).
 struct MpkPlan {
-    int32_t *cnt, *sizes, *off, *scan, *slot_node, *seen, *flag;
-    int64_t *table;
+    MpkDev dev;
+    int32_t *seen, *flag;
 };
 
 int64_t mpk_blocks(int64_t n) { return (n + kMpkRows - 1) / kMpkRows; }
 
-MpkPlan plan_mpk(Carver &c, int64_t n) {
+MpkPlan plan_mpk(Carver &c, int64_t n, size_t sw) {
     const int64_t nb = mpk_blocks(n);
     MpkPlan p;
-    p.cnt = c.take<int32_t>(4 * nb);
-    p.sizes = c.take<int32_t>(nb + 1);
-    p.off = c.take<int32_t>(nb + 1);
-    p.scan = c.take<int32_t>(scan_scratch_ints(nb + 1));
-    p.slot_node = c.take<int32_t>(nb * kMpkSlots);
-    p.table = c.take<int64_t>(nb * kMpkSlots);
+    p.dev.meta = c.take<int32_t>(4 * nb);
+    p.dev.node = c.take<int32_t>(nb * kMpkSlots);
+    p.dev.rowoff = c.take<uint16_t>(nb * (kMpk01 + 1));
+    p.dev.lcol = c.take<uint8_t>(nb * kMpkEnt);
+    p.dev.lval = c.take<char>(nb * kMpkEnt * sw);
+    p.dev.ldeg = c.take<char>(nb * kMpk01 * sw);
     p.seen = c.take<int32_t>(n + 1);
     p.flag = c.take<int32_t>(1);
     return p;
@@ -1185,19 +1308,17 @@ MpkPlan plan_mpk(Carver &c, int64_t n) {
 size_t smooth_ordered_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage) {
     Carver c(nullptr);
     plan_smooth(c, n, k, storage);
-    plan_mpk(c, n);
+    plan_mpk(c, n, 8);
     return c.used + 512;
 }
 
 namespace {
 
 template <typename TX, bool CENTER>
-void launch_sweep2(const sfg_csr *H, int32_t k, const MpkPlan &m, int64_t nb, const void *x, const double *mean,
-                   TX *y, double omega, hipStream_t s) {
+void launch_sweep2(int32_t k, const MpkPlan &m, int64_t nb, const void *x, const double *mean, TX *y, double omega,
+                   hipStream_t s) {
     using TIN = typename std::conditional<CENTER, double, TX>::type;
-    constexpr int VPL = 4;
-    hipLaunchKernelGGL((k_sweep2<TIN, TX, TX, TX, VPL, CENTER>), dim3((uint32_t)nb), dim3(256), 0, s, k, m.cnt, m.off,
-                       m.slot_node, m.table, H->rowptr, H->col, (const TX *)H->val, (const TX *)H->deg,
+    hipLaunchKernelGGL((k_sweep2<TIN, TX, TX, TX, 4, CENTER>), dim3((uint32_t)nb), dim3(256), 0, s, k, m.dev,
                        (const TIN *)x, mean, y, (TX)(1.0 - omega), (TX)omega);
     SFG_LAUNCH_CHECK();
 }
@@ -1213,9 +1334,9 @@ void run_smooth_pairs(const sfg_csr *H, int32_t k, int32_t sweeps, double omega,
         const bool last = (q == pairs - 1) && sweeps % 2 == 0;
         TX *dst = last ? (TX *)xout : (q % 2 == 0 ? b0 : b1);
         if (q == 0)
-            launch_sweep2<TX, true>(H, k, m, nb, x0, p.mean, dst, omega, s);
+            launch_sweep2<TX, true>(k, m, nb, x0, p.mean, dst, omega, s);
         else
-            launch_sweep2<TX, false>(H, k, m, nb, src, nullptr, dst, omega, s);
+            launch_sweep2<TX, false>(k, m, nb, src, nullptr, dst, omega, s);
         src = dst;
     }
     if (sweeps % 2 == 1)    // the odd last sweep: a single sweep in node order
@@ -1230,12 +1351,13 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
                    const double *x0, sfg_dtype storage, int32_t final_f32, void *x, void *ws, size_t ws_bytes,
                    hipStream_t s) {
     SFG_REQUIRE(H && order, SFG_EINVAL, "smooth_ordered: null pointer");
+    SFG_REQUIRE(H->n >= 1, SFG_EINVAL, "smooth_ordered: empty graph");
     SFG_REQUIRE(ws_bytes >= smooth_ordered_workspace_bytes(H->n, k < 1 ? 1 : k, storage), SFG_EWORKSPACE,
                 "smooth_ordered: workspace too small");
     const int64_t n = H->n;
     Carver c(ws);
     SmoothPlan p = plan_smooth(c, n, k < 1 ? 1 : k, storage);
-    MpkPlan m = plan_mpk(c, n);
+    MpkPlan m = plan_mpk(c, n, 8);
     // the order must be a permutation of the nodes, whichever path runs
     fill_i32(m.seen, n, 0, s);
     fill_i32(m.flag, 1, 0, s);
@@ -1243,30 +1365,30 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
     SFG_LAUNCH_CHECK();
     const size_t sx = dtype_size(storage);
     const bool shape_ok = (storage == SFG_F64 || storage == SFG_F32) && H->vt == storage && k >= 1 &&
-                          k % 4 == 0 && (size_t)k * sx <= (size_t)kMpkRowBytes && sweeps >= 2 &&
-                          H->nnz >= 1 && H->col && H->val;
+                          k % 4 == 0 && (size_t)k * sx <= (size_t)kMpkRowBytes && sweeps >= 2 && H->nnz >= 1 &&
+                          H->col && H->val && H->deg && env_int("SFG_SWEEP_PAIRS", 1) != 0;
     const int64_t nb = mpk_blocks(n);
-    if (shape_ok && env_int("SFG_SWEEP_PAIRS", 1) != 0) {
-        hipLaunchKernelGGL(k_mpk_build, dim3((uint32_t)nb), dim3(256), 0, s, n, order, H->rowptr, H->col, 0, m.cnt,
-                           m.sizes, m.off, m.slot_node, m.table, m.flag);
+    if (shape_ok) {
+        if (storage == SFG_F64)
+            hipLaunchKernelGGL(k_mpk_build<double>, dim3((uint32_t)nb), dim3(64), 0, s, n, order, H->rowptr, H->col,
+                               (const double *)H->val, (const double *)H->deg, m.dev, m.flag);
+        else
+            hipLaunchKernelGGL(k_mpk_build<float>, dim3((uint32_t)nb), dim3(64), 0, s, n, order, H->rowptr, H->col,
+                               (const float *)H->val, (const float *)H->deg, m.dev, m.flag);
         SFG_LAUNCH_CHECK();
     }
     int32_t flag = 0;
     SFG_HIP(hipMemcpyAsync(&flag, m.flag, sizeof(flag), hipMemcpyDeviceToHost, s));
     SFG_HIP(hipStreamSynchronize(s));
     SFG_REQUIRE(!(flag & 1), SFG_EINVAL, "smooth_ordered: order is not a permutation of the nodes");
-    if (!shape_ok || env_int("SFG_SWEEP_PAIRS", 1) == 0 || (flag & 2)) {
+    if (!shape_ok || (flag & 2)) {
         // the workspace starts with the plain smoothing's layout
         smooth(H, k, sweeps, omega, x0, storage, final_f32, x, ws, smooth_workspace_bytes(n, k < 1 ? 1 : k, storage),
                s, -1);
         return 0;
     }
-    exclusive_scan_i32(m.sizes, m.off, nb, m.scan, s);
-    hipLaunchKernelGGL(k_mpk_build, dim3((uint32_t)nb), dim3(256), 0, s, n, order, H->rowptr, H->col, 1, m.cnt,
-                       m.sizes, m.off, m.slot_node, m.table, m.flag);
-    SFG_LAUNCH_CHECK();
     SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_ordered: omega must be in (0, 1]");
-    SFG_REQUIRE(x0 && x && H->deg && H->rowptr, SFG_EINVAL, "smooth_ordered: null pointer");
+    SFG_REQUIRE(x0 && x, SFG_EINVAL, "smooth_ordered: null pointer");
     if (storage == SFG_F64)
         run_smooth_pairs<double>(H, k, sweeps, omega, x0, x, p, m, nb, s);
     else
