@@ -726,7 +726,7 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
 // block's neighbourhood small).  For block b with rows R0:
 //   R1 = neighbours of R0 outside R0,  R2 = neighbours of R1 outside R0 and R1.
 // A layout pass gives every block a slot per node of R0, R1 and R2 (R0 in
-// the order's sequence, then R1 and R2 ascending) and a local CSR of the rows
+// the order's sequence, then R1, then R2) and a local CSR of the rows
 // of R0 and R1: each entry's neighbour as a slot, its weight, in the row's
 // stored order, and the rows' degrees.  One workgroup then loads X_t of every
 // slot into LDS, forms X_t+1 of R0 and R1 there (all their neighbours have
@@ -738,13 +738,9 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
 // bit-identical.
 constexpr int kMpkRows = 64;      // R0 rows per block (one lane each in the layout pass)
 constexpr int kMpk01 = 112;       // capacity of R0 + R1
-constexpr int kMpkSlots = 168;    // capacity of R0 + R1 + R2 (the FP64 sweep's LDS then fits four workgroups per CU)
+constexpr int kMpkSlots = 168;    // capacity of R0 + R1 + R2 (about 26 KB of LDS per workgroup in FP64)
 constexpr int kMpkEnt = 288;      // capacity of the local CSR (entries of the rows of R0 + R1)
-constexpr int kMpkCand = 256;     // halo candidates (with repeats) per discovery step: four per lane
-constexpr int kMpkList = 128;     // R1 or R2 nodes the layout pass holds
 constexpr int kMpkRowBytes = 128; // row width the LDS holds: 16 FP64 or 32 FP32 columns
-constexpr int kMpkLongRow = 256;  // rows longer than this are left to the single sweep (see k_sweep_long)
-constexpr int64_t kMpkPad = 0x7fffffffffffffffll;
 
 // Per-block layout, fixed capacity per block (views into the workspace).
 struct MpkDev {
@@ -766,76 +762,48 @@ __device__ __forceinline__ int wave_incl_sum(int x) {
     return x;
 }
 
-// Ascending bitonic sort of 64 J keys held J per lane (element e = j * 64 + lane in k[j]).
-template <int J>
-__device__ __forceinline__ void wave_sort(int64_t (&k)[J]) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int size = 2; size <= 64 * J; size <<= 1)
-#pragma unroll
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            if (stride >= 64) {        // partners in registers j and j + stride / 64 of the same lane
-                const int js = stride >> 6;
-#pragma unroll
-                for (int j = 0; j < J; ++j)
-                    if ((j & js) == 0) {
-                        const bool up = ((j * 64 + lane) & size) == 0;
-                        const int64_t a = k[j], c = k[j | js];
-                        const int64_t lo = a < c ? a : c, hi = a < c ? c : a;
-                        k[j] = up ? lo : hi;
-                        k[j | js] = up ? hi : lo;
-                    }
-                continue;
-            }
-            const bool lower = (lane & stride) == 0;
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                const int64_t o = __shfl_xor(k[j], stride, 64);
-                const bool up = ((j * 64 + lane) & size) == 0;
-                k[j] = (lower == up) ? (k[j] < o ? k[j] : o) : (k[j] < o ? o : k[j]);
-            }
+// Node -> slot map of one block in LDS: open addressing, linear probing.
+constexpr int kMpkHash = 512;     // table entries (at least three per slot)
+constexpr int kMpkRegCols = 8;    // row entries the layout pass holds in registers; longer rows are re-read
+
+__device__ __forceinline__ int mpk_hash(int32_t q) { return (int)(((uint32_t)q * 0x9E3779B1u) >> 23); }
+
+// Inserts q.  New: takes the next slot from *next (its node into snode when
+// the slot is within capacity) and returns 1; present: 0; table full: -1.
+__device__ __forceinline__ int hs_insert(int32_t *keys, int32_t *vals, int32_t *next, int32_t *snode, int32_t q) {
+    int h = mpk_hash(q);
+    for (int probe = 0; probe < kMpkHash; ++probe) {
+        const int32_t old = atomicCAS(&keys[h], -1, q);
+        if (old == -1) {
+            const int32_t slot = atomicAdd(next, 1);
+            vals[h] = slot;
+            if (slot < kMpkSlots) snode[slot] = q;
+            return 1;
         }
+        if (old == q) return 0;
+        h = (h + 1) & (kMpkHash - 1);
+    }
+    return -1;
 }
 
-// The distinct keys (other than kMpkPad) of 64 J sorted keys into out[0, cap); returns their number.
-template <int J>
-__device__ __forceinline__ int wave_unique(const int64_t (&k)[J], int32_t *out, int cap) {
-    const int lane = threadIdx.x & 63;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    int before = 0;
+// Slot of q, -1 if absent.
+__device__ __forceinline__ int32_t hs_find(const int32_t *keys, const int32_t *vals, int32_t q) {
+    int h = mpk_hash(q);
+    for (int probe = 0; probe < kMpkHash; ++probe) {
+        const int32_t kk = keys[h];
+        if (kk == q) return vals[h];
+        if (kk == -1) return -1;
+        h = (h + 1) & (kMpkHash - 1);
+    }
+    return -1;
+}
+
+// The first kMpkRegCols column indices of a row, loaded together (the loops
+// over them are unrolled so that they stay in registers).
+__device__ __forceinline__ void row_cols(const int32_t *__restrict__ col, int32_t j0, int32_t len,
+                                         int32_t (&cc)[kMpkRegCols]) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-        const int64_t up = __shfl_up(k[j], 1, 64);
-        const int64_t prev_last = __shfl(k[j > 0 ? j - 1 : 0], 63, 64);
-        const int64_t pred = lane > 0 ? up : prev_last;
-        const bool first = k[j] != kMpkPad && ((j == 0 && lane == 0) || k[j] != pred);
-        const unsigned long long bm = __ballot(first);
-        const int r = before + __popcll(bm & lt);
-        if (first && r < cap) out[r] = (int32_t)k[j];
-        before += __popcll(bm);
-    }
-    return before;
-}
-
-__device__ __forceinline__ int lds_find(const int32_t *a, int len, int32_t key) {
-    int lo = 0, hi = len;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (a[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < len && a[lo] == key) ? lo : -1;
-}
-
-// Slot of node q in R0 (keys node << 8 | slot, ascending), -1 if absent.
-__device__ __forceinline__ int r0_slot(const int64_t *r0key, int s0, int32_t q) {
-    int lo = 0, hi = s0;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if ((int32_t)(r0key[mid] >> 8) < q) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < s0 && (int32_t)(r0key[lo] >> 8) == q) ? (int)(r0key[lo] & 0xff) : -1;
+    for (int t = 0; t < kMpkRegCols; ++t) cc[t] = t < len ? col[j0 + t] : -1;
 }
 
 // Order check: every order[i] in [0, n) and no node twice (seen[] zeroed by the caller).
@@ -847,114 +815,114 @@ __global__ void k_mpk_check(int64_t n, const int32_t *__restrict__ order, int32_
 }
 
 // Layout of one block per 64-lane workgroup.  A block that does not fit (a
-// halo over the capacities, a row over kMpkLongRow entries, an order entry
-// outside [0, n)) gets s0 = 0 and sets flag bit 2; the caller then runs the
-// single sweeps instead.
+// halo or its local CSR over the capacities, an order entry outside [0, n))
+// gets s0 = 0 and sets flag bit 2; the caller then runs the single sweeps
+// instead.  R1 and R2 slots are numbered in discovery order; which slot a
+// node takes changes where its row sits in the LDS, not any value.
 template <typename TW>
 __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__restrict__ order,
                                                   const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col, const TW *__restrict__ val,
                                                   const TW *__restrict__ deg, MpkDev L, int32_t *flag) {
-    __shared__ int64_t r0key[kMpkRows];
-    __shared__ int32_t cand[kMpkCand];
-    __shared__ int32_t r1n[kMpkList];
-    __shared__ int32_t r2n[kMpkList];
+    __shared__ int32_t keys[kMpkHash];
+    __shared__ int32_t vals[kMpkHash];
+    __shared__ int32_t snode[kMpkSlots];
+    __shared__ int32_t next;
+    __shared__ int32_t full;
     const int lane = threadIdx.x;
     const int64_t b = blockIdx.x;
     const int64_t base = b * kMpkRows;
     const int s0 = (int)(n - base < kMpkRows ? n - base : kMpkRows);
+#pragma unroll
+    for (int i = 0; i < kMpkHash / 64; ++i) keys[i * 64 + lane] = -1;
+    if (lane == 0) {
+        next = s0;
+        full = 0;
+    }
     const int32_t p = lane < s0 ? order[base + lane] : -1;
     const bool bad = lane < s0 && (p < 0 || p >= n);
     bool over = __ballot(bad) != 0ull;
-    const int plen = (lane < s0 && !bad) ? rowptr[p + 1] - rowptr[p] : 0;
-    over = over || __ballot(plen > kMpkLongRow) != 0ull;
-    // R0, node-sorted with its slots
-    {
-        int64_t key[1] = {(lane < s0 && !bad) ? (((int64_t)p << 8) | lane) : kMpkPad};
-        wave_sort<1>(key);
-        r0key[lane] = key[0];
+    int32_t j0 = 0, len = 0;
+    int32_t cc[kMpkRegCols];
+    if (lane < s0 && !bad) {
+        j0 = rowptr[p];
+        len = rowptr[p + 1] - j0;
+    }
+    over = over || __ballot(len > kMpkEnt) != 0ull;
+    if (!over) row_cols(col, j0, len, cc);
+    __syncthreads();
+    // R0: slot = position in the order
+    if (!over && lane < s0) {
+        snode[lane] = p;
+        int h = mpk_hash(p);
+        for (int probe = 0; probe < kMpkHash; ++probe) {
+            const int32_t old = atomicCAS(&keys[h], -1, p);
+            if (old == -1) {
+                vals[h] = lane;
+                break;
+            }
+            if (old == p) break;        // a repeated order entry: refused by the order check
+            h = (h + 1) & (kMpkHash - 1);
+        }
     }
     __syncthreads();
-    int s1 = 0, s2 = 0;
+    // R1: neighbours of R0 not yet in the map
     if (!over) {
-        // R1: neighbours of R0 outside R0
-        const int32_t j0 = lane < s0 ? rowptr[p] : 0;
-        int c = 0;
-        for (int32_t t = 0; t < plen; ++t) c += r0_slot(r0key, s0, col[j0 + t]) < 0 ? 1 : 0;
-        const int incl = wave_incl_sum(c);
-        const int total = __shfl(incl, 63, 64);
-        over = total > kMpkCand;
-        if (!over) {
-            int at = incl - c;
-            for (int32_t t = 0; t < plen; ++t) {
-                const int32_t q = col[j0 + t];
-                if (r0_slot(r0key, s0, q) < 0) cand[at++] = q;
+#pragma unroll
+        for (int t = 0; t < kMpkRegCols; ++t)
+            if (t < len && hs_insert(keys, vals, &next, snode, cc[t]) < 0) full = 1;
+        for (int t = kMpkRegCols; t < len; ++t)
+            if (hs_insert(keys, vals, &next, snode, col[j0 + t]) < 0) full = 1;
+    }
+    __syncthreads();
+    const int s01 = next;
+    over = over || full != 0 || s01 > kMpk01;
+    // R2: neighbours of R1 not yet in the map (R1 slots lane and 64 + lane)
+    int32_t j1[2] = {0, 0}, len1[2] = {0, 0};
+    int32_t c1[2][kMpkRegCols];
+    if (!over) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int r = s0 + h * 64 + lane;
+            if (r < s01) {
+                const int32_t q = snode[r];
+                j1[h] = rowptr[q];
+                len1[h] = rowptr[q + 1] - j1[h];
             }
         }
-        __syncthreads();
-        if (!over) {
-            int64_t key[kMpkCand / 64];
-#pragma unroll
-            for (int j = 0; j < kMpkCand / 64; ++j) key[j] = j * 64 + lane < total ? cand[j * 64 + lane] : kMpkPad;
-            wave_sort<kMpkCand / 64>(key);
-            s1 = wave_unique<kMpkCand / 64>(key, r1n, kMpkList);
-            over = s0 + s1 > kMpk01;
-        }
-        __syncthreads();
+        over = __ballot(len1[0] > kMpkEnt || len1[1] > kMpkEnt) != 0ull;
     }
     if (!over) {
-        // R2: neighbours of R1 outside R0 and R1 (R1 entries lane and 64 + lane)
-        int32_t j0[2] = {0, 0}, len[2] = {0, 0};
 #pragma unroll
-        for (int h = 0; h < 2; ++h)
-            if (h * 64 + lane < s1) {
-                const int32_t q1 = r1n[h * 64 + lane];
-                j0[h] = rowptr[q1];
-                len[h] = rowptr[q1 + 1] - j0[h];
-            }
-        over = __ballot(len[0] > kMpkLongRow || len[1] > kMpkLongRow) != 0ull;
-        int c = 0;
-        if (!over)
+        for (int h = 0; h < 2; ++h) row_cols(col, j1[h], len1[h], c1[h]);
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                for (int32_t t = 0; t < len[h]; ++t) {
-                    const int32_t x = col[j0[h] + t];
-                    c += (r0_slot(r0key, s0, x) < 0 && lds_find(r1n, s1, x) < 0) ? 1 : 0;
-                }
-        const int incl = wave_incl_sum(c);
-        const int total = __shfl(incl, 63, 64);
-        over = over || total > kMpkCand;
-        if (!over) {
-            int at = incl - c;
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                for (int32_t t = 0; t < len[h]; ++t) {
-                    const int32_t x = col[j0[h] + t];
-                    if (r0_slot(r0key, s0, x) < 0 && lds_find(r1n, s1, x) < 0) cand[at++] = x;
-                }
+            for (int t = 0; t < kMpkRegCols; ++t)
+                if (t < len1[h] && hs_insert(keys, vals, &next, snode, c1[h][t]) < 0) full = 1;
+            for (int t = kMpkRegCols; t < len1[h]; ++t)
+                if (hs_insert(keys, vals, &next, snode, col[j1[h] + t]) < 0) full = 1;
         }
-        __syncthreads();
-        if (!over) {
-            int64_t key[kMpkCand / 64];
-#pragma unroll
-            for (int j = 0; j < kMpkCand / 64; ++j) key[j] = j * 64 + lane < total ? cand[j * 64 + lane] : kMpkPad;
-            wave_sort<kMpkCand / 64>(key);
-            s2 = wave_unique<kMpkCand / 64>(key, r2n, kMpkList);
-            over = s0 + s1 + s2 > kMpkSlots;
-        }
-        __syncthreads();
     }
-    // local CSR of the rows of R0 and R1 (slots r = lane and 64 + lane)
-    const int s01 = s0 + s1;
-    int32_t na = 0, nb2 = 0, la = 0, lb = 0;
+    __syncthreads();
+    const int S = next;
+    over = over || full != 0 || S > kMpkSlots;
+    // local CSR of the rows of R0 and R1: slot lane (an R0 row, or R1 when the block is short) and slot 64 + lane
+    int32_t ja = 0, la = 0, jb = 0, lb = 0, na = 0, nb2 = 0;
     if (!over) {
-        if (lane < s01) {
-            na = lane < s0 ? p : r1n[lane - s0];
-            la = rowptr[na + 1] - rowptr[na];
+        if (lane < s0) {
+            na = p;
+            ja = j0;
+            la = len;
+        } else if (lane < s01) {
+            na = snode[lane];
+            ja = rowptr[na];
+            la = rowptr[na + 1] - ja;
         }
         if (64 + lane < s01) {
-            nb2 = r1n[64 + lane - s0];
-            lb = rowptr[nb2 + 1] - rowptr[nb2];
+            nb2 = snode[64 + lane];
+            jb = rowptr[nb2];
+            lb = rowptr[nb2 + 1] - jb;
         }
     }
     const int ia = wave_incl_sum(la);
@@ -974,31 +942,36 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     uint8_t *lc = L.lcol + b * kMpkEnt;
     TW *lv = (TW *)L.lval + b * kMpkEnt;
     TW *ld = (TW *)L.ldeg + b * kMpk01;
-    auto emit = [&](int r, int32_t node, int len, int start) {
-        ro[r] = (uint16_t)start;
-        ld[r] = deg[node];
-        const int32_t j0 = rowptr[node];
-        for (int t = 0; t < len; ++t) {
-            const int32_t q = col[j0 + t];
-            int sl = r0_slot(r0key, s0, q);
-            if (sl < 0) {
-                const int i1 = lds_find(r1n, s1, q);
-                sl = i1 >= 0 ? s0 + i1 : s01 + lds_find(r2n, s2, q);
+    const int32_t er[2] = {lane, 64 + lane}, en[2] = {na, nb2}, ej[2] = {ja, jb}, el[2] = {la, lb},
+                  es[2] = {ia - la, ib - lb};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (er[h] >= s01) continue;
+        ro[er[h]] = (uint16_t)es[h];
+        ld[er[h]] = deg[en[h]];
+        int32_t cr[kMpkRegCols];
+        row_cols(col, ej[h], el[h], cr);
+        TW vr[kMpkRegCols];
+#pragma unroll
+        for (int t = 0; t < kMpkRegCols; ++t) vr[t] = t < el[h] ? val[ej[h] + t] : TW(0);
+#pragma unroll
+        for (int t = 0; t < kMpkRegCols; ++t)
+            if (t < el[h]) {
+                lc[es[h] + t] = (uint8_t)hs_find(keys, vals, cr[t]);
+                lv[es[h] + t] = vr[t];
             }
-            lc[start + t] = (uint8_t)sl;
-            lv[start + t] = val[j0 + t];
+        for (int t = kMpkRegCols; t < el[h]; ++t) {
+            lc[es[h] + t] = (uint8_t)hs_find(keys, vals, col[ej[h] + t]);
+            lv[es[h] + t] = val[ej[h] + t];
         }
-    };
-    if (lane < s01) emit(lane, na, la, ia - la);
-    if (64 + lane < s01) emit(64 + lane, nb2, lb, ib - lb);
+    }
     if (lane == 0) ro[s01] = (uint16_t)nent;
     int32_t *nd = L.node + b * kMpkSlots;
-    const int S = s01 + s2;
-    for (int i = lane; i < S; i += 64) nd[i] = i < s0 ? order[base + i] : (i < s01 ? r1n[i - s0] : r2n[i - s01]);
+    for (int i = lane; i < S; i += 64) nd[i] = snode[i];
     if (lane == 0) {
         L.meta[4 * b] = s0;
-        L.meta[4 * b + 1] = s1;
-        L.meta[4 * b + 2] = s2;
+        L.meta[4 * b + 1] = s01 - s0;
+        L.meta[4 * b + 2] = S - s01;
         L.meta[4 * b + 3] = nent;
     }
 }
