@@ -188,20 +188,49 @@ def run_chunglu(args) -> dict:
     for l in range(L):
         x0[l] = torch.from_numpy(W.workload_block("chunglu", g.n, level=l)).cuda()
     out = {}
-    for name, storage in (("f32", torch.float32), ("f64", torch.float64)):
+    keeps = {}
+    # the library's own choice of node numbering per level (the spanning tree's preorder on the large levels),
+    # then both hierarchies in the input numbering for comparison (same bits); one untimed call first, so that
+    # no run pays the library's first device allocations
+    S.sfg_sparsify(g.n, u, v, w32, x0, S.make_params(levels=L, k=k, sweeps=T, frac=f, storage=torch.float32))
+    for name, storage, order in (("f32", torch.float32, None), ("f64", torch.float64, None),
+                                 ("f32_input_numbering", torch.float32, "0"),
+                                 ("f64_input_numbering", torch.float64, "0")):
         p = S.make_params(levels=L, k=k, sweeps=T, frac=f, storage=storage)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        keep, rep = S.sfg_sparsify(g.n, u, v, w32, x0, p)
-        t1 = time.perf_counter()
+        if order is not None:
+            os.environ["SFG_NODE_ORDER"] = order
+        try:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            keep, rep = S.sfg_sparsify(g.n, u, v, w32, x0, p)
+            t1 = time.perf_counter()
+        finally:
+            os.environ.pop("SFG_NODE_ORDER", None)
         out[name] = {"ms_total": round((t1 - t0) * 1e3, 1),
                      "levels": [{"n": r["n"], "m": r["m"], "n_cand": r["n_cand"], "k_sel": r["k_sel"],
-                                 "ms_smooth": round(r["ms_smooth"], 3), "ms_score": round(r["ms_score"], 3),
-                                 "ms_select": round(r["ms_select"], 3)} for r in rep],
+                                 "node_order": r["node_order"], "ms_smooth": round(r["ms_smooth"], 3),
+                                 "ms_score": round(r["ms_score"], 3), "ms_select": round(r["ms_select"], 3)}
+                                for r in rep],
                      "kept_edges": int((keep > 0).sum().item())}
+        keeps[name] = keep
         log(f"chunglu {name}: {out[name]['ms_total']} ms, sizes {[r['n'] for r in rep]}")
+    for dt in ("f32", "f64"):
+        out[dt + "_input_numbering"]["same_sparsifier"] = bool(torch.equal(keeps[dt], keeps[dt + "_input_numbering"]))
     G = S.sfg_laplacian_csr(g.n, u, v, w32)
     roof = sweep_roofline(G, x0[0], T, torch.float32, False, g.n, G.nnz, k, 4, 4)
+    roof["numbering"] = "input (ids in expected-degree order)"
+    # the same level-0 sweep in the preorder of G_0's maximum spanning tree, as the hierarchy runs it
+    tree, _ = S.sfg_spanning_tree(g.n, u, v, w32.double())
+    order = S.sfg_tree_order(g.n, u, v, w32.double(), tree).order.long()
+    inv = torch.empty_like(order)
+    inv[order] = torch.arange(g.n, device=order.device)
+    a, b = inv[u.long()], inv[v.long()]
+    lo, hi = torch.minimum(a, b), torch.maximum(a, b)
+    srt = torch.argsort(lo * g.n + hi)
+    Gp = S.sfg_laplacian_csr(g.n, lo[srt].to(torch.int32), hi[srt].to(torch.int32), w32[srt])
+    roof_p = sweep_roofline(Gp, x0[0][order].contiguous(), T, torch.float32, False, g.n, Gp.nnz, k, 4, 4)
+    roof_p["numbering"] = "preorder of the maximum spanning tree"
+    del Gp, G
     lv = out["f32"]["levels"]
     ratio = [round(lv[i]["n"] / lv[i + 1]["n"], 2) for i in range(len(lv) - 1) if lv[i + 1]["n"] > 0]
     return {"metric": "edges per second through the 5-level hierarchy (coarsening + scoring at every level)",
@@ -209,7 +238,8 @@ def run_chunglu(args) -> dict:
             "data": "synthetic",
             "config": {"workload": g.name, "nodes": g.n, "edges": g.m, "vectors": k, "sweeps": T, "frac": f,
                        "levels": L},
-            "runs": out, "coarsening_ratio": ratio, "roofline_f32_sweep_level0_graph": roof,
+            "runs": out, "coarsening_ratio": ratio, "roofline_f32_sweep_level0_graph": roof_p,
+            "roofline_f32_sweep_level0_graph_input_numbering": roof,
             "note": "ms_total includes the per-aggregate spanning forests (GPU Boruvka) and all coarsening"}
 
 

@@ -545,12 +545,16 @@ typedef struct {
     int32_t precision_fallback;   /* F16/BF16/F32 with a band: 1 when the re-scoring cone predicted for the
                                      expected band exceeded a quarter of the full pass, so the level ran the
                                      FP64 path instead (same selection, no reduced-precision pass) */
-    int32_t node_order;   /* numbering the level was swept in: 0 the input's, 1 the spanning tree's preorder
-                             (Jacobi smoother, single level; taken when the call plans at least 512 sweep
+    int32_t node_order;   /* numbering the level was swept in: 0 the input's, 1 the spanning tree's preorder.
+                             Single level (Jacobi smoother): taken when the call plans at least 512 sweep
                              launches of 8-column parts over all its batches, n >= 65536, and more than a
-                             quarter of the scoring graph's entries lie over 4096 rows from their own row;
-                             the environment variable SFG_NODE_ORDER=0 / 1 forces either).  Results are
-                             bit-identical either way: rows keep their entry order */
+                             quarter of the scoring graph's entries lie over 4096 rows from their own row.
+                             Hierarchy (levels > 1): per level, the preorder of a spanning tree of G_l, for the
+                             sweeps on G_l and on the level's sparsifier, when n_l >= 65536, the level's block
+                             of k vectors exceeds 96 MiB (256 MiB on the coarse levels, whose spanning tree is
+                             computed for it) and more than half of G_l's entries lie over 4096 rows from their
+                             own row.  The environment variable SFG_NODE_ORDER=0 / 1 forces
+                             either.  Results are bit-identical either way: rows keep their entry order */
     int64_t n_scored;      /* candidates scored exactly (n_cand, or the surrogate's share) */
     int32_t surrogate_fallback;   /* a surrogate was given but was not usable: the plain path ran */
 } sfg_level_report;

@@ -39,7 +39,10 @@ void affinity(const void *x, sfg_dtype xt, int64_t n, int32_t k, int64_t m, cons
 void convert_weights(const void *w, sfg_dtype wt, sfg_dtype want, int64_t m, void *out, hipStream_t s);
 int64_t spanning_tree_gpu(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const void *w, sfg_dtype wt,
                           const uint8_t *allowed, uint8_t *in_tree, DevArena &A, hipStream_t s);
-struct NodeOrder;
+void level_node_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const sfg_csr *G,
+                      const uint8_t *tree, int32_t k, sfg_dtype storage, NodeOrder *no, DevArena &A, hipStream_t s);
+sfg_csr relabel_csr(const sfg_csr *H, const int32_t *order, const int32_t *inv, DevArena &A, hipStream_t s);
+void gather_block(int64_t n, int32_t k, const int32_t *order, const double *src, double *dst, hipStream_t s);
 void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
                  const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
                  DevArena &A, hipStream_t s, int64_t k_take, NodeOrder *no);
@@ -418,11 +421,13 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
         lv[0].w32 = A.alloc<float>(m + 1);
         convert_weights(w, wt, SFG_F32, m, lv[0].w32, s);
     }
+    uint8_t *tree0 = A.alloc<uint8_t>(m + 1);
     {
-        uint8_t *t = A.alloc<uint8_t>(m + 1);
-        const int64_t comps = spanning_tree_gpu(n, m, u, v, lv[0].w64, SFG_F64, nullptr, t, A, s);
+        const int64_t comps = spanning_tree_gpu(n, m, u, v, lv[0].w64, SFG_F64, nullptr, tree0, A, s);
         if (comps != 1) fail(SFG_ENOTCONN, "sparsify: graph has " + std::to_string(comps) + " components");
     }
+    // node numbering of each level's sweeps (decided when the level is coarsened, or scored if it is the last)
+    std::vector<NodeOrder> ord(L);
     // ---- coarsening: G_0 .. G_{L-1}
     int built = 1;
     for (int l = 0; l + 1 < L; ++l) {
@@ -447,10 +452,24 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
             SFG_HIP(hipMemcpyAsync(&max_row, mr, 4, hipMemcpyDeviceToHost, s));
             SFG_HIP(hipStreamSynchronize(s));
         }
-        smooth(&G, p->k, p->sweeps, p->omega, x0 + (size_t)l * n * p->k, vt, 0, x, A.raw(wss), wss, s, max_row);
+        // the sweeps on G_l, in the level's node numbering; affinities per edge id, numbering-free
+        NodeOrder &no = ord[l];
+        level_node_order(F.n, F.m, F.u, F.v, F.w64, &G, l == 0 ? tree0 : nullptr, p->k, vt, &no, A, s);
+        const double *xl = x0 + (size_t)l * n * p->k;
+        const int32_t *au = F.u, *av = F.v;
+        sfg_csr Gs = G;
+        if (no.use) {
+            Gs = relabel_csr(&G, no.order, no.inv, A, s);
+            double *xg = A.alloc<double>((size_t)F.n * p->k + 1);
+            gather_block(F.n, p->k, no.order, xl, xg, s);
+            xl = xg;
+            au = no.u;
+            av = no.v;
+        }
+        smooth(&Gs, p->k, p->sweeps, p->omega, xl, vt, 0, x, A.raw(wss), wss, s, max_row);
         void *aff = A.raw((F.m + 1) * dtype_size(vt));
         const size_t wsa = affinity_workspace_bytes(F.n, p->k);
-        affinity(x, vt, F.n, p->k, F.m, F.u, F.v, aff, vt, A.raw(wsa), wsa, s);
+        affinity(x, vt, F.n, p->k, F.m, au, av, aff, vt, A.raw(wsa), wsa, s);
         LevelGraph &C = lv[l + 1];
         F.agg = A.alloc<int32_t>(F.n + 1);
         C.u = A.alloc<int32_t>(F.m + 1);
@@ -496,7 +515,7 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
         uint8_t *kp = (l == 1) ? keep : A.alloc<uint8_t>(F.m + 1);
         sfg_level_report *lr = rep ? &rep->level[l - 1] : nullptr;
         score_level(F.n, F.m, F.u, F.v, F.w64, F.w32, base, p, x0 + (size_t)(l - 1) * n * p->k, kp, lr, A, s, -1,
-                    nullptr);
+                    &ord[l - 1]);
         P = kp;
     }
 }

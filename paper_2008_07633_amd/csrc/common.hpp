@@ -170,6 +170,18 @@ void exclusive_scan_i32(const int32_t *in, int32_t *out, int64_t n, int32_t *scr
 void fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void fill_u8(uint8_t *p, int64_t n, uint8_t v, hipStream_t s);
 
+// Node numbering for the sweeps of a sparsify call or of one hierarchy level
+// (the rules are with score_level and level_node_order).
+struct NodeOrder {
+    int64_t launches = 0;       // planned column-part sweep launches (set by the caller)
+    bool decided = false;
+    bool use = false;
+    int32_t *order = nullptr;   // [n] node at new position i
+    int32_t *inv = nullptr;     // [n] new position of node j
+    int32_t *u = nullptr;       // [m] endpoints in the new numbering
+    int32_t *v = nullptr;
+};
+
 // Device buffers owned by one allocating call (sfg_sparsify, ...), carved
 // from chunks of at least 256 MB.  A call that ends with finish() (its stream
 // drained) hands its chunks to a per-device cache (up to 16 GiB) that later

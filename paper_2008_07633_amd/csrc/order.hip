@@ -60,23 +60,34 @@ __global__ void k_row_len(int64_t n, const int32_t *__restrict__ order, const in
 }
 
 // New row i is old row order[i]: entries in their stored order, columns
-// through inv, values, edge ids and the degree carried along.
+// through inv, values and edge ids carried along.  A thread per entry (rows
+// of power-law graphs run to thousands of entries): its new row is found by
+// binary search in the new row pointers.
 template <typename T>
-__global__ void k_row_copy(int64_t n, const int32_t *__restrict__ order, const int32_t *__restrict__ inv,
-                           const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
-                           const T *__restrict__ val, const int32_t *__restrict__ eid, const T *__restrict__ deg,
-                           const int32_t *__restrict__ nrowptr, int32_t *__restrict__ ncol, T *__restrict__ nval,
-                           int32_t *__restrict__ neid, T *__restrict__ ndeg) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int32_t p = order[i];
-    const int32_t a = rowptr[p], e = rowptr[p + 1], b = nrowptr[i];
-    for (int32_t j = a; j < e; ++j) {
-        ncol[b + (j - a)] = inv[col[j]];
-        nval[b + (j - a)] = val[j];
-        if (neid) neid[b + (j - a)] = eid[j];
+__global__ void k_entry_copy(int64_t n, int64_t nnz, const int32_t *__restrict__ order,
+                             const int32_t *__restrict__ inv, const int32_t *__restrict__ rowptr,
+                             const int32_t *__restrict__ col, const T *__restrict__ val,
+                             const int32_t *__restrict__ eid, const int32_t *__restrict__ nrowptr,
+                             int32_t *__restrict__ ncol, T *__restrict__ nval, int32_t *__restrict__ neid) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nnz || j >= nrowptr[n]) return;
+    int64_t lo = 0, hi = n - 1;     // the last row i with nrowptr[i] <= j
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (nrowptr[mid] <= j) lo = mid;
+        else hi = mid - 1;
     }
-    ndeg[i] = deg[p];
+    const int32_t src = rowptr[order[lo]] + (int32_t)(j - nrowptr[lo]);
+    ncol[j] = inv[col[src]];
+    nval[j] = val[src];
+    if (neid) neid[j] = eid[src];
+}
+
+template <typename T>
+__global__ void k_deg_copy(int64_t n, const int32_t *__restrict__ order, const T *__restrict__ deg,
+                           T *__restrict__ ndeg) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) ndeg[i] = deg[order[i]];
 }
 
 __global__ void k_map_ends(int64_t m, const int32_t *__restrict__ inv, const int32_t *__restrict__ u,
@@ -126,12 +137,18 @@ sfg_csr relabel_csr(const sfg_csr *H, const int32_t *order, const int32_t *inv, 
     hipLaunchKernelGGL(k_row_len, g, b, 0, s, n, order, H->rowptr, len);
     SFG_LAUNCH_CHECK();
     exclusive_scan_i32(len, rowptr, n, scr, s);
-    if (H->vt == SFG_F64)
-        hipLaunchKernelGGL(k_row_copy<double>, g, b, 0, s, n, order, inv, H->rowptr, H->col, (const double *)H->val,
-                           H->eid, (const double *)H->deg, rowptr, col, (double *)val, eid, (double *)deg);
-    else
-        hipLaunchKernelGGL(k_row_copy<float>, g, b, 0, s, n, order, inv, H->rowptr, H->col, (const float *)H->val,
-                           H->eid, (const float *)H->deg, rowptr, col, (float *)val, eid, (float *)deg);
+    const dim3 ge(grid_for(nnz > 0 ? nnz : 1, kB));
+    if (H->vt == SFG_F64) {
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_entry_copy<double>, ge, b, 0, s, n, nnz, order, inv, H->rowptr, H->col,
+                               (const double *)H->val, H->eid, rowptr, col, (double *)val, eid);
+        hipLaunchKernelGGL(k_deg_copy<double>, g, b, 0, s, n, order, (const double *)H->deg, (double *)deg);
+    } else {
+        if (nnz > 0)
+            hipLaunchKernelGGL(k_entry_copy<float>, ge, b, 0, s, n, nnz, order, inv, H->rowptr, H->col,
+                               (const float *)H->val, H->eid, rowptr, col, (float *)val, eid);
+        hipLaunchKernelGGL(k_deg_copy<float>, g, b, 0, s, n, order, (const float *)H->deg, (float *)deg);
+    }
     SFG_LAUNCH_CHECK();
     return sfg_csr{n, nnz, rowptr, col, val, eid, deg, H->vt};
 }

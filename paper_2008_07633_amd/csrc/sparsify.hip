@@ -298,9 +298,6 @@ struct Timer {
 
 }  // namespace
 
-// Embed (smooth on the scoring graph), score the edges outside `base`, add
-// the top k_take of them (k_take < 0: ceil(frac * n_cand)).  Writes keep
-// (1 = base, 2 = added); keep may be base itself.
 // Numbering of the nodes for the sweeps of one sparsify call, decided at its
 // first scored level and kept for the later batches: the input numbering, or
 // the preorder of the spanning tree (the edges marked 1 in the level's base).
@@ -315,15 +312,6 @@ struct Timer {
 // 16.6 ms in preorder, four batches 44.8 against 44.3 ms.
 // SFG_NODE_ORDER=0 keeps the input numbering, =1 always takes the preorder
 // (read at every call; tests use it).  Results do not depend on the choice.
-struct NodeOrder {
-    int64_t launches = 0;       // planned column-part sweep launches (set by the caller)
-    bool decided = false;
-    bool use = false;
-    int32_t *order = nullptr;   // [n] node at new position i
-    int32_t *inv = nullptr;     // [n] new position of node j
-    int32_t *u = nullptr;       // [m] endpoints in the new numbering
-    int32_t *v = nullptr;
-};
 
 namespace {
 
@@ -359,6 +347,53 @@ void make_node_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, c
 
 }  // namespace
 
+// Node order of one level of the hierarchy (Alg. 1): decided once per level
+// and used for its sweeps on G_l (the coarsening affinities) and, when the
+// level is scored, on its sparsifier.  The preorder of a spanning tree of G_l
+// (`tree`: its edges marked 1; nullptr = compute the maximum one) is taken
+// when the level has at least kOrderMinRows nodes, its block of k vectors
+// exceeds kOrderMinBlock bytes (kOrderMinBlockNoTree when the tree would have
+// to be computed first) and more than half of G_l's entries reach beyond
+// kNearRows rows.  The 4M-node Chung-Lu level-0 graph (input ids in
+// expected-degree order) sweeps in 1.38 ms in preorder against 3.57 ms (FP32)
+// and 5.9 against 7.3 ms (FP64); its FP32 hierarchy took 293 ms against 342.
+// Its 1M-node level 1 in FP64 (126 MB block, mostly served from the 256 MB
+// memory-side cache) gained less than its spanning tree and relabelling cost.
+// SFG_NODE_ORDER as above; results do not depend on the choice.
+constexpr double kOrderMinBlock = 96.0 * (1 << 20);
+constexpr double kOrderMinBlockNoTree = 256.0 * (1 << 20);
+
+void level_node_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const sfg_csr *G,
+                      const uint8_t *tree, int32_t k, sfg_dtype storage, NodeOrder *no, DevArena &A,
+                      hipStream_t s) {
+    no->decided = true;
+    no->use = false;
+    const int mode = node_order_mode();
+    if (mode == 0 || n < 2) return;
+    if (mode == 2) {
+        const double block = (double)n * k * dtype_size(storage);
+        if (n < kOrderMinRows || block <= (tree ? kOrderMinBlock : kOrderMinBlockNoTree)) return;
+        unsigned long long *far = A.alloc<unsigned long long>(1);
+        fill_i32((int32_t *)far, 2, 0, s);
+        far_entries(G, kNearRows, far, s);
+        unsigned long long far_h = 0;
+        SFG_HIP(hipMemcpyAsync(&far_h, far, 8, hipMemcpyDeviceToHost, s));
+        SFG_HIP(hipStreamSynchronize(s));
+        if (2 * far_h <= (unsigned long long)G->nnz) return;
+    }
+    if (!tree) {
+        uint8_t *t = A.alloc<uint8_t>(m + 1);
+        spanning_tree_gpu(n, m, u, v, w64, SFG_F64, nullptr, t, A, s);
+        tree = t;
+    }
+    no->use = true;
+    make_node_order(n, m, u, v, w64, tree, no, A, s);
+}
+
+// Embed (smooth on the scoring graph), score the edges outside `base`, add
+// the top k_take of them (k_take < 0: ceil(frac * n_cand)).  Writes keep
+// (1 = base, 2 = added); keep may be base itself.  `no` (may be nullptr):
+// the node numbering of the sweeps, decided here when not decided yet.
 void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
                  const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
                  DevArena &A, hipStream_t s, int64_t k_take, NodeOrder *no) {

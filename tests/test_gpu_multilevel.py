@@ -69,6 +69,24 @@ def test_multilevel_matches_oracle(S, orc, name, levels):
         assert lr["n_cand"] == lr_ref.n_cand and lr["k_sel"] == lr_ref.k_sel and lr["tau"] == lr_ref.tau
 
 
+@pytest.mark.parametrize("name,levels", [("chunglu20k", 5), ("mesh20", 3)])
+def test_multilevel_in_tree_preorder_matches_oracle(S, orc, name, levels, monkeypatch):
+    # every level's sweeps (on G_l for the affinities, on the level's sparsifier for the scores) in the preorder
+    # of a spanning tree of G_l: rows keep their entry order, so the hierarchy is the oracle's bit for bit
+    monkeypatch.setenv("SFG_NODE_ORDER", "1")
+    g = GRAPHS[name]()
+    k, T, f = 8, 10, 0.1
+    X0s = np.stack([W.random_block(g.n, k, 80 + l) for l in range(levels)])
+    ref, lv = orc.sparsify_multilevel(g.n, g.u, g.v, g.w, list(X0s), levels, T, f)
+    p = S.make_params(levels=levels, k=k, sweeps=T, frac=f)
+    keep, rep = S.sfg_sparsify(g.n, dev(g.u), dev(g.v), dev(g.w), dev(X0s), p)
+    # every swept level (the coarsest, P = G, is not swept)
+    assert [r["node_order"] for r in rep[:-1]] == [1] * (len(rep) - 1)
+    np.testing.assert_array_equal(keep.cpu().numpy(), ref.keep)
+    for lr_ref, lr in zip(ref.levels[::-1], rep):
+        assert lr["n_cand"] == lr_ref.n_cand and lr["k_sel"] == lr_ref.k_sel and lr["tau"] == lr_ref.tau
+
+
 def test_multilevel_fp32_is_a_valid_sparsifier(S, orc):
     g = W.chung_lu(20000, 200000, 2.2, seed=4)
     levels, k, T, f = 5, 16, 20, 0.1
