@@ -260,12 +260,13 @@ def headline(args, S, BW) -> dict:
 
     reps = args.sweep_reps
     t_smooth = BW.ev_time(lambda: P["smooth"](T), reps)
-    pairs = bool(P["info"].get("pairs", 0))
-    if pairs:
-        # a launch takes two sweeps; the pass over 2 sweeps holds one launch (which also centres) and the layout
-        t_two = BW.ev_time(lambda: P["smooth"](2), reps)
-        t_one = t_two
-        t_sweep = (t_smooth - t_two) / (T - 2)
+    per_pass = int(P["info"].get("sweeps_per_pass", 1))
+    fused = per_pass >= 2
+    if fused:
+        # a launch takes per_pass sweeps: T - per_pass sweeps run one full pass fewer (same layout, centring
+        # first pass and shorter last pass), so the difference is one launch
+        t_one = BW.ev_time(lambda: P["smooth"](T - per_pass), reps)
+        t_sweep = (t_smooth - t_one) / per_pass
     else:
         t_one = BW.ev_time(lambda: P["smooth"](1), reps)
         # the first sweep also centres (reads the FP64 block); the other T-1 are plain sweeps
@@ -278,11 +279,11 @@ def headline(args, S, BW) -> dict:
 
     bsw = sweep_bytes(g.n, nnz, k, sx, sw)
     bsc = score_bytes(ncand, g.n, k, sx, sw, sx)
-    parts = 1 if pairs else sweep_parts(g.n, nnz, k, sx, sw, gs)
+    parts = 1 if fused else sweep_parts(g.n, nnz, k, sx, sw, gs)
     # a launch of the fused kernel must move one sweep's bytes (the graph once, X_t in, X_t+2 out): X_t+1 stays
     # on chip.  Its roofline is taken against those bytes; the smoothing rate below counts B_sweep per sweep.
     b_launch = sweep_bytes(g.n, nnz, k // parts, sx, sw)
-    t_launch = (2 if pairs else 1) * t_sweep / parts
+    t_launch = per_pass * t_sweep / parts
     achieved = b_launch / (t_launch * 1e-3) / 1e9
     smoothing_gbs = bsw / (t_sweep * 1e-3) / 1e9
     working_set = sweep_bytes(g.n, nnz, k // parts, sx, sw)
@@ -294,14 +295,15 @@ def headline(args, S, BW) -> dict:
     traffic = None
     tf = HEADLINE[name]["traffic"]
     if os.path.exists(tf) and not gs:
-        ent = json.load(open(tf)).get(args.dtype + ("_pairs" if pairs else ""))
+        ent = json.load(open(tf)).get(args.dtype + (f"_pass{per_pass}" if fused else ""))
         if ent and ent.get("src_hash") == src_hash(SWEEP_SRC):
             traffic = ent["hbm_bytes_per_launch"]
     if gs:
         kname = f"k_sweep_color (one Gauss-Seidel sweep: {P['classes'][3]} colour classes of the tree, in place)"
-    elif pairs:
-        kname = (f"k_sweep2 (two damped-Jacobi sweeps of the {k}-vector block on the tree per launch, blocks of 64 "
-                 f"rows of the tree's preorder with their 2-hop neighbourhoods in LDS; bytes: one sweep's)")
+    elif fused:
+        kname = (f"k_sweep_pass<{per_pass}> ({per_pass} damped-Jacobi sweeps of the {k}-vector block on the tree "
+                 f"per launch, blocks of 64 rows of the tree's preorder with their {per_pass}-hop neighbourhoods in "
+                 f"LDS; bytes: one sweep's)")
     elif parts > 1:
         kname = f"k_sweep (one damped-Jacobi sweep of an 8-vector column part of the {k}-vector block on the tree)"
     else:
@@ -309,7 +311,7 @@ def headline(args, S, BW) -> dict:
     roofline = {"bound": bound, "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "GB/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": kname,
                 "algorithmic_bytes_per_launch": b_launch, "avg_launch_us": round(t_launch * 1e3, 2),
-                "launches_per_sweep": P["classes"][3] if gs else (0.5 if pairs else parts),
+                "launches_per_sweep": P["classes"][3] if gs else (round(1 / per_pass, 4) if fused else parts),
                 "working_set_bytes": working_set,
                 # the smoothing rate of the metric: T B_sweep / t(T sweeps), the graph and X counted once per sweep;
                 # with two sweeps per pass over X it can exceed the HBM peak (it is then the one-sweep-per-pass
@@ -337,7 +339,7 @@ def headline(args, S, BW) -> dict:
         "cpu_baseline": None,
         "copy": copy,
         "stages_ms": {"csr": round(t_csr, 4), "smooth": round(t_smooth, 4),
-                      ("smooth_2sweeps" if pairs else "smooth_1sweep"): round(t_one, 4),
+                      (f"smooth_{T - per_pass}sweeps" if fused else "smooth_1sweep"): round(t_one, 4),
                       "sweep": round(t_sweep, 4), "score": round(t_score, 4), "select": round(t_select, 4)},
         "edges_scored_per_s_score_kernel": round(ncand / (t_score * 1e-3), 1),
         "score_gbs": round(bsc / (t_score * 1e-3) / 1e9, 1),
@@ -363,8 +365,10 @@ def headline(args, S, BW) -> dict:
         P32 = scoring_pass(S, g, u, v, w64, tree, cand, x0, k, T, omega, ksel, torch.float32, False, dev, order)
         ms32 = timed_steps(torch, P32["step"], args.steps, args.warmup)
         # P32["sel"] holds the selection of the last timed step, made before these smoothing timings
-        if order is not None:
-            t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](2), reps)) / (T - 2)
+        pp32 = int(P32["info"].get("sweeps_per_pass", 1))
+        if pp32 >= 2:
+            t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](T - pp32),
+                                                                             reps)) / pp32
         else:
             t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](1), reps)) / (T - 1)
         b32 = sweep_bytes(g.n, nnz, k, 4, 4)

@@ -172,30 +172,36 @@ sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega,
                       void *ws, size_t ws_bytes, void *stream);
 
 /*
- * sfg_smooth with the rows taken in a given order, two sweeps per pass where
- * the graph allows: the same result, bit for bit.  The rows are split into
- * blocks of 64 consecutive entries of `order`; for each block a workgroup
- * loads the current iterate of the block's rows and of their 1- and 2-hop
- * neighbours into LDS, forms the next iterate of the block and its 1-hop
- * neighbours there, and writes the one after it for the block only, so the
- * block X is read about once and written once per two sweeps.  Every row is
- * formed with sfg_smooth's arithmetic (entries in stored order, the same
- * epilogue, the intermediate iterate rounded to the storage type).  The order
- * decides how small the neighbourhoods are: a spanning tree's preorder
- * (sfg_tree_order) keeps them to a few dozen rows on meshes and power grids.
- *   order      [n] int32 (device): a permutation of the nodes (checked)
- *   pairs_out  (host, may be NULL): 1 if the sweeps ran two per pass, 0 if the
- *              call ran sfg_smooth instead: storage other than F64/F32, k not
- *              a multiple of 4 or over 128 bytes per row, fewer than 2 sweeps,
- *              a row over 256 entries, or a block whose neighbourhood exceeds
- *              the LDS capacity (176 rows, 112 of them within one hop)
+ * sfg_smooth with the rows taken in a given order, several sweeps per pass
+ * over the block where the graph allows: the same result, bit for bit.  The
+ * rows are split into blocks of 64 consecutive entries of `order`.  A layout
+ * pass gives each block its h-hop neighbourhood (h = 2 in FP64, 3 in FP32,
+ * fewer when a block exceeds the LDS capacities below) and a local copy of
+ * the rows it needs.  For each block a workgroup then loads the current iterate of the
+ * block's rows and of that neighbourhood into LDS, forms up to h sweeps there
+ * (sweep j for the rows within h - j hops of the block) and writes the last
+ * one for the block only, so the block X is read about once and written once
+ * per h sweeps.  Every row is formed with sfg_smooth's arithmetic (entries in
+ * stored order, the same epilogue, every intermediate iterate rounded to the
+ * storage type).  The order decides how small the neighbourhoods are: a
+ * spanning tree's preorder (sfg_tree_order) keeps them to a few hundred rows
+ * on meshes and power grids.
+ *   order         [n] int32 (device): a permutation of the nodes (checked)
+ *   per_pass_out  (host, may be NULL): the sweeps each pass took, 2 to 4; 1 if
+ *                 the call ran sfg_smooth instead: storage other than F64/F32,
+ *                 k not a multiple of 4 or over 128 bytes per row, fewer than
+ *                 2 sweeps, or a block whose 2-hop layout exceeds the
+ *                 capacities (168 rows in all, 112 within one hop, 288 local
+ *                 entries; 4 hops: 288, 224 within three hops, 512; 3 hops:
+ *                 224, 160, 384).  The environment variable SFG_SWEEP_HOPS
+ *                 (2, 3 or 4, read at every call) caps h; 0 forces sfg_smooth
  *   other arguments as sfg_smooth
  * Workspace: sfg_workspace_bytes(SFG_OP_SMOOTH_ORDERED, n, 0, k, storage).
- * Synchronises once (to learn whether every block fits).
+ * Synchronises once per layout tried (to learn whether every block fits).
  * Errors: those of sfg_smooth; SFG_EINVAL when order is not a permutation.
  */
 sfg_status sfg_smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps, double omega,
-                              const double *x0, sfg_dtype storage, int32_t final_f32, void *x, int32_t *pairs_out,
+                              const double *x0, sfg_dtype storage, int32_t final_f32, void *x, int32_t *per_pass_out,
                               void *ws, size_t ws_bytes, void *stream);
 
 /*

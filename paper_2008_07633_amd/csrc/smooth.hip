@@ -381,8 +381,18 @@ __global__ __launch_bounds__(256) void k_sweep_hub64(int32_t kw, int32_t ldx, in
             }
             for (int32_t e = t; e < len; e += 256) sw[e] = val[jc + e];
             __syncthreads();
-            if (t < kw)
-                for (int32_t e = 0; e < len; ++e) acc = madd(acc, sw[e], sx[e * kw + t]);
+            if (t < kw) {
+                // entry order kept: products (independent of acc) read ahead, then the dependent adds
+                int32_t e = 0;
+                for (; e + 8 <= len; e += 8) {
+                    double pr[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) pr[q] = sw[e + q] * sx[(e + q) * kw + t];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) acc = acc + pr[q];
+                }
+                for (; e < len; ++e) acc = madd(acc, sw[e], sx[e * kw + t]);
+            }
             __syncthreads();
         }
         if (t < kw) {
@@ -720,36 +730,55 @@ void run_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const
     if (lr.side) SFG_HIP(hipStreamWaitEvent(s, lr.ez, 0));   // join: the last hub rows before anything after
 }
 
-// ------------------------------------------------------------------ two sweeps per pass through LDS
+// ------------------------------------------------------------------ several sweeps per pass through LDS
 // Rows are taken in blocks of kMpkRows consecutive entries of a caller's
 // order (a permutation of the nodes; a spanning tree's preorder keeps a
-// block's neighbourhood small).  For block b with rows R0:
-//   R1 = neighbours of R0 outside R0,  R2 = neighbours of R1 outside R0 and R1.
-// A layout pass gives every block a slot per node of R0, R1 and R2 (R0 in
-// the order's sequence, then R1, then R2) and a local CSR of the rows
-// of R0 and R1: each entry's neighbour as a slot, its weight, in the row's
-// stored order, and the rows' degrees.  One workgroup then loads X_t of every
-// slot into LDS, forms X_t+1 of R0 and R1 there (all their neighbours have
-// slots) and X_t+2 of R0 (all theirs are in R0 and R1), and writes only that:
-// X is read about (1 + |R1 ∪ R2| / |R0|) times and written once per two
-// sweeps instead of twice each.  Every row's value is formed with the single
-// sweep's arithmetic -- entries in stored order, the same epilogue, the
+// block's neighbourhood small).  For block b, layer L0 is its rows and layer
+// L(h+1) the neighbours of Lh not in L0..Lh.  A layout pass for H hops gives
+// every block a slot per node of L0..LH, layer by layer (L0 in the order's
+// sequence), and a local CSR of the rows of L0..L(H-1): each entry's
+// neighbour as a slot, its weight, in the row's stored order, and the rows'
+// degrees.  One workgroup then loads X_t of every slot into LDS and forms
+// m <= H sweeps there: sweep j+1 for the rows of L0..L(m-1-j), whose
+// neighbours all lie one layer further out, and writes X_t+m of L0 only.
+// X is read about (|L0..Lm| / |L0|) times and written once per m sweeps
+// instead of twice per sweep.  Every row's value is formed with the single
+// sweep's arithmetic -- entries in stored order, the same epilogue, every
 // intermediate iterate rounded to the storage type -- so the result is
-// bit-identical.
-constexpr int kMpkRows = 64;      // R0 rows per block (one lane each in the layout pass)
-constexpr int kMpk01 = 112;       // capacity of R0 + R1
-constexpr int kMpkSlots = 168;    // capacity of R0 + R1 + R2 (about 26 KB of LDS per workgroup in FP64)
-constexpr int kMpkEnt = 288;      // capacity of the local CSR (entries of the rows of R0 + R1)
+// bit-identical to m single sweeps.
+constexpr int kMpkRows = 64;      // rows of L0 per block
 constexpr int kMpkRowBytes = 128; // row width the LDS holds: 16 FP64 or 32 FP32 columns
+constexpr int kMpkMeta = 8;       // ints of a block's sizes: layer ends e_0..e_H, then the local entries at [7]
+constexpr int kMpkMaxHops = 4;
 
-// Per-block layout, fixed capacity per block (views into the workspace).
+// Capacities per block for H hops: slots of L0..LH, rows of L0..L(H-1),
+// local CSR entries, node->slot map entries.  Measured on the 200^3 mesh's
+// spanning tree in preorder (64-row blocks; largest block of 125,000):
+// H = 2: 155 slots, 106 rows, 249 entries; H = 3: 211, 155, 357;
+// H = 4: 272, 211, 479.
+template <int H> struct MpkCaps;
+template <> struct MpkCaps<2> {
+    static constexpr int kSlots = 168, kRows = 112, kEnt = 288, kHash = 512;
+    using Col = uint8_t;
+};
+template <> struct MpkCaps<3> {
+    static constexpr int kSlots = 224, kRows = 160, kEnt = 384, kHash = 512;
+    using Col = uint8_t;
+};
+template <> struct MpkCaps<4> {
+    static constexpr int kSlots = 288, kRows = 224, kEnt = 512, kHash = 1024;
+    using Col = uint16_t;
+};
+
+// Per-block layout at the capacities of the hop count it was built for
+// (views into the workspace, sized for the largest).
 struct MpkDev {
-    int32_t *meta;      // [4 nb]: s0, s1, s2, local entries
-    int32_t *node;      // [nb kMpkSlots]: node of each slot
-    uint16_t *rowoff;   // [nb (kMpk01 + 1)]: local CSR row starts of the slots of R0 + R1
-    uint8_t *lcol;      // [nb kMpkEnt]: slot of each entry's neighbour
-    void *lval;         // [nb kMpkEnt] of the graph's value type: entry weights
-    void *ldeg;         // [nb kMpk01] of that type: degrees of the rows of R0 + R1
+    int32_t *meta;      // [nb kMpkMeta]
+    int32_t *node;      // [nb kSlots]: node of each slot
+    uint16_t *rowoff;   // [nb (kRows + 1)]: local CSR row starts
+    void *lcol;         // [nb kEnt] of Col: slot of each entry's neighbour
+    void *lval;         // [nb kEnt] of the graph's value type: entry weights
+    void *ldeg;         // [nb kRows] of that type: degrees of the local rows
 };
 
 __device__ __forceinline__ int wave_incl_sum(int x) {
@@ -762,38 +791,43 @@ __device__ __forceinline__ int wave_incl_sum(int x) {
     return x;
 }
 
-// Node -> slot map of one block in LDS: open addressing, linear probing.
-constexpr int kMpkHash = 512;     // table entries (at least three per slot)
 constexpr int kMpkRegCols = 8;    // row entries the layout pass holds in registers; longer rows are re-read
 
-__device__ __forceinline__ int mpk_hash(int32_t q) { return (int)(((uint32_t)q * 0x9E3779B1u) >> 23); }
+__device__ __forceinline__ int mpk_hash(int32_t q, int bits) {
+    return (int)(((uint32_t)q * 0x9E3779B1u) >> (32 - bits));
+}
 
-// Inserts q.  New: takes the next slot from *next (its node into snode when
-// the slot is within capacity) and returns 1; present: 0; table full: -1.
-__device__ __forceinline__ int hs_insert(int32_t *keys, int32_t *vals, int32_t *next, int32_t *snode, int32_t q) {
-    int h = mpk_hash(q);
-    for (int probe = 0; probe < kMpkHash; ++probe) {
+// Node -> slot map of one block in LDS (open addressing, linear probing).
+// Inserts q: new -> takes the next slot from *next (its node into snode when
+// within nslots) and returns 1; present -> 0; table full -> -1.
+template <int HASH>
+__device__ __forceinline__ int hs_insert(int32_t *keys, int32_t *vals, int32_t *next, int32_t *snode, int nslots,
+                                         int32_t q) {
+    constexpr int bits = HASH == 1024 ? 10 : 9;
+    int h = mpk_hash(q, bits);
+    for (int probe = 0; probe < HASH; ++probe) {
         const int32_t old = atomicCAS(&keys[h], -1, q);
         if (old == -1) {
             const int32_t slot = atomicAdd(next, 1);
             vals[h] = slot;
-            if (slot < kMpkSlots) snode[slot] = q;
+            if (slot < nslots) snode[slot] = q;
             return 1;
         }
         if (old == q) return 0;
-        h = (h + 1) & (kMpkHash - 1);
+        h = (h + 1) & (HASH - 1);
     }
     return -1;
 }
 
-// Slot of q, -1 if absent.
+template <int HASH>
 __device__ __forceinline__ int32_t hs_find(const int32_t *keys, const int32_t *vals, int32_t q) {
-    int h = mpk_hash(q);
-    for (int probe = 0; probe < kMpkHash; ++probe) {
+    constexpr int bits = HASH == 1024 ? 10 : 9;
+    int h = mpk_hash(q, bits);
+    for (int probe = 0; probe < HASH; ++probe) {
         const int32_t kk = keys[h];
         if (kk == q) return vals[h];
         if (kk == -1) return -1;
-        h = (h + 1) & (kMpkHash - 1);
+        h = (h + 1) & (HASH - 1);
     }
     return -1;
 }
@@ -814,19 +848,22 @@ __global__ void k_mpk_check(int64_t n, const int32_t *__restrict__ order, int32_
     if (v < 0 || v >= n || atomicExch(&seen[v], 1) != 0) atomicOr(flag, 1);
 }
 
-// Layout of one block per 64-lane workgroup.  A block that does not fit (a
-// halo or its local CSR over the capacities, an order entry outside [0, n))
-// gets s0 = 0 and sets flag bit 2; the caller then runs the single sweeps
-// instead.  R1 and R2 slots are numbered in discovery order; which slot a
-// node takes changes where its row sits in the LDS, not any value.
-template <typename TW>
+// Layout of one block for H hops, one 64-lane workgroup per block.  A block
+// that does not fit (a layer, the rows or the local CSR over the capacities,
+// an order entry outside [0, n)) gets zero sizes and sets flag bit 2; the
+// caller then lays out for fewer hops, or runs the single sweeps.  Slots of
+// L1..LH are numbered in discovery order: which slot a node takes changes
+// where its row sits in the LDS, not any value.
+template <int H, typename TW>
 __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__restrict__ order,
                                                   const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col, const TW *__restrict__ val,
                                                   const TW *__restrict__ deg, MpkDev L, int32_t *flag) {
-    __shared__ int32_t keys[kMpkHash];
-    __shared__ int32_t vals[kMpkHash];
-    __shared__ int32_t snode[kMpkSlots];
+    using C = MpkCaps<H>;
+    using Col = typename C::Col;
+    __shared__ int32_t keys[C::kHash];
+    __shared__ int32_t vals[C::kHash];
+    __shared__ int32_t snode[C::kSlots];
     __shared__ int32_t next;
     __shared__ int32_t full;
     const int lane = threadIdx.x;
@@ -834,7 +871,7 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     const int64_t base = b * kMpkRows;
     const int s0 = (int)(n - base < kMpkRows ? n - base : kMpkRows);
 #pragma unroll
-    for (int i = 0; i < kMpkHash / 64; ++i) keys[i * 64 + lane] = -1;
+    for (int i = 0; i < C::kHash / 64; ++i) keys[i * 64 + lane] = -1;
     if (lane == 0) {
         next = s0;
         full = 0;
@@ -842,196 +879,225 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     const int32_t p = lane < s0 ? order[base + lane] : -1;
     const bool bad = lane < s0 && (p < 0 || p >= n);
     bool over = __ballot(bad) != 0ull;
-    int32_t j0 = 0, len = 0;
-    int32_t cc[kMpkRegCols];
-    if (lane < s0 && !bad) {
-        j0 = rowptr[p];
-        len = rowptr[p + 1] - j0;
-    }
-    over = over || __ballot(len > kMpkEnt) != 0ull;
-    if (!over) row_cols(col, j0, len, cc);
     __syncthreads();
-    // R0: slot = position in the order
+    // L0: slot = position in the order
     if (!over && lane < s0) {
         snode[lane] = p;
-        int h = mpk_hash(p);
-        for (int probe = 0; probe < kMpkHash; ++probe) {
+        int h = mpk_hash(p, C::kHash == 1024 ? 10 : 9);
+        for (int probe = 0; probe < C::kHash; ++probe) {
             const int32_t old = atomicCAS(&keys[h], -1, p);
             if (old == -1) {
                 vals[h] = lane;
                 break;
             }
             if (old == p) break;        // a repeated order entry: refused by the order check
-            h = (h + 1) & (kMpkHash - 1);
+            h = (h + 1) & (C::kHash - 1);
         }
     }
     __syncthreads();
-    // R1: neighbours of R0 not yet in the map
-    if (!over) {
+    // L(h+1): neighbours of the rows of Lh not yet in the map
+    int ends[H + 1];
+    ends[0] = s0;
+    int lo = 0;
 #pragma unroll
-        for (int t = 0; t < kMpkRegCols; ++t)
-            if (t < len && hs_insert(keys, vals, &next, snode, cc[t]) < 0) full = 1;
-        for (int t = kMpkRegCols; t < len; ++t)
-            if (hs_insert(keys, vals, &next, snode, col[j0 + t]) < 0) full = 1;
-    }
-    __syncthreads();
-    const int s01 = next;
-    over = over || full != 0 || s01 > kMpk01;
-    // R2: neighbours of R1 not yet in the map (R1 slots lane and 64 + lane)
-    int32_t j1[2] = {0, 0}, len1[2] = {0, 0};
-    int32_t c1[2][kMpkRegCols];
-    if (!over) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int r = s0 + h * 64 + lane;
-            if (r < s01) {
+    for (int h = 0; h < H; ++h) {
+        if (!over)
+            for (int r = lo + lane; r < ends[h]; r += 64) {
                 const int32_t q = snode[r];
-                j1[h] = rowptr[q];
-                len1[h] = rowptr[q + 1] - j1[h];
+                const int32_t j0 = rowptr[q], len = rowptr[q + 1] - j0;
+                if (len > C::kEnt) {
+                    full = 1;
+                    continue;
+                }
+                int32_t cc[kMpkRegCols];
+                row_cols(col, j0, len, cc);
+#pragma unroll
+                for (int t = 0; t < kMpkRegCols; ++t)
+                    if (t < len && hs_insert<C::kHash>(keys, vals, &next, snode, C::kSlots, cc[t]) < 0) full = 1;
+                for (int t = kMpkRegCols; t < len; ++t)
+                    if (hs_insert<C::kHash>(keys, vals, &next, snode, C::kSlots, col[j0 + t]) < 0) full = 1;
             }
-        }
-        over = __ballot(len1[0] > kMpkEnt || len1[1] > kMpkEnt) != 0ull;
+        __syncthreads();
+        ends[h + 1] = next;
+        over = over || full != 0 || ends[h + 1] > C::kSlots;
+        lo = ends[h];
+        __syncthreads();
     }
-    if (!over) {
+    const int R = ends[H - 1], S = ends[H];
+    over = over || R > C::kRows;
+    // local CSR of rows [0, R): row q 64 + lane, q < Q; the loads of all of a lane's rows go out together
+    constexpr int Q = (C::kRows + 63) / 64;
+    int32_t rq[Q], j0q[Q], lenq[Q], startq[Q];
+    int nent = 0;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) row_cols(col, j1[h], len1[h], c1[h]);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-#pragma unroll
-            for (int t = 0; t < kMpkRegCols; ++t)
-                if (t < len1[h] && hs_insert(keys, vals, &next, snode, c1[h][t]) < 0) full = 1;
-            for (int t = kMpkRegCols; t < len1[h]; ++t)
-                if (hs_insert(keys, vals, &next, snode, col[j1[h] + t]) < 0) full = 1;
-        }
+    for (int q = 0; q < Q; ++q) {
+        const int r = q * 64 + lane;
+        rq[q] = (!over && r < R) ? snode[r] : -1;
+        j0q[q] = rq[q] >= 0 ? rowptr[rq[q]] : 0;
+        lenq[q] = rq[q] >= 0 ? rowptr[rq[q] + 1] - j0q[q] : 0;
     }
-    __syncthreads();
-    const int S = next;
-    over = over || full != 0 || S > kMpkSlots;
-    // local CSR of the rows of R0 and R1: slot lane (an R0 row, or R1 when the block is short) and slot 64 + lane
-    int32_t ja = 0, la = 0, jb = 0, lb = 0, na = 0, nb2 = 0;
-    if (!over) {
-        if (lane < s0) {
-            na = p;
-            ja = j0;
-            la = len;
-        } else if (lane < s01) {
-            na = snode[lane];
-            ja = rowptr[na];
-            la = rowptr[na + 1] - ja;
-        }
-        if (64 + lane < s01) {
-            nb2 = snode[64 + lane];
-            jb = rowptr[nb2];
-            lb = rowptr[nb2 + 1] - jb;
-        }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int incl = wave_incl_sum(lenq[q]);
+        startq[q] = nent + incl - lenq[q];
+        nent += __shfl(incl, 63, 64);
     }
-    const int ia = wave_incl_sum(la);
-    const int tot_a = __shfl(ia, 63, 64);
-    const int ib = tot_a + wave_incl_sum(lb);
-    const int nent = __shfl(ib, 63, 64);
-    over = over || nent > kMpkEnt;
+    over = over || nent > C::kEnt;
     if (over) {
-        if (lane == 0) {
-            L.meta[4 * b] = 0;
-            L.meta[4 * b + 1] = L.meta[4 * b + 2] = L.meta[4 * b + 3] = 0;
-            atomicOr(flag, 2);
-        }
+        if (lane < kMpkMeta) L.meta[kMpkMeta * b + lane] = 0;
+        if (lane == 0) atomicOr(flag, 2);
         return;
     }
-    uint16_t *ro = L.rowoff + b * (kMpk01 + 1);
-    uint8_t *lc = L.lcol + b * kMpkEnt;
-    TW *lv = (TW *)L.lval + b * kMpkEnt;
-    TW *ld = (TW *)L.ldeg + b * kMpk01;
-    const int32_t er[2] = {lane, 64 + lane}, en[2] = {na, nb2}, ej[2] = {ja, jb}, el[2] = {la, lb},
-                  es[2] = {ia - la, ib - lb};
+    uint16_t *ro = L.rowoff + b * (C::kRows + 1);
+    Col *lc = (Col *)L.lcol + b * C::kEnt;
+    TW *lv = (TW *)L.lval + b * C::kEnt;
+    TW *ld = (TW *)L.ldeg + b * C::kRows;
+    int32_t cr[Q][kMpkRegCols];
+    TW vr[Q][kMpkRegCols];
+    TW dq[Q];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (er[h] >= s01) continue;
-        ro[er[h]] = (uint16_t)es[h];
-        ld[er[h]] = deg[en[h]];
-        int32_t cr[kMpkRegCols];
-        row_cols(col, ej[h], el[h], cr);
-        TW vr[kMpkRegCols];
+    for (int q = 0; q < Q; ++q) {
+        row_cols(col, j0q[q], lenq[q], cr[q]);
 #pragma unroll
-        for (int t = 0; t < kMpkRegCols; ++t) vr[t] = t < el[h] ? val[ej[h] + t] : TW(0);
+        for (int t = 0; t < kMpkRegCols; ++t) vr[q][t] = t < lenq[q] ? val[j0q[q] + t] : TW(0);
+        dq[q] = rq[q] >= 0 ? deg[rq[q]] : TW(0);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (rq[q] < 0) continue;
+        const int r = q * 64 + lane, at = startq[q], len = lenq[q], j0 = j0q[q];
+        ro[r] = (uint16_t)at;
+        ld[r] = dq[q];
 #pragma unroll
         for (int t = 0; t < kMpkRegCols; ++t)
-            if (t < el[h]) {
-                lc[es[h] + t] = (uint8_t)hs_find(keys, vals, cr[t]);
-                lv[es[h] + t] = vr[t];
+            if (t < len) {
+                lc[at + t] = (Col)hs_find<C::kHash>(keys, vals, cr[q][t]);
+                lv[at + t] = vr[q][t];
             }
-        for (int t = kMpkRegCols; t < el[h]; ++t) {
-            lc[es[h] + t] = (uint8_t)hs_find(keys, vals, col[ej[h] + t]);
-            lv[es[h] + t] = val[ej[h] + t];
+        for (int t = kMpkRegCols; t < len; ++t) {
+            lc[at + t] = (Col)hs_find<C::kHash>(keys, vals, col[j0 + t]);
+            lv[at + t] = val[j0 + t];
         }
     }
-    if (lane == 0) ro[s01] = (uint16_t)nent;
-    int32_t *nd = L.node + b * kMpkSlots;
+    if (lane == 0) ro[R] = (uint16_t)nent;
+    int32_t *nd = L.node + b * C::kSlots;
     for (int i = lane; i < S; i += 64) nd[i] = snode[i];
-    if (lane == 0) {
-        L.meta[4 * b] = s0;
-        L.meta[4 * b + 1] = s01 - s0;
-        L.meta[4 * b + 2] = S - s01;
-        L.meta[4 * b + 3] = nent;
-    }
+#pragma unroll
+    for (int h = 0; h <= H; ++h)
+        if (lane == h) L.meta[kMpkMeta * b + h] = ends[h];
+    if (lane == kMpkMeta - 1) L.meta[kMpkMeta * b + lane] = nent;
 }
 
-// Two sweeps of one block (see above).  k columns of TX, k * sizeof(TX) <=
-// kMpkRowBytes, VPL columns per lane; TIN the source block's type (the raw
-// FP64 block when CENTER: centred on load, as the single sweep does).  The
-// LDS holds X of every slot; X_t+1 of R0 and R1 is formed in registers and
-// written over it after a barrier (no row of R0 reads R2), so a workgroup
-// needs about 26 KB and six fit a CU.  Two dependent rounds of global loads:
-// the block's sizes and slot nodes, then X of the slots and the local CSR.
-constexpr int kMpkPasses = 6;     // row passes over the slots at the narrowest lanes-per-row (32 rows a pass)
-template <typename TIN, typename TX, typename TW, typename TA, int VPL, bool CENTER>
-__global__ __launch_bounds__(256) void k_sweep2(int32_t k, MpkDev L, const TIN *__restrict__ x,
-                                                const double *__restrict__ mean, TX *__restrict__ y, TA keep,
-                                                TA omega) {
-    __shared__ __align__(16) unsigned char xs_raw[kMpkSlots * kMpkRowBytes];
-    __shared__ int32_t nodes[kMpkSlots];
-    __shared__ TW lval[kMpkEnt];
-    __shared__ TW ldeg[kMpk01];
-    __shared__ uint16_t rowoff[kMpk01 + 1];
-    __shared__ uint8_t lcol[kMpkEnt];
-    TX *xs = reinterpret_cast<TX *>(xs_raw);
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+// LDS of one pass workgroup: X of every slot for KC columns, nodes, local CSR.
+template <int H, int KC, typename TX, typename TW>
+constexpr int mpk_pass_lds() {
+    using C = MpkCaps<H>;
+    return C::kSlots * KC * (int)sizeof(TX) + C::kSlots * 4 + C::kEnt * ((int)sizeof(TW) + (int)sizeof(typename C::Col)) +
+           C::kRows * (int)sizeof(TW) + (C::kRows + 1) * 2;
+}
+template <int H, int KC, typename TX, typename TW>
+constexpr int mpk_pass_waves() {
+    // workgroups of 4 waves a CU's 160 KB of LDS holds = waves per SIMD (registers are held to it)
+    return 163840 / mpk_pass_lds<H, KC, TX, TW>() > 8 ? 8 : 163840 / mpk_pass_lds<H, KC, TX, TW>();
+}
+
+// m sweeps of KC columns of one block (see above), 1 <= m <= H: workgroup w
+// takes block w / (k / KC) and column group w % (k / KC), k the block's
+// columns (its row stride).  VPL columns per lane; TIN the source block's
+// type (the raw FP64 block when CENTER: centred on load, as the single sweep
+// does).  The LDS holds X of every slot; each sweep's new rows are formed in
+// registers and written over the old ones after a barrier (no row of a sweep
+// reads a slot outside the next layer), so one X block's worth of LDS is
+// enough.  Narrower column groups take less LDS, so more workgroups share a
+// CU and hide the gathers' latency; the groups of a block are adjacent
+// workgroups of one XCD, so its layout is fetched once into that XCD's L2.
+// Two dependent rounds of global loads: the block's sizes and slot nodes,
+// then X of the slots and the local CSR.
+template <int H, int KC, typename TIN, typename TX, typename TW, typename TA, int VPL, bool CENTER>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mpk_pass_waves<H, KC, TX, TW>()))) void
+k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const double *__restrict__ mean,
+             TX *__restrict__ y, TA keep, TA omega) {
+    using C = MpkCaps<H>;
+    using Col = typename C::Col;
+    constexpr int LPR = KC / VPL;              // lanes per row
+    constexpr int RPP = 256 / LPR;             // rows a pass
+    constexpr int kSlotPasses = (C::kSlots + RPP - 1) / RPP;
+    constexpr int kRowPasses = (C::kRows + RPP - 1) / RPP;
+    constexpr int kStage = kSlotPasses < 4 ? kSlotPasses : 4;
+    __shared__ __align__(16) TX xs[C::kSlots * KC];
+    __shared__ int32_t nodes[C::kSlots];
+    __shared__ TW lval[C::kEnt];
+    __shared__ TW ldeg[C::kRows];
+    __shared__ uint16_t rowoff[C::kRows + 1];
+    __shared__ Col lcol[C::kEnt];
+    const int groups = k / KC;
+    const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t b = w / groups;
+    const int g0 = (int)(w - b * groups) * KC;
     const int t = threadIdx.x;
-    const int32_t *mp = L.meta + 4 * b;
-    const int s0 = mp[0], s1 = mp[1], s2 = mp[2], ne = mp[3];
-    const int s01 = s0 + s1, S = s01 + s2;
+    const int32_t *mp = L.meta + kMpkMeta * b;
+    int ends[H + 1];
+#pragma unroll
+    for (int h = 0; h <= H; ++h) ends[h] = mp[h];
+    const int ne = mp[kMpkMeta - 1];
+    int S = ends[H], R = ends[H - 1];
+#pragma unroll
+    for (int h = 1; h <= H; ++h)
+        if (h == m) {
+            S = ends[h];
+            R = ends[h - 1];
+        }
+    const int s0 = ends[0];
     // round 1: slot nodes (read to capacity, used to S)
-    if (t < kMpkSlots) nodes[t] = L.node[b * kMpkSlots + t];
+    for (int i = t; i < C::kSlots; i += 256) nodes[i] = L.node[b * C::kSlots + i];
     // round 2 issued early: the local CSR into registers
-    constexpr int kEntPer = (kMpkEnt + 255) / 256;
-    uint8_t ec[kEntPer];
+    constexpr int kEntPer = (C::kEnt + 255) / 256;
+    Col ec[kEntPer];
     TW ev[kEntPer];
 #pragma unroll
     for (int j = 0; j < kEntPer; ++j) {
         const int i = t + 256 * j;
         if (i < ne) {
-            ec[j] = L.lcol[b * kMpkEnt + i];
-            ev[j] = ((const TW *)L.lval)[b * kMpkEnt + i];
+            ec[j] = ((const Col *)L.lcol)[b * C::kEnt + i];
+            ev[j] = ((const TW *)L.lval)[b * C::kEnt + i];
         }
     }
-    uint16_t ro = 0;
-    TW dg = TW(0);
-    if (t <= s01) ro = L.rowoff[b * (kMpk01 + 1) + t];
-    if (t < s01) dg = ((const TW *)L.ldeg)[b * kMpk01 + t];
-    const int lpr = k / VPL;
-    const int rpp = 256 / lpr;                      // rows a pass; 256 % lpr lanes idle
-    const int ri0 = t / lpr, c = (t - ri0 * lpr) * VPL;
-    const bool lane_on = ri0 < rpp;
+    constexpr int kRowPer = (C::kRows + 1 + 255) / 256;
+    uint16_t ro[kRowPer];
+    TW dg[kRowPer];
+#pragma unroll
+    for (int j = 0; j < kRowPer; ++j) {
+        const int i = t + 256 * j;
+        if (i <= R) ro[j] = L.rowoff[b * (C::kRows + 1) + i];
+        if (i < R) dg[j] = ((const TW *)L.ldeg)[b * C::kRows + i];
+    }
+    const int ri0 = t / LPR, c = (t % LPR) * VPL;
+    const int rend = ri0 < RPP ? 0x7fffffff : 0;   // 256 % LPR lanes idle: no rows for them
     double mo[VPL];
 #pragma unroll
-    for (int i = 0; i < VPL; ++i) mo[i] = (CENTER && lane_on) ? mean[c + i] : 0.0;
+    for (int i = 0; i < VPL; ++i) mo[i] = CENTER ? mean[g0 + c + i] : 0.0;
     __syncthreads();
-    // X_t of every slot: all loads first, then the LDS stores
-    TA v[kMpkPasses][VPL];
+    // X_t of slots [0, S): loads of kStage passes, then their LDS stores
 #pragma unroll
-    for (int j = 0; j < kMpkPasses; ++j) {
-        const int r = ri0 + j * rpp;
-        if (lane_on && r < S) load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)nodes[r] * k + c, mo, v[j]);
+    for (int p0 = 0; p0 < kSlotPasses; p0 += kStage) {
+        if (p0 * RPP >= S) break;
+        TA v[kStage][VPL];
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) {
+            const int r = ri0 + (p0 + j) * RPP;
+            if (p0 + j < kSlotPasses && r < S && r < rend)
+                load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)nodes[r] * k + g0 + c, mo, v[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < kStage; ++j) {
+            const int r = ri0 + (p0 + j) * RPP;
+            if (p0 + j < kSlotPasses && r < S && r < rend) {
+                Vec<TX, VPL> st;
+#pragma unroll
+                for (int i = 0; i < VPL; ++i) st.v[i] = cvt<TX>(v[j][i]);
+                *reinterpret_cast<Vec<TX, VPL> *>(xs + r * KC + c) = st;
+            }
+        }
     }
 #pragma unroll
     for (int j = 0; j < kEntPer; ++j) {
@@ -1041,17 +1107,11 @@ __global__ __launch_bounds__(256) void k_sweep2(int32_t k, MpkDev L, const TIN *
             lval[i] = ev[j];
         }
     }
-    if (t <= s01) rowoff[t] = ro;
-    if (t < s01) ldeg[t] = dg;
 #pragma unroll
-    for (int j = 0; j < kMpkPasses; ++j) {
-        const int r = ri0 + j * rpp;
-        if (lane_on && r < S) {
-            Vec<TX, VPL> st;
-#pragma unroll
-            for (int i = 0; i < VPL; ++i) st.v[i] = cvt<TX>(v[j][i]);
-            *reinterpret_cast<Vec<TX, VPL> *>(xs + r * k + c) = st;
-        }
+    for (int j = 0; j < kRowPer; ++j) {
+        const int i = t + 256 * j;
+        if (i <= R) rowoff[i] = ro[j];
+        if (i < R) ldeg[i] = dg[j];
     }
     __syncthreads();
     // one sweep of row r from the LDS
@@ -1060,12 +1120,12 @@ __global__ __launch_bounds__(256) void k_sweep2(int32_t k, MpkDev L, const TIN *
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
         for (int e = rowoff[r]; e < rowoff[r + 1]; ++e) {
-            const TA w = cvt<TA>(lval[e]);
-            const Vec<TX, VPL> xv = *reinterpret_cast<const Vec<TX, VPL> *>(xs + lcol[e] * k + c);
+            const TA wv = cvt<TA>(lval[e]);
+            const Vec<TX, VPL> xv = *reinterpret_cast<const Vec<TX, VPL> *>(xs + (int)lcol[e] * KC + c);
 #pragma unroll
-            for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], w, cvt<TA>(xv.v[i]));
+            for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], wv, cvt<TA>(xv.v[i]));
         }
-        const Vec<TX, VPL> sv = *reinterpret_cast<const Vec<TX, VPL> *>(xs + r * k + c);
+        const Vec<TX, VPL> sv = *reinterpret_cast<const Vec<TX, VPL> *>(xs + r * KC + c);
         const TA d = cvt<TA>(ldeg[r]);
         Vec<TX, VPL> out;
 #pragma unroll
@@ -1077,24 +1137,29 @@ __global__ __launch_bounds__(256) void k_sweep2(int32_t k, MpkDev L, const TIN *
         }
         return out;
     };
-    // X_t+1 of R0 and R1 into registers, then over X_t in the LDS
-    constexpr int kP01 = (kMpk01 + 31) / 32;
-    Vec<TX, VPL> x1[kP01];
+    // sweeps 1..m-1: rows of L0..L(m-1-j) into registers, then over X in the LDS
+    for (int j = 0; j + 1 < m; ++j) {
+        int nrows = ends[0];
 #pragma unroll
-    for (int j = 0; j < kP01; ++j) {
-        const int r = ri0 + j * rpp;
-        if (lane_on && r < s01) x1[j] = row_sweep(r);
-    }
-    __syncthreads();
+        for (int h = 0; h < H; ++h)
+            if (h == m - 1 - j) nrows = ends[h];
+        Vec<TX, VPL> xr[kRowPasses];
 #pragma unroll
-    for (int j = 0; j < kP01; ++j) {
-        const int r = ri0 + j * rpp;
-        if (lane_on && r < s01) *reinterpret_cast<Vec<TX, VPL> *>(xs + r * k + c) = x1[j];
+        for (int q = 0; q < kRowPasses; ++q) {
+            const int r = ri0 + q * RPP;
+            if (r < nrows && r < rend) xr[q] = row_sweep(r);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kRowPasses; ++q) {
+            const int r = ri0 + q * RPP;
+            if (r < nrows && r < rend) *reinterpret_cast<Vec<TX, VPL> *>(xs + r * KC + c) = xr[q];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    // X_t+2 of R0 (its neighbours all lie in R0 and R1)
-    for (int r = ri0; lane_on && r < s0; r += rpp)
-        *reinterpret_cast<Vec<TX, VPL> *>(y + (int64_t)nodes[r] * k + c) = row_sweep(r);
+    // the last sweep: L0 (its neighbours all lie in L0 and L1)
+    for (int r = ri0; r < s0 && r < rend; r += RPP)
+        *reinterpret_cast<Vec<TX, VPL> *>(y + (int64_t)nodes[r] * k + g0 + c) = row_sweep(r);
 }
 
 }  // namespace
@@ -1256,7 +1321,7 @@ void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const dou
     }
 }
 
-// Two-sweeps-per-pass smoothing in a caller's row order (see k_sweep2).
+// Several sweeps per pass in a caller's row order (see k_sweep_pass).
 struct MpkPlan {
     MpkDev dev;
     int32_t *seen, *flag;
@@ -1264,15 +1329,17 @@ struct MpkPlan {
 
 int64_t mpk_blocks(int64_t n) { return (n + kMpkRows - 1) / kMpkRows; }
 
+// Sized for the largest capacities (four hops), so that any hop count fits.
 MpkPlan plan_mpk(Carver &c, int64_t n, size_t sw) {
+    using C = MpkCaps<kMpkMaxHops>;
     const int64_t nb = mpk_blocks(n);
     MpkPlan p;
-    p.dev.meta = c.take<int32_t>(4 * nb);
-    p.dev.node = c.take<int32_t>(nb * kMpkSlots);
-    p.dev.rowoff = c.take<uint16_t>(nb * (kMpk01 + 1));
-    p.dev.lcol = c.take<uint8_t>(nb * kMpkEnt);
-    p.dev.lval = c.take<char>(nb * kMpkEnt * sw);
-    p.dev.ldeg = c.take<char>(nb * kMpk01 * sw);
+    p.dev.meta = c.take<int32_t>(kMpkMeta * nb);
+    p.dev.node = c.take<int32_t>(nb * C::kSlots);
+    p.dev.rowoff = c.take<uint16_t>(nb * (C::kRows + 1));
+    p.dev.lcol = c.take<char>(nb * C::kEnt * sizeof(C::Col));
+    p.dev.lval = c.take<char>(nb * C::kEnt * sw);
+    p.dev.ldeg = c.take<char>(nb * C::kRows * sw);
     p.seen = c.take<int32_t>(n + 1);
     p.flag = c.take<int32_t>(1);
     return p;
@@ -1287,39 +1354,102 @@ size_t smooth_ordered_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage) {
 
 namespace {
 
-template <typename TX, bool CENTER>
-void launch_sweep2(int32_t k, const MpkPlan &m, int64_t nb, const void *x, const double *mean, TX *y, double omega,
-                   hipStream_t s) {
+// Columns a pass workgroup takes: the whole row (up to 128 bytes).
+// SFG_PASS_COLS = 8 (FP64) or 16 (FP32) splits 128-byte rows into two
+// 64-byte column groups instead, for tuning (measured on the 200^3 mesh's
+// tree: no faster at 3 hops, slower at 2).
+template <typename TX>
+int pass_cols(int32_t k) {
+    const int narrow = 64 / (int)sizeof(TX);
+    const int forced = env_int("SFG_PASS_COLS", 0);
+    if (forced == narrow && k % narrow == 0) return narrow;
+    return k;
+}
+
+template <int H, int KC, typename TX, bool CENTER>
+void launch_pass_kc(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TX *y,
+                    double omega, hipStream_t s) {
     using TIN = typename std::conditional<CENTER, double, TX>::type;
-    hipLaunchKernelGGL((k_sweep2<TIN, TX, TX, TX, 4, CENTER>), dim3((uint32_t)nb), dim3(256), 0, s, k, m.dev,
-                       (const TIN *)x, mean, y, (TX)(1.0 - omega), (TX)omega);
+    const int64_t items = nb * (k / KC);
+    SFG_REQUIRE(items <= 0x7fffffff, SFG_EUNSUPPORTED, "smooth_ordered: too many blocks");
+    hipLaunchKernelGGL((k_sweep_pass<H, KC, TIN, TX, TX, TX, 4, CENTER>), dim3((uint32_t)items), dim3(256), 0, s, k,
+                       m, mp.dev, (const TIN *)x, mean, y, (TX)(1.0 - omega), (TX)omega);
     SFG_LAUNCH_CHECK();
 }
 
-template <typename TX>
-void run_smooth_pairs(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const double *x0, void *xout,
-                      const SmoothPlan &p, const MpkPlan &m, int64_t nb, hipStream_t s) {
-    launch_column_means<double>(x0, H->n, k, p.partial, p.mean, s);
-    TX *b0 = (TX *)p.buf0, *b1 = (TX *)p.buf1;
-    const int32_t pairs = sweeps / 2;
-    const TX *src = nullptr;
-    for (int32_t q = 0; q < pairs; ++q) {
-        const bool last = (q == pairs - 1) && sweeps % 2 == 0;
-        TX *dst = last ? (TX *)xout : (q % 2 == 0 ? b0 : b1);
-        if (q == 0)
-            launch_sweep2<TX, true>(k, m, nb, x0, p.mean, dst, omega, s);
-        else
-            launch_sweep2<TX, false>(k, m, nb, src, nullptr, dst, omega, s);
-        src = dst;
+template <int H, typename TX, bool CENTER>
+void launch_pass(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TX *y,
+                 double omega, hipStream_t s) {
+    constexpr int wide = 128 / (int)sizeof(TX);
+    switch (pass_cols<TX>(k)) {
+        case 4: launch_pass_kc<H, 4, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        case 8: launch_pass_kc<H, 8, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        case 12: launch_pass_kc<H, 12, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        case 16: launch_pass_kc<H, 16, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        default: break;
     }
-    if (sweeps % 2 == 1)    // the odd last sweep: a single sweep in node order
-        launch_sweep<TX, TX, TX, TX, TX, false>(H, k, src, nullptr, (TX *)xout, omega, s);
+    if constexpr (wide == 32) {
+        switch (pass_cols<TX>(k)) {
+            case 20: launch_pass_kc<H, 20, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            case 24: launch_pass_kc<H, 24, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            case 28: launch_pass_kc<H, 28, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            case 32: launch_pass_kc<H, 32, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            default: break;
+        }
+    }
+    fail(SFG_EUNSUPPORTED, "smooth_ordered: no pass kernel for this width");
+}
+
+// Passes of H sweeps, the last one shorter when H does not divide the count.
+template <int H, typename TX>
+void run_smooth_passes(const sfg_csr *H_, int32_t k, int32_t sweeps, double omega, const double *x0, void *xout,
+                       const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s) {
+    launch_column_means<double>(x0, H_->n, k, p.partial, p.mean, s);
+    TX *b0 = (TX *)p.buf0, *b1 = (TX *)p.buf1;
+    const TX *src = nullptr;
+    for (int32_t done = 0, q = 0; done < sweeps; ++q) {
+        const int32_t m = sweeps - done < H ? sweeps - done : H;
+        TX *dst = done + m == sweeps ? (TX *)xout : (q % 2 == 0 ? b0 : b1);
+        if (q == 0)
+            launch_pass<H, TX, true>(k, m, mp, nb, x0, p.mean, dst, omega, s);
+        else
+            launch_pass<H, TX, false>(k, m, mp, nb, src, nullptr, dst, omega, s);
+        src = dst;
+        done += m;
+    }
+}
+
+template <int H>
+void build_layout(const sfg_csr *G, const int32_t *order, const MpkPlan &mp, int64_t nb, hipStream_t s) {
+    if (G->vt == SFG_F64)
+        hipLaunchKernelGGL((k_mpk_build<H, double>), dim3((uint32_t)nb), dim3(64), 0, s, G->n, order, G->rowptr,
+                           G->col, (const double *)G->val, (const double *)G->deg, mp.dev, mp.flag);
+    else
+        hipLaunchKernelGGL((k_mpk_build<H, float>), dim3((uint32_t)nb), dim3(64), 0, s, G->n, order, G->rowptr,
+                           G->col, (const float *)G->val, (const float *)G->deg, mp.dev, mp.flag);
+    SFG_LAUNCH_CHECK();
+}
+
+int32_t read_flag(const MpkPlan &mp, hipStream_t s) {
+    int32_t flag = 0;
+    SFG_HIP(hipMemcpyAsync(&flag, mp.flag, sizeof(flag), hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    SFG_REQUIRE(!(flag & 1), SFG_EINVAL, "smooth_ordered: order is not a permutation of the nodes");
+    return flag;
 }
 
 }  // namespace
 
-// Same result as smooth(); see sfg_smooth_ordered in the header.  Returns 1
-// when the sweeps ran two per pass, 0 when the plain path ran.
+// Same result as smooth(); see sfg_smooth_ordered in the header.  Returns the
+// sweeps each pass over X took: 1 when the plain path ran, else 2 to 4.
+// Hops are tried from SFG_SWEEP_HOPS (2, 3 or 4; default 2 in FP64, 3 in
+// FP32) down to 2 until every block's layout fits.  Measured on the 200^3
+// mesh's spanning tree in preorder, 16 vectors, per sweep: FP64 289 us with
+// 2 hops, 293 with 3, 334 with 4 (the deeper passes read X fewer times but
+// keep fewer workgroups a CU, and the gathers' latency then shows); FP32
+// 152-163 us with 3 hops, 177 with 2, 174 with 4.
+int default_hops(sfg_dtype storage) { return storage == SFG_F64 ? 2 : 3; }
+
 int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps, double omega,
                    const double *x0, sfg_dtype storage, int32_t final_f32, void *x, void *ws, size_t ws_bytes,
                    hipStream_t s) {
@@ -1330,43 +1460,52 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
     const int64_t n = H->n;
     Carver c(ws);
     SmoothPlan p = plan_smooth(c, n, k < 1 ? 1 : k, storage);
-    MpkPlan m = plan_mpk(c, n, 8);
+    MpkPlan mp = plan_mpk(c, n, 8);
     // the order must be a permutation of the nodes, whichever path runs
-    fill_i32(m.seen, n, 0, s);
-    fill_i32(m.flag, 1, 0, s);
-    hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, m.seen, m.flag);
+    fill_i32(mp.seen, n, 0, s);
+    fill_i32(mp.flag, 1, 0, s);
+    hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
     SFG_LAUNCH_CHECK();
     const size_t sx = dtype_size(storage);
+    const int want = env_int("SFG_SWEEP_HOPS", default_hops(storage));
     const bool shape_ok = (storage == SFG_F64 || storage == SFG_F32) && H->vt == storage && k >= 1 &&
                           k % 4 == 0 && (size_t)k * sx <= (size_t)kMpkRowBytes && sweeps >= 2 && H->nnz >= 1 &&
-                          H->col && H->val && H->deg && env_int("SFG_SWEEP_PAIRS", 1) != 0;
+                          H->col && H->val && H->deg && want >= 2;
     const int64_t nb = mpk_blocks(n);
+    int hops = 0;
     if (shape_ok) {
-        if (storage == SFG_F64)
-            hipLaunchKernelGGL(k_mpk_build<double>, dim3((uint32_t)nb), dim3(64), 0, s, n, order, H->rowptr, H->col,
-                               (const double *)H->val, (const double *)H->deg, m.dev, m.flag);
-        else
-            hipLaunchKernelGGL(k_mpk_build<float>, dim3((uint32_t)nb), dim3(64), 0, s, n, order, H->rowptr, H->col,
-                               (const float *)H->val, (const float *)H->deg, m.dev, m.flag);
-        SFG_LAUNCH_CHECK();
+        for (int h = want < kMpkMaxHops ? want : kMpkMaxHops; h >= 2 && hops == 0; --h) {
+            if (h == 4) build_layout<4>(H, order, mp, nb, s);
+            else if (h == 3) build_layout<3>(H, order, mp, nb, s);
+            else build_layout<2>(H, order, mp, nb, s);
+            if (read_flag(mp, s) & 2)
+                fill_i32(mp.flag, 1, 0, s);     // a block did not fit: fewer hops
+            else
+                hops = h;
+        }
+    } else {
+        read_flag(mp, s);
     }
-    int32_t flag = 0;
-    SFG_HIP(hipMemcpyAsync(&flag, m.flag, sizeof(flag), hipMemcpyDeviceToHost, s));
-    SFG_HIP(hipStreamSynchronize(s));
-    SFG_REQUIRE(!(flag & 1), SFG_EINVAL, "smooth_ordered: order is not a permutation of the nodes");
-    if (!shape_ok || (flag & 2)) {
+    if (hops == 0) {
         // the workspace starts with the plain smoothing's layout
         smooth(H, k, sweeps, omega, x0, storage, final_f32, x, ws, smooth_workspace_bytes(n, k < 1 ? 1 : k, storage),
                s, -1);
-        return 0;
+        return 1;
     }
     SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_ordered: omega must be in (0, 1]");
     SFG_REQUIRE(x0 && x, SFG_EINVAL, "smooth_ordered: null pointer");
-    if (storage == SFG_F64)
-        run_smooth_pairs<double>(H, k, sweeps, omega, x0, x, p, m, nb, s);
-    else
-        run_smooth_pairs<float>(H, k, sweeps, omega, x0, x, p, m, nb, s);
-    return 1;
+    const bool f64 = storage == SFG_F64;
+    if (hops == 4) {
+        if (f64) run_smooth_passes<4, double>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
+        else run_smooth_passes<4, float>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
+    } else if (hops == 3) {
+        if (f64) run_smooth_passes<3, double>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
+        else run_smooth_passes<3, float>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
+    } else {
+        if (f64) run_smooth_passes<2, double>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
+        else run_smooth_passes<2, float>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
+    }
+    return hops;
 }
 
 // Column means of a block (exact to double-double before one rounding);
@@ -1388,11 +1527,11 @@ size_t column_means_partial_bytes(int64_t n, int32_t k) { return (size_t)colsum_
 
 extern "C" sfg_status sfg_smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps,
                                          double omega, const double *x0, sfg_dtype storage, int32_t final_f32,
-                                         void *x, int32_t *pairs_out, void *ws, size_t ws_bytes, void *stream) {
+                                         void *x, int32_t *per_pass_out, void *ws, size_t ws_bytes, void *stream) {
     return sfg::guard([&] {
         const int used = sfg::smooth_ordered(H, order, k, sweeps, omega, x0, storage, final_f32, x, ws, ws_bytes,
                                              sfg::as_stream(stream));
-        if (pairs_out) *pairs_out = used;
+        if (per_pass_out) *per_pass_out = used;
     });
 }
 

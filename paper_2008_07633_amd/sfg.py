@@ -362,8 +362,9 @@ def sfg_smooth(H: Csr, x0: torch.Tensor, sweeps: int, omega: float = 0.5, storag
 def sfg_smooth_ordered(H: Csr, order: torch.Tensor, x0: torch.Tensor, sweeps: int, omega: float = 0.5,
                        storage=torch.float64, final_f32: bool = False, out: Optional[torch.Tensor] = None,
                        ws: Optional[torch.Tensor] = None, info: Optional[dict] = None) -> torch.Tensor:
-    """sfg_smooth with the rows taken in ``order`` (a permutation, e.g. a spanning tree's preorder), two
-    sweeps per pass where the graph allows; the same bits.  ``info["pairs"]`` tells which path ran."""
+    """sfg_smooth with the rows taken in ``order`` (a permutation, e.g. a spanning tree's preorder), several
+    sweeps per pass over the block where the graph allows; the same bits.  ``info["sweeps_per_pass"]``: 2 to 4,
+    or 1 when the plain path ran."""
     n, k = _block(x0, "x0", _F64, rows=H.n)
     _chk(order, "order", _I32, n)
     st = storage if isinstance(storage, int) else _TORCH_TO_SFG[storage]
@@ -374,12 +375,12 @@ def sfg_smooth_ordered(H: Csr, order: torch.Tensor, x0: torch.Tensor, sweeps: in
     if ws is None:
         ws = _ws(sfg_workspace_bytes(OP_SMOOTH_ORDERED, n, 0, k, st), x0.device)
     hs = H.struct()
-    pairs = ctypes.c_int32(0)
+    per_pass = ctypes.c_int32(0)
     _check(lib().sfg_smooth_ordered(ctypes.byref(hs), _ptr(order), k, sweeps, float(omega), _ptr(x0), st,
-                                    int(bool(final_f32)), _ptr(out), ctypes.byref(pairs), _ptr(ws, "ws", _U8),
+                                    int(bool(final_f32)), _ptr(out), ctypes.byref(per_pass), _ptr(ws, "ws", _U8),
                                     ws.numel(), _stream()))
     if info is not None:
-        info["pairs"] = int(pairs.value)
+        info["sweeps_per_pass"] = int(per_pass.value)
     return out
 
 

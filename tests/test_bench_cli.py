@@ -81,31 +81,31 @@ def test_bench_json_line_on_the_gpu():
     roof = d["roofline"]
     # the FP64 tree sweep of the 8M-node mesh moves 2.3 GB: far beyond the memory-side cache
     assert roof["bound"] == "hbm" and roof["unit"] == "GB/s" and roof["peak"] == 8000.0
-    # two sweeps per launch in the tree's preorder (k_sweep2; one sweep's bytes a launch)
-    assert roof["working_set_bytes"] > 256 << 20 and roof["launches_per_sweep"] == 0.5
+    # several sweeps per launch in the tree's preorder (k_sweep_pass; one sweep's bytes a launch)
+    assert roof["working_set_bytes"] > 256 << 20 and roof["launches_per_sweep"] in (0.25, 0.3333, 0.5)
     assert 0 < roof["frac"] <= 1 and abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
     assert "f32" in d and d["f32"]["selection_agreement_with_f64"] > 0.99
 
 
 @pytest.mark.gpu
 def test_bench_power_grid_lines_name_their_bound():
-    # two sweeps per launch (the default): X in and out of a launch, 292 MB, exceed the memory-side cache, so the
-    # launch is priced against the HBM peak.  One sweep per launch: the pass sweeps 8-column parts whose working
-    # set fits that cache, and its rate is compared with an in-cache copy instead.
+    # several sweeps per launch (the default): X in and out of a launch and the graph, 292 MB, exceed the
+    # memory-side cache, so the launch is priced against the HBM peak.  One sweep per launch: the pass sweeps
+    # 8-column parts whose working set fits that cache, and its rate is compared with an in-cache copy instead.
     import json
 
     import torch
 
     if torch.cuda.device_count() == 0:
         pytest.skip("no GPU")
-    for extra, bound, lps in (([], "hbm", 0.5), (["--single-sweep"], "cache", 2)):
+    for extra, bound, lps in (([], "hbm", (0.25, 0.3333, 0.5)), (["--single-sweep"], "cache", (2,))):
         r = run(["--workload", "powergrid", "--steps", "2", "--warmup", "1", "--no-cpu-baseline", "--sweep-reps",
                  "2"] + extra, timeout=300)
         assert r.returncode == 0, r.stderr[-2000:]
         d = json.loads([ln for ln in r.stdout.splitlines() if ln.strip()][-1])
         roof = d["roofline"]
         assert d["config"]["workload"].startswith("powergrid1000x1000")
-        assert roof["bound"] == bound and roof["launches_per_sweep"] == lps, (extra, roof)
+        assert roof["bound"] == bound and roof["launches_per_sweep"] in lps, (extra, roof)
         if bound == "cache":
             assert roof["working_set_bytes"] <= 256 << 20 and roof["peak"] == d["copy"]["in_cache_copy_gbs"]
         else:

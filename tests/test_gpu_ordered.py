@@ -1,7 +1,8 @@
-"""sfg_smooth_ordered: two sweeps per pass through LDS, in a given row order,
-bit-identical to sfg_smooth (and so to the oracle's smoothing) on every path
-it takes -- the fused pairs, the odd last sweep, and the plain fallback when a
-block's neighbourhood does not fit."""
+"""sfg_smooth_ordered: several sweeps per pass through LDS, in a given row
+order, bit-identical to sfg_smooth (and so to the oracle's smoothing) on every
+path it takes -- passes of 4, 3 or 2 sweeps, a shorter last pass, a layout
+for fewer hops when a block's neighbourhood does not fit, and the plain
+fallback."""
 import numpy as np
 import pytest
 import torch
@@ -41,25 +42,37 @@ GRAPHS = {
 }
 
 
+@pytest.mark.parametrize("hops", ["4", "3", "2"])
 @pytest.mark.parametrize("name", list(GRAPHS))
 @pytest.mark.parametrize("storage", [torch.float64, torch.float32])
-def test_ordered_tree_sweeps_are_bit_identical(S, name, storage):
+@pytest.mark.parametrize("split", [False, True])
+def test_ordered_tree_sweeps_are_bit_identical(S, name, storage, hops, split, monkeypatch):
+    # sweep counts that leave every remainder of a pass (20 = 5 x 4, 7 = 4 + 3 = 2 x 3 + 1, ...); split: two
+    # workgroups per block, one per 64-byte column group, where k allows
+    monkeypatch.setenv("SFG_SWEEP_HOPS", hops)
+    if split:
+        monkeypatch.setenv("SFG_PASS_COLS", "8" if storage == torch.float64 else "16")
     g = GRAPHS[name]()
     u, v, w, tree, order = tree_and_order(S, g)
     H = S.sfg_laplacian_csr(g.n, u, v, w.to(storage), mask=tree)
-    for k, sweeps in ((16, 20), (16, 7), (8, 2), (4, 3), (12, 5)):
+    for k, sweeps in ((16, 20), (16, 7), (8, 2), (4, 3), (12, 5), (16, 6)):
         X0 = dev(W.random_block(g.n, k, 510 + k + sweeps))
         ref = S.sfg_smooth(H, X0, sweeps, 0.5, storage=storage)
         info = {}
         got = S.sfg_smooth_ordered(H, order, X0, sweeps, 0.5, storage=storage, info=info)
         assert torch.equal(got, ref), (name, k, sweeps)
-        # the tree's preorder keeps every block's neighbourhood within the LDS capacity
-        assert info["pairs"] == 1, (name, k, sweeps)
+        # the tree's preorder keeps every block's neighbourhood within the LDS capacity of the hops asked for
+        # (the k-NN tree has nodes of higher degree: at least two hops fit there)
+        if name == "knn_20k":
+            assert 2 <= info["sweeps_per_pass"] <= int(hops), (name, k, sweeps)
+        else:
+            assert info["sweeps_per_pass"] == int(hops), (name, k, sweeps)
 
 
 @pytest.mark.parametrize("storage", [torch.float64, torch.float32])
 def test_ordered_sweeps_on_a_whole_graph(S, storage):
-    # the 3-D mesh itself in its tree's preorder: six neighbours per row, larger neighbourhoods
+    # the 3-D mesh itself in its tree's preorder: six neighbours per row, larger neighbourhoods; whatever
+    # layout fits (or none), the bits are sfg_smooth's
     g = W.mesh3d(12, 11, 10, seed=520, wdist=("lognormal", 0.0, 1.0))
     u, v, w, tree, order = tree_and_order(S, g)
     H = S.sfg_laplacian_csr(g.n, u, v, w.to(storage))
@@ -67,7 +80,36 @@ def test_ordered_sweeps_on_a_whole_graph(S, storage):
     ref = S.sfg_smooth(H, X0, 9, 0.5, storage=storage)
     info = {}
     got = S.sfg_smooth_ordered(H, order, X0, 9, 0.5, storage=storage, info=info)
-    assert torch.equal(got, ref) and info["pairs"] in (0, 1)
+    assert torch.equal(got, ref) and info["sweeps_per_pass"] in (1, 2, 3, 4)
+
+
+def test_ordered_takes_fewer_hops_when_more_do_not_fit(S, monkeypatch):
+    # the whole 2-D grid in its tree's preorder: four neighbours a row, so neighbourhoods grow fast with the
+    # hops, and at some cap a block's layout exceeds its capacities.  The library then lays out for fewer hops
+    # (or runs the plain sweeps): never more than the cap asked for, and the bits never change.
+    g = W.grid2d(200, 200, seed=525)
+    u, v, w, tree, order = tree_and_order(S, g)
+    H = S.sfg_laplacian_csr(g.n, u, v, w)
+    X0 = dev(W.random_block(g.n, 16, 526))
+    ref = S.sfg_smooth(H, X0, 12, 0.5)
+    for hops in ("4", "3", "2", "0"):
+        monkeypatch.setenv("SFG_SWEEP_HOPS", hops)
+        info = {}
+        got = S.sfg_smooth_ordered(H, order, X0, 12, 0.5, info=info)
+        assert torch.equal(got, ref), hops
+        assert 1 <= info["sweeps_per_pass"] <= max(int(hops), 1), hops
+    # the tree alone fits 4 hops; unset, FP64 takes 2 and FP32 3
+    monkeypatch.setenv("SFG_SWEEP_HOPS", "4")
+    Ht = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
+    info = {}
+    assert torch.equal(S.sfg_smooth_ordered(Ht, order, X0, 12, 0.5, info=info), S.sfg_smooth(Ht, X0, 12, 0.5))
+    assert info["sweeps_per_pass"] == 4
+    monkeypatch.delenv("SFG_SWEEP_HOPS")
+    for storage, hops in ((torch.float64, 2), (torch.float32, 3)):
+        Hs = S.sfg_laplacian_csr(g.n, u, v, w.to(storage), mask=tree)
+        info = {}
+        got = S.sfg_smooth_ordered(Hs, order, X0, 12, 0.5, storage=storage, info=info)
+        assert torch.equal(got, S.sfg_smooth(Hs, X0, 12, 0.5, storage=storage)) and info["sweeps_per_pass"] == hops
 
 
 def test_ordered_falls_back_and_checks(S, orc):
@@ -77,15 +119,15 @@ def test_ordered_falls_back_and_checks(S, orc):
     X0 = dev(W.random_block(g.n, 8, 531))
     ref = S.sfg_smooth(H, X0, 6, 0.5)
     # node order on the whole grid: a block of 64 nodes is one grid row, whose neighbours above and below
-    # exceed the one-hop capacity, so the plain path runs
+    # exceed even the 2-hop capacity, so the plain path runs
     info = {}
     ident = torch.arange(g.n, dtype=torch.int32, device="cuda")
     got = S.sfg_smooth_ordered(H, ident, X0, 6, 0.5, info=info)
-    assert torch.equal(got, ref) and info["pairs"] == 0
+    assert torch.equal(got, ref) and info["sweeps_per_pass"] == 1
     # and it is the oracle's smoothing
     Hc = orc.laplacian_csr(g.n, g.u, g.v, g.w)
     assert np.array_equal(got.cpu().numpy(), orc.smooth(Hc, orc.center(X0.cpu().numpy())[0], 6, 0.5))
-    # shapes the pairs do not take: zero and one sweep, 16-bit storage, k not a multiple of 4
+    # shapes the passes do not take: zero and one sweep, 16-bit storage, k not a multiple of 4
     tree, _ = S.sfg_spanning_tree(g.n, u, v, w)
     Ht = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
     order = S.sfg_tree_order(g.n, u, v, w, tree).order
@@ -93,12 +135,12 @@ def test_ordered_falls_back_and_checks(S, orc):
         X0k = dev(W.random_block(g.n, k, 532 + k))
         info = {}
         got = S.sfg_smooth_ordered(Ht, order, X0k, sweeps, 0.5, info=info)
-        assert torch.equal(got, S.sfg_smooth(Ht, X0k, sweeps, 0.5)) and info["pairs"] == 0
+        assert torch.equal(got, S.sfg_smooth(Ht, X0k, sweeps, 0.5)) and info["sweeps_per_pass"] == 1
     Ht32 = S.sfg_laplacian_csr(g.n, u, v, w.float(), mask=tree)
     info = {}
     got = S.sfg_smooth_ordered(Ht32, order, X0, 6, 0.5, storage=torch.float16, final_f32=True, info=info)
     assert torch.equal(got, S.sfg_smooth(Ht32, X0, 6, 0.5, storage=torch.float16, final_f32=True))
-    assert info["pairs"] == 0
+    assert info["sweeps_per_pass"] == 1
     # an order that is not a permutation is refused
     bad = order.clone()
     bad[5] = bad[6]
@@ -119,5 +161,5 @@ def test_ordered_matches_the_oracle_on_a_power_grid_tree(S, orc):
     info = {}
     got = S.sfg_smooth_ordered(H, order, dev(X0), 20, 0.5, info=info)
     Hc = orc.laplacian_csr(g.n, g.u[t], g.v[t], g.w[t])
-    assert info["pairs"] == 1
+    assert info["sweeps_per_pass"] == 2
     assert np.array_equal(got.cpu().numpy(), orc.smooth(Hc, orc.center(X0)[0], 20, 0.5))
