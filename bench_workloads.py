@@ -292,13 +292,16 @@ def mesh_steps(SG, g, u, v, w32, tree, cand, x0, models):
     """Step closures on one mesh, each returning (selection over the off-tree edges, threshold):
     plain(kk, T, f): the plain method in FP32 with the first kk vectors; ranked(model, f): the top f by the
     surrogate's prediction alone; pruned(model, cf, T, f): the top f of the exact scores of the surrogate's top
-    cf.  Buffers are preallocated; only the pruned path's candidate list is sized per call."""
+    cf.  Every smoothing (the plain one, the surrogate's cheap embedding, the pruned path's exact one) runs
+    several sweeps per pass in the spanning tree's preorder, which is input preparation like the tree.  Buffers
+    are preallocated; only the pruned path's candidate list is sized per call."""
     n = g.n
     nc = int(cand.numel())
     dev = u.device
     H = S.sfg_laplacian_csr(n, u, v, w32, mask=tree)
     G = S.sfg_laplacian_csr(n, u, v, w32)
-    ws_sm = torch.empty(S.sfg_workspace_bytes(S.OP_SMOOTH, n, 0, int(x0.shape[1]), torch.float32),
+    order = S.sfg_tree_order(n, u, v, w32.double(), tree).order
+    ws_sm = torch.empty(S.sfg_workspace_bytes(S.OP_SMOOTH_ORDERED, n, 0, int(x0.shape[1]), torch.float32),
                         dtype=torch.uint8, device=dev)
     ws_g = torch.empty(S.sfg_workspace_bytes(S.OP_LAPLACIAN_CSR, n, g.m, 0, torch.float32), dtype=torch.uint8,
                        device=dev)
@@ -328,7 +331,7 @@ def mesh_steps(SG, g, u, v, w32, tree, cand, x0, models):
     def plain(kk, T, f):
         xb, xo = block(kk)
         S.sfg_laplacian_csr(n, u, v, w32, mask=tree, out=H, nnz=nnz_t)
-        S.sfg_smooth(H, xb, T, 0.5, storage=torch.float32, out=xo, ws=ws_sm)
+        S.sfg_smooth_ordered(H, order, xb, T, 0.5, storage=torch.float32, out=xo, ws=ws_sm)
         S.sfg_edge_scores(xo, u, v, w32, cand=cand, out=score)
         return S.sfg_select_topk(score, int(math.ceil(f * nc)), sel=sel, tau=tau, ws=ws_sel, sync=False)
 
@@ -336,7 +339,8 @@ def mesh_steps(SG, g, u, v, w32, tree, cand, x0, models):
         # the network aggregates over G: build G's CSR and take the tree's from it
         S.sfg_laplacian_csr(n, u, v, w32, ws=ws_g, out=G, nnz=2 * g.m)
         S.sfg_csr_select(G, tree, out=H, nnz=nnz_t, ws=ws_cs)
-        xc = S.sfg_smooth(H, block(model.kc)[0], model.tc, 0.5, storage=torch.bfloat16, final_f32=True)
+        xc = S.sfg_smooth_ordered(H, order, block(model.kc)[0], model.tc, 0.5, storage=torch.bfloat16,
+                                  final_f32=True, ws=ws_sm)
         pp = SG.Prepared(n, u, v, w32, tree, cand, G, H, xc, model.tc)
         nf, ef = SG.features(pp, model.norm)
         return S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
@@ -349,7 +353,7 @@ def mesh_steps(SG, g, u, v, w32, tree, cand, x0, models):
         cpos = torch.nonzero(csel).reshape(-1)
         ce = cand[cpos].contiguous()
         xb, xo = block(int(x0.shape[1]))
-        S.sfg_smooth(H, xb, T, 0.5, storage=torch.float32, out=xo, ws=ws_sm)
+        S.sfg_smooth_ordered(H, order, xb, T, 0.5, storage=torch.float32, out=xo, ws=ws_sm)
         s2 = S.sfg_edge_scores(xo, u, v, w32, cand=ce)
         sel2, _ = S.sfg_select_topk(s2, min(int(math.ceil(f * nc)), int(ce.numel())), sync=False)
         full = torch.zeros(nc, dtype=torch.uint8, device=dev)
@@ -475,14 +479,16 @@ def run_surrogate(args) -> dict:
     ksel = int(math.ceil(f * nc))
     nnz = 2 * (g.n - 1)
     H = S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree)
-    ws_sm = torch.empty(S.sfg_workspace_bytes(S.OP_SMOOTH, g.n, 0, k, torch.float32), dtype=torch.uint8,
+    # every smoothing runs several sweeps per pass in the tree's preorder (input preparation, like the tree)
+    order = S.sfg_tree_order(g.n, u, v, w64, tree).order
+    ws_sm = torch.empty(S.sfg_workspace_bytes(S.OP_SMOOTH_ORDERED, g.n, 0, k, torch.float32), dtype=torch.uint8,
                         device="cuda")
     X = torch.empty((g.n, k), dtype=torch.float32, device="cuda")
     score = torch.empty(nc, dtype=torch.float32, device="cuda")
 
     def plain_step():
         S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree, out=H, nnz=nnz)
-        S.sfg_smooth(H, x0, T, 0.5, storage=torch.float32, out=X, ws=ws_sm)
+        S.sfg_smooth_ordered(H, order, x0, T, 0.5, storage=torch.float32, out=X, ws=ws_sm)
         S.sfg_edge_scores(X, u, v, w32, cand=cand, out=score)
         return S.sfg_select_topk(score, ksel, sync=False)
 
@@ -509,7 +515,8 @@ def run_surrogate(args) -> dict:
         def surrogate_pred():
             S.sfg_laplacian_csr(g.n, u, v, w32, ws=ws_g, out=G, nnz=2 * g.m)
             S.sfg_csr_select(G, tree, out=H, nnz=nnz, ws=ws_sel)
-            xc = S.sfg_smooth(H, x0c, model.tc, 0.5, storage=torch.bfloat16, final_f32=True)
+            xc = S.sfg_smooth_ordered(H, order, x0c, model.tc, 0.5, storage=torch.bfloat16, final_f32=True,
+                                      ws=ws_sm)
             pp = SG.Prepared(g.n, u, v, w32, tree, cand, G, H, xc, model.tc)
             nf, ef = SG.features(pp, model.norm)
             return S.sfg_mpnn_forward(G, model.params, nf, u, v, ef, cand=cand, act=torch.bfloat16, ws=ws_f)
@@ -519,7 +526,7 @@ def run_surrogate(args) -> dict:
             csel, _ = S.sfg_select_topk(pred, kcand, sync=False)
             cpos = torch.nonzero(csel).reshape(-1)
             ce = cand[cpos].contiguous()
-            S.sfg_smooth(H, x0, T, 0.5, storage=torch.float32, out=X, ws=ws_sm)
+            S.sfg_smooth_ordered(H, order, x0, T, 0.5, storage=torch.float32, out=X, ws=ws_sm)
             s2 = S.sfg_edge_scores(X, u, v, w32, cand=ce)
             sel2, _ = S.sfg_select_topk(s2, min(ksel, int(ce.numel())), sync=False)
             return cpos, sel2

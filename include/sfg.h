@@ -186,19 +186,25 @@ sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega,
  * storage type).  The order decides how small the neighbourhoods are: a
  * spanning tree's preorder (sfg_tree_order) keeps them to a few hundred rows
  * on meshes and power grids.
- *   order         [n] int32 (device): a permutation of the nodes (checked)
+ *   order         [n] int32 (device): a permutation of the nodes (checked
+ *                 whenever the passes run; unused, and not read, otherwise)
  *   per_pass_out  (host, may be NULL): the sweeps each pass took, 2 to 4; 1 if
- *                 the call ran sfg_smooth instead: storage other than F64/F32,
- *                 k not a multiple of 4 or over 128 bytes per row, fewer than
- *                 2 sweeps, or a block whose 2-hop layout exceeds the
- *                 capacities (168 rows in all, 112 within one hop, 288 local
- *                 entries; 4 hops: 288, 224 within three hops, 512; 3 hops:
- *                 224, 160, 384).  The environment variable SFG_SWEEP_HOPS
- *                 (2, 3 or 4, read at every call) caps h; 0 forces sfg_smooth
+ *                 the call ran sfg_smooth instead: sweeps x k x (bytes of a
+ *                 storage value) under 640 (a narrow block's few sweeps do
+ *                 not repay the layout pass), k not a multiple of 4 or
+ *                 over 128 bytes per row (F16/BF16: over 16 columns), fewer
+ *                 than 2 sweeps, a reduced-precision row over 256 entries
+ *                 (sfg_smooth sums those by lane groups), or a block whose
+ *                 2-hop layout exceeds the capacities (168 rows in all, 112
+ *                 within one hop, 288 local entries; 4 hops: 288, 224 within
+ *                 three hops, 512; 3 hops: 224, 160, 384).  The environment
+ *                 variable SFG_SWEEP_HOPS (2, 3 or 4, read at every call) caps
+ *                 h and takes the passes at any width; 0 forces sfg_smooth
  *   other arguments as sfg_smooth
  * Workspace: sfg_workspace_bytes(SFG_OP_SMOOTH_ORDERED, n, 0, k, storage).
  * Synchronises once per layout tried (to learn whether every block fits).
- * Errors: those of sfg_smooth; SFG_EINVAL when order is not a permutation.
+ * Errors: those of sfg_smooth; SFG_EINVAL when the passes would run and order
+ * is not a permutation.
  */
 sfg_status sfg_smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps, double omega,
                               const double *x0, sfg_dtype storage, int32_t final_f32, void *x, int32_t *per_pass_out,

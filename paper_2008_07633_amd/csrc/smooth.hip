@@ -850,7 +850,8 @@ __global__ void k_mpk_check(int64_t n, const int32_t *__restrict__ order, int32_
 
 // Layout of one block for H hops, one 64-lane workgroup per block.  A block
 // that does not fit (a layer, the rows or the local CSR over the capacities,
-// an order entry outside [0, n)) gets zero sizes and sets flag bit 2; the
+// a row the single sweep would not form in entry order, an order entry
+// outside [0, n)) gets zero sizes and sets flag bit 2; the
 // caller then lays out for fewer hops, or runs the single sweeps.  Slots of
 // L1..LH are numbered in discovery order: which slot a node takes changes
 // where its row sits in the LDS, not any value.
@@ -861,6 +862,9 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
                                                   const TW *__restrict__ deg, MpkDev L, int32_t *flag) {
     using C = MpkCaps<H>;
     using Col = typename C::Col;
+    // rows the single sweep forms in entry order: all FP64 rows (sfg_smooth keeps them in k_sweep), reduced
+    // precision rows up to kLongRow entries (longer ones go to k_sweep_long's lane-group sums there)
+    constexpr int kMaxRow = sizeof(TW) == 8 ? C::kEnt : (kLongRow < C::kEnt ? kLongRow : C::kEnt);
     __shared__ int32_t keys[C::kHash];
     __shared__ int32_t vals[C::kHash];
     __shared__ int32_t snode[C::kSlots];
@@ -905,7 +909,7 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
             for (int r = lo + lane; r < ends[h]; r += 64) {
                 const int32_t q = snode[r];
                 const int32_t j0 = rowptr[q], len = rowptr[q + 1] - j0;
-                if (len > C::kEnt) {
+                if (len > kMaxRow) {
                     full = 1;
                     continue;
                 }
@@ -1013,10 +1017,10 @@ constexpr int mpk_pass_waves() {
 // workgroups of one XCD, so its layout is fetched once into that XCD's L2.
 // Two dependent rounds of global loads: the block's sizes and slot nodes,
 // then X of the slots and the local CSR.
-template <int H, int KC, typename TIN, typename TX, typename TW, typename TA, int VPL, bool CENTER>
+template <int H, int KC, typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, bool CENTER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mpk_pass_waves<H, KC, TX, TW>()))) void
 k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const double *__restrict__ mean,
-             TX *__restrict__ y, TA keep, TA omega) {
+             TO *__restrict__ y, TA keep, TA omega) {
     using C = MpkCaps<H>;
     using Col = typename C::Col;
     constexpr int LPR = KC / VPL;              // lanes per row
@@ -1114,8 +1118,9 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const do
         if (i < R) ldeg[i] = dg[j];
     }
     __syncthreads();
-    // one sweep of row r from the LDS
-    auto row_sweep = [&](int r) {
+    // one sweep of row r from the LDS, stored as T (the storage type, or the last iterate's)
+    auto row_sweep = [&](int r, auto tag) {
+        using T = decltype(tag);
         TA acc[VPL];
 #pragma unroll
         for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
@@ -1127,13 +1132,13 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const do
         }
         const Vec<TX, VPL> sv = *reinterpret_cast<const Vec<TX, VPL> *>(xs + r * KC + c);
         const TA d = cvt<TA>(ldeg[r]);
-        Vec<TX, VPL> out;
+        Vec<T, VPL> out;
 #pragma unroll
         for (int i = 0; i < VPL; ++i) {
             const TA a = keep * cvt<TA>(sv.v[i]);
             const TA q = acc[i] / d;
             const TA bo = omega * q;
-            out.v[i] = cvt<TX>(a + bo);
+            out.v[i] = cvt<T>(a + bo);
         }
         return out;
     };
@@ -1147,7 +1152,7 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const do
 #pragma unroll
         for (int q = 0; q < kRowPasses; ++q) {
             const int r = ri0 + q * RPP;
-            if (r < nrows && r < rend) xr[q] = row_sweep(r);
+            if (r < nrows && r < rend) xr[q] = row_sweep(r, TX());
         }
         __syncthreads();
 #pragma unroll
@@ -1159,7 +1164,7 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const do
     }
     // the last sweep: L0 (its neighbours all lie in L0 and L1)
     for (int r = ri0; r < s0 && r < rend; r += RPP)
-        *reinterpret_cast<Vec<TX, VPL> *>(y + (int64_t)nodes[r] * k + g0 + c) = row_sweep(r);
+        *reinterpret_cast<Vec<TO, VPL> *>(y + (int64_t)nodes[r] * k + g0 + c) = row_sweep(r, TO());
 }
 
 }  // namespace
@@ -1366,57 +1371,85 @@ int pass_cols(int32_t k) {
     return k;
 }
 
-template <int H, int KC, typename TX, bool CENTER>
-void launch_pass_kc(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TX *y,
+// Weights and arithmetic: FP64 for FP64 storage, FP32 otherwise (as sfg_smooth).
+template <int H, int KC, typename TX, typename TO, bool CENTER>
+void launch_pass_kc(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TO *y,
                     double omega, hipStream_t s) {
     using TIN = typename std::conditional<CENTER, double, TX>::type;
+    using TA = typename std::conditional<sizeof(TX) == 8, double, float>::type;
     const int64_t items = nb * (k / KC);
     SFG_REQUIRE(items <= 0x7fffffff, SFG_EUNSUPPORTED, "smooth_ordered: too many blocks");
-    hipLaunchKernelGGL((k_sweep_pass<H, KC, TIN, TX, TX, TX, 4, CENTER>), dim3((uint32_t)items), dim3(256), 0, s, k,
-                       m, mp.dev, (const TIN *)x, mean, y, (TX)(1.0 - omega), (TX)omega);
+    hipLaunchKernelGGL((k_sweep_pass<H, KC, TIN, TX, TO, TA, TA, 4, CENTER>), dim3((uint32_t)items), dim3(256), 0, s,
+                       k, m, mp.dev, (const TIN *)x, mean, y, (TA)(1.0 - omega), (TA)omega);
     SFG_LAUNCH_CHECK();
 }
 
-template <int H, typename TX, bool CENTER>
-void launch_pass(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TX *y,
+template <int H, typename TX, typename TO, bool CENTER>
+void launch_pass(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TO *y,
                  double omega, hipStream_t s) {
     constexpr int wide = 128 / (int)sizeof(TX);
     switch (pass_cols<TX>(k)) {
-        case 4: launch_pass_kc<H, 4, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-        case 8: launch_pass_kc<H, 8, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-        case 12: launch_pass_kc<H, 12, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-        case 16: launch_pass_kc<H, 16, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        case 4: launch_pass_kc<H, 4, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        case 8: launch_pass_kc<H, 8, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        case 12: launch_pass_kc<H, 12, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        case 16: launch_pass_kc<H, 16, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
         default: break;
     }
     if constexpr (wide == 32) {
         switch (pass_cols<TX>(k)) {
-            case 20: launch_pass_kc<H, 20, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-            case 24: launch_pass_kc<H, 24, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-            case 28: launch_pass_kc<H, 28, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-            case 32: launch_pass_kc<H, 32, TX, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            case 20: launch_pass_kc<H, 20, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            case 24: launch_pass_kc<H, 24, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            case 28: launch_pass_kc<H, 28, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            case 32: launch_pass_kc<H, 32, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
             default: break;
         }
     }
     fail(SFG_EUNSUPPORTED, "smooth_ordered: no pass kernel for this width");
 }
 
-// Passes of H sweeps, the last one shorter when H does not divide the count.
+// Passes of H sweeps, the last one shorter when H does not divide the count;
+// with final_f32 (16-bit storage) the very last sweep stores FP32.
 template <int H, typename TX>
 void run_smooth_passes(const sfg_csr *H_, int32_t k, int32_t sweeps, double omega, const double *x0, void *xout,
-                       const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s) {
+                       bool final_f32, const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s) {
     launch_column_means<double>(x0, H_->n, k, p.partial, p.mean, s);
     TX *b0 = (TX *)p.buf0, *b1 = (TX *)p.buf1;
     const TX *src = nullptr;
     for (int32_t done = 0, q = 0; done < sweeps; ++q) {
         const int32_t m = sweeps - done < H ? sweeps - done : H;
-        TX *dst = done + m == sweeps ? (TX *)xout : (q % 2 == 0 ? b0 : b1);
+        const bool last = done + m == sweeps;
+        TX *dst = last ? (TX *)xout : (q % 2 == 0 ? b0 : b1);
+        if constexpr (sizeof(TX) == 2) {
+            if (last && final_f32) {
+                if (q == 0)
+                    launch_pass<H, TX, float, true>(k, m, mp, nb, x0, p.mean, (float *)xout, omega, s);
+                else
+                    launch_pass<H, TX, float, false>(k, m, mp, nb, src, nullptr, (float *)xout, omega, s);
+                break;
+            }
+        }
         if (q == 0)
-            launch_pass<H, TX, true>(k, m, mp, nb, x0, p.mean, dst, omega, s);
+            launch_pass<H, TX, TX, true>(k, m, mp, nb, x0, p.mean, dst, omega, s);
         else
-            launch_pass<H, TX, false>(k, m, mp, nb, src, nullptr, dst, omega, s);
+            launch_pass<H, TX, TX, false>(k, m, mp, nb, src, nullptr, dst, omega, s);
         src = dst;
         done += m;
     }
+}
+
+template <int H>
+void run_passes(sfg_dtype storage, const sfg_csr *G, int32_t k, int32_t sweeps, double omega, const double *x0,
+                void *x, bool final_f32, const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s) {
+    switch (storage) {
+        case SFG_F64: run_smooth_passes<H, double>(G, k, sweeps, omega, x0, x, false, p, mp, nb, s); return;
+        case SFG_F32: run_smooth_passes<H, float>(G, k, sweeps, omega, x0, x, false, p, mp, nb, s); return;
+        case SFG_F16: run_smooth_passes<H, __half>(G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s); return;
+        case SFG_BF16:
+            run_smooth_passes<H, __hip_bfloat16>(G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s);
+            return;
+        default: break;
+    }
+    fail(SFG_EUNSUPPORTED, "smooth_ordered: storage");
 }
 
 template <int H>
@@ -1442,6 +1475,15 @@ int32_t read_flag(const MpkPlan &mp, hipStream_t s) {
 
 // Same result as smooth(); see sfg_smooth_ordered in the header.  Returns the
 // sweeps each pass over X took: 1 when the plain path ran, else 2 to 4.
+// The passes are taken when sweeps x (bytes of a block row) >= kMpkMinBytes:
+// the layout pass and the per-block local CSR cost about as much as a few
+// sweeps of a narrow block.  Measured on the 200^3 mesh's tree (one call
+// with the CSR build, scores and selection): FP32 8 vectors, 20 sweeps 4.37
+// ms with passes against 5.63 without; FP32 4 vectors, 10 sweeps 3.07
+// against 2.85; BF16 4 vectors, 10 sweeps (a step of the surrogate's) 6.68
+// against 6.25.  Setting SFG_SWEEP_HOPS takes the passes at any width.
+constexpr int64_t kMpkMinBytes = 640;
+
 // Hops are tried from SFG_SWEEP_HOPS (2, 3 or 4; default 2 in FP64, 3 in
 // FP32) down to 2 until every block's layout fits.  Measured on the 200^3
 // mesh's spanning tree in preorder, 16 vectors, per sweep: FP64 289 us with
@@ -1461,19 +1503,25 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
     Carver c(ws);
     SmoothPlan p = plan_smooth(c, n, k < 1 ? 1 : k, storage);
     MpkPlan mp = plan_mpk(c, n, 8);
-    // the order must be a permutation of the nodes, whichever path runs
-    fill_i32(mp.seen, n, 0, s);
-    fill_i32(mp.flag, 1, 0, s);
-    hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
-    SFG_LAUNCH_CHECK();
     const size_t sx = dtype_size(storage);
     const int want = env_int("SFG_SWEEP_HOPS", default_hops(storage));
-    const bool shape_ok = (storage == SFG_F64 || storage == SFG_F32) && H->vt == storage && k >= 1 &&
-                          k % 4 == 0 && (size_t)k * sx <= (size_t)kMpkRowBytes && sweeps >= 2 && H->nnz >= 1 &&
-                          H->col && H->val && H->deg && want >= 2;
+    const bool pays = getenv("SFG_SWEEP_HOPS") != nullptr ||
+                      (int64_t)sweeps * k * (int64_t)dtype_size(storage) >= kMpkMinBytes;
+    // FP64 storage on FP64 weights; FP32, FP16, BF16 storage on FP32 weights (as sfg_smooth); 16-bit rows up
+    // to 16 columns
+    const bool types_ok = storage == SFG_F64 ? H->vt == SFG_F64
+                                             : (H->vt == SFG_F32 && (storage == SFG_F32 || k <= 16) &&
+                                                (storage == SFG_F32 || storage == SFG_F16 || storage == SFG_BF16));
+    const bool shape_ok = types_ok && pays && k >= 1 && k % 4 == 0 && (size_t)k * sx <= (size_t)kMpkRowBytes &&
+                          sweeps >= 2 && H->nnz >= 1 && H->col && H->val && H->deg && want >= 2;
     const int64_t nb = mpk_blocks(n);
     int hops = 0;
     if (shape_ok) {
+        // the passes take the rows in this order: it must be a permutation of the nodes
+        fill_i32(mp.seen, n, 0, s);
+        fill_i32(mp.flag, 1, 0, s);
+        hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
+        SFG_LAUNCH_CHECK();
         for (int h = want < kMpkMaxHops ? want : kMpkMaxHops; h >= 2 && hops == 0; --h) {
             if (h == 4) build_layout<4>(H, order, mp, nb, s);
             else if (h == 3) build_layout<3>(H, order, mp, nb, s);
@@ -1483,8 +1531,6 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
             else
                 hops = h;
         }
-    } else {
-        read_flag(mp, s);
     }
     if (hops == 0) {
         // the workspace starts with the plain smoothing's layout
@@ -1494,17 +1540,10 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
     }
     SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_ordered: omega must be in (0, 1]");
     SFG_REQUIRE(x0 && x, SFG_EINVAL, "smooth_ordered: null pointer");
-    const bool f64 = storage == SFG_F64;
-    if (hops == 4) {
-        if (f64) run_smooth_passes<4, double>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
-        else run_smooth_passes<4, float>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
-    } else if (hops == 3) {
-        if (f64) run_smooth_passes<3, double>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
-        else run_smooth_passes<3, float>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
-    } else {
-        if (f64) run_smooth_passes<2, double>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
-        else run_smooth_passes<2, float>(H, k, sweeps, omega, x0, x, p, mp, nb, s);
-    }
+    const bool f32last = final_f32 && (storage == SFG_F16 || storage == SFG_BF16);
+    if (hops == 4) run_passes<4>(storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s);
+    else if (hops == 3) run_passes<3>(storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s);
+    else run_passes<2>(storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s);
     return hops;
 }
 

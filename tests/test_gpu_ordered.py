@@ -127,29 +127,81 @@ def test_ordered_falls_back_and_checks(S, orc):
     # and it is the oracle's smoothing
     Hc = orc.laplacian_csr(g.n, g.u, g.v, g.w)
     assert np.array_equal(got.cpu().numpy(), orc.smooth(Hc, orc.center(X0.cpu().numpy())[0], 6, 0.5))
-    # shapes the passes do not take: zero and one sweep, 16-bit storage, k not a multiple of 4
+    # shapes the passes do not take: zero and one sweep, k not a multiple of 4, and (unless SFG_SWEEP_HOPS
+    # asks for them) narrow blocks with few sweeps: 4 FP32 vectors, 10 sweeps
     tree, _ = S.sfg_spanning_tree(g.n, u, v, w)
-    Ht = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
+    Ht32 = S.sfg_laplacian_csr(g.n, u, v, w.float(), mask=tree)
     order = S.sfg_tree_order(g.n, u, v, w, tree).order
+    X4 = dev(W.random_block(g.n, 4, 538))
+    info = {}
+    got = S.sfg_smooth_ordered(Ht32, order, X4, 10, 0.5, storage=torch.float32, info=info)
+    assert torch.equal(got, S.sfg_smooth(Ht32, X4, 10, 0.5, storage=torch.float32)) and info["sweeps_per_pass"] == 1
+    Ht = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
     for sweeps, k in ((0, 8), (1, 8), (5, 6)):
         X0k = dev(W.random_block(g.n, k, 532 + k))
         info = {}
         got = S.sfg_smooth_ordered(Ht, order, X0k, sweeps, 0.5, info=info)
         assert torch.equal(got, S.sfg_smooth(Ht, X0k, sweeps, 0.5)) and info["sweeps_per_pass"] == 1
-    Ht32 = S.sfg_laplacian_csr(g.n, u, v, w.float(), mask=tree)
+    # 16-bit rows over 16 columns
+    X24 = dev(W.random_block(g.n, 24, 539))
     info = {}
-    got = S.sfg_smooth_ordered(Ht32, order, X0, 6, 0.5, storage=torch.float16, final_f32=True, info=info)
-    assert torch.equal(got, S.sfg_smooth(Ht32, X0, 6, 0.5, storage=torch.float16, final_f32=True))
+    got = S.sfg_smooth_ordered(Ht32, order, X24, 6, 0.5, storage=torch.float16, final_f32=True, info=info)
+    assert torch.equal(got, S.sfg_smooth(Ht32, X24, 6, 0.5, storage=torch.float16, final_f32=True))
     assert info["sweeps_per_pass"] == 1
-    # an order that is not a permutation is refused
+    # an order that is not a permutation is refused where the passes would use it (16 FP64 vectors, 6 sweeps)
+    X16 = dev(W.random_block(g.n, 16, 537))
     bad = order.clone()
     bad[5] = bad[6]
     with pytest.raises(S.SfgError, match="SFG_EINVAL"):
-        S.sfg_smooth_ordered(Ht, bad, X0, 6, 0.5)
+        S.sfg_smooth_ordered(Ht, bad, X16, 6, 0.5)
     bad = order.clone()
     bad[0] = g.n
     with pytest.raises(S.SfgError, match="SFG_EINVAL"):
-        S.sfg_smooth_ordered(Ht, bad, X0, 6, 0.5)
+        S.sfg_smooth_ordered(Ht, bad, X16, 6, 0.5)
+    info = {}
+    assert torch.equal(S.sfg_smooth_ordered(Ht, order, X16, 6, 0.5, info=info), S.sfg_smooth(Ht, X16, 6, 0.5))
+    assert info["sweeps_per_pass"] == 2
+
+
+@pytest.mark.parametrize("hops", ["4", "3", "2"])
+@pytest.mark.parametrize("storage", [torch.float16, torch.bfloat16])
+@pytest.mark.parametrize("final_f32", [False, True])
+def test_ordered_sixteen_bit_storage_is_bit_identical(S, storage, final_f32, hops, monkeypatch):
+    # FP16 / BF16 storage, FP32 weights and arithmetic; with final_f32 only the very last sweep stores FP32
+    monkeypatch.setenv("SFG_SWEEP_HOPS", hops)
+    g = W.mesh3d(17, 13, 11, seed=545, wdist=("lognormal", 0.0, 1.5))
+    u, v, w, tree, order = tree_and_order(S, g)
+    H = S.sfg_laplacian_csr(g.n, u, v, w.float(), mask=tree)
+    for k, sweeps in ((4, 10), (16, 7), (8, 2), (12, 5)):
+        X0 = dev(W.random_block(g.n, k, 550 + k + sweeps))
+        ref = S.sfg_smooth(H, X0, sweeps, 0.5, storage=storage, final_f32=final_f32)
+        info = {}
+        got = S.sfg_smooth_ordered(H, order, X0, sweeps, 0.5, storage=storage, final_f32=final_f32, info=info)
+        assert got.dtype == ref.dtype and torch.equal(got, ref), (k, sweeps)
+        assert info["sweeps_per_pass"] == int(hops), (k, sweeps)
+
+
+@pytest.mark.parametrize("storage", [torch.float32, torch.float64])
+def test_ordered_hub_rows_keep_the_single_sweep_sums(S, storage, monkeypatch):
+    # a star of 270 leaves on a path: in reduced precision sfg_smooth sums rows over 256 entries by lane groups,
+    # so the passes must leave such a row to it (the FP64 row exceeds the local capacities instead)
+    monkeypatch.setenv("SFG_SWEEP_HOPS", "2")
+    n_leaf, n_path = 270, 500
+    n = 1 + n_leaf + n_path
+    u = list(range(1, n_leaf + 1)) + list(range(n_leaf, n - 1))
+    v = [0] * n_leaf + list(range(n_leaf + 1, n))
+    uu, vv = np.minimum(u, v).astype(np.int32), np.maximum(u, v).astype(np.int32)
+    o = np.lexsort((vv, uu))
+    rng = np.random.default_rng(560)
+    w = rng.uniform(0.5, 2.0, n - 1)
+    ut, vt, wt = dev(uu[o]), dev(vv[o]), dev(w)
+    tree, _ = S.sfg_spanning_tree(n, ut, vt, wt)
+    order = S.sfg_tree_order(n, ut, vt, wt, tree).order
+    H = S.sfg_laplacian_csr(n, ut, vt, wt.to(storage))
+    X0 = dev(W.random_block(n, 8, 561))
+    info = {}
+    got = S.sfg_smooth_ordered(H, order, X0, 6, 0.5, storage=storage, info=info)
+    assert torch.equal(got, S.sfg_smooth(H, X0, 6, 0.5, storage=storage)) and info["sweeps_per_pass"] == 1
 
 
 def test_ordered_matches_the_oracle_on_a_power_grid_tree(S, orc):
