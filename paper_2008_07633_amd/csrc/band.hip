@@ -121,12 +121,19 @@ __global__ __launch_bounds__(256) void k_bfs_seed(int64_t nseeds, const int32_t 
     }
 }
 
-// Expands group `level` (rows[begin, end), begin = sum of the earlier groups) into group level + 1.
+// Expands group `level` (rows[begin, end), begin = sum of the earlier groups) into group level + 1.  With
+// stop > 0 it does nothing once sum_{d <= level} cnt[d] (cap - d) exceeds stop (every workgroup reads the same
+// finished counts, so all agree): the rows found so far already weigh more than the caller's limit.
 __global__ __launch_bounds__(256) void k_bfs_expand(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                                     int32_t level, int32_t unreached, int32_t *dist, int32_t *cnt,
-                                                    int32_t *rows) {
+                                                    int32_t *rows, double stop) {
     int32_t begin = 0;
-    for (int32_t d = 0; d < level; ++d) begin += cnt[d];
+    double weight = 0.0;
+    for (int32_t d = 0; d < level; ++d) {
+        begin += cnt[d];
+        weight += (double)cnt[d] * (double)(unreached - 1 - d);
+    }
+    if (stop > 0.0 && weight + (double)cnt[level] * (double)(unreached - 1 - level) > stop) return;
     const int32_t end = begin + cnt[level];
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -154,10 +161,13 @@ __global__ __launch_bounds__(256) void k_bfs_expand(const int32_t *__restrict__ 
 
 // Groups of rows by hop distance (0..cap) from the endpoints of the nseeds
 // edges eids[]: rows (capacity n) and cnt (cap + 2 entries) on the device,
-// cnt also returned on the host.  Synchronises once.
+// cnt also returned on the host.  With stop > 0 the expansion ends early once
+// the groups found weigh more than stop (a row at distance d weighs cap - d:
+// the sweeps that recompute it); the counts are then partial.  Synchronises
+// once.
 std::vector<int32_t> bfs_groups(const sfg_csr *H, int64_t nseeds, const int32_t *eids, const int32_t *u,
                                 const int32_t *v, int32_t cap, int32_t *dist, int32_t *cnt, int32_t *rows,
-                                hipStream_t s) {
+                                hipStream_t s, double stop = 0.0) {
     const int64_t n = H->n;
     fill_i32(dist, n, cap + 1, s);
     fill_i32(cnt, cap + 2, 0, s);
@@ -166,7 +176,8 @@ std::vector<int32_t> bfs_groups(const sfg_csr *H, int64_t nseeds, const int32_t 
     SFG_LAUNCH_CHECK();
     const uint32_t eb = std::min<uint32_t>(grid_for(n, 256), kBfsBlocks);
     for (int32_t lvl = 0; lvl < cap; ++lvl) {
-        hipLaunchKernelGGL(k_bfs_expand, dim3(eb), dim3(256), 0, s, H->rowptr, H->col, lvl, cap + 1, dist, cnt, rows);
+        hipLaunchKernelGGL(k_bfs_expand, dim3(eb), dim3(256), 0, s, H->rowptr, H->col, lvl, cap + 1, dist, cnt, rows,
+                           stop);
         SFG_LAUNCH_CHECK();
     }
     std::vector<int32_t> hh(cap + 1);
@@ -199,9 +210,14 @@ __global__ void k_stride_sample(int64_t nb, int64_t nc, const int32_t *__restric
 // endpoints are stood in for by an evenly strided sample of the candidates
 // of the expected band size (about band * n_cand / 2: 0.4-0.6% of the
 // candidates for a 1% band on grids, meshes and kNN graphs), and the same
-// capped BFS measures their T-hop neighbourhood.  Synchronises.
+// capped BFS measures their T-hop neighbourhood.  The BFS stops as soon as
+// the share found exceeds `limit` (the caller's decision is then made: the
+// returned share is a lower bound above it); below it the share is exact.
+// On the 2M-point kNN graph with 20 sweeps the full BFS cost 2.4 ms.
+// Synchronises.
 double predicted_cone_share(const sfg_csr *H, int32_t sweeps, int64_t n_cand, const int32_t *cand,
-                            const int32_t *u, const int32_t *v, double band, DevArena &A, hipStream_t s) {
+                            const int32_t *u, const int32_t *v, double band, double limit, DevArena &A,
+                            hipStream_t s) {
     const int64_t n = H->n;
     if (n_cand <= 0 || sweeps <= 0) return 0.0;
     int64_t nb = (int64_t)std::ceil(0.5 * band * (double)n_cand);
@@ -212,7 +228,8 @@ double predicted_cone_share(const sfg_csr *H, int32_t sweeps, int64_t n_cand, co
     int32_t *dist = A.alloc<int32_t>(n + 1);
     int32_t *cnt = A.alloc<int32_t>(sweeps + 2);
     int32_t *rows = A.alloc<int32_t>(n + 1);
-    const std::vector<int32_t> hh = bfs_groups(H, nb, eids, u, v, sweeps, dist, cnt, rows, s);
+    const std::vector<int32_t> hh =
+        bfs_groups(H, nb, eids, u, v, sweeps, dist, cnt, rows, s, limit * (double)sweeps * (double)n);
     // sweep t recomputes the rows within sweeps-1-t hops
     int64_t within = 0, cone = 0;
     std::vector<int64_t> upto(sweeps + 1);

@@ -44,7 +44,8 @@ size_t coarsen_workspace_bytes(int64_t n, int64_t m);
 size_t mpnn_forward_workspace_bytes(int64_t n, sfg_dtype act);
 size_t mpnn_train_workspace_bytes(int64_t n, int64_t ne);
 double predicted_cone_share(const sfg_csr *H, int32_t sweeps, int64_t n_cand, const int32_t *cand,
-                            const int32_t *u, const int32_t *v, double band, DevArena &A, hipStream_t s);
+                            const int32_t *u, const int32_t *v, double band, double limit, DevArena &A,
+                            hipStream_t s);
 void far_entries(const sfg_csr *H, int64_t window, unsigned long long *count, hipStream_t s);
 void inverse_permutation(int64_t n, const int32_t *order, int32_t *inv, hipStream_t s);
 sfg_csr relabel_csr(const sfg_csr *H, const int32_t *order, const int32_t *inv, DevArena &A, hipStream_t s);
@@ -390,6 +391,62 @@ void level_node_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, 
     make_node_order(n, m, u, v, w64, tree, no, A, s);
 }
 
+namespace {
+
+// The scoring graph's CSR with values of type vt, in the numbering the sweeps
+// use: the node order is decided at the call's first scored level (see
+// NodeOrder above) and applied by copying rows in their stored entry order.
+struct ScoringGraph {
+    sfg_csr H{};
+    int32_t max_row = -1;   // longest row when the values are FP64 (FP64 hub rows are summed through LDS)
+};
+
+ScoringGraph scoring_graph(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64,
+                           const float *w32, sfg_dtype vt, const uint8_t *hmask, const uint8_t *base,
+                           const sfg_params *p, NodeOrder *no, DevArena &A, hipStream_t s) {
+    const void *wv = vt == SFG_F64 ? (const void *)w64 : (const void *)w32;
+    int32_t *rowptr = A.alloc<int32_t>(n + 1);
+    int32_t *col = A.alloc<int32_t>(2 * m + 1);
+    int32_t *eid = A.alloc<int32_t>(2 * m + 1);
+    void *val = A.raw((2 * m + 1) * dtype_size(vt));
+    void *deg = A.raw(n * dtype_size(vt));
+    const size_t wsb = csr_workspace_bytes(n, m);
+    build_csr(n, m, u, v, wv, vt, hmask, rowptr, col, val, eid, deg, A.raw(wsb), wsb, s);
+    ScoringGraph G;
+    G.H = sfg_csr{n, 0, rowptr, col, val, eid, deg, vt};
+    const int mode = node_order_mode();
+    const bool decide = no && !no->decided && p->smoother == SFG_SMOOTH_JACOBI && n >= 2 && mode != 0;
+    unsigned long long *far = nullptr;
+    if (decide && mode == 2 && n >= kOrderMinRows && no->launches >= kOrderMinLaunches) {
+        far = A.alloc<unsigned long long>(1);
+        fill_i32((int32_t *)far, 2, 0, s);
+        far_entries(&G.H, kNearRows, far, s);
+    }
+    // FP64 sums hub rows through LDS only where they are known to exist: the
+    // longest row comes back with the entry count
+    int32_t *mr = nullptr;
+    if (vt == SFG_F64) {
+        mr = A.alloc<int32_t>(1);
+        max_row_length(&G.H, mr, s);
+    }
+    int32_t nnz = 0;
+    unsigned long long far_h = 0;
+    SFG_HIP(hipMemcpyAsync(&nnz, rowptr + n, 4, hipMemcpyDeviceToHost, s));
+    if (far) SFG_HIP(hipMemcpyAsync(&far_h, far, 8, hipMemcpyDeviceToHost, s));
+    if (mr) SFG_HIP(hipMemcpyAsync(&G.max_row, mr, 4, hipMemcpyDeviceToHost, s));
+    SFG_HIP(hipStreamSynchronize(s));
+    G.H.nnz = nnz;
+    if (no && !no->decided) {
+        no->decided = true;
+        no->use = decide && (mode == 1 || (far && 4 * far_h > (unsigned long long)nnz));
+        if (no->use) make_node_order(n, m, u, v, w64, base, no, A, s);
+    }
+    if (no && no->use) G.H = relabel_csr(&G.H, no->order, no->inv, A, s);
+    return G;
+}
+
+}  // namespace
+
 // Embed (smooth on the scoring graph), score the edges outside `base`, add
 // the top k_take of them (k_take < 0: ceil(frac * n_cand)).  Writes keep
 // (1 = base, 2 = added); keep may be base itself.  `no` (may be nullptr):
@@ -397,54 +454,22 @@ void level_node_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, 
 void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
                  const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
                  DevArena &A, hipStream_t s, int64_t k_take, NodeOrder *no) {
-    const bool f64 = p->storage == SFG_F64;
-    const sfg_dtype vt = f64 ? SFG_F64 : SFG_F32;
-    const void *wv = f64 ? (const void *)w64 : (const void *)w32;
     const uint8_t *hmask = (p->embed == SFG_EMBED_GRAPH) ? nullptr : base;
     Timer tm(s);
     tm.start();
-    // scoring graph H
-    int32_t *rowptr = A.alloc<int32_t>(n + 1);
-    int32_t *col = A.alloc<int32_t>(2 * m + 1);
-    int32_t *eid = A.alloc<int32_t>(2 * m + 1);
-    void *val = A.raw((2 * m + 1) * dtype_size(vt));
-    void *deg = A.raw(n * dtype_size(vt));
-    size_t wsb = csr_workspace_bytes(n, m);
-    void *ws = A.raw(wsb);
-    build_csr(n, m, u, v, wv, vt, hmask, rowptr, col, val, eid, deg, ws, wsb, s);
-    sfg_csr H{n, 0, rowptr, col, val, eid, deg, vt};
-    const int mode = node_order_mode();
-    const bool decide = no && !no->decided && p->smoother == SFG_SMOOTH_JACOBI && n >= 2 && mode != 0;
-    unsigned long long *far = nullptr;
-    if (decide && mode == 2 && n >= kOrderMinRows && no->launches >= kOrderMinLaunches) {
-        far = A.alloc<unsigned long long>(1);
-        fill_i32((int32_t *)far, 2, 0, s);
-        far_entries(&H, kNearRows, far, s);
-    }
-    // FP64 sums hub rows through LDS only where they are known to exist: the
-    // longest row comes back with the entry count
-    int32_t *mr = nullptr;
-    if (f64) {
-        mr = A.alloc<int32_t>(1);
-        max_row_length(&H, mr, s);
-    }
-    int32_t nnz = 0, max_row = -1;
-    unsigned long long far_h = 0;
-    SFG_HIP(hipMemcpyAsync(&nnz, rowptr + n, 4, hipMemcpyDeviceToHost, s));
-    if (far) SFG_HIP(hipMemcpyAsync(&far_h, far, 8, hipMemcpyDeviceToHost, s));
-    if (mr) SFG_HIP(hipMemcpyAsync(&max_row, mr, 4, hipMemcpyDeviceToHost, s));
-    SFG_HIP(hipStreamSynchronize(s));
-    H.nnz = nnz;
-    if (no && !no->decided) {
-        no->decided = true;
-        no->use = decide && (mode == 1 || (far && 4 * far_h > (unsigned long long)nnz));
-        if (no->use) make_node_order(n, m, u, v, w64, base, no, A, s);
-    }
+    // The precision form (reduced-precision storage with an FP64 band) needs the
+    // FP64 scoring graph, for the band re-scoring or for the FP64 path the
+    // prediction below may send the level to: it is built first, and the
+    // reduced-precision values only when that path runs.
+    const bool band_form = p->storage != SFG_F64 && p->band > 0.0;
+    ScoringGraph G64, G;
+    if (band_form) G64 = scoring_graph(n, m, u, v, w64, w32, SFG_F64, hmask, base, p, no, A, s);
+    else G = scoring_graph(n, m, u, v, w64, w32, p->storage == SFG_F64 ? SFG_F64 : SFG_F32, hmask, base, p, no,
+                           A, s);
     // su, sv, sx0: endpoints and start block in the numbering the sweeps use
     const int32_t *su = u, *sv = v;
     const double *sx0 = x0;
     if (no && no->use) {
-        H = relabel_csr(&H, no->order, no->inv, A, s);
         double *xg = A.alloc<double>((size_t)n * p->k + 1);
         gather_block(n, p->k, no->order, x0, xg, s);
         sx0 = xg;
@@ -459,54 +484,66 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
     // SFG_PRECISION_PREDICT=0 (read at every call) keeps the precision form
     // regardless (tests use it to exercise the band re-scoring).
     const char *pe = getenv("SFG_PRECISION_PREDICT");
-    const bool predict = !(pe && atoi(pe) == 0);
-    if (predict && !f64 && p->band > 0.0 && p->smoother == SFG_SMOOTH_JACOBI) {
-        int32_t *cand0 = A.alloc<int32_t>(m + 1);
-        const int64_t nc0 = compact_ids(base, 0, m, cand0, A, s);
+    const bool predict = band_form && !(pe && atoi(pe) == 0) && p->smoother == SFG_SMOOTH_JACOBI;
+    bool fallback = false;
+    // candidates: edges outside the current sparsifier, ascending id
+    int32_t *cand = nullptr;
+    int64_t nc = -1;
+    if (predict) {
+        cand = A.alloc<int32_t>(m + 1);
+        nc = compact_ids(base, 0, m, cand, A, s);
+        const int32_t *cand0 = cand;
+        const int64_t nc0 = nc;
         const int64_t ks0 = k_take >= 0 ? k_take : (int64_t)std::ceil(p->frac * (double)nc0);
-        if (ks0 > 0 && ks0 < nc0 &&
-            4.0 * predicted_cone_share(&H, p->sweeps, nc0, cand0, su, sv, p->band, A, s) > 1.0) {
-            sfg_params p64 = *p;
-            p64.storage = SFG_F64;
-            p64.band = 0.0;
-            p64.final_f32 = 0;
-            score_level(n, m, u, v, w64, w32, base, &p64, x0, keep, rep, A, s, k_take, no);
-            if (rep) {
-                rep->precision_fallback = 1;
-                rep->cone_rows = (int64_t)p->sweeps * n;
-            }
-            return;
-        }
+        fallback = ks0 > 0 && ks0 < nc0 &&
+                   4.0 * predicted_cone_share(&G64.H, p->sweeps, nc0, cand0, su, sv, p->band, 0.25, A, s) > 1.0;
     }
+    sfg_params p64;
+    const sfg_params *q = p;
+    if (fallback) {
+        p64 = *p;
+        p64.storage = SFG_F64;
+        p64.band = 0.0;
+        p64.final_f32 = 0;
+        q = &p64;
+        G = G64;
+    } else if (band_form) {
+        G = scoring_graph(n, m, u, v, w64, w32, SFG_F32, hmask, base, p, no, A, s);
+    }
+    const bool f64 = q->storage == SFG_F64;
+    const sfg_dtype vt = f64 ? SFG_F64 : SFG_F32;
+    const void *wv = f64 ? (const void *)w64 : (const void *)w32;
+    const sfg_csr &H = G.H;
     // embedding
-    const bool f32last = p->final_f32 && (p->storage == SFG_F16 || p->storage == SFG_BF16);
-    const sfg_dtype xt = f32last ? SFG_F32 : p->storage;
-    void *x = A.raw((size_t)n * p->k * dtype_size(xt));
-    size_t wss = smooth_workspace_bytes(n, p->k, p->storage);
+    const bool f32last = q->final_f32 && (q->storage == SFG_F16 || q->storage == SFG_BF16);
+    const sfg_dtype xt = f32last ? SFG_F32 : q->storage;
+    void *x = A.raw((size_t)n * q->k * dtype_size(xt));
+    size_t wss = smooth_workspace_bytes(n, q->k, q->storage);
     void *wsm = A.raw(wss);
     float ms_other = tm.stop();
     tm.start();
-    if (p->smoother == SFG_SMOOTH_GAUSS_SEIDEL) {
+    if (q->smoother == SFG_SMOOTH_GAUSS_SEIDEL) {
         int32_t *color = A.alloc<int32_t>(n + 1);
         int32_t *class_rows = A.alloc<int32_t>(n + 1);
         const size_t wsc = color_workspace_bytes(n);
         std::vector<int32_t> class_ptr;
         color_graph(&H, color, class_rows, class_ptr, A.raw(wsc), wsc, s);
-        smooth_gs(&H, p->k, p->sweeps, p->omega, sx0, p->storage, class_rows, class_ptr, x, wsm, wss, s);
+        smooth_gs(&H, q->k, q->sweeps, q->omega, sx0, q->storage, class_rows, class_ptr, x, wsm, wss, s);
     } else {
-        smooth(&H, p->k, p->sweeps, p->omega, sx0, p->storage, p->final_f32, x, wsm, wss, s, max_row);
+        smooth(&H, q->k, q->sweeps, q->omega, sx0, q->storage, q->final_f32, x, wsm, wss, s, G.max_row);
     }
     float ms_smooth = tm.stop();
-    // candidates: edges outside the current sparsifier, ascending id
     tm.start();
-    int32_t *cand = A.alloc<int32_t>(m + 1);
-    const int64_t nc = compact_ids(base, 0, m, cand, A, s);
+    if (!cand) {
+        cand = A.alloc<int32_t>(m + 1);
+        nc = compact_ids(base, 0, m, cand, A, s);
+    }
     const sfg_dtype st = f64 ? SFG_F64 : SFG_F32;
     void *score = A.raw((nc + 1) * dtype_size(st));
-    edge_scores(x, xt, n, p->k, nc, cand, su, sv, wv, vt, score, st, s);
+    edge_scores(x, xt, n, q->k, nc, cand, su, sv, wv, vt, score, st, s);
     float ms_score = tm.stop();
     tm.start();
-    const int64_t ksel = k_take >= 0 ? k_take : (int64_t)std::ceil(p->frac * (double)nc);
+    const int64_t ksel = k_take >= 0 ? k_take : (int64_t)std::ceil(q->frac * (double)nc);
     SFG_REQUIRE(ksel <= nc, SFG_EINVAL, "sparsify: more edges requested than candidates");
     uint8_t *sel = A.alloc<uint8_t>(nc + 1);
     double *tau = A.alloc<double>(1);
@@ -526,25 +563,15 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
         rep->band = 0;
         rep->band_above = 0;
         rep->band_rounds = 0;
-        rep->cone_rows = 0;
+        rep->cone_rows = fallback ? (int64_t)p->sweeps * n : 0;
+        rep->precision_fallback = fallback ? 1 : 0;
         rep->node_order = (no && no->use) ? 1 : 0;
         rep->n_scored = nc;
     }
-    if (!f64 && p->band > 0.0 && ksel > 0 && ksel < nc) {
+    if (!f64 && q->band > 0.0 && ksel > 0 && ksel < nc) {
         // precision form: FP64 re-scoring of the edges near the threshold
-        int32_t *rowptr64 = rowptr;
-        void *val64 = val, *deg64 = deg;
-        int32_t *col64 = col, *eid64 = eid;
-        val64 = A.raw((2 * m + 1) * 8);
-        deg64 = A.raw(n * 8);
-        rowptr64 = A.alloc<int32_t>(n + 1);
-        col64 = A.alloc<int32_t>(2 * m + 1);
-        eid64 = A.alloc<int32_t>(2 * m + 1);
-        build_csr(n, m, u, v, w64, SFG_F64, hmask, rowptr64, col64, val64, eid64, deg64, ws, wsb, s);
-        sfg_csr H64{n, nnz, rowptr64, col64, val64, eid64, deg64, SFG_F64};
-        if (no && no->use) H64 = relabel_csr(&H64, no->order, no->inv, A, s);
-        band_rescore(&H64, p->k, p->sweeps, p->omega, sx0, nc, cand, su, sv, w64, (const float *)score, ksel, tau_h,
-                     p->band, sel, rep, A, s);
+        band_rescore(&G64.H, q->k, q->sweeps, q->omega, sx0, nc, cand, su, sv, w64, (const float *)score, ksel,
+                     tau_h, q->band, sel, rep, A, s);
     }
     hipLaunchKernelGGL(k_keep_init, dim3(grid_for(m, 256)), dim3(256), 0, s, m, base, keep);
     SFG_LAUNCH_CHECK();
