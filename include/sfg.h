@@ -569,6 +569,9 @@ typedef struct {
                              either.  Results are bit-identical either way: rows keep their entry order */
     int64_t n_scored;      /* candidates scored exactly (n_cand, or the surrogate's share) */
     int32_t surrogate_fallback;   /* a surrogate was given but was not usable: the plain path ran */
+    int32_t sweeps_per_pass;      /* Jacobi sweeps the level's scoring smoothing took per pass over the block: 1,
+                                     or 2 to 4 when the level was swept in the tree's preorder and
+                                     sfg_smooth_ordered's passes paid (same bits either way) */
 } sfg_level_report;
 
 typedef struct {

@@ -43,6 +43,10 @@ void level_node_order(int64_t n, int64_t m, const int32_t *u, const int32_t *v, 
                       const uint8_t *tree, int32_t k, sfg_dtype storage, NodeOrder *no, DevArena &A, hipStream_t s);
 sfg_csr relabel_csr(const sfg_csr *H, const int32_t *order, const int32_t *inv, DevArena &A, hipStream_t s);
 void gather_block(int64_t n, int32_t k, const int32_t *order, const double *src, double *dst, hipStream_t s);
+size_t smooth_ordered_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
+int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps, double omega,
+                   const double *x0, sfg_dtype storage, int32_t final_f32, void *x, void *ws, size_t ws_bytes,
+                   hipStream_t s, int32_t max_row);
 void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const double *w64, const float *w32,
                  const uint8_t *base, const sfg_params *p, const double *x0, uint8_t *keep, sfg_level_report *rep,
                  DevArena &A, hipStream_t s, int64_t k_take, NodeOrder *no);
@@ -466,7 +470,13 @@ void multilevel_sparsify(int64_t n, int64_t m, const int32_t *u, const int32_t *
             au = no.u;
             av = no.v;
         }
-        smooth(&Gs, p->k, p->sweeps, p->omega, xl, vt, 0, x, A.raw(wss), wss, s, max_row);
+        if (no.use) {
+            // in the tree's preorder the sweeps may take several per pass (where they pay; same bits)
+            const size_t wso = smooth_ordered_workspace_bytes(F.n, p->k, vt);
+            smooth_ordered(&Gs, nullptr, p->k, p->sweeps, p->omega, xl, vt, 0, x, A.raw(wso), wso, s, max_row);
+        } else {
+            smooth(&Gs, p->k, p->sweeps, p->omega, xl, vt, 0, x, A.raw(wss), wss, s, max_row);
+        }
         void *aff = A.raw((F.m + 1) * dtype_size(vt));
         const size_t wsa = affinity_workspace_bytes(F.n, p->k);
         affinity(x, vt, F.n, p->k, F.m, au, av, aff, vt, A.raw(wsa), wsa, s);

@@ -880,7 +880,7 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
         next = s0;
         full = 0;
     }
-    const int32_t p = lane < s0 ? order[base + lane] : -1;
+    const int32_t p = lane < s0 ? (order ? order[base + lane] : (int32_t)(base + lane)) : -1;
     const bool bad = lane < s0 && (p < 0 || p >= n);
     bool over = __ballot(bad) != 0ull;
     __syncthreads();
@@ -1483,6 +1483,11 @@ int32_t read_flag(const MpkPlan &mp, hipStream_t s) {
 // against 2.85; BF16 4 vectors, 10 sweeps (a step of the surrogate's) 6.68
 // against 6.25.  Setting SFG_SWEEP_HOPS takes the passes at any width.
 constexpr int64_t kMpkMinBytes = 640;
+// Graphs averaging more entries per row than this (whole meshes, power-law
+// graphs) have 1-hop halos beyond the layout's capacities for 64-row blocks:
+// they go to the plain path without trying a layout (SFG_SWEEP_HOPS still
+// forces the try).
+constexpr int64_t kMpkMaxEntriesPerRow = 4;
 
 // Hops are tried from SFG_SWEEP_HOPS (2, 3 or 4; default 2 in FP64, 3 in
 // FP32) down to 2 until every block's layout fits.  Measured on the 200^3
@@ -1492,10 +1497,13 @@ constexpr int64_t kMpkMinBytes = 640;
 // 152-163 us with 3 hops, 177 with 2, 174 with 4.
 int default_hops(sfg_dtype storage) { return storage == SFG_F64 ? 2 : 3; }
 
+// order == nullptr: the rows' own numbering (a graph already relabelled
+// into a locality order).  max_row as for smooth() (the plain path's FP64 hub
+// rows).
 int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps, double omega,
                    const double *x0, sfg_dtype storage, int32_t final_f32, void *x, void *ws, size_t ws_bytes,
-                   hipStream_t s) {
-    SFG_REQUIRE(H && order, SFG_EINVAL, "smooth_ordered: null pointer");
+                   hipStream_t s, int32_t max_row) {
+    SFG_REQUIRE(H, SFG_EINVAL, "smooth_ordered: null pointer");
     SFG_REQUIRE(H->n >= 1, SFG_EINVAL, "smooth_ordered: empty graph");
     SFG_REQUIRE(ws_bytes >= smooth_ordered_workspace_bytes(H->n, k < 1 ? 1 : k, storage), SFG_EWORKSPACE,
                 "smooth_ordered: workspace too small");
@@ -1506,7 +1514,8 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
     const size_t sx = dtype_size(storage);
     const int want = env_int("SFG_SWEEP_HOPS", default_hops(storage));
     const bool pays = getenv("SFG_SWEEP_HOPS") != nullptr ||
-                      (int64_t)sweeps * k * (int64_t)dtype_size(storage) >= kMpkMinBytes;
+                      ((int64_t)sweeps * k * (int64_t)dtype_size(storage) >= kMpkMinBytes &&
+                       H->nnz <= kMpkMaxEntriesPerRow * H->n);
     // FP64 storage on FP64 weights; FP32, FP16, BF16 storage on FP32 weights (as sfg_smooth); 16-bit rows up
     // to 16 columns
     const bool types_ok = storage == SFG_F64 ? H->vt == SFG_F64
@@ -1518,10 +1527,12 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
     int hops = 0;
     if (shape_ok) {
         // the passes take the rows in this order: it must be a permutation of the nodes
-        fill_i32(mp.seen, n, 0, s);
         fill_i32(mp.flag, 1, 0, s);
-        hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
-        SFG_LAUNCH_CHECK();
+        if (order) {
+            fill_i32(mp.seen, n, 0, s);
+            hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
+            SFG_LAUNCH_CHECK();
+        }
         for (int h = want < kMpkMaxHops ? want : kMpkMaxHops; h >= 2 && hops == 0; --h) {
             if (h == 4) build_layout<4>(H, order, mp, nb, s);
             else if (h == 3) build_layout<3>(H, order, mp, nb, s);
@@ -1535,7 +1546,7 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
     if (hops == 0) {
         // the workspace starts with the plain smoothing's layout
         smooth(H, k, sweeps, omega, x0, storage, final_f32, x, ws, smooth_workspace_bytes(n, k < 1 ? 1 : k, storage),
-               s, -1);
+               s, max_row);
         return 1;
     }
     SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_ordered: omega must be in (0, 1]");
@@ -1568,8 +1579,9 @@ extern "C" sfg_status sfg_smooth_ordered(const sfg_csr *H, const int32_t *order,
                                          double omega, const double *x0, sfg_dtype storage, int32_t final_f32,
                                          void *x, int32_t *per_pass_out, void *ws, size_t ws_bytes, void *stream) {
     return sfg::guard([&] {
+        SFG_REQUIRE(order, SFG_EINVAL, "smooth_ordered: null order");
         const int used = sfg::smooth_ordered(H, order, k, sweeps, omega, x0, storage, final_f32, x, ws, ws_bytes,
-                                             sfg::as_stream(stream));
+                                             sfg::as_stream(stream), -1);
         if (per_pass_out) *per_pass_out = used;
     });
 }

@@ -43,6 +43,10 @@ size_t affinity_workspace_bytes(int64_t n, int32_t k);
 size_t coarsen_workspace_bytes(int64_t n, int64_t m);
 size_t mpnn_forward_workspace_bytes(int64_t n, sfg_dtype act);
 size_t mpnn_train_workspace_bytes(int64_t n, int64_t ne);
+size_t smooth_ordered_workspace_bytes(int64_t n, int32_t k, sfg_dtype storage);
+int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sweeps, double omega,
+                   const double *x0, sfg_dtype storage, int32_t final_f32, void *x, void *ws, size_t ws_bytes,
+                   hipStream_t s, int32_t max_row);
 double predicted_cone_share(const sfg_csr *H, int32_t sweeps, int64_t n_cand, const int32_t *cand,
                             const int32_t *u, const int32_t *v, double band, double limit, DevArena &A,
                             hipStream_t s);
@@ -518,7 +522,9 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
     const bool f32last = q->final_f32 && (q->storage == SFG_F16 || q->storage == SFG_BF16);
     const sfg_dtype xt = f32last ? SFG_F32 : q->storage;
     void *x = A.raw((size_t)n * q->k * dtype_size(xt));
-    size_t wss = smooth_workspace_bytes(n, q->k, q->storage);
+    // in the tree's preorder the Jacobi sweeps can take several per pass (smooth_ordered decides, same bits)
+    const bool passes = no && no->use && q->smoother == SFG_SMOOTH_JACOBI;
+    size_t wss = passes ? smooth_ordered_workspace_bytes(n, q->k, q->storage) : smooth_workspace_bytes(n, q->k, q->storage);
     void *wsm = A.raw(wss);
     float ms_other = tm.stop();
     tm.start();
@@ -529,6 +535,10 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
         std::vector<int32_t> class_ptr;
         color_graph(&H, color, class_rows, class_ptr, A.raw(wsc), wsc, s);
         smooth_gs(&H, q->k, q->sweeps, q->omega, sx0, q->storage, class_rows, class_ptr, x, wsm, wss, s);
+    } else if (passes) {
+        const int per_pass = smooth_ordered(&H, nullptr, q->k, q->sweeps, q->omega, sx0, q->storage, q->final_f32, x,
+                                            wsm, wss, s, G.max_row);
+        if (rep) rep->sweeps_per_pass = per_pass;
     } else {
         smooth(&H, q->k, q->sweeps, q->omega, sx0, q->storage, q->final_f32, x, wsm, wss, s, G.max_row);
     }
@@ -567,6 +577,7 @@ void score_level(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const
         rep->precision_fallback = fallback ? 1 : 0;
         rep->node_order = (no && no->use) ? 1 : 0;
         rep->n_scored = nc;
+        if (!passes) rep->sweeps_per_pass = 1;
     }
     if (!f64 && q->band > 0.0 && ksel > 0 && ksel < nc) {
         // precision form: FP64 re-scoring of the edges near the threshold

@@ -102,7 +102,8 @@ class LevelReport(ctypes.Structure):
                 ("band_above", ctypes.c_int64), ("band_rounds", ctypes.c_int32),
                 ("ms_smooth", ctypes.c_float), ("ms_score", ctypes.c_float), ("ms_select", ctypes.c_float),
                 ("ms_other", ctypes.c_float), ("cone_rows", ctypes.c_int64), ("precision_fallback", ctypes.c_int32),
-                ("node_order", ctypes.c_int32), ("n_scored", ctypes.c_int64), ("surrogate_fallback", ctypes.c_int32)]
+                ("node_order", ctypes.c_int32), ("n_scored", ctypes.c_int64), ("surrogate_fallback", ctypes.c_int32),
+                ("sweeps_per_pass", ctypes.c_int32)]
 
 
 class Report(ctypes.Structure):

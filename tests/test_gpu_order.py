@@ -72,6 +72,12 @@ def test_preorder_matches_oracle(S, orc, graph, embed, monkeypatch):
     p = S.make_params(k=k, sweeps=T, frac=f, embed=S.EMBED_GRAPH if embed == "graph" else S.EMBED_SPARSIFIER)
     keep, rep = run(S, g, X0, p, "1", monkeypatch)
     assert rep[0]["node_order"] == 1
+    # in the preorder the tree embedding's FP64 sweeps run two per pass (sfg_smooth_ordered's passes) on the
+    # grid-like trees; a row beyond the layout (the star's hub) or a larger neighbourhood (the random trees) may
+    # send a level to one sweep per launch; the bits are the same either way
+    if embed == "sparsifier":
+        want = (2,) if g.name.startswith(("powergrid", "mesh", "grid")) else (1, 2)
+        assert rep[0]["sweeps_per_pass"] in want, g.name
     assert np.array_equal(keep, ref.keep)
     lr = ref.levels[0]
     assert rep[0]["n_cand"] == lr.n_cand and rep[0]["k_sel"] == lr.k_sel
