@@ -992,17 +992,45 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     if (lane == kMpkMeta - 1) L.meta[kMpkMeta * b + lane] = nent;
 }
 
-// LDS of one pass workgroup: X of every slot for KC columns, nodes, local CSR.
-template <int H, int KC, typename TX, typename TW>
+// LDS of one pass workgroup holding up to `slots` slots: X of every slot for
+// KC columns, the slot nodes, the local CSR of up to min(rows, slots) rows.
+constexpr int mpk_lds_bytes(int slots, int rows, int ent, int colb, int kc, int sx, int sw) {
+    const int r = rows < slots ? rows : slots;
+    return slots * (kc * sx + 4) + ent * (sw + colb) + r * sw + (r + 1) * 2;
+}
+template <int H, int KC, int KS, typename TX, typename TW>
 constexpr int mpk_pass_lds() {
     using C = MpkCaps<H>;
-    return C::kSlots * KC * (int)sizeof(TX) + C::kSlots * 4 + C::kEnt * ((int)sizeof(TW) + (int)sizeof(typename C::Col)) +
-           C::kRows * (int)sizeof(TW) + (C::kRows + 1) * 2;
+    return mpk_lds_bytes(KS, C::kRows, C::kEnt, (int)sizeof(typename C::Col), KC, (int)sizeof(TX), (int)sizeof(TW));
 }
-template <int H, int KC, typename TX, typename TW>
+template <int H, int KC, int KS, typename TX, typename TW>
 constexpr int mpk_pass_waves() {
     // workgroups of 4 waves a CU's 160 KB of LDS holds = waves per SIMD (registers are held to it)
-    return 163840 / mpk_pass_lds<H, KC, TX, TW>() > 8 ? 8 : 163840 / mpk_pass_lds<H, KC, TX, TW>();
+    return 163840 / mpk_pass_lds<H, KC, KS, TX, TW>() > 8 ? 8 : 163840 / mpk_pass_lds<H, KC, KS, TX, TW>();
+}
+// Slot capacity of the common-case pass kernel: the most slots whose LDS lets
+// eight workgroups share a CU (20,000 bytes each), at most the layout's.
+// Blocks with more slots (a fraction of a percent on the 200^3 mesh's tree)
+// go to a second launch at the full capacity.
+constexpr int mpk_small_slots(int slots, int rows, int ent, int colb, int kc, int sx, int sw) {
+    int ks = slots;
+    while (ks > 64 && mpk_lds_bytes(ks, rows, ent, colb, kc, sx, sw) > 20000) --ks;
+    return ks;
+}
+template <int H, int KC, typename TX, typename TW>
+constexpr int mpk_small_slots() {
+    using C = MpkCaps<H>;
+    return mpk_small_slots(C::kSlots, C::kRows, C::kEnt, (int)sizeof(typename C::Col), KC, (int)sizeof(TX),
+                           (int)sizeof(TW));
+}
+
+// Blocks of a layout for H hops whose slots exceed ks, listed for the
+// full-capacity launch (order irrelevant: each block writes its own rows).
+template <int H>
+__global__ void k_mpk_big(int64_t nb, const int32_t *__restrict__ meta, int32_t ks, int32_t *list, int32_t *cnt) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nb) return;
+    if (meta[kMpkMeta * b + H] > ks) list[atomicAdd(cnt, 1)] = (int32_t)b;
 }
 
 // m sweeps of KC columns of one block (see above), 1 <= m <= H: workgroup w
@@ -1017,32 +1045,38 @@ constexpr int mpk_pass_waves() {
 // workgroups of one XCD, so its layout is fetched once into that XCD's L2.
 // Two dependent rounds of global loads: the block's sizes and slot nodes,
 // then X of the slots and the local CSR.
-template <int H, int KC, typename TIN, typename TX, typename TO, typename TW, typename TA, int VPL, bool CENTER>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mpk_pass_waves<H, KC, TX, TW>()))) void
-k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const double *__restrict__ mean,
-             TO *__restrict__ y, TA keep, TA omega) {
+// KS: the slots this variant holds.  LISTED = false: every block, skipping
+// those with more than KS slots; LISTED = true: the blocks of list[] only.
+template <int H, int KC, int KS, bool LISTED, typename TIN, typename TX, typename TO, typename TW, typename TA,
+          int VPL, bool CENTER>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mpk_pass_waves<H, KC, KS, TX, TW>()))) void
+k_sweep_pass(int32_t k, int32_t m, MpkDev L, const int32_t *__restrict__ list, const TIN *__restrict__ x,
+             const double *__restrict__ mean, TO *__restrict__ y, TA keep, TA omega) {
     using C = MpkCaps<H>;
     using Col = typename C::Col;
+    constexpr int RK = C::kRows < KS ? C::kRows : KS;   // rows of L0..L(H-1) fit within the slots
     constexpr int LPR = KC / VPL;              // lanes per row
     constexpr int RPP = 256 / LPR;             // rows a pass
-    constexpr int kSlotPasses = (C::kSlots + RPP - 1) / RPP;
-    constexpr int kRowPasses = (C::kRows + RPP - 1) / RPP;
+    constexpr int kSlotPasses = (KS + RPP - 1) / RPP;
+    constexpr int kRowPasses = (RK + RPP - 1) / RPP;
     constexpr int kStage = kSlotPasses < 4 ? kSlotPasses : 4;
-    __shared__ __align__(16) TX xs[C::kSlots * KC];
-    __shared__ int32_t nodes[C::kSlots];
+    __shared__ __align__(16) TX xs[KS * KC];
+    __shared__ int32_t nodes[KS];
     __shared__ TW lval[C::kEnt];
-    __shared__ TW ldeg[C::kRows];
-    __shared__ uint16_t rowoff[C::kRows + 1];
+    __shared__ TW ldeg[RK];
+    __shared__ uint16_t rowoff[RK + 1];
     __shared__ Col lcol[C::kEnt];
     const int groups = k / KC;
-    const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t b = w / groups;
-    const int g0 = (int)(w - b * groups) * KC;
+    const uint32_t w = LISTED ? blockIdx.x : xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t item_b = w / groups;
+    const int64_t b = LISTED ? list[item_b] : item_b;
+    const int g0 = (int)(w - item_b * groups) * KC;
     const int t = threadIdx.x;
     const int32_t *mp = L.meta + kMpkMeta * b;
     int ends[H + 1];
 #pragma unroll
     for (int h = 0; h <= H; ++h) ends[h] = mp[h];
+    if (!LISTED && KS < C::kSlots && ends[H] > KS) return;   // the full-capacity launch takes this block
     const int ne = mp[kMpkMeta - 1];
     int S = ends[H], R = ends[H - 1];
 #pragma unroll
@@ -1052,8 +1086,8 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const do
             R = ends[h - 1];
         }
     const int s0 = ends[0];
-    // round 1: slot nodes (read to capacity, used to S)
-    for (int i = t; i < C::kSlots; i += 256) nodes[i] = L.node[b * C::kSlots + i];
+    // round 1: slot nodes (read to this variant's capacity, used to S)
+    for (int i = t; i < KS; i += 256) nodes[i] = L.node[b * C::kSlots + i];
     // round 2 issued early: the local CSR into registers
     constexpr int kEntPer = (C::kEnt + 255) / 256;
     Col ec[kEntPer];
@@ -1066,7 +1100,7 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const TIN *__restrict__ x, const do
             ev[j] = ((const TW *)L.lval)[b * C::kEnt + i];
         }
     }
-    constexpr int kRowPer = (C::kRows + 1 + 255) / 256;
+    constexpr int kRowPer = (RK + 1 + 255) / 256;
     uint16_t ro[kRowPer];
     TW dg[kRowPer];
 #pragma unroll
@@ -1329,7 +1363,10 @@ void smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega, const dou
 // Several sweeps per pass in a caller's row order (see k_sweep_pass).
 struct MpkPlan {
     MpkDev dev;
-    int32_t *seen, *flag;
+    int32_t *seen, *flag;    // flag[1]: the number of blocks listed in big
+    int32_t *big;
+    int64_t nbig = 0;        // host copy of flag[1]
+    int32_t small_slots = 0; // slots of the common-case launch (the layout's capacity: no second launch)
 };
 
 int64_t mpk_blocks(int64_t n) { return (n + kMpkRows - 1) / kMpkRows; }
@@ -1346,7 +1383,8 @@ MpkPlan plan_mpk(Carver &c, int64_t n, size_t sw) {
     p.dev.lval = c.take<char>(nb * C::kEnt * sw);
     p.dev.ldeg = c.take<char>(nb * C::kRows * sw);
     p.seen = c.take<int32_t>(n + 1);
-    p.flag = c.take<int32_t>(1);
+    p.flag = c.take<int32_t>(2);
+    p.big = c.take<int32_t>(nb);
     return p;
 }
 
@@ -1372,16 +1410,48 @@ int pass_cols(int32_t k) {
 }
 
 // Weights and arithmetic: FP64 for FP64 storage, FP32 otherwise (as sfg_smooth).
+// The common-case launch over every block at the small capacity, then the
+// blocks over it at the layout's full capacity.
 template <int H, int KC, typename TX, typename TO, bool CENTER>
 void launch_pass_kc(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TO *y,
                     double omega, hipStream_t s) {
     using TIN = typename std::conditional<CENTER, double, TX>::type;
     using TA = typename std::conditional<sizeof(TX) == 8, double, float>::type;
+    constexpr int KS = mpk_small_slots<H, KC, TX, TA>();
+    constexpr int KF = MpkCaps<H>::kSlots;
     const int64_t items = nb * (k / KC);
     SFG_REQUIRE(items <= 0x7fffffff, SFG_EUNSUPPORTED, "smooth_ordered: too many blocks");
-    hipLaunchKernelGGL((k_sweep_pass<H, KC, TIN, TX, TO, TA, TA, 4, CENTER>), dim3((uint32_t)items), dim3(256), 0, s,
-                       k, m, mp.dev, (const TIN *)x, mean, y, (TA)(1.0 - omega), (TA)omega);
+    SFG_REQUIRE(mp.small_slots == KS, SFG_EUNSUPPORTED, "smooth_ordered: layout listed for another capacity");
+    hipLaunchKernelGGL((k_sweep_pass<H, KC, KS, false, TIN, TX, TO, TA, TA, 4, CENTER>), dim3((uint32_t)items),
+                       dim3(256), 0, s, k, m, mp.dev, nullptr, (const TIN *)x, mean, y, (TA)(1.0 - omega), (TA)omega);
     SFG_LAUNCH_CHECK();
+    if constexpr (KS < KF) {
+        if (mp.nbig > 0) {
+            hipLaunchKernelGGL((k_sweep_pass<H, KC, KF, true, TIN, TX, TO, TA, TA, 4, CENTER>),
+                               dim3((uint32_t)(mp.nbig * (k / KC))), dim3(256), 0, s, k, m, mp.dev, mp.big,
+                               (const TIN *)x, mean, y, (TA)(1.0 - omega), (TA)omega);
+            SFG_LAUNCH_CHECK();
+        }
+    }
+}
+
+// Slots of the common-case launch for this storage, k and hop count (the
+// same constant launch_pass_kc instantiates).
+template <int H, typename TX>
+int small_slots_for(int32_t k) {
+    using TA = typename std::conditional<sizeof(TX) == 8, double, float>::type;
+    using C = MpkCaps<H>;
+    return mpk_small_slots(C::kSlots, C::kRows, C::kEnt, (int)sizeof(typename C::Col), pass_cols<TX>(k),
+                           (int)sizeof(TX), (int)sizeof(TA));
+}
+
+template <int H>
+int small_slots(sfg_dtype storage, int32_t k) {
+    switch (storage) {
+        case SFG_F64: return small_slots_for<H, double>(k);
+        case SFG_F32: return small_slots_for<H, float>(k);
+        default: return small_slots_for<H, __half>(k);
+    }
 }
 
 template <int H, typename TX, typename TO, bool CENTER>
@@ -1463,12 +1533,24 @@ void build_layout(const sfg_csr *G, const int32_t *order, const MpkPlan &mp, int
     SFG_LAUNCH_CHECK();
 }
 
-int32_t read_flag(const MpkPlan &mp, hipStream_t s) {
-    int32_t flag = 0;
-    SFG_HIP(hipMemcpyAsync(&flag, mp.flag, sizeof(flag), hipMemcpyDeviceToHost, s));
+int32_t read_flag(MpkPlan &mp, hipStream_t s) {
+    int32_t h[2] = {0, 0};
+    SFG_HIP(hipMemcpyAsync(h, mp.flag, sizeof(h), hipMemcpyDeviceToHost, s));
     SFG_HIP(hipStreamSynchronize(s));
-    SFG_REQUIRE(!(flag & 1), SFG_EINVAL, "smooth_ordered: order is not a permutation of the nodes");
-    return flag;
+    SFG_REQUIRE(!(h[0] & 1), SFG_EINVAL, "smooth_ordered: order is not a permutation of the nodes");
+    mp.nbig = h[1];
+    return h[0];
+}
+
+// Lists the blocks over the common-case capacity (flag[1] counts them).
+template <int H>
+void list_big(MpkPlan &mp, int64_t nb, sfg_dtype storage, int32_t k, hipStream_t s) {
+    mp.small_slots = small_slots<H>(storage, k);
+    if (mp.small_slots < MpkCaps<H>::kSlots) {
+        hipLaunchKernelGGL(k_mpk_big<H>, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, mp.dev.meta, mp.small_slots,
+                           mp.big, mp.flag + 1);
+        SFG_LAUNCH_CHECK();
+    }
 }
 
 }  // namespace
@@ -1527,18 +1609,25 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
     int hops = 0;
     if (shape_ok) {
         // the passes take the rows in this order: it must be a permutation of the nodes
-        fill_i32(mp.flag, 1, 0, s);
+        fill_i32(mp.flag, 2, 0, s);
         if (order) {
             fill_i32(mp.seen, n, 0, s);
             hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
             SFG_LAUNCH_CHECK();
         }
         for (int h = want < kMpkMaxHops ? want : kMpkMaxHops; h >= 2 && hops == 0; --h) {
-            if (h == 4) build_layout<4>(H, order, mp, nb, s);
-            else if (h == 3) build_layout<3>(H, order, mp, nb, s);
-            else build_layout<2>(H, order, mp, nb, s);
+            if (h == 4) {
+                build_layout<4>(H, order, mp, nb, s);
+                list_big<4>(mp, nb, storage, k, s);
+            } else if (h == 3) {
+                build_layout<3>(H, order, mp, nb, s);
+                list_big<3>(mp, nb, storage, k, s);
+            } else {
+                build_layout<2>(H, order, mp, nb, s);
+                list_big<2>(mp, nb, storage, k, s);
+            }
             if (read_flag(mp, s) & 2)
-                fill_i32(mp.flag, 1, 0, s);     // a block did not fit: fewer hops
+                fill_i32(mp.flag, 2, 0, s);     // a block did not fit: fewer hops
             else
                 hops = h;
         }
