@@ -361,6 +361,8 @@ __global__ __launch_bounds__(256) void k_sweep_hub64(int32_t kw, int32_t ldx, in
                                                      TO *__restrict__ y, double keep, double omega) {
     __shared__ double sx[kHubLds];
     __shared__ double sw[256];
+    __shared__ int32_t sc[256];
+    constexpr int kPer = kHubLds / 256;    // values a thread stages per chunk
     const int chunk = kHubLds / kw < 256 ? kHubLds / kw : 256;
     const int t = threadIdx.x;
     const int32_t cnt = *hub_cnt;
@@ -372,14 +374,30 @@ __global__ __launch_bounds__(256) void k_sweep_hub64(int32_t kw, int32_t ldx, in
         double acc = 0.0;
         for (int32_t jc = j0; jc < j1; jc += chunk) {
             const int32_t len = (j1 - jc) < chunk ? (j1 - jc) : chunk;
-            for (int32_t i = t; i < len * kw; i += 256) {
-                const int32_t e = i / kw, c = i - e * kw;
-                double v[1];
-                const double m1[1] = {CENTER ? mean[c] : 0.0};
-                load_row<TIN, TX, double, 1, CENTER>(x + (int64_t)col[jc + e] * ldx + c, m1, v);
-                sx[i] = v[0];
+            // the chunk's columns and weights, then its neighbour values: every thread's loads in flight
+            // before its LDS stores
+            if (t < len) {
+                sc[t] = col[jc + t];
+                sw[t] = val[jc + t];
             }
-            for (int32_t e = t; e < len; e += 256) sw[e] = val[jc + e];
+            __syncthreads();
+            double vv[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int32_t i = t + 256 * q;
+                if (i < len * kw) {
+                    const int32_t e = i / kw, c = i - e * kw;
+                    double v[1];
+                    const double m1[1] = {CENTER ? mean[c] : 0.0};
+                    load_row<TIN, TX, double, 1, CENTER>(x + (int64_t)sc[e] * ldx + c, m1, v);
+                    vv[q] = v[0];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int32_t i = t + 256 * q;
+                if (i < len * kw) sx[i] = vv[q];
+            }
             __syncthreads();
             if (t < kw) {
                 // entry order kept: products (independent of acc) read ahead, then the dependent adds
