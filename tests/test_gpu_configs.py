@@ -1,6 +1,7 @@
 """Parity at the full sizes of the 3-D mesh workload (200^3: 8,000,000 nodes,
 23,880,000 edges, 16 vectors, 20 sweeps, 10%) in the launch configuration the
-benchmark times, and of a 1M-node Chung-Lu graph through the 5-level hierarchy
+benchmark times (two FP64 sweeps per pass in the spanning tree's preorder,
+three in FP32), and of a 1M-node Chung-Lu graph through the 5-level hierarchy
 of Alg. 1.  The oracle runs each whole computation on the CPU (about a minute
 each); its results are shared by the tests of a module."""
 import numpy as np
@@ -38,9 +39,12 @@ def mesh(orc):
     return g, prm, X0, ref
 
 
-def test_mesh200_full_size_f64_identical(S, orc, mesh):
+@pytest.mark.parametrize("passes", [True, False])
+def test_mesh200_full_size_f64_identical(S, orc, mesh, passes):
     """The benchmark's step (tree CSR, FP64 smoothing of the 16-vector block, scores, selection): every one of
-    the 15,880,001 scores bit for bit, the selected set and the threshold."""
+    the 15,880,001 scores bit for bit, the selected set and the threshold.  passes: the smoothing as the
+    benchmark times it, two sweeps per pass in the tree's preorder (sfg_smooth_ordered); else one sweep per
+    launch in node order (--single-sweep)."""
     g, prm, X0, ref = mesh
     u, v, w = dev(g.u), dev(g.v), dev(g.w)
     tree, comps = S.sfg_spanning_tree(g.n, u, v, w)
@@ -49,7 +53,13 @@ def test_mesh200_full_size_f64_identical(S, orc, mesh):
     lr = ref.levels[0]
     assert np.array_equal(cand.cpu().numpy(), lr.cand)
     H = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
-    X = S.sfg_smooth(H, dev(X0), prm["sweeps"], 0.5, storage=torch.float64)
+    if passes:
+        order = S.sfg_tree_order(g.n, u, v, w, tree).order
+        info = {}
+        X = S.sfg_smooth_ordered(H, order, dev(X0), prm["sweeps"], 0.5, storage=torch.float64, info=info)
+        assert info["sweeps_per_pass"] == 2
+    else:
+        X = S.sfg_smooth(H, dev(X0), prm["sweeps"], 0.5, storage=torch.float64)
     s = S.sfg_edge_scores(X, u, v, w, cand=cand)
     assert np.array_equal(s.cpu().numpy(), lr.score)
     k = orc.ksel(prm["frac"], int(cand.numel()))
@@ -68,7 +78,11 @@ def test_mesh200_full_size_f32_close(S, orc, mesh):
     tree, _ = S.sfg_spanning_tree(g.n, u, v, w64)
     cand = torch.nonzero(tree == 0).reshape(-1).to(torch.int32)
     H = S.sfg_laplacian_csr(g.n, u, v, w32, mask=tree)
-    X = S.sfg_smooth(H, dev(X0), prm["sweeps"], 0.5, storage=torch.float32)
+    # as the benchmark's FP32 pass: three sweeps per pass in the tree's preorder (the same bits as sfg_smooth)
+    order = S.sfg_tree_order(g.n, u, v, w64, tree).order
+    info = {}
+    X = S.sfg_smooth_ordered(H, order, dev(X0), prm["sweeps"], 0.5, storage=torch.float32, info=info)
+    assert info["sweeps_per_pass"] == 3
     s = S.sfg_edge_scores(X, u, v, w32, cand=cand)
     err = orc.score_errors(s.cpu().numpy().astype(np.float64), lr.score, lr.tau)
     assert err["max_abs_over_tau"] < 1e-4, err
