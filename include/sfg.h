@@ -296,7 +296,7 @@ sfg_status sfg_select_topk(const void *score, sfg_dtype st, int64_t ne, int64_t 
  * that cannot allocate device memory: code under HIP graph capture, tight
  * serving loops, harnesses that forbid hipMalloc.  Same arguments (minus the
  * workspace), same kernels, same results.  Its scratch (selection state,
- * digit histogram, tie flags and ranks, scan partials) is a device array of
+ * digit histogram, the keys a radix pass copies, per-tile tie counts) is a device array of
  * 128 MiB (134217728 bytes) in the library, one copy per GPU, held from the
  * first call on that GPU until the process ends.  The first call on a device
  * looks up that copy's address (hipGetSymbolAddress) with the device current;

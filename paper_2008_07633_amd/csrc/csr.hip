@@ -7,14 +7,18 @@
 // sorted by (u, v), ascending column order inside a row is ascending edge id
 // order, and the degree is summed in that order in FP64.
 //
-//  1. the edge-list slice of every row by binary search over u (no atomics,
-//     so hub rows cost nothing extra); with a mask, a scan of it
-//  2. lower-part counts (integer atomics on v) and one scan: rowptr
-//  3. upper entries: one thread per edge writes its slot directly, and drops
-//     the edge id into the lower part of its other row (atomic slot)
-//  4. lower entries: every row's lower part is ordered by edge id: a thread per short row
-//     ranks its ids (rank = number of smaller ids), a workgroup per long row
-//     bitonic-sorts the segment in LDS; both write col/val/eid
+//  1. the edge-list slice of every row (its upper edges) by one coalesced
+//     pass over u
+//  2. a thread per row walks its slice: it counts its included upper edges
+//     and adds one to the lower count of each one's other end (integer
+//     atomics); slices over kWalk edges are walked by a wavefront instead;
+//     one scan of the row totals gives rowptr
+//  3. the same walk again: the row writes its upper entries in place, in
+//     order, and drops each edge into the lower part of its other row at an
+//     atomic slot (column, weight and id written there)
+//  4. lower parts of two or more entries are put in edge-id order: a thread
+//     per row ranks up to kRegSeg entries in registers, a workgroup per longer
+//     row bitonic-sorts the ids in LDS
 //  5. one thread per row sums its weights in column order, in FP64; rows
 //     over 256 entries (hubs) are staged through LDS by a wavefront and
 //     summed by one of its lanes in the same order
@@ -24,32 +28,35 @@ namespace sfg {
 
 namespace {
 
-constexpr int kShortSeg = 32;       // lower parts up to this length: one thread
+constexpr int kWalk = 64;           // upper slices longer than this: walked by a wavefront
+constexpr int kRegSeg = 8;          // lower parts up to this length: ranked in registers by one thread
 constexpr int kLdsSeg = 8192;       // longer ones are sorted in LDS up to this length
 constexpr int kDegLong = 256;       // rows longer than this: degree summed by a workgroup
 
 struct CsrPlan {
-    int32_t *estart, *inc, *incpos, *cnt_lo, *tot, *fill, *tmp, *long_rows, *long_cnt, *deg_rows, *deg_cnt, *scan;
-    int32_t *zeroed;      // cnt_lo, fill, long_cnt, deg_cnt: one contiguous range, cleared by one fill
+    int32_t *estart, *up, *cnt_lo, *tot, *fill, *tmp, *walk_rows, *walk_cnt, *long_rows, *long_cnt, *deg_rows,
+        *deg_cnt, *scan;
+    int32_t *zeroed;      // cnt_lo, fill, the three list counters: one contiguous range, cleared by one fill
     int64_t zeroed_len;
 };
 
 CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
     CsrPlan p;
     p.estart = c.take<int32_t>(n + 1);
-    p.inc = c.take<int32_t>(m + 1);
-    p.incpos = c.take<int32_t>(m + 1);
-    p.zeroed_len = 2 * (n + 1) + 2;
+    p.up = c.take<int32_t>(n + 1);
+    p.zeroed_len = 2 * (n + 1) + 3;
     p.zeroed = c.take<int32_t>(p.zeroed_len);
     p.cnt_lo = p.zeroed;
     p.fill = p.zeroed + (n + 1);
-    p.long_cnt = p.zeroed + 2 * (n + 1);
-    p.deg_cnt = p.long_cnt + 1;
+    p.walk_cnt = p.zeroed + 2 * (n + 1);
+    p.long_cnt = p.walk_cnt + 1;
+    p.deg_cnt = p.walk_cnt + 2;
     p.tot = c.take<int32_t>(n + 1);
     p.tmp = c.take<int32_t>(2 * m + 1);
+    p.walk_rows = c.take<int32_t>(n + 1);
     p.long_rows = c.take<int32_t>(n + 1);
     p.deg_rows = c.take<int32_t>(n + 1);
-    p.scan = c.take<int32_t>(scan_scratch_ints((n > m ? n : m) + 1));
+    p.scan = c.take<int32_t>(scan_scratch_ints(n + 1));
     return p;
 }
 
@@ -58,7 +65,7 @@ CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
 // exactly the p in (u[e-1], u[e]]: one coalesced pass over the edges.  The
 // range is clamped to [0, n], so an unsorted list cannot write out of bounds.
 __global__ void k_estart(int64_t n, int64_t m, const int32_t *__restrict__ u, int32_t *estart) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (e > m) return;
     int64_t lo = e == 0 ? 0 : (int64_t)u[e - 1] + 1;
     int64_t hi = e == m ? n : (int64_t)u[e];
@@ -67,79 +74,208 @@ __global__ void k_estart(int64_t n, int64_t m, const int32_t *__restrict__ u, in
     for (int64_t p = lo; p <= hi; ++p) estart[p] = (int32_t)e;
 }
 
-// Mask flags for the scan of included edges, and (like k_count_lo) the
-// lower-part count of every row, in one pass over the edges.
-__global__ void k_inc_count(int64_t m, const int32_t *__restrict__ v, const uint8_t *__restrict__ mask, int32_t *inc,
-                            int32_t *cnt_lo) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    const bool in = mask[e] != 0;
-    inc[e] = in ? 1 : 0;
-    if (in) atomicAdd(&cnt_lo[v[e]], 1);
+// Row p's slice of the edge list, clamped to [0, m] (the walks never leave the
+// list, whatever u held).
+__device__ __forceinline__ void slice(int64_t p, int64_t m, const int32_t *__restrict__ estart, int32_t &a,
+                                      int32_t &b) {
+    int64_t lo = estart[p], hi = estart[p + 1];
+    lo = lo < 0 ? 0 : (lo > m ? m : lo);
+    hi = hi < lo ? lo : (hi > m ? m : hi);
+    a = (int32_t)lo;
+    b = (int32_t)hi;
 }
 
-__global__ void k_count_lo(int64_t m, const int32_t *__restrict__ v, const uint8_t *__restrict__ mask,
-                           int32_t *cnt_lo) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    if (mask && mask[e] == 0) return;
-    atomicAdd(&cnt_lo[v[e]], 1);
+// An edge of row p's slice that the CSR takes: in the mask, and its other end
+// a node above p (anything else in a slice breaks the canonical form and is
+// left out by both walks alike).
+__device__ __forceinline__ bool takes(int64_t n, int64_t p, int32_t e, const int32_t *__restrict__ v,
+                                      const uint8_t *__restrict__ mask, int32_t &q) {
+    const bool on = mask ? mask[e] != 0 : true;
+    q = v[e];
+    return on && q > p && q < n;
 }
 
-__global__ void k_row_total(int64_t n, const int32_t *__restrict__ estart, const int32_t *__restrict__ incpos,
-                            const int32_t *__restrict__ cnt_lo, int32_t *tot) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int kGroup = 4;   // slice edges a thread handles with their loads and atomics issued together
+
+// First walk: up[p] = included upper edges of row p; each adds one to the
+// lower count of its other end.  Longer slices are listed for a wavefront.
+// Rows go to the XCDs in contiguous ranges (xcd_remap), so the lower-part
+// counters and entries of nearby rows stay in one XCD's L2.
+__global__ void k_walk_count(int64_t n, int64_t m, const int32_t *__restrict__ estart, const int32_t *__restrict__ v,
+                             const uint8_t *__restrict__ mask, int32_t *up, int32_t *cnt_lo, int32_t *walk_rows,
+                             int32_t *walk_cnt) {
+    const int64_t p = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    const int32_t a = estart[p], b = estart[p + 1];
-    const int32_t hi = incpos ? incpos[b] - incpos[a] : b - a;
-    tot[p] = cnt_lo[p] + hi;
+    int32_t a, b;
+    slice(p, m, estart, a, b);
+    if (b - a > kWalk) {
+        walk_rows[atomicAdd(walk_cnt, 1)] = (int32_t)p;
+        return;
+    }
+    int32_t c = 0;
+    for (int32_t e0 = a; e0 < b; e0 += kGroup) {
+        bool in[kGroup];
+        int32_t q[kGroup];
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) in[t] = e0 + t < b && takes(n, p, e0 + t, v, mask, q[t]);
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t)
+            if (in[t]) {
+                ++c;
+                atomicAdd(&cnt_lo[q[t]], 1);
+            }
+    }
+    up[p] = c;
 }
 
-// One pass over the edges: edge e is the upper entry of row u[e], written in
-// place, and a lower entry of row v[e], whose id is dropped into that row's
-// lower range (atomic slot; the ranking kernels order it by id).
+// Listed slices: one wavefront per row, 64 edges at a time.
+__global__ __launch_bounds__(256) void k_walk_count_long(int64_t n, int64_t m, const int32_t *__restrict__ estart,
+                                                         const int32_t *__restrict__ v,
+                                                         const uint8_t *__restrict__ mask, int32_t *up,
+                                                         int32_t *cnt_lo, const int32_t *__restrict__ walk_rows,
+                                                         const int32_t *__restrict__ walk_cnt) {
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t cnt = *walk_cnt;
+    for (int32_t r = blockIdx.x * 4 + wv; r < cnt; r += gridDim.x * 4) {
+        const int32_t p = walk_rows[r];
+        int32_t a, b;
+        slice(p, m, estart, a, b);
+        int32_t c = 0;
+        for (int32_t e0 = a; e0 < b; e0 += kWave) {
+            const int32_t e = e0 + lane;
+            int32_t q = 0;
+            const bool in = e < b && takes(n, p, e, v, mask, q);
+            if (in) atomicAdd(&cnt_lo[q], 1);
+            c += __popcll(__ballot(in));
+        }
+        if (lane == 0) up[p] = c;
+    }
+}
+
+__global__ void k_row_total(int64_t n, const int32_t *__restrict__ up, const int32_t *__restrict__ cnt_lo,
+                            int32_t *tot) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) tot[p] = cnt_lo[p] + up[p];
+}
+
+// Edge e = (p, q) of row p's slice: the k-th included one is the upper entry
+// rowptr[p] + cnt_lo[p] + k; its lower entry goes to an atomic slot of row q.
 template <typename TW>
-__global__ void k_fill_upper(int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
-                             const TW *__restrict__ w, const uint8_t *__restrict__ mask,
-                             const int32_t *__restrict__ incpos, const int32_t *__restrict__ estart,
-                             const int32_t *__restrict__ rowptr, const int32_t *__restrict__ cnt_lo, int32_t *col,
-                             TW *val, int32_t *eid, int32_t *fill, int32_t *tmp) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m) return;
-    if (mask && mask[e] == 0) return;
-    const int32_t p = u[e], q = v[e];
-    const int32_t k = incpos ? incpos[e] - incpos[estart[p]] : (int32_t)(e - estart[p]);
+__device__ __forceinline__ void put_edge(int64_t p, int32_t q, int32_t e, int32_t k, const TW *__restrict__ w,
+                                         const int32_t *__restrict__ rowptr, const int32_t *__restrict__ cnt_lo,
+                                         int32_t *col, TW *val, int32_t *eid, int32_t *fill) {
+    const TW we = w[e];
     const int32_t j = rowptr[p] + cnt_lo[p] + k;
     col[j] = q;
-    val[j] = w[e];
-    eid[j] = (int32_t)e;
-    const int32_t slot = atomicAdd(&fill[q], 1);
-    tmp[rowptr[q] + slot] = (int32_t)e;
+    val[j] = we;
+    eid[j] = e;
+    const int32_t i = rowptr[q] + atomicAdd(&fill[q], 1);
+    col[i] = (int32_t)p;
+    val[i] = we;
+    eid[i] = e;
 }
 
-// Ids in a segment are distinct, so the rank of an id is the number of
-// smaller ids; the entry goes to base + rank.
+// Second walk, the same edges in the same order as the first.
+template <typename TW>
+__global__ void k_walk_fill(int64_t n, int64_t m, const int32_t *__restrict__ estart, const int32_t *__restrict__ v,
+                            const TW *__restrict__ w, const uint8_t *__restrict__ mask,
+                            const int32_t *__restrict__ rowptr, const int32_t *__restrict__ cnt_lo, int32_t *col,
+                            TW *val, int32_t *eid, int32_t *fill) {
+    const int64_t p = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    int32_t a, b;
+    slice(p, m, estart, a, b);
+    if (b - a > kWalk) return;
+    int32_t j = rowptr[p] + cnt_lo[p];
+    for (int32_t e0 = a; e0 < b; e0 += kGroup) {
+        bool in[kGroup];
+        int32_t q[kGroup], at[kGroup];
+        TW we[kGroup];
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) in[t] = e0 + t < b && takes(n, p, e0 + t, v, mask, q[t]);
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t)
+            if (in[t]) {
+                we[t] = w[e0 + t];
+                at[t] = rowptr[q[t]] + atomicAdd(&fill[q[t]], 1);
+            }
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t)
+            if (in[t]) {
+                const int32_t e = e0 + t;
+                col[j] = q[t];
+                val[j] = we[t];
+                eid[j] = e;
+                ++j;
+                col[at[t]] = (int32_t)p;
+                val[at[t]] = we[t];
+                eid[at[t]] = e;
+            }
+    }
+}
+
+template <typename TW>
+__global__ __launch_bounds__(256) void k_walk_fill_long(int64_t n, int64_t m, const int32_t *__restrict__ estart,
+                                                        const int32_t *__restrict__ v, const TW *__restrict__ w,
+                                                        const uint8_t *__restrict__ mask,
+                                                        const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ cnt_lo, int32_t *col, TW *val,
+                                                        int32_t *eid, int32_t *fill,
+                                                        const int32_t *__restrict__ walk_rows,
+                                                        const int32_t *__restrict__ walk_cnt) {
+    const int wv = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const uint64_t below = (uint64_t(1) << lane) - 1;
+    const int32_t cnt = *walk_cnt;
+    for (int32_t r = blockIdx.x * 4 + wv; r < cnt; r += gridDim.x * 4) {
+        const int32_t p = walk_rows[r];
+        int32_t a, b;
+        slice(p, m, estart, a, b);
+        int32_t k = 0;
+        for (int32_t e0 = a; e0 < b; e0 += kWave) {
+            const int32_t e = e0 + lane;
+            int32_t q = 0;
+            const bool in = e < b && takes(n, p, e, v, mask, q);
+            const uint64_t bal = __ballot(in);
+            if (in) put_edge(p, q, e, k + __popcll(bal & below), w, rowptr, cnt_lo, col, val, eid, fill);
+            k += __popcll(bal);
+        }
+    }
+}
+
+// Lower parts of 2..kRegSeg entries: read into registers, each entry written
+// back at its rank by edge id (ids in a row are distinct).  Longer parts are
+// listed for k_rank_long; parts of one entry are in place already.
 template <typename TW>
 __global__ __launch_bounds__(256) void k_rank_short(int64_t n, const int32_t *__restrict__ rowptr,
-                                                    const int32_t *__restrict__ cnt_lo,
-                                                    const int32_t *__restrict__ tmp, const int32_t *__restrict__ u,
-                                                    const TW *__restrict__ w, int32_t *col, TW *val, int32_t *eid,
-                                                    int32_t *long_rows, int32_t *long_cnt) {
-    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    const int32_t *__restrict__ cnt_lo, int32_t *col, TW *val,
+                                                    int32_t *eid, int32_t *long_rows, int32_t *long_cnt) {
+    const int64_t row = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (row >= n) return;
     const int32_t len = cnt_lo[row];
-    if (len > kShortSeg) {
+    if (len < 2) return;
+    if (len > kRegSeg) {
         long_rows[atomicAdd(long_cnt, 1)] = (int32_t)row;
         return;
     }
     const int32_t base = rowptr[row];
-    for (int32_t i = 0; i < len; ++i) {
-        const int32_t mine = tmp[base + i];
+    int32_t id[kRegSeg], c[kRegSeg];
+    TW x[kRegSeg];
+#pragma unroll
+    for (int i = 0; i < kRegSeg; ++i) {
+        id[i] = i < len ? eid[base + i] : INT32_MAX;
+        c[i] = i < len ? col[base + i] : 0;
+        x[i] = i < len ? val[base + i] : TW(0);
+    }
+#pragma unroll
+    for (int i = 0; i < kRegSeg; ++i) {
         int32_t rank = 0;
-        for (int32_t j = 0; j < len; ++j) rank += (tmp[base + j] < mine) ? 1 : 0;
-        col[base + rank] = u[mine];
-        val[base + rank] = w[mine];
-        eid[base + rank] = mine;
+#pragma unroll
+        for (int j = 0; j < kRegSeg; ++j) rank += id[j] < id[i] ? 1 : 0;
+        if (i < len) {
+            col[base + rank] = c[i];
+            val[base + rank] = x[i];
+            eid[base + rank] = id[i];
+        }
     }
 }
 
@@ -155,8 +291,8 @@ __device__ __forceinline__ void put_lower(int32_t j, int32_t e, const int32_t *_
 // power of two with INT32_MAX); longer ones are ranked from global memory.
 template <typename TW>
 __global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ rowptr,
-                                                   const int32_t *__restrict__ cnt_lo,
-                                                   const int32_t *__restrict__ tmp, const int32_t *__restrict__ u,
+                                                   const int32_t *__restrict__ cnt_lo, int32_t *tmp,
+                                                   const int32_t *__restrict__ u,
                                                    const TW *__restrict__ w, int32_t *col, TW *val, int32_t *eid,
                                                    const int32_t *__restrict__ long_rows,
                                                    const int32_t *__restrict__ long_cnt) {
@@ -169,7 +305,7 @@ __global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ r
         if (len <= kLdsSeg) {
             int32_t pw = 1;
             while (pw < len) pw <<= 1;
-            for (int32_t i = threadIdx.x; i < pw; i += blockDim.x) seg[i] = i < len ? tmp[base + i] : INT32_MAX;
+            for (int32_t i = threadIdx.x; i < pw; i += blockDim.x) seg[i] = i < len ? eid[base + i] : INT32_MAX;
             __syncthreads();
             for (int32_t kk = 2; kk <= pw; kk <<= 1) {
                 for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
@@ -189,6 +325,9 @@ __global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ r
             }
             for (int32_t i = threadIdx.x; i < len; i += blockDim.x) put_lower(base + i, seg[i], u, w, col, val, eid);
         } else {
+            // ranked from a copy: the entries are rewritten in place
+            for (int32_t i = threadIdx.x; i < len; i += blockDim.x) tmp[base + i] = eid[base + i];
+            __syncthreads();
             for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
                 const int32_t mine = tmp[base + i];
                 int32_t rank = 0;
@@ -262,13 +401,16 @@ template <typename TW>
 void fill_entries(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const TW *w, const uint8_t *mask,
                   const CsrPlan &p, const int32_t *rowptr, int32_t *col, TW *val, int32_t *eid, TW *deg,
                   hipStream_t s) {
-    const dim3 gn(grid_for(n, 256)), gm(grid_for(m, 256)), b(256);
+    const dim3 gn(grid_for(n, 256)), b(256);
     if (m > 0) {
-        hipLaunchKernelGGL(k_fill_upper<TW>, gm, b, 0, s, m, u, v, w, mask, mask ? p.incpos : nullptr, p.estart,
-                           rowptr, p.cnt_lo, col, val, eid, p.fill, p.tmp);
+        hipLaunchKernelGGL(k_walk_fill<TW>, gn, b, 0, s, n, m, p.estart, v, w, mask, rowptr, p.cnt_lo, col, val, eid,
+                           p.fill);
         SFG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_rank_short<TW>, gn, b, 0, s, n, rowptr, p.cnt_lo, p.tmp, u, w, col, val, eid,
-                           p.long_rows, p.long_cnt);
+        hipLaunchKernelGGL(k_walk_fill_long<TW>, dim3(256), b, 0, s, n, m, p.estart, v, w, mask, rowptr, p.cnt_lo,
+                           col, val, eid, p.fill, p.walk_rows, p.walk_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_rank_short<TW>, gn, b, 0, s, n, rowptr, p.cnt_lo, col, val, eid, p.long_rows,
+                           p.long_cnt);
         SFG_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_rank_long<TW>, dim3(512), b, 0, s, rowptr, p.cnt_lo, p.tmp, u, w, col, val, eid,
                            p.long_rows, p.long_cnt);
@@ -434,21 +576,16 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
                 "laplacian_csr: null pointer");
     Carver c(ws);
     CsrPlan p = plan_csr(c, n, m);
-    const dim3 gn(grid_for(n, 256)), gm(grid_for(m, 256)), b(256);
+    const dim3 gn(grid_for(n, 256)), b(256);
     fill_i32(p.zeroed, p.zeroed_len, 0, s);
     hipLaunchKernelGGL(k_estart, dim3(grid_for(m + 1, 256)), b, 0, s, n, m, u, p.estart);
     SFG_LAUNCH_CHECK();
-    if (m > 0) {
-        if (mask) {
-            hipLaunchKernelGGL(k_inc_count, gm, b, 0, s, m, v, mask, p.inc, p.cnt_lo);
-            SFG_LAUNCH_CHECK();
-            exclusive_scan_i32(p.inc, p.incpos, m, p.scan, s);
-        } else {
-            hipLaunchKernelGGL(k_count_lo, gm, b, 0, s, m, v, mask, p.cnt_lo);
-            SFG_LAUNCH_CHECK();
-        }
-    }
-    hipLaunchKernelGGL(k_row_total, gn, b, 0, s, n, p.estart, (mask && m > 0) ? p.incpos : nullptr, p.cnt_lo, p.tot);
+    hipLaunchKernelGGL(k_walk_count, gn, b, 0, s, n, m, p.estart, v, mask, p.up, p.cnt_lo, p.walk_rows, p.walk_cnt);
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_walk_count_long, dim3(256), b, 0, s, n, m, p.estart, v, mask, p.up, p.cnt_lo, p.walk_rows,
+                       p.walk_cnt);
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_row_total, gn, b, 0, s, n, p.up, p.cnt_lo, p.tot);
     SFG_LAUNCH_CHECK();
     exclusive_scan_i32(p.tot, rowptr, n, p.scan, s);
     if (wt == SFG_F64)

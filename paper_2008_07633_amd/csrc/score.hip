@@ -2,12 +2,18 @@
 // smoothed block standing in for eigenvectors; Alg. 1's edge distortion) and
 // algebraic-distance node affinities (Sec. 3.2).
 //
-// One thread per edge: it streams the two endpoint rows of the node-major
-// block (k*elt contiguous bytes each, loaded 16 bytes at a time) and adds the
-// k terms in ascending column order, so FP64 scores equal the plain
-// sequential definition exactly.  Candidates are processed in their given
-// (ascending edge id) order, so the u-endpoint rows are read nearly
-// sequentially and the v-endpoint rows hit nearby cache lines on meshes.
+// Scores: a group of G lanes (G = 4, or 2 for 32-byte rows) takes one edge.
+// Lane l loads 16-byte pieces l, l + G, l + 2G, ... of both endpoint rows of
+// the node-major block, so one load instruction of a wavefront reads whole
+// 64-byte (or 32-byte) row segments instead of one 16-byte piece of 64
+// different rows.  The k squared differences are then added in ascending
+// column order by passing the running sum from lane to lane within the group
+// (a DPP rotation): lane l adds its piece when the sum reaches it.  FP64
+// scores therefore equal the plain sequential definition exactly.  Row sizes
+// that do not split into such groups take one lane per edge, the same
+// additions.  Candidates are processed in their given (ascending edge id)
+// order, so the u-endpoint rows are read nearly sequentially and the
+// v-endpoint rows hit nearby cache lines on meshes.
 #include "common.hpp"
 
 namespace sfg {
@@ -51,10 +57,85 @@ __global__ __launch_bounds__(256) void k_scores(int64_t ne, int32_t k, const int
     score[i] = (TS)(we * acc);
 }
 
+// The value of lane l - 1 of the same group of G lanes (lane G - 1 for lane
+// 0): quad_perm DPP, which moves data within aligned groups of four lanes.
+template <int G>
+__device__ __forceinline__ int rot_group(int x) {
+    static_assert(G == 2 || G == 4, "groups of 2 or 4 lanes");
+    constexpr int kCtrl = G == 4 ? (3 | (0 << 2) | (1 << 4) | (2 << 6)) : (1 | (0 << 2) | (3 << 4) | (2 << 6));
+    return __builtin_amdgcn_update_dpp(x, x, kCtrl, 0xF, 0xF, false);
+}
+
+template <int G>
+__device__ __forceinline__ float rot_group(float x) {
+    return __builtin_bit_cast(float, rot_group<G>(__builtin_bit_cast(int, x)));
+}
+
+template <int G>
+__device__ __forceinline__ double rot_group(double x) {
+    const int lo = rot_group<G>(__double2loint(x)), hi = rot_group<G>(__double2hiint(x));
+    return __hiloint2double(hi, lo);
+}
+
+// Row of K = G * VW * R elements: R rounds of G 16-byte pieces.  Every lane of
+// a group runs the same steps; at step (r, j) lane j holds the sum of the
+// first r*G*VW + (j+1)*VW terms, the other lanes' values are overwritten
+// before they are read.  Groups never straddle the grid's end: G divides 256.
+template <typename TX, typename TW, typename TA, typename TS, int G, int R>
+__global__ __launch_bounds__(256) void k_scores_grp(int64_t ne, const int32_t *__restrict__ cand,
+                                                    const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                                                    const TW *__restrict__ w, const TX *__restrict__ x,
+                                                    TS *__restrict__ score) {
+    constexpr int VW = 16 / sizeof(TX);
+    constexpr int K = G * VW * R;
+    const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t i = ((int64_t)b * 256 + threadIdx.x) / G;
+    const int l = threadIdx.x % G;
+    if (i >= ne) return;
+    const int64_t e = cand ? cand[i] : i;
+    const TX *xp = x + (int64_t)u[e] * K + l * VW;
+    const TX *xq = x + (int64_t)v[e] * K + l * VW;
+    TA d[R][VW];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const Vec<TX, VW> a = *reinterpret_cast<const Vec<TX, VW> *>(xp + r * G * VW);
+        const Vec<TX, VW> bq = *reinterpret_cast<const Vec<TX, VW> *>(xq + r * G * VW);
+#pragma unroll
+        for (int t = 0; t < VW; ++t) d[r][t] = cvt<TA>(a.v[t]) - cvt<TA>(bq.v[t]);
+    }
+    TA acc = TA(0);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (r + j > 0) acc = rot_group<G>(acc);
+#pragma unroll
+            for (int t = 0; t < VW; ++t) acc = sq_add(acc, d[r][t]);
+        }
+    }
+    if (l == G - 1) score[i] = (TS)(cvt<TA>(w[e]) * acc);
+}
+
+template <typename TX, typename TW, typename TA, typename TS, int G, int R>
+void launch_grp(int64_t ne, const int32_t *cand, const int32_t *u, const int32_t *v, const void *w, const void *x,
+                void *score, hipStream_t s) {
+    hipLaunchKernelGGL((k_scores_grp<TX, TW, TA, TS, G, R>), dim3(grid_for(ne * G, 256)), dim3(256), 0, s, ne, cand,
+                       u, v, (const TW *)w, (const TX *)x, (TS *)score);
+    SFG_LAUNCH_CHECK();
+}
+
 template <typename TX, typename TW, typename TA, typename TS>
 void launch_scores(int64_t ne, int32_t k, const int32_t *cand, const int32_t *u, const int32_t *v, const void *w,
                    const void *x, void *score, hipStream_t s) {
     constexpr int VW = 16 / sizeof(TX);
+    const int64_t row_bytes = (int64_t)k * (int64_t)sizeof(TX);
+    switch (row_bytes) {
+        case 32: return launch_grp<TX, TW, TA, TS, 2, 1>(ne, cand, u, v, w, x, score, s);
+        case 64: return launch_grp<TX, TW, TA, TS, 4, 1>(ne, cand, u, v, w, x, score, s);
+        case 128: return launch_grp<TX, TW, TA, TS, 4, 2>(ne, cand, u, v, w, x, score, s);
+        case 256: return launch_grp<TX, TW, TA, TS, 4, 4>(ne, cand, u, v, w, x, score, s);
+        default: break;
+    }
     const dim3 g(grid_for(ne, 256)), blk(256);
     if (k % VW == 0)
         hipLaunchKernelGGL((k_scores<TX, TW, TA, TS, VW>), g, blk, 0, s, ne, k, cand, u, v, (const TW *)w,

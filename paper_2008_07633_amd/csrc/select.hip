@@ -5,9 +5,14 @@
 // IEEE values map to unsigned keys that order like the values, so the k-th
 // largest key is found by most-significant-digit radix select: per pass, a
 // histogram (LDS, integer atomics) of the keys that still match the digits
-// fixed so far, then one workgroup picks the digit that contains rank k.  Passes stay on the device (no host round trips).
-// Ties at the threshold take the lowest positions: a scan over the tie flags
-// gives each tied key its rank.
+// fixed so far, then one workgroup picks the digit that contains rank k.
+// Passes stay on the device (no host round trips).  The third pass also
+// copies the keys that match its prefix (two digits fixed: normally a tiny
+// share) to a buffer, and the later passes read that buffer instead of the
+// scores.  Ties at the threshold take the lowest positions: when the last
+// digit's bucket is taken whole (the usual case) the keys >= the threshold
+// are kept; otherwise per-tile tie counts, their scan, and a scan inside each
+// tile give every tied key its rank.
 #include <mutex>
 
 #include "common.hpp"
@@ -25,13 +30,17 @@ namespace {
 constexpr int kBins = 2048;
 constexpr int kHistThreads = 256;
 
+constexpr int kTieTile = 4096;       // keys per workgroup in the tie count and the marking
+constexpr int kCompactPass = 2;      // the pass (0-based) that copies its matching keys to the buffer
+
 struct SelState {
     uint64_t prefix;
     uint64_t fixed;
     int64_t krem;      // rank (1-based) still sought inside the current bucket
     int64_t count_gt;  // keys known to be larger than the bucket
+    uint64_t ncopy;    // keys copied to the buffer by the compacting pass
     uint32_t err;
-    uint32_t pad;
+    uint32_t all_ties; // the last pick takes every key equal to the threshold
 };
 
 template <typename TS> struct KeyOf;
@@ -86,29 +95,53 @@ __global__ void k_sel_init(SelState *st, int64_t k, uint32_t *hist) {
         st->fixed = 0;
         st->krem = k;
         st->count_gt = 0;
+        st->ncopy = 0;
         st->err = 0;
+        st->all_ties = 0;
     }
     for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
 }
 
-template <typename TS>
+// One radix pass.  FROM_BUF: read the keys the compacting pass copied (their
+// count is st->ncopy) instead of the scores.  copy != nullptr: append the
+// keys that match the prefix to copy[] (one atomic per wavefront).
+template <typename TS, bool FROM_BUF>
 __global__ __launch_bounds__(kHistThreads) void k_sel_hist(int64_t ne, const TS *__restrict__ score,
-                                                           const SelState *__restrict__ st, int shift, int width,
-                                                           int check, uint32_t *hist, SelState *stw) {
+                                                           const typename KeyOf<TS>::K *__restrict__ buf,
+                                                           SelState *st, int shift, int width, int check,
+                                                           uint32_t *hist, typename KeyOf<TS>::K *copy) {
     using K = typename KeyOf<TS>::K;
     __shared__ uint32_t h[kBins];
     for (int b = threadIdx.x; b < kBins; b += blockDim.x) h[b] = 0;
     __syncthreads();
     const K prefix = (K)st->prefix, fixed = (K)st->fixed;
     const K dmask = (K(1) << width) - 1;
+    const int64_t cnt = FROM_BUF ? (int64_t)st->ncopy : ne;
+    const int lane = threadIdx.x % kWave;
     uint32_t bad = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ne; i += (int64_t)gridDim.x * blockDim.x) {
-        const TS sv = score[i];
-        if (check) bad |= is_nan_bits<TS>(raw_bits(sv)) ? 1u : 0u;
-        const K key = key_of(sv);
-        if ((key & fixed) == prefix) atomicAdd(&h[(key >> shift) & dmask], 1u);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+        K key;
+        if (FROM_BUF) {
+            key = buf[i];
+        } else {
+            const TS sv = score[i];
+            if (check) bad |= is_nan_bits<TS>(raw_bits(sv)) ? 1u : 0u;
+            key = key_of(sv);
+        }
+        const bool match = (key & fixed) == prefix;
+        if (match) atomicAdd(&h[(key >> shift) & dmask], 1u);
+        if (copy) {
+            const uint64_t bal = __ballot(match);
+            if (bal) {
+                const int leader = __ffsll((unsigned long long)bal) - 1;
+                unsigned long long base = 0;
+                if (lane == leader) base = atomicAdd((unsigned long long *)&st->ncopy, (unsigned long long)__popcll(bal));
+                base = __shfl(base, leader, kWave);
+                if (match) copy[base + __popcll(bal & ((uint64_t(1) << lane) - 1))] = key;
+            }
+        }
     }
-    if (bad) atomicOr(&stw->err, 1u);   // NaN
+    if (bad) atomicOr(&st->err, 1u);   // NaN
     __syncthreads();
     for (int b = threadIdx.x; b < kBins; b += blockDim.x)
         if (h[b]) atomicAdd(&hist[b], h[b]);
@@ -116,7 +149,7 @@ __global__ __launch_bounds__(kHistThreads) void k_sel_hist(int64_t ne, const TS 
 
 // One workgroup of 256 threads, 8 bins each; finds the digit holding rank
 // krem counted from the top, updates the state and clears the histogram.
-__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, int shift, int width) {
+__global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, int shift, int width, int last) {
     __shared__ int64_t suffix[257];
     const int t = threadIdx.x;
     const int nb = 1 << width;
@@ -150,6 +183,7 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, 
             if (krem <= acc + c) {
                 st->count_gt += acc;
                 st->krem = krem - acc;
+                if (last) st->all_ties = (krem - acc == c) ? 1u : 0u;
                 st->prefix |= (uint64_t)b << shift;
                 st->fixed |= (uint64_t)(nb - 1) << shift;
                 break;
@@ -165,30 +199,102 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, 
     }
 }
 
+// Keys of tile t: t*kTieTile + j*256 + thread, j = 0..15 (ascending position
+// in (j, thread) order).
+__device__ __forceinline__ int32_t block_sum(int32_t x) {
+    __shared__ int32_t part[256 / kWave];
+    for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_down(x, off, kWave);
+    if (threadIdx.x % kWave == 0) part[threadIdx.x / kWave] = x;
+    __syncthreads();
+    int32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < 256 / kWave; ++w) t += part[w];
+    __syncthreads();
+    return t;
+}
+
+// Exclusive scan over the 256 threads of the block, in thread order.
+__device__ __forceinline__ int32_t block_excl(int32_t x, int32_t &total) {
+    __shared__ int32_t part[256 / kWave];
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    int32_t inc = x;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int32_t y = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += y;
+    }
+    if (lane == kWave - 1) part[wv] = inc;
+    __syncthreads();
+    int32_t off = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 256 / kWave; ++w) {
+        off += w < wv ? part[w] : 0;
+        tot += part[w];
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - x;
+}
+
+// Keys equal to the threshold in each tile; nothing to do when the bucket is
+// taken whole.
 template <typename TS>
-__global__ void k_sel_flags(int64_t ne, const TS *__restrict__ score, const SelState *__restrict__ st,
-                            int32_t *flags) {
+__global__ __launch_bounds__(256) void k_sel_tiecount(int64_t ne, const TS *__restrict__ score,
+                                                      const SelState *__restrict__ st, int32_t *tcnt) {
     using K = typename KeyOf<TS>::K;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ne) return;
-    flags[i] = key_of(score[i]) == (K)st->prefix ? 1 : 0;
+    if (st->all_ties) return;
+    const K thr = (K)st->prefix;
+    const int64_t base = (int64_t)blockIdx.x * kTieTile + threadIdx.x;
+    int32_t c = 0;
+#pragma unroll 4
+    for (int j = 0; j < kTieTile / 256; ++j) {
+        const int64_t i = base + j * 256;
+        if (i < ne && key_of(score[i]) == thr) ++c;
+    }
+    c = block_sum(c);
+    if (threadIdx.x == 0) tcnt[blockIdx.x] = c;
+}
+
+// In-place exclusive scan of the tile counts, one workgroup.
+__global__ __launch_bounds__(256) void k_sel_tiescan(int32_t *tcnt, int64_t nt, const SelState *__restrict__ st) {
+    if (st->all_ties) return;
+    int32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nt; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const int32_t x = i < nt ? tcnt[i] : 0;
+        int32_t tot;
+        const int32_t ex = block_excl(x, tot);
+        if (i < nt) tcnt[i] = carry + ex;
+        carry += tot;
+    }
 }
 
 template <typename TS>
-__global__ void k_sel_mark(int64_t ne, const TS *__restrict__ score, const SelState *__restrict__ st,
-                           const int32_t *__restrict__ tie_rank, uint8_t *sel, double *tau) {
+__global__ __launch_bounds__(256) void k_sel_mark(int64_t ne, const TS *__restrict__ score,
+                                                  const SelState *__restrict__ st,
+                                                  const int32_t *__restrict__ tpos, uint8_t *sel, double *tau) {
     using K = typename KeyOf<TS>::K;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const K thr = (K)st->prefix;
-    if (i == 0) {
-        *tau = st->err ? __builtin_nan("") : (double)value_of<TS>(thr);
+    const int64_t base = (int64_t)blockIdx.x * kTieTile + threadIdx.x;
+    if (base == 0) *tau = st->err ? __builtin_nan("") : (double)value_of<TS>(thr);
+    if (st->all_ties) {
+#pragma unroll 4
+        for (int j = 0; j < kTieTile / 256; ++j) {
+            const int64_t i = base + j * 256;
+            if (i < ne) sel[i] = key_of(score[i]) >= thr ? 1 : 0;
+        }
+        return;
     }
-    if (i >= ne) return;
-    const K key = key_of(score[i]);
-    uint8_t s = 0;
-    if (key > thr) s = 1;
-    else if (key == thr && tie_rank[i] < st->krem) s = 1;
-    sel[i] = s;
+    const int64_t krem = st->krem;
+    int32_t rank = tpos[blockIdx.x];
+    for (int j = 0; j < kTieTile / 256; ++j) {
+        const int64_t i = base + j * 256;
+        const K key = i < ne ? key_of(score[i]) : K(0);
+        const int32_t tie = (i < ne && key == thr) ? 1 : 0;
+        int32_t tot;
+        const int32_t ex = block_excl(tie, tot);
+        if (i < ne) sel[i] = (key > thr || (tie && (int64_t)(rank + ex) < krem)) ? 1 : 0;
+        rank += tot;
+    }
 }
 
 __global__ void k_sel_empty(double *tau) { *tau = __builtin_inf(); }
@@ -196,16 +302,16 @@ __global__ void k_sel_empty(double *tau) { *tau = __builtin_inf(); }
 struct SelPlan {
     SelState *st;
     uint32_t *hist;
-    int32_t *flags, *rank, *scan;
+    uint64_t *buf;      // keys copied by the compacting pass (room for all ne)
+    int32_t *tcnt;      // tie counts per tile, then their exclusive scan
 };
 
 SelPlan plan_select(Carver &c, int64_t ne) {
     SelPlan p;
     p.st = c.take<SelState>(1);
     p.hist = c.take<uint32_t>(kBins);
-    p.flags = c.take<int32_t>(ne + 1);
-    p.rank = c.take<int32_t>(ne + 1);
-    p.scan = c.take<int32_t>(scan_scratch_ints(ne + 1));
+    p.buf = c.take<uint64_t>(ne + 1);
+    p.tcnt = c.take<int32_t>((ne + kTieTile - 1) / kTieTile + 1);
     return p;
 }
 
@@ -218,23 +324,32 @@ void run_select(const TS *score, int64_t ne, int64_t k, uint8_t *sel, double *ta
     int64_t hb = (ne + kHistThreads * 16 - 1) / (kHistThreads * 16);
     if (hb > 2048) hb = 2048;
     if (hb < 1) hb = 1;
-    int hi = B;
-    bool first = true;
+    using K = typename KeyOf<TS>::K;
+    K *buf = reinterpret_cast<K *>(p.buf);
+    int hi = B, pass = 0;
     while (hi > 0) {
         const int width = hi >= 11 ? 11 : hi;
         const int shift = hi - width;
-        hipLaunchKernelGGL(k_sel_hist<TS>, dim3((uint32_t)hb), dim3(kHistThreads), 0, s, ne, score, p.st, shift,
-                           width, first ? 1 : 0, p.hist, p.st);
+        const int last = shift == 0 ? 1 : 0;
+        if (pass <= kCompactPass)
+            hipLaunchKernelGGL((k_sel_hist<TS, false>), dim3((uint32_t)hb), dim3(kHistThreads), 0, s, ne, score,
+                               (const K *)nullptr, p.st, shift, width, pass == 0 ? 1 : 0, p.hist,
+                               (pass == kCompactPass && !last) ? buf : (K *)nullptr);
+        else
+            hipLaunchKernelGGL((k_sel_hist<TS, true>), dim3((uint32_t)hb), dim3(kHistThreads), 0, s, ne, score, buf,
+                               p.st, shift, width, 0, p.hist, (K *)nullptr);
         SFG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, p.st, p.hist, shift, width);
+        hipLaunchKernelGGL(k_sel_pick, dim3(1), dim3(256), 0, s, p.st, p.hist, shift, width, last);
         SFG_LAUNCH_CHECK();
         hi = shift;
-        first = false;
+        ++pass;
     }
-    hipLaunchKernelGGL(k_sel_flags<TS>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, score, p.st, p.flags);
+    const int64_t nt = (ne + kTieTile - 1) / kTieTile;
+    hipLaunchKernelGGL(k_sel_tiecount<TS>, dim3((uint32_t)nt), dim3(256), 0, s, ne, score, p.st, p.tcnt);
     SFG_LAUNCH_CHECK();
-    exclusive_scan_i32(p.flags, p.rank, ne, p.scan, s);
-    hipLaunchKernelGGL(k_sel_mark<TS>, dim3(grid_for(ne, 256)), dim3(256), 0, s, ne, score, p.st, p.rank, sel, tau);
+    hipLaunchKernelGGL(k_sel_tiescan, dim3(1), dim3(256), 0, s, p.tcnt, nt, p.st);
+    SFG_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_sel_mark<TS>, dim3((uint32_t)nt), dim3(256), 0, s, ne, score, p.st, p.tcnt, sel, tau);
     SFG_LAUNCH_CHECK();
 }
 

@@ -858,12 +858,26 @@ __device__ __forceinline__ void row_cols(const int32_t *__restrict__ col, int32_
     for (int t = 0; t < kMpkRegCols; ++t) cc[t] = t < len ? col[j0 + t] : -1;
 }
 
-// Order check: every order[i] in [0, n) and no node twice (seen[] zeroed by the caller).
-__global__ void k_mpk_check(int64_t n, const int32_t *__restrict__ order, int32_t *seen, int32_t *flag) {
+// Order check, no atomics and no cleared memory: every order[i] in [0, n),
+// and seen[order[i]] = i stored by k_mpk_mark, then read back by
+// k_mpk_verify.  A node listed twice keeps only one of its positions, so the
+// other position finds a different value: any duplicate sets flag bit 0.
+__global__ void k_mpk_mark(int64_t n, const int32_t *__restrict__ order, int32_t *seen, int32_t *flag) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t v = order[i];
-    if (v < 0 || v >= n || atomicExch(&seen[v], 1) != 0) atomicOr(flag, 1);
+    if (v < 0 || v >= n)
+        atomicOr(flag, 1);
+    else
+        seen[v] = (int32_t)i;
+}
+
+__global__ void k_mpk_verify(int64_t n, const int32_t *__restrict__ order, const int32_t *__restrict__ seen,
+                             int32_t *flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = order[i];
+    if (v >= 0 && v < n && seen[v] != (int32_t)i) atomicOr(flag, 1);
 }
 
 // Layout of one block for H hops, one 64-lane workgroup per block.  A block
@@ -1629,8 +1643,9 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
         // the passes take the rows in this order: it must be a permutation of the nodes
         fill_i32(mp.flag, 2, 0, s);
         if (order) {
-            fill_i32(mp.seen, n, 0, s);
-            hipLaunchKernelGGL(k_mpk_check, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
+            hipLaunchKernelGGL(k_mpk_mark, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
+            SFG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_mpk_verify, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
             SFG_LAUNCH_CHECK();
         }
         for (int h = want < kMpkMaxHops ? want : kMpkMaxHops; h >= 2 && hops == 0; --h) {

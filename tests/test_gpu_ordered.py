@@ -158,6 +158,16 @@ def test_ordered_falls_back_and_checks(S, orc):
     bad[0] = g.n
     with pytest.raises(S.SfgError, match="SFG_EINVAL"):
         S.sfg_smooth_ordered(Ht, bad, X16, 6, 0.5)
+    # a negative entry, and a duplicate at the two ends of the order, right after a valid call on the same graph
+    bad = order.clone()
+    bad[g.n // 2] = -1
+    with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+        S.sfg_smooth_ordered(Ht, bad, X16, 6, 0.5)
+    S.sfg_smooth_ordered(Ht, order, X16, 6, 0.5)
+    bad = order.clone()
+    bad[g.n - 1] = bad[0]
+    with pytest.raises(S.SfgError, match="SFG_EINVAL"):
+        S.sfg_smooth_ordered(Ht, bad, X16, 6, 0.5)
     info = {}
     assert torch.equal(S.sfg_smooth_ordered(Ht, order, X16, 6, 0.5, info=info), S.sfg_smooth(Ht, X16, 6, 0.5))
     assert info["sweeps_per_pass"] == 2

@@ -285,6 +285,29 @@ def test_select_many_equal_keys_at_the_threshold(S, orc, dt):
             assert tau == tau_ref == 1.5
 
 
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_select_keys_sharing_their_high_digits(S, orc, dt):
+    """Scores that agree in their top 22 bits (and many in more): the first
+    radix passes leave almost every key in one bucket, so the pass that copies
+    the matching keys to its buffer copies nearly all of them, and the later
+    passes work on that buffer."""
+    rng = np.random.default_rng(83)
+    ne = 250001
+    if dt == torch.float64:
+        s = 1.0 + rng.integers(0, 1 << 22, ne) * 2.0 ** -50
+    else:
+        s = 1.0 + rng.integers(0, 1 << 12, ne) * 2.0 ** -23
+    s = s.astype(dt == torch.float64 and np.float64 or np.float32).astype(np.float64)
+    eid = np.arange(ne, dtype=np.int32)
+    for k in (1, 17, ne // 3, ne - 1):
+        sel, tau = S.sfg_select_topk(dev(s, dt), k)
+        pos, tau_ref = orc.select_topk(s, eid, k)
+        want = np.zeros(ne, np.uint8)
+        want[pos] = 1
+        assert np.array_equal(host(sel), want), k
+        assert tau == tau_ref
+
+
 def test_select_rejects_bad_scores(S):
     s = torch.tensor([1.0, float("nan"), 3.0], dtype=torch.float64, device="cuda")
     with pytest.raises(S.SfgError, match="SFG_ENUMERIC"):
@@ -492,6 +515,35 @@ def test_csr_long_lower_parts(S, orc, n, center):
     assert np.array_equal(host(H.eid)[:H.nnz], ref.eid)
     assert np.array_equal(host(H.val)[:H.nnz], ref.val)
     assert np.array_equal(host(H.deg), ref.deg)
+
+
+@pytest.mark.parametrize("keep", [0.5, 0.03, 1.0])
+def test_csr_masked_long_slices(S, orc, keep):
+    # hubs whose upper slices (edges (p, q), q > p) run past one wavefront's 64 edges, with a random share of the
+    # edges masked out, beside short rows: the walks count and place the kept edges in order
+    n = 5000
+    rng = np.random.default_rng(int(keep * 1000) + 17)
+    hubs = np.array([0, 1, 7, 4000])
+    key = [h * n + np.arange(h + 1, n) for h in hubs]
+    key.append(np.arange(0, n - 1) * n + np.arange(1, n))
+    key.append(rng.integers(0, n, 20000) * n + rng.integers(0, n, 20000))
+    key = np.concatenate(key)
+    a, b = key // n, key % n
+    key = np.unique(np.minimum(a, b) * n + np.maximum(a, b))
+    key = key[key // n != key % n]
+    u, v = (key // n).astype(np.int32), (key % n).astype(np.int32)
+    w = rng.uniform(0.5, 2.0, u.shape[0])
+    sel = rng.random(u.shape[0]) < keep
+    for wdt in (np.float64, np.float32):
+        wt = w.astype(wdt)
+        ref = orc.laplacian_csr(n, u[sel], v[sel], wt[sel].astype(np.float64))
+        H = S.sfg_laplacian_csr(n, dev(u), dev(v), dev(wt), mask=dev(sel.astype(np.uint8)))
+        assert H.nnz == ref.col.shape[0]
+        assert np.array_equal(host(H.rowptr), ref.rowptr.astype(np.int32))
+        assert np.array_equal(host(H.col)[:H.nnz], ref.col)
+        assert np.array_equal(host(H.eid)[:H.nnz], np.nonzero(sel)[0][ref.eid])
+        assert np.array_equal(host(H.val)[:H.nnz], ref.val.astype(wdt))
+        assert np.array_equal(host(H.deg), ref.deg.astype(wdt))
 
 
 # --------------------------------------------------------------------------- Gauss-Seidel reading
