@@ -64,14 +64,27 @@ CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
 // u, so edge e (e = 0..m, with u[-1] = -1 and u[m] = n) is that first edge for
 // exactly the p in (u[e-1], u[e]]: one coalesced pass over the edges.  The
 // range is clamped to [0, n], so an unsorted list cannot write out of bounds.
+// A thread takes kEdgesPerThread consecutive edges (their u loads issued together).
+constexpr int kEdgesPerThread = 4;
+
 __global__ void k_estart(int64_t n, int64_t m, const int32_t *__restrict__ u, int32_t *estart) {
-    const int64_t e = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (e > m) return;
-    int64_t lo = e == 0 ? 0 : (int64_t)u[e - 1] + 1;
-    int64_t hi = e == m ? n : (int64_t)u[e];
-    if (lo < 0) lo = 0;
-    if (hi > n) hi = n;
-    for (int64_t p = lo; p <= hi; ++p) estart[p] = (int32_t)e;
+    const int64_t e0 = ((int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x) * kEdgesPerThread;
+    if (e0 > m) return;
+    int64_t uu[kEdgesPerThread + 1];
+#pragma unroll
+    for (int t = 0; t <= kEdgesPerThread; ++t) {
+        const int64_t e = e0 - 1 + t;
+        uu[t] = e < 0 ? -1 : (e >= m ? n : (int64_t)u[e]);
+    }
+#pragma unroll
+    for (int t = 0; t < kEdgesPerThread; ++t) {
+        const int64_t e = e0 + t;
+        if (e > m) break;
+        int64_t lo = uu[t] + 1, hi = uu[t + 1];
+        if (lo < 0) lo = 0;
+        if (hi > n) hi = n;
+        for (int64_t p = lo; p <= hi; ++p) estart[p] = (int32_t)e;
+    }
 }
 
 // Row p's slice of the edge list, clamped to [0, m] (the walks never leave the
@@ -578,7 +591,8 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
     CsrPlan p = plan_csr(c, n, m);
     const dim3 gn(grid_for(n, 256)), b(256);
     fill_i32(p.zeroed, p.zeroed_len, 0, s);
-    hipLaunchKernelGGL(k_estart, dim3(grid_for(m + 1, 256)), b, 0, s, n, m, u, p.estart);
+    hipLaunchKernelGGL(k_estart, dim3(grid_for((m + kEdgesPerThread) / kEdgesPerThread, 256)), b, 0, s, n, m, u,
+                       p.estart);
     SFG_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_walk_count, gn, b, 0, s, n, m, p.estart, v, mask, p.up, p.cnt_lo, p.walk_rows, p.walk_cnt);
     SFG_LAUNCH_CHECK();

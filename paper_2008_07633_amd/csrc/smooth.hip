@@ -1444,9 +1444,13 @@ int pass_cols(int32_t k) {
 // Weights and arithmetic: FP64 for FP64 storage, FP32 otherwise (as sfg_smooth).
 // The common-case launch over every block at the small capacity, then the
 // blocks over it at the layout's full capacity.
+// Launches of one pass: the common-case launch over every block, the
+// full-capacity launch over the listed blocks.
+constexpr int kPartSmall = 1, kPartListed = 2, kPartBoth = 3;
+
 template <int H, int KC, typename TX, typename TO, bool CENTER>
 void launch_pass_kc(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TO *y,
-                    double omega, hipStream_t s) {
+                    double omega, hipStream_t s, int parts) {
     using TIN = typename std::conditional<CENTER, double, TX>::type;
     using TA = typename std::conditional<sizeof(TX) == 8, double, float>::type;
     constexpr int KS = mpk_small_slots<H, KC, TX, TA>();
@@ -1454,11 +1458,14 @@ void launch_pass_kc(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const v
     const int64_t items = nb * (k / KC);
     SFG_REQUIRE(items <= 0x7fffffff, SFG_EUNSUPPORTED, "smooth_ordered: too many blocks");
     SFG_REQUIRE(mp.small_slots == KS, SFG_EUNSUPPORTED, "smooth_ordered: layout listed for another capacity");
-    hipLaunchKernelGGL((k_sweep_pass<H, KC, KS, false, TIN, TX, TO, TA, TA, 4, CENTER>), dim3((uint32_t)items),
-                       dim3(256), 0, s, k, m, mp.dev, nullptr, (const TIN *)x, mean, y, (TA)(1.0 - omega), (TA)omega);
-    SFG_LAUNCH_CHECK();
+    if (parts & kPartSmall) {
+        hipLaunchKernelGGL((k_sweep_pass<H, KC, KS, false, TIN, TX, TO, TA, TA, 4, CENTER>), dim3((uint32_t)items),
+                           dim3(256), 0, s, k, m, mp.dev, nullptr, (const TIN *)x, mean, y, (TA)(1.0 - omega),
+                           (TA)omega);
+        SFG_LAUNCH_CHECK();
+    }
     if constexpr (KS < KF) {
-        if (mp.nbig > 0) {
+        if ((parts & kPartListed) && mp.nbig > 0) {
             hipLaunchKernelGGL((k_sweep_pass<H, KC, KF, true, TIN, TX, TO, TA, TA, 4, CENTER>),
                                dim3((uint32_t)(mp.nbig * (k / KC))), dim3(256), 0, s, k, m, mp.dev, mp.big,
                                (const TIN *)x, mean, y, (TA)(1.0 - omega), (TA)omega);
@@ -1488,21 +1495,21 @@ int small_slots(sfg_dtype storage, int32_t k) {
 
 template <int H, typename TX, typename TO, bool CENTER>
 void launch_pass(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void *x, const double *mean, TO *y,
-                 double omega, hipStream_t s) {
+                 double omega, hipStream_t s, int parts) {
     constexpr int wide = 128 / (int)sizeof(TX);
     switch (pass_cols<TX>(k)) {
-        case 4: launch_pass_kc<H, 4, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-        case 8: launch_pass_kc<H, 8, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-        case 12: launch_pass_kc<H, 12, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-        case 16: launch_pass_kc<H, 16, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+        case 4: launch_pass_kc<H, 4, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s, parts); return;
+        case 8: launch_pass_kc<H, 8, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s, parts); return;
+        case 12: launch_pass_kc<H, 12, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s, parts); return;
+        case 16: launch_pass_kc<H, 16, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s, parts); return;
         default: break;
     }
     if constexpr (wide == 32) {
         switch (pass_cols<TX>(k)) {
-            case 20: launch_pass_kc<H, 20, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-            case 24: launch_pass_kc<H, 24, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-            case 28: launch_pass_kc<H, 28, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
-            case 32: launch_pass_kc<H, 32, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s); return;
+            case 20: launch_pass_kc<H, 20, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s, parts); return;
+            case 24: launch_pass_kc<H, 24, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s, parts); return;
+            case 28: launch_pass_kc<H, 28, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s, parts); return;
+            case 32: launch_pass_kc<H, 32, TX, TO, CENTER>(k, m, mp, nb, x, mean, y, omega, s, parts); return;
             default: break;
         }
     }
@@ -1511,29 +1518,34 @@ void launch_pass(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void
 
 // Passes of H sweeps, the last one shorter when H does not divide the count;
 // with final_f32 (16-bit storage) the very last sweep stores FP32.
+// first_parts: the launches of the first pass to make here (the common-case
+// one may have gone out already); first_only: stop after the first pass.
+// p.mean holds the column means (enqueued earlier on the same stream).
 template <int H, typename TX>
 void run_smooth_passes(const sfg_csr *H_, int32_t k, int32_t sweeps, double omega, const double *x0, void *xout,
-                       bool final_f32, const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s) {
-    launch_column_means<double>(x0, H_->n, k, p.partial, p.mean, s);
+                       bool final_f32, const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s,
+                       int first_parts, bool first_only) {
     TX *b0 = (TX *)p.buf0, *b1 = (TX *)p.buf1;
     const TX *src = nullptr;
     for (int32_t done = 0, q = 0; done < sweeps; ++q) {
+        if (q == 1 && first_only) break;
+        const int parts = q == 0 ? first_parts : kPartBoth;
         const int32_t m = sweeps - done < H ? sweeps - done : H;
         const bool last = done + m == sweeps;
         TX *dst = last ? (TX *)xout : (q % 2 == 0 ? b0 : b1);
         if constexpr (sizeof(TX) == 2) {
             if (last && final_f32) {
                 if (q == 0)
-                    launch_pass<H, TX, float, true>(k, m, mp, nb, x0, p.mean, (float *)xout, omega, s);
+                    launch_pass<H, TX, float, true>(k, m, mp, nb, x0, p.mean, (float *)xout, omega, s, parts);
                 else
-                    launch_pass<H, TX, float, false>(k, m, mp, nb, src, nullptr, (float *)xout, omega, s);
+                    launch_pass<H, TX, float, false>(k, m, mp, nb, src, nullptr, (float *)xout, omega, s, parts);
                 break;
             }
         }
         if (q == 0)
-            launch_pass<H, TX, TX, true>(k, m, mp, nb, x0, p.mean, dst, omega, s);
+            launch_pass<H, TX, TX, true>(k, m, mp, nb, x0, p.mean, dst, omega, s, parts);
         else
-            launch_pass<H, TX, TX, false>(k, m, mp, nb, src, nullptr, dst, omega, s);
+            launch_pass<H, TX, TX, false>(k, m, mp, nb, src, nullptr, dst, omega, s, parts);
         src = dst;
         done += m;
     }
@@ -1541,17 +1553,35 @@ void run_smooth_passes(const sfg_csr *H_, int32_t k, int32_t sweeps, double omeg
 
 template <int H>
 void run_passes(sfg_dtype storage, const sfg_csr *G, int32_t k, int32_t sweeps, double omega, const double *x0,
-                void *x, bool final_f32, const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s) {
+                void *x, bool final_f32, const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s,
+                int first_parts, bool first_only) {
     switch (storage) {
-        case SFG_F64: run_smooth_passes<H, double>(G, k, sweeps, omega, x0, x, false, p, mp, nb, s); return;
-        case SFG_F32: run_smooth_passes<H, float>(G, k, sweeps, omega, x0, x, false, p, mp, nb, s); return;
-        case SFG_F16: run_smooth_passes<H, __half>(G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s); return;
+        case SFG_F64:
+            run_smooth_passes<H, double>(G, k, sweeps, omega, x0, x, false, p, mp, nb, s, first_parts, first_only);
+            return;
+        case SFG_F32:
+            run_smooth_passes<H, float>(G, k, sweeps, omega, x0, x, false, p, mp, nb, s, first_parts, first_only);
+            return;
+        case SFG_F16:
+            run_smooth_passes<H, __half>(G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s, first_parts,
+                                         first_only);
+            return;
         case SFG_BF16:
-            run_smooth_passes<H, __hip_bfloat16>(G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s);
+            run_smooth_passes<H, __hip_bfloat16>(G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s, first_parts,
+                                                 first_only);
             return;
         default: break;
     }
     fail(SFG_EUNSUPPORTED, "smooth_ordered: storage");
+}
+
+void run_passes_h(int hops, sfg_dtype storage, const sfg_csr *G, int32_t k, int32_t sweeps, double omega,
+                  const double *x0, void *x, bool final_f32, const SmoothPlan &p, const MpkPlan &mp, int64_t nb,
+                  hipStream_t s, int first_parts, bool first_only) {
+    if (hops == 4) run_passes<4>(storage, G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s, first_parts, first_only);
+    else if (hops == 3)
+        run_passes<3>(storage, G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s, first_parts, first_only);
+    else run_passes<2>(storage, G, k, sweeps, omega, x0, x, final_f32, p, mp, nb, s, first_parts, first_only);
 }
 
 template <int H>
@@ -1565,13 +1595,68 @@ void build_layout(const sfg_csr *G, const int32_t *order, const MpkPlan &mp, int
     SFG_LAUNCH_CHECK();
 }
 
+// The layout's two flag words, copied to pinned host memory (one buffer and
+// one event per device, created on first use and kept for the process).
+// begin() enqueues the copy; the host may enqueue more work before wait(),
+// which blocks until the copy is done (not until the stream drains).  The
+// buffer is held, under its device's lock, from begin() to wait().
+class FlagRead {
+  public:
+    FlagRead(MpkPlan &mp, hipStream_t s) : mp_(mp), s_(s) {
+        int dev = 0;
+        SFG_HIP(hipGetDevice(&dev));
+        SFG_REQUIRE(dev >= 0 && dev < 64, SFG_EUNSUPPORTED, "smooth_ordered: device index over 63");
+        Slot &sl = slot(dev);
+        lock_ = std::unique_lock<std::mutex>(sl.mu);
+        if (!sl.host) {
+            SFG_HIP(hipHostMalloc((void **)&sl.host, 2 * sizeof(int32_t), hipHostMallocDefault));
+            SFG_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+        }
+        sl_ = &sl;
+        SFG_HIP(hipMemcpyAsync(sl.host, mp.flag, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        SFG_HIP(hipEventRecord(sl.ev, s));
+    }
+    // Left without wait() (an error in between): the copy lands before the
+    // buffer goes to the next caller.
+    ~FlagRead() {
+        if (lock_.owns_lock()) (void)hipEventSynchronize(sl_->ev);
+    }
+    FlagRead(const FlagRead &) = delete;
+    FlagRead &operator=(const FlagRead &) = delete;
+    // The flag word; bit 0 (the order is not a permutation) raises SFG_EINVAL
+    // once the stream has drained, so nothing enqueued after begin() still
+    // runs when the error reaches the caller.
+    int32_t wait() {
+        SFG_HIP(hipEventSynchronize(sl_->ev));
+        const int32_t f = sl_->host[0];
+        mp_.nbig = sl_->host[1];
+        lock_.unlock();
+        if (f & 1) {
+            SFG_HIP(hipStreamSynchronize(s_));
+            fail(SFG_EINVAL, "smooth_ordered: order is not a permutation of the nodes");
+        }
+        return f;
+    }
+
+  private:
+    struct Slot {
+        std::mutex mu;
+        int32_t *host = nullptr;
+        hipEvent_t ev = nullptr;
+    };
+    static Slot &slot(int dev) {
+        static Slot slots[64];
+        return slots[dev];
+    }
+    MpkPlan &mp_;
+    hipStream_t s_;
+    Slot *sl_ = nullptr;
+    std::unique_lock<std::mutex> lock_;
+};
+
 int32_t read_flag(MpkPlan &mp, hipStream_t s) {
-    int32_t h[2] = {0, 0};
-    SFG_HIP(hipMemcpyAsync(h, mp.flag, sizeof(h), hipMemcpyDeviceToHost, s));
-    SFG_HIP(hipStreamSynchronize(s));
-    SFG_REQUIRE(!(h[0] & 1), SFG_EINVAL, "smooth_ordered: order is not a permutation of the nodes");
-    mp.nbig = h[1];
-    return h[0];
+    FlagRead fr(mp, s);
+    return fr.wait();
 }
 
 // Lists the blocks over the common-case capacity (flag[1] counts them).
@@ -1639,16 +1724,21 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
                           sweeps >= 2 && H->nnz >= 1 && H->col && H->val && H->deg && want >= 2;
     const int64_t nb = mpk_blocks(n);
     int hops = 0;
+    bool started = false;
     if (shape_ok) {
-        // the passes take the rows in this order: it must be a permutation of the nodes
+        SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_ordered: omega must be in (0, 1]");
+        SFG_REQUIRE(x0 && x, SFG_EINVAL, "smooth_ordered: null pointer");
+        const bool f32last = final_f32 && (storage == SFG_F16 || storage == SFG_BF16);
         fill_i32(mp.flag, 2, 0, s);
         if (order) {
+            // the passes take the rows in this order: it must be a permutation of the nodes
             hipLaunchKernelGGL(k_mpk_mark, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
             SFG_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_mpk_verify, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
             SFG_LAUNCH_CHECK();
         }
-        for (int h = want < kMpkMaxHops ? want : kMpkMaxHops; h >= 2 && hops == 0; --h) {
+        const int first = want < kMpkMaxHops ? want : kMpkMaxHops;
+        for (int h = first; h >= 2 && hops == 0; --h) {
             if (h == 4) {
                 build_layout<4>(H, order, mp, nb, s);
                 list_big<4>(mp, nb, storage, k, s);
@@ -1659,25 +1749,35 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
                 build_layout<2>(H, order, mp, nb, s);
                 list_big<2>(mp, nb, storage, k, s);
             }
-            if (read_flag(mp, s) & 2)
+            int32_t f;
+            if (h == first) {
+                // while the host waits for the flags, the GPU takes the column means and the common-case launch
+                // of the first pass: the start of the smoothing if the layout stands, redone otherwise (blocks
+                // that do not fit have zero sizes, so the launch stays inside every buffer either way)
+                FlagRead fr(mp, s);
+                launch_column_means<double>(x0, n, k, p.partial, p.mean, s);
+                run_passes_h(h, storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s, kPartSmall, true);
+                f = fr.wait();
+                started = !(f & 2);
+            } else {
+                f = read_flag(mp, s);
+            }
+            if (f & 2)
                 fill_i32(mp.flag, 2, 0, s);     // a block did not fit: fewer hops
             else
                 hops = h;
         }
+        if (hops >= 2) {
+            if (!started) launch_column_means<double>(x0, n, k, p.partial, p.mean, s);
+            run_passes_h(hops, storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s,
+                         started ? kPartListed : kPartBoth, false);
+            return hops;
+        }
     }
-    if (hops == 0) {
-        // the workspace starts with the plain smoothing's layout
-        smooth(H, k, sweeps, omega, x0, storage, final_f32, x, ws, smooth_workspace_bytes(n, k < 1 ? 1 : k, storage),
-               s, max_row);
-        return 1;
-    }
-    SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_ordered: omega must be in (0, 1]");
-    SFG_REQUIRE(x0 && x, SFG_EINVAL, "smooth_ordered: null pointer");
-    const bool f32last = final_f32 && (storage == SFG_F16 || storage == SFG_BF16);
-    if (hops == 4) run_passes<4>(storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s);
-    else if (hops == 3) run_passes<3>(storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s);
-    else run_passes<2>(storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s);
-    return hops;
+    // the workspace starts with the plain smoothing's layout
+    smooth(H, k, sweeps, omega, x0, storage, final_f32, x, ws, smooth_workspace_bytes(n, k < 1 ? 1 : k, storage), s,
+           max_row);
+    return 1;
 }
 
 // Column means of a block (exact to double-double before one rounding);
