@@ -263,10 +263,13 @@ def headline(args, S, BW) -> dict:
     per_pass = int(P["info"].get("sweeps_per_pass", 1))
     fused = per_pass >= 2
     if fused:
-        # a launch takes per_pass sweeps: a call of per_pass sweeps is the same layout and the centring first
-        # pass alone, so the difference is the T - per_pass sweeps of the remaining launches
-        t_one = BW.ev_time(lambda: P["smooth"](per_pass), reps)
-        t_sweep = (t_smooth - t_one) / (T - per_pass)
+        # a launch takes per_pass sweeps: a call of two passes is the same layout, the centring first pass and
+        # one more, so the difference is the T - 2 per_pass sweeps of the remaining launches (a call of a single
+        # pass would be too short to take the passes at all)
+        t0_sweeps = 2 * per_pass
+        t_one = BW.ev_time(lambda: P["smooth"](t0_sweeps), reps)
+        assert int(P["info"].get("sweeps_per_pass", 1)) == per_pass, "the two-pass call did not take the passes"
+        t_sweep = (t_smooth - t_one) / (T - t0_sweeps)
     else:
         t_one = BW.ev_time(lambda: P["smooth"](1), reps)
         # the first sweep also centres (reads the FP64 block); the other T-1 are plain sweeps
@@ -339,7 +342,7 @@ def headline(args, S, BW) -> dict:
         "cpu_baseline": None,
         "copy": copy,
         "stages_ms": {"csr": round(t_csr, 4), "smooth": round(t_smooth, 4),
-                      (f"smooth_{per_pass}sweeps" if fused else "smooth_1sweep"): round(t_one, 4),
+                      (f"smooth_{2 * per_pass}sweeps" if fused else "smooth_1sweep"): round(t_one, 4),
                       "sweep": round(t_sweep, 4), "score": round(t_score, 4), "select": round(t_select, 4)},
         "edges_scored_per_s_score_kernel": round(ncand / (t_score * 1e-3), 1),
         "score_gbs": round(bsc / (t_score * 1e-3) / 1e9, 1),
@@ -367,8 +370,9 @@ def headline(args, S, BW) -> dict:
         # P32["sel"] holds the selection of the last timed step, made before these smoothing timings
         pp32 = int(P32["info"].get("sweeps_per_pass", 1))
         if pp32 >= 2:
-            t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](pp32),
-                                                                             reps)) / (T - pp32)
+            t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](2 * pp32),
+                                                                             reps)) / (T - 2 * pp32)
+            assert int(P32["info"].get("sweeps_per_pass", 1)) == pp32, "the two-pass call did not take the passes"
         else:
             t32 = (BW.ev_time(lambda: P32["smooth"](T), reps) - BW.ev_time(lambda: P32["smooth"](1), reps)) / (T - 1)
         b32 = sweep_bytes(g.n, nnz, k, 4, 4)

@@ -190,7 +190,7 @@ sfg_status sfg_smooth(const sfg_csr *H, int32_t k, int32_t sweeps, double omega,
  *                 whenever the passes run; unused, and not read, otherwise)
  *   per_pass_out  (host, may be NULL): the sweeps each pass took, 2 to 4; 1 if
  *                 the call ran sfg_smooth instead: sweeps x k x (bytes of a
- *                 storage value) under 640 (a narrow block's few sweeps do
+ *                 storage value) under 320 (a narrow block's few sweeps do
  *                 not repay the layout pass), k not a multiple of 4 or
  *                 over 128 bytes per row (F16/BF16: over 16 columns), fewer
  *                 than 2 sweeps, a reduced-precision row over 256 entries

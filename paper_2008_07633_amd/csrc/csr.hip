@@ -9,13 +9,16 @@
 //
 //  1. the edge-list slice of every row (its upper edges) by one coalesced
 //     pass over u
-//  2. a thread per row walks its slice: it counts its included upper edges
-//     and adds one to the lower count of each one's other end (integer
-//     atomics); slices over kWalk edges are walked by a wavefront instead;
-//     one scan of the row totals gives rowptr
-//  3. the same walk again: the row writes its upper entries in place, in
-//     order, and drops each edge into the lower part of its other row at an
-//     atomic slot (column, weight and id written there)
+//  2. sparse edge lists (at most kWalkDensity edges per node): a thread per
+//     row walks its slice: it counts its included upper edges and adds one to
+//     the lower count of each one's other end (integer atomics); slices over
+//     kWalk edges are walked by a wavefront instead.  Denser lists: a thread
+//     per edge counts, and a scan of the mask flags ranks the included edges
+//     within their slices.  One scan of the row totals gives rowptr
+//  3. the same walk again (denser lists: a thread per edge): each included
+//     edge writes its upper entry in place, in order, and drops itself into
+//     the lower part of its other row at an atomic slot (column, weight and
+//     id written there)
 //  4. lower parts of two or more entries are put in edge-id order: a thread
 //     per row ranks up to kRegSeg entries in registers, a workgroup per longer
 //     row bitonic-sorts the ids in LDS
@@ -30,12 +33,13 @@ namespace {
 
 constexpr int kWalk = 64;           // upper slices longer than this: walked by a wavefront
 constexpr int kRegSeg = 8;          // lower parts up to this length: ranked in registers by one thread
+constexpr int kShortSeg = 32;       // up to this length: ranked by one thread; longer ones by a workgroup
 constexpr int kLdsSeg = 8192;       // longer ones are sorted in LDS up to this length
 constexpr int kDegLong = 256;       // rows longer than this: degree summed by a workgroup
 
 struct CsrPlan {
     int32_t *estart, *up, *cnt_lo, *tot, *fill, *tmp, *walk_rows, *walk_cnt, *long_rows, *long_cnt, *deg_rows,
-        *deg_cnt, *scan;
+        *deg_cnt, *inc, *incpos, *scan;
     int32_t *zeroed;      // cnt_lo, fill, the three list counters: one contiguous range, cleared by one fill
     int64_t zeroed_len;
 };
@@ -56,9 +60,17 @@ CsrPlan plan_csr(Carver &c, int64_t n, int64_t m) {
     p.walk_rows = c.take<int32_t>(n + 1);
     p.long_rows = c.take<int32_t>(n + 1);
     p.deg_rows = c.take<int32_t>(n + 1);
-    p.scan = c.take<int32_t>(scan_scratch_ints(n + 1));
+    p.inc = c.take<int32_t>(m + 1);
+    p.incpos = c.take<int32_t>(m + 1);
+    p.scan = c.take<int32_t>(scan_scratch_ints((n > m ? n : m) + 1));
     return p;
 }
+
+// Graphs whose edge list holds at most this many edges per node (meshes,
+// trees, power grids) are built by row walks; denser ones (power-law graphs,
+// coarse Galerkin graphs) have many slices too long for one thread and are
+// built edge-parallel.  Both give the same CSR.
+constexpr int64_t kWalkDensity = 4;
 
 // estart[p] = first edge with u >= p (p = 0..n).  The edge list is sorted by
 // u, so edge e (e = 0..m, with u[-1] = -1 and u[m] = n) is that first edge for
@@ -255,19 +267,114 @@ __global__ __launch_bounds__(256) void k_walk_fill_long(int64_t n, int64_t m, co
     }
 }
 
-// Lower parts of 2..kRegSeg entries: read into registers, each entry written
-// back at its rank by edge id (ids in a row are distinct).  Longer parts are
-// listed for k_rank_long; parts of one entry are in place already.
+// ---- edge-parallel build of denser graphs: mask flags and their scan give
+// each included edge its rank within its row's slice; one thread per edge
+// writes the upper entry in place and drops the lower entry at an atomic slot
+// of its other row, as put_edge does for the walks.
+__global__ void k_inc_count(int64_t m, const int32_t *__restrict__ v, const uint8_t *__restrict__ mask, int32_t *inc,
+                            int32_t *cnt_lo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    const bool in = mask[e] != 0;
+    inc[e] = in ? 1 : 0;
+    if (in) atomicAdd(&cnt_lo[v[e]], 1);
+}
+
+__global__ void k_count_lo(int64_t m, const int32_t *__restrict__ v, int32_t *cnt_lo) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) atomicAdd(&cnt_lo[v[e]], 1);
+}
+
+__global__ void k_row_total_edges(int64_t n, const int32_t *__restrict__ estart, const int32_t *__restrict__ incpos,
+                                  const int32_t *__restrict__ cnt_lo, int32_t *tot) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t a = estart[p], b = estart[p + 1];
+    tot[p] = cnt_lo[p] + (incpos ? incpos[b] - incpos[a] : b - a);
+}
+
+// The lower entries of this build go to their rows as edge ids only (tmp, at
+// an atomic slot); k_rank_short_ids then writes them, ordered, with their
+// columns and weights gathered from the edge list.
+template <typename TW>
+__global__ void k_fill_edges(int64_t m, const int32_t *__restrict__ u, const int32_t *__restrict__ v,
+                             const TW *__restrict__ w, const uint8_t *__restrict__ mask,
+                             const int32_t *__restrict__ incpos, const int32_t *__restrict__ estart,
+                             const int32_t *__restrict__ rowptr, const int32_t *__restrict__ cnt_lo, int32_t *col,
+                             TW *val, int32_t *eid, int32_t *fill, int32_t *tmp) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m) return;
+    if (mask && mask[e] == 0) return;
+    const int32_t p = u[e], q = v[e];
+    const int32_t k = incpos ? incpos[e] - incpos[estart[p]] : (int32_t)(e - estart[p]);
+    const int32_t j = rowptr[p] + cnt_lo[p] + k;
+    col[j] = q;
+    val[j] = w[e];
+    eid[j] = (int32_t)e;
+    tmp[rowptr[q] + atomicAdd(&fill[q], 1)] = (int32_t)e;
+}
+
+// Lower parts of up to kShortSeg ids in tmp: ids in a segment are distinct,
+// so the rank of an id is the number of smaller ids; the entry (column and
+// weight gathered from the edge list) goes to base + rank.  Longer parts are
+// listed for k_rank_long.
+
+template <typename TW>
+__global__ __launch_bounds__(256) void k_rank_short_ids(int64_t n, const int32_t *__restrict__ rowptr,
+                                                        const int32_t *__restrict__ cnt_lo,
+                                                        const int32_t *__restrict__ tmp,
+                                                        const int32_t *__restrict__ u, const TW *__restrict__ w,
+                                                        int32_t *col, TW *val, int32_t *eid, int32_t *long_rows,
+                                                        int32_t *long_cnt) {
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= n) return;
+    const int32_t len = cnt_lo[row];
+    if (len > kShortSeg) {
+        long_rows[atomicAdd(long_cnt, 1)] = (int32_t)row;
+        return;
+    }
+    const int32_t base = rowptr[row];
+    for (int32_t i = 0; i < len; ++i) {
+        const int32_t mine = tmp[base + i];
+        int32_t rank = 0;
+        for (int32_t j = 0; j < len; ++j) rank += (tmp[base + j] < mine) ? 1 : 0;
+        col[base + rank] = u[mine];
+        val[base + rank] = w[mine];
+        eid[base + rank] = mine;
+    }
+}
+
+// Lower parts written in place at atomic slots (the row walks): parts of
+// 2..kRegSeg entries are read into registers and each entry written back at
+// its rank by edge id (ids in a row are distinct); parts up to kShortSeg are
+// ranked from a copy of their ids in tmp; longer ones are listed for
+// k_rank_long.  Parts of one entry are in place already.
 template <typename TW>
 __global__ __launch_bounds__(256) void k_rank_short(int64_t n, const int32_t *__restrict__ rowptr,
-                                                    const int32_t *__restrict__ cnt_lo, int32_t *col, TW *val,
-                                                    int32_t *eid, int32_t *long_rows, int32_t *long_cnt) {
+                                                    const int32_t *__restrict__ cnt_lo,
+                                                    const int32_t *__restrict__ u, const TW *__restrict__ w,
+                                                    int32_t *col, TW *val, int32_t *eid, int32_t *tmp,
+                                                    int32_t *long_rows, int32_t *long_cnt) {
     const int64_t row = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (row >= n) return;
     const int32_t len = cnt_lo[row];
     if (len < 2) return;
-    if (len > kRegSeg) {
+    if (len > kShortSeg) {
         long_rows[atomicAdd(long_cnt, 1)] = (int32_t)row;
+        return;
+    }
+    if (len > kRegSeg) {
+        // ranked from a copy of the ids (the entries are rewritten in place), columns and weights gathered
+        const int32_t b0 = rowptr[row];
+        for (int32_t i = 0; i < len; ++i) tmp[b0 + i] = eid[b0 + i];
+        for (int32_t i = 0; i < len; ++i) {
+            const int32_t mine = tmp[b0 + i];
+            int32_t rank = 0;
+            for (int32_t j = 0; j < len; ++j) rank += (tmp[b0 + j] < mine) ? 1 : 0;
+            col[b0 + rank] = u[mine];
+            val[b0 + rank] = w[mine];
+            eid[b0 + rank] = mine;
+        }
         return;
     }
     const int32_t base = rowptr[row];
@@ -300,9 +407,10 @@ __device__ __forceinline__ void put_lower(int32_t j, int32_t e, const int32_t *_
     eid[j] = e;
 }
 
-// Long lower parts: up to kLdsSeg ids are bitonic-sorted in LDS (padded to a
-// power of two with INT32_MAX); longer ones are ranked from global memory.
-template <typename TW>
+// Long lower parts: up to kLdsSeg ids (from tmp, or from the row's own eid
+// entries) are bitonic-sorted in LDS (padded to a power of two with
+// INT32_MAX); longer ones are ranked from global memory (from a copy in tmp).
+template <typename TW, bool IDS_IN_TMP>
 __global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ rowptr,
                                                    const int32_t *__restrict__ cnt_lo, int32_t *tmp,
                                                    const int32_t *__restrict__ u,
@@ -318,7 +426,8 @@ __global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ r
         if (len <= kLdsSeg) {
             int32_t pw = 1;
             while (pw < len) pw <<= 1;
-            for (int32_t i = threadIdx.x; i < pw; i += blockDim.x) seg[i] = i < len ? eid[base + i] : INT32_MAX;
+            const int32_t *ids = IDS_IN_TMP ? tmp : eid;
+            for (int32_t i = threadIdx.x; i < pw; i += blockDim.x) seg[i] = i < len ? ids[base + i] : INT32_MAX;
             __syncthreads();
             for (int32_t kk = 2; kk <= pw; kk <<= 1) {
                 for (int32_t jj = kk >> 1; jj > 0; jj >>= 1) {
@@ -338,9 +447,11 @@ __global__ __launch_bounds__(256) void k_rank_long(const int32_t *__restrict__ r
             }
             for (int32_t i = threadIdx.x; i < len; i += blockDim.x) put_lower(base + i, seg[i], u, w, col, val, eid);
         } else {
-            // ranked from a copy: the entries are rewritten in place
-            for (int32_t i = threadIdx.x; i < len; i += blockDim.x) tmp[base + i] = eid[base + i];
-            __syncthreads();
+            if (!IDS_IN_TMP) {
+                // ranked from a copy: the entries are rewritten in place
+                for (int32_t i = threadIdx.x; i < len; i += blockDim.x) tmp[base + i] = eid[base + i];
+                __syncthreads();
+            }
             for (int32_t i = threadIdx.x; i < len; i += blockDim.x) {
                 const int32_t mine = tmp[base + i];
                 int32_t rank = 0;
@@ -411,23 +522,35 @@ __global__ __launch_bounds__(256) void k_degree_long(const int32_t *__restrict__
 }
 
 template <typename TW>
-void fill_entries(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const TW *w, const uint8_t *mask,
-                  const CsrPlan &p, const int32_t *rowptr, int32_t *col, TW *val, int32_t *eid, TW *deg,
-                  hipStream_t s) {
+void fill_entries(bool walk, int64_t n, int64_t m, const int32_t *u, const int32_t *v, const TW *w,
+                  const uint8_t *mask, const CsrPlan &p, const int32_t *rowptr, int32_t *col, TW *val, int32_t *eid,
+                  TW *deg, hipStream_t s) {
     const dim3 gn(grid_for(n, 256)), b(256);
     if (m > 0) {
-        hipLaunchKernelGGL(k_walk_fill<TW>, gn, b, 0, s, n, m, p.estart, v, w, mask, rowptr, p.cnt_lo, col, val, eid,
-                           p.fill);
-        SFG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_walk_fill_long<TW>, dim3(256), b, 0, s, n, m, p.estart, v, w, mask, rowptr, p.cnt_lo,
-                           col, val, eid, p.fill, p.walk_rows, p.walk_cnt);
-        SFG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_rank_short<TW>, gn, b, 0, s, n, rowptr, p.cnt_lo, col, val, eid, p.long_rows,
-                           p.long_cnt);
-        SFG_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_rank_long<TW>, dim3(512), b, 0, s, rowptr, p.cnt_lo, p.tmp, u, w, col, val, eid,
-                           p.long_rows, p.long_cnt);
-        SFG_LAUNCH_CHECK();
+        if (walk) {
+            hipLaunchKernelGGL(k_walk_fill<TW>, gn, b, 0, s, n, m, p.estart, v, w, mask, rowptr, p.cnt_lo, col, val,
+                               eid, p.fill);
+            SFG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_walk_fill_long<TW>, dim3(256), b, 0, s, n, m, p.estart, v, w, mask, rowptr,
+                               p.cnt_lo, col, val, eid, p.fill, p.walk_rows, p.walk_cnt);
+            SFG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_rank_short<TW>, gn, b, 0, s, n, rowptr, p.cnt_lo, u, w, col, val, eid, p.tmp,
+                               p.long_rows, p.long_cnt);
+            SFG_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_rank_long<TW, false>), dim3(512), b, 0, s, rowptr, p.cnt_lo, p.tmp, u, w, col, val,
+                               eid, p.long_rows, p.long_cnt);
+            SFG_LAUNCH_CHECK();
+        } else {
+            hipLaunchKernelGGL(k_fill_edges<TW>, dim3(grid_for(m, 256)), b, 0, s, m, u, v, w, mask,
+                               mask ? p.incpos : nullptr, p.estart, rowptr, p.cnt_lo, col, val, eid, p.fill, p.tmp);
+            SFG_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_rank_short_ids<TW>, gn, b, 0, s, n, rowptr, p.cnt_lo, p.tmp, u, w, col, val, eid,
+                               p.long_rows, p.long_cnt);
+            SFG_LAUNCH_CHECK();
+            hipLaunchKernelGGL((k_rank_long<TW, true>), dim3(512), b, 0, s, rowptr, p.cnt_lo, p.tmp, u, w, col, val,
+                               eid, p.long_rows, p.long_cnt);
+            SFG_LAUNCH_CHECK();
+        }
     }
     hipLaunchKernelGGL(k_degree<TW>, gn, b, 0, s, n, rowptr, val, deg, p.deg_rows, p.deg_cnt);
     SFG_LAUNCH_CHECK();
@@ -594,19 +717,36 @@ void build_csr(int64_t n, int64_t m, const int32_t *u, const int32_t *v, const v
     hipLaunchKernelGGL(k_estart, dim3(grid_for((m + kEdgesPerThread) / kEdgesPerThread, 256)), b, 0, s, n, m, u,
                        p.estart);
     SFG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_walk_count, gn, b, 0, s, n, m, p.estart, v, mask, p.up, p.cnt_lo, p.walk_rows, p.walk_cnt);
-    SFG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_walk_count_long, dim3(256), b, 0, s, n, m, p.estart, v, mask, p.up, p.cnt_lo, p.walk_rows,
-                       p.walk_cnt);
-    SFG_LAUNCH_CHECK();
-    hipLaunchKernelGGL(k_row_total, gn, b, 0, s, n, p.up, p.cnt_lo, p.tot);
-    SFG_LAUNCH_CHECK();
+    const bool walk = m <= kWalkDensity * n;
+    if (walk) {
+        hipLaunchKernelGGL(k_walk_count, gn, b, 0, s, n, m, p.estart, v, mask, p.up, p.cnt_lo, p.walk_rows,
+                           p.walk_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_walk_count_long, dim3(256), b, 0, s, n, m, p.estart, v, mask, p.up, p.cnt_lo,
+                           p.walk_rows, p.walk_cnt);
+        SFG_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_row_total, gn, b, 0, s, n, p.up, p.cnt_lo, p.tot);
+        SFG_LAUNCH_CHECK();
+    } else {
+        const dim3 gm(grid_for(m, 256));
+        if (mask) {
+            hipLaunchKernelGGL(k_inc_count, gm, b, 0, s, m, v, mask, p.inc, p.cnt_lo);
+            SFG_LAUNCH_CHECK();
+            exclusive_scan_i32(p.inc, p.incpos, m, p.scan, s);
+        } else {
+            hipLaunchKernelGGL(k_count_lo, gm, b, 0, s, m, v, p.cnt_lo);
+            SFG_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_row_total_edges, gn, b, 0, s, n, p.estart, mask ? p.incpos : nullptr, p.cnt_lo, p.tot);
+        SFG_LAUNCH_CHECK();
+    }
     exclusive_scan_i32(p.tot, rowptr, n, p.scan, s);
     if (wt == SFG_F64)
-        fill_entries<double>(n, m, u, v, (const double *)w, mask, p, rowptr, col, (double *)val, eid, (double *)deg,
-                             s);
+        fill_entries<double>(walk, n, m, u, v, (const double *)w, mask, p, rowptr, col, (double *)val, eid,
+                             (double *)deg, s);
     else
-        fill_entries<float>(n, m, u, v, (const float *)w, mask, p, rowptr, col, (float *)val, eid, (float *)deg, s);
+        fill_entries<float>(walk, n, m, u, v, (const float *)w, mask, p, rowptr, col, (float *)val, eid,
+                            (float *)deg, s);
 }
 
 }  // namespace sfg

@@ -1676,12 +1676,13 @@ void list_big(MpkPlan &mp, int64_t nb, sfg_dtype storage, int32_t k, hipStream_t
 // sweeps each pass over X took: 1 when the plain path ran, else 2 to 4.
 // The passes are taken when sweeps x (bytes of a block row) >= kMpkMinBytes:
 // the layout pass and the per-block local CSR cost about as much as a few
-// sweeps of a narrow block.  Measured on the 200^3 mesh's tree (one call
-// with the CSR build, scores and selection): FP32 8 vectors, 20 sweeps 4.37
-// ms with passes against 5.63 without; FP32 4 vectors, 10 sweeps 3.07
-// against 2.85; BF16 4 vectors, 10 sweeps (a step of the surrogate's) 6.68
-// against 6.25.  Setting SFG_SWEEP_HOPS takes the passes at any width.
-constexpr int64_t kMpkMinBytes = 640;
+// sweeps of a narrow block.  Measured on the 200^3 mesh's tree (one
+// smoothing call, passes of 3 against one sweep per launch): BF16 16
+// vectors, 10 sweeps (320 bytes) 2.50 ms against 3.04; FP32 4 vectors, 20
+// sweeps (320) 2.35 against 2.74; FP32 4 vectors, 10 sweeps (160) 1.57
+// against 1.49; BF16 4 vectors, 20 sweeps (160) 2.35 against 2.28.
+// Setting SFG_SWEEP_HOPS takes the passes at any width.
+constexpr int64_t kMpkMinBytes = 320;
 // Graphs averaging more entries per row than this (whole meshes, power-law
 // graphs) have 1-hop halos beyond the layout's capacities for 64-row blocks:
 // they go to the plain path without trying a layout (SFG_SWEEP_HOPS still

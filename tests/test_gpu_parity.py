@@ -41,6 +41,8 @@ def host(t):
 GRAPHS = {
     "grid64": lambda: W.workload_graph("grid64"),
     "rand1500": lambda: W.random_connected(1500, 4000, seed=71, wdist=("lognormal", 0.0, 1.0)),
+    # over 4 edges per node: the CSR is built edge-parallel instead of by row walks
+    "dense800": lambda: W.random_connected(800, 6400, seed=75, wdist=("lognormal", 0.0, 1.0)),
     "pgrid_97": lambda: W.powergrid(97, 103, 0.02, seed=72),
     "mesh_13": lambda: W.mesh3d(13, 11, 9, seed=73),
     "path2": lambda: W.grid2d(1, 2, seed=74),
@@ -513,6 +515,31 @@ def test_csr_long_lower_parts(S, orc, n, center):
     H = S.sfg_laplacian_csr(n, dev(u), dev(v), dev(w))
     assert np.array_equal(host(H.col)[:H.nnz], ref.col)
     assert np.array_equal(host(H.eid)[:H.nnz], ref.eid)
+    assert np.array_equal(host(H.val)[:H.nnz], ref.val)
+    assert np.array_equal(host(H.deg), ref.deg)
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_csr_medium_lower_parts(S, orc, masked):
+    # a path (under 4 edges per node: the row walks) with rows whose lower parts hold 2..40 entries: in registers
+    # up to 8, ranked by one thread from a copy up to 32, by a workgroup beyond
+    n = 3000
+    rng = np.random.default_rng(91)
+    key = [np.arange(n - 1) * n + np.arange(1, n)]
+    for q, cnt in ((2999, 20), (2998, 9), (2990, 32), (2980, 33), (2970, 40), (2960, 8), (2950, 2)):
+        lo = rng.choice(q - 1, cnt, replace=False)
+        key.append(lo * n + q)
+    key = np.unique(np.concatenate(key))
+    u, v = (key // n).astype(np.int32), (key % n).astype(np.int32)
+    w = rng.uniform(0.5, 2.0, u.shape[0])
+    sel = rng.random(u.shape[0]) < 0.8 if masked else np.ones(u.shape[0], bool)
+    assert u.shape[0] <= 4 * n
+    ref = orc.laplacian_csr(n, u[sel], v[sel], w[sel])
+    H = S.sfg_laplacian_csr(n, dev(u), dev(v), dev(w), mask=dev(sel.astype(np.uint8)) if masked else None)
+    assert H.nnz == ref.col.shape[0]
+    assert np.array_equal(host(H.rowptr), ref.rowptr.astype(np.int32))
+    assert np.array_equal(host(H.col)[:H.nnz], ref.col)
+    assert np.array_equal(host(H.eid)[:H.nnz], np.nonzero(sel)[0][ref.eid])
     assert np.array_equal(host(H.val)[:H.nnz], ref.val)
     assert np.array_equal(host(H.deg), ref.deg)
 
