@@ -72,14 +72,42 @@ __global__ void k_lap(int64_t n, int32_t k, const int32_t *__restrict__ rowptr, 
 
 __device__ __forceinline__ double safe_div(double a, double b) { return b != 0.0 ? a / b : 0.0; }
 
-// p = z + beta p with beta_c = rz_new_c / rz_c on active columns
-__global__ void k_cg_dir(int64_t n, int32_t k, uint32_t active, const double *__restrict__ rz_new,
-                         const double *__restrict__ rz, const double *__restrict__ z, double *__restrict__ p) {
+// p = z + beta p with beta_c = rz_new_c / rz_c on active columns (the mask
+// `active`, or *dmask when the device keeps it)
+__global__ void k_cg_dir(int64_t n, int32_t k, uint32_t active, const uint32_t *__restrict__ dmask,
+                         const double *__restrict__ rz_new, const double *__restrict__ rz,
+                         const double *__restrict__ z, double *__restrict__ p) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * k) return;
     const int c = (int)(t % k);
-    if (!((active >> c) & 1u)) return;
+    const uint32_t act = dmask ? *dmask : active;
+    if (!((act >> c) & 1u)) return;
     p[t] = z[t] + safe_div(rz_new[c], rz[c]) * p[t];
+}
+
+// Convergence test on the device, after each iteration: a column whose
+// ||r||^2 is no longer above tol^2 ||z||^2 leaves the mask (the same test, on
+// the same values, as the host makes otherwise); *dit counts the iterations
+// that had an active column.
+__global__ void k_cg_check(int32_t k, const double *__restrict__ rr, const double *__restrict__ zz, double tol2,
+                           uint32_t *dmask, int64_t *dit) {
+    if (threadIdx.x != 0) return;
+    uint32_t m = *dmask;
+    if (m) ++*dit;
+    for (int c = 0; c < k; ++c)
+        if (((m >> c) & 1u) && !(rr[c] > tol2 * zz[c])) m &= ~(1u << c);
+    *dmask = m;
+}
+
+// Iterations between the host's reads of a device-kept convergence mask
+// (after the first few, which are read at 1, 2, 4 and 8).
+constexpr int kPoll = 16;
+
+__global__ void k_cg_mask_init(uint32_t active, uint32_t *dmask, int64_t *dit) {
+    if (threadIdx.x == 0) {
+        *dmask = active;
+        *dit = 0;
+    }
 }
 
 __global__ void k_zero(int64_t cnt, double *__restrict__ x) {
@@ -221,6 +249,7 @@ __global__ void k_lap_resid(int64_t n, int32_t k, const int32_t *__restrict__ ro
 
 // x += alpha p, r -= alpha Ap (alpha_c = rz_c / pAp_c on active columns) and partial sums of r . r
 __global__ __launch_bounds__(kB) void k_cg_step_rr(int64_t n, int32_t k, uint32_t active,
+                                                   const uint32_t *__restrict__ dmask,
                                                    const double *__restrict__ rz, const double *__restrict__ pap,
                                                    const double *__restrict__ p, const double *__restrict__ ap,
                                                    double *__restrict__ x, double *__restrict__ r,
@@ -228,7 +257,7 @@ __global__ __launch_bounds__(kB) void k_cg_step_rr(int64_t n, int32_t k, uint32_
     __shared__ double sh[kB];
     const int G = kB / k;
     const int g = threadIdx.x / k, c = threadIdx.x % k;
-    const bool on = (active >> c) & 1u;
+    const bool on = ((dmask ? *dmask : active) >> c) & 1u;
     const double a = on ? safe_div(rz[c], pap[c]) : 0.0;
     double acc = 0.0;
     if (g < G)
@@ -465,7 +494,10 @@ struct KappaEstimator {
     // from X = Y diag(theta) when theta is given, else from 0.  A column stops
     // when ||r|| <= tol ||Z||.  Returns the iterations; *hit_cap at the cap.
     // check_every: convergence test every so many iterations (each costs a wait
-    // for the host); an exact preconditioner (P = its tree) converges in one
+    // for the host); an exact preconditioner (P = its tree) converges in one.
+    // check_every = 0: the test runs on the device after every iteration (a
+    // converged column stops changing at once, as with a host test every
+    // iteration) and the host only polls the mask every kPoll iterations.
     int64_t solve(double tol, int32_t max_iter, const double *theta, bool *hit_cap, int check_every = 4) {
         double *rz0 = small, *rz1 = small + 64, *pap = small + 128, *rr = small + 192, *zz = small + 256;
         const dim3 g(grid_for(n * k, kB)), b(kB);
@@ -491,7 +523,17 @@ struct KappaEstimator {
         if (!active) return 0;
         tree_precond_pre(&T, k, R, Zp, rz0, pre_ws, s);
         SFG_HIP(hipMemcpyAsync(Pd, Zp, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
-        const int kCheck = check_every < 1 ? 1 : check_every;
+        const bool dev_check = check_every == 0;
+        const int kCheck = dev_check ? kPoll : (check_every < 1 ? 1 : check_every);
+        uint32_t *dmask = nullptr;
+        int64_t *dit = nullptr;
+        if (dev_check) {
+            dmask = reinterpret_cast<uint32_t *>(small + 320 + 64);
+            dit = reinterpret_cast<int64_t *>(small + 320 + 65);
+            hipLaunchKernelGGL(k_cg_mask_init, dim3(1), dim3(64), 0, s, active, dmask, dit);
+            SFG_LAUNCH_CHECK();
+        }
+        const double tol2 = tol * tol;
         int64_t it = 0;
         while (active) {
             if (it == max_iter) {
@@ -507,18 +549,38 @@ struct KappaEstimator {
                                    part);
             SFG_LAUNCH_CHECK();
             finish_partials((int32_t)(k % 2 == 0 ? lg2 : lg), k, part, pap, s);
-            hipLaunchKernelGGL(k_cg_step_rr, dim3(lg), dim3(kB), 0, s, n, k, active, rz0, pap, Pd, AP, X, R, part);
+            hipLaunchKernelGGL(k_cg_step_rr, dim3(lg), dim3(kB), 0, s, n, k, active, dmask, rz0, pap, Pd, AP, X, R,
+                               part);
             SFG_LAUNCH_CHECK();
             finish_partials((int32_t)lg, k, part, rr, s);
             tree_precond_pre(&T, k, R, Zp, rz1, pre_ws, s);
-            hipLaunchKernelGGL(k_cg_dir, g, b, 0, s, n, k, active, rz1, rz0, Zp, Pd);
+            hipLaunchKernelGGL(k_cg_dir, g, b, 0, s, n, k, active, dmask, rz1, rz0, Zp, Pd);
             SFG_LAUNCH_CHECK();
             std::swap(rz0, rz1);
-            if (it % kCheck == 0 || it == max_iter) {
+            if (dev_check) {
+                hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, s, k, rr, zz, tol2, dmask, dit);
+                SFG_LAUNCH_CHECK();
+                // polls after iterations 1, 2, 4, 8, then every kPoll: a solve that converges at once (an
+                // exact preconditioner) is not run on for kPoll iterations
+                const bool poll = (it < kPoll && (it & (it - 1)) == 0) || it % kCheck == 0 || it == max_iter;
+                if (poll) {
+                    uint32_t hm = 0;
+                    SFG_HIP(hipMemcpyAsync(&hm, dmask, sizeof(hm), hipMemcpyDeviceToHost, s));
+                    SFG_HIP(hipStreamSynchronize(s));
+                    active = hm;
+                }
+            } else if (it % kCheck == 0 || it == max_iter) {
                 const std::vector<double> h = to_host(rr, k);
                 for (int c = 0; c < k; ++c)
-                    if (((active >> c) & 1u) && !(h[c] > tol * tol * hz[c])) active &= ~(1u << c);
+                    if (((active >> c) & 1u) && !(h[c] > tol2 * hz[c])) active &= ~(1u << c);
             }
+        }
+        if (dev_check) {
+            // iterations after every column had converged changed nothing: count the ones that did
+            int64_t hit = 0;
+            SFG_HIP(hipMemcpyAsync(&hit, dit, sizeof(hit), hipMemcpyDeviceToHost, s));
+            SFG_HIP(hipStreamSynchronize(s));
+            return hit;
         }
         return it;
     }
@@ -692,9 +754,10 @@ int64_t run_pcg(KappaEstimator &e, const uint8_t *keep, const double *b, double 
         hipLaunchKernelGGL(k_ground_rhs, g, blk, 0, s, n, rin, sum, e.Z);
         SFG_LAUNCH_CHECK();
         bool cap = false;
-        // checked every iteration: iterations past convergence would only add
-        // rounding noise, which the tree solve amplifies, to the preconditioner
-        inner += e.solve(inner_tol, inner_max, nullptr, &cap, 1);
+        // tested after every iteration, on the device: iterations past
+        // convergence would only add rounding noise, which the tree solve
+        // amplifies, to the preconditioner
+        inner += e.solve(inner_tol, inner_max, nullptr, &cap, 0);
         capped = capped || cap;
         hipLaunchKernelGGL(k_shift0, g, blk, 0, s, n, e.X, zout);
         SFG_LAUNCH_CHECK();
