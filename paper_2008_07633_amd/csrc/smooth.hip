@@ -931,7 +931,15 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
         }
     }
     __syncthreads();
-    // L(h+1): neighbours of the rows of Lh not yet in the map
+    // L(h+1): neighbours of the rows of Lh not yet in the map.  A row this lane
+    // discovers as row q 64 + lane (every row when the layers start at
+    // multiples of 64, as full blocks' first two do) keeps its entry range
+    // and first columns in registers for the local CSR below.
+    constexpr int Q = (C::kRows + 63) / 64;
+    int32_t sj0[Q], slen[Q], scol[Q][kMpkRegCols];
+    bool have[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) have[q] = false;
     int ends[H + 1];
     ends[0] = s0;
     int lo = 0;
@@ -948,6 +956,15 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
                 int32_t cc[kMpkRegCols];
                 row_cols(col, j0, len, cc);
 #pragma unroll
+                for (int qq = 0; qq < Q; ++qq)
+                    if (r == qq * 64 + lane) {
+                        have[qq] = true;
+                        sj0[qq] = j0;
+                        slen[qq] = len;
+#pragma unroll
+                        for (int t = 0; t < kMpkRegCols; ++t) scol[qq][t] = cc[t];
+                    }
+#pragma unroll
                 for (int t = 0; t < kMpkRegCols; ++t)
                     if (t < len && hs_insert<C::kHash>(keys, vals, &next, snode, C::kSlots, cc[t]) < 0) full = 1;
                 for (int t = kMpkRegCols; t < len; ++t)
@@ -961,16 +978,21 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     }
     const int R = ends[H - 1], S = ends[H];
     over = over || R > C::kRows;
-    // local CSR of rows [0, R): row q 64 + lane, q < Q; the loads of all of a lane's rows go out together
-    constexpr int Q = (C::kRows + 63) / 64;
+    // local CSR of rows [0, R): row q 64 + lane, q < Q; rows not kept above are loaded again, all of a lane's
+    // loads together
     int32_t rq[Q], j0q[Q], lenq[Q], startq[Q];
     int nent = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int r = q * 64 + lane;
         rq[q] = (!over && r < R) ? snode[r] : -1;
-        j0q[q] = rq[q] >= 0 ? rowptr[rq[q]] : 0;
-        lenq[q] = rq[q] >= 0 ? rowptr[rq[q] + 1] - j0q[q] : 0;
+        if (rq[q] >= 0 && have[q]) {
+            j0q[q] = sj0[q];
+            lenq[q] = slen[q];
+        } else {
+            j0q[q] = rq[q] >= 0 ? rowptr[rq[q]] : 0;
+            lenq[q] = rq[q] >= 0 ? rowptr[rq[q] + 1] - j0q[q] : 0;
+        }
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -993,7 +1015,12 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     TW dq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        row_cols(col, j0q[q], lenq[q], cr[q]);
+        if (have[q]) {
+#pragma unroll
+            for (int t = 0; t < kMpkRegCols; ++t) cr[q][t] = scol[q][t];
+        } else {
+            row_cols(col, j0q[q], lenq[q], cr[q]);
+        }
 #pragma unroll
         for (int t = 0; t < kMpkRegCols; ++t) vr[q][t] = t < lenq[q] ? val[j0q[q] + t] : TW(0);
         dq[q] = rq[q] >= 0 ? deg[rq[q]] : TW(0);
