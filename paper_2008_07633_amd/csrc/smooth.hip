@@ -862,8 +862,10 @@ __device__ __forceinline__ void row_cols(const int32_t *__restrict__ col, int32_
 // and seen[order[i]] = i stored by k_mpk_mark, then read back by
 // k_mpk_verify.  A node listed twice keeps only one of its positions, so the
 // other position finds a different value: any duplicate sets flag bit 0.
+// Each XCD takes a contiguous range of positions, whose nodes (a part of a
+// traversal) share the lines of seen in its L2.
 __global__ void k_mpk_mark(int64_t n, const int32_t *__restrict__ order, int32_t *seen, int32_t *flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t v = order[i];
     if (v < 0 || v >= n)
@@ -874,7 +876,7 @@ __global__ void k_mpk_mark(int64_t n, const int32_t *__restrict__ order, int32_t
 
 __global__ void k_mpk_verify(int64_t n, const int32_t *__restrict__ order, const int32_t *__restrict__ seen,
                              int32_t *flag) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int32_t v = order[i];
     if (v >= 0 && v < n && seen[v] != (int32_t)i) atomicOr(flag, 1);
@@ -903,7 +905,9 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     __shared__ int32_t next;
     __shared__ int32_t full;
     const int lane = threadIdx.x;
-    const int64_t b = blockIdx.x;
+    // consecutive blocks (neighbouring parts of the order) on one XCD: the
+    // rows they share stay in that XCD's L2
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int64_t base = b * kMpkRows;
     const int s0 = (int)(n - base < kMpkRows ? n - base : kMpkRows);
 #pragma unroll
@@ -931,22 +935,29 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
         }
     }
     __syncthreads();
-    // L(h+1): neighbours of the rows of Lh not yet in the map.  A row this lane
-    // discovers as row q 64 + lane (every row when the layers start at
-    // multiples of 64, as full blocks' first two do) keeps its entry range
-    // and first columns in registers for the local CSR below.
+    // L(h+1): neighbours of the rows of Lh not yet in the map.  Row r belongs
+    // to lane r % 64 as its row q = r / 64 from its discovery to the local CSR
+    // below: its entry range and first columns stay in registers.  A level
+    // whose rows run past Q 64 (beyond the layout's rows anyway) fails the
+    // block.
     constexpr int Q = (C::kRows + 63) / 64;
     int32_t sj0[Q], slen[Q], scol[Q][kMpkRegCols];
-    bool have[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) have[q] = false;
+    for (int q = 0; q < Q; ++q) {
+        sj0[q] = 0;
+        slen[q] = 0;
+    }
     int ends[H + 1];
     ends[0] = s0;
     int lo = 0;
 #pragma unroll
     for (int h = 0; h < H; ++h) {
-        if (!over)
-            for (int r = lo + lane; r < ends[h]; r += 64) {
+        if (!over) {
+            if (ends[h] > Q * 64 && lane == 0) full = 1;
+#pragma unroll
+            for (int qq = 0; qq < Q; ++qq) {
+                const int r = qq * 64 + lane;
+                if (r < lo || r >= ends[h]) continue;
                 const int32_t q = snode[r];
                 const int32_t j0 = rowptr[q], len = rowptr[q + 1] - j0;
                 if (len > kMaxRow) {
@@ -955,21 +966,17 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
                 }
                 int32_t cc[kMpkRegCols];
                 row_cols(col, j0, len, cc);
+                sj0[qq] = j0;
+                slen[qq] = len;
 #pragma unroll
-                for (int qq = 0; qq < Q; ++qq)
-                    if (r == qq * 64 + lane) {
-                        have[qq] = true;
-                        sj0[qq] = j0;
-                        slen[qq] = len;
-#pragma unroll
-                        for (int t = 0; t < kMpkRegCols; ++t) scol[qq][t] = cc[t];
-                    }
+                for (int t = 0; t < kMpkRegCols; ++t) scol[qq][t] = cc[t];
 #pragma unroll
                 for (int t = 0; t < kMpkRegCols; ++t)
                     if (t < len && hs_insert<C::kHash>(keys, vals, &next, snode, C::kSlots, cc[t]) < 0) full = 1;
                 for (int t = kMpkRegCols; t < len; ++t)
                     if (hs_insert<C::kHash>(keys, vals, &next, snode, C::kSlots, col[j0 + t]) < 0) full = 1;
             }
+        }
         __syncthreads();
         ends[h + 1] = next;
         over = over || full != 0 || ends[h + 1] > C::kSlots;
@@ -978,21 +985,16 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     }
     const int R = ends[H - 1], S = ends[H];
     over = over || R > C::kRows;
-    // local CSR of rows [0, R): row q 64 + lane, q < Q; rows not kept above are loaded again, all of a lane's
-    // loads together
+    // local CSR of rows [0, R): row q 64 + lane, q < Q, every one of them
+    // discovered above unless the block failed
     int32_t rq[Q], j0q[Q], lenq[Q], startq[Q];
     int nent = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int r = q * 64 + lane;
         rq[q] = (!over && r < R) ? snode[r] : -1;
-        if (rq[q] >= 0 && have[q]) {
-            j0q[q] = sj0[q];
-            lenq[q] = slen[q];
-        } else {
-            j0q[q] = rq[q] >= 0 ? rowptr[rq[q]] : 0;
-            lenq[q] = rq[q] >= 0 ? rowptr[rq[q] + 1] - j0q[q] : 0;
-        }
+        j0q[q] = rq[q] >= 0 ? sj0[q] : 0;
+        lenq[q] = rq[q] >= 0 ? slen[q] : 0;
     }
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -1015,12 +1017,8 @@ __global__ __launch_bounds__(64) void k_mpk_build(int64_t n, const int32_t *__re
     TW dq[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        if (have[q]) {
 #pragma unroll
-            for (int t = 0; t < kMpkRegCols; ++t) cr[q][t] = scol[q][t];
-        } else {
-            row_cols(col, j0q[q], lenq[q], cr[q]);
-        }
+        for (int t = 0; t < kMpkRegCols; ++t) cr[q][t] = scol[q][t];
 #pragma unroll
         for (int t = 0; t < kMpkRegCols; ++t) vr[q][t] = t < lenq[q] ? val[j0q[q] + t] : TW(0);
         dq[q] = rq[q] >= 0 ? deg[rq[q]] : TW(0);
