@@ -29,6 +29,11 @@ namespace {
 
 constexpr int kBins = 2048;
 constexpr int kHistThreads = 256;
+// The global histogram is kept in one copy per XCD (a workgroup adds into copy
+// blockIdx % kHistCopies), so the device-scope atomics of the workgroups'
+// flushes spread over kHistCopies times as many addresses; the pick adds the
+// copies.
+constexpr int kHistCopies = kNumXcd;
 
 constexpr int kTieTile = 4096;       // keys per workgroup in the tie count and the marking
 constexpr int kCompactPass = 2;      // the pass (0-based) that copies its matching keys to the buffer
@@ -99,7 +104,7 @@ __global__ void k_sel_init(SelState *st, int64_t k, uint32_t *hist) {
         st->err = 0;
         st->all_ties = 0;
     }
-    for (int b = threadIdx.x; b < kBins; b += blockDim.x) hist[b] = 0;
+    for (int b = threadIdx.x; b < kBins * kHistCopies; b += blockDim.x) hist[b] = 0;
 }
 
 // One radix pass.  FROM_BUF: read the keys the compacting pass copied (their
@@ -143,14 +148,18 @@ __global__ __launch_bounds__(kHistThreads) void k_sel_hist(int64_t ne, const TS 
     }
     if (bad) atomicOr(&st->err, 1u);   // NaN
     __syncthreads();
+    uint32_t *hc = hist + (blockIdx.x % kHistCopies) * kBins;
     for (int b = threadIdx.x; b < kBins; b += blockDim.x)
-        if (h[b]) atomicAdd(&hist[b], h[b]);
+        if (h[b]) atomicAdd(&hc[b], h[b]);
 }
 
 // One workgroup of 256 threads, 8 bins each; finds the digit holding rank
 // krem counted from the top, updates the state and clears the histogram.
+// The copies' counts are first added into LDS by coalesced loads (bin b by
+// thread b % 256), and cleared the same way at the end.
 __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, int shift, int width, int last) {
     __shared__ int64_t suffix[257];
+    __shared__ uint32_t cnt[kBins];
     const int t = threadIdx.x;
     const int nb = 1 << width;
     const int per = (nb + 255) / 256;
@@ -158,10 +167,21 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, 
     // thread that updates the state below does so only after the scan's
     // barriers, so no thread can see its new value.
     const int64_t krem = st->krem;
+#pragma unroll
+    for (int i = 0; i < kBins / 256; ++i) {
+        const int b = i * 256 + t;
+        if (b < nb) {
+            uint32_t c = 0;
+#pragma unroll
+            for (int k = 0; k < kHistCopies; ++k) c += hist[k * kBins + b];
+            cnt[b] = c;
+        }
+    }
+    __syncthreads();
     int64_t mine = 0;
     for (int i = 0; i < per; ++i) {
         const int b = t * per + i;
-        if (b < nb) mine += hist[b];
+        if (b < nb) mine += cnt[b];
     }
     suffix[t] = mine;
     if (t == 0) suffix[256] = 0;
@@ -179,7 +199,7 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, 
         for (int i = per - 1; i >= 0; --i) {
             const int b = t * per + i;
             if (b >= nb) continue;
-            const int64_t c = hist[b];
+            const int64_t c = cnt[b];
             if (krem <= acc + c) {
                 st->count_gt += acc;
                 st->krem = krem - acc;
@@ -193,9 +213,12 @@ __global__ __launch_bounds__(256) void k_sel_pick(SelState *st, uint32_t *hist, 
     }
     __syncthreads();
     if (t == 0 && suffix[0] < krem) st->err |= 2u;
-    for (int i = 0; i < per; ++i) {
-        const int b = t * per + i;
-        if (b < nb) hist[b] = 0;
+#pragma unroll
+    for (int i = 0; i < kBins / 256; ++i) {
+        const int b = i * 256 + t;
+        if (b < nb)
+#pragma unroll
+            for (int k = 0; k < kHistCopies; ++k) hist[k * kBins + b] = 0;
     }
 }
 
@@ -309,7 +332,7 @@ struct SelPlan {
 SelPlan plan_select(Carver &c, int64_t ne) {
     SelPlan p;
     p.st = c.take<SelState>(1);
-    p.hist = c.take<uint32_t>(kBins);
+    p.hist = c.take<uint32_t>(kBins * kHistCopies);
     p.buf = c.take<uint64_t>(ne + 1);
     p.tcnt = c.take<int32_t>((ne + kTieTile - 1) / kTieTile + 1);
     return p;

@@ -12,11 +12,15 @@ const char *last_error_cstr() { return g_last_error.c_str(); }
 // ------------------------------------------------------------------ scan
 // Three passes: tile sums, one-block scan of the tile sums, tile rescans.
 // A tile is 256 threads x 8 items.  Integer adds, so the result does not
-// depend on the association order.
+// depend on the association order.  Global loads and stores are striped
+// (item i of a thread at tile offset i 256 + thread), so every instruction
+// covers 256 contiguous bytes; the rescan turns them into per-thread runs of 8
+// consecutive items through LDS.
 
 constexpr int kScanThreads = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kScanThreads * kScanItems;
+constexpr int kScanSumItems = 16;   // tile sums per thread in the one-block scan
 
 __device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -29,7 +33,8 @@ __device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
 }
 
 // Block-wide exclusive scan of one value per thread; returns the block total
-// through `total`.
+// through `total`.  Its barriers also order every LDS access a thread made
+// before the call ahead of any access made after it by another thread.
 __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t &total) {
     __shared__ int32_t wsum[kScanThreads / kWave];
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
@@ -48,47 +53,77 @@ __device__ __forceinline__ int32_t block_excl_scan(int32_t x, int32_t &total) {
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_tile_sums(const int32_t *in, int64_t n, int32_t *tsum) {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
     int32_t s = 0;
 #pragma unroll
     for (int i = 0; i < kScanItems; ++i)
-        if (base + i < n) s += in[base + i];
+        if (base + i * kScanThreads < n) s += in[base + i * kScanThreads];
     int32_t tot;
     block_excl_scan(s, tot);
     if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
 }
 
+// One workgroup; thread t scans tile sums t kScanSumItems .. + kScanSumItems - 1
+// of each round of 256 kScanSumItems.
 __global__ __launch_bounds__(kScanThreads) void k_scan_tile_sums(int32_t *tsum, int64_t nt, int32_t *grand) {
     int32_t carry = 0;
-    for (int64_t base = 0; base < nt; base += kScanThreads) {
-        int64_t i = base + threadIdx.x;
-        int32_t x = i < nt ? tsum[i] : 0;
+    for (int64_t base = 0; base < nt; base += kScanThreads * kScanSumItems) {
+        const int64_t b0 = base + (int64_t)threadIdx.x * kScanSumItems;
+        int32_t v[kScanSumItems];
+        int32_t s = 0;
+#pragma unroll
+        for (int j = 0; j < kScanSumItems; ++j) {
+            v[j] = b0 + j < nt ? tsum[b0 + j] : 0;
+            s += v[j];
+        }
         int32_t tot;
-        int32_t ex = block_excl_scan(x, tot);
-        if (i < nt) tsum[i] = carry + ex;
+        int32_t run = carry + block_excl_scan(s, tot);
+#pragma unroll
+        for (int j = 0; j < kScanSumItems; ++j) {
+            if (b0 + j < nt) tsum[b0 + j] = run;
+            run += v[j];
+        }
         carry += tot;
     }
     if (threadIdx.x == 0) *grand = carry;
 }
 
+// LDS index of tile item i, one pad word per 32 against bank conflicts of the
+// per-thread runs.
+__device__ __forceinline__ int scan_pad(int i) { return i + (i >> 5); }
+
 __global__ __launch_bounds__(kScanThreads) void k_tile_rescan(const int32_t *in, int32_t *out, int64_t n,
                                                               const int32_t *tsum, const int32_t *grand) {
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    __shared__ int32_t sh[kScanTile + kScanTile / 32];
+    const int t = threadIdx.x;
+    const int64_t tile0 = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = tile0 + i * kScanThreads + t;
+        sh[scan_pad(i * kScanThreads + t)] = idx < n ? in[idx] : 0;
+    }
+    __syncthreads();
     int32_t v[kScanItems];
     int32_t s = 0;
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        v[i] = (base + i < n) ? in[base + i] : 0;
-        s += v[i];
+    for (int j = 0; j < kScanItems; ++j) {
+        v[j] = sh[scan_pad(t * kScanItems + j)];
+        s += v[j];
     }
     int32_t tot;
     int32_t ex = block_excl_scan(s, tot) + tsum[blockIdx.x];
 #pragma unroll
-    for (int i = 0; i < kScanItems; ++i) {
-        if (base + i < n) out[base + i] = ex;
-        ex += v[i];
+    for (int j = 0; j < kScanItems; ++j) {
+        sh[scan_pad(t * kScanItems + j)] = ex;
+        ex += v[j];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = *grand;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        const int64_t idx = tile0 + i * kScanThreads + t;
+        if (idx < n) out[idx] = sh[scan_pad(i * kScanThreads + t)];
+    }
+    if (blockIdx.x == 0 && t == 0) out[n] = *grand;
 }
 
 size_t scan_scratch_ints(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 2; }
