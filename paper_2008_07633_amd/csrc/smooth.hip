@@ -1755,6 +1755,18 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
         SFG_REQUIRE(omega > 0.0 && omega <= 1.0, SFG_EINVAL, "smooth_ordered: omega must be in (0, 1]");
         SFG_REQUIRE(x0 && x, SFG_EINVAL, "smooth_ordered: null pointer");
         const bool f32last = final_f32 && (storage == SFG_F16 || storage == SFG_BF16);
+        // the column means on a side stream, beside the layout pass (which
+        // waits on dependent loads rather than on bandwidth); the first pass
+        // waits for them
+        struct Fork {
+            hipEvent_t es = nullptr, ez = nullptr;
+            ~Fork() {
+                if (es) (void)hipEventDestroy(es);
+                if (ez) (void)hipEventDestroy(ez);
+            }
+        } fork;
+        SFG_HIP(hipEventCreateWithFlags(&fork.es, hipEventDisableTiming));
+        SFG_HIP(hipEventCreateWithFlags(&fork.ez, hipEventDisableTiming));
         fill_i32(mp.flag, 2, 0, s);
         if (order) {
             // the passes take the rows in this order: it must be a permutation of the nodes
@@ -1763,6 +1775,11 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
             hipLaunchKernelGGL(k_mpk_verify, dim3(grid_for(n, 256)), dim3(256), 0, s, n, order, mp.seen, mp.flag);
             SFG_LAUNCH_CHECK();
         }
+        const hipStream_t side = side_stream();
+        SFG_HIP(hipEventRecord(fork.es, s));   // after everything so far on s (x0 among it)
+        SFG_HIP(hipStreamWaitEvent(side, fork.es, 0));
+        launch_column_means<double>(x0, n, k, p.partial, p.mean, side);
+        SFG_HIP(hipEventRecord(fork.ez, side));
         const int first = want < kMpkMaxHops ? want : kMpkMaxHops;
         for (int h = first; h >= 2 && hops == 0; --h) {
             if (h == 4) {
@@ -1781,7 +1798,7 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
                 // of the first pass: the start of the smoothing if the layout stands, redone otherwise (blocks
                 // that do not fit have zero sizes, so the launch stays inside every buffer either way)
                 FlagRead fr(mp, s);
-                launch_column_means<double>(x0, n, k, p.partial, p.mean, s);
+                SFG_HIP(hipStreamWaitEvent(s, fork.ez, 0));   // join: the means before the first pass
                 run_passes_h(h, storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s, kPartSmall, true);
                 f = fr.wait();
                 started = !(f & 2);
@@ -1794,7 +1811,6 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
                 hops = h;
         }
         if (hops >= 2) {
-            if (!started) launch_column_means<double>(x0, n, k, p.partial, p.mean, s);
             run_passes_h(hops, storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s,
                          started ? kPartListed : kPartBoth, false);
             return hops;
