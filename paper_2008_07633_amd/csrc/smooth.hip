@@ -1545,7 +1545,8 @@ void launch_pass(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const void
 // with final_f32 (16-bit storage) the very last sweep stores FP32.
 // first_parts: the launches of the first pass to make here (the common-case
 // one may have gone out already); first_only: stop after the first pass.
-// p.mean holds the column means (enqueued earlier on the same stream).
+// p.mean holds the column means (enqueued earlier, on this stream or on one
+// it waits for).
 template <int H, typename TX>
 void run_smooth_passes(const sfg_csr *H_, int32_t k, int32_t sweeps, double omega, const double *x0, void *xout,
                        bool final_f32, const SmoothPlan &p, const MpkPlan &mp, int64_t nb, hipStream_t s,
@@ -1794,9 +1795,10 @@ int smooth_ordered(const sfg_csr *H, const int32_t *order, int32_t k, int32_t sw
             }
             int32_t f;
             if (h == first) {
-                // while the host waits for the flags, the GPU takes the column means and the common-case launch
-                // of the first pass: the start of the smoothing if the layout stands, redone otherwise (blocks
-                // that do not fit have zero sizes, so the launch stays inside every buffer either way)
+                // while the host waits for the flags, the GPU finishes the column means and takes the
+                // common-case launch of the first pass: the start of the smoothing if the layout stands, redone
+                // otherwise (blocks that do not fit have zero sizes, so the launch stays inside every buffer
+                // either way)
                 FlagRead fr(mp, s);
                 SFG_HIP(hipStreamWaitEvent(s, fork.ez, 0));   // join: the means before the first pass
                 run_passes_h(h, storage, H, k, sweeps, omega, x0, x, f32last, p, mp, nb, s, kPartSmall, true);
