@@ -216,6 +216,32 @@ def run_chunglu(args) -> dict:
         log(f"chunglu {name}: {out[name]['ms_total']} ms, sizes {[r['n'] for r in rep]}")
     for dt in ("f32", "f64"):
         out[dt + "_input_numbering"]["same_sparsifier"] = bool(torch.equal(keeps[dt], keeps[dt + "_input_numbering"]))
+    # quality of the FP32 hierarchy's output (Table 2 reports kappa(L_G, L_P) per graph; Fig. 10 the share of
+    # each level's off-subgraph edges that the level adds): kappa of P and of the level-0 spanning tree alone,
+    # both estimated with the library defaults on the FP64 weights
+    w64 = w32.double()
+    est = S.make_kappa_params()
+    # the estimator preconditions with a spanning tree of P marked 1 (P's own maximum spanning tree; P holds the
+    # per-aggregate forests and the mapped coarse edges, not G's tree), every other edge of P marked 2; for
+    # contrast, G's maximum spanning tree alone
+    kept = keeps["f32"] > 0
+    treeP, ncP = S.sfg_spanning_tree(g.n, u, v, w64, allowed=kept.to(torch.uint8))
+    keep = torch.where(treeP > 0, 1, torch.where(kept, 2, 0)).to(torch.uint8)
+    tree0, _ = S.sfg_spanning_tree(g.n, u, v, w64)
+    quality = {"kept_edges": int(kept.sum().item()), "components_of_P": ncP,
+               "g_tree_edges_in_P": int((kept & (tree0 > 0)).sum().item()), "g_tree_edges": int((tree0 > 0).sum().item()),
+               "estimator": {"vectors": est.k, "steps": est.steps, "inner_tol": est.tol}}
+    for name, kp in (("kappa_P", keep), ("kappa_g_tree", (tree0 > 0).to(torch.uint8))):
+        t0 = time.perf_counter()
+        kap, krep = S.sfg_kappa_estimate(g.n, u, v, w64, kp, est)
+        quality[name] = round(kap, 2)
+        quality[name + "_s"] = round(time.perf_counter() - t0, 2)
+        quality[name + "_cg_iterations"] = krep["inner_iters"]
+        log(f"chunglu {name}: {kap:.2f} ({quality[name + '_s']} s, {krep['inner_iters']} CG iterations)")
+    quality["levels"] = [{"level": i, "n": r["n"], "off_subgraph_edges": r["n_cand"], "added": r["k_sel"],
+                          "share_added": round(r["k_sel"] / r["n_cand"], 4) if r["n_cand"] else None}
+                         for i, r in enumerate(out["f32"]["levels"])]
+    out["f32"]["quality"] = quality
     G = S.sfg_laplacian_csr(g.n, u, v, w32)
     roof = sweep_roofline(G, x0[0], T, torch.float32, False, g.n, G.nnz, k, 4, 4)
     roof["numbering"] = "input (ids in expected-degree order)"
