@@ -788,6 +788,15 @@ template <> struct MpkCaps<4> {
     using Col = uint16_t;
 };
 
+// Blocks over the common-case launch's slot capacity are swept by that
+// launch too, gathering their first sweep's X_t from global memory, rather
+// than by a second launch at the layout's full capacity -- where the
+// common-case launch holds the layout's every row (its slots at least the
+// layout's rows), so that only X of the outer slots is missing.
+constexpr bool kMpkGatherWide = true;
+template <int H, int KS>
+constexpr bool mpk_gathers() { return kMpkGatherWide && KS < MpkCaps<H>::kSlots && MpkCaps<H>::kRows <= KS; }
+
 // Per-block layout at the capacities of the hop count it was built for
 // (views into the workspace, sized for the largest).
 struct MpkDev {
@@ -1133,7 +1142,8 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const int32_t *__restrict__ list, c
     int ends[H + 1];
 #pragma unroll
     for (int h = 0; h <= H; ++h) ends[h] = mp[h];
-    if (!LISTED && KS < C::kSlots && ends[H] > KS) return;   // the full-capacity launch takes this block
+    constexpr bool kGather = !LISTED && mpk_gathers<H, KS>();
+    if (!LISTED && KS < C::kSlots && !kGather && ends[H] > KS) return;   // the full-capacity launch takes this block
     const int ne = mp[kMpkMeta - 1];
     int S = ends[H], R = ends[H - 1];
 #pragma unroll
@@ -1142,6 +1152,12 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const int32_t *__restrict__ list, c
             S = ends[h];
             R = ends[h - 1];
         }
+    // a block with more slots than this variant holds: nothing is staged, the
+    // first sweep gathers X_t from global memory (the same values, converted as
+    // the staging converts them), and the later sweeps read the rows it wrote to
+    // the LDS.  Those are rows of the local CSR, all of which fit here (RK is the
+    // layout's row capacity when kGather), as do their row starts and degrees.
+    const bool gather = kGather && S > KS;
     const int s0 = ends[0];
     // round 1: slot nodes (read to this variant's capacity, used to S)
     for (int i = t; i < KS; i += 256) nodes[i] = L.node[b * C::kSlots + i];
@@ -1175,7 +1191,7 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const int32_t *__restrict__ list, c
     // X_t of slots [0, S): loads of kStage passes, then their LDS stores
 #pragma unroll
     for (int p0 = 0; p0 < kSlotPasses; p0 += kStage) {
-        if (p0 * RPP >= S) break;
+        if (p0 * RPP >= S || gather) break;
         TA v[kStage][VPL];
 #pragma unroll
         for (int j = 0; j < kStage; ++j) {
@@ -1233,6 +1249,39 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const int32_t *__restrict__ list, c
         }
         return out;
     };
+    // the same sweep of row r with X_t gathered from global memory (gather mode's first sweep)
+    auto row_sweep_g = [&](int r, auto tag) {
+        using T = decltype(tag);
+        auto xt = [&](int slot, TA (&o)[VPL]) {
+            const int32_t node = slot < KS ? nodes[slot] : L.node[b * C::kSlots + slot];
+            TA v[VPL];
+            load_row<TIN, TX, TA, VPL, CENTER>(x + (int64_t)node * k + g0 + c, mo, v);
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) o[i] = cvt<TA>(cvt<TX>(v[i]));
+        };
+        TA acc[VPL];
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) acc[i] = TA(0);
+        for (int e = rowoff[r]; e < rowoff[r + 1]; ++e) {
+            const TA wv = cvt<TA>(lval[e]);
+            TA xv[VPL];
+            xt((int)lcol[e], xv);
+#pragma unroll
+            for (int i = 0; i < VPL; ++i) acc[i] = madd(acc[i], wv, xv[i]);
+        }
+        TA sv[VPL];
+        xt(r, sv);
+        const TA d = cvt<TA>(ldeg[r]);
+        Vec<T, VPL> out;
+#pragma unroll
+        for (int i = 0; i < VPL; ++i) {
+            const TA a = keep * sv[i];
+            const TA q = acc[i] / d;
+            const TA bo = omega * q;
+            out.v[i] = cvt<T>(a + bo);
+        }
+        return out;
+    };
     // sweeps 1..m-1: rows of L0..L(m-1-j) into registers, then over X in the LDS
     for (int j = 0; j + 1 < m; ++j) {
         int nrows = ends[0];
@@ -1243,7 +1292,7 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const int32_t *__restrict__ list, c
 #pragma unroll
         for (int q = 0; q < kRowPasses; ++q) {
             const int r = ri0 + q * RPP;
-            if (r < nrows && r < rend) xr[q] = row_sweep(r, TX());
+            if (r < nrows && r < rend) xr[q] = (gather && j == 0) ? row_sweep_g(r, TX()) : row_sweep(r, TX());
         }
         __syncthreads();
 #pragma unroll
@@ -1255,7 +1304,8 @@ k_sweep_pass(int32_t k, int32_t m, MpkDev L, const int32_t *__restrict__ list, c
     }
     // the last sweep: L0 (its neighbours all lie in L0 and L1)
     for (int r = ri0; r < s0 && r < rend; r += RPP)
-        *reinterpret_cast<Vec<TO, VPL> *>(y + (int64_t)nodes[r] * k + g0 + c) = row_sweep(r, TO());
+        *reinterpret_cast<Vec<TO, VPL> *>(y + (int64_t)nodes[r] * k + g0 + c) =
+            (gather && m == 1) ? row_sweep_g(r, TO()) : row_sweep(r, TO());
 }
 
 }  // namespace
@@ -1489,7 +1539,7 @@ void launch_pass_kc(int32_t k, int32_t m, const MpkPlan &mp, int64_t nb, const v
                            (TA)omega);
         SFG_LAUNCH_CHECK();
     }
-    if constexpr (KS < KF) {
+    if constexpr (KS < KF && !mpk_gathers<H, KS>()) {
         if ((parts & kPartListed) && mp.nbig > 0) {
             hipLaunchKernelGGL((k_sweep_pass<H, KC, KF, true, TIN, TX, TO, TA, TA, 4, CENTER>),
                                dim3((uint32_t)(mp.nbig * (k / KC))), dim3(256), 0, s, k, m, mp.dev, mp.big,
