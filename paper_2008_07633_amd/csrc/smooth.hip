@@ -1739,7 +1739,9 @@ int32_t read_flag(MpkPlan &mp, hipStream_t s) {
 template <int H>
 void list_big(MpkPlan &mp, int64_t nb, sfg_dtype storage, int32_t k, hipStream_t s) {
     mp.small_slots = small_slots<H>(storage, k);
-    if (mp.small_slots < MpkCaps<H>::kSlots) {
+    // no list where the common-case launch sweeps every block (mpk_gathers)
+    const bool gathers = kMpkGatherWide && MpkCaps<H>::kRows <= mp.small_slots;
+    if (mp.small_slots < MpkCaps<H>::kSlots && !gathers) {
         hipLaunchKernelGGL(k_mpk_big<H>, dim3(grid_for(nb, 256)), dim3(256), 0, s, nb, mp.dev.meta, mp.small_slots,
                            mp.big, mp.flag + 1);
         SFG_LAUNCH_CHECK();
