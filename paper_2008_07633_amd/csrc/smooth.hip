@@ -1077,7 +1077,8 @@ constexpr int mpk_pass_waves() {
 // Slot capacity of the common-case pass kernel: the most slots whose LDS lets
 // eight workgroups share a CU (20,000 bytes each), at most the layout's.
 // Blocks with more slots (a fraction of a percent on the 200^3 mesh's tree)
-// go to a second launch at the full capacity.
+// are swept by the same launch from global memory where it holds all of the
+// layout's rows (mpk_gathers), else by a second launch at the full capacity.
 constexpr int mpk_small_slots(int slots, int rows, int ent, int colb, int kc, int sx, int sw) {
     int ks = slots;
     while (ks > 64 && mpk_lds_bytes(ks, rows, ent, colb, kc, sx, sw) > 20000) --ks;
@@ -1111,8 +1112,10 @@ __global__ void k_mpk_big(int64_t nb, const int32_t *__restrict__ meta, int32_t 
 // workgroups of one XCD, so its layout is fetched once into that XCD's L2.
 // Two dependent rounds of global loads: the block's sizes and slot nodes,
 // then X of the slots and the local CSR.
-// KS: the slots this variant holds.  LISTED = false: every block, skipping
-// those with more than KS slots; LISTED = true: the blocks of list[] only.
+// KS: the slots this variant holds.  LISTED = false: every block (those with
+// more than KS slots gathered, or skipped for the listed launch where the
+// variant does not hold all of the layout's rows); LISTED = true: the blocks
+// of list[] only.
 template <int H, int KC, int KS, bool LISTED, typename TIN, typename TX, typename TO, typename TW, typename TA,
           int VPL, bool CENTER>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(mpk_pass_waves<H, KC, KS, TX, TW>()))) void
