@@ -377,26 +377,36 @@ __global__ __launch_bounds__(256) void k_rank_short(int64_t n, const int32_t *__
         }
         return;
     }
+    // the ids first: a part already in edge-id order (half of the two-entry
+    // parts) is left as it is; otherwise its columns and weights are loaded
+    // too and the entries that move are written at their ranks
     const int32_t base = rowptr[row];
-    int32_t id[kRegSeg], c[kRegSeg];
+    int32_t id[kRegSeg], rank[kRegSeg];
+#pragma unroll
+    for (int i = 0; i < kRegSeg; ++i) id[i] = i < len ? eid[base + i] : INT32_MAX;
+    bool moves = false;
+#pragma unroll
+    for (int i = 0; i < kRegSeg; ++i) {
+        rank[i] = 0;
+#pragma unroll
+        for (int j = 0; j < kRegSeg; ++j) rank[i] += id[j] < id[i] ? 1 : 0;
+        moves = moves || (i < len && rank[i] != i);
+    }
+    if (!moves) return;
+    int32_t c[kRegSeg];
     TW x[kRegSeg];
 #pragma unroll
     for (int i = 0; i < kRegSeg; ++i) {
-        id[i] = i < len ? eid[base + i] : INT32_MAX;
         c[i] = i < len ? col[base + i] : 0;
         x[i] = i < len ? val[base + i] : TW(0);
     }
 #pragma unroll
-    for (int i = 0; i < kRegSeg; ++i) {
-        int32_t rank = 0;
-#pragma unroll
-        for (int j = 0; j < kRegSeg; ++j) rank += id[j] < id[i] ? 1 : 0;
-        if (i < len) {
-            col[base + rank] = c[i];
-            val[base + rank] = x[i];
-            eid[base + rank] = id[i];
+    for (int i = 0; i < kRegSeg; ++i)
+        if (i < len && rank[i] != i) {
+            col[base + rank[i]] = c[i];
+            val[base + rank[i]] = x[i];
+            eid[base + rank[i]] = id[i];
         }
-    }
 }
 
 template <typename TW>
