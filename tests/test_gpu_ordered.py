@@ -69,6 +69,47 @@ def test_ordered_tree_sweeps_are_bit_identical(S, name, storage, hops, split, mo
             assert info["sweeps_per_pass"] == int(hops), (name, k, sweeps)
 
 
+def two_hop_slots(n, tu, tv, order, rows=64):
+    """Slots of each block's 2-hop layout (L0 = the block's rows of the order, L1 and L2 the new neighbours of
+    the layer before), from the tree's edges, on the host."""
+    import scipy.sparse as sp
+
+    a = sp.coo_matrix((np.ones(2 * tu.size), (np.r_[tu, tv], np.r_[tv, tu])), shape=(n, n)).tocsr()
+    ptr, ind = a.indptr, a.indices
+    out = []
+    for b in range(0, n, rows):
+        l0 = set(order[b:b + rows].tolist())
+        l1 = set()
+        for p in l0:
+            l1.update(ind[ptr[p]:ptr[p + 1]].tolist())
+        l1 -= l0
+        l2 = set()
+        for p in l1:
+            l2.update(ind[ptr[p]:ptr[p + 1]].tolist())
+        l2 -= l0 | l1
+        out.append(len(l0) + len(l1) + len(l2))
+    return np.array(out)
+
+
+def test_ordered_blocks_over_the_common_capacity(S):
+    # FP64, 16 vectors, two hops: the common-case launch holds 123 slots a block. The blocks of this tree whose
+    # 2-hop neighbourhood holds more (up to the layout's 168) stage nothing and gather their first sweep's X_t
+    # from global memory in the same launch. The host checks that such blocks exist; the bits are sfg_smooth's.
+    g = W.mesh3d(60, 60, 60, seed=540, wdist=("lognormal", 0.0, 1.5))
+    u, v, w, tree, order = tree_and_order(S, g)
+    t = tree.cpu().numpy().astype(bool)
+    slots = two_hop_slots(g.n, g.u[t], g.v[t], order.cpu().numpy())
+    assert (slots > 123).sum() >= 1 and (slots <= 168).all(), (int((slots > 123).sum()), int(slots.max()))
+    H = S.sfg_laplacian_csr(g.n, u, v, w, mask=tree)
+    for sweeps in (4, 5):
+        X0 = dev(W.random_block(g.n, 16, 541 + sweeps))
+        ref = S.sfg_smooth(H, X0, sweeps, 0.5)
+        info = {}
+        got = S.sfg_smooth_ordered(H, order, X0, sweeps, 0.5, info=info)
+        assert info["sweeps_per_pass"] == 2, sweeps
+        assert torch.equal(got, ref), sweeps
+
+
 @pytest.mark.parametrize("storage", [torch.float64, torch.float32])
 def test_ordered_sweeps_on_a_whole_graph(S, storage):
     # the 3-D mesh itself in its tree's preorder: six neighbours per row, larger neighbourhoods; whatever
